@@ -1,0 +1,109 @@
+"""Seeded synthetic inputs and the model-parameter set shared by the HIP path and the oracle.
+
+This module holds inputs only: no arithmetic of the method.  Tests, bench.py
+and smoke() draw initial fields and parameters here and hand the same arrays
+to both the C-ABI library and the CPU oracle.
+
+Model parameters (dimensionless, Appendix A of Huang & Yang; hats dropped):
+  theta     = R T / (V_m Delta E), T = 1037 K, V_m = 1.48e-5 m^3/mol, Delta E = 3.3e7 J/m^3
+  gamma_c   = 2.5e-9 J/m / (Delta E L^2), gamma_eta = 6.0e-12 J/m / (Delta E L^2), L = 1.5 nm
+  kappa     = 0.008 (c-mobility prefactor), eps0 = 0.049 (lattice misfit per unit c)
+  L_eta     = 1 (eta-mobility, absorbed in the time unit)
+The CALPHAD coefficients (e0, L0..L3, U1, U4) and the elastic constants are not
+printed in the paper.  The synthetic set below keeps e0 = L1 = L2 = L3 = 0 and
+fits (L0, U1, U4) so that the reduced energy has a common tangent between the
+wells (c, eta) = (0.137, 1) and (0.229, 0.02) with d f / d eta = 0 at the
+ordered well (the equilibria the paper quotes at 1037 K); oracle/fit_coefficients.py
+reproduces the fit.  C11, C12, C44 are round positive-definite cubic values
+of the magnitude of a Ni-base alloy's stiffness divided by Delta E.
+"""
+
+import numpy as np
+
+R_GAS = 8.314462618
+T_K = 1037.0
+V_M = 1.48e-5
+DELTA_E = 3.3e7
+LENGTH = 1.5e-9
+
+DEFAULT_MODEL = {
+    "theta": R_GAS * T_K / (V_M * DELTA_E),
+    "w_c": 1.0,
+    "e0": 0.0,
+    "L": (-173.2737, 0.0, 0.0, 0.0),
+    "U1": -19.77085,
+    "U4": 3.857830,
+    "gamma_c": 2.5e-9 / (DELTA_E * LENGTH ** 2),
+    "gamma_eta": 6.0e-12 / (DELTA_E * LENGTH ** 2),
+    "kappa": 0.008,
+    "L_eta": 1.0,
+    "eps0": 0.049,
+    "C11": 6000.0,
+    "C12": 4000.0,
+    "C44": 3000.0,
+    "Lscale": 1.0,
+    "S": 10,
+    "n_eta": 3,
+}
+
+H = 0.25  # grid spacing of every experiment in Section 5
+
+# Solver settings: Newton rtol 1e-8, GMRES rtol 1e-6 (Section 5), restart 30,
+# Schwarz tiles 32 x 32 with overlap 2 for the 2D workloads.
+DEFAULT_SOLVER = {
+    "newton_rtol": 1e-8,
+    "newton_atol_rms": 1e-12,
+    "newton_maxit": 20,
+    "gmres_rtol": 1e-6,
+    "gmres_atol_rms": 1e-14,
+    "gmres_restart": 30,
+    "gmres_maxit": 600,
+    "tile": (32, 32, 1),
+    "overlap": 2,
+    "ls_alpha": 1e-4,
+    "ls_max_halvings": 10,
+}
+
+WORKLOADS = {
+    # 2D 64 x 64, 10 fixed steps dt = 1e-2
+    "pf2d_64": {"n": (64, 64), "seed": 1, "cbar": 0.17, "steps": 10, "dt": 1e-2},
+    # 2D 512 x 512, adaptive dt in [1e-3, 1], 200 steps
+    "pf2d_512": {"n": (512, 512), "seed": 2, "cbar": 0.17, "steps": 200,
+                 "dt_min": 1e-3, "dt_max": 1.0, "zeta": 100.0},
+    # 3D 128^3, adaptive dt in [1e-3, 1], 100 steps
+    "pf3d_128": {"n": (128, 128, 128), "seed": 3, "cbar": 0.17, "steps": 100,
+                 "dt_min": 1e-3, "dt_max": 1.0, "zeta": 100.0},
+}
+
+
+def init_fields(n, seed, cbar=0.17, amp_c=0.01, eta_base=1.0, amp_eta=0.01):
+    """Seeded initial state on a periodic grid of sizes n (x first).
+
+    c = cbar + U(-amp_c, amp_c); eta_p = eta_base + U(-amp_eta, amp_eta), p = 1..3
+    (eta_p = 1 is the disordered gamma matrix; the noise is the perturbation).
+    Draw order: c, eta_1, eta_2, eta_3, each in C order with x fastest, from
+    numpy.random.default_rng(seed) (PCG64).  Returns (c0, eta0) with shapes
+    (*reversed(n)) and (3, *reversed(n)), float64.
+    """
+    shape = tuple(reversed(tuple(n)))
+    rng = np.random.default_rng(seed)
+    c0 = cbar + rng.uniform(-amp_c, amp_c, size=shape)
+    eta0 = np.empty((3,) + shape)
+    for p in range(3):
+        eta0[p] = eta_base + rng.uniform(-amp_eta, amp_eta, size=shape)
+    return c0, eta0
+
+
+def random_state(n, seed, cbar=0.17, amp=0.02, u_amp=1e-3):
+    """A random valid full state X (c, eta_1..3, u_1..d) for kernel-level tests:
+    shape (4 + d, *reversed(n)).  The displacement is random, not in equilibrium."""
+    d = len(n)
+    shape = tuple(reversed(tuple(n)))
+    rng = np.random.default_rng(seed)
+    X = np.empty((4 + d,) + shape)
+    X[0] = cbar + rng.uniform(-amp, amp, size=shape)
+    for p in range(3):
+        X[1 + p] = 1.0 + rng.uniform(-5 * amp, 5 * amp, size=shape)
+    for I in range(d):
+        X[4 + I] = rng.uniform(-u_amp, u_amp, size=shape)
+    return X
