@@ -1,0 +1,176 @@
+/*
+ * pfnks.h -- C ABI of the MI355X Newton-Krylov-Schwarz solver for one time step of the
+ * discrete-variational-derivative (DVD) scheme of Huang & Yang, "Parallel energy stable
+ * phase field simulations of Ni-based alloys system".
+ *
+ * The library advances the composition c, the three long-range order parameters eta_1..3
+ * and the displacement u_1..u_d on a periodic d-dimensional grid (d = 2 or 3) by one step
+ * of scheme (NSOA-1) (Section 3): the semi-implicit DVD update of (c, eta) together with the
+ * discrete mechanical equilibrium (mechanicalequilibrium-dis), solved by inexact Newton with
+ * right-preconditioned restarted GMRES and a restricted additive Schwarz (RAS) preconditioner
+ * (Section 4).  Free energy: Appendix A (sublattice chemical energy with the logarithmic
+ * terms, cubic elastic energy); discrete gradient: Section 3 eqs. (D2-1), (dvds-1) and
+ * Appendix B, generalised to three order parameters.
+ *
+ * Conventions shared by every entry point
+ *   - Every function returns an int status (PFNKS_OK = 0 or a negative PFNKS_E* code);
+ *     none throws, none keeps global mutable state.  pfnks_strerror() gives the text.
+ *   - Arrays handed in by pointer are HOST arrays unless the name starts with d_.  Fields are
+ *     structure-of-arrays planes of n[0]*n[1]*n[2] doubles each, x fastest (index
+ *     i + n0*(j + n1*k)), in the order c, eta_1, eta_2, eta_3, u_1 .. u_d.
+ *   - Device memory: the library never allocates device memory.  The caller allocates the
+ *     workspace (pfnks_workspace_bytes) and keeps it alive until pfnks_destroy; the library
+ *     allocates only a small pinned host buffer per problem.
+ *   - Work is ordered on the HIP stream given at creation (NULL = the null stream).  Every
+ *     call that returns host values synchronises that stream.
+ *   - Distinct problems may be used from distinct host threads; one problem must not be used
+ *     by two threads at once.
+ */
+#ifndef PFNKS_H
+#define PFNKS_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  PFNKS_OK = 0,
+  PFNKS_EINVAL = -1,   /* bad argument: null pointer, size, parameter outside its range  */
+  PFNKS_EDOMAIN = -2,  /* a state outside the log domain: need 0 < c < 1, 0 < c eta_i < 1  */
+  PFNKS_ENOSPACE = -3, /* workspace smaller than pfnks_workspace_bytes                      */
+  PFNKS_ENOCONV = -4,  /* Newton did not converge; the state is left at t_n                */
+  PFNKS_EDEVICE = -5   /* a HIP runtime error; pfnks_last_error() has its text              */
+};
+
+typedef enum { PFNKS_FP64 = 0, PFNKS_MIXED = 1 } pfnks_precision;
+
+/* Preconditioner.  PFNKS_PC_RAS: one-level restricted additive Schwarz over all fields
+ * (Section 4, left-RAS z = sum_t R_t^0' A_t^{-1} R_t^delta r), tile solve in LDS.
+ * PFNKS_PC_RAS_SPECTRAL: the same RAS over (c, eta) composed block-lower-triangularly with an
+ * exact Fourier solve of the constant-coefficient periodic displacement block. */
+typedef enum { PFNKS_PC_RAS = 0, PFNKS_PC_RAS_SPECTRAL = 1 } pfnks_pc;
+
+typedef struct {
+  int dim;      /* 2 or 3                                                     */
+  int n[3];     /* nodes per direction (n[2] = 1 when dim == 2); even sizes  */
+  double h;     /* grid spacing; periodic box of side n[k]*h                  */
+} pfnks_grid;
+
+/* Dimensionless model parameters (Appendix A; values divided by V_m*DeltaE). */
+typedef struct {
+  double theta;      /* RT / (V_m DeltaE)                                              */
+  double w_c;        /* weight of theta*Psi(c): 1 = the form of Section 2 and (D2-1)    */
+  double e0;         /* (E0_Al - E0_Ni)                                                */
+  double L[4];       /* Redlich-Kister L0..L3 of the disordered excess energy          */
+  double U1, U4;     /* ordering parameters of E^ord                                   */
+  double gamma_c;    /* gradient coefficient of c                                      */
+  double gamma_eta;  /* gradient coefficient of each eta_p                             */
+  double kappa;      /* mobility prefactor, M = kappa c (1 - c)                        */
+  double L_eta;      /* relaxation coefficient of eta (1 as written)                   */
+  double eps0;       /* lattice misfit per unit composition                            */
+  double C11, C12, C44; /* cubic elastic constants                                     */
+  double Lscale;     /* multiplier of the Hooke tensor (Section 5.1); 0 = no elasticity */
+  int S;             /* order of the Taylor-stabilised quotient Psi_S (Section 3), 1..30 */
+} pfnks_model;
+
+typedef struct {
+  double newton_rtol;     /* eps_r: stop when ||F|| <= max(eps_r ||F(X0)||, eps_a)          */
+  double newton_atol_rms; /* eps_a per unknown: eps_a = newton_atol_rms * sqrt(#unknowns)     */
+  int newton_maxit;       /* Newton iterations before PFNKS_ENOCONV                         */
+  double gmres_rtol;      /* xi_r: ||J S + F|| <= max(xi_r ||F||, xi_a)                     */
+  double gmres_atol_rms;  /* xi_a per unknown                                               */
+  int gmres_restart;      /* Krylov basis size m (1..64)                                    */
+  int gmres_maxit;        /* total GMRES iterations per Newton step                         */
+  int tile[3];            /* owned tile of the Schwarz preconditioner (tile[2] = 1 in 2D)   */
+  int overlap;            /* delta: extra layers of each subdomain on every side (0..4)     */
+  int sweeps;             /* symmetric multicolour block Gauss-Seidel sweeps per tile solve */
+  pfnks_pc pc;            /* preconditioner                                                 */
+  pfnks_precision precision; /* PFNKS_FP64 only in this version                            */
+  double ls_alpha;        /* Armijo constant of the backtracking line search                */
+  int ls_max_halvings;    /* halvings of lambda before the step is declared failed          */
+} pfnks_solver;
+
+typedef struct {
+  int newton_its, gmres_its, ls_backtracks, status;
+  double res0;            /* ||F(X^n)||                                 */
+  double res_final;       /* ||F(X^{n+1})||                             */
+  double dx_rms;          /* RMS of X^{n+1} - X^n over c and eta        */
+  double energy;          /* discrete energy E~^{n+1}                   */
+  double energy_parts[3]; /* chemical, elastic, interfacial             */
+  double mass;            /* <c^{n+1}> = h^d sum c                      */
+} pfnks_step_stats;
+
+typedef struct pfnks_problem pfnks_problem;
+
+/* Bytes of device workspace a problem of this shape needs (device memory the caller owns).
+ * Errors: PFNKS_EINVAL for a null pointer, dim not 2 or 3, an odd or non-positive size, a
+ * tile that does not divide the grid, overlap or restart out of range. */
+int pfnks_workspace_bytes(const pfnks_grid* grid, const pfnks_model* model,
+                          const pfnks_solver* solver, size_t* bytes);
+
+/* Create a problem from the initial data c^0 and eta^0 (Section 2: initial conditions;
+ * periodic boundary conditions).  c0: one host plane; eta0: three host planes, both copied.
+ * Computes cbar^0 = mean(c^0) (the reference composition of the eigenstrain, Section 3) and the
+ * initial displacement u^0 from the discrete equilibrium (mechanicalequilibrium-dis) at c^0,
+ * with zero mean on every parity class (the gauge of the central difference).
+ * d_workspace: device buffer of ws_bytes >= pfnks_workspace_bytes(), 256-byte aligned,
+ * owned by the caller.  hip_stream: a hipStream_t or NULL.
+ * Errors: PFNKS_EINVAL, PFNKS_ENOSPACE, PFNKS_EDOMAIN (some 0 < c, c*eta_i < 1 violated,
+ * eta_4 = 4 - eta_1 - eta_2 - eta_3), PFNKS_EDEVICE. */
+int pfnks_create_problem(const pfnks_grid* grid, const pfnks_model* model,
+                         const pfnks_solver* solver, const double* c0, const double* eta0,
+                         void* d_workspace, size_t ws_bytes, void* hip_stream,
+                         pfnks_problem** out);
+
+/* One step of scheme (NSOA-1) with step size dt (Section 3), solved by the Newton-Krylov-
+ * Schwarz method of Section 4 from X_0 = X^n.  The c-part of every Newton update is
+ * projected so that the total mass is exactly that of X^n (Theorem 3.2, item 1).  On
+ * success the state becomes X^{n+1}, t += dt, and stats (may be NULL) is filled.
+ * On PFNKS_ENOCONV the state is unchanged (the adaptive driver of Section 4 retries
+ * with a smaller dt).  Errors: PFNKS_EINVAL (dt <= 0), PFNKS_ENOCONV, PFNKS_EDEVICE. */
+int pfnks_step(pfnks_problem* p, double dt, pfnks_step_stats* stats);
+
+/* Discrete free energy E~ of eqs. (relations)/(freeenergy) at the current state; parts
+ * (may be NULL) receives (chemical E1+E2, elastic E3, interfacial E4). */
+int pfnks_energy(pfnks_problem* p, double* total, double parts[3]);
+
+/* Discrete mass <c> = h^d sum_i c_i (Theorem 3.2). */
+int pfnks_mass(pfnks_problem* p, double* mass);
+
+/* Copy the state to host: X receives 4 + dim planes (c, eta_1..3, u_1..u_d); t may be NULL. */
+int pfnks_get_state(pfnks_problem* p, double* X, double* t);
+
+/* Replace the state (4 + dim host planes) and time, e.g. to resume from a checkpoint taken
+ * with pfnks_get_state.  The displacement is used as given.  Errors: PFNKS_EDOMAIN. */
+int pfnks_set_state(pfnks_problem* p, const double* X, double t);
+
+/* Release the handle (host memory only; the caller frees the workspace afterwards). */
+int pfnks_destroy(pfnks_problem* p);
+
+const char* pfnks_strerror(int status);
+/* Text of the last PFNKS_EDEVICE on this thread. */
+const char* pfnks_last_error(void);
+
+/* ---- building blocks of the step, exposed for parity tests (host arrays) ------------ */
+
+/* F(X; X^n, dt), the residual of (NSOA-1) with the current state as X^n.
+ * X, F: 4 + dim host planes. */
+int pfnks_debug_residual(pfnks_problem* p, const double* X, double dt, double* F);
+
+/* w = J(X) v, the Jacobian of the residual at X (current state as X^n) applied to v.
+ * X, v, w: 4 + dim host planes. */
+int pfnks_debug_jv(pfnks_problem* p, const double* X, double dt, const double* v, double* w);
+
+/* z = M^{-1} r, the preconditioner built at X (current state as X^n).  r, z: host planes. */
+int pfnks_debug_pc(pfnks_problem* p, const double* X, double dt, const double* r, double* z);
+
+/* Counters of the last pfnks_step: kernel launches and host synchronisations. */
+int pfnks_debug_counters(pfnks_problem* p, long long* launches, long long* syncs);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PFNKS_H */

@@ -1,0 +1,289 @@
+// Vector kernels of the Krylov solver and the grid reductions of the Newton step.
+//
+// Every reduction is two-stage and deterministic: each of kRedBlocks workgroups writes one
+// partial per value (partial[v * kRedBlocks + block]), then launch_finalize sums the partials
+// in a fixed tree order.  No atomics, so results are bitwise reproducible run to run.
+#include "pf_internal.h"
+
+namespace pf {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+// Sum of one value over the workgroup (wave64 shuffles, then the four waves via LDS).
+__device__ inline double block_sum(double v, double* lds) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) lds[wave] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) {
+    for (int w = 0; w < kThreads / 64; ++w) r += lds[w];
+  }
+  return r;  // valid in thread 0
+}
+
+template <int MAXV>
+__global__ __launch_bounds__(kThreads) void k_multidot(long long n, int nv, const double* __restrict__ V,
+                                                       long long ldv, const double* __restrict__ w,
+                                                       double* __restrict__ partial) {
+  __shared__ double lds[kThreads / 64];
+  double acc[MAXV + 1];
+#pragma unroll
+  for (int v = 0; v <= MAXV; ++v) acc[v] = 0.0;
+  for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < n;
+       e += (long long)gridDim.x * kThreads) {
+    const double we = w[e];
+#pragma unroll
+    for (int v = 0; v < MAXV; ++v)
+      if (v < nv) acc[v] += we * V[v * ldv + e];
+    acc[MAXV] += we * we;
+  }
+#pragma unroll
+  for (int v = 0; v < MAXV; ++v) {
+    if (v < nv) {
+      double s = block_sum(acc[v], lds);
+      if (threadIdx.x == 0) partial[v * kRedBlocks + blockIdx.x] = s;
+    }
+  }
+  double s = block_sum(acc[MAXV], lds);
+  if (threadIdx.x == 0) partial[nv * kRedBlocks + blockIdx.x] = s;
+}
+
+struct Coefs {
+  double c[kMaxRed];
+};
+
+template <int MAXV>
+__global__ __launch_bounds__(kThreads) void k_update(long long n, int nv, const double* __restrict__ V,
+                                                     long long ldv, Coefs cf, const double* __restrict__ w,
+                                                     double scale, double* __restrict__ out,
+                                                     double* __restrict__ partial) {
+  __shared__ double lds[kThreads / 64];
+  double acc = 0.0;
+  for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < n;
+       e += (long long)gridDim.x * kThreads) {
+    double x = w[e];
+#pragma unroll
+    for (int v = 0; v < MAXV; ++v)
+      if (v < nv) x -= cf.c[v] * V[v * ldv + e];
+    acc += x * x;
+    out[e] = scale * x;
+  }
+  double s = block_sum(acc, lds);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+template <int MAXV>
+__global__ __launch_bounds__(kThreads) void k_lincomb(long long n, int nv, const double* __restrict__ V,
+                                                      long long ldv, Coefs cf, double beta,
+                                                      double* __restrict__ out) {
+  for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < n;
+       e += (long long)gridDim.x * kThreads) {
+    double x = (beta == 0.0) ? 0.0 : beta * out[e];
+#pragma unroll
+    for (int v = 0; v < MAXV; ++v)
+      if (v < nv) x += cf.c[v] * V[v * ldv + e];
+    out[e] = x;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_axpby(long long n, double a, const double* __restrict__ x,
+                                                    double b, const double* __restrict__ y,
+                                                    double* __restrict__ out) {
+  for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < n;
+       e += (long long)gridDim.x * kThreads) {
+    double v = a * x[e];
+    if (b != 0.0) v += b * y[e];
+    out[e] = v;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_finalize(const double* __restrict__ partial, int nvals,
+                                                       double* __restrict__ out) {
+  __shared__ double lds[kThreads / 64];
+  for (int v = 0; v < nvals; ++v) {
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < kRedBlocks; b += kThreads) acc += partial[v * kRedBlocks + b];
+    double s = block_sum(acc, lds);
+    if (threadIdx.x == 0) out[v] = s;
+  }
+}
+
+// sum of x, and sum of (y - yn): the two means of the mass projection of a Newton update
+__global__ __launch_bounds__(kThreads) void k_sum2(long long n, const double* __restrict__ x,
+                                                   const double* __restrict__ y,
+                                                   const double* __restrict__ yn,
+                                                   double* __restrict__ partial) {
+  __shared__ double lds[kThreads / 64];
+  double a = 0.0, b = 0.0;
+  for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < n;
+       e += (long long)gridDim.x * kThreads) {
+    a += x[e];
+    b += y[e] - yn[e];
+  }
+  double sa = block_sum(a, lds);
+  double sb = block_sum(b, lds);
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x] = sa;
+    partial[kRedBlocks + blockIdx.x] = sb;
+  }
+}
+
+// Trial point of the line search, X_t = X + lam (S + shift e_c), with the log-domain check
+// 0 < c < 1, 0 < c eta_i < 1 (i = 1..4, eta_4 = 4 - eta_1 - eta_2 - eta_3).
+__global__ __launch_bounds__(kThreads) void k_trial(long long N, int nf, const double* __restrict__ X,
+                                                    const double* __restrict__ S, double lam,
+                                                    double shift, double* __restrict__ Xt,
+                                                    double* __restrict__ partial) {
+  __shared__ double lds[kThreads / 64];
+  double bad = 0.0;
+  for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < N;
+       e += (long long)gridDim.x * kThreads) {
+    const double c = X[e] + lam * (S[e] + shift);
+    Xt[e] = c;
+    double esum = 0.0;
+    double prod_ok = (c > 0.0 && c < 1.0) ? 1.0 : 0.0;
+    for (int p = 1; p <= 3; ++p) {
+      const double ep = X[p * N + e] + lam * S[p * N + e];
+      Xt[p * N + e] = ep;
+      esum += ep;
+      const double y = c * ep;
+      if (!(y > 0.0 && y < 1.0)) prod_ok = 0.0;
+    }
+    const double y4 = c * (4.0 - esum);
+    if (!(y4 > 0.0 && y4 < 1.0)) prod_ok = 0.0;
+    for (int f = 4; f < nf; ++f) Xt[f * N + e] = X[f * N + e] + lam * S[f * N + e];
+    bad += 1.0 - prod_ok;
+  }
+  double s = block_sum(bad, lds);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kThreads) void k_dx2(long long n, const double* __restrict__ X,
+                                                  const double* __restrict__ Xn,
+                                                  double* __restrict__ partial) {
+  __shared__ double lds[kThreads / 64];
+  double a = 0.0;
+  for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < n;
+       e += (long long)gridDim.x * kThreads) {
+    const double d = X[e] - Xn[e];
+    a += d * d;
+  }
+  double s = block_sum(a, lds);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// Sums of each displacement component over each parity class (i mod 2, j mod 2, k mod 2).
+__global__ __launch_bounds__(kThreads) void k_class_sums(Consts K, const double* __restrict__ u,
+                                                         double* __restrict__ partial) {
+  __shared__ double lds[kThreads / 64];
+  const int ncls = 1 << K.dim;
+  double acc[3][8];
+  for (int I = 0; I < 3; ++I)
+    for (int c = 0; c < 8; ++c) acc[I][c] = 0.0;
+  for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < K.N;
+       e += (long long)gridDim.x * kThreads) {
+    const long long i = e % K.nx, t = e / K.nx, j = t % K.ny, k = t / K.ny;
+    const int cls = (int)((i & 1) | ((j & 1) << 1) | ((k & 1) << 2));
+    for (int I = 0; I < K.dim; ++I) {
+      const double v = u[I * K.N + e];
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        if (c == cls) acc[I][c] += v;
+    }
+  }
+  for (int I = 0; I < K.dim; ++I)
+    for (int c = 0; c < ncls; ++c) {
+      double s = block_sum(acc[I][c], lds);
+      if (threadIdx.x == 0) partial[(I * ncls + c) * kRedBlocks + blockIdx.x] = s;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_class_shift(Consts K, double* __restrict__ u,
+                                                          const double* __restrict__ sums) {
+  const int ncls = 1 << K.dim;
+  const double inv = (double)ncls / (double)K.N;  // every class holds N / 2^d nodes
+  for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < K.N;
+       e += (long long)gridDim.x * kThreads) {
+    const long long i = e % K.nx, t = e / K.nx, j = t % K.ny, k = t / K.ny;
+    const int cls = (int)((i & 1) | ((j & 1) << 1) | ((k & 1) << 2));
+    for (int I = 0; I < K.dim; ++I) u[I * K.N + e] -= sums[I * ncls + cls] * inv;
+  }
+}
+
+int grid_for(long long n) {
+  long long b = (n + kThreads - 1) / kThreads;
+  return (int)(b < kRedBlocks ? b : kRedBlocks);
+}
+
+}  // namespace
+
+#define DISPATCH_MAXV(nv, KERNEL, ...)                                               \
+  do {                                                                               \
+    if ((nv) <= 4) hipLaunchKernelGGL(KERNEL<4>, __VA_ARGS__);                       \
+    else if ((nv) <= 8) hipLaunchKernelGGL(KERNEL<8>, __VA_ARGS__);                  \
+    else if ((nv) <= 16) hipLaunchKernelGGL(KERNEL<16>, __VA_ARGS__);                \
+    else if ((nv) <= 32) hipLaunchKernelGGL(KERNEL<32>, __VA_ARGS__);                \
+    else hipLaunchKernelGGL(KERNEL<64>, __VA_ARGS__);                                \
+  } while (0)
+
+// partial receives nv + 1 values: <w, V_v> for v < nv and <w, w>.  Always kRedBlocks blocks.
+void launch_multidot(long long n, int nv, const double* V, long long ldv, const double* w,
+                     double* partial, hipStream_t s) {
+  DISPATCH_MAXV(nv, k_multidot, dim3(kRedBlocks), dim3(kThreads), 0, s, n, nv, V, ldv, w, partial);
+}
+
+// out = scale * (w - sum_v coef[v] V_v); partial: ||w - sum coef V||^2.
+void launch_update(long long n, int nv, const double* V, long long ldv, const double* coef,
+                   const double* w, double scale, double* out, double* partial, hipStream_t s) {
+  Coefs cf{};
+  for (int v = 0; v < nv; ++v) cf.c[v] = coef[v];
+  DISPATCH_MAXV(nv, k_update, dim3(kRedBlocks), dim3(kThreads), 0, s, n, nv, V, ldv, cf, w, scale,
+                out, partial);
+}
+
+// out = beta * out + sum_v coef[v] V_v
+void launch_lincomb(long long n, int nv, const double* V, long long ldv, const double* coef,
+                    double beta, double* out, hipStream_t s) {
+  Coefs cf{};
+  for (int v = 0; v < nv; ++v) cf.c[v] = coef[v];
+  DISPATCH_MAXV(nv, k_lincomb, dim3(grid_for(n)), dim3(kThreads), 0, s, n, nv, V, ldv, cf, beta,
+                out);
+}
+
+void launch_axpby(long long n, double a, const double* x, double b, const double* y, double* out,
+                  hipStream_t s) {
+  hipLaunchKernelGGL(k_axpby, dim3(grid_for(n)), dim3(kThreads), 0, s, n, a, x, b, y, out);
+}
+
+void launch_finalize(const double* partial, int nvals, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, s, partial, nvals, out);
+}
+
+void launch_sum2(long long n, const double* x, const double* y, const double* yn, double* partial,
+                 hipStream_t s) {
+  hipLaunchKernelGGL(k_sum2, dim3(kRedBlocks), dim3(kThreads), 0, s, n, x, y, yn, partial);
+}
+
+void launch_trial(const Consts& K, int nf, const double* X, const double* S, double lam,
+                  double shift, double* Xt, double* partial, hipStream_t s) {
+  hipLaunchKernelGGL(k_trial, dim3(kRedBlocks), dim3(kThreads), 0, s, K.N, nf, X, S, lam, shift,
+                     Xt, partial);
+}
+
+void launch_dx2(long long n4, const double* X, const double* Xn, double* partial, hipStream_t s) {
+  hipLaunchKernelGGL(k_dx2, dim3(kRedBlocks), dim3(kThreads), 0, s, n4, X, Xn, partial);
+}
+
+void launch_class_sums(const Consts& K, const double* u, double* partial, hipStream_t s) {
+  hipLaunchKernelGGL(k_class_sums, dim3(kRedBlocks), dim3(kThreads), 0, s, K, u, partial);
+}
+
+void launch_class_shift(const Consts& K, double* u, const double* sums, hipStream_t s) {
+  hipLaunchKernelGGL(k_class_shift, dim3(grid_for(K.N)), dim3(kThreads), 0, s, K, u, sums);
+}
+
+}  // namespace pf

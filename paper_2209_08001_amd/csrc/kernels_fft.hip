@@ -1,0 +1,288 @@
+// Exact solve of the displacement block of the NSOA-1 Jacobian by discrete Fourier transform.
+//
+// The displacement rows of scheme (NSOA-1) are the discrete equilibrium
+// (mechanicalequilibrium-dis) sum_J Dhat_J sigma_IJ = 0 with sigma = Lscale C : eps and
+// eps_IJ = (Dhat_J u_I + Dhat_I u_J)/2.  On a periodic grid with homogeneous cubic C that
+// operator is diagonalised by the DFT: Dhat_J -> i S_J, S_J = sin(2 pi m_J / n_J) / h, and
+//   Khat_IK = - sum_{J,L} C_IJKL S_J S_L
+//           = -[C11 S_I^2 + C44 sum_{J != I} S_J^2]     (I = K)
+//           = -(C12 + C44) S_I S_K                      (I != K).
+// Modes with every S_J = 0 (the parity-class constants that Dhat annihilates) get u = 0, which
+// is the zero-mean-per-parity-class gauge.
+//
+// Transforms: in-LDS radix-2 decimation-in-time FFTs along one direction at a time, several
+// lines per workgroup, complex double.  Two real fields travel as one complex field
+// (q_1 + i q_2); their spectra are separated with the conjugate-symmetric mirror k -> -k.
+#include "pf_internal.h"
+
+namespace pf {
+
+namespace {
+
+constexpr int kFftThreads = 256;
+constexpr int kFftLds = 4096;  // complex doubles per workgroup (64 KiB)
+
+__device__ inline double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// Lines of length n (power of two), points pstride apart; line l starts at
+// (l % la) * lb + (l / la) * lc.  contiguous = 1 when pstride == 1 (threads walk along a line),
+// else consecutive threads take consecutive lines (la lines adjacent in memory).
+__global__ __launch_bounds__(kFftThreads) void k_fft_lines(double2* __restrict__ data, int n, int logn,
+                                                           long long pstride, long long la,
+                                                           long long lb, long long lc, long long nlines,
+                                                           int lpb, const double2* __restrict__ tw,
+                                                           int inverse, int contiguous) {
+  __shared__ double2 sm[kFftLds];
+  const long long line0 = (long long)blockIdx.x * lpb;
+  const int total = lpb * n;
+  for (int e = threadIdx.x; e < total; e += kFftThreads) {
+    int l, p;
+    if (contiguous) {
+      l = e / n;
+      p = e - l * n;
+    } else {
+      l = e % lpb;
+      p = e / lpb;
+    }
+    const long long line = line0 + l;
+    if (line < nlines) {
+      const long long off = (line % la) * lb + (line / la) * lc;
+      const int rp = (int)(__brev((unsigned)p) >> (32 - logn));
+      sm[l * n + rp] = data[off + p * pstride];
+    }
+  }
+  __syncthreads();
+  const int halfn = n >> 1;
+  for (int s = 1; s <= logn; ++s) {
+    const int half = 1 << (s - 1);
+    const int tstride = n >> s;  // twiddle index step
+    for (int t = threadIdx.x; t < lpb * halfn; t += kFftThreads) {
+      const int l = t / halfn, r = t - l * halfn;
+      const int grp = r / half, pos = r - grp * half;
+      const int i0 = l * n + grp * 2 * half + pos, i1 = i0 + half;
+      double2 w = tw[pos * tstride];
+      if (inverse) w.y = -w.y;
+      const double2 a0 = sm[i0];
+      const double2 a1 = cmul(sm[i1], w);
+      sm[i0] = make_double2(a0.x + a1.x, a0.y + a1.y);
+      sm[i1] = make_double2(a0.x - a1.x, a0.y - a1.y);
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < total; e += kFftThreads) {
+    int l, p;
+    if (contiguous) {
+      l = e / n;
+      p = e - l * n;
+    } else {
+      l = e % lpb;
+      p = e / lpb;
+    }
+    const long long line = line0 + l;
+    if (line < nlines) {
+      const long long off = (line % la) * lb + (line / la) * lc;
+      data[off + p * pstride] = sm[l * n + p];
+    }
+  }
+}
+
+__device__ inline int wrapi(int a, int n) {
+  a += (a < 0) ? n : 0;
+  a -= (a >= n) ? n : 0;
+  return a;
+}
+
+// q_I = r_I + a Dhat_I zc; z0 = q_1 + i q_2, z1 = q_3 (3D)
+__global__ __launch_bounds__(256) void k_pack(Consts K, const double* __restrict__ r, double a,
+                                              const double* __restrict__ zc, double2* __restrict__ z0,
+                                              double2* __restrict__ z1) {
+  for (long long n = (long long)blockIdx.x * 256 + threadIdx.x; n < K.N; n += (long long)gridDim.x * 256) {
+    const int i = (int)(n % K.nx);
+    const long long t = n / K.nx;
+    const int j = (int)(t % K.ny), k = (int)(t / K.ny);
+    double q[3] = {0.0, 0.0, 0.0};
+    for (int I = 0; I < K.dim; ++I) {
+      double v = r ? r[I * K.N + n] : 0.0;
+      if (zc && a != 0.0) {
+        long long np, nm;
+        if (I == 0) {
+          np = wrapi(i + 1, K.nx) + (long long)K.nx * (j + (long long)K.ny * k);
+          nm = wrapi(i - 1, K.nx) + (long long)K.nx * (j + (long long)K.ny * k);
+        } else if (I == 1) {
+          np = i + (long long)K.nx * (wrapi(j + 1, K.ny) + (long long)K.ny * k);
+          nm = i + (long long)K.nx * (wrapi(j - 1, K.ny) + (long long)K.ny * k);
+        } else {
+          np = i + (long long)K.nx * (j + (long long)K.ny * wrapi(k + 1, K.nz));
+          nm = i + (long long)K.nx * (j + (long long)K.ny * wrapi(k - 1, K.nz));
+        }
+        v += a * (zc[np] - zc[nm]) * K.i2h;
+      }
+      q[I] = v;
+    }
+    z0[n] = make_double2(q[0], q[1]);
+    if (K.dim == 3) z1[n] = make_double2(q[2], 0.0);
+  }
+}
+
+// pointwise solve Khat uhat = qhat; w0 = uhat_1 + i uhat_2, w1 = uhat_3
+__global__ __launch_bounds__(256) void k_symbol_solve(Consts K, const double2* __restrict__ z0,
+                                                      const double2* __restrict__ z1,
+                                                      double2* __restrict__ w0,
+                                                      double2* __restrict__ w1) {
+  for (long long n = (long long)blockIdx.x * 256 + threadIdx.x; n < K.N; n += (long long)gridDim.x * 256) {
+    const int i = (int)(n % K.nx);
+    const long long t = n / K.nx;
+    const int j = (int)(t % K.ny), k = (int)(t / K.ny);
+    const long long nm = (long long)wrapi(-i, K.nx) +
+                         (long long)K.nx * ((long long)wrapi(-j, K.ny) + (long long)K.ny * wrapi(-k, K.nz));
+    double S[3];
+    S[0] = sinpi(2.0 * i / K.nx) * K.ih;
+    S[1] = sinpi(2.0 * j / K.ny) * K.ih;
+    S[2] = (K.dim == 3) ? sinpi(2.0 * k / K.nz) * K.ih : 0.0;
+    const double2 a = z0[n], b = z0[nm];
+    // spectra of the two real fields packed in z0
+    double2 Q[3];
+    Q[0] = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
+    Q[1] = make_double2(0.5 * (a.y + b.y), -0.5 * (a.x - b.x));
+    Q[2] = (K.dim == 3) ? z1[n] : make_double2(0.0, 0.0);
+    double2 U[3] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
+    double s2 = S[0] * S[0] + S[1] * S[1] + S[2] * S[2];
+    if (!K.elastic) {
+      for (int I = 0; I < K.dim; ++I) U[I] = Q[I];  // identity rows when there is no elasticity
+    } else if (s2 != 0.0) {
+      double A[3][3];
+      for (int I = 0; I < K.dim; ++I)
+        for (int L = 0; L < K.dim; ++L) {
+          if (I == L) {
+            A[I][I] = -(K.C11 * S[I] * S[I] + K.C44 * (s2 - S[I] * S[I]));
+          } else {
+            A[I][L] = -(K.C12 + K.C44) * S[I] * S[L];
+          }
+        }
+      if (K.dim == 2) {
+        const double det = A[0][0] * A[1][1] - A[0][1] * A[1][0];
+        const double id = 1.0 / det;
+        for (int c = 0; c < 2; ++c) {
+          const double q0 = c ? Q[0].y : Q[0].x, q1 = c ? Q[1].y : Q[1].x;
+          const double u0 = (A[1][1] * q0 - A[0][1] * q1) * id;
+          const double u1 = (A[0][0] * q1 - A[1][0] * q0) * id;
+          if (c) {
+            U[0].y = u0;
+            U[1].y = u1;
+          } else {
+            U[0].x = u0;
+            U[1].x = u1;
+          }
+        }
+      } else {
+        // symmetric 3 x 3 by the adjugate
+        const double c00 = A[1][1] * A[2][2] - A[1][2] * A[2][1];
+        const double c01 = A[0][2] * A[2][1] - A[0][1] * A[2][2];
+        const double c02 = A[0][1] * A[1][2] - A[0][2] * A[1][1];
+        const double c11 = A[0][0] * A[2][2] - A[0][2] * A[2][0];
+        const double c12 = A[0][2] * A[1][0] - A[0][0] * A[1][2];
+        const double c22 = A[0][0] * A[1][1] - A[0][1] * A[1][0];
+        const double det = A[0][0] * c00 + A[0][1] * (A[1][2] * A[2][0] - A[1][0] * A[2][2]) +
+                           A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+        const double id = 1.0 / det;
+        const double Ai[3][3] = {{c00 * id, c01 * id, c02 * id},
+                                 {c01 * id, c11 * id, c12 * id},
+                                 {c02 * id, c12 * id, c22 * id}};
+        for (int I = 0; I < 3; ++I) {
+          double re = 0.0, im = 0.0;
+          for (int L = 0; L < 3; ++L) {
+            re += Ai[I][L] * Q[L].x;
+            im += Ai[I][L] * Q[L].y;
+          }
+          U[I] = make_double2(re, im);
+        }
+      }
+    }
+    // u_1 + i u_2 has spectrum U_1 + i U_2
+    w0[n] = make_double2(U[0].x - U[1].y, U[0].y + U[1].x);
+    if (K.dim == 3) w1[n] = U[2];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_unpack(Consts K, const double2* __restrict__ w0,
+                                                const double2* __restrict__ w1,
+                                                double* __restrict__ u) {
+  const double inv = 1.0 / (double)K.N;
+  for (long long n = (long long)blockIdx.x * 256 + threadIdx.x; n < K.N; n += (long long)gridDim.x * 256) {
+    const double2 a = w0[n];
+    u[n] = a.x * inv;
+    u[K.N + n] = a.y * inv;
+    if (K.dim == 3) u[2 * K.N + n] = w1[n].x * inv;
+  }
+}
+
+int ilog2(int n) {
+  int l = 0;
+  while ((1 << l) < n) ++l;
+  return l;
+}
+
+void fft_dir(const Consts& K, const FftPlan& P, double2* data, int dir, int inverse, hipStream_t s) {
+  const int n = P.n[dir];
+  const int logn = ilog2(n);
+  int lpb = kFftLds / n;
+  if (lpb < 1) lpb = 1;
+  long long nlines, la, lb, lc, pstride;
+  const long long nx = K.nx, ny = K.ny;
+  if (dir == 0) {
+    nlines = ny * K.nz;
+    la = 1;
+    lb = 0;
+    lc = nx;
+    pstride = 1;
+  } else if (dir == 1) {
+    nlines = nx * K.nz;
+    la = nx;
+    lb = 1;
+    lc = nx * ny;
+    pstride = nx;
+  } else {
+    nlines = nx * ny;
+    la = nx * ny;
+    lb = 1;
+    lc = 0;
+    pstride = nx * ny;
+  }
+  if (dir != 0 && lpb > la) lpb = (int)la;  // consecutive lines of a block stay adjacent
+  const long long blocks = (nlines + lpb - 1) / lpb;
+  hipLaunchKernelGGL(k_fft_lines, dim3((unsigned)blocks), dim3(kFftThreads), 0, s, data, n, logn,
+                     pstride, la, lb, lc, nlines, lpb, P.tw[dir], inverse, dir == 0 ? 1 : 0);
+}
+
+void fft_all(const Consts& K, const FftPlan& P, double2* data, int inverse, hipStream_t s) {
+  for (int dir = 0; dir < K.dim; ++dir) fft_dir(K, P, data, dir, inverse, s);
+}
+
+int grid_n(long long n) {
+  long long b = (n + 255) / 256;
+  return (int)(b < 4096 ? b : 4096);
+}
+
+}  // namespace
+
+// u = K^{-1} (r + a Dhat zc) on the displacement block.  work0, work1: 2 N complex each in 3D
+// (N each in 2D).
+void launch_spectral_solve(const Consts& K, const FftPlan& P, const double* r, double a,
+                           const double* zc, double2* work0, double2* work1, double* u,
+                           hipStream_t s) {
+  double2* z0 = work0;
+  double2* z1 = work0 + K.N;
+  double2* w0 = work1;
+  double2* w1 = work1 + K.N;
+  hipLaunchKernelGGL(k_pack, dim3(grid_n(K.N)), dim3(256), 0, s, K, r, a, zc, z0, z1);
+  fft_all(K, P, z0, 0, s);
+  if (K.dim == 3) fft_all(K, P, z1, 0, s);
+  hipLaunchKernelGGL(k_symbol_solve, dim3(grid_n(K.N)), dim3(256), 0, s, K, z0, z1, w0, w1);
+  fft_all(K, P, w0, 1, s);
+  if (K.dim == 3) fft_all(K, P, w1, 1, s);
+  hipLaunchKernelGGL(k_unpack, dim3(grid_n(K.N)), dim3(256), 0, s, K, w0, w1, u);
+}
+
+}  // namespace pf

@@ -1,0 +1,512 @@
+// Stencil kernels of the NSOA-1 step: residual F, local linearisation, matrix-free J v, energy.
+//
+// Scheme (NSOA-1) of Section 3 in d dimensions (tensor-product operators on a periodic grid):
+//   G_c   = G_chem,c(V^{n+1}, V^n) - eps0 sum_I sigma_bar_II - gamma_c Lap_h c_bar
+//   G_eta = G_chem,eta_p(V^{n+1}, V^n)                     - gamma_eta Lap_h eta_bar_p
+//   F_c   = (c^{n+1} - c^n)/dt - div_h(M grad_h G_c),  M_{i+1/2} = kappa (g_i + g_{i+1})/2,
+//           g = c^n (1 - c^n)                     (face mobility at t_n, Section 3)
+//   F_eta = (eta^{n+1} - eta^n)/dt + L_eta G_eta
+//   F_u_I = sum_J Dhat_J sigma_IJ(u^{n+1}, c^{n+1})  (mechanicalequilibrium-dis)
+// G_chem is the discrete variational derivative of the Appendix-A chemical energy:
+// G^1 by product-rule quotients (Appendix B, generalised to eta_1..3) and G^{2,S} from the
+// Taylor-stabilised quotient Psi_S of eq. (D2-1), evaluated in closed form:
+//   Psi_S[a, b] = ln(ybar/(1-ybar)) + P(rho^2) - P(tau^2),  P(x) = sum_{j=1}^{S-1} x^j/(2j(2j+1)),
+//   ybar = (a+b)/2, delta = (a-b)/2, rho = delta/(1-ybar), tau = delta/ybar
+// (the odd Taylor terms Psi^(2j+1)(ybar) delta^(2j) / (2j+1)! summed by derivative order).
+//
+// Layout: SoA planes of N doubles, x fastest; fields c, eta_1..3, u_1..u_d.
+#include "pf_internal.h"
+
+namespace pf {
+
+namespace {
+
+constexpr int kBX = 64, kBY = 4;  // stencil launches: one wave along x, four rows
+
+// ---------------------------------------------------------------------------------
+// indexing
+// ---------------------------------------------------------------------------------
+struct Pt {
+  int i, j, k;
+};
+
+__device__ inline int wrap(int a, int n) {
+  a += (a < 0) ? n : 0;
+  a -= (a >= n) ? n : 0;
+  return a;
+}
+
+__device__ inline long long at(const Consts& K, Pt p, int di, int dj, int dk) {
+  const int i = wrap(p.i + di, K.nx), j = wrap(p.j + dj, K.ny), k = wrap(p.k + dk, K.nz);
+  return (long long)i + (long long)K.nx * ((long long)j + (long long)K.ny * k);
+}
+
+__device__ inline long long at_dir(const Consts& K, Pt p, int dir, int s) {
+  return at(K, p, dir == 0 ? s : 0, dir == 1 ? s : 0, dir == 2 ? s : 0);
+}
+
+__device__ inline Pt shift(Pt p, int dir, int s) {
+  if (dir == 0) p.i += s;
+  else if (dir == 1) p.j += s;
+  else p.k += s;
+  return p;
+}
+
+__device__ inline long long lin(const Consts& K, Pt p) {
+  return (long long)p.i + (long long)K.nx * ((long long)p.j + (long long)K.ny * p.k);
+}
+
+__device__ inline Pt coords(const Consts& K, long long n) {
+  Pt p;
+  p.i = (int)(n % K.nx);
+  const long long t = n / K.nx;
+  p.j = (int)(t % K.ny);
+  p.k = (int)(t / K.ny);
+  return p;
+}
+
+// 2*d+1 point Laplacian of one plane
+__device__ inline double lap(const Consts& K, const double* __restrict__ f, Pt p, double fc) {
+  double s = 0.0;
+  for (int dir = 0; dir < K.dim; ++dir) s += f[at_dir(K, p, dir, 1)] + f[at_dir(K, p, dir, -1)];
+  return (s - 2.0 * K.dim * fc) * K.ih2;
+}
+
+// Dhat_dir of one plane at p (p may be an unwrapped neighbour)
+__device__ inline double dhat(const Consts& K, const double* __restrict__ f, Pt p, int dir) {
+  return (f[at_dir(K, p, dir, 1)] - f[at_dir(K, p, dir, -1)]) * K.i2h;
+}
+
+// sigma_IJ at point p from displacement planes u (d planes) and composition c.
+// xi = 1 includes the eigenstrain -eps0 (c - cbar0) delta_IJ; for a perturbation (J v) the
+// composition enters as -eps0 dc (xi = 1, cref = 0).
+__device__ inline double sigma(const Consts& K, const double* __restrict__ u, long long N,
+                               const double* __restrict__ c, double cref, Pt p, int I, int J) {
+  if (I != J) {
+    return K.C44 * (dhat(K, u + (long long)J * N, p, I) + dhat(K, u + (long long)I * N, p, J));
+  }
+  const double ec = K.eps0 * (c[at(K, p, 0, 0, 0)] - cref);
+  double s = 0.0;
+  for (int L = 0; L < K.dim; ++L) {
+    const double e = dhat(K, u + (long long)L * N, p, L) - ec;
+    s += (L == I ? K.C11 : K.C12) * e;
+  }
+  return s;
+}
+
+// sum_J Dhat_J sigma_IJ at p
+__device__ inline double div_sigma(const Consts& K, const double* __restrict__ u, long long N,
+                                   const double* __restrict__ c, double cref, Pt p, int I) {
+  double s = 0.0;
+  for (int J = 0; J < K.dim; ++J) {
+    s += sigma(K, u, N, c, cref, shift(p, J, 1), I, J) - sigma(K, u, N, c, cref, shift(p, J, -1), I, J);
+  }
+  return s * K.i2h;
+}
+
+// ---------------------------------------------------------------------------------
+// Taylor-stabilised quotient Psi_S[a, b] and its derivative in a
+// ---------------------------------------------------------------------------------
+template <bool D>
+__device__ inline double psi_quot(const Consts& K, double a, double b, double& dq) {
+  const double yb = 0.5 * (a + b), de = 0.5 * (a - b);
+  const double iy = 1.0 / yb, iz = 1.0 / (1.0 - yb);
+  const double rho = de * iz, tau = de * iy;
+  const double x1 = rho * rho, x2 = tau * tau;
+  double p1 = 0.0, p2 = 0.0, d1 = 0.0, d2 = 0.0;
+  for (int j = K.S - 2; j >= 0; --j) {
+    p1 = p1 * x1 + K.qs[j];
+    p2 = p2 * x2 + K.qs[j];
+    if (D) {
+      d1 = d1 * x1 + K.qd[j];
+      d2 = d2 * x2 + K.qd[j];
+    }
+  }
+  if (D) dq = 0.5 * (iy + iz) + d1 * (rho * iz) * (1.0 + rho) - d2 * (tau * iy) * (1.0 - tau);
+  return log(yb * iz) + x1 * p1 - x2 * p2;
+}
+
+// divided difference g[a, b] of g = sum_{m=1}^{deg} co[m] c^m and its derivative in a,
+// via q_1 = 1, q_{m+1} = a q_m + b^m (expanded form: finite at a = b)
+__device__ inline double poly_dd(const double* co, int deg, double a, double b, double& dval) {
+  double q = 1.0, dq = 0.0, bm = b;
+  double val = co[1];
+  dval = 0.0;
+  for (int m = 1; m < deg; ++m) {
+    const double qn = a * q + bm;
+    const double dqn = q + a * dq;
+    q = qn;
+    dq = dqn;
+    bm *= b;
+    val += co[m + 1] * q;
+    dval += co[m + 1] * dq;
+  }
+  return val;
+}
+
+// eta_p appears in phi_k: phi_1 = 1 - (eta_1 + eta_2)/2, phi_2 = 1 - (eta_1 + eta_3)/2,
+// phi_3 = 1 - (eta_2 + eta_3)/2  (Appendix A)
+__device__ inline bool in_phi(int k, int p) {
+  return (k == 0 && p < 2) || (k == 1 && p != 1) || (k == 2 && p > 0);
+}
+
+// Chemical discrete gradient (G_c, G_eta_1..3) and, if JAC, B = d G / d (c, eta_1..3)^{n+1}
+// (row-major 4 x 4).
+template <bool JAC>
+__device__ inline void chem_dg(const Consts& K, double c1, const double* e1, double c0,
+                               const double* e0, double& Gc, double* Ge, double* B) {
+  double f1[3], f0[3];
+  f1[0] = 1.0 - 0.5 * (e1[0] + e1[1]);
+  f1[1] = 1.0 - 0.5 * (e1[0] + e1[2]);
+  f1[2] = 1.0 - 0.5 * (e1[1] + e1[2]);
+  f0[0] = 1.0 - 0.5 * (e0[0] + e0[1]);
+  f0[1] = 1.0 - 0.5 * (e0[0] + e0[2]);
+  f0[2] = 1.0 - 0.5 * (e0[1] + e0[2]);
+  const double S2b = 0.5 * (f1[0] * f1[0] + f1[1] * f1[1] + f1[2] * f1[2] + f0[0] * f0[0] +
+                            f0[1] * f0[1] + f0[2] * f0[2]);
+  const double P3b = 0.5 * (f1[0] * f1[1] * f1[2] + f0[0] * f0[1] * f0[2]);
+  const double Aco[4] = {0.0, 0.0, K.A2, K.A3};
+  const double Bco[4] = {0.0, 0.0, 0.0, K.B3};
+  double dp, dA, dB;
+  const double pq = poly_dd(K.pc, 5, c1, c0, dp);
+  const double Aq = poly_dd(Aco, 3, c1, c0, dA);
+  const double Bq = poly_dd(Bco, 3, c1, c0, dB);
+  const double A1 = (K.A2 + K.A3 * c1) * c1 * c1, A0 = (K.A2 + K.A3 * c0) * c0 * c0;
+  const double Ab = 0.5 * (A1 + A0), Bb = 0.5 * K.B3 * (c1 * c1 * c1 + c0 * c0 * c0);
+  // G^1: product-rule quotients
+  Gc = pq + S2b * Aq + P3b * Bq;
+  double T[3], Gphi[3];
+  for (int k = 0; k < 3; ++k) {
+    const int a = (k == 0) ? 1 : 0, b = (k == 2) ? 1 : 2;
+    T[k] = (f0[a] * f0[b] + f1[a] * f1[b]) * (1.0 / 3.0) + (f0[a] * f1[b] + f1[a] * f0[b]) * (1.0 / 6.0);
+    Gphi[k] = Ab * (f1[k] + f0[k]) + Bb * T[k];
+  }
+  for (int p = 0; p < 3; ++p) {
+    double s = 0.0;
+    for (int k = 0; k < 3; ++k)
+      if (in_phi(k, p)) s += Gphi[k];
+    Ge[p] = -0.5 * s;
+  }
+  // G^{2,S}: y_i = c eta_i, eta_4 = 4 - eta_1 - eta_2 - eta_3
+  double y1[4], y0[4], eb[4], Q[4], dQ[4];
+  const double e14 = 4.0 - e1[0] - e1[1] - e1[2], e04 = 4.0 - e0[0] - e0[1] - e0[2];
+  for (int i = 0; i < 4; ++i) {
+    const double a1 = (i < 3) ? e1[i] : e14, a0 = (i < 3) ? e0[i] : e04;
+    y1[i] = c1 * a1;
+    y0[i] = c0 * a0;
+    eb[i] = 0.5 * (a1 + a0);
+    Q[i] = psi_quot<JAC>(K, y1[i], y0[i], dQ[i]);
+  }
+  double dQc = 0.0;
+  const double Qc = (K.w_c != 0.0) ? psi_quot<JAC>(K, c1, c0, dQc) : 0.0;
+  const double cb = 0.5 * (c1 + c0);
+  Gc += K.theta * (K.w_c * Qc + 0.25 * (eb[0] * Q[0] + eb[1] * Q[1] + eb[2] * Q[2] + eb[3] * Q[3]));
+  for (int p = 0; p < 3; ++p) Ge[p] += 0.25 * K.theta * cb * (Q[p] - Q[3]);
+
+  if (JAC) {
+    const double a1[4] = {e1[0], e1[1], e1[2], e14};
+    // row c
+    B[0] = dp + S2b * dA + P3b * dB +
+           K.theta * (K.w_c * dQc + 0.25 * (eb[0] * dQ[0] * a1[0] + eb[1] * dQ[1] * a1[1] +
+                                            eb[2] * dQ[2] * a1[2] + eb[3] * dQ[3] * a1[3]));
+    for (int p = 0; p < 3; ++p) {
+      double dS2 = 0.0, dP3 = 0.0;
+      for (int k = 0; k < 3; ++k) {
+        if (!in_phi(k, p)) continue;
+        const int a = (k == 0) ? 1 : 0, b = (k == 2) ? 1 : 2;
+        dS2 += -f1[k];               // d(phi_k^2)/d eta_p /2 ... times 1/2 from the average: see below
+        dP3 += -0.5 * f1[a] * f1[b];
+      }
+      // S2b = (S2^1 + S2^0)/2: d S2b/d eta_p = (1/2) sum_k 2 phi_k^1 (-1/2) = -(1/2) sum_k phi_k^1
+      // P3b: d P3b / d eta_p = (1/2) sum_k (-1/2) prod_{l != k} phi_l^1
+      B[1 + p] = 0.5 * dS2 * Aq + 0.5 * dP3 * Bq +
+                 0.25 * K.theta * (0.5 * Q[p] + eb[p] * dQ[p] * c1 - 0.5 * Q[3] - eb[3] * dQ[3] * c1);
+    }
+    // rows eta_p
+    const double dA1 = (2.0 * K.A2 + 3.0 * K.A3 * c1) * c1;  // A'(c^{n+1})
+    const double dB1 = 3.0 * K.B3 * c1 * c1;                  // B'(c^{n+1})
+    for (int p = 0; p < 3; ++p) {
+      double sc = 0.0;
+      for (int k = 0; k < 3; ++k)
+        if (in_phi(k, p)) sc += 0.5 * dA1 * (f1[k] + f0[k]) + 0.5 * dB1 * T[k];
+      B[4 * (1 + p)] = -0.5 * sc + 0.25 * K.theta * (0.5 * (Q[p] - Q[3]) + cb * (dQ[p] * a1[p] - dQ[3] * e14));
+      for (int q = 0; q < 3; ++q) {
+        double s = 0.0;
+        for (int k = 0; k < 3; ++k) {
+          if (!in_phi(k, p)) continue;
+          const int a = (k == 0) ? 1 : 0, b = (k == 2) ? 1 : 2;
+          // d phi_k / d eta_q = -1/2 if eta_q in phi_k
+          double dT = 0.0;
+          if (in_phi(a, q)) dT += -0.5 * (f1[b] * (1.0 / 3.0) + f0[b] * (1.0 / 6.0));
+          if (in_phi(b, q)) dT += -0.5 * (f1[a] * (1.0 / 3.0) + f0[a] * (1.0 / 6.0));
+          s += Ab * (in_phi(k, q) ? -0.5 : 0.0) + Bb * dT;
+        }
+        B[4 * (1 + p) + 1 + q] = -0.5 * s + 0.25 * K.theta * cb * ((p == q ? dQ[p] * c1 : 0.0) + dQ[3] * c1);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// residual
+// ---------------------------------------------------------------------------------
+// pass 1: G_c, G_eta (4 planes) and F_u
+__global__ __launch_bounds__(kBX* kBY) void k_residual_g(Consts K, const double* __restrict__ X,
+                                                         const double* __restrict__ Xn,
+                                                         double* __restrict__ G4,
+                                                         double* __restrict__ F) {
+  Pt p{(int)(blockIdx.x * kBX + threadIdx.x), (int)(blockIdx.y * kBY + threadIdx.y), (int)blockIdx.z};
+  if (p.i >= K.nx || p.j >= K.ny) return;
+  const long long N = K.N, n = lin(K, p);
+  const double c1 = X[n], c0 = Xn[n];
+  double e1[3], e0[3], Gc, Ge[3];
+  for (int q = 0; q < 3; ++q) {
+    e1[q] = X[(1 + q) * N + n];
+    e0[q] = Xn[(1 + q) * N + n];
+  }
+  chem_dg<false>(K, c1, e1, c0, e0, Gc, Ge, nullptr);
+  // elastic part of G_c: -eps0 * (sum_I sigma_II^{n+1} + sum_I sigma_II^n) / 2
+  if (K.elastic) {
+    double div1 = 0.0, div0 = 0.0;
+    for (int I = 0; I < K.dim; ++I) {
+      div1 += dhat(K, X + (4 + I) * N, p, I);
+      div0 += dhat(K, Xn + (4 + I) * N, p, I);
+    }
+    const double tr1 = K.Ctr * (div1 - K.dim * K.eps0 * (c1 - K.cbar0));
+    const double tr0 = K.Ctr * (div0 - K.dim * K.eps0 * (c0 - K.cbar0));
+    Gc -= K.eps0 * 0.5 * (tr1 + tr0);
+  }
+  Gc -= K.gamma_c * 0.5 * (lap(K, X, p, c1) + lap(K, Xn, p, c0));
+  G4[n] = Gc;
+  for (int q = 0; q < 3; ++q) {
+    Ge[q] -= K.gamma_eta * 0.5 * (lap(K, X + (1 + q) * N, p, e1[q]) + lap(K, Xn + (1 + q) * N, p, e0[q]));
+    G4[(1 + q) * N + n] = Ge[q];
+  }
+  for (int I = 0; I < K.dim; ++I) {
+    F[(4 + I) * N + n] = K.elastic ? div_sigma(K, X + 4 * N, N, X, K.cbar0, p, I) : X[(4 + I) * N + n];
+  }
+}
+
+__device__ inline double block_sum(double v, double* lds) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) lds[wave] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r += lds[w];
+  return r;
+}
+
+// div_h (M grad_h g) at p with face mobilities from g_n = c^n (1 - c^n)
+__device__ inline double div_M_grad(const Consts& K, const double* __restrict__ g,
+                                    const double* __restrict__ cn, Pt p, long long n) {
+  const double gc = g[n];
+  const double mc = cn[n] * (1.0 - cn[n]);
+  double s = 0.0;
+  for (int dir = 0; dir < K.dim; ++dir) {
+    const long long np = at_dir(K, p, dir, 1), nm = at_dir(K, p, dir, -1);
+    const double Mp = 0.5 * K.kappa * (mc + cn[np] * (1.0 - cn[np]));
+    const double Mm = 0.5 * K.kappa * (mc + cn[nm] * (1.0 - cn[nm]));
+    s += Mp * (g[np] - gc) - Mm * (gc - g[nm]);
+  }
+  return s * K.ih2;
+}
+
+// pass 2: F_c, F_eta; partial[0] = ||F||^2, partial[1] = number of nodes outside the log domain
+__global__ __launch_bounds__(256) void k_residual_f(Consts K, double dt, const double* __restrict__ X,
+                                                    const double* __restrict__ Xn,
+                                                    const double* __restrict__ G4,
+                                                    double* __restrict__ F,
+                                                    double* __restrict__ partial) {
+  __shared__ double lds[4];
+  const long long N = K.N;
+  const double idt = 1.0 / dt;
+  double nrm = 0.0, bad = 0.0;
+  for (long long n = (long long)blockIdx.x * 256 + threadIdx.x; n < N; n += (long long)gridDim.x * 256) {
+    const Pt p = coords(K, n);
+    const double c1 = X[n];
+    const double fc = (c1 - Xn[n]) * idt - div_M_grad(K, G4, Xn, p, n);
+    F[n] = fc;
+    nrm += fc * fc;
+    bool ok = (c1 > 0.0 && c1 < 1.0);
+    double esum = 0.0;
+    for (int q = 0; q < 3; ++q) {
+      const double e1 = X[(1 + q) * N + n];
+      const double fe = (e1 - Xn[(1 + q) * N + n]) * idt + K.L_eta * G4[(1 + q) * N + n];
+      F[(1 + q) * N + n] = fe;
+      nrm += fe * fe;
+      esum += e1;
+      const double y = c1 * e1;
+      ok = ok && (y > 0.0 && y < 1.0);
+    }
+    const double y4 = c1 * (4.0 - esum);
+    ok = ok && (y4 > 0.0 && y4 < 1.0);
+    for (int I = 0; I < K.dim; ++I) {
+      const double fu = F[(4 + I) * N + n];
+      nrm += fu * fu;
+    }
+    bad += ok ? 0.0 : 1.0;
+  }
+  const double s0 = block_sum(nrm, lds);
+  const double s1 = block_sum(bad, lds);
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x] = s0;
+    partial[kRedBlocks + blockIdx.x] = s1;
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// linearisation: B = d G_chem / d V^{n+1}, 16 planes (row-major 4 x 4 per node)
+// ---------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_linearise(Consts K, const double* __restrict__ X,
+                                                   const double* __restrict__ Xn,
+                                                   double* __restrict__ B) {
+  const long long N = K.N;
+  for (long long n = (long long)blockIdx.x * 256 + threadIdx.x; n < N; n += (long long)gridDim.x * 256) {
+    double e1[3], e0[3], Ge[3], Gc, b[16];
+    for (int q = 0; q < 3; ++q) {
+      e1[q] = X[(1 + q) * N + n];
+      e0[q] = Xn[(1 + q) * N + n];
+    }
+    chem_dg<true>(K, X[n], e1, Xn[n], e0, Gc, Ge, b);
+    for (int q = 0; q < 16; ++q) B[q * N + n] = b[q];
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// matrix-free Jacobian-vector product
+//   dG_c   = B_c. v + kel v_c - (eps0/2) Ctr div_h v_u - (gamma_c/2) Lap_h v_c
+//   (Jv)_c = v_c/dt - div_h(M grad_h dG_c)
+//   (Jv)_e = v_e/dt + L_eta (B_e. v - (gamma_eta/2) Lap_h v_e)
+//   (Jv)_u = sum_J Dhat_J sigma_IJ(v_u, v_c)   (composition enters through -eps0 v_c)
+// ---------------------------------------------------------------------------------
+__global__ __launch_bounds__(kBX* kBY) void k_jv_g(Consts K, double dt, const double* __restrict__ B,
+                                                   const double* __restrict__ v,
+                                                   double* __restrict__ dG,
+                                                   double* __restrict__ w) {
+  Pt p{(int)(blockIdx.x * kBX + threadIdx.x), (int)(blockIdx.y * kBY + threadIdx.y), (int)blockIdx.z};
+  if (p.i >= K.nx || p.j >= K.ny) return;
+  const long long N = K.N, n = lin(K, p);
+  double vv[4];
+  for (int q = 0; q < 4; ++q) vv[q] = v[q * N + n];
+  double g = K.kel * vv[0] - 0.5 * K.gamma_c * lap(K, v, p, vv[0]);
+  for (int q = 0; q < 4; ++q) g += B[q * N + n] * vv[q];
+  if (K.elastic) {
+    double div = 0.0;
+    for (int I = 0; I < K.dim; ++I) div += dhat(K, v + (4 + I) * N, p, I);
+    g -= 0.5 * K.eps0 * K.Ctr * div;
+  }
+  dG[n] = g;
+  const double idt = 1.0 / dt;
+  for (int e = 0; e < 3; ++e) {
+    double s = -0.5 * K.gamma_eta * lap(K, v + (1 + e) * N, p, vv[1 + e]);
+    for (int q = 0; q < 4; ++q) s += B[(4 * (1 + e) + q) * N + n] * vv[q];
+    w[(1 + e) * N + n] = vv[1 + e] * idt + K.L_eta * s;
+  }
+  for (int I = 0; I < K.dim; ++I) {
+    w[(4 + I) * N + n] = K.elastic ? div_sigma(K, v + 4 * N, N, v, 0.0, p, I) : v[(4 + I) * N + n];
+  }
+}
+
+__global__ __launch_bounds__(kBX* kBY) void k_jv_c(Consts K, double dt, const double* __restrict__ cn,
+                                                   const double* __restrict__ v,
+                                                   const double* __restrict__ dG,
+                                                   double* __restrict__ w) {
+  Pt p{(int)(blockIdx.x * kBX + threadIdx.x), (int)(blockIdx.y * kBY + threadIdx.y), (int)blockIdx.z};
+  if (p.i >= K.nx || p.j >= K.ny) return;
+  const long long n = lin(K, p);
+  w[n] = v[n] / dt - div_M_grad(K, dG, cn, p, n);
+}
+
+// ---------------------------------------------------------------------------------
+// energy (eqs. (relations)/(freeenergy)) and mass; partial: chem, elastic, interfacial, sum c
+// ---------------------------------------------------------------------------------
+__device__ inline double psi(double z) { return z * log(z) + (1.0 - z) * log(1.0 - z); }
+
+__global__ __launch_bounds__(256) void k_energy(Consts K, const double* __restrict__ X,
+                                                double* __restrict__ partial) {
+  __shared__ double lds[4];
+  const long long N = K.N;
+  double ech = 0.0, eel = 0.0, ein = 0.0, mc = 0.0;
+  for (long long n = (long long)blockIdx.x * 256 + threadIdx.x; n < N; n += (long long)gridDim.x * 256) {
+    const Pt p = coords(K, n);
+    const double c = X[n];
+    double e[4], f[3];
+    e[0] = X[N + n];
+    e[1] = X[2 * N + n];
+    e[2] = X[3 * N + n];
+    e[3] = 4.0 - e[0] - e[1] - e[2];
+    f[0] = 1.0 - 0.5 * (e[0] + e[1]);
+    f[1] = 1.0 - 0.5 * (e[0] + e[2]);
+    f[2] = 1.0 - 0.5 * (e[1] + e[2]);
+    double pv = 0.0;
+    for (int m = 5; m >= 0; --m) pv = pv * c + K.pc[m];
+    const double Av = (K.A2 + K.A3 * c) * c * c, Bv = K.B3 * c * c * c;
+    double ideal = K.w_c * psi(c);
+    for (int i = 0; i < 4; ++i) ideal += 0.25 * psi(c * e[i]);
+    ech += pv + Av * (f[0] * f[0] + f[1] * f[1] + f[2] * f[2]) + Bv * f[0] * f[1] * f[2] + K.theta * ideal;
+    // elastic: eps^el : sigma / 2
+    if (K.elastic) {
+      double s = 0.0;
+      for (int I = 0; I < K.dim; ++I)
+        for (int J = 0; J < K.dim; ++J) {
+          double eij = 0.5 * (dhat(K, X + (4 + I) * N, p, J) + dhat(K, X + (4 + J) * N, p, I));
+          if (I == J) eij -= K.eps0 * (c - K.cbar0);
+          s += eij * sigma(K, X + 4 * N, N, X, K.cbar0, p, I, J);
+        }
+      eel += 0.5 * s;
+    }
+    // interfacial: gamma/2 sum_k ((D+ w)^2 + (D- w)^2)/2
+    for (int fld = 0; fld < 4; ++fld) {
+      const double* w = X + fld * N;
+      const double gam = (fld == 0) ? K.gamma_c : K.gamma_eta;
+      const double wc = w[n];
+      double s = 0.0;
+      for (int dir = 0; dir < K.dim; ++dir) {
+        const double dp = (w[at_dir(K, p, dir, 1)] - wc) * K.ih, dm = (wc - w[at_dir(K, p, dir, -1)]) * K.ih;
+        s += 0.5 * (dp * dp + dm * dm);
+      }
+      ein += 0.5 * gam * s;
+    }
+    mc += c;
+  }
+  const double a = block_sum(ech, lds), b = block_sum(eel, lds), cc = block_sum(ein, lds),
+               d = block_sum(mc, lds);
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x] = a;
+    partial[kRedBlocks + blockIdx.x] = b;
+    partial[2 * kRedBlocks + blockIdx.x] = cc;
+    partial[3 * kRedBlocks + blockIdx.x] = d;
+  }
+}
+
+dim3 stencil_grid(const Consts& K) {
+  return dim3((K.nx + kBX - 1) / kBX, (K.ny + kBY - 1) / kBY, K.nz);
+}
+
+}  // namespace
+
+void launch_residual(const Consts& K, double dt, const double* X, const double* Xn, double* G4,
+                     double* F, double* partial, hipStream_t s) {
+  hipLaunchKernelGGL(k_residual_g, stencil_grid(K), dim3(kBX, kBY), 0, s, K, X, Xn, G4, F);
+  hipLaunchKernelGGL(k_residual_f, dim3(kRedBlocks), dim3(256), 0, s, K, dt, X, Xn, G4, F, partial);
+}
+
+void launch_linearise(const Consts& K, const double* X, const double* Xn, double* B, hipStream_t s) {
+  long long nb = (K.N + 255) / 256;
+  hipLaunchKernelGGL(k_linearise, dim3((unsigned)(nb < 4096 ? nb : 4096)), dim3(256), 0, s, K, X, Xn, B);
+}
+
+void launch_jv(const Consts& K, double dt, const double* B, const double* cn, const double* v,
+               double* dG, double* w, hipStream_t s) {
+  hipLaunchKernelGGL(k_jv_g, stencil_grid(K), dim3(kBX, kBY), 0, s, K, dt, B, v, dG, w);
+  hipLaunchKernelGGL(k_jv_c, stencil_grid(K), dim3(kBX, kBY), 0, s, K, dt, cn, v, dG, w);
+}
+
+void launch_energy(const Consts& K, const double* X, double* partial, hipStream_t s) {
+  hipLaunchKernelGGL(k_energy, dim3(kRedBlocks), dim3(256), 0, s, K, X, partial);
+}
+
+}  // namespace pf

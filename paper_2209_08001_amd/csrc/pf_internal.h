@@ -1,0 +1,88 @@
+// Internal declarations of the pfnks library: the per-problem constant block the kernels
+// read and the host-side launch wrappers.  Not part of the public ABI (include/pfnks.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace pf {
+
+constexpr int kMaxS = 30;         // largest order of the Psi_S quotient
+constexpr int kRedBlocks = 1024;  // partial sums of the two-stage grid reductions
+constexpr int kMaxRed = 80;       // values reduced in one pass (GMRES multi-dot: j + 2 <= 66)
+
+// Everything a kernel needs to know about the grid and the model.  Passed by value.
+struct Consts {
+  int dim;
+  int nx, ny, nz;        // nodes per direction (nz = 1 in 2D)
+  long long N;           // nodes
+  double h, ih, ih2;     // h, 1/h, 1/h^2
+  double i2h;            // 1/(2h)
+  // chemical energy, dimensionless (Appendix A)
+  double pc[6];          // p(c) = sum pc[m] c^m   (e0 c + c(1-c) sum L_k (2c-1)^k)
+  double A2, A3;         // A(c) = A2 c^2 + A3 c^3  (sum phi^2 coefficient)
+  double B3;             // B(c) = B3 c^3           (phi1 phi2 phi3 coefficient)
+  double theta, w_c;
+  double gamma_c, gamma_eta, kappa, L_eta;
+  double eps0, cbar0;
+  double C11, C12, C44;  // already multiplied by Lscale
+  double Ctr;            // C11 + (d-1) C12: sum_I sigma_II = Ctr * trace(eps)
+  double kel;            // (d/2) eps0^2 Ctr: d/dc^{n+1} of -eps0 * trace(sigma_bar)
+  int elastic;           // 0: Lscale = 0, the displacement rows become u = 0
+  int S;
+  double qs[kMaxS];      // qs[j-1] = 1/(2j(2j+1)), j = 1..S-1  (coefficients of P)
+  double qd[kMaxS];      // qd[j-1] = 1/(2(2j+1))               (coefficients of P')
+};
+
+// ---- phase-field kernels (kernels_phase.hip) ---------------------------------------
+// X, Xn: nf planes (c, eta1..3, u1..ud); all plane strides are N.
+void launch_residual(const Consts& K, double dt, const double* X, const double* Xn, double* G4,
+                     double* F, double* partial, hipStream_t s);
+void launch_linearise(const Consts& K, const double* X, const double* Xn, double* B,
+                      hipStream_t s);
+void launch_jv(const Consts& K, double dt, const double* B, const double* cn, const double* v,
+               double* dG, double* w, hipStream_t s);
+void launch_energy(const Consts& K, const double* X, double* partial, hipStream_t s);
+
+// ---- Schwarz tile solve (kernels_ras.hip) -------------------------------------------
+struct TileCfg {
+  int tx, ty, tz;   // owned tile
+  int ov;           // overlap delta
+  int sweeps;       // symmetric GS sweeps
+  int with_u;       // 1: all fields (plain RAS); 0: (c, eta) block only
+};
+void launch_ras(const Consts& K, const TileCfg& T, double dt, const double* B, const double* cn,
+                const double* r, double* z, hipStream_t s);
+size_t ras_lds_bytes(const Consts& K, const TileCfg& T);
+
+// ---- spectral displacement solve (kernels_fft.hip) -----------------------------------
+struct FftPlan {
+  int n[3];
+  const double2* tw[3];  // twiddles exp(-2 pi i k / n), k < n/2, one table per direction
+};
+// q_I = r_I + a D-hat_I zc (r may be null), solve K u = q by FFT, write u (d planes).
+void launch_spectral_solve(const Consts& K, const FftPlan& P, const double* r, double a,
+                           const double* zc, double2* work0, double2* work1, double* u,
+                           hipStream_t s);
+
+// ---- vector kernels and reductions (kernels_blas.hip) --------------------------------
+// V: nv vectors of length n stored ldv apart
+void launch_multidot(long long n, int nv, const double* V, long long ldv, const double* w,
+                     double* partial, hipStream_t s);
+void launch_update(long long n, int nv, const double* V, long long ldv, const double* coef,
+                   const double* w, double scale, double* out, double* partial, hipStream_t s);
+void launch_lincomb(long long n, int nv, const double* V, long long ldv, const double* coef,
+                    double beta, double* out, hipStream_t s);
+void launch_axpby(long long n, double a, const double* x, double b, const double* y, double* out,
+                  hipStream_t s);
+void launch_finalize(const double* partial, int nvals, double* out, hipStream_t s);
+void launch_sum2(long long n, const double* x, const double* y, const double* yn, double* partial,
+                 hipStream_t s);
+void launch_trial(const Consts& K, int nf, const double* X, const double* S, double lam,
+                  double shift, double* Xt, double* partial, hipStream_t s);
+void launch_dx2(long long n4, const double* X, const double* Xn, double* partial, hipStream_t s);
+void launch_class_sums(const Consts& K, const double* u, double* partial, hipStream_t s);
+void launch_class_shift(const Consts& K, double* u, const double* sums, hipStream_t s);
+
+}  // namespace pf

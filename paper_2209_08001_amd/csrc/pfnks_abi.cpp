@@ -1,0 +1,730 @@
+// C ABI of the pfnks library (include/pfnks.h): problem set-up, the Newton-Krylov-Schwarz
+// step of Section 4 of Huang & Yang, and the energy / mass queries.
+//
+// Host code drives the kernels on one HIP stream.  Scalars cross to the host once per GMRES
+// iteration (the Hessenberg column), once per residual evaluation and once per reduction of
+// the step close; all vectors stay in the caller's device workspace.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/pfnks.h"
+#include "pf_internal.h"
+
+using pf::Consts;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int device_error(hipError_t e, const char* what) {
+  g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+  return PFNKS_EDEVICE;
+}
+
+#define HIPCHK(call)                                       \
+  do {                                                     \
+    hipError_t e_ = (call);                                \
+    if (e_ != hipSuccess) return device_error(e_, #call);  \
+  } while (0)
+
+bool is_pow2(int n) { return n >= 2 && (n & (n - 1)) == 0; }
+
+// ---------------------------------------------------------------------------------------
+// workspace layout
+// ---------------------------------------------------------------------------------------
+struct Layout {
+  size_t off[32];
+  size_t total;
+};
+
+enum Buf {
+  B_X, B_XN, B_XT, B_F, B_FT, B_S, B_B, B_BPC, B_G4, B_DG, B_V, B_W, B_Z, B_TMP, B_PART, B_RED,
+  B_FFT0, B_FFT1, B_TW0, B_TW1, B_TW2, B_COUNT
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+Layout make_layout(int dim, long long N, int restart, const int* n) {
+  const int nf = 4 + dim;
+  const size_t vec = sizeof(double) * (size_t)nf * N;
+  size_t sz[B_COUNT];
+  sz[B_X] = sz[B_XN] = sz[B_XT] = sz[B_F] = sz[B_FT] = sz[B_S] = vec;
+  sz[B_B] = sz[B_BPC] = sizeof(double) * 16 * (size_t)N;
+  sz[B_G4] = sizeof(double) * 4 * (size_t)N;
+  sz[B_DG] = sizeof(double) * (size_t)N;
+  sz[B_V] = vec * (size_t)(restart + 1);
+  sz[B_W] = sz[B_Z] = sz[B_TMP] = vec;
+  sz[B_PART] = sizeof(double) * (size_t)pf::kRedBlocks * pf::kMaxRed;
+  sz[B_RED] = sizeof(double) * pf::kMaxRed;
+  const size_t cplx = sizeof(double2) * (size_t)N * (dim == 3 ? 2 : 1);
+  sz[B_FFT0] = sz[B_FFT1] = cplx;
+  sz[B_TW0] = sizeof(double2) * (size_t)(n[0] / 2 + 1);
+  sz[B_TW1] = sizeof(double2) * (size_t)(n[1] / 2 + 1);
+  sz[B_TW2] = sizeof(double2) * (size_t)((dim == 3 ? n[2] : 2) / 2 + 1);
+  Layout L{};
+  size_t o = 0;
+  for (int b = 0; b < B_COUNT; ++b) {
+    L.off[b] = o;
+    o += align256(sz[b]);
+  }
+  L.total = o;
+  return L;
+}
+
+int validate(const pfnks_grid* g, const pfnks_model* m, const pfnks_solver* s) {
+  if (!g || !m || !s) return PFNKS_EINVAL;
+  if (g->dim != 2 && g->dim != 3) return PFNKS_EINVAL;
+  if (!(g->h > 0.0)) return PFNKS_EINVAL;
+  for (int k = 0; k < g->dim; ++k) {
+    if (!is_pow2(g->n[k]) || g->n[k] < 4) return PFNKS_EINVAL;  // FFT sizes, even parity classes
+    const int t = s->tile[k];
+    if (t <= 0 || g->n[k] % t != 0) return PFNKS_EINVAL;
+    if (t + 2 * s->overlap > g->n[k]) return PFNKS_EINVAL;
+  }
+  if (g->dim == 2 && g->n[2] != 1) return PFNKS_EINVAL;
+  if (s->overlap < 0 || s->overlap > 4) return PFNKS_EINVAL;
+  if (s->gmres_restart < 1 || s->gmres_restart > 64) return PFNKS_EINVAL;
+  if (s->sweeps < 1 || s->sweeps > 16) return PFNKS_EINVAL;
+  if (s->newton_maxit < 1 || s->gmres_maxit < 1) return PFNKS_EINVAL;
+  if (s->pc < 0 || s->pc > 3) return PFNKS_EINVAL;
+  if (s->precision != PFNKS_FP64) return PFNKS_EINVAL;
+  if (m->S < 1 || m->S > pf::kMaxS) return PFNKS_EINVAL;
+  if (!(m->kappa >= 0.0) || !(m->L_eta > 0.0) || m->Lscale < 0.0) return PFNKS_EINVAL;
+  // extended tile must fit the kernel's registers (<= 4 nodes per thread of 512) and the
+  // 160 KiB of LDS of one compute unit
+  long long ext = 1, zpad = 1, dpad = 1;
+  for (int k = 0; k < g->dim; ++k) {
+    ext *= s->tile[k] + 2 * s->overlap;
+    zpad *= s->tile[k] + 2 * s->overlap + 4;
+    dpad *= s->tile[k] + 2 * s->overlap + 2;
+  }
+  if (ext > 4 * 512) return PFNKS_EINVAL;
+  const int nfz = (s->pc == PFNKS_PC_RAS) ? 4 + g->dim : 4;
+  if (s->pc <= PFNKS_PC_RAS_SPECTRAL && 8 * (nfz * zpad + 2 * dpad) > 160 * 1024) return PFNKS_EINVAL;
+  return PFNKS_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------
+// problem
+// ---------------------------------------------------------------------------------------
+struct pfnks_problem {
+  pfnks_grid grid;
+  pfnks_model model;
+  pfnks_solver solver;
+  Consts K;
+  pf::TileCfg T;
+  pf::FftPlan plan;
+  int nf;
+  long long N, nvec;
+  hipStream_t stream;
+  char* ws;
+  double *X, *Xn, *Xt, *F, *Ft, *S, *B, *Bpc, *G4, *dG, *V, *w, *z, *tmp, *part, *red;
+  double2 *fft0, *fft1;
+  double* hbuf;  // pinned host scalars
+  double t;
+  long long launches, syncs;
+};
+
+namespace {
+
+void make_consts(pfnks_problem* p) {
+  Consts& K = p->K;
+  std::memset(&K, 0, sizeof(K));
+  const pfnks_grid& g = p->grid;
+  const pfnks_model& m = p->model;
+  K.dim = g.dim;
+  K.nx = g.n[0];
+  K.ny = g.n[1];
+  K.nz = (g.dim == 3) ? g.n[2] : 1;
+  K.N = (long long)K.nx * K.ny * K.nz;
+  K.h = g.h;
+  K.ih = 1.0 / g.h;
+  K.ih2 = 1.0 / (g.h * g.h);
+  K.i2h = 0.5 / g.h;
+  // p(c) = e0 c + c (1 - c) sum_k L_k (2c - 1)^k, expanded to monomials
+  double poly[6] = {0, 0, 0, 0, 0, 0};
+  double pw[6] = {1, 0, 0, 0, 0, 0};  // (2c - 1)^k
+  for (int k = 0; k < 4; ++k) {
+    // add L_k * (c - c^2) * pw
+    for (int a = 0; a < 4; ++a) {
+      poly[a + 1] += m.L[k] * pw[a];
+      poly[a + 2] -= m.L[k] * pw[a];
+    }
+    double nxt[6] = {0, 0, 0, 0, 0, 0};
+    for (int a = 0; a < 5; ++a) {
+      nxt[a + 1] += 2.0 * pw[a];
+      nxt[a] -= pw[a];
+    }
+    std::memcpy(pw, nxt, sizeof(pw));
+  }
+  poly[1] += m.e0;
+  for (int a = 0; a < 6; ++a) K.pc[a] = poly[a];
+  K.A2 = 4.0 * m.U1 + 12.0 * m.U4;
+  K.A3 = -24.0 * m.U4;
+  K.B3 = -48.0 * m.U4;
+  K.theta = m.theta;
+  K.w_c = m.w_c;
+  K.gamma_c = m.gamma_c;
+  K.gamma_eta = m.gamma_eta;
+  K.kappa = m.kappa;
+  K.L_eta = m.L_eta;
+  K.eps0 = m.eps0;
+  K.C11 = m.Lscale * m.C11;
+  K.C12 = m.Lscale * m.C12;
+  K.C44 = m.Lscale * m.C44;
+  K.Ctr = K.C11 + (g.dim - 1) * K.C12;
+  K.kel = 0.5 * g.dim * m.eps0 * m.eps0 * K.Ctr;
+  K.elastic = (m.Lscale != 0.0) ? 1 : 0;
+  K.S = m.S;
+  for (int j = 1; j <= m.S - 1; ++j) {
+    K.qs[j - 1] = 1.0 / (2.0 * j * (2.0 * j + 1.0));
+    K.qd[j - 1] = 1.0 / (2.0 * (2.0 * j + 1.0));
+  }
+}
+
+// finalize partial sums of nvals values and copy them to p->hbuf
+int reduce_to_host(pfnks_problem* p, int nvals) {
+  pf::launch_finalize(p->part, nvals, p->red, p->stream);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(p->hbuf, p->red, sizeof(double) * nvals, hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  p->launches += 1;
+  p->syncs += 1;
+  return PFNKS_OK;
+}
+
+// F = F(X; Xn, dt); returns ||F|| and the count of out-of-domain nodes
+int residual(pfnks_problem* p, const double* X, double dt, double* F, double* nrm, double* bad) {
+  pf::launch_residual(p->K, dt, X, p->Xn, p->G4, F, p->part, p->stream);
+  p->launches += 2;
+  int st = reduce_to_host(p, 2);
+  if (st) return st;
+  *nrm = std::sqrt(p->hbuf[0]);
+  *bad = p->hbuf[1];
+  return PFNKS_OK;
+}
+
+int dot_norm(pfnks_problem* p, const double* x, double* nrm) {
+  pf::launch_multidot(p->nvec, 0, x, 0, x, p->part, p->stream);
+  p->launches += 1;
+  int st = reduce_to_host(p, 1);
+  if (st) return st;
+  *nrm = std::sqrt(p->hbuf[0]);
+  return PFNKS_OK;
+}
+
+// z = M^{-1} r with the lagged preconditioner blocks Bpc
+void pc_apply(pfnks_problem* p, double dt, const double* r, double* z) {
+  const long long N = p->N;
+  const int pc = p->solver.pc;
+  if (pc == PFNKS_PC_RAS) {
+    pf::TileCfg T = p->T;
+    T.with_u = 1;
+    pf::launch_ras(p->K, T, dt, p->Bpc, p->Xn, r, z, p->stream);
+    p->launches += 1;
+    return;
+  }
+  if (pc == PFNKS_PC_RAS_SPECTRAL) {
+    pf::TileCfg T = p->T;
+    T.with_u = 0;
+    pf::launch_ras(p->K, T, dt, p->Bpc, p->Xn, r, z, p->stream);
+    p->launches += 1;
+  } else {
+    // 2 (no preconditioner) and 3 (spectral displacement block only): z_w = r_w
+    pf::launch_axpby(4 * N, 1.0, r, 0.0, nullptr, z, p->stream);
+    p->launches += 1;
+  }
+  if (pc == 2) {
+    pf::launch_axpby((long long)p->K.dim * N, 1.0, r + 4 * N, 0.0, nullptr, z + 4 * N, p->stream);
+    p->launches += 1;
+    return;
+  }
+  // displacement block: z_u = K^{-1} (r_u - J_uc z_c) = K^{-1} (r_u + eps0 Ctr Dhat z_c)
+  pf::launch_spectral_solve(p->K, p->plan, r + 4 * N, p->K.eps0 * p->K.Ctr, z, p->fft0, p->fft1,
+                            z + 4 * N, p->stream);
+  p->launches += 3 + 4 * p->K.dim * (p->K.dim == 3 ? 2 : 1);
+}
+
+void jv(pfnks_problem* p, double dt, const double* Bm, const double* v, double* w) {
+  pf::launch_jv(p->K, dt, Bm, p->Xn, v, p->dG, w, p->stream);
+  p->launches += 2;
+}
+
+// Solve J S = -F (right-preconditioned restarted GMRES, classical Gram-Schmidt with a second
+// pass when cancellation is severe).  Returns status; *its = iterations; *ok = converged.
+int gmres(pfnks_problem* p, double dt, const double* Bm, double fnorm, double tol, int* its,
+          int* ok) {
+  const long long n = p->nvec;
+  const int m = p->solver.gmres_restart;
+  const int maxit = p->solver.gmres_maxit;
+  double* V = p->V;
+  std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1), y(m);
+  int total = 0;
+  *ok = 0;
+  HIPCHK(hipMemsetAsync(p->S, 0, sizeof(double) * n, p->stream));
+  // r = -F
+  pf::launch_axpby(n, -1.0, p->F, 0.0, nullptr, p->tmp, p->stream);
+  double beta = fnorm;
+  p->launches += 1;
+  while (true) {
+    if (beta <= tol) {
+      *ok = 1;
+      break;
+    }
+    pf::launch_axpby(n, 1.0 / beta, p->tmp, 0.0, nullptr, V, p->stream);
+    p->launches += 1;
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int j = 0;
+    double resid = beta;
+    for (; j < m && total < maxit; ++j) {
+      pc_apply(p, dt, V + j * n, p->z);
+      jv(p, dt, Bm, p->z, p->w);
+      pf::launch_multidot(n, j + 1, V, n, p->w, p->part, p->stream);
+      p->launches += 1;
+      int st = reduce_to_host(p, j + 2);
+      if (st) return st;
+      double* h = &H[(size_t)j * (m + 1)];  // column j
+      double hh = 0.0;
+      for (int i = 0; i <= j; ++i) {
+        h[i] = p->hbuf[i];
+        hh += h[i] * h[i];
+      }
+      const double ww = p->hbuf[j + 1];
+      double nrm2 = ww - hh;
+      double hnext;
+      if (nrm2 > 1e-2 * ww) {
+        hnext = std::sqrt(nrm2);
+        pf::launch_update(n, j + 1, V, n, h, p->w, 1.0 / hnext, V + (j + 1) * n, p->part, p->stream);
+        p->launches += 1;
+      } else {
+        // cancellation: explicit second classical Gram-Schmidt pass
+        pf::launch_update(n, j + 1, V, n, h, p->w, 1.0, p->w, p->part, p->stream);
+        pf::launch_multidot(n, j + 1, V, n, p->w, p->part, p->stream);
+        p->launches += 2;
+        st = reduce_to_host(p, j + 2);
+        if (st) return st;
+        std::vector<double> h2(j + 1);
+        double hh2 = 0.0;
+        for (int i = 0; i <= j; ++i) {
+          h2[i] = p->hbuf[i];
+          h[i] += h2[i];
+          hh2 += h2[i] * h2[i];
+        }
+        const double ww2 = p->hbuf[j + 1];
+        pf::launch_update(n, j + 1, V, n, h2.data(), p->w, 1.0, p->w, p->part, p->stream);
+        p->launches += 1;
+        st = reduce_to_host(p, 1);
+        if (st) return st;
+        hnext = std::sqrt(p->hbuf[0]);
+        (void)ww2;
+        (void)hh2;
+        if (hnext > 0.0) {
+          pf::launch_axpby(n, 1.0 / hnext, p->w, 0.0, nullptr, V + (j + 1) * n, p->stream);
+          p->launches += 1;
+        }
+      }
+      h[j + 1] = hnext;
+      // apply previous rotations, then a new one
+      for (int i = 0; i < j; ++i) {
+        const double a = h[i], b = h[i + 1];
+        h[i] = cs[i] * a + sn[i] * b;
+        h[i + 1] = -sn[i] * a + cs[i] * b;
+      }
+      const double a = h[j], b = h[j + 1];
+      const double r = std::hypot(a, b);
+      cs[j] = (r == 0.0) ? 1.0 : a / r;
+      sn[j] = (r == 0.0) ? 0.0 : b / r;
+      h[j] = r;
+      h[j + 1] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      resid = std::fabs(g[j + 1]);
+      ++total;
+      if (!std::isfinite(resid)) return PFNKS_ENOCONV;
+      if (resid <= tol || hnext == 0.0) {
+        ++j;
+        break;
+      }
+    }
+    // y = H^{-1} g (upper triangular j x j)
+    const int k = j;
+    for (int i = k - 1; i >= 0; --i) {
+      double s = g[i];
+      for (int c = i + 1; c < k; ++c) s -= H[(size_t)c * (m + 1) + i] * y[c];
+      y[i] = s / H[(size_t)i * (m + 1) + i];
+    }
+    // S += M^{-1} (V y)
+    pf::launch_lincomb(n, k, V, n, y.data(), 0.0, p->tmp, p->stream);
+    pc_apply(p, dt, p->tmp, p->z);
+    pf::launch_axpby(n, 1.0, p->S, 1.0, p->z, p->S, p->stream);
+    p->launches += 2;
+    if (resid <= tol) {
+      *ok = 1;
+      break;
+    }
+    if (total >= maxit) break;
+    // restart: r = -F - J S
+    jv(p, dt, Bm, p->S, p->w);
+    pf::launch_axpby(n, -1.0, p->F, -1.0, p->w, p->tmp, p->stream);
+    p->launches += 1;
+    int st = dot_norm(p, p->tmp, &beta);
+    if (st) return st;
+  }
+  *its = total;
+  return PFNKS_OK;
+}
+
+int step_close(pfnks_problem* p, pfnks_step_stats* st, const double* X, double dt_unused) {
+  (void)dt_unused;
+  // energy parts and mass at X
+  pf::launch_energy(p->K, X, p->part, p->stream);
+  p->launches += 1;
+  int s = reduce_to_host(p, 4);
+  if (s) return s;
+  const double hd = std::pow(p->grid.h, p->grid.dim);
+  if (st) {
+    st->energy_parts[0] = p->hbuf[0] * hd;
+    st->energy_parts[1] = p->hbuf[1] * hd;
+    st->energy_parts[2] = p->hbuf[2] * hd;
+    st->energy = st->energy_parts[0] + st->energy_parts[1] + st->energy_parts[2];
+    st->mass = p->hbuf[3] * hd;
+  }
+  return PFNKS_OK;
+}
+
+int project_gauge(pfnks_problem* p, double* X) {
+  pf::launch_class_sums(p->K, X + 4 * p->N, p->part, p->stream);
+  const int ncls = 1 << p->grid.dim;
+  pf::launch_finalize(p->part, p->grid.dim * ncls, p->red, p->stream);
+  pf::launch_class_shift(p->K, X + 4 * p->N, p->red, p->stream);
+  p->launches += 3;
+  return PFNKS_OK;
+}
+
+int check_domain_host(const double* c, const double* eta, long long N) {
+  for (long long i = 0; i < N; ++i) {
+    const double cc = c[i];
+    if (!(cc > 0.0 && cc < 1.0)) return PFNKS_EDOMAIN;
+    double es = 0.0;
+    for (int q = 0; q < 3; ++q) {
+      const double y = cc * eta[q * N + i];
+      es += eta[q * N + i];
+      if (!(y > 0.0 && y < 1.0)) return PFNKS_EDOMAIN;
+    }
+    const double y4 = cc * (4.0 - es);
+    if (!(y4 > 0.0 && y4 < 1.0)) return PFNKS_EDOMAIN;
+  }
+  return PFNKS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pfnks_workspace_bytes(const pfnks_grid* grid, const pfnks_model* model, const pfnks_solver* solver,
+                          size_t* bytes) {
+  if (!bytes) return PFNKS_EINVAL;
+  int st = validate(grid, model, solver);
+  if (st) return st;
+  const long long N = (long long)grid->n[0] * grid->n[1] * (grid->dim == 3 ? grid->n[2] : 1);
+  *bytes = make_layout(grid->dim, N, solver->gmres_restart, grid->n).total;
+  return PFNKS_OK;
+}
+
+int pfnks_create_problem(const pfnks_grid* grid, const pfnks_model* model, const pfnks_solver* solver,
+                         const double* c0, const double* eta0, void* d_workspace, size_t ws_bytes,
+                         void* hip_stream, pfnks_problem** out) {
+  if (!out || !c0 || !eta0 || !d_workspace) return PFNKS_EINVAL;
+  *out = nullptr;
+  int st = validate(grid, model, solver);
+  if (st) return st;
+  if (((uintptr_t)d_workspace & 255) != 0) return PFNKS_EINVAL;
+  const long long N = (long long)grid->n[0] * grid->n[1] * (grid->dim == 3 ? grid->n[2] : 1);
+  const Layout L = make_layout(grid->dim, N, solver->gmres_restart, grid->n);
+  if (ws_bytes < L.total) return PFNKS_ENOSPACE;
+  st = check_domain_host(c0, eta0, N);
+  if (st) return st;
+
+  pfnks_problem* p = new pfnks_problem();
+  p->grid = *grid;
+  if (grid->dim == 2) p->grid.n[2] = 1;
+  p->model = *model;
+  p->solver = *solver;
+  p->nf = 4 + grid->dim;
+  p->N = N;
+  p->nvec = (long long)p->nf * N;
+  p->stream = (hipStream_t)hip_stream;
+  p->ws = (char*)d_workspace;
+  make_consts(p);
+  p->T.tx = solver->tile[0];
+  p->T.ty = solver->tile[1];
+  p->T.tz = (grid->dim == 3) ? solver->tile[2] : 1;
+  p->T.ov = solver->overlap;
+  p->T.sweeps = solver->sweeps;
+  p->T.with_u = 0;
+  auto ptr = [&](int b) { return (double*)(p->ws + L.off[b]); };
+  p->X = ptr(B_X);
+  p->Xn = ptr(B_XN);
+  p->Xt = ptr(B_XT);
+  p->F = ptr(B_F);
+  p->Ft = ptr(B_FT);
+  p->S = ptr(B_S);
+  p->B = ptr(B_B);
+  p->Bpc = ptr(B_BPC);
+  p->G4 = ptr(B_G4);
+  p->dG = ptr(B_DG);
+  p->V = ptr(B_V);
+  p->w = ptr(B_W);
+  p->z = ptr(B_Z);
+  p->tmp = ptr(B_TMP);
+  p->part = ptr(B_PART);
+  p->red = ptr(B_RED);
+  p->fft0 = (double2*)(p->ws + L.off[B_FFT0]);
+  p->fft1 = (double2*)(p->ws + L.off[B_FFT1]);
+  p->t = 0.0;
+
+  auto fail = [&](int code) {
+    if (p->hbuf) (void)hipHostFree(p->hbuf);
+    delete p;
+    return code;
+  };
+  hipError_t e = hipHostMalloc((void**)&p->hbuf, sizeof(double) * pf::kMaxRed, hipHostMallocDefault);
+  if (e != hipSuccess) return fail(device_error(e, "hipHostMalloc"));
+
+  // twiddle tables exp(-2 pi i k / n), k < n/2
+  for (int d = 0; d < 3; ++d) {
+    const int nd = (d < grid->dim) ? grid->n[d] : 2;
+    std::vector<double2> tw(nd / 2 + 1);
+    for (int k = 0; k <= nd / 2; ++k) {
+      const double ang = -2.0 * M_PI * (double)k / (double)nd;
+      tw[k] = make_double2(std::cos(ang), std::sin(ang));
+    }
+    double2* dst = (double2*)(p->ws + L.off[B_TW0 + d]);
+    e = hipMemcpy(dst, tw.data(), sizeof(double2) * tw.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail(device_error(e, "hipMemcpy twiddles"));
+    p->plan.tw[d] = dst;
+    p->plan.n[d] = nd;
+  }
+  // state: c, eta, u = 0
+  e = hipMemcpy(p->Xn, c0, sizeof(double) * N, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p->Xn + N, eta0, sizeof(double) * 3 * N, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(p->Xn + 4 * N, 0, sizeof(double) * grid->dim * N);
+  if (e != hipSuccess) return fail(device_error(e, "state upload"));
+  // cbar0 = mean(c0) by a grid reduction
+  pf::launch_sum2(N, p->Xn, p->Xn, p->Xn, p->part, p->stream);
+  st = reduce_to_host(p, 1);
+  if (st) return fail(st);
+  p->K.cbar0 = p->hbuf[0] / (double)N;
+  // u0 from the discrete equilibrium at c0: K u = eps0 Ctr Dhat c0 (the cbar0 shift drops out)
+  pf::launch_spectral_solve(p->K, p->plan, nullptr, p->K.eps0 * p->K.Ctr, p->Xn, p->fft0, p->fft1,
+                            p->Xn + 4 * N, p->stream);
+  e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) return fail(device_error(e, "elastic init"));
+  *out = p;
+  return PFNKS_OK;
+}
+
+int pfnks_step(pfnks_problem* p, double dt, pfnks_step_stats* stats) {
+  if (!p || !(dt > 0.0) || !std::isfinite(dt)) return PFNKS_EINVAL;
+  pfnks_step_stats st{};
+  p->launches = 0;
+  p->syncs = 0;
+  const long long n = p->nvec, N = p->N;
+  const pfnks_solver& sv = p->solver;
+  const double sq = std::sqrt((double)n);
+  const double eps_a = sv.newton_atol_rms * sq, xi_a = sv.gmres_atol_rms * sq;
+  // X_0 = X^n
+  HIPCHK(hipMemcpyAsync(p->X, p->Xn, sizeof(double) * n, hipMemcpyDeviceToDevice, p->stream));
+  double fn, bad;
+  int s = residual(p, p->X, dt, p->F, &fn, &bad);
+  if (s) return s;
+  st.res0 = fn;
+  const double r0 = fn;
+  int converged = (fn <= eps_a) || fn == 0.0;
+  int newton = 0, gm_total = 0, backtracks = 0;
+  for (; !converged && newton < sv.newton_maxit; ++newton) {
+    // linearise at X; the preconditioner blocks are set up once per step (lagged)
+    double* Bm = p->B;
+    if (newton == 0) {
+      pf::launch_linearise(p->K, p->X, p->Xn, p->Bpc, p->stream);
+      Bm = p->Bpc;
+    } else {
+      pf::launch_linearise(p->K, p->X, p->Xn, p->B, p->stream);
+    }
+    p->launches += 1;
+    const double tol = std::fmax(sv.gmres_rtol * fn, xi_a);
+    int its = 0, ok = 0;
+    s = gmres(p, dt, Bm, fn, tol, &its, &ok);
+    gm_total += its;
+    if (s == PFNKS_ENOCONV) break;
+    if (s) return s;
+    // mass projection of the update: sum S_c = -sum (c - c^n)
+    pf::launch_sum2(N, p->S, p->X, p->Xn, p->part, p->stream);
+    p->launches += 1;
+    s = reduce_to_host(p, 2);
+    if (s) return s;
+    const double shift = -(p->hbuf[0] + p->hbuf[1]) / (double)N;
+    // backtracking line search (Armijo)
+    double lam = 1.0, ft = 0.0;
+    bool accepted = false;
+    for (int hv = 0; hv <= sv.ls_max_halvings; ++hv) {
+      pf::launch_trial(p->K, p->nf, p->X, p->S, lam, shift, p->Xt, p->part, p->stream);
+      p->launches += 1;
+      s = reduce_to_host(p, 1);
+      if (s) return s;
+      if (p->hbuf[0] == 0.0) {
+        s = residual(p, p->Xt, dt, p->Ft, &ft, &bad);
+        if (s) return s;
+        if (bad == 0.0 && std::isfinite(ft) && ft * ft <= (1.0 - 2.0 * sv.ls_alpha * lam) * fn * fn) {
+          accepted = true;
+          break;
+        }
+      }
+      lam *= 0.5;
+      ++backtracks;
+    }
+    if (!accepted) break;
+    std::swap(p->X, p->Xt);
+    std::swap(p->F, p->Ft);
+    fn = ft;
+    if (fn <= std::fmax(sv.newton_rtol * r0, eps_a)) {
+      converged = 1;
+      ++newton;
+      break;
+    }
+  }
+  st.newton_its = newton;
+  st.gmres_its = gm_total;
+  st.ls_backtracks = backtracks;
+  st.res_final = fn;
+  if (!converged) {
+    st.status = PFNKS_ENOCONV;
+    if (stats) *stats = st;
+    HIPCHK(hipStreamSynchronize(p->stream));
+    return PFNKS_ENOCONV;
+  }
+  if (sv.pc == PFNKS_PC_RAS || sv.pc == 2) project_gauge(p, p->X);
+  // step close: ||X - X^n|| over c and eta, energy, mass
+  pf::launch_dx2(4 * N, p->X, p->Xn, p->part, p->stream);
+  p->launches += 1;
+  s = reduce_to_host(p, 1);
+  if (s) return s;
+  st.dx_rms = std::sqrt(p->hbuf[0] / (4.0 * N));
+  s = step_close(p, &st, p->X, dt);
+  if (s) return s;
+  std::swap(p->X, p->Xn);
+  p->t += dt;
+  st.status = PFNKS_OK;
+  if (stats) *stats = st;
+  return PFNKS_OK;
+}
+
+int pfnks_energy(pfnks_problem* p, double* total, double parts[3]) {
+  if (!p || !total) return PFNKS_EINVAL;
+  pfnks_step_stats st{};
+  int s = step_close(p, &st, p->Xn, 0.0);
+  if (s) return s;
+  *total = st.energy;
+  if (parts)
+    for (int k = 0; k < 3; ++k) parts[k] = st.energy_parts[k];
+  return PFNKS_OK;
+}
+
+int pfnks_mass(pfnks_problem* p, double* mass) {
+  if (!p || !mass) return PFNKS_EINVAL;
+  pfnks_step_stats st{};
+  int s = step_close(p, &st, p->Xn, 0.0);
+  if (s) return s;
+  *mass = st.mass;
+  return PFNKS_OK;
+}
+
+int pfnks_get_state(pfnks_problem* p, double* X, double* t) {
+  if (!p || !X) return PFNKS_EINVAL;
+  HIPCHK(hipMemcpyAsync(X, p->Xn, sizeof(double) * p->nvec, hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  if (t) *t = p->t;
+  return PFNKS_OK;
+}
+
+int pfnks_set_state(pfnks_problem* p, const double* X, double t) {
+  if (!p || !X) return PFNKS_EINVAL;
+  int s = check_domain_host(X, X + p->N, p->N);
+  if (s) return s;
+  HIPCHK(hipMemcpyAsync(p->Xn, X, sizeof(double) * p->nvec, hipMemcpyHostToDevice, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  p->t = t;
+  return PFNKS_OK;
+}
+
+int pfnks_destroy(pfnks_problem* p) {
+  if (!p) return PFNKS_EINVAL;
+  if (p->stream) (void)hipStreamSynchronize(p->stream);
+  if (p->hbuf) (void)hipHostFree(p->hbuf);
+  delete p;
+  return PFNKS_OK;
+}
+
+const char* pfnks_strerror(int status) {
+  switch (status) {
+    case PFNKS_OK: return "ok";
+    case PFNKS_EINVAL: return "invalid argument";
+    case PFNKS_EDOMAIN: return "state outside the log domain (need 0 < c < 1 and 0 < c*eta_i < 1)";
+    case PFNKS_ENOSPACE: return "workspace too small";
+    case PFNKS_ENOCONV: return "Newton iteration did not converge";
+    case PFNKS_EDEVICE: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+const char* pfnks_last_error(void) { return g_last_error.c_str(); }
+
+int pfnks_debug_residual(pfnks_problem* p, const double* X, double dt, double* F) {
+  if (!p || !X || !F || !(dt > 0.0)) return PFNKS_EINVAL;
+  HIPCHK(hipMemcpyAsync(p->Xt, X, sizeof(double) * p->nvec, hipMemcpyHostToDevice, p->stream));
+  double fn, bad;
+  int s = residual(p, p->Xt, dt, p->Ft, &fn, &bad);
+  if (s) return s;
+  HIPCHK(hipMemcpyAsync(F, p->Ft, sizeof(double) * p->nvec, hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  return PFNKS_OK;
+}
+
+int pfnks_debug_jv(pfnks_problem* p, const double* X, double dt, const double* v, double* w) {
+  if (!p || !X || !v || !w || !(dt > 0.0)) return PFNKS_EINVAL;
+  HIPCHK(hipMemcpyAsync(p->Xt, X, sizeof(double) * p->nvec, hipMemcpyHostToDevice, p->stream));
+  HIPCHK(hipMemcpyAsync(p->tmp, v, sizeof(double) * p->nvec, hipMemcpyHostToDevice, p->stream));
+  pf::launch_linearise(p->K, p->Xt, p->Xn, p->B, p->stream);
+  jv(p, dt, p->B, p->tmp, p->w);
+  HIPCHK(hipMemcpyAsync(w, p->w, sizeof(double) * p->nvec, hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  return PFNKS_OK;
+}
+
+int pfnks_debug_pc(pfnks_problem* p, const double* X, double dt, const double* r, double* z) {
+  if (!p || !X || !r || !z || !(dt > 0.0)) return PFNKS_EINVAL;
+  HIPCHK(hipMemcpyAsync(p->Xt, X, sizeof(double) * p->nvec, hipMemcpyHostToDevice, p->stream));
+  HIPCHK(hipMemcpyAsync(p->tmp, r, sizeof(double) * p->nvec, hipMemcpyHostToDevice, p->stream));
+  pf::launch_linearise(p->K, p->Xt, p->Xn, p->Bpc, p->stream);
+  pc_apply(p, dt, p->tmp, p->z);
+  HIPCHK(hipMemcpyAsync(z, p->z, sizeof(double) * p->nvec, hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  return PFNKS_OK;
+}
+
+int pfnks_debug_counters(pfnks_problem* p, long long* launches, long long* syncs) {
+  if (!p) return PFNKS_EINVAL;
+  if (launches) *launches = p->launches;
+  if (syncs) *syncs = p->syncs;
+  return PFNKS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,53 @@
+"""The C-ABI library loads on the CPU host and exports every symbol include/pfnks.h declares
+(no compute calls: no GPU here)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pfnks.h")
+LIB = os.path.join(ROOT, "paper_2209_08001_amd", "libpfnks.so")
+
+
+def declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(pfnks_\w+)\s*\(", text, re.M)))
+
+
+def test_header_declares_the_step_api():
+    names = declared()
+    for n in ("pfnks_create_problem", "pfnks_step", "pfnks_energy", "pfnks_mass", "pfnks_workspace_bytes"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(LIB):
+        pytest.skip("libpfnks.so not built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_lists_every_declared_symbol():
+    from paper_2209_08001_amd import pfnks
+
+    assert sorted(pfnks.EXPORTED) == declared()
+
+
+def test_workspace_bytes_and_validation_on_host():
+    """pfnks_workspace_bytes is pure host arithmetic: sizes and argument errors."""
+    if not os.path.exists(LIB):
+        pytest.skip("libpfnks.so not built")
+    from paper_2209_08001_amd import pfnks
+    from paper_2209_08001_amd import workloads as W
+
+    b = pfnks.workspace_bytes((512, 512), W.H, W.DEFAULT_MODEL, W.DEFAULT_SOLVER)
+    N = 512 * 512
+    assert b >= (31 + 12) * 6 * 8 * N
+    with pytest.raises(pfnks.PfnksError):
+        pfnks.workspace_bytes((100, 100), W.H, W.DEFAULT_MODEL, W.DEFAULT_SOLVER)  # not a power of 2
+    with pytest.raises(pfnks.PfnksError):
+        pfnks.workspace_bytes((64, 64), W.H, W.DEFAULT_MODEL, dict(W.DEFAULT_SOLVER, tile=(48, 48, 1)))

@@ -1,0 +1,234 @@
+"""Parity of the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Tolerances.  Kernel-level results (F, J v, energy) differ from the oracle only by rounding
+order: each entry sums at most ~60 FP64 terms whose magnitude is at most ~1e3 times the
+largest entry of the field for these random states, so |gpu - oracle| <= 60 * 1.1e-16 * 1e3
+~ 1e-11 relative to the field's max-norm; the tests use 1e-10.  Step-level results compare
+the Newton-Krylov root (stopped at ||F|| <= 1e-8 ||F_0||, GMRES at 1e-6) with the oracle's
+exact-LU root: the required bound is 1e-8 relative to the field's max-norm.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import Grid, Oracle, jacobian, residual
+from oracle.model import Model
+from oracle.scheme import energy as oracle_energy
+from oracle.scheme import strain_el
+from paper_2209_08001_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _cuda():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _problem(n, c0, e0, model=None, **solver_kw):
+    from paper_2209_08001_amd import pfnks
+
+    sv = dict(W.DEFAULT_SOLVER)
+    sv.update(solver_kw)
+    if len(n) == 3 and "tile" not in solver_kw:
+        sv["tile"] = (8, 8, 8)
+        sv["overlap"] = 1
+    elif "tile" not in solver_kw:
+        # largest power-of-two tile <= 32 whose extended block fits the grid side
+        t = []
+        for nk in n:
+            tk = 32
+            while tk + 2 * sv["overlap"] > nk:
+                tk //= 2
+            t.append(tk)
+        sv["tile"] = (t[0], t[1], 1)
+    return pfnks.Problem(n, W.H, model or W.DEFAULT_MODEL, sv, c0, e0)
+
+
+def _note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _relmax(a, b):
+    return np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)
+
+
+@pytest.mark.parametrize("n", [(64, 64), (32, 64), (16, 16, 16)])
+def test_residual_parity(n):
+    _cuda()
+    _note(f"residual parity n={n}")
+    c0, e0 = W.init_fields(n, 11)
+    p = _problem(n, c0, e0)
+    Xn, _ = p.get_state()
+    X = Xn + 0.2 * (W.random_state(n, 12) - W.random_state(n, 12).mean(axis=tuple(range(1, len(n) + 1)), keepdims=True)) * 0.05
+    X[0] = Xn[0] + np.random.default_rng(3).uniform(-0.01, 0.01, X[0].shape)
+    g = Grid(n, W.H)
+    m = Model.from_dict(W.DEFAULT_MODEL)
+    cb0 = float(c0.mean())
+    for dt in (0.01, 1.0):
+        Fg = p.debug_residual(X, dt)
+        Fo = residual(X, Xn, dt, g, m, cb0)
+        for f in range(X.shape[0]):
+            assert _relmax(Fg[f], Fo[f]) <= 1e-10, (dt, f, _relmax(Fg[f], Fo[f]))
+    p.close()
+
+
+@pytest.mark.parametrize("n", [(64, 64), (16, 16, 16)])
+def test_jv_parity(n):
+    _cuda()
+    _note(f"jv parity n={n}")
+    c0, e0 = W.init_fields(n, 13)
+    p = _problem(n, c0, e0)
+    Xn, _ = p.get_state()
+    X = Xn.copy()
+    X[:4] += np.random.default_rng(4).uniform(-0.01, 0.01, X[:4].shape)
+    v = np.random.default_rng(5).normal(size=X.shape)
+    g = Grid(n, W.H)
+    m = Model.from_dict(W.DEFAULT_MODEL)
+    for dt in (0.01, 1.0):
+        wg = p.debug_jv(X, dt, v)
+        J = jacobian(X, Xn, dt, g, m)
+        wo = (J @ v.ravel()).reshape(X.shape)
+        for f in range(X.shape[0]):
+            assert _relmax(wg[f], wo[f]) <= 1e-10, (dt, f, _relmax(wg[f], wo[f]))
+    p.close()
+
+
+@pytest.mark.parametrize("n", [(64, 64), (32, 16), (16, 16, 16)])
+def test_elastic_init_and_energy(n):
+    _cuda()
+    _note(f"elastic init / energy n={n}")
+    c0, e0 = W.init_fields(n, 17)
+    p = _problem(n, c0, e0)
+    o = Oracle(n, W.H, W.DEFAULT_MODEL, c0, e0)
+    Xg, _ = p.get_state()
+    # same gauge (zero mean per parity class): compare u directly, and the strain
+    for I in range(len(n)):
+        assert _relmax(Xg[4 + I], o.X[4 + I]) <= 1e-10
+    eg = strain_el(Xg[4:], Xg[0], o.cbar0, o.grid, o.m)
+    eo = strain_el(o.X[4:], o.X[0], o.cbar0, o.grid, o.m)
+    for I in range(len(n)):
+        for J in range(len(n)):
+            assert np.max(np.abs(eg[I][J] - eo[I][J])) <= 1e-12
+    Eg, parts_g = p.energy()
+    Eo, parts_o = o.energy()
+    assert abs(Eg - Eo) <= 1e-12 * abs(Eo)
+    for a, b in zip(parts_g, parts_o):
+        assert abs(a - b) <= 1e-11 * abs(Eo)
+    assert abs(p.mass() - o.mass()) <= 1e-14 * abs(o.mass())
+    p.close()
+
+
+def test_spectral_block_is_exact_solve():
+    """With the (c, eta) block left alone, the preconditioner's displacement output solves
+    K z_u = r_u + eps0 Ctr Dhat r_c exactly (the oracle's sparse displacement block)."""
+    from paper_2209_08001_amd import pfnks
+
+    _cuda()
+    _note("spectral block")
+    n = (32, 32)
+    c0, e0 = W.init_fields(n, 19)
+    p = _problem(n, c0, e0, pc=pfnks.PC_SPECTRAL)
+    Xn, _ = p.get_state()
+    r = np.random.default_rng(8).normal(size=Xn.shape)
+    g = Grid(n, W.H)
+    m = Model.from_dict(W.DEFAULT_MODEL)
+    # project r_u onto the range (zero class means) as GMRES vectors are
+    cls, ncls = g.parity_class()
+    for I in range(2):
+        for k in range(ncls):
+            r[4 + I][cls == k] -= r[4 + I][cls == k].mean()
+    z = p.debug_pc(Xn, 0.1, r)
+    J = jacobian(Xn, Xn, 0.1, g, m)
+    N = g.N
+    Juu = J[4 * N:, 4 * N:]
+    Juc = J[4 * N:, :N]
+    lhs = Juu @ z[4:].ravel()
+    rhs = r[4:].ravel() - Juc @ z[0].ravel()
+    assert np.max(np.abs(lhs - rhs)) <= 1e-9 * np.max(np.abs(rhs))
+    assert np.array_equal(z[:4], r[:4])
+    p.close()
+
+
+@pytest.mark.parametrize("pc", ["ras_spectral", "ras"])
+def test_pc_linear_and_deterministic(pc):
+    from paper_2209_08001_amd import pfnks
+
+    _cuda()
+    _note(f"pc linearity {pc}")
+    n = (64, 64)
+    c0, e0 = W.init_fields(n, 23)
+    p = _problem(n, c0, e0, pc=pfnks.PC_RAS if pc == "ras" else pfnks.PC_RAS_SPECTRAL)
+    Xn, _ = p.get_state()
+    rng = np.random.default_rng(9)
+    r1 = rng.normal(size=Xn.shape)
+    r2 = rng.normal(size=Xn.shape)
+    z1 = p.debug_pc(Xn, 0.05, r1)
+    z2 = p.debug_pc(Xn, 0.05, r2)
+    z12 = p.debug_pc(Xn, 0.05, 2.0 * r1 - 3.0 * r2)
+    assert np.max(np.abs(z12 - (2 * z1 - 3 * z2))) <= 1e-9 * np.max(np.abs(z12))
+    assert np.array_equal(z1, p.debug_pc(Xn, 0.05, r1))
+    p.close()
+
+
+@pytest.fixture(scope="module")
+def oracle_c1():
+    n = W.WORKLOADS["pf2d_64"]["n"]
+    c0, e0 = W.init_fields(n, W.WORKLOADS["pf2d_64"]["seed"])
+    o = Oracle(n, W.H, W.DEFAULT_MODEL, c0, e0)
+    traj = [o.X.copy()]
+    info = []
+    for _ in range(W.WORKLOADS["pf2d_64"]["steps"]):
+        info.append(o.step(W.WORKLOADS["pf2d_64"]["dt"]))
+        traj.append(o.X.copy())
+    return c0, e0, traj, info, o
+
+
+@pytest.mark.parametrize("pc", ["ras_spectral", "ras"])
+def test_step_parity_pf2d_64(oracle_c1, pc):
+    """2D 64 x 64, 10 steps of dt = 1e-2: every step within 1e-8 of the oracle's root,
+    mass conserved to 1e-13, energy non-increasing."""
+    from paper_2209_08001_amd import pfnks
+
+    _cuda()
+    c0, e0, traj, info, o = oracle_c1
+    _note(f"step parity pf2d_64 pc={pc}")
+    p = _problem((64, 64), c0, e0, pc=pfnks.PC_RAS if pc == "ras" else pfnks.PC_RAS_SPECTRAL)
+    m0 = p.mass()
+    E_prev = p.energy()[0]
+    for k in range(10):
+        st = p.step(0.01)
+        X, t = p.get_state()
+        for f in range(X.shape[0]):
+            err = _relmax(X[f], traj[k + 1][f])
+            assert err <= 1e-8, (k, f, err)
+        assert abs(st["mass"] - m0) <= 1e-13 * abs(m0)
+        assert st["energy"] <= E_prev + 1e-12 * abs(E_prev)
+        assert abs(st["energy"] - info[k]["energy"]) <= 1e-9 * abs(info[k]["energy"])
+        E_prev = st["energy"]
+    assert abs(t - 0.1) < 1e-14
+    p.close()
+
+
+def test_enoconv_leaves_state():
+    """A step forced to fail (one Newton iteration allowed, huge dt) returns ENOCONV and
+    leaves the state and time untouched."""
+    from paper_2209_08001_amd import pfnks
+
+    _cuda()
+    _note("enoconv")
+    n = (32, 32)
+    c0, e0 = W.init_fields(n, 29)
+    p = _problem(n, c0, e0, newton_maxit=1)
+    X0, t0 = p.get_state()
+    status, st = p.try_step(50.0)
+    assert status == pfnks.PFNKS_ENOCONV
+    X1, t1 = p.get_state()
+    assert np.array_equal(X0, X1) and t0 == t1
+    p.close()
