@@ -169,6 +169,25 @@ int pfnks_debug_pc(pfnks_problem* p, const double* X, double dt, const double* r
 /* Counters of the last pfnks_step: kernel launches and host synchronisations. */
 int pfnks_debug_counters(pfnks_problem* p, long long* launches, long long* syncs);
 
+/* Live kernel timing.  pfnks_debug_profile(p, 1) clears the totals and brackets every launch
+ * of the kernel kinds below with HIP events recorded on the problem's stream (0 switches it
+ * off).  pfnks_debug_kernel_time returns, for one kind, the number of timed launches, their
+ * summed GPU duration in milliseconds and their summed algorithmic bytes (the bytes the
+ * operation must move: reads of its inputs plus writes of its outputs, once each). */
+enum {
+  PFNKS_K_RESIDUAL = 0,  /* residual F (two kernels)                    */
+  PFNKS_K_LINEARISE = 1, /* local 4 x 4 chemical blocks                 */
+  PFNKS_K_JV = 2,        /* matrix-free Jacobian apply (two kernels)    */
+  PFNKS_K_RAS = 3,       /* Schwarz tile solve                          */
+  PFNKS_K_SPECTRAL = 4,  /* Fourier solve of the displacement block     */
+  PFNKS_K_MULTIDOT = 5,  /* GMRES classical Gram-Schmidt dot products   */
+  PFNKS_K_UPDATE = 6,    /* GMRES orthogonal update and normalisation   */
+  PFNKS_KERNEL_KINDS = 7
+};
+int pfnks_debug_profile(pfnks_problem* p, int enable);
+int pfnks_debug_kernel_time(pfnks_problem* p, int kind, long long* launches, double* ms_total,
+                            double* bytes_total);
+
 #ifdef __cplusplus
 }
 #endif

@@ -130,6 +130,17 @@ struct pfnks_problem {
   double* hbuf;  // pinned host scalars
   double t;
   long long launches, syncs;
+  // live kernel timing (HIP events on the problem's stream), off unless enabled
+  int prof;
+  struct Rec {
+    int kind;
+    hipEvent_t a, b;
+    double bytes;
+  };
+  std::vector<Rec> pending;
+  std::vector<hipEvent_t> pool;
+  long long kcount[PFNKS_KERNEL_KINDS];
+  double kms[PFNKS_KERNEL_KINDS], kbytes[PFNKS_KERNEL_KINDS];
 };
 
 namespace {
@@ -189,6 +200,53 @@ void make_consts(pfnks_problem* p) {
   }
 }
 
+hipEvent_t prof_event(pfnks_problem* p) {
+  if (!p->pool.empty()) {
+    hipEvent_t e = p->pool.back();
+    p->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// bracket the launches of one kernel kind with events (when profiling is on)
+struct Prof {
+  pfnks_problem* p;
+  int kind;
+  double bytes;
+  hipEvent_t a;
+  Prof(pfnks_problem* p_, int kind_, double bytes_) : p(p_), kind(kind_), bytes(bytes_), a(nullptr) {
+    if (p->prof) {
+      a = prof_event(p);
+      if (a) (void)hipEventRecord(a, p->stream);
+    }
+  }
+  ~Prof() {
+    if (!a) return;
+    hipEvent_t b = prof_event(p);
+    if (!b) return;
+    (void)hipEventRecord(b, p->stream);
+    p->pending.push_back({kind, a, b, bytes});
+  }
+};
+
+// after a stream synchronisation: turn finished event pairs into per-kind totals
+void prof_resolve(pfnks_problem* p) {
+  for (auto& r : p->pending) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      p->kcount[r.kind] += 1;
+      p->kms[r.kind] += ms;
+      p->kbytes[r.kind] += r.bytes;
+    }
+    p->pool.push_back(r.a);
+    p->pool.push_back(r.b);
+  }
+  p->pending.clear();
+}
+
 // finalize partial sums of nvals values and copy them to p->hbuf
 int reduce_to_host(pfnks_problem* p, int nvals) {
   pf::launch_finalize(p->part, nvals, p->red, p->stream);
@@ -197,12 +255,16 @@ int reduce_to_host(pfnks_problem* p, int nvals) {
   HIPCHK(hipStreamSynchronize(p->stream));
   p->launches += 1;
   p->syncs += 1;
+  if (!p->pending.empty()) prof_resolve(p);
   return PFNKS_OK;
 }
 
 // F = F(X; Xn, dt); returns ||F|| and the count of out-of-domain nodes
 int residual(pfnks_problem* p, const double* X, double dt, double* F, double* nrm, double* bad) {
-  pf::launch_residual(p->K, dt, X, p->Xn, p->G4, F, p->part, p->stream);
+  {
+    Prof pr(p, PFNKS_K_RESIDUAL, 8.0 * 3 * p->nvec);
+    pf::launch_residual(p->K, dt, X, p->Xn, p->G4, F, p->part, p->stream);
+  }
   p->launches += 2;
   int st = reduce_to_host(p, 2);
   if (st) return st;
@@ -220,6 +282,17 @@ int dot_norm(pfnks_problem* p, const double* x, double* nrm) {
   return PFNKS_OK;
 }
 
+// algorithmic bytes of one Schwarz apply: every extended tile reads r (nfz planes), the
+// chemical blocks (16) and c^n (1); the owned nodes write z (nfz planes)
+double ras_bytes(pfnks_problem* p, int nfz) {
+  double rho = 1.0;
+  for (int k = 0; k < p->K.dim; ++k) {
+    const int t = p->solver.tile[k];
+    rho *= (double)(t + 2 * p->solver.overlap) / t;
+  }
+  return 8.0 * p->N * (rho * (nfz + 17) + nfz);
+}
+
 // z = M^{-1} r with the lagged preconditioner blocks Bpc
 void pc_apply(pfnks_problem* p, double dt, const double* r, double* z) {
   const long long N = p->N;
@@ -227,6 +300,7 @@ void pc_apply(pfnks_problem* p, double dt, const double* r, double* z) {
   if (pc == PFNKS_PC_RAS) {
     pf::TileCfg T = p->T;
     T.with_u = 1;
+    Prof pr(p, PFNKS_K_RAS, ras_bytes(p, 4 + p->K.dim));
     pf::launch_ras(p->K, T, dt, p->Bpc, p->Xn, r, z, p->stream);
     p->launches += 1;
     return;
@@ -234,6 +308,7 @@ void pc_apply(pfnks_problem* p, double dt, const double* r, double* z) {
   if (pc == PFNKS_PC_RAS_SPECTRAL) {
     pf::TileCfg T = p->T;
     T.with_u = 0;
+    Prof pr(p, PFNKS_K_RAS, ras_bytes(p, 4));
     pf::launch_ras(p->K, T, dt, p->Bpc, p->Xn, r, z, p->stream);
     p->launches += 1;
   } else {
@@ -247,12 +322,14 @@ void pc_apply(pfnks_problem* p, double dt, const double* r, double* z) {
     return;
   }
   // displacement block: z_u = K^{-1} (r_u - J_uc z_c) = K^{-1} (r_u + eps0 Ctr Dhat z_c)
+  Prof pr(p, PFNKS_K_SPECTRAL, 8.0 * (2 * p->K.dim + 1) * N);
   pf::launch_spectral_solve(p->K, p->plan, r + 4 * N, p->K.eps0 * p->K.Ctr, z, p->fft0, p->fft1,
                             z + 4 * N, p->stream);
   p->launches += 3 + 4 * p->K.dim * (p->K.dim == 3 ? 2 : 1);
 }
 
 void jv(pfnks_problem* p, double dt, const double* Bm, const double* v, double* w) {
+  Prof pr(p, PFNKS_K_JV, 8.0 * (2 * p->nvec + 17 * p->N));
   pf::launch_jv(p->K, dt, Bm, p->Xn, v, p->dG, w, p->stream);
   p->launches += 2;
 }
@@ -287,7 +364,10 @@ int gmres(pfnks_problem* p, double dt, const double* Bm, double fnorm, double to
     for (; j < m && total < maxit; ++j) {
       pc_apply(p, dt, V + j * n, p->z);
       jv(p, dt, Bm, p->z, p->w);
-      pf::launch_multidot(n, j + 1, V, n, p->w, p->part, p->stream);
+      {
+        Prof pr(p, PFNKS_K_MULTIDOT, 8.0 * (j + 2) * n);
+        pf::launch_multidot(n, j + 1, V, n, p->w, p->part, p->stream);
+      }
       p->launches += 1;
       int st = reduce_to_host(p, j + 2);
       if (st) return st;
@@ -302,6 +382,7 @@ int gmres(pfnks_problem* p, double dt, const double* Bm, double fnorm, double to
       double hnext;
       if (nrm2 > 1e-2 * ww) {
         hnext = std::sqrt(nrm2);
+        Prof pr(p, PFNKS_K_UPDATE, 8.0 * (j + 3) * n);
         pf::launch_update(n, j + 1, V, n, h, p->w, 1.0 / hnext, V + (j + 1) * n, p->part, p->stream);
         p->launches += 1;
       } else {
@@ -454,6 +535,12 @@ int pfnks_create_problem(const pfnks_grid* grid, const pfnks_model* model, const
   if (st) return st;
 
   pfnks_problem* p = new pfnks_problem();
+  p->prof = 0;
+  for (int k = 0; k < PFNKS_KERNEL_KINDS; ++k) {
+    p->kcount[k] = 0;
+    p->kms[k] = 0.0;
+    p->kbytes[k] = 0.0;
+  }
   p->grid = *grid;
   if (grid->dim == 2) p->grid.n[2] = 1;
   p->model = *model;
@@ -553,11 +640,14 @@ int pfnks_step(pfnks_problem* p, double dt, pfnks_step_stats* stats) {
   for (; !converged && newton < sv.newton_maxit; ++newton) {
     // linearise at X; the preconditioner blocks are set up once per step (lagged)
     double* Bm = p->B;
-    if (newton == 0) {
-      pf::launch_linearise(p->K, p->X, p->Xn, p->Bpc, p->stream);
-      Bm = p->Bpc;
-    } else {
-      pf::launch_linearise(p->K, p->X, p->Xn, p->B, p->stream);
+    {
+      Prof pr(p, PFNKS_K_LINEARISE, 8.0 * 24 * N);
+      if (newton == 0) {
+        pf::launch_linearise(p->K, p->X, p->Xn, p->Bpc, p->stream);
+        Bm = p->Bpc;
+      } else {
+        pf::launch_linearise(p->K, p->X, p->Xn, p->B, p->stream);
+      }
     }
     p->launches += 1;
     const double tol = std::fmax(sv.gmres_rtol * fn, xi_a);
@@ -668,8 +758,34 @@ int pfnks_set_state(pfnks_problem* p, const double* X, double t) {
 int pfnks_destroy(pfnks_problem* p) {
   if (!p) return PFNKS_EINVAL;
   if (p->stream) (void)hipStreamSynchronize(p->stream);
+  prof_resolve(p);
+  for (hipEvent_t e : p->pool) (void)hipEventDestroy(e);
   if (p->hbuf) (void)hipHostFree(p->hbuf);
   delete p;
+  return PFNKS_OK;
+}
+
+int pfnks_debug_profile(pfnks_problem* p, int enable) {
+  if (!p) return PFNKS_EINVAL;
+  HIPCHK(hipStreamSynchronize(p->stream));
+  prof_resolve(p);
+  p->prof = enable ? 1 : 0;
+  for (int k = 0; k < PFNKS_KERNEL_KINDS; ++k) {
+    p->kcount[k] = 0;
+    p->kms[k] = 0.0;
+    p->kbytes[k] = 0.0;
+  }
+  return PFNKS_OK;
+}
+
+int pfnks_debug_kernel_time(pfnks_problem* p, int kind, long long* launches, double* ms_total,
+                            double* bytes_total) {
+  if (!p || kind < 0 || kind >= PFNKS_KERNEL_KINDS) return PFNKS_EINVAL;
+  HIPCHK(hipStreamSynchronize(p->stream));
+  prof_resolve(p);
+  if (launches) *launches = p->kcount[kind];
+  if (ms_total) *ms_total = p->kms[kind];
+  if (bytes_total) *bytes_total = p->kbytes[kind];
   return PFNKS_OK;
 }
 

@@ -30,7 +30,10 @@ EXPORTED = [
     "pfnks_workspace_bytes", "pfnks_create_problem", "pfnks_step", "pfnks_energy", "pfnks_mass",
     "pfnks_get_state", "pfnks_set_state", "pfnks_destroy", "pfnks_strerror", "pfnks_last_error",
     "pfnks_debug_residual", "pfnks_debug_jv", "pfnks_debug_pc", "pfnks_debug_counters",
+    "pfnks_debug_profile", "pfnks_debug_kernel_time",
 ]
+
+KERNEL_KINDS = ["residual", "linearise", "jv", "ras", "spectral", "multidot", "update"]
 
 
 class pfnks_grid(ctypes.Structure):
@@ -105,6 +108,8 @@ def load():
     lib.pfnks_debug_jv.argtypes = [P, dp, ctypes.c_double, dp, dp]
     lib.pfnks_debug_pc.argtypes = [P, dp, ctypes.c_double, dp, dp]
     lib.pfnks_debug_counters.argtypes = [P, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong)]
+    lib.pfnks_debug_profile.argtypes = [P, ctypes.c_int]
+    lib.pfnks_debug_kernel_time.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_longlong), dp, dp]
     for name in EXPORTED:
         if name not in ("pfnks_strerror", "pfnks_last_error"):
             getattr(lib, name).restype = ctypes.c_int
@@ -275,6 +280,45 @@ class Problem:
         b = ctypes.c_longlong()
         _check(load().pfnks_debug_counters(self._h, ctypes.byref(a), ctypes.byref(b)), "pfnks_debug_counters")
         return a.value, b.value
+
+    def profile(self, enable):
+        """Switch live kernel timing (HIP events on the problem's stream) on or off; clears totals."""
+        _check(load().pfnks_debug_profile(self._h, 1 if enable else 0), "pfnks_debug_profile")
+
+    def kernel_time(self, kind):
+        """(launches, total ms, total algorithmic bytes) of one kernel kind since profile(True)."""
+        k = KERNEL_KINDS.index(kind) if isinstance(kind, str) else int(kind)
+        a = ctypes.c_longlong()
+        ms = ctypes.c_double()
+        by = ctypes.c_double()
+        _check(load().pfnks_debug_kernel_time(self._h, k, ctypes.byref(a), ctypes.byref(ms), ctypes.byref(by)),
+               "pfnks_debug_kernel_time")
+        return a.value, ms.value, by.value
+
+    def kernel_table(self):
+        out = {}
+        for k in KERNEL_KINDS:
+            n, ms, by = self.kernel_time(k)
+            if n:
+                out[k] = {"launches": n, "total_ms": ms, "avg_us": 1e3 * ms / n,
+                          "GB_s": by / (ms * 1e-3) / 1e9 if ms > 0 else None}
+        return out
+
+    def roofline(self, peak_gbs):
+        """Roofline entry of the kernel kind with the largest total time: algorithmic bytes per
+        launch over its average launch duration, against the HBM peak."""
+        best = None
+        for k in KERNEL_KINDS:
+            n, ms, by = self.kernel_time(k)
+            if n and (best is None or ms > best[2]):
+                best = (k, n, ms, by)
+        if best is None:
+            return None
+        k, n, ms, by = best
+        achieved = by / (ms * 1e-3) / 1e9
+        return {"kernel": k, "bound": "hbm", "achieved": achieved, "peak": peak_gbs, "unit": "GB/s",
+                "frac": achieved / peak_gbs, "traffic": None, "launches": n,
+                "avg_launch_us": 1e3 * ms / n, "bytes_per_launch": by / n}
 
     def close(self):
         if getattr(self, "_h", None):
