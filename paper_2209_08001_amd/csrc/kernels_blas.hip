@@ -33,23 +33,40 @@ __global__ __launch_bounds__(kThreads) void k_multidot(long long n, int nv, cons
   double acc[MAXV + 1];
 #pragma unroll
   for (int v = 0; v <= MAXV; ++v) acc[v] = 0.0;
-  for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < n;
+  // n and ldv are even and every vector is 16-byte aligned: two elements per load
+  const long long n2 = n >> 1, ld2 = ldv >> 1;
+  const double2* __restrict__ V2 = reinterpret_cast<const double2*>(V);
+  const double2* __restrict__ w2 = reinterpret_cast<const double2*>(w);
+  for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < n2;
        e += (long long)gridDim.x * kThreads) {
-    const double we = w[e];
+    const double2 we = w2[e];
 #pragma unroll
     for (int v = 0; v < MAXV; ++v)
-      if (v < nv) acc[v] += we * V[v * ldv + e];
-    acc[MAXV] += we * we;
+      if (v < nv) {
+        const double2 y = V2[v * ld2 + e];
+        acc[v] += we.x * y.x + we.y * y.y;
+      }
+    acc[MAXV] += we.x * we.x + we.y * we.y;
   }
+  // every wave reduces all its values with shuffles; one barrier; then one thread per value
+  __shared__ double wl[kThreads / 64][MAXV + 1];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-  for (int v = 0; v < MAXV; ++v) {
-    if (v < nv) {
-      double s = block_sum(acc[v], lds);
-      if (threadIdx.x == 0) partial[v * kRedBlocks + blockIdx.x] = s;
+  for (int v = 0; v <= MAXV; ++v) {
+    if (v < nv || v == MAXV) {
+      double x = acc[v];
+      for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+      if (lane == 0) wl[wave][v] = x;
     }
   }
-  double s = block_sum(acc[MAXV], lds);
-  if (threadIdx.x == 0) partial[nv * kRedBlocks + blockIdx.x] = s;
+  (void)lds;
+  __syncthreads();
+  if ((int)threadIdx.x <= nv) {
+    const int v = (threadIdx.x == (unsigned)nv) ? MAXV : threadIdx.x;
+    double x = 0.0;
+    for (int w = 0; w < kThreads / 64; ++w) x += wl[w][v];
+    partial[threadIdx.x * kRedBlocks + blockIdx.x] = x;
+  }
 }
 
 struct Coefs {
@@ -63,14 +80,23 @@ __global__ __launch_bounds__(kThreads) void k_update(long long n, int nv, const 
                                                      double* __restrict__ partial) {
   __shared__ double lds[kThreads / 64];
   double acc = 0.0;
-  for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < n;
+  // n and ldv are even and every vector is 16-byte aligned: two elements per load
+  const long long n2 = n >> 1, ld2 = ldv >> 1;
+  const double2* __restrict__ V2 = reinterpret_cast<const double2*>(V);
+  const double2* __restrict__ w2 = reinterpret_cast<const double2*>(w);
+  double2* __restrict__ o2 = reinterpret_cast<double2*>(out);
+  for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < n2;
        e += (long long)gridDim.x * kThreads) {
-    double x = w[e];
+    double2 x = w2[e];
 #pragma unroll
     for (int v = 0; v < MAXV; ++v)
-      if (v < nv) x -= cf.c[v] * V[v * ldv + e];
-    acc += x * x;
-    out[e] = scale * x;
+      if (v < nv) {
+        const double2 y = V2[v * ld2 + e];
+        x.x -= cf.c[v] * y.x;
+        x.y -= cf.c[v] * y.y;
+      }
+    acc += x.x * x.x + x.y * x.y;
+    o2[e] = make_double2(scale * x.x, scale * x.y);
   }
   double s = block_sum(acc, lds);
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
@@ -101,14 +127,30 @@ __global__ __launch_bounds__(kThreads) void k_axpby(long long n, double a, const
   }
 }
 
-__global__ __launch_bounds__(kThreads) void k_finalize(const double* __restrict__ partial, int nvals,
-                                                       double* __restrict__ out) {
-  __shared__ double lds[kThreads / 64];
-  for (int v = 0; v < nvals; ++v) {
-    double acc = 0.0;
-    for (int b = threadIdx.x; b < kRedBlocks; b += kThreads) acc += partial[v * kRedBlocks + b];
-    double s = block_sum(acc, lds);
-    if (threadIdx.x == 0) out[v] = s;
+// Second stage: one thread per partial (kRedBlocks threads), every value loaded at once
+// (independent loads in flight), wave shuffle trees, then one thread per value sums the
+// waves.  Fixed order, so the result is deterministic.
+template <int MAXV>
+__global__ __launch_bounds__(kRedBlocks) void k_finalize(const double* __restrict__ partial, int nvals,
+                                                         double* __restrict__ out) {
+  __shared__ double wl[kRedBlocks / 64][MAXV];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double acc[MAXV];
+#pragma unroll
+  for (int v = 0; v < MAXV; ++v) acc[v] = (v < nvals) ? partial[v * kRedBlocks + threadIdx.x] : 0.0;
+#pragma unroll
+  for (int v = 0; v < MAXV; ++v) {
+    if (v < nvals) {
+      double x = acc[v];
+      for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+      if (lane == 0) wl[wave][v] = x;
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < nvals) {
+    double x = 0.0;
+    for (int w = 0; w < kRedBlocks / 64; ++w) x += wl[w][threadIdx.x];
+    out[threadIdx.x] = x;
   }
 }
 
@@ -182,23 +224,30 @@ __global__ __launch_bounds__(kThreads) void k_class_sums(Consts K, const double*
   __shared__ double lds[kThreads / 64];
   const int ncls = 1 << K.dim;
   double acc[3][8];
+#pragma unroll
   for (int I = 0; I < 3; ++I)
+#pragma unroll
     for (int c = 0; c < 8; ++c) acc[I][c] = 0.0;
   for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < K.N;
        e += (long long)gridDim.x * kThreads) {
     const long long i = e % K.nx, t = e / K.nx, j = t % K.ny, k = t / K.ny;
     const int cls = (int)((i & 1) | ((j & 1) << 1) | ((k & 1) << 2));
-    for (int I = 0; I < K.dim; ++I) {
-      const double v = u[I * K.N + e];
+#pragma unroll
+    for (int I = 0; I < 3; ++I) {
+      const double v = (I < K.dim) ? u[I * K.N + e] : 0.0;
 #pragma unroll
       for (int c = 0; c < 8; ++c)
         if (c == cls) acc[I][c] += v;
     }
   }
-  for (int I = 0; I < K.dim; ++I)
-    for (int c = 0; c < ncls; ++c) {
-      double s = block_sum(acc[I][c], lds);
-      if (threadIdx.x == 0) partial[(I * ncls + c) * kRedBlocks + blockIdx.x] = s;
+#pragma unroll
+  for (int I = 0; I < 3; ++I)
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      if (I < K.dim && c < ncls) {
+        double s = block_sum(acc[I][c], lds);
+        if (threadIdx.x == 0) partial[(I * ncls + c) * kRedBlocks + blockIdx.x] = s;
+      }
     }
 }
 
@@ -260,7 +309,11 @@ void launch_axpby(long long n, double a, const double* x, double b, const double
 }
 
 void launch_finalize(const double* partial, int nvals, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, s, partial, nvals, out);
+  if (nvals <= 4) hipLaunchKernelGGL(k_finalize<4>, dim3(1), dim3(kRedBlocks), 0, s, partial, nvals, out);
+  else if (nvals <= 8) hipLaunchKernelGGL(k_finalize<8>, dim3(1), dim3(kRedBlocks), 0, s, partial, nvals, out);
+  else if (nvals <= 16) hipLaunchKernelGGL(k_finalize<16>, dim3(1), dim3(kRedBlocks), 0, s, partial, nvals, out);
+  else if (nvals <= 32) hipLaunchKernelGGL(k_finalize<32>, dim3(1), dim3(kRedBlocks), 0, s, partial, nvals, out);
+  else hipLaunchKernelGGL(k_finalize<80>, dim3(1), dim3(kRedBlocks), 0, s, partial, nvals, out);
 }
 
 void launch_sum2(long long n, const double* x, const double* y, const double* yn, double* partial,

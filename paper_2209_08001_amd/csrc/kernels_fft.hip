@@ -88,6 +88,160 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_lines(double2* __restrict__
   }
 }
 
+// ---- fused 2D pipeline ------------------------------------------------------------------
+// In-LDS transform of one line of n = 2^logn complex points stored at buf[0 .. n) in
+// bit-reversed order; radix-4 stage pairs (two radix-2 stages per thread, 4 points in
+// registers) and a final radix-2 stage when logn is odd.  All threads of the block take part;
+// nl lines are transformed together (line l at buf + l * n).
+__device__ inline void fft_lds(double2* buf, int n, int logn, int nl, const double2* __restrict__ tw,
+                               int inverse) {
+  int s = 1;
+  for (; s + 1 <= logn; s += 2) {
+    const int half = 1 << (s - 1);
+    const int nq = n >> 2;  // quads per line
+    for (int t = threadIdx.x; t < nl * nq; t += blockDim.x) {
+      const int l = t / nq, r = t - l * nq;
+      const int grp = r / half, pos = r - grp * half;
+      double2* b = buf + l * n + grp * 4 * half + pos;
+      double2 w1 = tw[pos * (n >> s)];                 // W_{2 half}^pos
+      double2 w2 = tw[pos * (n >> (s + 1))];           // W_{4 half}^pos
+      double2 w3 = tw[(pos + half) * (n >> (s + 1))];  // W_{4 half}^(pos + half)
+      if (inverse) {
+        w1.y = -w1.y;
+        w2.y = -w2.y;
+        w3.y = -w3.y;
+      }
+      const double2 a0 = b[0], a1 = cmul(b[half], w1), a2 = b[2 * half], a3 = cmul(b[3 * half], w1);
+      const double2 c0 = make_double2(a0.x + a1.x, a0.y + a1.y), c1 = make_double2(a0.x - a1.x, a0.y - a1.y);
+      const double2 c2 = make_double2(a2.x + a3.x, a2.y + a3.y), c3 = make_double2(a2.x - a3.x, a2.y - a3.y);
+      const double2 d2 = cmul(c2, w2), d3 = cmul(c3, w3);
+      b[0] = make_double2(c0.x + d2.x, c0.y + d2.y);
+      b[2 * half] = make_double2(c0.x - d2.x, c0.y - d2.y);
+      b[half] = make_double2(c1.x + d3.x, c1.y + d3.y);
+      b[3 * half] = make_double2(c1.x - d3.x, c1.y - d3.y);
+    }
+    __syncthreads();
+  }
+  if (s == logn) {
+    const int half = 1 << (s - 1);
+    const int nh = n >> 1;
+    for (int t = threadIdx.x; t < nl * nh; t += blockDim.x) {
+      const int l = t / nh, r = t - l * nh;
+      const int grp = r / half, pos = r - grp * half;
+      double2* b = buf + l * n + grp * 2 * half + pos;
+      double2 w = tw[pos * (n >> s)];
+      if (inverse) w.y = -w.y;
+      const double2 a0 = b[0], a1 = cmul(b[half], w);
+      b[0] = make_double2(a0.x + a1.x, a0.y + a1.y);
+      b[half] = make_double2(a0.x - a1.x, a0.y - a1.y);
+    }
+    __syncthreads();
+  }
+}
+
+__device__ inline int brev(int p, int logn) { return (int)(__brev((unsigned)p) >> (32 - logn)); }
+
+// pass 1: rows j0 .. j0+nl-1: q = r_u + a Dhat z_c packed as q_x + i q_y, forward FFT along x
+__global__ __launch_bounds__(256) void k_fft2_rows_fwd(Consts K, const double* __restrict__ r, double a,
+                                                       const double* __restrict__ zc, int logn, int nl,
+                                                       const double2* __restrict__ tw,
+                                                       double2* __restrict__ out) {
+  extern __shared__ double2 sm[];  // nl * n
+  const int n = K.nx;
+  const int j0 = blockIdx.x * nl;
+  for (int e = threadIdx.x; e < nl * n; e += blockDim.x) {
+    const int l = e / n, i = e - l * n, j = j0 + l;
+    const long long m = (long long)i + (long long)n * j;
+    double qx = r ? r[m] : 0.0, qy = r ? r[K.N + m] : 0.0;
+    if (zc && a != 0.0) {
+      const int ip = (i + 1 == n) ? 0 : i + 1, im = (i == 0) ? n - 1 : i - 1;
+      const int jp = (j + 1 == K.ny) ? 0 : j + 1, jm = (j == 0) ? K.ny - 1 : j - 1;
+      qx += a * (zc[ip + (long long)n * j] - zc[im + (long long)n * j]) * K.i2h;
+      qy += a * (zc[i + (long long)n * jp] - zc[i + (long long)n * jm]) * K.i2h;
+    }
+    sm[l * n + brev(i, logn)] = make_double2(qx, qy);
+  }
+  __syncthreads();
+  fft_lds(sm, n, logn, nl, tw, 0);
+  for (int e = threadIdx.x; e < nl * n; e += blockDim.x) {
+    const int l = e / n, i = e - l * n;
+    out[(long long)i + (long long)n * (j0 + l)] = sm[e];
+  }
+}
+
+// pass 2: the column pair (kx, -kx): forward FFT along y, pointwise solve of the 2 x 2
+// symbol system (needs Z(k) and Z(-k), both in this block), inverse FFT along y.
+__global__ __launch_bounds__(256) void k_fft2_cols_solve(Consts K, int logn, const double2* __restrict__ tw,
+                                                         const double* __restrict__ sx,
+                                                         const double* __restrict__ syt,
+                                                         double2* __restrict__ data) {
+  extern __shared__ double2 sm[];  // 2 n, then the output spectra (2 n)
+  double2* wo = sm + 2 * K.ny;
+  const int n = K.ny, nx = K.nx;
+  const int kx = blockIdx.x;           // 0 .. nx/2
+  const int kxm = (kx == 0) ? 0 : nx - kx;
+  const int ncol = (kx == kxm) ? 1 : 2;
+  for (int e = threadIdx.x; e < ncol * n; e += blockDim.x) {
+    const int l = e / n, j = e - l * n;
+    const int col = l ? kxm : kx;
+    sm[l * n + brev(j, logn)] = data[(long long)col + (long long)nx * j];
+  }
+  __syncthreads();
+  fft_lds(sm, n, logn, ncol, tw, 0);
+  for (int e = threadIdx.x; e < ncol * n; e += blockDim.x) {
+    const int l = e / n, j = e - l * n;
+    const int col = l ? kxm : kx;
+    const int lm = (ncol == 1) ? 0 : 1 - l;   // the mirror column's line
+    const int jm = (j == 0) ? 0 : n - j;
+    const double2 av = sm[l * n + j], bv = sm[lm * n + jm];
+    double2 Q0 = make_double2(0.5 * (av.x + bv.x), 0.5 * (av.y - bv.y));
+    double2 Q1 = make_double2(0.5 * (av.y + bv.y), -0.5 * (av.x - bv.x));
+    double2 U0 = make_double2(0.0, 0.0), U1 = make_double2(0.0, 0.0);
+    const double S0 = sx[col], S1 = syt[j];
+    const double s2 = S0 * S0 + S1 * S1;
+    if (!K.elastic) {
+      U0 = Q0;
+      U1 = Q1;
+    } else if (s2 != 0.0) {
+      const double A00 = -(K.C11 * S0 * S0 + K.C44 * S1 * S1), A11 = -(K.C11 * S1 * S1 + K.C44 * S0 * S0);
+      const double A01 = -(K.C12 + K.C44) * S0 * S1;
+      const double id = 1.0 / (A00 * A11 - A01 * A01);
+      U0 = make_double2((A11 * Q0.x - A01 * Q1.x) * id, (A11 * Q0.y - A01 * Q1.y) * id);
+      U1 = make_double2((A00 * Q1.x - A01 * Q0.x) * id, (A00 * Q1.y - A01 * Q0.y) * id);
+    }
+    // spectrum of u_x + i u_y, written in bit-reversed order for the inverse transform
+    wo[l * n + brev(j, logn)] = make_double2(U0.x - U1.y, U0.y + U1.x);
+  }
+  __syncthreads();
+  fft_lds(wo, n, logn, ncol, tw, 1);
+  for (int e = threadIdx.x; e < ncol * n; e += blockDim.x) {
+    const int l = e / n, j = e - l * n;
+    const int col = l ? kxm : kx;
+    data[(long long)col + (long long)nx * j] = wo[e];
+  }
+}
+
+// pass 3: inverse FFT along x, unpack u_x = Re / N, u_y = Im / N
+__global__ __launch_bounds__(256) void k_fft2_rows_inv(Consts K, int logn, int nl, const double2* __restrict__ tw,
+                                                       const double2* __restrict__ in, double* __restrict__ u) {
+  extern __shared__ double2 sm[];  // nl * n
+  const int n = K.nx;
+  const int j0 = blockIdx.x * nl;
+  for (int e = threadIdx.x; e < nl * n; e += blockDim.x) {
+    const int l = e / n, i = e - l * n;
+    sm[l * n + brev(i, logn)] = in[(long long)i + (long long)n * (j0 + l)];
+  }
+  __syncthreads();
+  fft_lds(sm, n, logn, nl, tw, 1);
+  const double inv = 1.0 / (double)K.N;
+  for (int e = threadIdx.x; e < nl * n; e += blockDim.x) {
+    const int l = e / n, i = e - l * n;
+    const long long m = (long long)i + (long long)n * (j0 + l);
+    u[m] = sm[e].x * inv;
+    u[K.N + m] = sm[e].y * inv;
+  }
+}
+
 __device__ inline int wrapi(int a, int n) {
   a += (a < 0) ? n : 0;
   a -= (a >= n) ? n : 0;
@@ -95,15 +249,17 @@ __device__ inline int wrapi(int a, int n) {
 }
 
 // q_I = r_I + a Dhat_I zc; z0 = q_1 + i q_2, z1 = q_3 (3D)
+template <int DIM>
 __global__ __launch_bounds__(256) void k_pack(Consts K, const double* __restrict__ r, double a,
                                               const double* __restrict__ zc, double2* __restrict__ z0,
                                               double2* __restrict__ z1) {
-  for (long long n = (long long)blockIdx.x * 256 + threadIdx.x; n < K.N; n += (long long)gridDim.x * 256) {
-    const int i = (int)(n % K.nx);
-    const long long t = n / K.nx;
-    const int j = (int)(t % K.ny), k = (int)(t / K.ny);
+  const int i = blockIdx.x * 256 + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
+  if (i >= K.nx) return;
+  {
+    const long long n = (long long)i + (long long)K.nx * ((long long)j + (long long)K.ny * k);
     double q[3] = {0.0, 0.0, 0.0};
-    for (int I = 0; I < K.dim; ++I) {
+#pragma unroll
+    for (int I = 0; I < DIM; ++I) {
       double v = r ? r[I * K.N + n] : 0.0;
       if (zc && a != 0.0) {
         long long np, nm;
@@ -122,46 +278,53 @@ __global__ __launch_bounds__(256) void k_pack(Consts K, const double* __restrict
       q[I] = v;
     }
     z0[n] = make_double2(q[0], q[1]);
-    if (K.dim == 3) z1[n] = make_double2(q[2], 0.0);
+    if (DIM == 3) z1[n] = make_double2(q[2], 0.0);
   }
 }
 
 // pointwise solve Khat uhat = qhat; w0 = uhat_1 + i uhat_2, w1 = uhat_3
+template <int DIM>
 __global__ __launch_bounds__(256) void k_symbol_solve(Consts K, const double2* __restrict__ z0,
                                                       const double2* __restrict__ z1,
                                                       double2* __restrict__ w0,
-                                                      double2* __restrict__ w1) {
-  for (long long n = (long long)blockIdx.x * 256 + threadIdx.x; n < K.N; n += (long long)gridDim.x * 256) {
-    const int i = (int)(n % K.nx);
-    const long long t = n / K.nx;
-    const int j = (int)(t % K.ny), k = (int)(t / K.ny);
+                                                      double2* __restrict__ w1,
+                                                      const double* __restrict__ sx,
+                                                      const double* __restrict__ sy,
+                                                      const double* __restrict__ szt) {
+  const int i = blockIdx.x * 256 + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
+  if (i >= K.nx) return;
+  {
+    const long long n = (long long)i + (long long)K.nx * ((long long)j + (long long)K.ny * k);
     const long long nm = (long long)wrapi(-i, K.nx) +
                          (long long)K.nx * ((long long)wrapi(-j, K.ny) + (long long)K.ny * wrapi(-k, K.nz));
     double S[3];
-    S[0] = sinpi(2.0 * i / K.nx) * K.ih;
-    S[1] = sinpi(2.0 * j / K.ny) * K.ih;
-    S[2] = (K.dim == 3) ? sinpi(2.0 * k / K.nz) * K.ih : 0.0;
+    S[0] = sx[i];
+    S[1] = sy[j];
+    S[2] = (DIM == 3) ? szt[k] : 0.0;
     const double2 a = z0[n], b = z0[nm];
     // spectra of the two real fields packed in z0
     double2 Q[3];
     Q[0] = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
     Q[1] = make_double2(0.5 * (a.y + b.y), -0.5 * (a.x - b.x));
-    Q[2] = (K.dim == 3) ? z1[n] : make_double2(0.0, 0.0);
+    Q[2] = (DIM == 3) ? z1[n] : make_double2(0.0, 0.0);
     double2 U[3] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
     double s2 = S[0] * S[0] + S[1] * S[1] + S[2] * S[2];
     if (!K.elastic) {
-      for (int I = 0; I < K.dim; ++I) U[I] = Q[I];  // identity rows when there is no elasticity
+#pragma unroll
+      for (int I = 0; I < DIM; ++I) U[I] = Q[I];  // identity rows when there is no elasticity
     } else if (s2 != 0.0) {
       double A[3][3];
-      for (int I = 0; I < K.dim; ++I)
-        for (int L = 0; L < K.dim; ++L) {
+#pragma unroll
+      for (int I = 0; I < DIM; ++I)
+#pragma unroll
+        for (int L = 0; L < DIM; ++L) {
           if (I == L) {
             A[I][I] = -(K.C11 * S[I] * S[I] + K.C44 * (s2 - S[I] * S[I]));
           } else {
             A[I][L] = -(K.C12 + K.C44) * S[I] * S[L];
           }
         }
-      if (K.dim == 2) {
+      if (DIM == 2) {
         const double det = A[0][0] * A[1][1] - A[0][1] * A[1][0];
         const double id = 1.0 / det;
         for (int c = 0; c < 2; ++c) {
@@ -202,7 +365,7 @@ __global__ __launch_bounds__(256) void k_symbol_solve(Consts K, const double2* _
     }
     // u_1 + i u_2 has spectrum U_1 + i U_2
     w0[n] = make_double2(U[0].x - U[1].y, U[0].y + U[1].x);
-    if (K.dim == 3) w1[n] = U[2];
+    if (DIM == 3) w1[n] = U[2];
   }
 }
 
@@ -227,8 +390,12 @@ int ilog2(int n) {
 void fft_dir(const Consts& K, const FftPlan& P, double2* data, int dir, int inverse, hipStream_t s) {
   const int n = P.n[dir];
   const int logn = ilog2(n);
-  int lpb = kFftLds / n;
+  // enough workgroups to fill the chip: one 256-butterfly stage per workgroup (n <= 512),
+  // at least two adjacent lines for the strided passes (32-byte segments)
+  int lpb = 512 / n;
   if (lpb < 1) lpb = 1;
+  if (dir != 0 && lpb < 2) lpb = 2;
+  if (lpb * n > kFftLds) lpb = kFftLds / n;
   long long nlines, la, lb, lc, pstride;
   const long long nx = K.nx, ny = K.ny;
   if (dir == 0) {
@@ -272,14 +439,31 @@ int grid_n(long long n) {
 void launch_spectral_solve(const Consts& K, const FftPlan& P, const double* r, double a,
                            const double* zc, double2* work0, double2* work1, double* u,
                            hipStream_t s) {
+  if (K.dim == 2 && K.ny <= 1024 && K.nx <= 1024) {
+    const int lx = ilog2(K.nx), ly = ilog2(K.ny);
+    int nl = 512 / K.nx;
+    if (nl < 1) nl = 1;
+    while (K.ny % nl) nl >>= 1;
+    const size_t lrow = sizeof(double2) * nl * K.nx, lcol = sizeof(double2) * 4 * K.ny;
+    hipLaunchKernelGGL(k_fft2_rows_fwd, dim3(K.ny / nl), dim3(256), lrow, s, K, r, a, zc, lx, nl, P.tw[0], work0);
+    hipLaunchKernelGGL(k_fft2_cols_solve, dim3(K.nx / 2 + 1), dim3(256), lcol, s, K, ly, P.tw[1], P.sn[0],
+                       P.sn[1], work0);
+    hipLaunchKernelGGL(k_fft2_rows_inv, dim3(K.ny / nl), dim3(256), lrow, s, K, lx, nl, P.tw[0], work0, u);
+    return;
+  }
   double2* z0 = work0;
   double2* z1 = work0 + K.N;
   double2* w0 = work1;
   double2* w1 = work1 + K.N;
-  hipLaunchKernelGGL(k_pack, dim3(grid_n(K.N)), dim3(256), 0, s, K, r, a, zc, z0, z1);
+  const dim3 g3((K.nx + 255) / 256, K.ny, K.nz);
+  if (K.dim == 2) hipLaunchKernelGGL(k_pack<2>, g3, dim3(256), 0, s, K, r, a, zc, z0, z1);
+  else hipLaunchKernelGGL(k_pack<3>, g3, dim3(256), 0, s, K, r, a, zc, z0, z1);
   fft_all(K, P, z0, 0, s);
   if (K.dim == 3) fft_all(K, P, z1, 0, s);
-  hipLaunchKernelGGL(k_symbol_solve, dim3(grid_n(K.N)), dim3(256), 0, s, K, z0, z1, w0, w1);
+  if (K.dim == 2)
+    hipLaunchKernelGGL(k_symbol_solve<2>, g3, dim3(256), 0, s, K, z0, z1, w0, w1, P.sn[0], P.sn[1], P.sn[2]);
+  else
+    hipLaunchKernelGGL(k_symbol_solve<3>, g3, dim3(256), 0, s, K, z0, z1, w0, w1, P.sn[0], P.sn[1], P.sn[2]);
   fft_all(K, P, w0, 1, s);
   if (K.dim == 3) fft_all(K, P, w1, 1, s);
   hipLaunchKernelGGL(k_unpack, dim3(grid_n(K.N)), dim3(256), 0, s, K, w0, w1, u);

@@ -24,7 +24,7 @@ namespace pf {
 
 namespace {
 
-constexpr int kRasThreads = 512;
+constexpr int kRasThreads = 768;
 
 struct Geo {
   int ex, ey, ez;      // extended tile
@@ -90,22 +90,27 @@ __global__ __launch_bounds__(kRasThreads) void k_ras(Consts K, Geo G, double dt,
                                                      const double* __restrict__ rg,
                                                      double* __restrict__ zg) {
   constexpr int NFZ = WU ? 4 + DIM : 4;
+  constexpr int NCOL = (DIM == 3) ? 7 : 5;
   extern __shared__ double lds[];
   const int zsz = G.zx * G.zy * G.zz;
   const int dsz = G.dx * G.dy * G.dz;
-  double* zs = lds;              // NFZ planes of zsz
-  double* dg = zs + NFZ * zsz;   // dsz
+  const int ne = G.ex * G.ey * G.ez;
+  double* zs = lds;              // NFZ planes of zsz: the iterate with a zero ring of 2
+  double* dg = zs + NFZ * zsz;   // dsz: dG on ext and a ring of 1
   double* gg = dg + dsz;         // dsz: g = c^n (1 - c^n)
+  double* bc = gg + dsz;         // 4 planes of ne: c-row of the chemical block
+  int* perm = (int*)(bc + 4 * ne);  // ne: ext nodes sorted by colour
+  int* rowoff = perm + ne;          // NCOL * rows: colour offsets of each row
+  __shared__ int cstart[NCOL + 1], cfill[NCOL];
 
   const int t = blockIdx.x;
   const int tix = t % G.ntx, tiy = (t / G.ntx) % G.nty, tiz = t / (G.ntx * G.nty);
   const int ox = tix * G.tx - G.ov, oy = tiy * G.ty - G.ov, oz = (DIM == 3) ? tiz * G.tz - G.ov : 0;
   const long long N = K.N;
-  const int sy = G.zx, sz = G.zx * G.zy;  // LDS strides of the iterate
-  const int ty_ = G.dx, tz_ = G.dx * G.dy; // strides of dG / g
+  const int sy = G.zx, sz = G.zx * G.zy;    // LDS strides of the iterate
+  const int ty_ = G.dx, tz_ = G.dx * G.dy;  // strides of dG / g
   const int ring = 2;
 
-  for (int q = threadIdx.x; q < NFZ * zsz; q += kRasThreads) zs[q] = 0.0;
   for (int q = threadIdx.x; q < dsz; q += kRasThreads) {
     const int a = q % G.dx, b = (q / G.dx) % G.dy, c = q / (G.dx * G.dy);
     const int gi = wrapg(ox + a - 1, K.nx), gj = wrapg(oy + b - 1, K.ny);
@@ -114,104 +119,187 @@ __global__ __launch_bounds__(kRasThreads) void k_ras(Consts K, Geo G, double dt,
     gg[q] = v * (1.0 - v);
     dg[q] = 0.0;
   }
+  __syncthreads();
+  // c-row blocks into LDS
+  for (int q = threadIdx.x; q < ne; q += kRasThreads) {
+    const int a = q % G.ex, b = (q / G.ex) % G.ey, c = q / (G.ex * G.ey);
+    const int gi = wrapg(ox + a, K.nx), gj = wrapg(oy + b, K.ny);
+    const int gk = (DIM == 3) ? wrapg(oz + c, K.nz) : 0;
+    const long long n = gi + (long long)K.nx * (gj + (long long)K.ny * gk);
+#pragma unroll
+    for (int f = 0; f < 4; ++f) bc[f * ne + q] = Bg[f * N + n];
+  }
+  // Colour-sorted order, computed arithmetically: in row (b, c) the nodes of colour col are
+  // a = r0 + NCOL m with r0 = (col - 2b - 3c) mod NCOL; rowoff[col][row] is the number of
+  // colour-col nodes in the rows before.  (The order inside a colour is immaterial: nodes of
+  // one colour do not couple.)
+  const int nrow = G.ey * G.ez;
+  for (int idx = threadIdx.x; idx < NCOL * nrow; idx += kRasThreads) {
+    const int col = idx / nrow, row = idx % nrow;
+    int acc = 0;
+    for (int r = 0; r < row; ++r) {
+      const int b = r % G.ey, c = r / G.ey;
+      const int r0 = ((col - 2 * b - ((DIM == 3) ? 3 * c : 0)) % NCOL + NCOL) % NCOL;
+      acc += (r0 < G.ex) ? (G.ex - 1 - r0) / NCOL + 1 : 0;
+    }
+    rowoff[idx] = acc;
+  }
+  __syncthreads();
+  if (threadIdx.x < NCOL) {
+    const int col = threadIdx.x, r = nrow - 1;
+    const int b = r % G.ey, c = r / G.ey;
+    const int r0 = ((col - 2 * b - ((DIM == 3) ? 3 * c : 0)) % NCOL + NCOL) % NCOL;
+    cfill[col] = rowoff[col * nrow + r] + ((r0 < G.ex) ? (G.ex - 1 - r0) / NCOL + 1 : 0);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int c = 0; c < NCOL; ++c) {
+      cstart[c] = acc;
+      acc += cfill[c];
+    }
+    cstart[NCOL] = acc;
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < ne; q += kRasThreads) {
+    const int a = q % G.ex, b = (q / G.ex) % G.ey, c = q / (G.ex * G.ey);
+    const int col = (DIM == 3) ? (a + 2 * b + 3 * c) % 7 : (a + 2 * b) % 5;
+    const int r0 = ((col - 2 * b - ((DIM == 3) ? 3 * c : 0)) % NCOL + NCOL) % NCOL;
+    perm[cstart[col] + rowoff[col * nrow + b + G.ey * c] + (a - r0) / NCOL] = q;
+  }
+  __syncthreads();
 
-  // owned nodes: rhs and chemical block in registers
-  const int ne = G.ex * G.ey * G.ez;
+  // nodes of this thread: right-hand side and eta-rows of the chemical block in registers.
+  // The planes are staged through LDS four at a time with row-major (coalesced) loads and
+  // then picked up by the thread that owns each node in colour order.
   double rr[NPT][NFZ];
-  double bb[NPT][16];
-  int zi_[NPT], di_[NPT], col_[NPT];
+  double be[NPT][12];
+  int zi_[NPT], di_[NPT], q_[NPT], col_[NPT];
 #pragma unroll
   for (int m = 0; m < NPT; ++m) {
-    const int q = threadIdx.x + m * kRasThreads;
+    const int pos = threadIdx.x + m * kRasThreads;
     col_[m] = -1;
-    zi_[m] = 0;
-    di_[m] = 0;
-    if (q < ne) {
+    zi_[m] = di_[m] = q_[m] = 0;
+    if (pos < ne) {
+      const int q = perm[pos];
+      const int a = q % G.ex, b = (q / G.ex) % G.ey, c = q / (G.ex * G.ey);
+      q_[m] = q;
+      zi_[m] = (a + ring) + sy * (b + ring) + ((DIM == 3) ? sz * (c + ring) : 0);
+      di_[m] = (a + 1) + ty_ * (b + 1) + ((DIM == 3) ? tz_ * (c + 1) : 0);
+      col_[m] = (DIM == 3) ? (a + 2 * b + 3 * c) % 7 : (a + 2 * b) % 5;
+    }
+  }
+  constexpr int NPL = NFZ + 12;  // staged planes: r (NFZ), then B rows 1..3 (12)
+  for (int p0 = 0; p0 < NPL; p0 += 4) {
+    const int np = (NPL - p0 < 4) ? NPL - p0 : 4;
+    for (int q = threadIdx.x; q < ne; q += kRasThreads) {
       const int a = q % G.ex, b = (q / G.ex) % G.ey, c = q / (G.ex * G.ey);
       const int gi = wrapg(ox + a, K.nx), gj = wrapg(oy + b, K.ny);
       const int gk = (DIM == 3) ? wrapg(oz + c, K.nz) : 0;
       const long long n = gi + (long long)K.nx * (gj + (long long)K.ny * gk);
-      for (int f = 0; f < NFZ; ++f) rr[m][f] = rg[f * N + n];
-      for (int f = 0; f < 16; ++f) bb[m][f] = Bg[f * N + n];
-      zi_[m] = (a + ring) + sy * (b + ring) + ((DIM == 3) ? sz * (c + ring) : 0);
-      di_[m] = (a + 1) + ty_ * (b + 1) + ((DIM == 3) ? tz_ * (c + 1) : 0);
-      col_[m] = (DIM == 3) ? (a + 2 * b + 3 * c) % 7 : (a + 2 * b) % 5;
-    } else {
-#pragma unroll
-      for (int f = 0; f < NFZ; ++f) rr[m][f] = 0.0;
-#pragma unroll
-      for (int f = 0; f < 16; ++f) bb[m][f] = 0.0;
+      for (int k = 0; k < np; ++k) {
+        const int pl = p0 + k;
+        zs[k * ne + q] = (pl < NFZ) ? rg[pl * N + n] : Bg[(4 + pl - NFZ) * N + n];
+      }
     }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < NPT; ++m) {
+      if (col_[m] < 0) continue;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int pl = p0 + k;
+        if (k >= np) break;
+        const double v = zs[k * ne + q_[m]];
+#pragma unroll
+        for (int f = 0; f < NFZ; ++f)
+          if (pl == f) rr[m][f] = v;
+#pragma unroll
+        for (int f = 0; f < 12; ++f)
+          if (pl == NFZ + f) be[m][f] = v;
+      }
+    }
+    __syncthreads();
   }
+  for (int q = threadIdx.x; q < NFZ * zsz; q += kRasThreads) zs[q] = 0.0;
   __syncthreads();
 
-  const int ncol = (DIM == 3) ? 7 : 5;
   const double idt = 1.0 / dt;
   const double lapc = -2.0 * DIM * K.ih2;
   const int sdir_z[3] = {1, sy, sz};
   const int sdir_d[3] = {1, ty_, tz_};
   const double a_u = -0.5 * K.eps0 * K.Ctr;  // coefficient of div_h z_u in dG
+  const double dcc0 = idt;                   // parts of the c-c diagonal entry
+  const double dcc1 = K.kel + K.gamma_c * DIM * K.ih2 + 0.5 * K.gamma_c * K.ih2;
+  const double dee = idt + K.L_eta * K.gamma_eta * DIM * K.ih2;
   bool first = true;
 
   for (int sw = 0; sw < G.sweeps; ++sw) {
     for (int pass = 0; pass < 2; ++pass) {
-      for (int cc = 0; cc < ncol; ++cc) {
-        const int col = pass == 0 ? cc : ncol - 1 - cc;
-        // ---- dG on ext (owned) and on the ring of width 1 ------------------------------
+      for (int cc = 0; cc < NCOL; ++cc) {
+        const int col = pass == 0 ? cc : NCOL - 1 - cc;
+        // ---- dG on ext and on the ring of width 1 (all threads) -----------------------
         if (!first) {
-#pragma unroll
-          for (int m = 0; m < NPT; ++m) {
-            if (col_[m] < 0) continue;
-            const int zi = zi_[m];
-            double s = K.kel * zs[zi];
-#pragma unroll
-            for (int f = 0; f < 4; ++f) s += bb[m][f] * zs[f * zsz + zi];
-            double l = lapc * zs[zi];
-#pragma unroll
-            for (int d = 0; d < DIM; ++d) l += (zs[zi + sdir_z[d]] + zs[zi - sdir_z[d]]) * K.ih2;
-            s -= 0.5 * K.gamma_c * l;
-            if (WU) {
-              double dv = 0.0;
-#pragma unroll
-              for (int d = 0; d < DIM; ++d)
-                dv += zs[(4 + d) * zsz + zi + sdir_z[d]] - zs[(4 + d) * zsz + zi - sdir_z[d]];
-              s += a_u * dv * K.i2h;
-            }
-            dg[di_[m]] = s;
-          }
-          // ring positions (no chemical block there: the iterate is zero outside ext)
-          for (int q = threadIdx.x; q < dsz; q += kRasThreads) {
-            const int a = q % G.dx, b = (q / G.dx) % G.dy, c = q / (G.dx * G.dy);
+          for (int qd = threadIdx.x; qd < dsz; qd += kRasThreads) {
+            const int a = qd % G.dx, b = (qd / G.dx) % G.dy, c = qd / (G.dx * G.dy);
             const bool inside = a >= 1 && a <= G.ex && b >= 1 && b <= G.ey &&
                                 (DIM == 2 || (c >= 1 && c <= G.ez));
-            if (inside) continue;
-            const int zi = (a - 1 + ring) + sy * (b - 1 + ring) + ((DIM == 3) ? sz * (c - 1 + ring) : 0);
-            double l = 0.0;
+            const int pz = (a - 1 + ring) + sy * (b - 1 + ring) + ((DIM == 3) ? sz * (c - 1 + ring) : 0);
+            double l = lapc * zs[pz];
 #pragma unroll
-            for (int d = 0; d < DIM; ++d) l += (zs[zi + sdir_z[d]] + zs[zi - sdir_z[d]]) * K.ih2;
-            double s = -0.5 * K.gamma_c * l;
+            for (int d = 0; d < DIM; ++d) l += (zs[pz + sdir_z[d]] + zs[pz - sdir_z[d]]) * K.ih2;
+            double sg_ = -0.5 * K.gamma_c * l;
+            if (inside) {
+              const int qe = (a - 1) + G.ex * ((b - 1) + ((DIM == 3) ? G.ey * (c - 1) : 0));
+              sg_ += K.kel * zs[pz];
+#pragma unroll
+              for (int f = 0; f < 4; ++f) sg_ += bc[f * ne + qe] * zs[f * zsz + pz];
+            }
             if (WU) {
               double dv = 0.0;
 #pragma unroll
               for (int d = 0; d < DIM; ++d)
-                dv += zs[(4 + d) * zsz + zi + sdir_z[d]] - zs[(4 + d) * zsz + zi - sdir_z[d]];
-              s += a_u * dv * K.i2h;
+                dv += zs[(4 + d) * zsz + pz + sdir_z[d]] - zs[(4 + d) * zsz + pz - sdir_z[d]];
+              sg_ += a_u * dv * K.i2h;
             }
-            dg[q] = s;
+            dg[qd] = sg_;
           }
           __syncthreads();
         }
         first = false;
-        // ---- update the nodes of this colour -------------------------------------------
+        // ---- update the nodes of this colour (a contiguous range of threads) -------------
+        // A thread's nodes lie in different colour ranges (a range is shorter than the block),
+        // so at most one of them is active here: select it, then run one copy of the update.
+        int msel = -1;
 #pragma unroll
-        for (int m = 0; m < NPT; ++m) {
-          if (col_[m] != col) continue;
-          const int zi = zi_[m], di = di_[m];
+        for (int m = 0; m < NPT; ++m)
+          if (col_[m] == col) msel = m;
+        if (msel >= 0) {
+          double rv[NFZ], bv[12];
+#pragma unroll
+          for (int f = 0; f < NFZ; ++f) {
+            rv[f] = rr[0][f];
+#pragma unroll
+            for (int m = 1; m < NPT; ++m) rv[f] = (msel == m) ? rr[m][f] : rv[f];
+          }
+#pragma unroll
+          for (int f = 0; f < 12; ++f) {
+            bv[f] = be[0][f];
+#pragma unroll
+            for (int m = 1; m < NPT; ++m) bv[f] = (msel == m) ? be[m][f] : bv[f];
+          }
+          int zi = zi_[0], di = di_[0], q = q_[0];
+#pragma unroll
+          for (int m = 1; m < NPT; ++m) {
+            zi = (msel == m) ? zi_[m] : zi;
+            di = (msel == m) ? di_[m] : di;
+            q = (msel == m) ? q_[m] : q;
+          }
           double zv[NFZ];
 #pragma unroll
           for (int f = 0; f < NFZ; ++f) zv[f] = zs[f * zsz + zi];
           double res[NFZ];
-          // c row
+          // c row: z_c/dt - div_h(M grad_h dG)
           double sumM = 0.0, dM[3] = {0.0, 0.0, 0.0};
           double divm = 0.0;
           const double g0 = gg[di], dg0 = dg[di];
@@ -223,26 +311,27 @@ __global__ __launch_bounds__(kRasThreads) void k_ras(Consts K, Geo G, double dt,
             sumM += Mp + Mm;
             dM[d] = Mm - Mp;
           }
-          res[0] = rr[m][0] - (zv[0] * idt - divm * K.ih2);
-          // eta rows
+          res[0] = rv[0] - (zv[0] * idt - divm * K.ih2);
+          // eta rows: z_e/dt + L_eta (B_e . z - (gamma_eta/2) Lap_h z_e)
 #pragma unroll
           for (int e = 0; e < 3; ++e) {
             const int ze = (1 + e) * zsz + zi;
-            double l = lapc * zs[ze];
+            double l = lapc * zv[1 + e];
 #pragma unroll
             for (int d = 0; d < DIM; ++d) l += (zs[ze + sdir_z[d]] + zs[ze - sdir_z[d]]) * K.ih2;
             double s = -0.5 * K.gamma_eta * l;
 #pragma unroll
-            for (int f = 0; f < 4; ++f) s += bb[m][4 * (1 + e) + f] * zv[f];
-            res[1 + e] = rr[m][1 + e] - (zv[1 + e] * idt + K.L_eta * s);
+            for (int f = 0; f < 4; ++f) s += bv[4 * e + f] * zv[f];
+            res[1 + e] = rv[1 + e] - (zv[1 + e] * idt + K.L_eta * s);
           }
-          // u rows
+          // u rows: sum_J Dhat_J sigma_IJ(z_u, z_c)
           if (WU) {
 #pragma unroll
             for (int I = 0; I < DIM; ++I) {
               double acc = 0.0;
 #pragma unroll
               for (int J = 0; J < DIM; ++J) {
+#pragma unroll
                 for (int sgn = -1; sgn <= 1; sgn += 2) {
                   const int pz = zi + sgn * sdir_z[J];
                   double sig;
@@ -261,55 +350,64 @@ __global__ __launch_bounds__(kRasThreads) void k_ras(Consts K, Geo G, double dt,
                   acc += sgn * sig;
                 }
               }
-              res[4 + I] = rr[m][4 + I] - acc * K.i2h;
+              res[4 + I] = rv[4 + I] - acc * K.i2h;
             }
           }
-          // diagonal block and its solve
-          double Dw[4][4];
+          // diagonal block of the node, solved through the Schur complement on c:
+          //   [d_cc  u'] [x_c]   [r_c]      E = dee I + L_eta B_ee (3 x 3, dominated by 1/dt)
+          //   [v     E ] [x_e] = [r_e],     x_c = (r_c - u'E^{-1} r_e) / (d_cc - u'E^{-1} v)
           const double sc = sumM * K.ih2;
-          Dw[0][0] = idt + sc * (bb[m][0] + K.kel + K.gamma_c * DIM * K.ih2 + 0.5 * K.gamma_c * K.ih2);
-          for (int q = 1; q < 4; ++q) Dw[0][q] = sc * bb[m][q];
-#pragma unroll
-          for (int e = 0; e < 3; ++e) {
-            Dw[1 + e][0] = K.L_eta * bb[m][4 * (1 + e)];
-#pragma unroll
-            for (int q = 1; q < 4; ++q)
-              Dw[1 + e][q] = K.L_eta * bb[m][4 * (1 + e) + q] + ((q == 1 + e) ? idt + K.L_eta * K.gamma_eta * DIM * K.ih2 : 0.0);
-          }
-          double x[4] = {res[0], res[1], res[2], res[3]};
-          double xu[3] = {0.0, 0.0, 0.0};
+          double xc = res[0];
           if (WU) {
-            const double duu = -(K.C11 + (DIM - 1) * K.C44) * 0.5 * K.ih2;
+            const double iduu = -2.0 * K.h * K.h / (K.C11 + (DIM - 1) * K.C44);
 #pragma unroll
             for (int I = 0; I < DIM; ++I) {
-              xu[I] = res[4 + I] / duu;
-              x[0] -= (K.eps0 * K.Ctr * 0.25 * K.ih2 * K.ih) * dM[I] * xu[I];
+              res[4 + I] *= iduu;  // x_u
+              xc -= (K.eps0 * K.Ctr * 0.25 * K.ih2 * K.ih) * dM[I] * res[4 + I];
             }
           }
-          solve_small<4>(Dw, x);
+          double E00 = dee + K.L_eta * bv[1], E01 = K.L_eta * bv[2], E02 = K.L_eta * bv[3];
+          double E10 = K.L_eta * bv[5], E11 = dee + K.L_eta * bv[6], E12 = K.L_eta * bv[7];
+          double E20 = K.L_eta * bv[9], E21 = K.L_eta * bv[10], E22 = dee + K.L_eta * bv[11];
+          const double A00 = E11 * E22 - E12 * E21, A01 = E02 * E21 - E01 * E22, A02 = E01 * E12 - E02 * E11;
+          const double A10 = E12 * E20 - E10 * E22, A11 = E00 * E22 - E02 * E20, A12 = E02 * E10 - E00 * E12;
+          const double A20 = E10 * E21 - E11 * E20, A21 = E01 * E20 - E00 * E21, A22 = E00 * E11 - E01 * E10;
+          const double idet = 1.0 / (E00 * A00 + E01 * A10 + E02 * A20);
+          // y = E^{-1} r_e, w = E^{-1} v  (v_e = L_eta B_e,c)
+          const double r1 = res[1], r2 = res[2], r3 = res[3];
+          const double v1 = K.L_eta * bv[0], v2 = K.L_eta * bv[4], v3 = K.L_eta * bv[8];
+          const double y1 = (A00 * r1 + A01 * r2 + A02 * r3) * idet;
+          const double y2 = (A10 * r1 + A11 * r2 + A12 * r3) * idet;
+          const double y3 = (A20 * r1 + A21 * r2 + A22 * r3) * idet;
+          const double w1 = (A00 * v1 + A01 * v2 + A02 * v3) * idet;
+          const double w2 = (A10 * v1 + A11 * v2 + A12 * v3) * idet;
+          const double w3 = (A20 * v1 + A21 * v2 + A22 * v3) * idet;
+          const double u1 = sc * bc[ne + q], u2 = sc * bc[2 * ne + q], u3 = sc * bc[3 * ne + q];
+          const double dcc = dcc0 + sc * (bc[q] + dcc1);
+          xc = (xc - (u1 * y1 + u2 * y2 + u3 * y3)) / (dcc - (u1 * w1 + u2 * w2 + u3 * w3));
+          double x[4] = {xc, y1 - w1 * xc, y2 - w2 * xc, y3 - w3 * xc};
 #pragma unroll
           for (int f = 0; f < 4; ++f) zs[f * zsz + zi] = zv[f] + x[f];
           if (WU) {
 #pragma unroll
-            for (int I = 0; I < DIM; ++I) zs[(4 + I) * zsz + zi] = zv[4 + I] + xu[I];
+            for (int I = 0; I < DIM; ++I) zs[(4 + I) * zsz + zi] = zv[4 + I] + res[4 + I];
           }
         }
         __syncthreads();
       }
     }
   }
-  // restricted prolongation: write the owned nodes only
-#pragma unroll
-  for (int m = 0; m < NPT; ++m) {
-    if (col_[m] < 0) continue;
-    const int q = threadIdx.x + m * kRasThreads;
+  // restricted prolongation: write the owned nodes only (coalesced, row-major)
+  for (int q = threadIdx.x; q < ne; q += kRasThreads) {
     const int a = q % G.ex, b = (q / G.ex) % G.ey, c = q / (G.ex * G.ey);
     if (a < G.ov || a >= G.ov + G.tx || b < G.ov || b >= G.ov + G.ty) continue;
     if (DIM == 3 && (c < G.ov || c >= G.ov + G.tz)) continue;
     const int gi = wrapg(ox + a, K.nx), gj = wrapg(oy + b, K.ny);
     const int gk = (DIM == 3) ? wrapg(oz + c, K.nz) : 0;
     const long long n = gi + (long long)K.nx * (gj + (long long)K.ny * gk);
-    for (int f = 0; f < NFZ; ++f) zg[f * N + n] = zs[f * zsz + zi_[m]];
+    const int zi = (a + ring) + sy * (b + ring) + ((DIM == 3) ? sz * (c + ring) : 0);
+#pragma unroll
+    for (int f = 0; f < NFZ; ++f) zg[f * N + n] = zs[f * zsz + zi];
   }
 }
 
@@ -346,10 +444,8 @@ void launch_dim(const Consts& K, const Geo& G, size_t lds, int ntiles, int npt, 
     break;
   switch (npt) {
     PF_RAS_CASE(1)
-    PF_RAS_CASE(2)
-    PF_RAS_CASE(3)
     default:
-      PF_RAS_CASE(4)
+      PF_RAS_CASE(2)
   }
 #undef PF_RAS_CASE
 }
@@ -359,15 +455,18 @@ void launch_dim(const Consts& K, const Geo& G, size_t lds, int ntiles, int npt, 
 size_t ras_lds_bytes(const Consts& K, const TileCfg& T) {
   const Geo G = make_geo(K, T);
   const int nfz = T.with_u ? 4 + K.dim : 4;
-  return sizeof(double) * ((size_t)nfz * G.zx * G.zy * G.zz + 2 * (size_t)G.dx * G.dy * G.dz);
+  const size_t ne = (size_t)G.ex * G.ey * G.ez;
+  const size_t ncol = (K.dim == 3) ? 7 : 5;
+  return sizeof(double) * ((size_t)nfz * G.zx * G.zy * G.zz + 2 * (size_t)G.dx * G.dy * G.dz + 4 * ne) +
+         sizeof(int) * (ne + ncol * G.ey * G.ez);
 }
 
-// nodes of the extended tile per thread (1..4), 0 if the tile does not fit
+// nodes of the extended tile per thread (1..2), 0 if the tile does not fit
 int ras_npt(const Consts& K, const TileCfg& T) {
   const Geo G = make_geo(K, T);
   const int ne = G.ex * G.ey * G.ez;
   const int npt = (ne + kRasThreads - 1) / kRasThreads;
-  return npt <= 4 ? npt : 0;
+  return npt <= 2 ? npt : 0;
 }
 
 void launch_ras(const Consts& K, const TileCfg& T, double dt, const double* B, const double* cn,

@@ -60,6 +60,7 @@ size_t ras_lds_bytes(const Consts& K, const TileCfg& T);
 struct FftPlan {
   int n[3];
   const double2* tw[3];  // twiddles exp(-2 pi i k / n), k < n/2, one table per direction
+  const double* sn[3];   // symbols S_m = sin(2 pi m / n) / h, m < n (exact 0 at m = 0, n/2)
 };
 // q_I = r_I + a D-hat_I zc (r may be null), solve K u = q by FFT, write u (d planes).
 void launch_spectral_solve(const Consts& K, const FftPlan& P, const double* r, double a,

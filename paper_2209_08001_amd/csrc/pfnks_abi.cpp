@@ -44,7 +44,7 @@ struct Layout {
 
 enum Buf {
   B_X, B_XN, B_XT, B_F, B_FT, B_S, B_B, B_BPC, B_G4, B_DG, B_V, B_W, B_Z, B_TMP, B_PART, B_RED,
-  B_FFT0, B_FFT1, B_TW0, B_TW1, B_TW2, B_COUNT
+  B_FFT0, B_FFT1, B_TW0, B_TW1, B_TW2, B_SN0, B_SN1, B_SN2, B_COUNT
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -66,6 +66,9 @@ Layout make_layout(int dim, long long N, int restart, const int* n) {
   sz[B_TW0] = sizeof(double2) * (size_t)(n[0] / 2 + 1);
   sz[B_TW1] = sizeof(double2) * (size_t)(n[1] / 2 + 1);
   sz[B_TW2] = sizeof(double2) * (size_t)((dim == 3 ? n[2] : 2) / 2 + 1);
+  sz[B_SN0] = sizeof(double) * (size_t)n[0];
+  sz[B_SN1] = sizeof(double) * (size_t)n[1];
+  sz[B_SN2] = sizeof(double) * (size_t)(dim == 3 ? n[2] : 2);
   Layout L{};
   size_t o = 0;
   for (int b = 0; b < B_COUNT; ++b) {
@@ -95,7 +98,7 @@ int validate(const pfnks_grid* g, const pfnks_model* m, const pfnks_solver* s) {
   if (s->precision != PFNKS_FP64) return PFNKS_EINVAL;
   if (m->S < 1 || m->S > pf::kMaxS) return PFNKS_EINVAL;
   if (!(m->kappa >= 0.0) || !(m->L_eta > 0.0) || m->Lscale < 0.0) return PFNKS_EINVAL;
-  // extended tile must fit the kernel's registers (<= 4 nodes per thread of 512) and the
+  // extended tile must fit the kernel's registers (<= 2 nodes per thread of 768) and the
   // 160 KiB of LDS of one compute unit
   long long ext = 1, zpad = 1, dpad = 1;
   for (int k = 0; k < g->dim; ++k) {
@@ -103,9 +106,13 @@ int validate(const pfnks_grid* g, const pfnks_model* m, const pfnks_solver* s) {
     zpad *= s->tile[k] + 2 * s->overlap + 4;
     dpad *= s->tile[k] + 2 * s->overlap + 2;
   }
-  if (ext > 4 * 512) return PFNKS_EINVAL;
+  if (ext > 2 * 768) return PFNKS_EINVAL;
   const int nfz = (s->pc == PFNKS_PC_RAS) ? 4 + g->dim : 4;
-  if (s->pc <= PFNKS_PC_RAS_SPECTRAL && 8 * (nfz * zpad + 2 * dpad) > 160 * 1024) return PFNKS_EINVAL;
+  const long long rows = (g->dim == 3) ? (long long)(s->tile[1] + 2 * s->overlap) * (s->tile[2] + 2 * s->overlap)
+                                       : (long long)(s->tile[1] + 2 * s->overlap);
+  const long long ncol = (g->dim == 3) ? 7 : 5;
+  if (s->pc <= PFNKS_PC_RAS_SPECTRAL && 8 * (nfz * zpad + 2 * dpad + 4 * ext) + 4 * (ext + ncol * rows) > 160 * 1024)
+    return PFNKS_EINVAL;
   return PFNKS_OK;
 }
 
@@ -599,6 +606,14 @@ int pfnks_create_problem(const pfnks_grid* grid, const pfnks_model* model, const
     if (e != hipSuccess) return fail(device_error(e, "hipMemcpy twiddles"));
     p->plan.tw[d] = dst;
     p->plan.n[d] = nd;
+    // Fourier symbol of the central difference: i sin(2 pi m / n) / h
+    std::vector<double> sn(nd);
+    for (int m = 0; m < nd; ++m)
+      sn[m] = (m == 0 || 2 * m == nd) ? 0.0 : std::sin(2.0 * M_PI * (double)m / (double)nd) / grid->h;
+    double* sdst = (double*)(p->ws + L.off[B_SN0 + d]);
+    e = hipMemcpy(sdst, sn.data(), sizeof(double) * nd, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail(device_error(e, "hipMemcpy symbols"));
+    p->plan.sn[d] = sdst;
   }
   // state: c, eta, u = 0
   e = hipMemcpy(p->Xn, c0, sizeof(double) * N, hipMemcpyHostToDevice);
