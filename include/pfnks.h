@@ -169,9 +169,9 @@ int pfnks_debug_pc(pfnks_problem* p, const double* X, double dt, const double* r
 /* Counters of the last pfnks_step: kernel launches and host synchronisations. */
 int pfnks_debug_counters(pfnks_problem* p, long long* launches, long long* syncs);
 
-/* Live kernel timing.  pfnks_debug_profile(p, 1) clears the totals and brackets every launch
- * of the kernel kinds below with HIP events recorded on the problem's stream (0 switches it
- * off).  pfnks_debug_kernel_time returns, for one kind, the number of timed launches, their
+/* Live kernel timing.  pfnks_debug_profile(p, mask) clears the totals and brackets every
+ * launch of the kernel kinds whose bit (1 << kind) is set in mask with HIP events recorded on
+ * the problem's stream (mask 0 switches it off; each bracket costs two event records).  pfnks_debug_kernel_time returns, for one kind, the number of timed launches, their
  * summed GPU duration in milliseconds and their summed algorithmic bytes (the bytes the
  * operation must move: reads of its inputs plus writes of its outputs, once each). */
 enum {
@@ -184,7 +184,7 @@ enum {
   PFNKS_K_UPDATE = 6,    /* GMRES orthogonal update and normalisation   */
   PFNKS_KERNEL_KINDS = 7
 };
-int pfnks_debug_profile(pfnks_problem* p, int enable);
+int pfnks_debug_profile(pfnks_problem* p, int mask);
 int pfnks_debug_kernel_time(pfnks_problem* p, int kind, long long* launches, double* ms_total,
                             double* bytes_total);
 

@@ -42,7 +42,7 @@ __global__ __launch_bounds__(kThreads) void k_multidot(long long n, int nv, cons
     const double2 we = w2[e];
 #pragma unroll
     for (int v = 0; v < MAXV; ++v)
-      if (v < nv) {
+      if (MAXV <= 32 || v < nv) {
         const double2 y = V2[v * ld2 + e];
         acc[v] += we.x * y.x + we.y * y.y;
       }
@@ -53,7 +53,7 @@ __global__ __launch_bounds__(kThreads) void k_multidot(long long n, int nv, cons
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int v = 0; v <= MAXV; ++v) {
-    if (v < nv || v == MAXV) {
+    if (MAXV <= 32 || v < nv || v == MAXV) {
       double x = acc[v];
       for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
       if (lane == 0) wl[wave][v] = x;
@@ -90,10 +90,49 @@ __global__ __launch_bounds__(kThreads) void k_update(long long n, int nv, const 
     double2 x = w2[e];
 #pragma unroll
     for (int v = 0; v < MAXV; ++v)
-      if (v < nv) {
+      if (MAXV <= 32 || v < nv) {
         const double2 y = V2[v * ld2 + e];
         x.x -= cf.c[v] * y.x;
         x.y -= cf.c[v] * y.y;
+      }
+    acc += x.x * x.x + x.y * x.y;
+    o2[e] = make_double2(scale * x.x, scale * x.y);
+  }
+  double s = block_sum(acc, lds);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// v_{j+1} = (w - sum_v h_v V_v) / h_{j+1,j} with the coefficients read from device memory
+// (hc = [h_0 .. h_{nv-1}, <w, w>], written by the finalize of the multi-dot) and
+// h_{j+1,j} = sqrt(<w,w> - sum h_v^2); partial: ||w - sum h V||^2 for a later check.
+template <int MAXV>
+__global__ __launch_bounds__(kThreads) void k_update_dev(long long n, int nv, const double* __restrict__ V,
+                                                         long long ldv, const double* __restrict__ hc,
+                                                         const double* __restrict__ w, double* __restrict__ out,
+                                                         double* __restrict__ partial) {
+  __shared__ double lds[kThreads / 64];
+  double c[MAXV];
+  double hh = 0.0;
+#pragma unroll
+  for (int v = 0; v < MAXV; ++v) {
+    c[v] = (MAXV <= 32 || v < nv) ? hc[v] : 0.0;
+    hh += c[v] * c[v];
+  }
+  const double scale = 1.0 / sqrt(hc[nv] - hh);
+  double acc = 0.0;
+  const long long n2 = n >> 1, ld2 = ldv >> 1;
+  const double2* __restrict__ V2 = reinterpret_cast<const double2*>(V);
+  const double2* __restrict__ w2 = reinterpret_cast<const double2*>(w);
+  double2* __restrict__ o2 = reinterpret_cast<double2*>(out);
+  for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < n2;
+       e += (long long)gridDim.x * kThreads) {
+    double2 x = w2[e];
+#pragma unroll
+    for (int v = 0; v < MAXV; ++v)
+      if (MAXV <= 32 || v < nv) {
+        const double2 y = V2[v * ld2 + e];
+        x.x -= c[v] * y.x;
+        x.y -= c[v] * y.y;
       }
     acc += x.x * x.x + x.y * x.y;
     o2[e] = make_double2(scale * x.x, scale * x.y);
@@ -111,7 +150,7 @@ __global__ __launch_bounds__(kThreads) void k_lincomb(long long n, int nv, const
     double x = (beta == 0.0) ? 0.0 : beta * out[e];
 #pragma unroll
     for (int v = 0; v < MAXV; ++v)
-      if (v < nv) x += cf.c[v] * V[v * ldv + e];
+      if (MAXV <= 32 || v < nv) x += cf.c[v] * V[v * ldv + e];
     out[e] = x;
   }
 }
@@ -132,15 +171,15 @@ __global__ __launch_bounds__(kThreads) void k_axpby(long long n, double a, const
 // waves.  Fixed order, so the result is deterministic.
 template <int MAXV>
 __global__ __launch_bounds__(kRedBlocks) void k_finalize(const double* __restrict__ partial, int nvals,
-                                                         double* __restrict__ out) {
+                                                         double* __restrict__ out, double* __restrict__ out2) {
   __shared__ double wl[kRedBlocks / 64][MAXV];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double acc[MAXV];
 #pragma unroll
-  for (int v = 0; v < MAXV; ++v) acc[v] = (v < nvals) ? partial[v * kRedBlocks + threadIdx.x] : 0.0;
+  for (int v = 0; v < MAXV; ++v) acc[v] = (MAXV <= 32 || v < nvals) ? partial[v * kRedBlocks + threadIdx.x] : 0.0;
 #pragma unroll
   for (int v = 0; v < MAXV; ++v) {
-    if (v < nvals) {
+    if (MAXV <= 32 || v < nvals) {
       double x = acc[v];
       for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
       if (lane == 0) wl[wave][v] = x;
@@ -151,6 +190,7 @@ __global__ __launch_bounds__(kRedBlocks) void k_finalize(const double* __restric
     double x = 0.0;
     for (int w = 0; w < kRedBlocks / 64; ++w) x += wl[w][threadIdx.x];
     out[threadIdx.x] = x;
+    if (out2) out2[threadIdx.x] = x;
   }
 }
 
@@ -270,18 +310,43 @@ int grid_for(long long n) {
 
 }  // namespace
 
-#define DISPATCH_MAXV(nv, KERNEL, ...)                                               \
-  do {                                                                               \
-    if ((nv) <= 4) hipLaunchKernelGGL(KERNEL<4>, __VA_ARGS__);                       \
-    else if ((nv) <= 8) hipLaunchKernelGGL(KERNEL<8>, __VA_ARGS__);                  \
-    else if ((nv) <= 16) hipLaunchKernelGGL(KERNEL<16>, __VA_ARGS__);                \
-    else if ((nv) <= 32) hipLaunchKernelGGL(KERNEL<32>, __VA_ARGS__);                \
-    else hipLaunchKernelGGL(KERNEL<64>, __VA_ARGS__);                                \
+// Exact-count instantiations (every guarded load is then unconditional and all of them can be
+// in flight at once); counts above 32 use the 64-wide guarded form.
+#define PF_CASE(N, KERNEL, ...) \
+  case N:                       \
+    hipLaunchKernelGGL(KERNEL<N>, __VA_ARGS__); \
+    break;
+#define DISPATCH_MAXV(nv, KERNEL, ...)                                                        \
+  do {                                                                                        \
+    switch (nv) {                                                                             \
+      PF_CASE(1, KERNEL, __VA_ARGS__) PF_CASE(2, KERNEL, __VA_ARGS__)                         \
+      PF_CASE(3, KERNEL, __VA_ARGS__) PF_CASE(4, KERNEL, __VA_ARGS__)                         \
+      PF_CASE(5, KERNEL, __VA_ARGS__) PF_CASE(6, KERNEL, __VA_ARGS__)                         \
+      PF_CASE(7, KERNEL, __VA_ARGS__) PF_CASE(8, KERNEL, __VA_ARGS__)                         \
+      PF_CASE(9, KERNEL, __VA_ARGS__) PF_CASE(10, KERNEL, __VA_ARGS__)                        \
+      PF_CASE(11, KERNEL, __VA_ARGS__) PF_CASE(12, KERNEL, __VA_ARGS__)                       \
+      PF_CASE(13, KERNEL, __VA_ARGS__) PF_CASE(14, KERNEL, __VA_ARGS__)                       \
+      PF_CASE(15, KERNEL, __VA_ARGS__) PF_CASE(16, KERNEL, __VA_ARGS__)                       \
+      PF_CASE(17, KERNEL, __VA_ARGS__) PF_CASE(18, KERNEL, __VA_ARGS__)                       \
+      PF_CASE(19, KERNEL, __VA_ARGS__) PF_CASE(20, KERNEL, __VA_ARGS__)                       \
+      PF_CASE(21, KERNEL, __VA_ARGS__) PF_CASE(22, KERNEL, __VA_ARGS__)                       \
+      PF_CASE(23, KERNEL, __VA_ARGS__) PF_CASE(24, KERNEL, __VA_ARGS__)                       \
+      PF_CASE(25, KERNEL, __VA_ARGS__) PF_CASE(26, KERNEL, __VA_ARGS__)                       \
+      PF_CASE(27, KERNEL, __VA_ARGS__) PF_CASE(28, KERNEL, __VA_ARGS__)                       \
+      PF_CASE(29, KERNEL, __VA_ARGS__) PF_CASE(30, KERNEL, __VA_ARGS__)                       \
+      PF_CASE(31, KERNEL, __VA_ARGS__) PF_CASE(32, KERNEL, __VA_ARGS__)                       \
+      default:                                                                                \
+        hipLaunchKernelGGL(KERNEL<64>, __VA_ARGS__);                                          \
+    }                                                                                         \
   } while (0)
 
 // partial receives nv + 1 values: <w, V_v> for v < nv and <w, w>.  Always kRedBlocks blocks.
 void launch_multidot(long long n, int nv, const double* V, long long ldv, const double* w,
                      double* partial, hipStream_t s) {
+  if (nv == 0) {
+    hipLaunchKernelGGL(k_multidot<0>, dim3(kRedBlocks), dim3(kThreads), 0, s, n, nv, V, ldv, w, partial);
+    return;
+  }
   DISPATCH_MAXV(nv, k_multidot, dim3(kRedBlocks), dim3(kThreads), 0, s, n, nv, V, ldv, w, partial);
 }
 
@@ -292,6 +357,11 @@ void launch_update(long long n, int nv, const double* V, long long ldv, const do
   for (int v = 0; v < nv; ++v) cf.c[v] = coef[v];
   DISPATCH_MAXV(nv, k_update, dim3(kRedBlocks), dim3(kThreads), 0, s, n, nv, V, ldv, cf, w, scale,
                 out, partial);
+}
+
+void launch_update_dev(long long n, int nv, const double* V, long long ldv, const double* hc,
+                       const double* w, double* out, double* partial, hipStream_t s) {
+  DISPATCH_MAXV(nv, k_update_dev, dim3(kRedBlocks), dim3(kThreads), 0, s, n, nv, V, ldv, hc, w, out, partial);
 }
 
 // out = beta * out + sum_v coef[v] V_v
@@ -308,12 +378,12 @@ void launch_axpby(long long n, double a, const double* x, double b, const double
   hipLaunchKernelGGL(k_axpby, dim3(grid_for(n)), dim3(kThreads), 0, s, n, a, x, b, y, out);
 }
 
-void launch_finalize(const double* partial, int nvals, double* out, hipStream_t s) {
-  if (nvals <= 4) hipLaunchKernelGGL(k_finalize<4>, dim3(1), dim3(kRedBlocks), 0, s, partial, nvals, out);
-  else if (nvals <= 8) hipLaunchKernelGGL(k_finalize<8>, dim3(1), dim3(kRedBlocks), 0, s, partial, nvals, out);
-  else if (nvals <= 16) hipLaunchKernelGGL(k_finalize<16>, dim3(1), dim3(kRedBlocks), 0, s, partial, nvals, out);
-  else if (nvals <= 32) hipLaunchKernelGGL(k_finalize<32>, dim3(1), dim3(kRedBlocks), 0, s, partial, nvals, out);
-  else hipLaunchKernelGGL(k_finalize<80>, dim3(1), dim3(kRedBlocks), 0, s, partial, nvals, out);
+void launch_finalize(const double* partial, int nvals, double* out, hipStream_t s, double* out2) {
+  if (nvals > 32) {
+    hipLaunchKernelGGL(k_finalize<80>, dim3(1), dim3(kRedBlocks), 0, s, partial, nvals, out, out2);
+    return;
+  }
+  DISPATCH_MAXV(nvals, k_finalize, dim3(1), dim3(kRedBlocks), 0, s, partial, nvals, out, out2);
 }
 
 void launch_sum2(long long n, const double* x, const double* y, const double* yn, double* partial,

@@ -420,6 +420,74 @@ __global__ __launch_bounds__(kBX* kBY) void k_jv_c(Consts K, double dt, const do
   w[n] = v[n] / dt - div_M_grad(K, dG, cn, p, n);
 }
 
+// fused J v: one block of kBX x kBY (x 1) nodes; dG on the block and a halo of one node is
+// computed into LDS, the c row reads it there; eta and u rows as in k_jv_g.
+template <int DIM>
+__global__ __launch_bounds__(kBX* kBY) void k_jv_fused(Consts K, double dt, const double* __restrict__ B,
+                                                       const double* __restrict__ cn,
+                                                       const double* __restrict__ v,
+                                                       double* __restrict__ w) {
+  constexpr int HX = kBX + 2, HY = kBY + 2, HZ = (DIM == 3) ? 3 : 1;
+  __shared__ double sdg[HX * HY * HZ];
+  const long long N = K.N;
+  const int i0 = blockIdx.x * kBX, j0 = blockIdx.y * kBY, k0 = blockIdx.z;
+  const int tid = threadIdx.x + kBX * threadIdx.y;
+  const double Ka = -0.5 * K.eps0 * K.Ctr;
+  for (int q = tid; q < HX * HY * HZ; q += kBX * kBY) {
+    const int a = q % HX, b = (q / HX) % HY, c = q / (HX * HY);
+    Pt p{wrap(i0 + a - 1, K.nx), wrap(j0 + b - 1, K.ny), (DIM == 3) ? wrap(k0 + c - 1, K.nz) : 0};
+    const long long n = lin(K, p);
+    double vv[4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) vv[f] = v[f * N + n];
+    double g = K.kel * vv[0] - 0.5 * K.gamma_c * lap(K, v, p, vv[0]);
+#pragma unroll
+    for (int f = 0; f < 4; ++f) g += B[f * N + n] * vv[f];
+    if (K.elastic) {
+      double div = 0.0;
+#pragma unroll
+      for (int I = 0; I < DIM; ++I) div += dhat(K, v + (4 + I) * N, p, I);
+      g += Ka * div;
+    }
+    sdg[q] = g;
+  }
+  __syncthreads();
+  Pt p{i0 + (int)threadIdx.x, j0 + (int)threadIdx.y, k0};
+  if (p.i >= K.nx || p.j >= K.ny) return;
+  const long long n = lin(K, p);
+  const int hq = (threadIdx.x + 1) + HX * ((threadIdx.y + 1) + ((DIM == 3) ? HY : 0));
+  const int hs[3] = {1, HX, HX * HY};
+  const double idt = 1.0 / dt;
+  // c row
+  {
+    const double mc = cn[n] * (1.0 - cn[n]);
+    const double g0 = sdg[hq];
+    double s = 0.0;
+#pragma unroll
+    for (int dir = 0; dir < DIM; ++dir) {
+      const long long np = at_dir(K, p, dir, 1), nm = at_dir(K, p, dir, -1);
+      const double Mp = 0.5 * K.kappa * (mc + cn[np] * (1.0 - cn[np]));
+      const double Mm = 0.5 * K.kappa * (mc + cn[nm] * (1.0 - cn[nm]));
+      s += Mp * (sdg[hq + hs[dir]] - g0) - Mm * (g0 - sdg[hq - hs[dir]]);
+    }
+    w[n] = v[n] * idt - s * K.ih2;
+  }
+  double vv[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) vv[q] = v[q * N + n];
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    double s = -0.5 * K.gamma_eta * lap(K, v + (1 + e) * N, p, vv[1 + e]);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) s += B[(4 * (1 + e) + q) * N + n] * vv[q];
+    w[(1 + e) * N + n] = vv[1 + e] * idt + K.L_eta * s;
+  }
+#pragma unroll
+  for (int I = 0; I < DIM; ++I) {
+    w[(4 + I) * N + n] = K.elastic ? div_sigma(K, v + 4 * N, N, v, 0.0, p, I) : v[(4 + I) * N + n];
+  }
+}
+
 // ---------------------------------------------------------------------------------
 // energy (eqs. (relations)/(freeenergy)) and mass; partial: chem, elastic, interfacial, sum c
 // ---------------------------------------------------------------------------------
@@ -501,8 +569,9 @@ void launch_linearise(const Consts& K, const double* X, const double* Xn, double
 
 void launch_jv(const Consts& K, double dt, const double* B, const double* cn, const double* v,
                double* dG, double* w, hipStream_t s) {
-  hipLaunchKernelGGL(k_jv_g, stencil_grid(K), dim3(kBX, kBY), 0, s, K, dt, B, v, dG, w);
-  hipLaunchKernelGGL(k_jv_c, stencil_grid(K), dim3(kBX, kBY), 0, s, K, dt, cn, v, dG, w);
+  (void)dG;
+  if (K.dim == 2) hipLaunchKernelGGL(k_jv_fused<2>, stencil_grid(K), dim3(kBX, kBY), 0, s, K, dt, B, cn, v, w);
+  else hipLaunchKernelGGL(k_jv_fused<3>, stencil_grid(K), dim3(kBX, kBY), 0, s, K, dt, B, cn, v, w);
 }
 
 void launch_energy(const Consts& K, const double* X, double* partial, hipStream_t s) {

@@ -77,7 +77,10 @@ void launch_lincomb(long long n, int nv, const double* V, long long ldv, const d
                     double beta, double* out, hipStream_t s);
 void launch_axpby(long long n, double a, const double* x, double b, const double* y, double* out,
                   hipStream_t s);
-void launch_finalize(const double* partial, int nvals, double* out, hipStream_t s);
+void launch_finalize(const double* partial, int nvals, double* out, hipStream_t s, double* out2 = nullptr);
+// v_{j+1} from device-resident Gram-Schmidt coefficients hc = [h_0..h_{nv-1}, <w,w>]
+void launch_update_dev(long long n, int nv, const double* V, long long ldv, const double* hc,
+                       const double* w, double* out, double* partial, hipStream_t s);
 void launch_sum2(long long n, const double* x, const double* y, const double* yn, double* partial,
                  hipStream_t s);
 void launch_trial(const Consts& K, int nf, const double* X, const double* S, double lam,

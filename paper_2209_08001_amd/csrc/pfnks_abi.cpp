@@ -44,7 +44,7 @@ struct Layout {
 
 enum Buf {
   B_X, B_XN, B_XT, B_F, B_FT, B_S, B_B, B_BPC, B_G4, B_DG, B_V, B_W, B_Z, B_TMP, B_PART, B_RED,
-  B_FFT0, B_FFT1, B_TW0, B_TW1, B_TW2, B_SN0, B_SN1, B_SN2, B_COUNT
+  B_FFT0, B_FFT1, B_TW0, B_TW1, B_TW2, B_SN0, B_SN1, B_SN2, B_HDEV, B_COUNT
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -69,6 +69,7 @@ Layout make_layout(int dim, long long N, int restart, const int* n) {
   sz[B_SN0] = sizeof(double) * (size_t)n[0];
   sz[B_SN1] = sizeof(double) * (size_t)n[1];
   sz[B_SN2] = sizeof(double) * (size_t)(dim == 3 ? n[2] : 2);
+  sz[B_HDEV] = sizeof(double) * (size_t)(restart + 1) * (restart + 2);
   Layout L{};
   size_t o = 0;
   for (int b = 0; b < B_COUNT; ++b) {
@@ -134,7 +135,10 @@ struct pfnks_problem {
   char* ws;
   double *X, *Xn, *Xt, *F, *Ft, *S, *B, *Bpc, *G4, *dG, *V, *w, *z, *tmp, *part, *red;
   double2 *fft0, *fft1;
-  double* hbuf;  // pinned host scalars
+  double* hbuf;   // pinned host scalars (written directly by the finalize kernels)
+  double* hdev;   // device Gram-Schmidt columns [h_0..h_j, <w,w>], one slot of m+2 per j
+  double* hhost;  // pinned host mirror of hdev
+  std::vector<hipEvent_t> hev;  // one per Arnoldi column
   double t;
   long long launches, syncs;
   // live kernel timing (HIP events on the problem's stream), off unless enabled
@@ -225,7 +229,7 @@ struct Prof {
   double bytes;
   hipEvent_t a;
   Prof(pfnks_problem* p_, int kind_, double bytes_) : p(p_), kind(kind_), bytes(bytes_), a(nullptr) {
-    if (p->prof) {
+    if (p->prof & (1 << kind)) {
       a = prof_event(p);
       if (a) (void)hipEventRecord(a, p->stream);
     }
@@ -239,9 +243,13 @@ struct Prof {
   }
 };
 
-// after a stream synchronisation: turn finished event pairs into per-kind totals
+// turn finished event pairs into per-kind totals; pairs still in flight (recorded in stream
+// order after the last completed work) stay pending
 void prof_resolve(pfnks_problem* p) {
-  for (auto& r : p->pending) {
+  size_t done = 0;
+  for (; done < p->pending.size(); ++done) {
+    auto& r = p->pending[done];
+    if (hipEventQuery(r.b) != hipSuccess) break;
     float ms = 0.0f;
     if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
       p->kcount[r.kind] += 1;
@@ -251,14 +259,13 @@ void prof_resolve(pfnks_problem* p) {
     p->pool.push_back(r.a);
     p->pool.push_back(r.b);
   }
-  p->pending.clear();
+  p->pending.erase(p->pending.begin(), p->pending.begin() + done);
 }
 
 // finalize partial sums of nvals values and copy them to p->hbuf
 int reduce_to_host(pfnks_problem* p, int nvals) {
-  pf::launch_finalize(p->part, nvals, p->red, p->stream);
+  pf::launch_finalize(p->part, nvals, p->red, p->stream, p->hbuf);
   HIPCHK(hipGetLastError());
-  HIPCHK(hipMemcpyAsync(p->hbuf, p->red, sizeof(double) * nvals, hipMemcpyDeviceToHost, p->stream));
   HIPCHK(hipStreamSynchronize(p->stream));
   p->launches += 1;
   p->syncs += 1;
@@ -341,22 +348,44 @@ void jv(pfnks_problem* p, double dt, const double* Bm, const double* v, double* 
   p->launches += 2;
 }
 
-// Solve J S = -F (right-preconditioned restarted GMRES, classical Gram-Schmidt with a second
-// pass when cancellation is severe).  Returns status; *its = iterations; *ok = converged.
+// Solve J S = -F: right-preconditioned restarted GMRES with classical Gram-Schmidt.
+// The Gram-Schmidt coefficients stay on the device (the update kernel reads them and forms
+// h_{j+1,j} = sqrt(<w,w> - sum h_i^2)); the finalize kernel also writes them to pinned host
+// memory.  The host enqueues Arnoldi step j+1 before it reads column j (Givens rotations,
+// convergence test), so the device never waits for the host; at most one step per cycle is
+// computed and discarded.  When <w,w> - sum h^2 has lost more than two digits, the cycle ends
+// there and GMRES restarts from the true residual.
 int gmres(pfnks_problem* p, double dt, const double* Bm, double fnorm, double tol, int* its,
           int* ok) {
   const long long n = p->nvec;
   const int m = p->solver.gmres_restart;
   const int maxit = p->solver.gmres_maxit;
+  const int ld = m + 2;
   double* V = p->V;
   std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1), y(m);
   int total = 0;
   *ok = 0;
+  *its = 0;
   HIPCHK(hipMemsetAsync(p->S, 0, sizeof(double) * n, p->stream));
   // r = -F
   pf::launch_axpby(n, -1.0, p->F, 0.0, nullptr, p->tmp, p->stream);
   double beta = fnorm;
   p->launches += 1;
+  auto launch_step = [&](int j) {
+    pc_apply(p, dt, V + j * n, p->z);
+    jv(p, dt, Bm, p->z, p->w);
+    {
+      Prof pr(p, PFNKS_K_MULTIDOT, 8.0 * (j + 2) * n);
+      pf::launch_multidot(n, j + 1, V, n, p->w, p->part, p->stream);
+    }
+    pf::launch_finalize(p->part, j + 2, p->hdev + j * ld, p->stream, p->hhost + j * ld);
+    (void)hipEventRecord(p->hev[j], p->stream);
+    {
+      Prof pr(p, PFNKS_K_UPDATE, 8.0 * (j + 3) * n);
+      pf::launch_update_dev(n, j + 1, V, n, p->hdev + j * ld, p->w, V + (j + 1) * n, p->part, p->stream);
+    }
+    p->launches += 3;
+  };
   while (true) {
     if (beta <= tol) {
       *ok = 1;
@@ -366,61 +395,30 @@ int gmres(pfnks_problem* p, double dt, const double* Bm, double fnorm, double to
     p->launches += 1;
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
-    int j = 0;
+    int launched = 1, k = 0;
+    bool conv = false;
     double resid = beta;
-    for (; j < m && total < maxit; ++j) {
-      pc_apply(p, dt, V + j * n, p->z);
-      jv(p, dt, Bm, p->z, p->w);
-      {
-        Prof pr(p, PFNKS_K_MULTIDOT, 8.0 * (j + 2) * n);
-        pf::launch_multidot(n, j + 1, V, n, p->w, p->part, p->stream);
+    launch_step(0);
+    for (int j = 0;; ++j) {
+      if (launched == j + 1 && j + 1 < m && total + launched < maxit) {
+        launch_step(j + 1);
+        ++launched;
       }
-      p->launches += 1;
-      int st = reduce_to_host(p, j + 2);
-      if (st) return st;
+      HIPCHK(hipEventSynchronize(p->hev[j]));
+      p->syncs += 1;
+      if (!p->pending.empty()) prof_resolve(p);
+      const double* hj = p->hhost + j * ld;
       double* h = &H[(size_t)j * (m + 1)];  // column j
       double hh = 0.0;
       for (int i = 0; i <= j; ++i) {
-        h[i] = p->hbuf[i];
+        h[i] = hj[i];
         hh += h[i] * h[i];
       }
-      const double ww = p->hbuf[j + 1];
-      double nrm2 = ww - hh;
-      double hnext;
-      if (nrm2 > 1e-2 * ww) {
-        hnext = std::sqrt(nrm2);
-        Prof pr(p, PFNKS_K_UPDATE, 8.0 * (j + 3) * n);
-        pf::launch_update(n, j + 1, V, n, h, p->w, 1.0 / hnext, V + (j + 1) * n, p->part, p->stream);
-        p->launches += 1;
-      } else {
-        // cancellation: explicit second classical Gram-Schmidt pass
-        pf::launch_update(n, j + 1, V, n, h, p->w, 1.0, p->w, p->part, p->stream);
-        pf::launch_multidot(n, j + 1, V, n, p->w, p->part, p->stream);
-        p->launches += 2;
-        st = reduce_to_host(p, j + 2);
-        if (st) return st;
-        std::vector<double> h2(j + 1);
-        double hh2 = 0.0;
-        for (int i = 0; i <= j; ++i) {
-          h2[i] = p->hbuf[i];
-          h[i] += h2[i];
-          hh2 += h2[i] * h2[i];
-        }
-        const double ww2 = p->hbuf[j + 1];
-        pf::launch_update(n, j + 1, V, n, h2.data(), p->w, 1.0, p->w, p->part, p->stream);
-        p->launches += 1;
-        st = reduce_to_host(p, 1);
-        if (st) return st;
-        hnext = std::sqrt(p->hbuf[0]);
-        (void)ww2;
-        (void)hh2;
-        if (hnext > 0.0) {
-          pf::launch_axpby(n, 1.0 / hnext, p->w, 0.0, nullptr, V + (j + 1) * n, p->stream);
-          p->launches += 1;
-        }
-      }
+      const double ww = hj[j + 1];
+      const double nrm2 = ww - hh;
+      const bool cancel = !(nrm2 > 1e-2 * ww);
+      const double hnext = std::sqrt(std::fmax(nrm2, 0.0));
       h[j + 1] = hnext;
-      // apply previous rotations, then a new one
       for (int i = 0; i < j; ++i) {
         const double a = h[i], b = h[i + 1];
         h[i] = cs[i] * a + sn[i] * b;
@@ -436,25 +434,29 @@ int gmres(pfnks_problem* p, double dt, const double* Bm, double fnorm, double to
       g[j] = cs[j] * g[j];
       resid = std::fabs(g[j + 1]);
       ++total;
-      if (!std::isfinite(resid)) return PFNKS_ENOCONV;
-      if (resid <= tol || hnext == 0.0) {
-        ++j;
+      k = j + 1;
+      if (!std::isfinite(resid)) {
+        (void)hipStreamSynchronize(p->stream);
+        return PFNKS_ENOCONV;
+      }
+      if (resid <= tol) {
+        conv = true;
         break;
       }
+      if (cancel || hnext == 0.0 || j + 1 == m || total >= maxit) break;
     }
-    // y = H^{-1} g (upper triangular j x j)
-    const int k = j;
+    // y = H^{-1} g (upper triangular k x k)
     for (int i = k - 1; i >= 0; --i) {
-      double s = g[i];
-      for (int c = i + 1; c < k; ++c) s -= H[(size_t)c * (m + 1) + i] * y[c];
-      y[i] = s / H[(size_t)i * (m + 1) + i];
+      double s_ = g[i];
+      for (int c = i + 1; c < k; ++c) s_ -= H[(size_t)c * (m + 1) + i] * y[c];
+      y[i] = s_ / H[(size_t)i * (m + 1) + i];
     }
     // S += M^{-1} (V y)
     pf::launch_lincomb(n, k, V, n, y.data(), 0.0, p->tmp, p->stream);
     pc_apply(p, dt, p->tmp, p->z);
     pf::launch_axpby(n, 1.0, p->S, 1.0, p->z, p->S, p->stream);
     p->launches += 2;
-    if (resid <= tol) {
+    if (conv) {
       *ok = 1;
       break;
     }
@@ -543,6 +545,8 @@ int pfnks_create_problem(const pfnks_grid* grid, const pfnks_model* model, const
 
   pfnks_problem* p = new pfnks_problem();
   p->prof = 0;
+  p->hbuf = nullptr;
+  p->hhost = nullptr;
   for (int k = 0; k < PFNKS_KERNEL_KINDS; ++k) {
     p->kcount[k] = 0;
     p->kms[k] = 0.0;
@@ -587,11 +591,23 @@ int pfnks_create_problem(const pfnks_grid* grid, const pfnks_model* model, const
 
   auto fail = [&](int code) {
     if (p->hbuf) (void)hipHostFree(p->hbuf);
+    if (p->hhost) (void)hipHostFree(p->hhost);
+    for (auto ev : p->hev)
+      if (ev) (void)hipEventDestroy(ev);
     delete p;
     return code;
   };
   hipError_t e = hipHostMalloc((void**)&p->hbuf, sizeof(double) * pf::kMaxRed, hipHostMallocDefault);
   if (e != hipSuccess) return fail(device_error(e, "hipHostMalloc"));
+  const int mres = solver->gmres_restart;
+  e = hipHostMalloc((void**)&p->hhost, sizeof(double) * (mres + 1) * (mres + 2), hipHostMallocDefault);
+  if (e != hipSuccess) return fail(device_error(e, "hipHostMalloc"));
+  p->hdev = (double*)(p->ws + L.off[B_HDEV]);
+  p->hev.resize(mres + 1, nullptr);
+  for (auto& ev : p->hev) {
+    e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) return fail(device_error(e, "hipEventCreate"));
+  }
 
   // twiddle tables exp(-2 pi i k / n), k < n/2
   for (int d = 0; d < 3; ++d) {
@@ -775,7 +791,9 @@ int pfnks_destroy(pfnks_problem* p) {
   if (p->stream) (void)hipStreamSynchronize(p->stream);
   prof_resolve(p);
   for (hipEvent_t e : p->pool) (void)hipEventDestroy(e);
+  for (hipEvent_t e : p->hev) (void)hipEventDestroy(e);
   if (p->hbuf) (void)hipHostFree(p->hbuf);
+  if (p->hhost) (void)hipHostFree(p->hhost);
   delete p;
   return PFNKS_OK;
 }
@@ -784,7 +802,7 @@ int pfnks_debug_profile(pfnks_problem* p, int enable) {
   if (!p) return PFNKS_EINVAL;
   HIPCHK(hipStreamSynchronize(p->stream));
   prof_resolve(p);
-  p->prof = enable ? 1 : 0;
+  p->prof = enable & ((1 << PFNKS_KERNEL_KINDS) - 1);
   for (int k = 0; k < PFNKS_KERNEL_KINDS; ++k) {
     p->kcount[k] = 0;
     p->kms[k] = 0.0;

@@ -281,9 +281,18 @@ class Problem:
         _check(load().pfnks_debug_counters(self._h, ctypes.byref(a), ctypes.byref(b)), "pfnks_debug_counters")
         return a.value, b.value
 
-    def profile(self, enable):
-        """Switch live kernel timing (HIP events on the problem's stream) on or off; clears totals."""
-        _check(load().pfnks_debug_profile(self._h, 1 if enable else 0), "pfnks_debug_profile")
+    def profile(self, kinds):
+        """Live kernel timing (HIP events on the problem's stream) for the given kernel kinds
+        (names, True for all, False/None for none); clears the totals."""
+        if kinds is True:
+            mask = (1 << len(KERNEL_KINDS)) - 1
+        elif not kinds:
+            mask = 0
+        else:
+            mask = 0
+            for k in ([kinds] if isinstance(kinds, str) else kinds):
+                mask |= 1 << KERNEL_KINDS.index(k)
+        _check(load().pfnks_debug_profile(self._h, mask), "pfnks_debug_profile")
 
     def kernel_time(self, kind):
         """(launches, total ms, total algorithmic bytes) of one kernel kind since profile(True)."""
