@@ -112,6 +112,9 @@ def main():
     ap.add_argument("--sweeps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="before the run, copy a device buffer of this many MiB once (a plain copy "
+                         "kernel of known size, to scale the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -131,6 +134,12 @@ def main():
     if len(n) == 3:
         solver.update(tile=(8, 8, 8), overlap=1)
     dev = "cuda:0"
+    if args.copy_calibration_mb > 0:
+        src = torch.ones(args.copy_calibration_mb * (1 << 20) // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # warm-up on a scratch problem; it also times every kernel kind to find the dominant one
     dominant = "ras"

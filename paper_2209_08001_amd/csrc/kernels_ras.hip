@@ -24,7 +24,7 @@ namespace pf {
 
 namespace {
 
-constexpr int kRasThreads = 768;
+constexpr int kRasThreads = 512;
 
 struct Geo {
   int ex, ey, ez;      // extended tile
@@ -444,8 +444,9 @@ void launch_dim(const Consts& K, const Geo& G, size_t lds, int ntiles, int npt, 
     break;
   switch (npt) {
     PF_RAS_CASE(1)
+    PF_RAS_CASE(2)
     default:
-      PF_RAS_CASE(2)
+      PF_RAS_CASE(3)
   }
 #undef PF_RAS_CASE
 }
@@ -461,12 +462,12 @@ size_t ras_lds_bytes(const Consts& K, const TileCfg& T) {
          sizeof(int) * (ne + ncol * G.ey * G.ez);
 }
 
-// nodes of the extended tile per thread (1..2), 0 if the tile does not fit
+// nodes of the extended tile per thread (1..3), 0 if the tile does not fit
 int ras_npt(const Consts& K, const TileCfg& T) {
   const Geo G = make_geo(K, T);
   const int ne = G.ex * G.ey * G.ez;
   const int npt = (ne + kRasThreads - 1) / kRasThreads;
-  return npt <= 2 ? npt : 0;
+  return npt <= 3 ? npt : 0;
 }
 
 void launch_ras(const Consts& K, const TileCfg& T, double dt, const double* B, const double* cn,

@@ -99,7 +99,7 @@ int validate(const pfnks_grid* g, const pfnks_model* m, const pfnks_solver* s) {
   if (s->precision != PFNKS_FP64) return PFNKS_EINVAL;
   if (m->S < 1 || m->S > pf::kMaxS) return PFNKS_EINVAL;
   if (!(m->kappa >= 0.0) || !(m->L_eta > 0.0) || m->Lscale < 0.0) return PFNKS_EINVAL;
-  // extended tile must fit the kernel's registers (<= 2 nodes per thread of 768) and the
+  // extended tile must fit the kernel's registers (<= 3 nodes per thread of 512) and the
   // 160 KiB of LDS of one compute unit
   long long ext = 1, zpad = 1, dpad = 1;
   for (int k = 0; k < g->dim; ++k) {
@@ -107,7 +107,7 @@ int validate(const pfnks_grid* g, const pfnks_model* m, const pfnks_solver* s) {
     zpad *= s->tile[k] + 2 * s->overlap + 4;
     dpad *= s->tile[k] + 2 * s->overlap + 2;
   }
-  if (ext > 2 * 768) return PFNKS_EINVAL;
+  if (ext > 3 * 512) return PFNKS_EINVAL;
   const int nfz = (s->pc == PFNKS_PC_RAS) ? 4 + g->dim : 4;
   const long long rows = (g->dim == 3) ? (long long)(s->tile[1] + 2 * s->overlap) * (s->tile[2] + 2 * s->overlap)
                                        : (long long)(s->tile[1] + 2 * s->overlap);
