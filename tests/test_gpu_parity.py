@@ -232,3 +232,36 @@ def test_enoconv_leaves_state():
     X1, t1 = p.get_state()
     assert np.array_equal(X0, X1) and t0 == t1
     p.close()
+
+
+@pytest.fixture(scope="module")
+def oracle_3d():
+    n = (8, 8, 8)
+    c0, e0 = W.init_fields(n, 31)
+    o = Oracle(n, W.H, W.DEFAULT_MODEL, c0, e0)
+    traj = [o.X.copy()]
+    for dt in (0.01, 0.05):
+        o.step(dt)
+        traj.append(o.X.copy())
+    return n, c0, e0, traj
+
+
+@pytest.mark.parametrize("pc", ["ras_spectral", "ras"])
+def test_step_parity_3d(oracle_3d, pc):
+    """3D 8 x 8 x 8 (tiles 4^3, overlap 1), two steps: within 1e-8 of the oracle's root."""
+    from paper_2209_08001_amd import pfnks
+
+    _cuda()
+    n, c0, e0, traj = oracle_3d
+    _note(f"step parity 3d pc={pc}")
+    p = _problem(n, c0, e0, tile=(4, 4, 4), overlap=1,
+                 pc=pfnks.PC_RAS if pc == "ras" else pfnks.PC_RAS_SPECTRAL)
+    m0 = p.mass()
+    for k, dt in enumerate((0.01, 0.05)):
+        st = p.step(dt)
+        X, _ = p.get_state()
+        for f in range(X.shape[0]):
+            err = _relmax(X[f], traj[k + 1][f])
+            assert err <= 1e-8, (k, f, err)
+        assert abs(st["mass"] - m0) <= 1e-13 * abs(m0)
+    p.close()
