@@ -52,6 +52,37 @@ def adaptive_run(p, nsteps, wl, pf, record=None):
     return lat, stats
 
 
+# source file of each kernel kind; a stored traffic figure is used only while that file is
+# byte-identical to the one it was measured with
+KERNEL_SOURCE = {"residual": "kernels_phase.hip", "linearise": "kernels_phase.hip", "jv": "kernels_phase.hip",
+                 "ras": "kernels_ras.hip", "spectral": "kernels_fft.hip", "multidot": "kernels_blas.hip",
+                 "update": "kernels_blas.hip"}
+
+
+def kernel_source_sha256(kind):
+    import hashlib
+
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2209_08001_amd", "csrc")
+    with open(os.path.join(csrc, KERNEL_SOURCE[kind]), "rb") as fh:
+        h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kind, workload, precision):
+    """HBM bytes per launch of one kernel from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE, each scaled by the reading of a plain copy of known size), or
+    None when there is none for this kernel and workload or the kernel source has changed."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None, None
+    with open(path) as fh:
+        rec = json.load(fh).get(f"{kind}/{workload}/{precision}")
+    if not rec or rec.get("source_sha256") != kernel_source_sha256(kind):
+        return None, None
+    return rec["traffic_bytes_per_launch"], rec["summary"]
+
+
 def percentile(xs, q):
     s = sorted(xs)
     if not s:
@@ -74,13 +105,16 @@ def cpu_baseline(wl_name, budget_s=30.0):
     times = []
     used = []
     t_all = time.perf_counter()
+    wall = cpu = 0.0
     for s in sizes:
         n = (s, s)
         c0, e0 = W.init_fields(n, wl["seed"], cbar=wl["cbar"])
         o = Oracle(n, W.H, W.DEFAULT_MODEL, c0, e0)
-        t0 = time.perf_counter()
+        t0, c0_cpu = time.perf_counter(), time.process_time()
         o.step(wl.get("dt_min", wl.get("dt")))
         times.append(time.perf_counter() - t0)
+        wall += times[-1]
+        cpu += time.process_time() - c0_cpu
         used.append(s * s)
         if time.perf_counter() - t_all > budget_s:
             break
@@ -90,11 +124,13 @@ def cpu_baseline(wl_name, budget_s=30.0):
     b, a = np.polyfit(lx, ly, 1) if len(used) > 1 else (1.0, ly[0] - lx[0])
     Nw = float(np.prod(wl["n"]))
     t_w = math.exp(a) * Nw ** b
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or 1
+    # threads actually used: process CPU time over wall time of the timed solves
+    threads = max(1, round(cpu / wall)) if wall > 0 else 1
     return {
         "value": 1.0 / t_w,
         "unit": "steps/s",
         "cores": threads,
+        "cpu_time_over_wall": cpu / wall if wall > 0 else None,
         "kind": "oracle",
         "sample": (f"first step (dt = dt_min) of the seeded trajectory on {', '.join(f'{s}x{s}' for s in sizes[:len(used)])} "
                    f"(measured {', '.join(f'{t:.2f}' for t in times)} s), extrapolated to {wl['n'][0]}x{wl['n'][1]} "
@@ -110,6 +146,9 @@ def main():
     ap.add_argument("--workload", default="pf2d_512")
     ap.add_argument("--pc", default="ras_spectral", choices=["ras_spectral", "ras"])
     ap.add_argument("--sweeps", type=int, default=2)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
+                    help="mixed: float Krylov basis and Schwarz/Fourier preconditioner, double "
+                         "residual, J v arithmetic, Newton update, energy and mass")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
@@ -130,7 +169,8 @@ def main():
     n = wl["n"]
     c0, e0 = W.init_fields(n, wl["seed"], cbar=wl["cbar"])
     solver = dict(W.DEFAULT_SOLVER, sweeps=args.sweeps,
-                  pc=pfnks.PC_RAS if args.pc == "ras" else pfnks.PC_RAS_SPECTRAL)
+                  pc=pfnks.PC_RAS if args.pc == "ras" else pfnks.PC_RAS_SPECTRAL,
+                  precision=pfnks.MIXED if args.precision == "mixed" else pfnks.FP64)
     if len(n) == 3:
         solver.update(tile=(8, 8, 8), overlap=1)
     dev = "cuda:0"
@@ -180,7 +220,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f64+f32",
         "data": "synthetic",
         "config": {
             "workload": args.workload,
@@ -188,6 +228,7 @@ def main():
             "unknowns_per_node": 4 + len(n),
             "dt_range": [wl["dt_min"], wl["dt_max"]],
             "preconditioner": args.pc,
+            "precision": args.precision,
             "tile": list(solver["tile"][:len(n)]),
             "overlap": solver["overlap"],
             "gs_sweeps": args.sweeps,
@@ -206,7 +247,13 @@ def main():
         "energy_increase_max": energy_up,
     }
     if not args.no_roofline:
-        out["roofline"] = p.roofline(HBM_PEAK_GBS)
+        roof = p.roofline(HBM_PEAK_GBS)
+        traffic, summary = measured_traffic(roof["kernel"], args.workload, args.precision)
+        roof["traffic"] = traffic
+        if traffic is not None:
+            roof["traffic_over_algorithmic"] = traffic / roof["bytes_per_launch"]
+            roof["traffic_source"] = summary
+        out["roofline"] = roof
     p.close()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload)

@@ -49,8 +49,16 @@ typedef enum { PFNKS_FP64 = 0, PFNKS_MIXED = 1 } pfnks_precision;
 /* Preconditioner.  PFNKS_PC_RAS: one-level restricted additive Schwarz over all fields
  * (Section 4, left-RAS z = sum_t R_t^0' A_t^{-1} R_t^delta r), tile solve in LDS.
  * PFNKS_PC_RAS_SPECTRAL: the same RAS over (c, eta) composed block-lower-triangularly with an
- * exact Fourier solve of the constant-coefficient periodic displacement block. */
-typedef enum { PFNKS_PC_RAS = 0, PFNKS_PC_RAS_SPECTRAL = 1 } pfnks_pc;
+ * exact Fourier solve of the constant-coefficient periodic displacement block.
+ * PFNKS_PC_NONE: identity (unpreconditioned GMRES; for testing and comparison).
+ * PFNKS_PC_SPECTRAL: identity on (c, eta) composed with the same exact displacement solve
+ * (isolates the Fourier block for testing). */
+typedef enum {
+  PFNKS_PC_RAS = 0,
+  PFNKS_PC_RAS_SPECTRAL = 1,
+  PFNKS_PC_NONE = 2,
+  PFNKS_PC_SPECTRAL = 3
+} pfnks_pc;
 
 typedef struct {
   int dim;      /* 2 or 3                                                     */

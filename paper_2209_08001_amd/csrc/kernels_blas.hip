@@ -11,6 +11,18 @@ namespace {
 
 constexpr int kThreads = 256;
 
+// two-element vector of the basis type (16-byte loads for double, 8-byte for float)
+template <typename T>
+struct Vec2;
+template <>
+struct Vec2<double> {
+  using type = double2;
+};
+template <>
+struct Vec2<float> {
+  using type = float2;
+};
+
 // Sum of one value over the workgroup (wave64 shuffles, then the four waves via LDS).
 __device__ inline double block_sum(double v, double* lds) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
@@ -25,8 +37,8 @@ __device__ inline double block_sum(double v, double* lds) {
   return r;  // valid in thread 0
 }
 
-template <int MAXV>
-__global__ __launch_bounds__(kThreads) void k_multidot(long long n, int nv, const double* __restrict__ V,
+template <int MAXV, typename T>
+__global__ __launch_bounds__(kThreads) void k_multidot(long long n, int nv, const T* __restrict__ V,
                                                        long long ldv, const double* __restrict__ w,
                                                        double* __restrict__ partial) {
   __shared__ double lds[kThreads / 64];
@@ -35,7 +47,8 @@ __global__ __launch_bounds__(kThreads) void k_multidot(long long n, int nv, cons
   for (int v = 0; v <= MAXV; ++v) acc[v] = 0.0;
   // n and ldv are even and every vector is 16-byte aligned: two elements per load
   const long long n2 = n >> 1, ld2 = ldv >> 1;
-  const double2* __restrict__ V2 = reinterpret_cast<const double2*>(V);
+  using T2 = typename Vec2<T>::type;
+  const T2* __restrict__ V2 = reinterpret_cast<const T2*>(V);
   const double2* __restrict__ w2 = reinterpret_cast<const double2*>(w);
   for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < n2;
        e += (long long)gridDim.x * kThreads) {
@@ -43,8 +56,8 @@ __global__ __launch_bounds__(kThreads) void k_multidot(long long n, int nv, cons
 #pragma unroll
     for (int v = 0; v < MAXV; ++v)
       if (MAXV <= 32 || v < nv) {
-        const double2 y = V2[v * ld2 + e];
-        acc[v] += we.x * y.x + we.y * y.y;
+        const T2 y = V2[v * ld2 + e];
+        acc[v] += we.x * (double)y.x + we.y * (double)y.y;
       }
     acc[MAXV] += we.x * we.x + we.y * we.y;
   }
@@ -105,10 +118,10 @@ __global__ __launch_bounds__(kThreads) void k_update(long long n, int nv, const 
 // v_{j+1} = (w - sum_v h_v V_v) / h_{j+1,j} with the coefficients read from device memory
 // (hc = [h_0 .. h_{nv-1}, <w, w>], written by the finalize of the multi-dot) and
 // h_{j+1,j} = sqrt(<w,w> - sum h_v^2); partial: ||w - sum h V||^2 for a later check.
-template <int MAXV>
-__global__ __launch_bounds__(kThreads) void k_update_dev(long long n, int nv, const double* __restrict__ V,
+template <int MAXV, typename T>
+__global__ __launch_bounds__(kThreads) void k_update_dev(long long n, int nv, const T* __restrict__ V,
                                                          long long ldv, const double* __restrict__ hc,
-                                                         const double* __restrict__ w, double* __restrict__ out,
+                                                         const double* __restrict__ w, T* __restrict__ out,
                                                          double* __restrict__ partial) {
   __shared__ double lds[kThreads / 64];
   double c[MAXV];
@@ -121,48 +134,53 @@ __global__ __launch_bounds__(kThreads) void k_update_dev(long long n, int nv, co
   const double scale = 1.0 / sqrt(hc[nv] - hh);
   double acc = 0.0;
   const long long n2 = n >> 1, ld2 = ldv >> 1;
-  const double2* __restrict__ V2 = reinterpret_cast<const double2*>(V);
+  using T2 = typename Vec2<T>::type;
+  const T2* __restrict__ V2 = reinterpret_cast<const T2*>(V);
   const double2* __restrict__ w2 = reinterpret_cast<const double2*>(w);
-  double2* __restrict__ o2 = reinterpret_cast<double2*>(out);
+  T2* __restrict__ o2 = reinterpret_cast<T2*>(out);
   for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < n2;
        e += (long long)gridDim.x * kThreads) {
     double2 x = w2[e];
 #pragma unroll
     for (int v = 0; v < MAXV; ++v)
       if (MAXV <= 32 || v < nv) {
-        const double2 y = V2[v * ld2 + e];
-        x.x -= c[v] * y.x;
-        x.y -= c[v] * y.y;
+        const T2 y = V2[v * ld2 + e];
+        x.x -= c[v] * (double)y.x;
+        x.y -= c[v] * (double)y.y;
       }
     acc += x.x * x.x + x.y * x.y;
-    o2[e] = make_double2(scale * x.x, scale * x.y);
+    T2 o;
+    o.x = (T)(scale * x.x);
+    o.y = (T)(scale * x.y);
+    o2[e] = o;
   }
   double s = block_sum(acc, lds);
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
-template <int MAXV>
-__global__ __launch_bounds__(kThreads) void k_lincomb(long long n, int nv, const double* __restrict__ V,
+template <int MAXV, typename T, typename To>
+__global__ __launch_bounds__(kThreads) void k_lincomb(long long n, int nv, const T* __restrict__ V,
                                                       long long ldv, Coefs cf, double beta,
-                                                      double* __restrict__ out) {
+                                                      To* __restrict__ out) {
   for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < n;
        e += (long long)gridDim.x * kThreads) {
-    double x = (beta == 0.0) ? 0.0 : beta * out[e];
+    double x = (beta == 0.0) ? 0.0 : beta * (double)out[e];
 #pragma unroll
     for (int v = 0; v < MAXV; ++v)
-      if (MAXV <= 32 || v < nv) x += cf.c[v] * V[v * ldv + e];
-    out[e] = x;
+      if (MAXV <= 32 || v < nv) x += cf.c[v] * (double)V[v * ldv + e];
+    out[e] = (To)x;
   }
 }
 
-__global__ __launch_bounds__(kThreads) void k_axpby(long long n, double a, const double* __restrict__ x,
-                                                    double b, const double* __restrict__ y,
-                                                    double* __restrict__ out) {
+template <typename Tx, typename Ty, typename To>
+__global__ __launch_bounds__(kThreads) void k_axpby(long long n, double a, const Tx* __restrict__ x,
+                                                    double b, const Ty* __restrict__ y,
+                                                    To* __restrict__ out) {
   for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < n;
        e += (long long)gridDim.x * kThreads) {
-    double v = a * x[e];
-    if (b != 0.0) v += b * y[e];
-    out[e] = v;
+    double v = a * (double)x[e];
+    if (b != 0.0) v += b * (double)y[e];
+    out[e] = (To)v;
   }
 }
 
@@ -312,78 +330,92 @@ int grid_for(long long n) {
 
 // Exact-count instantiations (every guarded load is then unconditional and all of them can be
 // in flight at once); counts above 32 use the 64-wide guarded form.
-#define PF_CASE(N, KERNEL, ...) \
-  case N:                       \
-    hipLaunchKernelGGL(KERNEL<N>, __VA_ARGS__); \
-    break;
-#define DISPATCH_MAXV(nv, KERNEL, ...)                                                        \
-  do {                                                                                        \
-    switch (nv) {                                                                             \
-      PF_CASE(1, KERNEL, __VA_ARGS__) PF_CASE(2, KERNEL, __VA_ARGS__)                         \
-      PF_CASE(3, KERNEL, __VA_ARGS__) PF_CASE(4, KERNEL, __VA_ARGS__)                         \
-      PF_CASE(5, KERNEL, __VA_ARGS__) PF_CASE(6, KERNEL, __VA_ARGS__)                         \
-      PF_CASE(7, KERNEL, __VA_ARGS__) PF_CASE(8, KERNEL, __VA_ARGS__)                         \
-      PF_CASE(9, KERNEL, __VA_ARGS__) PF_CASE(10, KERNEL, __VA_ARGS__)                        \
-      PF_CASE(11, KERNEL, __VA_ARGS__) PF_CASE(12, KERNEL, __VA_ARGS__)                       \
-      PF_CASE(13, KERNEL, __VA_ARGS__) PF_CASE(14, KERNEL, __VA_ARGS__)                       \
-      PF_CASE(15, KERNEL, __VA_ARGS__) PF_CASE(16, KERNEL, __VA_ARGS__)                       \
-      PF_CASE(17, KERNEL, __VA_ARGS__) PF_CASE(18, KERNEL, __VA_ARGS__)                       \
-      PF_CASE(19, KERNEL, __VA_ARGS__) PF_CASE(20, KERNEL, __VA_ARGS__)                       \
-      PF_CASE(21, KERNEL, __VA_ARGS__) PF_CASE(22, KERNEL, __VA_ARGS__)                       \
-      PF_CASE(23, KERNEL, __VA_ARGS__) PF_CASE(24, KERNEL, __VA_ARGS__)                       \
-      PF_CASE(25, KERNEL, __VA_ARGS__) PF_CASE(26, KERNEL, __VA_ARGS__)                       \
-      PF_CASE(27, KERNEL, __VA_ARGS__) PF_CASE(28, KERNEL, __VA_ARGS__)                       \
-      PF_CASE(29, KERNEL, __VA_ARGS__) PF_CASE(30, KERNEL, __VA_ARGS__)                       \
-      PF_CASE(31, KERNEL, __VA_ARGS__) PF_CASE(32, KERNEL, __VA_ARGS__)                       \
-      default:                                                                                \
-        hipLaunchKernelGGL(KERNEL<64>, __VA_ARGS__);                                          \
-    }                                                                                         \
-  } while (0)
+#define PF_NV_CASES(F)                                                                        \
+  case 1: F(1); break; case 2: F(2); break; case 3: F(3); break; case 4: F(4); break;         \
+  case 5: F(5); break; case 6: F(6); break; case 7: F(7); break; case 8: F(8); break;         \
+  case 9: F(9); break; case 10: F(10); break; case 11: F(11); break; case 12: F(12); break;   \
+  case 13: F(13); break; case 14: F(14); break; case 15: F(15); break; case 16: F(16); break; \
+  case 17: F(17); break; case 18: F(18); break; case 19: F(19); break; case 20: F(20); break; \
+  case 21: F(21); break; case 22: F(22); break; case 23: F(23); break; case 24: F(24); break; \
+  case 25: F(25); break; case 26: F(26); break; case 27: F(27); break; case 28: F(28); break; \
+  case 29: F(29); break; case 30: F(30); break; case 31: F(31); break; case 32: F(32); break; \
+  default: F(64);
 
 // partial receives nv + 1 values: <w, V_v> for v < nv and <w, w>.  Always kRedBlocks blocks.
-void launch_multidot(long long n, int nv, const double* V, long long ldv, const double* w,
-                     double* partial, hipStream_t s) {
+template <typename T>
+void launch_multidot(long long n, int nv, const T* V, long long ldv, const double* w, double* partial,
+                     hipStream_t s) {
   if (nv == 0) {
-    hipLaunchKernelGGL(k_multidot<0>, dim3(kRedBlocks), dim3(kThreads), 0, s, n, nv, V, ldv, w, partial);
+    hipLaunchKernelGGL((k_multidot<0, T>), dim3(kRedBlocks), dim3(kThreads), 0, s, n, nv, V, ldv, w, partial);
     return;
   }
-  DISPATCH_MAXV(nv, k_multidot, dim3(kRedBlocks), dim3(kThreads), 0, s, n, nv, V, ldv, w, partial);
+#define F(N) hipLaunchKernelGGL((k_multidot<N, T>), dim3(kRedBlocks), dim3(kThreads), 0, s, n, nv, V, ldv, w, partial)
+  switch (nv) { PF_NV_CASES(F) }
+#undef F
 }
+template void launch_multidot<double>(long long, int, const double*, long long, const double*, double*, hipStream_t);
+template void launch_multidot<float>(long long, int, const float*, long long, const double*, double*, hipStream_t);
 
-// out = scale * (w - sum_v coef[v] V_v); partial: ||w - sum coef V||^2.
+// out = scale * (w - sum_v coef[v] V_v); partial: ||w - sum coef V||^2
 void launch_update(long long n, int nv, const double* V, long long ldv, const double* coef,
                    const double* w, double scale, double* out, double* partial, hipStream_t s) {
   Coefs cf{};
   for (int v = 0; v < nv; ++v) cf.c[v] = coef[v];
-  DISPATCH_MAXV(nv, k_update, dim3(kRedBlocks), dim3(kThreads), 0, s, n, nv, V, ldv, cf, w, scale,
-                out, partial);
+#define F(N) hipLaunchKernelGGL(k_update<N>, dim3(kRedBlocks), dim3(kThreads), 0, s, n, nv, V, ldv, cf, w, scale, out, partial)
+  switch (nv) { PF_NV_CASES(F) }
+#undef F
 }
 
-void launch_update_dev(long long n, int nv, const double* V, long long ldv, const double* hc,
-                       const double* w, double* out, double* partial, hipStream_t s) {
-  DISPATCH_MAXV(nv, k_update_dev, dim3(kRedBlocks), dim3(kThreads), 0, s, n, nv, V, ldv, hc, w, out, partial);
+template <typename T>
+void launch_update_dev(long long n, int nv, const T* V, long long ldv, const double* hc, const double* w,
+                       T* out, double* partial, hipStream_t s) {
+#define F(N) hipLaunchKernelGGL((k_update_dev<N, T>), dim3(kRedBlocks), dim3(kThreads), 0, s, n, nv, V, ldv, hc, w, out, partial)
+  switch (nv) { PF_NV_CASES(F) }
+#undef F
 }
+template void launch_update_dev<double>(long long, int, const double*, long long, const double*, const double*,
+                                        double*, double*, hipStream_t);
+template void launch_update_dev<float>(long long, int, const float*, long long, const double*, const double*,
+                                       float*, double*, hipStream_t);
 
 // out = beta * out + sum_v coef[v] V_v
-void launch_lincomb(long long n, int nv, const double* V, long long ldv, const double* coef,
-                    double beta, double* out, hipStream_t s) {
+template <typename T, typename To>
+void launch_lincomb(long long n, int nv, const T* V, long long ldv, const double* coef, double beta, To* out,
+                    hipStream_t s) {
   Coefs cf{};
   for (int v = 0; v < nv; ++v) cf.c[v] = coef[v];
-  DISPATCH_MAXV(nv, k_lincomb, dim3(grid_for(n)), dim3(kThreads), 0, s, n, nv, V, ldv, cf, beta,
-                out);
+#define F(N) hipLaunchKernelGGL((k_lincomb<N, T, To>), dim3(grid_for(n)), dim3(kThreads), 0, s, n, nv, V, ldv, cf, beta, out)
+  switch (nv) { PF_NV_CASES(F) }
+#undef F
 }
+template void launch_lincomb<double, double>(long long, int, const double*, long long, const double*, double,
+                                             double*, hipStream_t);
+template void launch_lincomb<float, float>(long long, int, const float*, long long, const double*, double, float*,
+                                           hipStream_t);
 
-void launch_axpby(long long n, double a, const double* x, double b, const double* y, double* out,
-                  hipStream_t s) {
-  hipLaunchKernelGGL(k_axpby, dim3(grid_for(n)), dim3(kThreads), 0, s, n, a, x, b, y, out);
+template <typename Tx, typename Ty, typename To>
+void launch_axpby(long long n, double a, const Tx* x, double b, const Ty* y, To* out, hipStream_t s) {
+  hipLaunchKernelGGL((k_axpby<Tx, Ty, To>), dim3(grid_for(n)), dim3(kThreads), 0, s, n, a, x, b, y, out);
 }
+template void launch_axpby<double, double, double>(long long, double, const double*, double, const double*,
+                                                   double*, hipStream_t);
+template void launch_axpby<double, double, float>(long long, double, const double*, double, const double*, float*,
+                                                  hipStream_t);
+template void launch_axpby<double, float, double>(long long, double, const double*, double, const float*, double*,
+                                                  hipStream_t);
+template void launch_axpby<float, float, float>(long long, double, const float*, double, const float*, float*,
+                                                hipStream_t);
+template void launch_axpby<float, float, double>(long long, double, const float*, double, const float*, double*,
+                                                 hipStream_t);
 
 void launch_finalize(const double* partial, int nvals, double* out, hipStream_t s, double* out2) {
+#define F(N) hipLaunchKernelGGL(k_finalize<N>, dim3(1), dim3(kRedBlocks), 0, s, partial, nvals, out, out2)
   if (nvals > 32) {
-    hipLaunchKernelGGL(k_finalize<80>, dim3(1), dim3(kRedBlocks), 0, s, partial, nvals, out, out2);
+    F(80);
     return;
   }
-  DISPATCH_MAXV(nvals, k_finalize, dim3(1), dim3(kRedBlocks), 0, s, partial, nvals, out, out2);
+  switch (nvals) { PF_NV_CASES(F) }
+#undef F
 }
 
 void launch_sum2(long long n, const double* x, const double* y, const double* yn, double* partial,

@@ -142,8 +142,9 @@ __device__ inline void fft_lds(double2* buf, int n, int logn, int nl, const doub
 __device__ inline int brev(int p, int logn) { return (int)(__brev((unsigned)p) >> (32 - logn)); }
 
 // pass 1: rows j0 .. j0+nl-1: q = r_u + a Dhat z_c packed as q_x + i q_y, forward FFT along x
-__global__ __launch_bounds__(256) void k_fft2_rows_fwd(Consts K, const double* __restrict__ r, double a,
-                                                       const double* __restrict__ zc, int logn, int nl,
+template <typename T>
+__global__ __launch_bounds__(256) void k_fft2_rows_fwd(Consts K, const T* __restrict__ r, double a,
+                                                       const T* __restrict__ zc, int logn, int nl,
                                                        const double2* __restrict__ tw,
                                                        double2* __restrict__ out) {
   extern __shared__ double2 sm[];  // nl * n
@@ -152,12 +153,12 @@ __global__ __launch_bounds__(256) void k_fft2_rows_fwd(Consts K, const double* _
   for (int e = threadIdx.x; e < nl * n; e += blockDim.x) {
     const int l = e / n, i = e - l * n, j = j0 + l;
     const long long m = (long long)i + (long long)n * j;
-    double qx = r ? r[m] : 0.0, qy = r ? r[K.N + m] : 0.0;
+    double qx = r ? (double)r[m] : 0.0, qy = r ? (double)r[K.N + m] : 0.0;
     if (zc && a != 0.0) {
       const int ip = (i + 1 == n) ? 0 : i + 1, im = (i == 0) ? n - 1 : i - 1;
       const int jp = (j + 1 == K.ny) ? 0 : j + 1, jm = (j == 0) ? K.ny - 1 : j - 1;
-      qx += a * (zc[ip + (long long)n * j] - zc[im + (long long)n * j]) * K.i2h;
-      qy += a * (zc[i + (long long)n * jp] - zc[i + (long long)n * jm]) * K.i2h;
+      qx += a * ((double)zc[ip + (long long)n * j] - (double)zc[im + (long long)n * j]) * K.i2h;
+      qy += a * ((double)zc[i + (long long)n * jp] - (double)zc[i + (long long)n * jm]) * K.i2h;
     }
     sm[l * n + brev(i, logn)] = make_double2(qx, qy);
   }
@@ -222,8 +223,9 @@ __global__ __launch_bounds__(256) void k_fft2_cols_solve(Consts K, int logn, con
 }
 
 // pass 3: inverse FFT along x, unpack u_x = Re / N, u_y = Im / N
+template <typename T>
 __global__ __launch_bounds__(256) void k_fft2_rows_inv(Consts K, int logn, int nl, const double2* __restrict__ tw,
-                                                       const double2* __restrict__ in, double* __restrict__ u) {
+                                                       const double2* __restrict__ in, T* __restrict__ u) {
   extern __shared__ double2 sm[];  // nl * n
   const int n = K.nx;
   const int j0 = blockIdx.x * nl;
@@ -237,8 +239,8 @@ __global__ __launch_bounds__(256) void k_fft2_rows_inv(Consts K, int logn, int n
   for (int e = threadIdx.x; e < nl * n; e += blockDim.x) {
     const int l = e / n, i = e - l * n;
     const long long m = (long long)i + (long long)n * (j0 + l);
-    u[m] = sm[e].x * inv;
-    u[K.N + m] = sm[e].y * inv;
+    u[m] = (T)(sm[e].x * inv);
+    u[K.N + m] = (T)(sm[e].y * inv);
   }
 }
 
@@ -249,9 +251,9 @@ __device__ inline int wrapi(int a, int n) {
 }
 
 // q_I = r_I + a Dhat_I zc; z0 = q_1 + i q_2, z1 = q_3 (3D)
-template <int DIM>
-__global__ __launch_bounds__(256) void k_pack(Consts K, const double* __restrict__ r, double a,
-                                              const double* __restrict__ zc, double2* __restrict__ z0,
+template <int DIM, typename T>
+__global__ __launch_bounds__(256) void k_pack(Consts K, const T* __restrict__ r, double a,
+                                              const T* __restrict__ zc, double2* __restrict__ z0,
                                               double2* __restrict__ z1) {
   const int i = blockIdx.x * 256 + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
   if (i >= K.nx) return;
@@ -260,7 +262,7 @@ __global__ __launch_bounds__(256) void k_pack(Consts K, const double* __restrict
     double q[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int I = 0; I < DIM; ++I) {
-      double v = r ? r[I * K.N + n] : 0.0;
+      double v = r ? (double)r[I * K.N + n] : 0.0;
       if (zc && a != 0.0) {
         long long np, nm;
         if (I == 0) {
@@ -273,7 +275,7 @@ __global__ __launch_bounds__(256) void k_pack(Consts K, const double* __restrict
           np = i + (long long)K.nx * (j + (long long)K.ny * wrapi(k + 1, K.nz));
           nm = i + (long long)K.nx * (j + (long long)K.ny * wrapi(k - 1, K.nz));
         }
-        v += a * (zc[np] - zc[nm]) * K.i2h;
+        v += a * ((double)zc[np] - (double)zc[nm]) * K.i2h;
       }
       q[I] = v;
     }
@@ -369,15 +371,16 @@ __global__ __launch_bounds__(256) void k_symbol_solve(Consts K, const double2* _
   }
 }
 
+template <typename T>
 __global__ __launch_bounds__(256) void k_unpack(Consts K, const double2* __restrict__ w0,
                                                 const double2* __restrict__ w1,
-                                                double* __restrict__ u) {
+                                                T* __restrict__ u) {
   const double inv = 1.0 / (double)K.N;
   for (long long n = (long long)blockIdx.x * 256 + threadIdx.x; n < K.N; n += (long long)gridDim.x * 256) {
     const double2 a = w0[n];
-    u[n] = a.x * inv;
-    u[K.N + n] = a.y * inv;
-    if (K.dim == 3) u[2 * K.N + n] = w1[n].x * inv;
+    u[n] = (T)(a.x * inv);
+    u[K.N + n] = (T)(a.y * inv);
+    if (K.dim == 3) u[2 * K.N + n] = (T)(w1[n].x * inv);
   }
 }
 
@@ -435,9 +438,10 @@ int grid_n(long long n) {
 }  // namespace
 
 // u = K^{-1} (r + a Dhat zc) on the displacement block.  work0, work1: 2 N complex each in 3D
-// (N each in 2D).
-void launch_spectral_solve(const Consts& K, const FftPlan& P, const double* r, double a,
-                           const double* zc, double2* work0, double2* work1, double* u,
+// (N each in 2D).  T: element type of r, zc and u (the transforms run in double).
+template <typename T>
+void launch_spectral_solve(const Consts& K, const FftPlan& P, const T* r, double a,
+                           const T* zc, double2* work0, double2* work1, T* u,
                            hipStream_t s) {
   if (K.dim == 2 && K.ny <= 1024 && K.nx <= 1024) {
     const int lx = ilog2(K.nx), ly = ilog2(K.ny);
@@ -445,10 +449,10 @@ void launch_spectral_solve(const Consts& K, const FftPlan& P, const double* r, d
     if (nl < 1) nl = 1;
     while (K.ny % nl) nl >>= 1;
     const size_t lrow = sizeof(double2) * nl * K.nx, lcol = sizeof(double2) * 4 * K.ny;
-    hipLaunchKernelGGL(k_fft2_rows_fwd, dim3(K.ny / nl), dim3(256), lrow, s, K, r, a, zc, lx, nl, P.tw[0], work0);
+    hipLaunchKernelGGL(k_fft2_rows_fwd<T>, dim3(K.ny / nl), dim3(256), lrow, s, K, r, a, zc, lx, nl, P.tw[0], work0);
     hipLaunchKernelGGL(k_fft2_cols_solve, dim3(K.nx / 2 + 1), dim3(256), lcol, s, K, ly, P.tw[1], P.sn[0],
                        P.sn[1], work0);
-    hipLaunchKernelGGL(k_fft2_rows_inv, dim3(K.ny / nl), dim3(256), lrow, s, K, lx, nl, P.tw[0], work0, u);
+    hipLaunchKernelGGL(k_fft2_rows_inv<T>, dim3(K.ny / nl), dim3(256), lrow, s, K, lx, nl, P.tw[0], work0, u);
     return;
   }
   double2* z0 = work0;
@@ -456,8 +460,8 @@ void launch_spectral_solve(const Consts& K, const FftPlan& P, const double* r, d
   double2* w0 = work1;
   double2* w1 = work1 + K.N;
   const dim3 g3((K.nx + 255) / 256, K.ny, K.nz);
-  if (K.dim == 2) hipLaunchKernelGGL(k_pack<2>, g3, dim3(256), 0, s, K, r, a, zc, z0, z1);
-  else hipLaunchKernelGGL(k_pack<3>, g3, dim3(256), 0, s, K, r, a, zc, z0, z1);
+  if (K.dim == 2) hipLaunchKernelGGL((k_pack<2, T>), g3, dim3(256), 0, s, K, r, a, zc, z0, z1);
+  else hipLaunchKernelGGL((k_pack<3, T>), g3, dim3(256), 0, s, K, r, a, zc, z0, z1);
   fft_all(K, P, z0, 0, s);
   if (K.dim == 3) fft_all(K, P, z1, 0, s);
   if (K.dim == 2)
@@ -466,7 +470,12 @@ void launch_spectral_solve(const Consts& K, const FftPlan& P, const double* r, d
     hipLaunchKernelGGL(k_symbol_solve<3>, g3, dim3(256), 0, s, K, z0, z1, w0, w1, P.sn[0], P.sn[1], P.sn[2]);
   fft_all(K, P, w0, 1, s);
   if (K.dim == 3) fft_all(K, P, w1, 1, s);
-  hipLaunchKernelGGL(k_unpack, dim3(grid_n(K.N)), dim3(256), 0, s, K, w0, w1, u);
+  hipLaunchKernelGGL(k_unpack<T>, dim3(grid_n(K.N)), dim3(256), 0, s, K, w0, w1, u);
 }
+
+template void launch_spectral_solve<double>(const Consts&, const FftPlan&, const double*, double, const double*,
+                                            double2*, double2*, double*, hipStream_t);
+template void launch_spectral_solve<float>(const Consts&, const FftPlan&, const float*, double, const float*,
+                                           double2*, double2*, float*, hipStream_t);
 
 }  // namespace pf

@@ -65,27 +65,33 @@ __device__ inline Pt coords(const Consts& K, long long n) {
   return p;
 }
 
+// The stencil helpers read planes of element type T (double, or the float of a mixed-precision
+// Krylov vector) and compute in double.
+
 // 2*d+1 point Laplacian of one plane
-__device__ inline double lap(const Consts& K, const double* __restrict__ f, Pt p, double fc) {
+template <typename T>
+__device__ inline double lap(const Consts& K, const T* __restrict__ f, Pt p, double fc) {
   double s = 0.0;
-  for (int dir = 0; dir < K.dim; ++dir) s += f[at_dir(K, p, dir, 1)] + f[at_dir(K, p, dir, -1)];
+  for (int dir = 0; dir < K.dim; ++dir) s += (double)f[at_dir(K, p, dir, 1)] + (double)f[at_dir(K, p, dir, -1)];
   return (s - 2.0 * K.dim * fc) * K.ih2;
 }
 
 // Dhat_dir of one plane at p (p may be an unwrapped neighbour)
-__device__ inline double dhat(const Consts& K, const double* __restrict__ f, Pt p, int dir) {
-  return (f[at_dir(K, p, dir, 1)] - f[at_dir(K, p, dir, -1)]) * K.i2h;
+template <typename T>
+__device__ inline double dhat(const Consts& K, const T* __restrict__ f, Pt p, int dir) {
+  return ((double)f[at_dir(K, p, dir, 1)] - (double)f[at_dir(K, p, dir, -1)]) * K.i2h;
 }
 
 // sigma_IJ at point p from displacement planes u (d planes) and composition c.
 // xi = 1 includes the eigenstrain -eps0 (c - cbar0) delta_IJ; for a perturbation (J v) the
 // composition enters as -eps0 dc (xi = 1, cref = 0).
-__device__ inline double sigma(const Consts& K, const double* __restrict__ u, long long N,
-                               const double* __restrict__ c, double cref, Pt p, int I, int J) {
+template <typename T>
+__device__ inline double sigma(const Consts& K, const T* __restrict__ u, long long N,
+                               const T* __restrict__ c, double cref, Pt p, int I, int J) {
   if (I != J) {
     return K.C44 * (dhat(K, u + (long long)J * N, p, I) + dhat(K, u + (long long)I * N, p, J));
   }
-  const double ec = K.eps0 * (c[at(K, p, 0, 0, 0)] - cref);
+  const double ec = K.eps0 * ((double)c[at(K, p, 0, 0, 0)] - cref);
   double s = 0.0;
   for (int L = 0; L < K.dim; ++L) {
     const double e = dhat(K, u + (long long)L * N, p, L) - ec;
@@ -95,8 +101,9 @@ __device__ inline double sigma(const Consts& K, const double* __restrict__ u, lo
 }
 
 // sum_J Dhat_J sigma_IJ at p
-__device__ inline double div_sigma(const Consts& K, const double* __restrict__ u, long long N,
-                                   const double* __restrict__ c, double cref, Pt p, int I) {
+template <typename T>
+__device__ inline double div_sigma(const Consts& K, const T* __restrict__ u, long long N,
+                                   const T* __restrict__ c, double cref, Pt p, int I) {
   double s = 0.0;
   for (int J = 0; J < K.dim; ++J) {
     s += sigma(K, u, N, c, cref, shift(p, J, 1), I, J) - sigma(K, u, N, c, cref, shift(p, J, -1), I, J);
@@ -360,9 +367,11 @@ __global__ __launch_bounds__(256) void k_residual_f(Consts K, double dt, const d
 // ---------------------------------------------------------------------------------
 // linearisation: B = d G_chem / d V^{n+1}, 16 planes (row-major 4 x 4 per node)
 // ---------------------------------------------------------------------------------
+// B: the 16 block planes in double; Bf (optional): the same rounded to float, for a
+// mixed-precision preconditioner
 __global__ __launch_bounds__(256) void k_linearise(Consts K, const double* __restrict__ X,
                                                    const double* __restrict__ Xn,
-                                                   double* __restrict__ B) {
+                                                   double* __restrict__ B, float* __restrict__ Bf) {
   const long long N = K.N;
   for (long long n = (long long)blockIdx.x * 256 + threadIdx.x; n < N; n += (long long)gridDim.x * 256) {
     double e1[3], e0[3], Ge[3], Gc, b[16];
@@ -372,6 +381,8 @@ __global__ __launch_bounds__(256) void k_linearise(Consts K, const double* __res
     }
     chem_dg<true>(K, X[n], e1, Xn[n], e0, Gc, Ge, b);
     for (int q = 0; q < 16; ++q) B[q * N + n] = b[q];
+    if (Bf)
+      for (int q = 0; q < 16; ++q) Bf[q * N + n] = (float)b[q];
   }
 }
 
@@ -382,50 +393,14 @@ __global__ __launch_bounds__(256) void k_linearise(Consts K, const double* __res
 //   (Jv)_e = v_e/dt + L_eta (B_e. v - (gamma_eta/2) Lap_h v_e)
 //   (Jv)_u = sum_J Dhat_J sigma_IJ(v_u, v_c)   (composition enters through -eps0 v_c)
 // ---------------------------------------------------------------------------------
-__global__ __launch_bounds__(kBX* kBY) void k_jv_g(Consts K, double dt, const double* __restrict__ B,
-                                                   const double* __restrict__ v,
-                                                   double* __restrict__ dG,
-                                                   double* __restrict__ w) {
-  Pt p{(int)(blockIdx.x * kBX + threadIdx.x), (int)(blockIdx.y * kBY + threadIdx.y), (int)blockIdx.z};
-  if (p.i >= K.nx || p.j >= K.ny) return;
-  const long long N = K.N, n = lin(K, p);
-  double vv[4];
-  for (int q = 0; q < 4; ++q) vv[q] = v[q * N + n];
-  double g = K.kel * vv[0] - 0.5 * K.gamma_c * lap(K, v, p, vv[0]);
-  for (int q = 0; q < 4; ++q) g += B[q * N + n] * vv[q];
-  if (K.elastic) {
-    double div = 0.0;
-    for (int I = 0; I < K.dim; ++I) div += dhat(K, v + (4 + I) * N, p, I);
-    g -= 0.5 * K.eps0 * K.Ctr * div;
-  }
-  dG[n] = g;
-  const double idt = 1.0 / dt;
-  for (int e = 0; e < 3; ++e) {
-    double s = -0.5 * K.gamma_eta * lap(K, v + (1 + e) * N, p, vv[1 + e]);
-    for (int q = 0; q < 4; ++q) s += B[(4 * (1 + e) + q) * N + n] * vv[q];
-    w[(1 + e) * N + n] = vv[1 + e] * idt + K.L_eta * s;
-  }
-  for (int I = 0; I < K.dim; ++I) {
-    w[(4 + I) * N + n] = K.elastic ? div_sigma(K, v + 4 * N, N, v, 0.0, p, I) : v[(4 + I) * N + n];
-  }
-}
-
-__global__ __launch_bounds__(kBX* kBY) void k_jv_c(Consts K, double dt, const double* __restrict__ cn,
-                                                   const double* __restrict__ v,
-                                                   const double* __restrict__ dG,
-                                                   double* __restrict__ w) {
-  Pt p{(int)(blockIdx.x * kBX + threadIdx.x), (int)(blockIdx.y * kBY + threadIdx.y), (int)blockIdx.z};
-  if (p.i >= K.nx || p.j >= K.ny) return;
-  const long long n = lin(K, p);
-  w[n] = v[n] / dt - div_M_grad(K, dG, cn, p, n);
-}
-
-// fused J v: one block of kBX x kBY (x 1) nodes; dG on the block and a halo of one node is
-// computed into LDS, the c row reads it there; eta and u rows as in k_jv_g.
-template <int DIM>
+// J v in one pass: one block of kBX x kBY (x 1) nodes; dG on the block and a halo of one node
+// is computed into LDS, the c row reads it there; the eta and u rows are local stencils.
+// v has element type Tv (double, or float for a mixed-precision Krylov vector); the
+// arithmetic and w are double.
+template <int DIM, typename Tv>
 __global__ __launch_bounds__(kBX* kBY) void k_jv_fused(Consts K, double dt, const double* __restrict__ B,
                                                        const double* __restrict__ cn,
-                                                       const double* __restrict__ v,
+                                                       const Tv* __restrict__ v,
                                                        double* __restrict__ w) {
   constexpr int HX = kBX + 2, HY = kBY + 2, HZ = (DIM == 3) ? 3 : 1;
   __shared__ double sdg[HX * HY * HZ];
@@ -470,7 +445,7 @@ __global__ __launch_bounds__(kBX* kBY) void k_jv_fused(Consts K, double dt, cons
       const double Mm = 0.5 * K.kappa * (mc + cn[nm] * (1.0 - cn[nm]));
       s += Mp * (sdg[hq + hs[dir]] - g0) - Mm * (g0 - sdg[hq - hs[dir]]);
     }
-    w[n] = v[n] * idt - s * K.ih2;
+    w[n] = (double)v[n] * idt - s * K.ih2;
   }
   double vv[4];
 #pragma unroll
@@ -484,7 +459,7 @@ __global__ __launch_bounds__(kBX* kBY) void k_jv_fused(Consts K, double dt, cons
   }
 #pragma unroll
   for (int I = 0; I < DIM; ++I) {
-    w[(4 + I) * N + n] = K.elastic ? div_sigma(K, v + 4 * N, N, v, 0.0, p, I) : v[(4 + I) * N + n];
+    w[(4 + I) * N + n] = K.elastic ? div_sigma(K, v + 4 * N, N, v, 0.0, p, I) : (double)v[(4 + I) * N + n];
   }
 }
 
@@ -562,17 +537,24 @@ void launch_residual(const Consts& K, double dt, const double* X, const double* 
   hipLaunchKernelGGL(k_residual_f, dim3(kRedBlocks), dim3(256), 0, s, K, dt, X, Xn, G4, F, partial);
 }
 
-void launch_linearise(const Consts& K, const double* X, const double* Xn, double* B, hipStream_t s) {
+void launch_linearise(const Consts& K, const double* X, const double* Xn, double* B, float* Bf,
+                      hipStream_t s) {
   long long nb = (K.N + 255) / 256;
-  hipLaunchKernelGGL(k_linearise, dim3((unsigned)(nb < 4096 ? nb : 4096)), dim3(256), 0, s, K, X, Xn, B);
+  hipLaunchKernelGGL(k_linearise, dim3((unsigned)(nb < 4096 ? nb : 4096)), dim3(256), 0, s, K, X, Xn, B, Bf);
 }
 
-void launch_jv(const Consts& K, double dt, const double* B, const double* cn, const double* v,
-               double* dG, double* w, hipStream_t s) {
-  (void)dG;
-  if (K.dim == 2) hipLaunchKernelGGL(k_jv_fused<2>, stencil_grid(K), dim3(kBX, kBY), 0, s, K, dt, B, cn, v, w);
-  else hipLaunchKernelGGL(k_jv_fused<3>, stencil_grid(K), dim3(kBX, kBY), 0, s, K, dt, B, cn, v, w);
+template <typename Tv>
+void launch_jv(const Consts& K, double dt, const double* B, const double* cn, const Tv* v, double* w,
+               hipStream_t s) {
+  if (K.dim == 2)
+    hipLaunchKernelGGL((k_jv_fused<2, Tv>), stencil_grid(K), dim3(kBX, kBY), 0, s, K, dt, B, cn, v, w);
+  else
+    hipLaunchKernelGGL((k_jv_fused<3, Tv>), stencil_grid(K), dim3(kBX, kBY), 0, s, K, dt, B, cn, v, w);
 }
+template void launch_jv<double>(const Consts&, double, const double*, const double*, const double*, double*,
+                                hipStream_t);
+template void launch_jv<float>(const Consts&, double, const double*, const double*, const float*, double*,
+                               hipStream_t);
 
 void launch_energy(const Consts& K, const double* X, double* partial, hipStream_t s) {
   hipLaunchKernelGGL(k_energy, dim3(kRedBlocks), dim3(256), 0, s, K, X, partial);

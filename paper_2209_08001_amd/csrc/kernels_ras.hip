@@ -35,70 +35,28 @@ struct Geo {
   int sweeps;
 };
 
-template <int NF>
-__device__ inline void solve_small(double (&D)[NF][NF], double (&x)[NF]) {
-  // Gauss elimination with partial pivoting (NF <= 4)
-#pragma unroll
-  for (int k = 0; k < NF; ++k) {
-    int piv = k;
-    double best = fabs(D[k][k]);
-#pragma unroll
-    for (int i = k + 1; i < NF; ++i) {
-      if (fabs(D[i][k]) > best) {
-        best = fabs(D[i][k]);
-        piv = i;
-      }
-    }
-    if (piv != k) {
-#pragma unroll
-      for (int j = 0; j < NF; ++j) {
-        const double t = D[k][j];
-        D[k][j] = D[piv][j];
-        D[piv][j] = t;
-      }
-      const double t = x[k];
-      x[k] = x[piv];
-      x[piv] = t;
-    }
-    const double inv = 1.0 / D[k][k];
-#pragma unroll
-    for (int i = k + 1; i < NF; ++i) {
-      const double f = D[i][k] * inv;
-#pragma unroll
-      for (int j = k; j < NF; ++j) D[i][j] -= f * D[k][j];
-      x[i] -= f * x[k];
-    }
-  }
-#pragma unroll
-  for (int k = NF - 1; k >= 0; --k) {
-    double s = x[k];
-#pragma unroll
-    for (int j = k + 1; j < NF; ++j) s -= D[k][j] * x[j];
-    x[k] = s / D[k][k];
-  }
-}
-
 __device__ inline int wrapg(int a, int n) {
   a %= n;
   return a < 0 ? a + n : a;
 }
 
-template <int DIM, bool WU, int NPT>
+template <int DIM, bool WU, int NPT, typename R>
 __global__ __launch_bounds__(kRasThreads) void k_ras(Consts K, Geo G, double dt,
-                                                     const double* __restrict__ Bg,
+                                                     const R* __restrict__ Bg,
                                                      const double* __restrict__ cn,
-                                                     const double* __restrict__ rg,
-                                                     double* __restrict__ zg) {
+                                                     const R* __restrict__ rg,
+                                                     R* __restrict__ zg) {
   constexpr int NFZ = WU ? 4 + DIM : 4;
   constexpr int NCOL = (DIM == 3) ? 7 : 5;
-  extern __shared__ double lds[];
+  extern __shared__ double lds_raw[];
+  R* lds = reinterpret_cast<R*>(lds_raw);
   const int zsz = G.zx * G.zy * G.zz;
   const int dsz = G.dx * G.dy * G.dz;
   const int ne = G.ex * G.ey * G.ez;
-  double* zs = lds;              // NFZ planes of zsz: the iterate with a zero ring of 2
-  double* dg = zs + NFZ * zsz;   // dsz: dG on ext and a ring of 1
-  double* gg = dg + dsz;         // dsz: g = c^n (1 - c^n)
-  double* bc = gg + dsz;         // 4 planes of ne: c-row of the chemical block
+  R* zs = lds;              // NFZ planes of zsz: the iterate with a zero ring of 2
+  R* dg = zs + NFZ * zsz;   // dsz: dG on ext and a ring of 1
+  R* gg = dg + dsz;         // dsz: g = c^n (1 - c^n)
+  R* bc = gg + dsz;         // 4 planes of ne: c-row of the chemical block
   int* perm = (int*)(bc + 4 * ne);  // ne: ext nodes sorted by colour
   int* rowoff = perm + ne;          // NCOL * rows: colour offsets of each row
   __shared__ int cstart[NCOL + 1], cfill[NCOL];
@@ -116,8 +74,8 @@ __global__ __launch_bounds__(kRasThreads) void k_ras(Consts K, Geo G, double dt,
     const int gi = wrapg(ox + a - 1, K.nx), gj = wrapg(oy + b - 1, K.ny);
     const int gk = (DIM == 3) ? wrapg(oz + c - 1, K.nz) : 0;
     const double v = cn[gi + (long long)K.nx * (gj + (long long)K.ny * gk)];
-    gg[q] = v * (1.0 - v);
-    dg[q] = 0.0;
+    gg[q] = (R)(v * (1.0 - v));
+    dg[q] = R(0);
   }
   __syncthreads();
   // c-row blocks into LDS
@@ -172,8 +130,8 @@ __global__ __launch_bounds__(kRasThreads) void k_ras(Consts K, Geo G, double dt,
   // nodes of this thread: right-hand side and eta-rows of the chemical block in registers.
   // The planes are staged through LDS four at a time with row-major (coalesced) loads and
   // then picked up by the thread that owns each node in colour order.
-  double rr[NPT][NFZ];
-  double be[NPT][12];
+  R rr[NPT][NFZ];
+  R be[NPT][12];
   int zi_[NPT], di_[NPT], q_[NPT], col_[NPT];
 #pragma unroll
   for (int m = 0; m < NPT; ++m) {
@@ -210,7 +168,7 @@ __global__ __launch_bounds__(kRasThreads) void k_ras(Consts K, Geo G, double dt,
       for (int k = 0; k < 4; ++k) {
         const int pl = p0 + k;
         if (k >= np) break;
-        const double v = zs[k * ne + q_[m]];
+        const R v = zs[k * ne + q_[m]];
 #pragma unroll
         for (int f = 0; f < NFZ; ++f)
           if (pl == f) rr[m][f] = v;
@@ -221,17 +179,23 @@ __global__ __launch_bounds__(kRasThreads) void k_ras(Consts K, Geo G, double dt,
     }
     __syncthreads();
   }
-  for (int q = threadIdx.x; q < NFZ * zsz; q += kRasThreads) zs[q] = 0.0;
+  for (int q = threadIdx.x; q < NFZ * zsz; q += kRasThreads) zs[q] = R(0);
   __syncthreads();
 
-  const double idt = 1.0 / dt;
-  const double lapc = -2.0 * DIM * K.ih2;
+  // coefficients in the arithmetic type of the solve (formed in double, rounded once)
+  const R idt = (R)(1.0 / dt);
+  const R ih2 = (R)K.ih2, i2h = (R)K.i2h, kel = (R)K.kel, Le = (R)K.L_eta, eps0 = (R)K.eps0;
+  const R C11 = (R)K.C11, C12 = (R)K.C12, C44 = (R)K.C44;
+  const R lapc = (R)(-2.0 * DIM * K.ih2);
+  const R hgc = (R)(-0.5 * K.gamma_c), hge = (R)(-0.5 * K.gamma_eta), hk = (R)(0.5 * K.kappa);
   const int sdir_z[3] = {1, sy, sz};
   const int sdir_d[3] = {1, ty_, tz_};
-  const double a_u = -0.5 * K.eps0 * K.Ctr;  // coefficient of div_h z_u in dG
-  const double dcc0 = idt;                   // parts of the c-c diagonal entry
-  const double dcc1 = K.kel + K.gamma_c * DIM * K.ih2 + 0.5 * K.gamma_c * K.ih2;
-  const double dee = idt + K.L_eta * K.gamma_eta * DIM * K.ih2;
+  const R a_u = (R)(-0.5 * K.eps0 * K.Ctr * K.i2h);  // coefficient of the difference of z_u in dG
+  const R dcc0 = idt;                                // parts of the c-c diagonal entry
+  const R dcc1 = (R)(K.kel + K.gamma_c * DIM * K.ih2 + 0.5 * K.gamma_c * K.ih2);
+  const R dee = (R)(1.0 / dt + K.L_eta * K.gamma_eta * DIM * K.ih2);
+  const R iduu = (R)(-2.0 * K.h * K.h / (K.C11 + (DIM - 1) * K.C44));
+  const R cxu = (R)(K.eps0 * K.Ctr * 0.25 * K.ih2 * K.ih);
   bool first = true;
 
   for (int sw = 0; sw < G.sweeps; ++sw) {
@@ -245,22 +209,22 @@ __global__ __launch_bounds__(kRasThreads) void k_ras(Consts K, Geo G, double dt,
             const bool inside = a >= 1 && a <= G.ex && b >= 1 && b <= G.ey &&
                                 (DIM == 2 || (c >= 1 && c <= G.ez));
             const int pz = (a - 1 + ring) + sy * (b - 1 + ring) + ((DIM == 3) ? sz * (c - 1 + ring) : 0);
-            double l = lapc * zs[pz];
+            R l = lapc * zs[pz];
 #pragma unroll
-            for (int d = 0; d < DIM; ++d) l += (zs[pz + sdir_z[d]] + zs[pz - sdir_z[d]]) * K.ih2;
-            double sg_ = -0.5 * K.gamma_c * l;
+            for (int d = 0; d < DIM; ++d) l += (zs[pz + sdir_z[d]] + zs[pz - sdir_z[d]]) * ih2;
+            R sg_ = hgc * l;
             if (inside) {
               const int qe = (a - 1) + G.ex * ((b - 1) + ((DIM == 3) ? G.ey * (c - 1) : 0));
-              sg_ += K.kel * zs[pz];
+              sg_ += kel * zs[pz];
 #pragma unroll
               for (int f = 0; f < 4; ++f) sg_ += bc[f * ne + qe] * zs[f * zsz + pz];
             }
             if (WU) {
-              double dv = 0.0;
+              R dv = R(0);
 #pragma unroll
               for (int d = 0; d < DIM; ++d)
                 dv += zs[(4 + d) * zsz + pz + sdir_z[d]] - zs[(4 + d) * zsz + pz - sdir_z[d]];
-              sg_ += a_u * dv * K.i2h;
+              sg_ += a_u * dv;
             }
             dg[qd] = sg_;
           }
@@ -275,7 +239,7 @@ __global__ __launch_bounds__(kRasThreads) void k_ras(Consts K, Geo G, double dt,
         for (int m = 0; m < NPT; ++m)
           if (col_[m] == col) msel = m;
         if (msel >= 0) {
-          double rv[NFZ], bv[12];
+          R rv[NFZ], bv[12];
 #pragma unroll
           for (int f = 0; f < NFZ; ++f) {
             rv[f] = rr[0][f];
@@ -295,97 +259,96 @@ __global__ __launch_bounds__(kRasThreads) void k_ras(Consts K, Geo G, double dt,
             di = (msel == m) ? di_[m] : di;
             q = (msel == m) ? q_[m] : q;
           }
-          double zv[NFZ];
+          R zv[NFZ];
 #pragma unroll
           for (int f = 0; f < NFZ; ++f) zv[f] = zs[f * zsz + zi];
-          double res[NFZ];
+          R res[NFZ];
           // c row: z_c/dt - div_h(M grad_h dG)
-          double sumM = 0.0, dM[3] = {0.0, 0.0, 0.0};
-          double divm = 0.0;
-          const double g0 = gg[di], dg0 = dg[di];
+          R sumM = R(0), dM[3] = {R(0), R(0), R(0)};
+          R divm = R(0);
+          const R g0 = gg[di], dg0 = dg[di];
 #pragma unroll
           for (int d = 0; d < DIM; ++d) {
-            const double Mp = 0.5 * K.kappa * (g0 + gg[di + sdir_d[d]]);
-            const double Mm = 0.5 * K.kappa * (g0 + gg[di - sdir_d[d]]);
+            const R Mp = hk * (g0 + gg[di + sdir_d[d]]);
+            const R Mm = hk * (g0 + gg[di - sdir_d[d]]);
             divm += Mp * (dg[di + sdir_d[d]] - dg0) - Mm * (dg0 - dg[di - sdir_d[d]]);
             sumM += Mp + Mm;
             dM[d] = Mm - Mp;
           }
-          res[0] = rv[0] - (zv[0] * idt - divm * K.ih2);
+          res[0] = rv[0] - (zv[0] * idt - divm * ih2);
           // eta rows: z_e/dt + L_eta (B_e . z - (gamma_eta/2) Lap_h z_e)
 #pragma unroll
           for (int e = 0; e < 3; ++e) {
             const int ze = (1 + e) * zsz + zi;
-            double l = lapc * zv[1 + e];
+            R l = lapc * zv[1 + e];
 #pragma unroll
-            for (int d = 0; d < DIM; ++d) l += (zs[ze + sdir_z[d]] + zs[ze - sdir_z[d]]) * K.ih2;
-            double s = -0.5 * K.gamma_eta * l;
+            for (int d = 0; d < DIM; ++d) l += (zs[ze + sdir_z[d]] + zs[ze - sdir_z[d]]) * ih2;
+            R s = hge * l;
 #pragma unroll
             for (int f = 0; f < 4; ++f) s += bv[4 * e + f] * zv[f];
-            res[1 + e] = rv[1 + e] - (zv[1 + e] * idt + K.L_eta * s);
+            res[1 + e] = rv[1 + e] - (zv[1 + e] * idt + Le * s);
           }
           // u rows: sum_J Dhat_J sigma_IJ(z_u, z_c)
           if (WU) {
 #pragma unroll
             for (int I = 0; I < DIM; ++I) {
-              double acc = 0.0;
+              R acc = R(0);
 #pragma unroll
               for (int J = 0; J < DIM; ++J) {
 #pragma unroll
                 for (int sgn = -1; sgn <= 1; sgn += 2) {
                   const int pz = zi + sgn * sdir_z[J];
-                  double sig;
+                  R sig;
                   if (I != J) {
-                    sig = K.C44 * ((zs[(4 + J) * zsz + pz + sdir_z[I]] - zs[(4 + J) * zsz + pz - sdir_z[I]]) +
-                                   (zs[(4 + I) * zsz + pz + sdir_z[J]] - zs[(4 + I) * zsz + pz - sdir_z[J]])) * K.i2h;
+                    sig = C44 * ((zs[(4 + J) * zsz + pz + sdir_z[I]] - zs[(4 + J) * zsz + pz - sdir_z[I]]) +
+                                 (zs[(4 + I) * zsz + pz + sdir_z[J]] - zs[(4 + I) * zsz + pz - sdir_z[J]])) * i2h;
                   } else {
-                    const double ec = K.eps0 * zs[pz];
-                    sig = 0.0;
+                    const R ec = eps0 * zs[pz];
+                    sig = R(0);
 #pragma unroll
                     for (int L = 0; L < DIM; ++L) {
-                      const double e = (zs[(4 + L) * zsz + pz + sdir_z[L]] - zs[(4 + L) * zsz + pz - sdir_z[L]]) * K.i2h - ec;
-                      sig += (L == I ? K.C11 : K.C12) * e;
+                      const R e = (zs[(4 + L) * zsz + pz + sdir_z[L]] - zs[(4 + L) * zsz + pz - sdir_z[L]]) * i2h - ec;
+                      sig += (L == I ? C11 : C12) * e;
                     }
                   }
-                  acc += sgn * sig;
+                  acc += (sgn > 0) ? sig : -sig;
                 }
               }
-              res[4 + I] = rv[4 + I] - acc * K.i2h;
+              res[4 + I] = rv[4 + I] - acc * i2h;
             }
           }
           // diagonal block of the node, solved through the Schur complement on c:
           //   [d_cc  u'] [x_c]   [r_c]      E = dee I + L_eta B_ee (3 x 3, dominated by 1/dt)
           //   [v     E ] [x_e] = [r_e],     x_c = (r_c - u'E^{-1} r_e) / (d_cc - u'E^{-1} v)
-          const double sc = sumM * K.ih2;
-          double xc = res[0];
+          const R sc = sumM * ih2;
+          R xc = res[0];
           if (WU) {
-            const double iduu = -2.0 * K.h * K.h / (K.C11 + (DIM - 1) * K.C44);
 #pragma unroll
             for (int I = 0; I < DIM; ++I) {
               res[4 + I] *= iduu;  // x_u
-              xc -= (K.eps0 * K.Ctr * 0.25 * K.ih2 * K.ih) * dM[I] * res[4 + I];
+              xc -= cxu * dM[I] * res[4 + I];
             }
           }
-          double E00 = dee + K.L_eta * bv[1], E01 = K.L_eta * bv[2], E02 = K.L_eta * bv[3];
-          double E10 = K.L_eta * bv[5], E11 = dee + K.L_eta * bv[6], E12 = K.L_eta * bv[7];
-          double E20 = K.L_eta * bv[9], E21 = K.L_eta * bv[10], E22 = dee + K.L_eta * bv[11];
-          const double A00 = E11 * E22 - E12 * E21, A01 = E02 * E21 - E01 * E22, A02 = E01 * E12 - E02 * E11;
-          const double A10 = E12 * E20 - E10 * E22, A11 = E00 * E22 - E02 * E20, A12 = E02 * E10 - E00 * E12;
-          const double A20 = E10 * E21 - E11 * E20, A21 = E01 * E20 - E00 * E21, A22 = E00 * E11 - E01 * E10;
-          const double idet = 1.0 / (E00 * A00 + E01 * A10 + E02 * A20);
+          const R E00 = dee + Le * bv[1], E01 = Le * bv[2], E02 = Le * bv[3];
+          const R E10 = Le * bv[5], E11 = dee + Le * bv[6], E12 = Le * bv[7];
+          const R E20 = Le * bv[9], E21 = Le * bv[10], E22 = dee + Le * bv[11];
+          const R A00 = E11 * E22 - E12 * E21, A01 = E02 * E21 - E01 * E22, A02 = E01 * E12 - E02 * E11;
+          const R A10 = E12 * E20 - E10 * E22, A11 = E00 * E22 - E02 * E20, A12 = E02 * E10 - E00 * E12;
+          const R A20 = E10 * E21 - E11 * E20, A21 = E01 * E20 - E00 * E21, A22 = E00 * E11 - E01 * E10;
+          const R idet = R(1) / (E00 * A00 + E01 * A10 + E02 * A20);
           // y = E^{-1} r_e, w = E^{-1} v  (v_e = L_eta B_e,c)
-          const double r1 = res[1], r2 = res[2], r3 = res[3];
-          const double v1 = K.L_eta * bv[0], v2 = K.L_eta * bv[4], v3 = K.L_eta * bv[8];
-          const double y1 = (A00 * r1 + A01 * r2 + A02 * r3) * idet;
-          const double y2 = (A10 * r1 + A11 * r2 + A12 * r3) * idet;
-          const double y3 = (A20 * r1 + A21 * r2 + A22 * r3) * idet;
-          const double w1 = (A00 * v1 + A01 * v2 + A02 * v3) * idet;
-          const double w2 = (A10 * v1 + A11 * v2 + A12 * v3) * idet;
-          const double w3 = (A20 * v1 + A21 * v2 + A22 * v3) * idet;
-          const double u1 = sc * bc[ne + q], u2 = sc * bc[2 * ne + q], u3 = sc * bc[3 * ne + q];
-          const double dcc = dcc0 + sc * (bc[q] + dcc1);
+          const R r1 = res[1], r2 = res[2], r3 = res[3];
+          const R v1 = Le * bv[0], v2 = Le * bv[4], v3 = Le * bv[8];
+          const R y1 = (A00 * r1 + A01 * r2 + A02 * r3) * idet;
+          const R y2 = (A10 * r1 + A11 * r2 + A12 * r3) * idet;
+          const R y3 = (A20 * r1 + A21 * r2 + A22 * r3) * idet;
+          const R w1 = (A00 * v1 + A01 * v2 + A02 * v3) * idet;
+          const R w2 = (A10 * v1 + A11 * v2 + A12 * v3) * idet;
+          const R w3 = (A20 * v1 + A21 * v2 + A22 * v3) * idet;
+          const R u1 = sc * bc[ne + q], u2 = sc * bc[2 * ne + q], u3 = sc * bc[3 * ne + q];
+          const R dcc = dcc0 + sc * (bc[q] + dcc1);
           xc = (xc - (u1 * y1 + u2 * y2 + u3 * y3)) / (dcc - (u1 * w1 + u2 * w2 + u3 * w3));
-          double x[4] = {xc, y1 - w1 * xc, y2 - w2 * xc, y3 - w3 * xc};
+          const R x[4] = {xc, y1 - w1 * xc, y2 - w2 * xc, y3 - w3 * xc};
 #pragma unroll
           for (int f = 0; f < 4; ++f) zs[f * zsz + zi] = zv[f] + x[f];
           if (WU) {
@@ -432,14 +395,14 @@ Geo make_geo(const Consts& K, const TileCfg& T) {
   return G;
 }
 
-template <int DIM, bool WU>
+template <int DIM, bool WU, typename R>
 void launch_dim(const Consts& K, const Geo& G, size_t lds, int ntiles, int npt, double dt,
-                const double* B, const double* cn, const double* r, double* z, hipStream_t s) {
+                const R* B, const double* cn, const R* r, R* z, hipStream_t s) {
 #define PF_RAS_CASE(NPTV)                                                                          \
   case NPTV:                                                                                       \
-    (void)hipFuncSetAttribute((const void*)k_ras<DIM, WU, NPTV>,                                      \
+    (void)hipFuncSetAttribute((const void*)k_ras<DIM, WU, NPTV, R>,                                   \
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                    \
-    hipLaunchKernelGGL((k_ras<DIM, WU, NPTV>), dim3(ntiles), dim3(kRasThreads), lds, s, K, G, dt, \
+    hipLaunchKernelGGL((k_ras<DIM, WU, NPTV, R>), dim3(ntiles), dim3(kRasThreads), lds, s, K, G, dt, \
                        B, cn, r, z);                                                               \
     break;
   switch (npt) {
@@ -453,12 +416,12 @@ void launch_dim(const Consts& K, const Geo& G, size_t lds, int ntiles, int npt, 
 
 }  // namespace
 
-size_t ras_lds_bytes(const Consts& K, const TileCfg& T) {
+size_t ras_lds_bytes(const Consts& K, const TileCfg& T, size_t real_bytes) {
   const Geo G = make_geo(K, T);
   const int nfz = T.with_u ? 4 + K.dim : 4;
   const size_t ne = (size_t)G.ex * G.ey * G.ez;
   const size_t ncol = (K.dim == 3) ? 7 : 5;
-  return sizeof(double) * ((size_t)nfz * G.zx * G.zy * G.zz + 2 * (size_t)G.dx * G.dy * G.dz + 4 * ne) +
+  return real_bytes * ((size_t)nfz * G.zx * G.zy * G.zz + 2 * (size_t)G.dx * G.dy * G.dz + 4 * ne) +
          sizeof(int) * (ne + ncol * G.ey * G.ez);
 }
 
@@ -470,19 +433,24 @@ int ras_npt(const Consts& K, const TileCfg& T) {
   return npt <= 3 ? npt : 0;
 }
 
-void launch_ras(const Consts& K, const TileCfg& T, double dt, const double* B, const double* cn,
-                const double* r, double* z, hipStream_t s) {
+template <typename R>
+void launch_ras(const Consts& K, const TileCfg& T, double dt, const R* B, const double* cn,
+                const R* r, R* z, hipStream_t s) {
   const Geo G = make_geo(K, T);
   const int ntiles = G.ntx * G.nty * ((K.dim == 3) ? K.nz / T.tz : 1);
-  const size_t lds = ras_lds_bytes(K, T);
+  const size_t lds = ras_lds_bytes(K, T, sizeof(R));
   const int npt = ras_npt(K, T);
   if (K.dim == 2) {
-    if (T.with_u) launch_dim<2, true>(K, G, lds, ntiles, npt, dt, B, cn, r, z, s);
-    else launch_dim<2, false>(K, G, lds, ntiles, npt, dt, B, cn, r, z, s);
+    if (T.with_u) launch_dim<2, true, R>(K, G, lds, ntiles, npt, dt, B, cn, r, z, s);
+    else launch_dim<2, false, R>(K, G, lds, ntiles, npt, dt, B, cn, r, z, s);
   } else {
-    if (T.with_u) launch_dim<3, true>(K, G, lds, ntiles, npt, dt, B, cn, r, z, s);
-    else launch_dim<3, false>(K, G, lds, ntiles, npt, dt, B, cn, r, z, s);
+    if (T.with_u) launch_dim<3, true, R>(K, G, lds, ntiles, npt, dt, B, cn, r, z, s);
+    else launch_dim<3, false, R>(K, G, lds, ntiles, npt, dt, B, cn, r, z, s);
   }
 }
+template void launch_ras<double>(const Consts&, const TileCfg&, double, const double*, const double*,
+                                 const double*, double*, hipStream_t);
+template void launch_ras<float>(const Consts&, const TileCfg&, double, const float*, const double*,
+                                const float*, float*, hipStream_t);
 
 }  // namespace pf

@@ -39,10 +39,13 @@ struct Consts {
 // X, Xn: nf planes (c, eta1..3, u1..ud); all plane strides are N.
 void launch_residual(const Consts& K, double dt, const double* X, const double* Xn, double* G4,
                      double* F, double* partial, hipStream_t s);
-void launch_linearise(const Consts& K, const double* X, const double* Xn, double* B,
+// B: 16 block planes; Bf (may be null): the same rounded to float
+void launch_linearise(const Consts& K, const double* X, const double* Xn, double* B, float* Bf,
                       hipStream_t s);
-void launch_jv(const Consts& K, double dt, const double* B, const double* cn, const double* v,
-               double* dG, double* w, hipStream_t s);
+// w = J v; v has element type Tv (double or float), w is double
+template <typename Tv>
+void launch_jv(const Consts& K, double dt, const double* B, const double* cn, const Tv* v, double* w,
+               hipStream_t s);
 void launch_energy(const Consts& K, const double* X, double* partial, hipStream_t s);
 
 // ---- Schwarz tile solve (kernels_ras.hip) -------------------------------------------
@@ -52,9 +55,11 @@ struct TileCfg {
   int sweeps;       // symmetric GS sweeps
   int with_u;       // 1: all fields (plain RAS); 0: (c, eta) block only
 };
-void launch_ras(const Consts& K, const TileCfg& T, double dt, const double* B, const double* cn,
-                const double* r, double* z, hipStream_t s);
-size_t ras_lds_bytes(const Consts& K, const TileCfg& T);
+// R (double or float): element type of the blocks B, of r and z, and of the tile arithmetic
+template <typename R>
+void launch_ras(const Consts& K, const TileCfg& T, double dt, const R* B, const double* cn,
+                const R* r, R* z, hipStream_t s);
+size_t ras_lds_bytes(const Consts& K, const TileCfg& T, size_t real_bytes);
 
 // ---- spectral displacement solve (kernels_fft.hip) -----------------------------------
 struct FftPlan {
@@ -63,24 +68,32 @@ struct FftPlan {
   const double* sn[3];   // symbols S_m = sin(2 pi m / n) / h, m < n (exact 0 at m = 0, n/2)
 };
 // q_I = r_I + a D-hat_I zc (r may be null), solve K u = q by FFT, write u (d planes).
-void launch_spectral_solve(const Consts& K, const FftPlan& P, const double* r, double a,
-                           const double* zc, double2* work0, double2* work1, double* u,
+// T (double or float) is the element type of r, zc and u; the transforms run in double.
+template <typename T>
+void launch_spectral_solve(const Consts& K, const FftPlan& P, const T* r, double a,
+                           const T* zc, double2* work0, double2* work1, T* u,
                            hipStream_t s);
 
 // ---- vector kernels and reductions (kernels_blas.hip) --------------------------------
-// V: nv vectors of length n stored ldv apart
-void launch_multidot(long long n, int nv, const double* V, long long ldv, const double* w,
+// V: nv vectors of length n stored ldv apart.  The basis element type T is double or float
+// (instantiated for both); every sum is accumulated in double.
+template <typename T>
+void launch_multidot(long long n, int nv, const T* V, long long ldv, const double* w,
                      double* partial, hipStream_t s);
 void launch_update(long long n, int nv, const double* V, long long ldv, const double* coef,
                    const double* w, double scale, double* out, double* partial, hipStream_t s);
-void launch_lincomb(long long n, int nv, const double* V, long long ldv, const double* coef,
-                    double beta, double* out, hipStream_t s);
-void launch_axpby(long long n, double a, const double* x, double b, const double* y, double* out,
-                  hipStream_t s);
+template <typename T, typename To>
+void launch_lincomb(long long n, int nv, const T* V, long long ldv, const double* coef,
+                    double beta, To* out, hipStream_t s);
+// out = a x + b y (y unread when b == 0); instantiated for (d,d,d), (d,d,f), (d,f,d), (f,f,f),
+// (f,f,d)
+template <typename Tx, typename Ty, typename To>
+void launch_axpby(long long n, double a, const Tx* x, double b, const Ty* y, To* out, hipStream_t s);
 void launch_finalize(const double* partial, int nvals, double* out, hipStream_t s, double* out2 = nullptr);
 // v_{j+1} from device-resident Gram-Schmidt coefficients hc = [h_0..h_{nv-1}, <w,w>]
-void launch_update_dev(long long n, int nv, const double* V, long long ldv, const double* hc,
-                       const double* w, double* out, double* partial, hipStream_t s);
+template <typename T>
+void launch_update_dev(long long n, int nv, const T* V, long long ldv, const double* hc,
+                       const double* w, T* out, double* partial, hipStream_t s);
 void launch_sum2(long long n, const double* x, const double* y, const double* yn, double* partial,
                  hipStream_t s);
 void launch_trial(const Consts& K, int nf, const double* X, const double* S, double lam,

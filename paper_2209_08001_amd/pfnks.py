@@ -26,6 +26,9 @@ PC_RAS_SPECTRAL = 1
 PC_NONE = 2
 PC_SPECTRAL = 3
 
+FP64 = 0   # every vector and kernel in double
+MIXED = 1  # float Krylov basis, preconditioner and tile solve; double residual, J v, update
+
 EXPORTED = [
     "pfnks_workspace_bytes", "pfnks_create_problem", "pfnks_step", "pfnks_energy", "pfnks_mass",
     "pfnks_get_state", "pfnks_set_state", "pfnks_destroy", "pfnks_strerror", "pfnks_last_error",
@@ -170,7 +173,7 @@ def make_solver(d, dim):
     s.overlap = d["overlap"]
     s.sweeps = d.get("sweeps", 2)
     s.pc = d.get("pc", PC_RAS_SPECTRAL)
-    s.precision = 0
+    s.precision = d.get("precision", FP64)
     s.ls_alpha = d["ls_alpha"]
     s.ls_max_halvings = d["ls_max_halvings"]
     return s

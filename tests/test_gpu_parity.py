@@ -177,6 +177,33 @@ def test_pc_linear_and_deterministic(pc):
     p.close()
 
 
+@pytest.mark.parametrize("pc", ["ras_spectral", "ras"])
+def test_pc_mixed_close_to_fp64(pc):
+    """The float preconditioner is the double one up to float rounding: a fixed number of
+    Gauss-Seidel sweeps (a linear map whose norm is O(10) for these blocks) and one FFT solve,
+    each rounding at 2^-24 ~ 6e-8 relative, so ~6e-7 of the max-norm bounds the difference
+    (measured: 8e-8); the test uses 1e-6."""
+    from paper_2209_08001_amd import pfnks
+
+    _cuda()
+    _note(f"pc mixed vs fp64 {pc}")
+    n = (64, 64)
+    c0, e0 = W.init_fields(n, 23)
+    kind = pfnks.PC_RAS if pc == "ras" else pfnks.PC_RAS_SPECTRAL
+    pd = _problem(n, c0, e0, pc=kind)
+    pm = _problem(n, c0, e0, pc=kind, precision=pfnks.MIXED)
+    Xn, _ = pd.get_state()
+    r = np.random.default_rng(9).normal(size=Xn.shape)
+    zd = pd.debug_pc(Xn, 0.05, r)
+    zm = pm.debug_pc(Xn, 0.05, r)
+    err = _relmax(zm, zd)
+    _note(f"  max |z_mixed - z_fp64| / max |z_fp64| = {err:.3e}")
+    assert err <= 1e-6
+    assert np.array_equal(zm, pm.debug_pc(Xn, 0.05, r))
+    pd.close()
+    pm.close()
+
+
 @pytest.fixture(scope="module")
 def oracle_c1():
     n = W.WORKLOADS["pf2d_64"]["n"]
@@ -190,24 +217,30 @@ def oracle_c1():
     return c0, e0, traj, info, o
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
 @pytest.mark.parametrize("pc", ["ras_spectral", "ras"])
-def test_step_parity_pf2d_64(oracle_c1, pc):
+def test_step_parity_pf2d_64(oracle_c1, pc, prec):
     """2D 64 x 64, 10 steps of dt = 1e-2: every step within 1e-8 of the oracle's root,
-    mass conserved to 1e-13, energy non-increasing."""
+    mass conserved to 1e-13, energy non-increasing.  In mixed precision only the Krylov
+    correction is float; the Newton residual that decides convergence is double, so the
+    same bound applies."""
     from paper_2209_08001_amd import pfnks
 
     _cuda()
     c0, e0, traj, info, o = oracle_c1
-    _note(f"step parity pf2d_64 pc={pc}")
-    p = _problem((64, 64), c0, e0, pc=pfnks.PC_RAS if pc == "ras" else pfnks.PC_RAS_SPECTRAL)
+    _note(f"step parity pf2d_64 pc={pc} precision={prec}")
+    p = _problem((64, 64), c0, e0, pc=pfnks.PC_RAS if pc == "ras" else pfnks.PC_RAS_SPECTRAL,
+                 precision=pfnks.MIXED if prec == "mixed" else pfnks.FP64)
     m0 = p.mass()
     E_prev = p.energy()[0]
     for k in range(10):
         st = p.step(0.01)
         X, t = p.get_state()
+        errs = [_relmax(X[f], traj[k + 1][f]) for f in range(X.shape[0])]
+        _note(f"  step {k}: newton={st['newton_its']} gmres={st['gmres_its']} "
+              f"|F|/|F0|={st['res_final'] / st['res0']:.2e} max err={max(errs):.2e} (field {int(np.argmax(errs))})")
         for f in range(X.shape[0]):
-            err = _relmax(X[f], traj[k + 1][f])
-            assert err <= 1e-8, (k, f, err)
+            assert errs[f] <= 1e-8, (k, f, errs[f])
         assert abs(st["mass"] - m0) <= 1e-13 * abs(m0)
         assert st["energy"] <= E_prev + 1e-12 * abs(E_prev)
         assert abs(st["energy"] - info[k]["energy"]) <= 1e-9 * abs(info[k]["energy"])
@@ -246,22 +279,63 @@ def oracle_3d():
     return n, c0, e0, traj
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
 @pytest.mark.parametrize("pc", ["ras_spectral", "ras"])
-def test_step_parity_3d(oracle_3d, pc):
+def test_step_parity_3d(oracle_3d, pc, prec):
     """3D 8 x 8 x 8 (tiles 4^3, overlap 1), two steps: within 1e-8 of the oracle's root."""
     from paper_2209_08001_amd import pfnks
 
     _cuda()
     n, c0, e0, traj = oracle_3d
-    _note(f"step parity 3d pc={pc}")
+    _note(f"step parity 3d pc={pc} precision={prec}")
     p = _problem(n, c0, e0, tile=(4, 4, 4), overlap=1,
-                 pc=pfnks.PC_RAS if pc == "ras" else pfnks.PC_RAS_SPECTRAL)
+                 pc=pfnks.PC_RAS if pc == "ras" else pfnks.PC_RAS_SPECTRAL,
+                 precision=pfnks.MIXED if prec == "mixed" else pfnks.FP64)
     m0 = p.mass()
     for k, dt in enumerate((0.01, 0.05)):
         st = p.step(dt)
         X, _ = p.get_state()
+        errs = [_relmax(X[f], traj[k + 1][f]) for f in range(X.shape[0])]
+        _note(f"  step {k}: newton={st['newton_its']} gmres={st['gmres_its']} "
+              f"|F|/|F0|={st['res_final'] / st['res0']:.2e} max err={max(errs):.2e} (field {int(np.argmax(errs))})")
         for f in range(X.shape[0]):
-            err = _relmax(X[f], traj[k + 1][f])
-            assert err <= 1e-8, (k, f, err)
+            assert errs[f] <= 1e-8, (k, f, errs[f])
         assert abs(st["mass"] - m0) <= 1e-13 * abs(m0)
     p.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("wl", ["pf2d_512", "pf3d_128"])
+def test_full_size_first_step_root(wl, prec):
+    """Full-size workloads, the first step of the adaptive trajectory (dt = dt_min) in the
+    launch configuration the benchmark times.  The oracle's LU solve does not reach these
+    sizes, so the root is checked by properties that hold at any size: the oracle's own
+    residual at the GPU's X^{n+1} is below the Newton stopping bound (relative 1e-8 of the
+    oracle's residual at X^n, with 10 % slack for the evaluation's rounding), the mass is
+    unchanged to 1e-13 and the discrete energy does not increase."""
+    from paper_2209_08001_amd import pfnks
+
+    _cuda()
+    spec = W.WORKLOADS[wl]
+    n = spec["n"]
+    _note(f"full-size root {wl} precision={prec}")
+    c0, e0 = W.init_fields(n, spec["seed"], cbar=spec["cbar"])
+    kw = dict(precision=pfnks.MIXED if prec == "mixed" else pfnks.FP64)
+    if len(n) == 2:
+        kw["tile"] = (32, 32, 1)
+    p = _problem(n, c0, e0, **kw)
+    Xn, _ = p.get_state()
+    m0, E0 = p.mass(), p.energy()[0]
+    dt = spec["dt_min"]
+    st = p.step(dt)
+    X1, _ = p.get_state()
+    p.close()
+    g = Grid(n, W.H)
+    m = Model.from_dict(W.DEFAULT_MODEL)
+    cb0 = float(c0.mean())
+    r0 = np.linalg.norm(residual(Xn, Xn, dt, g, m, cb0))
+    r1 = np.linalg.norm(residual(X1, Xn, dt, g, m, cb0))
+    _note(f"  newton={st['newton_its']} gmres={st['gmres_its']} |F0|={r0:.3e} |F1|={r1:.3e}")
+    assert r1 <= 1.1 * W.DEFAULT_SOLVER["newton_rtol"] * r0, (r1, r0)
+    assert abs(st["mass"] - m0) <= 1e-13 * abs(m0)
+    assert st["energy"] <= E0 + 1e-12 * abs(E0)
