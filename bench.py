@@ -183,6 +183,7 @@ def main():
 
     # warm-up on a scratch problem; it also times every kernel kind to find the dominant one
     dominant = "ras"
+    table = {}
     if args.warmup > 0:
         pw = pfnks.Problem(n, W.H, W.DEFAULT_MODEL, solver, c0, e0, device=dev)
         pw.profile(True)
@@ -246,6 +247,11 @@ def main():
         "mass_rel_drift_max": mass_drift,
         "energy_increase_max": energy_up,
     }
+    if table:
+        # every kernel kind timed with events during the warm-up steps (algorithmic bytes)
+        out["warmup_kernels"] = {k: {"launches": v["launches"], "avg_us": round(v["avg_us"], 2),
+                                     "GB_s": round(v["GB_s"], 1) if v["GB_s"] else None}
+                                 for k, v in table.items()}
     if not args.no_roofline:
         roof = p.roofline(HBM_PEAK_GBS)
         traffic, summary = measured_traffic(roof["kernel"], args.workload, args.precision)

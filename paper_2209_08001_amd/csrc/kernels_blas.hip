@@ -392,6 +392,8 @@ template void launch_lincomb<double, double>(long long, int, const double*, long
                                              double*, hipStream_t);
 template void launch_lincomb<float, float>(long long, int, const float*, long long, const double*, double, float*,
                                            hipStream_t);
+template void launch_lincomb<float, double>(long long, int, const float*, long long, const double*, double,
+                                            double*, hipStream_t);
 
 template <typename Tx, typename Ty, typename To>
 void launch_axpby(long long n, double a, const Tx* x, double b, const Ty* y, To* out, hipStream_t s) {

@@ -56,6 +56,20 @@ __device__ inline long long lin(const Consts& K, Pt p) {
   return (long long)p.i + (long long)K.nx * ((long long)p.j + (long long)K.ny * p.k);
 }
 
+// Block coordinates of a stencil launch, reordered for the 8 XCDs: workgroups go to the XCDs
+// round-robin by linear id, so linear id b is given block b' = (b mod 8) * (nb / 8) + b / 8
+// (when nb is a multiple of 8).  Each XCD then sweeps a contiguous band of rows and the halo
+// lines shared by neighbouring blocks are fetched once into its own L2.
+__device__ inline void xcd_block(int& bx, int& by, int& bz) {
+  const int gx = gridDim.x, gy = gridDim.y;
+  const int nb = gx * gy * gridDim.z;
+  int b = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+  if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
+  bx = b % gx;
+  by = (b / gx) % gy;
+  bz = b / (gx * gy);
+}
+
 __device__ inline Pt coords(const Consts& K, long long n) {
   Pt p;
   p.i = (int)(n % K.nx);
@@ -262,7 +276,9 @@ __global__ __launch_bounds__(kBX* kBY) void k_residual_g(Consts K, const double*
                                                          const double* __restrict__ Xn,
                                                          double* __restrict__ G4,
                                                          double* __restrict__ F) {
-  Pt p{(int)(blockIdx.x * kBX + threadIdx.x), (int)(blockIdx.y * kBY + threadIdx.y), (int)blockIdx.z};
+  int bx, by, bz;
+  xcd_block(bx, by, bz);
+  Pt p{bx * kBX + (int)threadIdx.x, by * kBY + (int)threadIdx.y, bz};
   if (p.i >= K.nx || p.j >= K.ny) return;
   const long long N = K.N, n = lin(K, p);
   const double c1 = X[n], c0 = Xn[n];
@@ -405,7 +421,9 @@ __global__ __launch_bounds__(kBX* kBY) void k_jv_fused(Consts K, double dt, cons
   constexpr int HX = kBX + 2, HY = kBY + 2, HZ = (DIM == 3) ? 3 : 1;
   __shared__ double sdg[HX * HY * HZ];
   const long long N = K.N;
-  const int i0 = blockIdx.x * kBX, j0 = blockIdx.y * kBY, k0 = blockIdx.z;
+  int bx, by, bz;
+  xcd_block(bx, by, bz);
+  const int i0 = bx * kBX, j0 = by * kBY, k0 = bz;
   const int tid = threadIdx.x + kBX * threadIdx.y;
   const double Ka = -0.5 * K.eps0 * K.Ctr;
   for (int q = tid; q < HX * HY * HZ; q += kBX * kBY) {

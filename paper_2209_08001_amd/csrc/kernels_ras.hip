@@ -26,6 +26,10 @@ namespace {
 
 constexpr int kRasThreads = 512;
 
+// bound on the dG nodes (extended tile and its ring of one) per thread; the host rejects tile
+// shapes that need more
+constexpr __host__ __device__ int ras_dg_iters(int dim, int npt) { return dim == 2 ? npt + 1 : npt + 2; }
+
 struct Geo {
   int ex, ey, ez;      // extended tile
   int zx, zy, zz;      // LDS iterate (ext + ring of 2; zz = 1 in 2D)
@@ -40,6 +44,11 @@ __device__ inline int wrapg(int a, int n) {
   return a < 0 ? a + n : a;
 }
 
+// float tiles are small enough that two workgroups share a compute unit's LDS (3D 8^3 tiles
+// with overlap 1: 80 KB each); registers are capped so that both fit (4 waves per SIMD)
+template <typename R>
+constexpr int ras_waves_per_simd() { return sizeof(R) == 4 ? 4 : 2; }
+
 template <int DIM, bool WU, int NPT, typename R>
 __global__ __launch_bounds__(kRasThreads) void k_ras(Consts K, Geo G, double dt,
                                                      const R* __restrict__ Bg,
@@ -48,6 +57,7 @@ __global__ __launch_bounds__(kRasThreads) void k_ras(Consts K, Geo G, double dt,
                                                      R* __restrict__ zg) {
   constexpr int NFZ = WU ? 4 + DIM : 4;
   constexpr int NCOL = (DIM == 3) ? 7 : 5;
+  constexpr int DIT = ras_dg_iters(DIM, NPT);  // dG nodes per thread (ext + ring of 1)
   extern __shared__ double lds_raw[];
   R* lds = reinterpret_cast<R*>(lds_raw);
   const int zsz = G.zx * G.zy * G.zz;
@@ -61,7 +71,11 @@ __global__ __launch_bounds__(kRasThreads) void k_ras(Consts K, Geo G, double dt,
   int* rowoff = perm + ne;          // NCOL * rows: colour offsets of each row
   __shared__ int cstart[NCOL + 1], cfill[NCOL];
 
-  const int t = blockIdx.x;
+  // tile of this workgroup: workgroups go to the 8 XCDs round-robin, so each XCD is given a
+  // contiguous run of tiles (whole tile rows) and the overlap shared by neighbouring tiles is
+  // fetched once into its own L2
+  int t = blockIdx.x;
+  if ((gridDim.x & 7) == 0) t = (t & 7) * (gridDim.x >> 3) + (t >> 3);
   const int tix = t % G.ntx, tiy = (t / G.ntx) % G.nty, tiz = t / (G.ntx * G.nty);
   const int ox = tix * G.tx - G.ov, oy = tiy * G.ty - G.ov, oz = (DIM == 3) ? tiz * G.tz - G.ov : 0;
   const long long N = K.N;
@@ -196,6 +210,51 @@ __global__ __launch_bounds__(kRasThreads) void k_ras(Consts K, Geo G, double dt,
   const R dee = (R)(1.0 / dt + K.L_eta * K.gamma_eta * DIM * K.ih2);
   const R iduu = (R)(-2.0 * K.h * K.h / (K.C11 + (DIM - 1) * K.C44));
   const R cxu = (R)(K.eps0 * K.Ctr * 0.25 * K.ih2 * K.ih);
+  // dG at iterate position pz; qe: c-row block index, -1 on the ring of width 1 (where only
+  // the Laplacian term enters)
+  auto dg_at = [&](int pz, int qe) -> R {
+    R l = lapc * zs[pz];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) l += (zs[pz + sdir_z[d]] + zs[pz - sdir_z[d]]) * ih2;
+    R sg_ = hgc * l;
+    if (qe >= 0) {
+      sg_ += kel * zs[pz];
+#pragma unroll
+      for (int f = 0; f < 4; ++f) sg_ += bc[f * ne + qe] * zs[f * zsz + pz];
+    }
+    if (WU) {
+      R dv = R(0);
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) dv += zs[(4 + d) * zsz + pz + sdir_z[d]] - zs[(4 + d) * zsz + pz - sdir_z[d]];
+      sg_ += a_u * dv;
+    }
+    return sg_;
+  };
+  auto dg_node = [&](int qd, int& pz, int& qe) {
+    const int a = qd % G.dx, b = (qd / G.dx) % G.dy, c = qd / (G.dx * G.dy);
+    const bool inside = a >= 1 && a <= G.ex && b >= 1 && b <= G.ey && (DIM == 2 || (c >= 1 && c <= G.ez));
+    pz = (a - 1 + ring) + sy * (b - 1 + ring) + ((DIM == 3) ? sz * (c - 1 + ring) : 0);
+    qe = inside ? (a - 1) + G.ex * ((b - 1) + ((DIM == 3) ? G.ey * (c - 1) : 0)) : -1;
+  };
+  // The dG phase either keeps this thread's dG nodes precomputed (packed pz | (qe + 1) << 16,
+  // pz < 2^16 since the iterate holds fewer than 2^14 nodes) and forms all values before the
+  // stores, so that their LDS loads are in flight together (stores to dg could otherwise alias
+  // them), or walks its nodes one at a time with fewer live registers: the float 3D tile needs
+  // the latter to keep two workgroups resident per compute unit.
+  constexpr bool kBatch = !(DIM == 3 && sizeof(R) == 4);
+  int dpq[kBatch ? DIT : 1];
+  if constexpr (kBatch) {
+#pragma unroll
+    for (int it = 0; it < DIT; ++it) {
+      const int qd = threadIdx.x + it * kRasThreads;
+      dpq[it] = -1;
+      if (qd < dsz) {
+        int pz, qe;
+        dg_node(qd, pz, qe);
+        dpq[it] = pz | ((qe + 1) << 16);
+      }
+    }
+  }
   bool first = true;
 
   for (int sw = 0; sw < G.sweeps; ++sw) {
@@ -204,29 +263,20 @@ __global__ __launch_bounds__(kRasThreads) void k_ras(Consts K, Geo G, double dt,
         const int col = pass == 0 ? cc : NCOL - 1 - cc;
         // ---- dG on ext and on the ring of width 1 (all threads) -----------------------
         if (!first) {
-          for (int qd = threadIdx.x; qd < dsz; qd += kRasThreads) {
-            const int a = qd % G.dx, b = (qd / G.dx) % G.dy, c = qd / (G.dx * G.dy);
-            const bool inside = a >= 1 && a <= G.ex && b >= 1 && b <= G.ey &&
-                                (DIM == 2 || (c >= 1 && c <= G.ez));
-            const int pz = (a - 1 + ring) + sy * (b - 1 + ring) + ((DIM == 3) ? sz * (c - 1 + ring) : 0);
-            R l = lapc * zs[pz];
+          if constexpr (kBatch) {
+            R sgv[DIT];
 #pragma unroll
-            for (int d = 0; d < DIM; ++d) l += (zs[pz + sdir_z[d]] + zs[pz - sdir_z[d]]) * ih2;
-            R sg_ = hgc * l;
-            if (inside) {
-              const int qe = (a - 1) + G.ex * ((b - 1) + ((DIM == 3) ? G.ey * (c - 1) : 0));
-              sg_ += kel * zs[pz];
+            for (int it = 0; it < DIT; ++it)
+              sgv[it] = (dpq[it] < 0) ? R(0) : dg_at(dpq[it] & 0xffff, (dpq[it] >> 16) - 1);
 #pragma unroll
-              for (int f = 0; f < 4; ++f) sg_ += bc[f * ne + qe] * zs[f * zsz + pz];
+            for (int it = 0; it < DIT; ++it)
+              if (dpq[it] >= 0) dg[threadIdx.x + it * kRasThreads] = sgv[it];
+          } else {
+            for (int qd = threadIdx.x; qd < dsz; qd += kRasThreads) {
+              int pz, qe;
+              dg_node(qd, pz, qe);
+              dg[qd] = dg_at(pz, qe);
             }
-            if (WU) {
-              R dv = R(0);
-#pragma unroll
-              for (int d = 0; d < DIM; ++d)
-                dv += zs[(4 + d) * zsz + pz + sdir_z[d]] - zs[(4 + d) * zsz + pz - sdir_z[d]];
-              sg_ += a_u * dv;
-            }
-            dg[qd] = sg_;
           }
           __syncthreads();
         }
@@ -425,12 +475,15 @@ size_t ras_lds_bytes(const Consts& K, const TileCfg& T, size_t real_bytes) {
          sizeof(int) * (ne + ncol * G.ey * G.ez);
 }
 
-// nodes of the extended tile per thread (1..3), 0 if the tile does not fit
+// nodes of the extended tile per thread (1..3), 0 if the tile does not fit (more than three
+// nodes per thread, or more dG nodes than the kernel's unrolled loop holds)
 int ras_npt(const Consts& K, const TileCfg& T) {
   const Geo G = make_geo(K, T);
   const int ne = G.ex * G.ey * G.ez;
   const int npt = (ne + kRasThreads - 1) / kRasThreads;
-  return npt <= 3 ? npt : 0;
+  const int dsz = G.dx * G.dy * G.dz;
+  if (npt > 3 || (dsz + kRasThreads - 1) / kRasThreads > ras_dg_iters(K.dim, npt)) return 0;
+  return npt;
 }
 
 template <typename R>

@@ -43,7 +43,7 @@ struct Layout {
 };
 
 enum Buf {
-  B_X, B_XN, B_XT, B_F, B_FT, B_S, B_B, B_BPC, B_G4, B_V, B_W, B_Z, B_TMP, B_TMPV, B_PART, B_RED,
+  B_X, B_XN, B_XT, B_F, B_FT, B_S, B_B, B_BPC, B_G4, B_V, B_ZB, B_W, B_Z, B_TMP, B_TMPV, B_PART, B_RED,
   B_FFT0, B_FFT1, B_TW0, B_TW1, B_TW2, B_SN0, B_SN1, B_SN2, B_HDEV, B_COUNT
 };
 
@@ -52,7 +52,7 @@ size_t krylov_bytes(int precision) { return precision == PFNKS_MIXED ? sizeof(fl
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Krylov basis V, the preconditioned vector z, the cycle-end combination tmpv and the lagged
+// Krylov basis V, the preconditioned basis Z, the single vectors z and tmpv and the lagged
 // preconditioner blocks Bpc are stored in the Krylov element type (float when mixed); the
 // state, residuals, Newton update S, J v output w and the Jacobian blocks B are double.
 Layout make_layout(int dim, long long N, int restart, const int* n, int precision) {
@@ -66,6 +66,7 @@ Layout make_layout(int dim, long long N, int restart, const int* n, int precisio
   sz[B_BPC] = kb * 16 * (size_t)N;
   sz[B_G4] = sizeof(double) * 4 * (size_t)N;
   sz[B_V] = kvec * (size_t)(restart + 1);
+  sz[B_ZB] = kvec * (size_t)restart;
   sz[B_W] = sz[B_TMP] = vec;
   sz[B_Z] = kvec;
   sz[B_TMPV] = (precision == PFNKS_MIXED) ? kvec : 0;  // aliases tmp in FP64
@@ -145,7 +146,7 @@ struct pfnks_problem {
   hipStream_t stream;
   char* ws;
   double *X, *Xn, *Xt, *F, *Ft, *S, *B, *G4, *w, *tmp, *part, *red;
-  void *Bpc, *V, *z, *tmpv;  // Krylov element type: double (PFNKS_FP64) or float (PFNKS_MIXED)
+  void *Bpc, *V, *Zb, *z, *tmpv;  // Krylov element type: double (PFNKS_FP64) or float (PFNKS_MIXED)
   size_t kb;                 // bytes of that element
   double2 *fft0, *fft1;
   double* hbuf;   // pinned host scalars (written directly by the finalize kernels)
@@ -366,7 +367,11 @@ void jv(pfnks_problem* p, double dt, const double* Bm, const Tv* v, double* w) {
   p->launches += 1;
 }
 
-// Solve J S = -F: right-preconditioned restarted GMRES with classical Gram-Schmidt.
+// Solve J S = -F: right-preconditioned restarted GMRES with classical Gram-Schmidt, in the
+// flexible form: the preconditioned vectors z_j = M^{-1} v_j are kept (Z) and the correction
+// is S += Z y, so J Z = V H holds up to the rounding of the stored v_{j+1} even when M^{-1}
+// is applied in float (rounding makes it slightly nonlinear), and no preconditioner apply
+// is needed at the end of a cycle.
 // The Gram-Schmidt coefficients stay on the device (the update kernel reads them and forms
 // h_{j+1,j} = sqrt(<w,w> - sum h_i^2)); the finalize kernel also writes them to pinned host
 // memory.  The host enqueues Arnoldi step j+1 before it reads column j (Givens rotations,
@@ -384,8 +389,7 @@ int gmres(pfnks_problem* p, double dt, const double* Bm, double fnorm, double to
   const int ld = m + 2;
   const double kb = (double)sizeof(T);
   T* V = static_cast<T*>(p->V);
-  T* z = static_cast<T*>(p->z);
-  T* tmpv = static_cast<T*>(p->tmpv);
+  T* Z = static_cast<T*>(p->Zb);
   std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1), y(m);
   int total = 0;
   *ok = 0;
@@ -396,8 +400,8 @@ int gmres(pfnks_problem* p, double dt, const double* Bm, double fnorm, double to
   double beta = fnorm;
   p->launches += 1;
   auto launch_step = [&](int j) {
-    pc_apply<T>(p, dt, V + j * n, z);
-    jv<T>(p, dt, Bm, z, p->w);
+    pc_apply<T>(p, dt, V + j * n, Z + j * n);
+    jv<T>(p, dt, Bm, Z + j * n, p->w);
     {
       Prof pr(p, PFNKS_K_MULTIDOT, (kb * (j + 1) + 8.0) * n);
       pf::launch_multidot<T>(n, j + 1, V, n, p->w, p->part, p->stream);
@@ -420,7 +424,6 @@ int gmres(pfnks_problem* p, double dt, const double* Bm, double fnorm, double to
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
     int launched = 1, k = 0;
-    bool conv = false;
     double resid = beta;
     launch_step(0);
     for (int j = 0;; ++j) {
@@ -463,10 +466,7 @@ int gmres(pfnks_problem* p, double dt, const double* Bm, double fnorm, double to
         (void)hipStreamSynchronize(p->stream);
         return PFNKS_ENOCONV;
       }
-      if (resid <= tol) {
-        conv = true;
-        break;
-      }
+      if (resid <= tol) break;
       if (cancel || hnext == 0.0 || j + 1 == m || total >= maxit) break;
     }
     // y = H^{-1} g (upper triangular k x k)
@@ -475,22 +475,22 @@ int gmres(pfnks_problem* p, double dt, const double* Bm, double fnorm, double to
       for (int c = i + 1; c < k; ++c) s_ -= H[(size_t)c * (m + 1) + i] * y[c];
       y[i] = s_ / H[(size_t)i * (m + 1) + i];
     }
-    // S += M^{-1} (V y)
-    pf::launch_lincomb<T, T>(n, k, V, n, y.data(), 0.0, tmpv, p->stream);
-    pc_apply<T>(p, dt, tmpv, z);
-    pf::launch_axpby<double, T, double>(n, 1.0, p->S, 1.0, z, p->S, p->stream);
-    p->launches += 2;
-    if (conv) {
-      *ok = 1;
-      break;
-    }
-    if (total >= maxit) break;
-    // restart: r = -F - J S
+    // S += Z y
+    pf::launch_lincomb<T, double>(n, k, Z, n, y.data(), 1.0, p->S, p->stream);
+    p->launches += 1;
+    // the true residual r = -F - J S decides convergence (the Hessenberg estimate can be
+    // optimistic by the rounding of the stored basis, 2^-24 when it is float) and starts the
+    // next cycle
     jv<double>(p, dt, Bm, p->S, p->w);
     pf::launch_axpby<double, double, double>(n, -1.0, p->F, -1.0, p->w, p->tmp, p->stream);
     p->launches += 1;
     int st = dot_norm(p, p->tmp, &beta);
     if (st) return st;
+    if (beta <= tol) {
+      *ok = 1;
+      break;
+    }
+    if (total >= maxit) break;
   }
   *its = total;
   return PFNKS_OK;
@@ -592,6 +592,10 @@ int pfnks_create_problem(const pfnks_grid* grid, const pfnks_model* model, const
   p->T.ov = solver->overlap;
   p->T.sweeps = solver->sweeps;
   p->T.with_u = 0;
+  if (solver->pc <= PFNKS_PC_RAS_SPECTRAL && pf::ras_npt(p->K, p->T) == 0) {
+    delete p;
+    return PFNKS_EINVAL;  // tile shape beyond what the tile kernel holds per thread
+  }
   auto ptr = [&](int b) { return (double*)(p->ws + L.off[b]); };
   p->kb = krylov_bytes(solver->precision);
   p->X = ptr(B_X);
@@ -604,6 +608,7 @@ int pfnks_create_problem(const pfnks_grid* grid, const pfnks_model* model, const
   p->Bpc = ptr(B_BPC);
   p->G4 = ptr(B_G4);
   p->V = ptr(B_V);
+  p->Zb = ptr(B_ZB);
   p->w = ptr(B_W);
   p->z = ptr(B_Z);
   p->tmp = ptr(B_TMP);
