@@ -146,6 +146,8 @@ def main():
     ap.add_argument("--workload", default="pf2d_512")
     ap.add_argument("--pc", default="ras_spectral", choices=["ras_spectral", "ras"])
     ap.add_argument("--sweeps", type=int, default=2)
+    ap.add_argument("--tile", default=None, help="Schwarz tile, e.g. 32,32 (2D) or 8,8,8 (3D)")
+    ap.add_argument("--overlap", type=int, default=None)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
                     help="mixed: float Krylov basis and Schwarz/Fourier preconditioner, double "
                          "residual, J v arithmetic, Newton update, energy and mass")
@@ -173,6 +175,11 @@ def main():
                   precision=pfnks.MIXED if args.precision == "mixed" else pfnks.FP64)
     if len(n) == 3:
         solver.update(tile=(8, 8, 8), overlap=1)
+    if args.tile:
+        t = tuple(int(v) for v in args.tile.split(","))
+        solver["tile"] = t if len(t) == 3 else (t[0], t[1], 1)
+    if args.overlap is not None:
+        solver["overlap"] = args.overlap
     dev = "cuda:0"
     if args.copy_calibration_mb > 0:
         src = torch.ones(args.copy_calibration_mb * (1 << 20) // 8, dtype=torch.float64, device=dev)

@@ -141,6 +141,14 @@ __device__ inline void fft_lds(double2* buf, int n, int logn, int nl, const doub
 
 __device__ inline int brev(int p, int logn) { return (int)(__brev((unsigned)p) >> (32 - logn)); }
 
+// Workgroups go to the 8 XCDs round-robin by id: block b < nb (nb a multiple of 8) is given
+// index (b mod 8) * (nb / 8) + b / 8, so that each XCD works on a contiguous band; other
+// blocks keep their id.
+__device__ inline int xcd_band(int b, int nb) {
+  if ((nb & 7) != 0 || b >= nb) return b;
+  return (b & 7) * (nb >> 3) + (b >> 3);
+}
+
 // pass 1: rows j0 .. j0+nl-1: q = r_u + a Dhat z_c packed as q_x + i q_y, forward FFT along x
 template <typename T>
 __global__ __launch_bounds__(256) void k_fft2_rows_fwd(Consts K, const T* __restrict__ r, double a,
@@ -149,7 +157,7 @@ __global__ __launch_bounds__(256) void k_fft2_rows_fwd(Consts K, const T* __rest
                                                        double2* __restrict__ out) {
   extern __shared__ double2 sm[];  // nl * n
   const int n = K.nx;
-  const int j0 = blockIdx.x * nl;
+  const int j0 = xcd_band(blockIdx.x, gridDim.x) * nl;
   for (int e = threadIdx.x; e < nl * n; e += blockDim.x) {
     const int l = e / n, i = e - l * n, j = j0 + l;
     const long long m = (long long)i + (long long)n * j;
@@ -179,7 +187,9 @@ __global__ __launch_bounds__(256) void k_fft2_cols_solve(Consts K, int logn, con
   extern __shared__ double2 sm[];  // 2 n, then the output spectra (2 n)
   double2* wo = sm + 2 * K.ny;
   const int n = K.ny, nx = K.nx;
-  const int kx = blockIdx.x;           // 0 .. nx/2
+  // 0 .. nx/2; the first multiple-of-8 blocks in XCD-band order, so that the columns one XCD
+  // reads are adjacent and share cache lines
+  const int kx = xcd_band(blockIdx.x, (gridDim.x - 1) & ~7);
   const int kxm = (kx == 0) ? 0 : nx - kx;
   const int ncol = (kx == kxm) ? 1 : 2;
   for (int e = threadIdx.x; e < ncol * n; e += blockDim.x) {
@@ -228,7 +238,7 @@ __global__ __launch_bounds__(256) void k_fft2_rows_inv(Consts K, int logn, int n
                                                        const double2* __restrict__ in, T* __restrict__ u) {
   extern __shared__ double2 sm[];  // nl * n
   const int n = K.nx;
-  const int j0 = blockIdx.x * nl;
+  const int j0 = xcd_band(blockIdx.x, gridDim.x) * nl;
   for (int e = threadIdx.x; e < nl * n; e += blockDim.x) {
     const int l = e / n, i = e - l * n;
     sm[l * n + brev(i, logn)] = in[(long long)i + (long long)n * (j0 + l)];

@@ -24,10 +24,12 @@ namespace pf {
 
 namespace {
 
-constexpr int kRasThreads = 512;
+// workgroup sizes of the tile kernel: 512 threads, or 256 when the tile fits three nodes per
+// thread and two workgroups fit the LDS of one compute unit (they then overlap their barriers)
+constexpr int kRasThreadsMax = 512, kRasThreadsSmall = 256;
 
-// bound on the dG nodes (extended tile and its ring of one) per thread; the host rejects tile
-// shapes that need more
+// bound on the dG nodes (extended tile and its ring of one) per thread of the batched dG
+// phase; the host rejects tile shapes that need more
 constexpr __host__ __device__ int ras_dg_iters(int dim, int npt) { return dim == 2 ? npt + 1 : npt + 2; }
 
 struct Geo {
@@ -49,15 +51,14 @@ __device__ inline int wrapg(int a, int n) {
 template <typename R>
 constexpr int ras_waves_per_simd() { return sizeof(R) == 4 ? 4 : 2; }
 
-template <int DIM, bool WU, int NPT, typename R>
-__global__ __launch_bounds__(kRasThreads) void k_ras(Consts K, Geo G, double dt,
+template <int DIM, bool WU, int NPT, typename R, int TH>
+__global__ __launch_bounds__(TH, (TH == kRasThreadsSmall) ? 2 : 1) void k_ras(Consts K, Geo G, double dt,
                                                      const R* __restrict__ Bg,
                                                      const double* __restrict__ cn,
                                                      const R* __restrict__ rg,
                                                      R* __restrict__ zg) {
   constexpr int NFZ = WU ? 4 + DIM : 4;
   constexpr int NCOL = (DIM == 3) ? 7 : 5;
-  constexpr int DIT = ras_dg_iters(DIM, NPT);  // dG nodes per thread (ext + ring of 1)
   extern __shared__ double lds_raw[];
   R* lds = reinterpret_cast<R*>(lds_raw);
   const int zsz = G.zx * G.zy * G.zz;
@@ -83,7 +84,7 @@ __global__ __launch_bounds__(kRasThreads) void k_ras(Consts K, Geo G, double dt,
   const int ty_ = G.dx, tz_ = G.dx * G.dy;  // strides of dG / g
   const int ring = 2;
 
-  for (int q = threadIdx.x; q < dsz; q += kRasThreads) {
+  for (int q = threadIdx.x; q < dsz; q += TH) {
     const int a = q % G.dx, b = (q / G.dx) % G.dy, c = q / (G.dx * G.dy);
     const int gi = wrapg(ox + a - 1, K.nx), gj = wrapg(oy + b - 1, K.ny);
     const int gk = (DIM == 3) ? wrapg(oz + c - 1, K.nz) : 0;
@@ -93,7 +94,7 @@ __global__ __launch_bounds__(kRasThreads) void k_ras(Consts K, Geo G, double dt,
   }
   __syncthreads();
   // c-row blocks into LDS
-  for (int q = threadIdx.x; q < ne; q += kRasThreads) {
+  for (int q = threadIdx.x; q < ne; q += TH) {
     const int a = q % G.ex, b = (q / G.ex) % G.ey, c = q / (G.ex * G.ey);
     const int gi = wrapg(ox + a, K.nx), gj = wrapg(oy + b, K.ny);
     const int gk = (DIM == 3) ? wrapg(oz + c, K.nz) : 0;
@@ -106,7 +107,7 @@ __global__ __launch_bounds__(kRasThreads) void k_ras(Consts K, Geo G, double dt,
   // colour-col nodes in the rows before.  (The order inside a colour is immaterial: nodes of
   // one colour do not couple.)
   const int nrow = G.ey * G.ez;
-  for (int idx = threadIdx.x; idx < NCOL * nrow; idx += kRasThreads) {
+  for (int idx = threadIdx.x; idx < NCOL * nrow; idx += TH) {
     const int col = idx / nrow, row = idx % nrow;
     int acc = 0;
     for (int r = 0; r < row; ++r) {
@@ -133,7 +134,7 @@ __global__ __launch_bounds__(kRasThreads) void k_ras(Consts K, Geo G, double dt,
     cstart[NCOL] = acc;
   }
   __syncthreads();
-  for (int q = threadIdx.x; q < ne; q += kRasThreads) {
+  for (int q = threadIdx.x; q < ne; q += TH) {
     const int a = q % G.ex, b = (q / G.ex) % G.ey, c = q / (G.ex * G.ey);
     const int col = (DIM == 3) ? (a + 2 * b + 3 * c) % 7 : (a + 2 * b) % 5;
     const int r0 = ((col - 2 * b - ((DIM == 3) ? 3 * c : 0)) % NCOL + NCOL) % NCOL;
@@ -146,25 +147,29 @@ __global__ __launch_bounds__(kRasThreads) void k_ras(Consts K, Geo G, double dt,
   // then picked up by the thread that owns each node in colour order.
   R rr[NPT][NFZ];
   R be[NPT][12];
-  int zi_[NPT], di_[NPT], q_[NPT], col_[NPT];
+  // per node, packed in 16-bit halves (every index is below 2^16): zd = iterate position |
+  // dG position << 16, qc = ext index | (colour + 1) << 16 (colour -1: no node)
+  int zd_[NPT], qc_[NPT];
+  int col_[NPT];
 #pragma unroll
   for (int m = 0; m < NPT; ++m) {
-    const int pos = threadIdx.x + m * kRasThreads;
+    const int pos = threadIdx.x + m * TH;
     col_[m] = -1;
-    zi_[m] = di_[m] = q_[m] = 0;
+    zd_[m] = qc_[m] = 0;
     if (pos < ne) {
       const int q = perm[pos];
       const int a = q % G.ex, b = (q / G.ex) % G.ey, c = q / (G.ex * G.ey);
-      q_[m] = q;
-      zi_[m] = (a + ring) + sy * (b + ring) + ((DIM == 3) ? sz * (c + ring) : 0);
-      di_[m] = (a + 1) + ty_ * (b + 1) + ((DIM == 3) ? tz_ * (c + 1) : 0);
+      const int zi = (a + ring) + sy * (b + ring) + ((DIM == 3) ? sz * (c + ring) : 0);
+      const int di = (a + 1) + ty_ * (b + 1) + ((DIM == 3) ? tz_ * (c + 1) : 0);
       col_[m] = (DIM == 3) ? (a + 2 * b + 3 * c) % 7 : (a + 2 * b) % 5;
+      zd_[m] = zi | (di << 16);
+      qc_[m] = q;
     }
   }
   constexpr int NPL = NFZ + 12;  // staged planes: r (NFZ), then B rows 1..3 (12)
   for (int p0 = 0; p0 < NPL; p0 += 4) {
     const int np = (NPL - p0 < 4) ? NPL - p0 : 4;
-    for (int q = threadIdx.x; q < ne; q += kRasThreads) {
+    for (int q = threadIdx.x; q < ne; q += TH) {
       const int a = q % G.ex, b = (q / G.ex) % G.ey, c = q / (G.ex * G.ey);
       const int gi = wrapg(ox + a, K.nx), gj = wrapg(oy + b, K.ny);
       const int gk = (DIM == 3) ? wrapg(oz + c, K.nz) : 0;
@@ -182,7 +187,7 @@ __global__ __launch_bounds__(kRasThreads) void k_ras(Consts K, Geo G, double dt,
       for (int k = 0; k < 4; ++k) {
         const int pl = p0 + k;
         if (k >= np) break;
-        const R v = zs[k * ne + q_[m]];
+        const R v = zs[k * ne + qc_[m]];
 #pragma unroll
         for (int f = 0; f < NFZ; ++f)
           if (pl == f) rr[m][f] = v;
@@ -193,7 +198,7 @@ __global__ __launch_bounds__(kRasThreads) void k_ras(Consts K, Geo G, double dt,
     }
     __syncthreads();
   }
-  for (int q = threadIdx.x; q < NFZ * zsz; q += kRasThreads) zs[q] = R(0);
+  for (int q = threadIdx.x; q < NFZ * zsz; q += TH) zs[q] = R(0);
   __syncthreads();
 
   // coefficients in the arithmetic type of the solve (formed in double, rounded once)
@@ -201,7 +206,7 @@ __global__ __launch_bounds__(kRasThreads) void k_ras(Consts K, Geo G, double dt,
   const R ih2 = (R)K.ih2, i2h = (R)K.i2h, kel = (R)K.kel, Le = (R)K.L_eta, eps0 = (R)K.eps0;
   const R C11 = (R)K.C11, C12 = (R)K.C12, C44 = (R)K.C44;
   const R lapc = (R)(-2.0 * DIM * K.ih2);
-  const R hgc = (R)(-0.5 * K.gamma_c), hge = (R)(-0.5 * K.gamma_eta), hk = (R)(0.5 * K.kappa);
+  const R hgc = (R)(-0.5 * K.gamma_c), hk = (R)(0.5 * K.kappa);
   const int sdir_z[3] = {1, sy, sz};
   const int sdir_d[3] = {1, ty_, tz_};
   const R a_u = (R)(-0.5 * K.eps0 * K.Ctr * K.i2h);  // coefficient of the difference of z_u in dG
@@ -210,6 +215,138 @@ __global__ __launch_bounds__(kRasThreads) void k_ras(Consts K, Geo G, double dt,
   const R dee = (R)(1.0 / dt + K.L_eta * K.gamma_eta * DIM * K.ih2);
   const R iduu = (R)(-2.0 * K.h * K.h / (K.C11 + (DIM - 1) * K.C44));
   const R cxu = (R)(K.eps0 * K.Ctr * 0.25 * K.ih2 * K.ih);
+  const R cge = (R)(0.5 * K.L_eta * K.gamma_eta * K.ih2);  // eta-row neighbour coefficient
+  // Per node, the diagonal block of the tile operator (the node's own unknowns) is
+  //   [d_cc  u'  ]      d_cc = 1/dt + sc (B_cc + kel + gamma_c (2 DIM + 1) / (2 h^2)),
+  //   [v     E   ]      u_e = sc B_ce, v_e = L_eta B_ec, E = dee I + L_eta B_ee,
+  // sc = (sum of the 2 DIM face mobilities) / h^2.  It is constant during the sweeps.
+  // block_inverse: E^{-1} (by the adjugate) and w = E^{-1} v from the eta rows bv of B.
+  auto block_inverse = [&](const R* bv, R* Ai, R* w) {
+    const R E00 = dee + Le * bv[1], E01 = Le * bv[2], E02 = Le * bv[3];
+    const R E10 = Le * bv[5], E11 = dee + Le * bv[6], E12 = Le * bv[7];
+    const R E20 = Le * bv[9], E21 = Le * bv[10], E22 = dee + Le * bv[11];
+    const R A00 = E11 * E22 - E12 * E21, A01 = E02 * E21 - E01 * E22, A02 = E01 * E12 - E02 * E11;
+    const R A10 = E12 * E20 - E10 * E22, A11 = E00 * E22 - E02 * E20, A12 = E02 * E10 - E00 * E12;
+    const R A20 = E10 * E21 - E11 * E20, A21 = E01 * E20 - E00 * E21, A22 = E00 * E11 - E01 * E10;
+    const R idet = R(1) / (E00 * A00 + E01 * A10 + E02 * A20);
+    Ai[0] = A00 * idet; Ai[1] = A01 * idet; Ai[2] = A02 * idet;
+    Ai[3] = A10 * idet; Ai[4] = A11 * idet; Ai[5] = A12 * idet;
+    Ai[6] = A20 * idet; Ai[7] = A21 * idet; Ai[8] = A22 * idet;
+    const R v1 = Le * bv[0], v2 = Le * bv[4], v3 = Le * bv[8];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) w[e] = Ai[3 * e] * v1 + Ai[3 * e + 1] * v2 + Ai[3 * e + 2] * v3;
+  };
+  // Float tiles keep E^{-1}, w and 1 / (d_cc - u'w) per node in registers (formed once);
+  // double tiles keep the 12 eta-row entries of B instead and form them in every update
+  // (the precomputed form does not fit the registers of three double nodes per thread).
+  constexpr bool kPre = sizeof(R) == 4;
+  constexpr int NPRE = kPre ? NPT : 1;
+  R ai[NPRE][9], wq[NPRE][3], invd[NPRE];
+  if constexpr (kPre) {
+#pragma unroll
+    for (int m = 0; m < NPT; ++m) {
+      block_inverse(be[m], ai[m], wq[m]);
+      invd[m] = R(0);
+      if (col_[m] >= 0) {
+        const int di = zd_[m] >> 16, q = qc_[m];
+        const R g0 = gg[di];
+        R sumM = R(0);
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) sumM += hk * (g0 + gg[di + sdir_d[d]]) + hk * (g0 + gg[di - sdir_d[d]]);
+        const R sc = sumM * ih2;
+        const R dcc = dcc0 + sc * (bc[q] + dcc1);
+        const R uw = sc * (bc[ne + q] * wq[m][0] + bc[2 * ne + q] * wq[m][1] + bc[3 * ne + q] * wq[m][2]);
+        invd[m] = R(1) / (dcc - uw);
+      }
+    }
+  }
+
+  // Block Gauss-Seidel update of one node.  The eta rows are taken in Gauss-Seidel form:
+  // with rhs_e = r_e + (L_eta gamma_eta / (2 h^2)) (sum of the 2 DIM neighbours of z_e) the
+  // new values satisfy E z_e' + v z_c' = rhs_e, so z_e' = y - w z_c' with y = E^{-1} rhs_e.
+  // The c row is taken in correction form, x_c = (res_c - u'E^{-1} res_e) / (d_cc - u'w) with
+  // E^{-1} res_e = y - z_e - w z_c; the displacement rows (with_u) by their diagonal.
+  auto update_node = [&](const R* rv, const R* Ai, const R* w, R id, int zi, int di, int q) {
+    R zv[NFZ];
+#pragma unroll
+    for (int f = 0; f < NFZ; ++f) zv[f] = zs[f * zsz + zi];
+    // c row residual: r_c - (z_c/dt - div_h(M grad_h dG))
+    R sumM = R(0), dM[3] = {R(0), R(0), R(0)};
+    R divm = R(0);
+    const R g0 = gg[di], dg0 = dg[di];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const R Mp = hk * (g0 + gg[di + sdir_d[d]]);
+      const R Mm = hk * (g0 + gg[di - sdir_d[d]]);
+      divm += Mp * (dg[di + sdir_d[d]] - dg0) - Mm * (dg0 - dg[di - sdir_d[d]]);
+      sumM += Mp + Mm;
+      dM[d] = Mm - Mp;
+    }
+    R xc = rv[0] - (zv[0] * idt - divm * ih2);
+    // eta rows: y = E^{-1} rhs_e
+    R rh[3];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+      const int ze = (1 + e) * zsz + zi;
+      R nb = R(0);
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) nb += zs[ze + sdir_z[d]] + zs[ze - sdir_z[d]];
+      rh[e] = rv[1 + e] + cge * nb;
+    }
+    R y[3];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) y[e] = Ai[3 * e] * rh[0] + Ai[3 * e + 1] * rh[1] + Ai[3 * e + 2] * rh[2];
+    // u rows: x_u = (r_u - sum_J Dhat_J sigma_IJ(z_u, z_c)) / d_uu, and their coupling into the c row
+    R xu[3] = {R(0), R(0), R(0)};
+    if (WU) {
+#pragma unroll
+      for (int I = 0; I < DIM; ++I) {
+        R acc = R(0);
+#pragma unroll
+        for (int J = 0; J < DIM; ++J) {
+#pragma unroll
+          for (int sgn = -1; sgn <= 1; sgn += 2) {
+            const int pz = zi + sgn * sdir_z[J];
+            R sig;
+            if (I != J) {
+              sig = C44 * ((zs[(4 + J) * zsz + pz + sdir_z[I]] - zs[(4 + J) * zsz + pz - sdir_z[I]]) +
+                           (zs[(4 + I) * zsz + pz + sdir_z[J]] - zs[(4 + I) * zsz + pz - sdir_z[J]])) * i2h;
+            } else {
+              const R ec = eps0 * zs[pz];
+              sig = R(0);
+#pragma unroll
+              for (int L = 0; L < DIM; ++L) {
+                const R e = (zs[(4 + L) * zsz + pz + sdir_z[L]] - zs[(4 + L) * zsz + pz - sdir_z[L]]) * i2h - ec;
+                sig += (L == I ? C11 : C12) * e;
+              }
+            }
+            acc += (sgn > 0) ? sig : -sig;
+          }
+        }
+        xu[I] = (rv[4 + I] - acc * i2h) * iduu;
+        xc -= cxu * dM[I] * xu[I];
+      }
+    }
+    const R sc = sumM * ih2;
+    R t = R(0);
+#pragma unroll
+    for (int e = 0; e < 3; ++e) t += bc[(1 + e) * ne + q] * (y[e] - zv[1 + e] - w[e] * zv[0]);
+    if (kPre) {
+      xc = (xc - sc * t) * id;
+    } else {
+      const R uw = sc * (bc[ne + q] * w[0] + bc[2 * ne + q] * w[1] + bc[3 * ne + q] * w[2]);
+      xc = (xc - sc * t) / (dcc0 + sc * (bc[q] + dcc1) - uw);
+    }
+    const R zc = zv[0] + xc;
+    zs[zi] = zc;
+#pragma unroll
+    for (int e = 0; e < 3; ++e) zs[(1 + e) * zsz + zi] = y[e] - w[e] * zc;
+    if (WU) {
+#pragma unroll
+      for (int I = 0; I < DIM; ++I) zs[(4 + I) * zsz + zi] = zv[4 + I] + xu[I];
+    }
+  };
+
   // dG at iterate position pz; qe: c-row block index, -1 on the ring of width 1 (where only
   // the Laplacian term enters)
   auto dg_at = [&](int pz, int qe) -> R {
@@ -237,16 +374,17 @@ __global__ __launch_bounds__(kRasThreads) void k_ras(Consts K, Geo G, double dt,
     qe = inside ? (a - 1) + G.ex * ((b - 1) + ((DIM == 3) ? G.ey * (c - 1) : 0)) : -1;
   };
   // The dG phase either keeps this thread's dG nodes precomputed (packed pz | (qe + 1) << 16,
-  // pz < 2^16 since the iterate holds fewer than 2^14 nodes) and forms all values before the
-  // stores, so that their LDS loads are in flight together (stores to dg could otherwise alias
-  // them), or walks its nodes one at a time with fewer live registers: the float 3D tile needs
-  // the latter to keep two workgroups resident per compute unit.
+  // pz < 2^16) and forms all their values before the stores, so that their LDS loads are in
+  // flight together (stores to dg could otherwise alias them), or walks its nodes one at a
+  // time with fewer live registers: the float 3D tile needs the latter to keep two workgroups
+  // resident per compute unit.
   constexpr bool kBatch = !(DIM == 3 && sizeof(R) == 4);
-  int dpq[kBatch ? DIT : 1];
+  constexpr int DIT = kBatch ? ras_dg_iters(DIM, NPT) : 1;
+  int dpq[DIT];
   if constexpr (kBatch) {
 #pragma unroll
     for (int it = 0; it < DIT; ++it) {
-      const int qd = threadIdx.x + it * kRasThreads;
+      const int qd = threadIdx.x + it * TH;
       dpq[it] = -1;
       if (qd < dsz) {
         int pz, qe;
@@ -270,9 +408,9 @@ __global__ __launch_bounds__(kRasThreads) void k_ras(Consts K, Geo G, double dt,
               sgv[it] = (dpq[it] < 0) ? R(0) : dg_at(dpq[it] & 0xffff, (dpq[it] >> 16) - 1);
 #pragma unroll
             for (int it = 0; it < DIT; ++it)
-              if (dpq[it] >= 0) dg[threadIdx.x + it * kRasThreads] = sgv[it];
+              if (dpq[it] >= 0) dg[threadIdx.x + it * TH] = sgv[it];
           } else {
-            for (int qd = threadIdx.x; qd < dsz; qd += kRasThreads) {
+            for (int qd = threadIdx.x; qd < dsz; qd += TH) {
               int pz, qe;
               dg_node(qd, pz, qe);
               dg[qd] = dg_at(pz, qe);
@@ -289,129 +427,51 @@ __global__ __launch_bounds__(kRasThreads) void k_ras(Consts K, Geo G, double dt,
         for (int m = 0; m < NPT; ++m)
           if (col_[m] == col) msel = m;
         if (msel >= 0) {
-          R rv[NFZ], bv[12];
+          R rv[NFZ], av[9], wv[3], idv = R(0);
+          int zd = zd_[0], q = qc_[0];
 #pragma unroll
-          for (int f = 0; f < NFZ; ++f) {
-            rv[f] = rr[0][f];
-#pragma unroll
-            for (int m = 1; m < NPT; ++m) rv[f] = (msel == m) ? rr[m][f] : rv[f];
-          }
-#pragma unroll
-          for (int f = 0; f < 12; ++f) {
-            bv[f] = be[0][f];
-#pragma unroll
-            for (int m = 1; m < NPT; ++m) bv[f] = (msel == m) ? be[m][f] : bv[f];
-          }
-          int zi = zi_[0], di = di_[0], q = q_[0];
+          for (int f = 0; f < NFZ; ++f) rv[f] = rr[0][f];
 #pragma unroll
           for (int m = 1; m < NPT; ++m) {
-            zi = (msel == m) ? zi_[m] : zi;
-            di = (msel == m) ? di_[m] : di;
-            q = (msel == m) ? q_[m] : q;
+            const bool sel = (msel == m);
+#pragma unroll
+            for (int f = 0; f < NFZ; ++f) rv[f] = sel ? rr[m][f] : rv[f];
+            zd = sel ? zd_[m] : zd;
+            q = sel ? qc_[m] : q;
           }
-          R zv[NFZ];
+          if constexpr (kPre) {
+            idv = invd[0];
 #pragma unroll
-          for (int f = 0; f < NFZ; ++f) zv[f] = zs[f * zsz + zi];
-          R res[NFZ];
-          // c row: z_c/dt - div_h(M grad_h dG)
-          R sumM = R(0), dM[3] = {R(0), R(0), R(0)};
-          R divm = R(0);
-          const R g0 = gg[di], dg0 = dg[di];
+            for (int k = 0; k < 9; ++k) av[k] = ai[0][k];
 #pragma unroll
-          for (int d = 0; d < DIM; ++d) {
-            const R Mp = hk * (g0 + gg[di + sdir_d[d]]);
-            const R Mm = hk * (g0 + gg[di - sdir_d[d]]);
-            divm += Mp * (dg[di + sdir_d[d]] - dg0) - Mm * (dg0 - dg[di - sdir_d[d]]);
-            sumM += Mp + Mm;
-            dM[d] = Mm - Mp;
-          }
-          res[0] = rv[0] - (zv[0] * idt - divm * ih2);
-          // eta rows: z_e/dt + L_eta (B_e . z - (gamma_eta/2) Lap_h z_e)
+            for (int e = 0; e < 3; ++e) wv[e] = wq[0][e];
 #pragma unroll
-          for (int e = 0; e < 3; ++e) {
-            const int ze = (1 + e) * zsz + zi;
-            R l = lapc * zv[1 + e];
+            for (int m = 1; m < NPT; ++m) {
+              const bool sel = (msel == m);
 #pragma unroll
-            for (int d = 0; d < DIM; ++d) l += (zs[ze + sdir_z[d]] + zs[ze - sdir_z[d]]) * ih2;
-            R s = hge * l;
+              for (int k = 0; k < 9; ++k) av[k] = sel ? ai[m][k] : av[k];
 #pragma unroll
-            for (int f = 0; f < 4; ++f) s += bv[4 * e + f] * zv[f];
-            res[1 + e] = rv[1 + e] - (zv[1 + e] * idt + Le * s);
-          }
-          // u rows: sum_J Dhat_J sigma_IJ(z_u, z_c)
-          if (WU) {
-#pragma unroll
-            for (int I = 0; I < DIM; ++I) {
-              R acc = R(0);
-#pragma unroll
-              for (int J = 0; J < DIM; ++J) {
-#pragma unroll
-                for (int sgn = -1; sgn <= 1; sgn += 2) {
-                  const int pz = zi + sgn * sdir_z[J];
-                  R sig;
-                  if (I != J) {
-                    sig = C44 * ((zs[(4 + J) * zsz + pz + sdir_z[I]] - zs[(4 + J) * zsz + pz - sdir_z[I]]) +
-                                 (zs[(4 + I) * zsz + pz + sdir_z[J]] - zs[(4 + I) * zsz + pz - sdir_z[J]])) * i2h;
-                  } else {
-                    const R ec = eps0 * zs[pz];
-                    sig = R(0);
-#pragma unroll
-                    for (int L = 0; L < DIM; ++L) {
-                      const R e = (zs[(4 + L) * zsz + pz + sdir_z[L]] - zs[(4 + L) * zsz + pz - sdir_z[L]]) * i2h - ec;
-                      sig += (L == I ? C11 : C12) * e;
-                    }
-                  }
-                  acc += (sgn > 0) ? sig : -sig;
-                }
-              }
-              res[4 + I] = rv[4 + I] - acc * i2h;
+              for (int e = 0; e < 3; ++e) wv[e] = sel ? wq[m][e] : wv[e];
+              idv = sel ? invd[m] : idv;
             }
-          }
-          // diagonal block of the node, solved through the Schur complement on c:
-          //   [d_cc  u'] [x_c]   [r_c]      E = dee I + L_eta B_ee (3 x 3, dominated by 1/dt)
-          //   [v     E ] [x_e] = [r_e],     x_c = (r_c - u'E^{-1} r_e) / (d_cc - u'E^{-1} v)
-          const R sc = sumM * ih2;
-          R xc = res[0];
-          if (WU) {
+          } else {
+            R bv[12];
 #pragma unroll
-            for (int I = 0; I < DIM; ++I) {
-              res[4 + I] *= iduu;  // x_u
-              xc -= cxu * dM[I] * res[4 + I];
-            }
-          }
-          const R E00 = dee + Le * bv[1], E01 = Le * bv[2], E02 = Le * bv[3];
-          const R E10 = Le * bv[5], E11 = dee + Le * bv[6], E12 = Le * bv[7];
-          const R E20 = Le * bv[9], E21 = Le * bv[10], E22 = dee + Le * bv[11];
-          const R A00 = E11 * E22 - E12 * E21, A01 = E02 * E21 - E01 * E22, A02 = E01 * E12 - E02 * E11;
-          const R A10 = E12 * E20 - E10 * E22, A11 = E00 * E22 - E02 * E20, A12 = E02 * E10 - E00 * E12;
-          const R A20 = E10 * E21 - E11 * E20, A21 = E01 * E20 - E00 * E21, A22 = E00 * E11 - E01 * E10;
-          const R idet = R(1) / (E00 * A00 + E01 * A10 + E02 * A20);
-          // y = E^{-1} r_e, w = E^{-1} v  (v_e = L_eta B_e,c)
-          const R r1 = res[1], r2 = res[2], r3 = res[3];
-          const R v1 = Le * bv[0], v2 = Le * bv[4], v3 = Le * bv[8];
-          const R y1 = (A00 * r1 + A01 * r2 + A02 * r3) * idet;
-          const R y2 = (A10 * r1 + A11 * r2 + A12 * r3) * idet;
-          const R y3 = (A20 * r1 + A21 * r2 + A22 * r3) * idet;
-          const R w1 = (A00 * v1 + A01 * v2 + A02 * v3) * idet;
-          const R w2 = (A10 * v1 + A11 * v2 + A12 * v3) * idet;
-          const R w3 = (A20 * v1 + A21 * v2 + A22 * v3) * idet;
-          const R u1 = sc * bc[ne + q], u2 = sc * bc[2 * ne + q], u3 = sc * bc[3 * ne + q];
-          const R dcc = dcc0 + sc * (bc[q] + dcc1);
-          xc = (xc - (u1 * y1 + u2 * y2 + u3 * y3)) / (dcc - (u1 * w1 + u2 * w2 + u3 * w3));
-          const R x[4] = {xc, y1 - w1 * xc, y2 - w2 * xc, y3 - w3 * xc};
+            for (int f = 0; f < 12; ++f) bv[f] = be[0][f];
 #pragma unroll
-          for (int f = 0; f < 4; ++f) zs[f * zsz + zi] = zv[f] + x[f];
-          if (WU) {
+            for (int m = 1; m < NPT; ++m)
 #pragma unroll
-            for (int I = 0; I < DIM; ++I) zs[(4 + I) * zsz + zi] = zv[4 + I] + res[4 + I];
+              for (int f = 0; f < 12; ++f) bv[f] = (msel == m) ? be[m][f] : bv[f];
+            block_inverse(bv, av, wv);
           }
+          update_node(rv, av, wv, idv, zd & 0xffff, zd >> 16, q);
         }
         __syncthreads();
       }
     }
   }
   // restricted prolongation: write the owned nodes only (coalesced, row-major)
-  for (int q = threadIdx.x; q < ne; q += kRasThreads) {
+  for (int q = threadIdx.x; q < ne; q += TH) {
     const int a = q % G.ex, b = (q / G.ex) % G.ey, c = q / (G.ex * G.ey);
     if (a < G.ov || a >= G.ov + G.tx || b < G.ov || b >= G.ov + G.ty) continue;
     if (DIM == 3 && (c < G.ov || c >= G.ov + G.tz)) continue;
@@ -445,15 +505,14 @@ Geo make_geo(const Consts& K, const TileCfg& T) {
   return G;
 }
 
-template <int DIM, bool WU, typename R>
-void launch_dim(const Consts& K, const Geo& G, size_t lds, int ntiles, int npt, double dt,
-                const R* B, const double* cn, const R* r, R* z, hipStream_t s) {
-#define PF_RAS_CASE(NPTV)                                                                          \
-  case NPTV:                                                                                       \
-    (void)hipFuncSetAttribute((const void*)k_ras<DIM, WU, NPTV, R>,                                   \
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                    \
-    hipLaunchKernelGGL((k_ras<DIM, WU, NPTV, R>), dim3(ntiles), dim3(kRasThreads), lds, s, K, G, dt, \
-                       B, cn, r, z);                                                               \
+template <int DIM, bool WU, typename R, int TH>
+void launch_npt(const Geo& G, const Consts& K, size_t lds, int ntiles, int npt, double dt, const R* B,
+                const double* cn, const R* r, R* z, hipStream_t s) {
+#define PF_RAS_CASE(NPTV)                                                                             \
+  case NPTV:                                                                                          \
+    (void)hipFuncSetAttribute((const void*)k_ras<DIM, WU, NPTV, R, TH>,                              \
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                  \
+    hipLaunchKernelGGL((k_ras<DIM, WU, NPTV, R, TH>), dim3(ntiles), dim3(TH), lds, s, K, G, dt, B, cn, r, z); \
     break;
   switch (npt) {
     PF_RAS_CASE(1)
@@ -462,6 +521,25 @@ void launch_dim(const Consts& K, const Geo& G, size_t lds, int ntiles, int npt, 
       PF_RAS_CASE(3)
   }
 #undef PF_RAS_CASE
+}
+
+template <int DIM, bool WU, typename R>
+void launch_dim(const Consts& K, const Geo& G, size_t lds, int ntiles, int th, int npt, double dt,
+                const R* B, const double* cn, const R* r, R* z, hipStream_t s) {
+  if (!WU && th == kRasThreadsSmall)
+    launch_npt<DIM, false, R, kRasThreadsSmall>(G, K, lds, ntiles, npt, dt, B, cn, r, z, s);
+  else
+    launch_npt<DIM, WU, R, kRasThreadsMax>(G, K, lds, ntiles, npt, dt, B, cn, r, z, s);
+}
+
+// nodes of the extended tile per thread (1..3) at th threads, 0 if the tile does not fit
+// (more than three nodes per thread, or more dG nodes than the batched dG phase holds)
+int npt_for(int dim, const Geo& G, int th) {
+  const int ne = G.ex * G.ey * G.ez;
+  const int npt = (ne + th - 1) / th;
+  const int dsz = G.dx * G.dy * G.dz;
+  if (npt > 3 || (dsz + th - 1) / th > ras_dg_iters(dim, npt)) return 0;
+  return npt;
 }
 
 }  // namespace
@@ -475,15 +553,16 @@ size_t ras_lds_bytes(const Consts& K, const TileCfg& T, size_t real_bytes) {
          sizeof(int) * (ne + ncol * G.ey * G.ez);
 }
 
-// nodes of the extended tile per thread (1..3), 0 if the tile does not fit (more than three
-// nodes per thread, or more dG nodes than the kernel's unrolled loop holds)
-int ras_npt(const Consts& K, const TileCfg& T) {
+int ras_threads(const Consts& K, const TileCfg& T, size_t real_bytes, int* npt) {
   const Geo G = make_geo(K, T);
-  const int ne = G.ex * G.ey * G.ez;
-  const int npt = (ne + kRasThreads - 1) / kRasThreads;
-  const int dsz = G.dx * G.dy * G.dz;
-  if (npt > 3 || (dsz + kRasThreads - 1) / kRasThreads > ras_dg_iters(K.dim, npt)) return 0;
-  return npt;
+  const int ns = npt_for(K.dim, G, kRasThreadsSmall);
+  if (!T.with_u && ns > 0 && 2 * ras_lds_bytes(K, T, real_bytes) <= 160 * 1024) {
+    if (npt) *npt = ns;
+    return kRasThreadsSmall;
+  }
+  const int nm = npt_for(K.dim, G, kRasThreadsMax);
+  if (npt) *npt = nm;
+  return nm > 0 ? kRasThreadsMax : 0;
 }
 
 template <typename R>
@@ -492,13 +571,14 @@ void launch_ras(const Consts& K, const TileCfg& T, double dt, const R* B, const 
   const Geo G = make_geo(K, T);
   const int ntiles = G.ntx * G.nty * ((K.dim == 3) ? K.nz / T.tz : 1);
   const size_t lds = ras_lds_bytes(K, T, sizeof(R));
-  const int npt = ras_npt(K, T);
+  int npt = 0;
+  const int th = ras_threads(K, T, sizeof(R), &npt);
   if (K.dim == 2) {
-    if (T.with_u) launch_dim<2, true, R>(K, G, lds, ntiles, npt, dt, B, cn, r, z, s);
-    else launch_dim<2, false, R>(K, G, lds, ntiles, npt, dt, B, cn, r, z, s);
+    if (T.with_u) launch_dim<2, true, R>(K, G, lds, ntiles, th, npt, dt, B, cn, r, z, s);
+    else launch_dim<2, false, R>(K, G, lds, ntiles, th, npt, dt, B, cn, r, z, s);
   } else {
-    if (T.with_u) launch_dim<3, true, R>(K, G, lds, ntiles, npt, dt, B, cn, r, z, s);
-    else launch_dim<3, false, R>(K, G, lds, ntiles, npt, dt, B, cn, r, z, s);
+    if (T.with_u) launch_dim<3, true, R>(K, G, lds, ntiles, th, npt, dt, B, cn, r, z, s);
+    else launch_dim<3, false, R>(K, G, lds, ntiles, th, npt, dt, B, cn, r, z, s);
   }
 }
 template void launch_ras<double>(const Consts&, const TileCfg&, double, const double*, const double*,

@@ -60,8 +60,9 @@ template <typename R>
 void launch_ras(const Consts& K, const TileCfg& T, double dt, const R* B, const double* cn,
                 const R* r, R* z, hipStream_t s);
 size_t ras_lds_bytes(const Consts& K, const TileCfg& T, size_t real_bytes);
-// nodes of the extended tile per thread of the tile kernel (1..3); 0: shape not supported
-int ras_npt(const Consts& K, const TileCfg& T);
+// workgroup size of the tile kernel for this tile shape and element size (0: shape not
+// supported); *npt (may be null): nodes of the extended tile per thread
+int ras_threads(const Consts& K, const TileCfg& T, size_t real_bytes, int* npt);
 
 // ---- spectral displacement solve (kernels_fft.hip) -----------------------------------
 struct FftPlan {

@@ -592,7 +592,9 @@ int pfnks_create_problem(const pfnks_grid* grid, const pfnks_model* model, const
   p->T.ov = solver->overlap;
   p->T.sweeps = solver->sweeps;
   p->T.with_u = 0;
-  if (solver->pc <= PFNKS_PC_RAS_SPECTRAL && pf::ras_npt(p->K, p->T) == 0) {
+  pf::TileCfg tcheck = p->T;
+  tcheck.with_u = (solver->pc == PFNKS_PC_RAS) ? 1 : 0;
+  if (solver->pc <= PFNKS_PC_RAS_SPECTRAL && pf::ras_threads(p->K, tcheck, krylov_bytes(solver->precision), nullptr) == 0) {
     delete p;
     return PFNKS_EINVAL;  // tile shape beyond what the tile kernel holds per thread
   }

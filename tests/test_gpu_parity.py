@@ -249,6 +249,27 @@ def test_step_parity_pf2d_64(oracle_c1, pc, prec):
     p.close()
 
 
+@pytest.mark.parametrize("tile,prec", [((16, 32), "fp64"), ((32, 16), "fp64"), ((16, 16), "fp64"),
+                                       ((16, 32), "mixed"), ((8, 8), "fp64")])
+def test_step_parity_tile_shapes(oracle_c1, tile, prec):
+    """2D 64 x 64, 3 steps with other Schwarz tile shapes (they select the 256-thread tile
+    kernel and other nodes-per-thread counts): within 1e-8 of the oracle's root."""
+    from paper_2209_08001_amd import pfnks
+
+    _cuda()
+    c0, e0, traj, info, o = oracle_c1
+    _note(f"step parity pf2d_64 tile={tile} precision={prec}")
+    p = _problem((64, 64), c0, e0, tile=(tile[0], tile[1], 1),
+                 precision=pfnks.MIXED if prec == "mixed" else pfnks.FP64)
+    for k in range(3):
+        st = p.step(0.01)
+        X, _ = p.get_state()
+        errs = [_relmax(X[f], traj[k + 1][f]) for f in range(X.shape[0])]
+        _note(f"  step {k}: newton={st['newton_its']} gmres={st['gmres_its']} max err={max(errs):.2e}")
+        assert max(errs) <= 1e-8, (k, errs)
+    p.close()
+
+
 def test_enoconv_leaves_state():
     """A step forced to fail (one Newton iteration allowed, huge dt) returns ENOCONV and
     leaves the state and time untouched."""
