@@ -25,33 +25,6 @@ METRIC = "Newton time steps/s + HBM GB/s % peak at 1e-8 rel err; p50/p99 step la
 HBM_PEAK_GBS = 8000.0
 
 
-def adaptive_run(p, nsteps, wl, pf, record=None):
-    """Section 4 driver: predict dt from the previous step's change rate, retry on ENOCONV."""
-    dt_min, dt_max, zeta = wl["dt_min"], wl["dt_max"], wl["zeta"]
-    rate = None
-    lat = []
-    stats = []
-    for _ in range(nsteps):
-        dt = dt_min if rate is None else max(dt_min, dt_max / math.sqrt(1.0 + zeta * rate * rate))
-        t0 = time.perf_counter()
-        retries = 0
-        while True:
-            status, st = p.try_step(dt)
-            if status == pf.PFNKS_OK:
-                break
-            dt /= math.sqrt(2.0)
-            zeta *= 2.0
-            retries += 1
-            if dt < dt_min * 2.0 ** -6:
-                raise RuntimeError("adaptive driver: step failed down to the dt floor")
-        lat.append(time.perf_counter() - t0)
-        st["dt"] = dt
-        st["retries"] = retries
-        stats.append(st)
-        rate = st["dx_rms"] / dt
-    return lat, stats
-
-
 # source file of each kernel kind; a stored traffic figure is used only while that file is
 # byte-identical to the one it was measured with
 KERNEL_SOURCE = {"residual": "kernels_phase.hip", "linearise": "kernels_phase.hip", "jv": "kernels_phase.hip",
@@ -138,6 +111,75 @@ def cpu_baseline(wl_name, budget_s=30.0):
     }
 
 
+def run_ensemble(args, wl):
+    """Ensemble workload: every instance takes K adaptive steps; the instances are stepped
+    together (pfnks_batch_step, one stream per instance).  value = instance steps per second
+    over the whole ensemble."""
+    import torch
+
+    from paper_2209_08001_amd import pfnks
+    from paper_2209_08001_amd import workloads as W
+    from paper_2209_08001_amd.driver import adaptive_batch_run
+
+    members = W.ensemble_members(wl)
+    solver = dict(W.DEFAULT_SOLVER, sweeps=args.sweeps,
+                  pc=pfnks.PC_RAS if args.pc == "ras" else pfnks.PC_RAS_SPECTRAL,
+                  precision=pfnks.MIXED if args.precision == "mixed" else pfnks.FP64)
+    dev = "cuda:0"
+
+    def make(ms):
+        out = []
+        for m in ms:
+            c0, e0 = W.init_fields(m["n"], m["seed"], cbar=m["cbar"])
+            out.append(pfnks.Problem(m["n"], W.H, W.DEFAULT_MODEL, solver, c0, e0, device=dev,
+                                     stream=torch.cuda.Stream(device=dev)))
+        return out
+
+    if args.warmup > 0:
+        scratch = make(members[:8])
+        adaptive_batch_run(scratch, args.warmup, wl, args.threads)
+        for p in scratch:
+            p.close()
+        del scratch
+    probs = make(members)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat, stats = adaptive_batch_run(probs, args.steps, wl, args.threads)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    k = len(probs)
+    nodes = sum(p.N for p in probs)
+    newton = sum(s["newton_its"] for ss in stats for s in ss)
+    gmres = sum(s["gmres_its"] for ss in stats for s in ss)
+    out = {
+        "metric": "ensemble Newton time steps/s (instance steps, all instances)",
+        "value": k * args.steps / elapsed,
+        "unit": "instance steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f64+f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "instances": k, "total_nodes": nodes,
+                   "sides": sorted({p.n[0] for p in probs}), "precision": args.precision,
+                   "preconditioner": args.pc, "host_threads": args.threads},
+        "node_steps_per_s": nodes * args.steps / elapsed,
+        "p50_round_ms": 1e3 * percentile(lat, 50),
+        "p99_round_ms": 1e3 * percentile(lat, 99),
+        "newton_per_step": newton / (k * args.steps),
+        "gmres_per_newton": gmres / max(newton, 1),
+        "retries": sum(s["retries"] for ss in stats for s in ss),
+        "roofline": None,
+    }
+    for p in probs:
+        p.close()
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -153,6 +195,8 @@ def main():
                          "residual, J v arithmetic, Newton update, energy and mass")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--threads", type=int, default=16,
+                    help="ensemble workloads: host threads driving the instances (pfnks_batch_step)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="before the run, copy a device buffer of this many MiB once (a plain copy "
                          "kernel of known size, to scale the FETCH_SIZE / WRITE_SIZE counters)")
@@ -166,8 +210,11 @@ def main():
 
     from paper_2209_08001_amd import pfnks
     from paper_2209_08001_amd import workloads as W
+    from paper_2209_08001_amd.driver import adaptive_run
 
     wl = W.WORKLOADS[args.workload]
+    if wl.get("ensemble"):
+        return run_ensemble(args, wl)
     n = wl["n"]
     c0, e0 = W.init_fields(n, wl["seed"], cbar=wl["cbar"])
     solver = dict(W.DEFAULT_SOLVER, sweeps=args.sweeps,
@@ -194,7 +241,7 @@ def main():
     if args.warmup > 0:
         pw = pfnks.Problem(n, W.H, W.DEFAULT_MODEL, solver, c0, e0, device=dev)
         pw.profile(True)
-        adaptive_run(pw, args.warmup, wl, pfnks)
+        adaptive_run(pw, args.warmup, wl)
         table = pw.kernel_table()
         if table:
             dominant = max(table, key=lambda k: table[k]["total_ms"])
@@ -208,7 +255,7 @@ def main():
     E0 = p.energy()[0]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    lat, stats = adaptive_run(p, args.steps, wl, pfnks)
+    lat, stats = adaptive_run(p, args.steps, wl)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
 

@@ -140,6 +140,18 @@ int pfnks_create_problem(const pfnks_grid* grid, const pfnks_model* model,
  * with a smaller dt).  Errors: PFNKS_EINVAL (dt <= 0), PFNKS_ENOCONV, PFNKS_EDEVICE. */
 int pfnks_step(pfnks_problem* p, double dt, pfnks_step_stats* stats);
 
+/* One step of each of k independent problems (an ensemble), dts[i] for problem i, run
+ * concurrently: host threads (at most `threads`, 0 = min(k, 16)) take problems from a shared
+ * counter and call pfnks_step on them, so each problem's kernels go to the stream it was
+ * created with; problems on distinct streams overlap on the GPU.  Every problem must appear
+ * once (a handle is not used by two threads).  stats (may be NULL) and status (may be NULL)
+ * receive k records.  Each problem's result is bitwise the result of pfnks_step on it alone.
+ * Returns PFNKS_OK when every step succeeded, else the status of the first failing index
+ * (PFNKS_ENOCONV steps leave their problem unchanged, the others advance).
+ * Errors: PFNKS_EINVAL (null arrays, k < 0, a handle given twice). */
+int pfnks_batch_step(pfnks_problem* const* problems, int k, const double* dts, int threads,
+                     pfnks_step_stats* stats, int* status);
+
 /* Discrete free energy E~ of eqs. (relations)/(freeenergy) at the current state; parts
  * (may be NULL) receives (chemical E1+E2, elastic E3, interfacial E4). */
 int pfnks_energy(pfnks_problem* p, double* total, double parts[3]);

@@ -21,6 +21,7 @@ FLAGS = [
     "-O3",
     "-std=c++17",
     "-fPIC",
+    "-pthread",
     "-shared",
     "-Wall",
     "-Wno-unused-function",
@@ -53,7 +54,7 @@ def build(verbose=True):
     if failed:
         raise RuntimeError("hipcc failed")
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", "-o", tmp] + objs
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
     return LIB

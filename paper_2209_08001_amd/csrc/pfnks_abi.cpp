@@ -6,10 +6,13 @@
 // the step close; all vectors stay in the caller's device workspace.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/pfnks.h"
@@ -783,6 +786,40 @@ int pfnks_step(pfnks_problem* p, double dt, pfnks_step_stats* stats) {
   st.status = PFNKS_OK;
   if (stats) *stats = st;
   return PFNKS_OK;
+}
+
+int pfnks_batch_step(pfnks_problem* const* problems, int k, const double* dts, int threads,
+                     pfnks_step_stats* stats, int* status) {
+  if (!problems || !dts || k < 0 || threads < 0) return PFNKS_EINVAL;
+  for (int i = 0; i < k; ++i) {
+    if (!problems[i]) return PFNKS_EINVAL;
+    for (int j = 0; j < i; ++j)
+      if (problems[j] == problems[i]) return PFNKS_EINVAL;
+  }
+  std::vector<int> st(k, PFNKS_OK);
+  std::atomic<int> next{0};
+  auto work = [&]() {
+    for (;;) {
+      const int i = next.fetch_add(1);
+      if (i >= k) break;
+      st[i] = pfnks_step(problems[i], dts[i], stats ? &stats[i] : nullptr);
+    }
+  };
+  const int nth = std::min(k, threads > 0 ? threads : 16);
+  if (nth <= 1) {
+    work();
+  } else {
+    std::vector<std::thread> pool;
+    pool.reserve(nth);
+    for (int t = 0; t < nth; ++t) pool.emplace_back(work);
+    for (auto& t : pool) t.join();
+  }
+  int first = PFNKS_OK;
+  for (int i = 0; i < k; ++i) {
+    if (status) status[i] = st[i];
+    if (first == PFNKS_OK && st[i] != PFNKS_OK) first = st[i];
+  }
+  return first;
 }
 
 int pfnks_energy(pfnks_problem* p, double* total, double parts[3]) {

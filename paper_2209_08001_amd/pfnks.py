@@ -33,7 +33,7 @@ EXPORTED = [
     "pfnks_workspace_bytes", "pfnks_create_problem", "pfnks_step", "pfnks_energy", "pfnks_mass",
     "pfnks_get_state", "pfnks_set_state", "pfnks_destroy", "pfnks_strerror", "pfnks_last_error",
     "pfnks_debug_residual", "pfnks_debug_jv", "pfnks_debug_pc", "pfnks_debug_counters",
-    "pfnks_debug_profile", "pfnks_debug_kernel_time",
+    "pfnks_debug_profile", "pfnks_debug_kernel_time", "pfnks_batch_step",
 ]
 
 KERNEL_KINDS = ["residual", "linearise", "jv", "ras", "spectral", "multidot", "update"]
@@ -113,6 +113,8 @@ def load():
     lib.pfnks_debug_counters.argtypes = [P, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong)]
     lib.pfnks_debug_profile.argtypes = [P, ctypes.c_int]
     lib.pfnks_debug_kernel_time.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_longlong), dp, dp]
+    lib.pfnks_batch_step.argtypes = [ctypes.POINTER(P), ctypes.c_int, dp, ctypes.c_int,
+                                     ctypes.POINTER(pfnks_step_stats), ctypes.POINTER(ctypes.c_int)]
     for name in EXPORTED:
         if name not in ("pfnks_strerror", "pfnks_last_error"):
             getattr(lib, name).restype = ctypes.c_int
@@ -188,6 +190,24 @@ def workspace_bytes(n, h, model, solver):
     _check(lib.pfnks_workspace_bytes(ctypes.byref(g), ctypes.byref(m), ctypes.byref(s), ctypes.byref(out)),
            "pfnks_workspace_bytes")
     return out.value
+
+
+def batch_step(problems, dts, threads=0):
+    """One step of every problem (pfnks_batch_step): returns (statuses, stats dicts).
+    Raises on errors other than ENOCONV; an ENOCONV problem is left unchanged."""
+    lib = load()
+    k = len(problems)
+    hs = (ctypes.c_void_p * k)(*[p._h.value for p in problems])
+    d = (ctypes.c_double * k)(*[float(x) for x in dts])
+    st = (pfnks_step_stats * k)()
+    status = (ctypes.c_int * k)()
+    rc = lib.pfnks_batch_step(hs, ctypes.c_int(k), d, ctypes.c_int(threads), st, status)
+    for s_ in status:
+        if s_ not in (PFNKS_OK, PFNKS_ENOCONV):
+            _check(s_, "pfnks_batch_step")
+    if rc not in (PFNKS_OK, PFNKS_ENOCONV):
+        _check(rc, "pfnks_batch_step")
+    return list(status), [x.as_dict() for x in st]
 
 
 class Problem:

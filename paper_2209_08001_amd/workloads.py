@@ -73,7 +73,24 @@ WORKLOADS = {
     # 3D 128^3, adaptive dt in [1e-3, 1], 100 steps
     "pf3d_128": {"n": (128, 128, 128), "seed": 3, "cbar": 0.17, "steps": 100,
                  "dt_min": 1e-3, "dt_max": 1.0, "zeta": 100.0},
+    # ensemble of 64 independent 2D instances (sides and mean compositions drawn from seed 4,
+    # instance k's noise from seed 4000 + k), 50 adaptive steps each
+    "ens2d_64": {"ensemble": True, "count": 64, "seed": 4, "sides": (128, 256, 512),
+                 "cbar_range": (0.13, 0.21), "steps": 50, "dt_min": 1e-3, "dt_max": 1.0, "zeta": 100.0},
 }
+
+
+def ensemble_members(wl):
+    """Instances of an ensemble workload: list of {"n", "seed", "cbar"}.  Side and mean
+    composition of instance k are the k-th draws of numpy.random.default_rng(wl["seed"])
+    (side uniform over wl["sides"], then cbar uniform in wl["cbar_range"])."""
+    rng = np.random.default_rng(wl["seed"])
+    out = []
+    for k in range(wl["count"]):
+        side = int(rng.choice(np.array(wl["sides"])))
+        cbar = float(rng.uniform(*wl["cbar_range"]))
+        out.append({"n": (side, side), "seed": wl["seed"] * 1000 + k, "cbar": cbar})
+    return out
 
 
 def init_fields(n, seed, cbar=0.17, amp_c=0.01, eta_base=1.0, amp_eta=0.01):

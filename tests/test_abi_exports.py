@@ -51,3 +51,18 @@ def test_workspace_bytes_and_validation_on_host():
         pfnks.workspace_bytes((100, 100), W.H, W.DEFAULT_MODEL, W.DEFAULT_SOLVER)  # not a power of 2
     with pytest.raises(pfnks.PfnksError):
         pfnks.workspace_bytes((64, 64), W.H, W.DEFAULT_MODEL, dict(W.DEFAULT_SOLVER, tile=(48, 48, 1)))
+
+
+def test_batch_step_rejects_bad_arguments_on_host():
+    """pfnks_batch_step validates its arrays before touching any problem."""
+    if not os.path.exists(LIB):
+        pytest.skip("libpfnks.so not built")
+    from paper_2209_08001_amd import pfnks
+
+    lib = pfnks.load()
+    assert lib.pfnks_batch_step(None, 1, None, 0, None, None) == pfnks.PFNKS_EINVAL
+    d = (ctypes.c_double * 1)(0.1)
+    hs = (ctypes.c_void_p * 1)(None)
+    assert lib.pfnks_batch_step(hs, 1, d, 0, None, None) == pfnks.PFNKS_EINVAL
+    assert lib.pfnks_batch_step(hs, -1, d, 0, None, None) == pfnks.PFNKS_EINVAL
+    assert lib.pfnks_batch_step(hs, 0, d, 0, None, None) == pfnks.PFNKS_OK

@@ -270,6 +270,54 @@ def test_step_parity_tile_shapes(oracle_c1, tile, prec):
     p.close()
 
 
+def test_batch_step_equals_single_and_oracle(oracle_c1):
+    """pfnks_batch_step over an ensemble of unlike instances (2D and 3D, FP64 and mixed,
+    one stream each, stepped concurrently by host threads): every instance ends bitwise
+    equal to the same instance stepped alone, and the pf2d_64 member stays within 1e-8 of
+    the oracle's root."""
+    import torch
+
+    from paper_2209_08001_amd import pfnks
+
+    _cuda()
+    c0, e0, traj, info, o = oracle_c1
+    _note("batch step vs single")
+    specs = [((64, 64), None, "fp64"), ((32, 32), 5, "fp64"), ((32, 64), 6, "mixed"),
+             ((16, 16, 16), 7, "fp64"), ((64, 64), 8, "mixed")]
+
+    dts = [0.01, 0.01, 0.01]
+    batch = []
+    for n, seed, prec in specs:
+        cc, ee = (c0, e0) if seed is None else W.init_fields(n, seed)
+        sv = dict(W.DEFAULT_SOLVER, precision=pfnks.MIXED if prec == "mixed" else pfnks.FP64)
+        sv["tile"] = (4, 4, 4) if len(n) == 3 else (16, 16, 1)
+        sv["overlap"] = 1 if len(n) == 3 else 2
+        batch.append(pfnks.Problem(n, W.H, W.DEFAULT_MODEL, sv, cc, ee, stream=torch.cuda.Stream()))
+    for dt in dts:
+        status, st = pfnks.batch_step(batch, [dt] * len(batch), threads=4)
+        assert all(x == pfnks.PFNKS_OK for x in status)
+    alone = []
+    for n, seed, prec in specs:
+        cc, ee = (c0, e0) if seed is None else W.init_fields(n, seed)
+        sv = dict(W.DEFAULT_SOLVER, precision=pfnks.MIXED if prec == "mixed" else pfnks.FP64)
+        sv["tile"] = (4, 4, 4) if len(n) == 3 else (16, 16, 1)
+        sv["overlap"] = 1 if len(n) == 3 else 2
+        q = pfnks.Problem(n, W.H, W.DEFAULT_MODEL, sv, cc, ee)
+        for dt in dts:
+            q.step(dt)
+        alone.append(q)
+    for i, (pb, pa) in enumerate(zip(batch, alone)):
+        Xb, tb = pb.get_state()
+        Xa, ta = pa.get_state()
+        assert np.array_equal(Xb, Xa) and tb == ta, i
+    X0, _ = batch[0].get_state()
+    err = max(_relmax(X0[f], traj[3][f]) for f in range(X0.shape[0]))
+    _note(f"  pf2d_64 member after 3 batch steps: max err {err:.2e}")
+    assert err <= 1e-8
+    for p in batch + alone:
+        p.close()
+
+
 def test_enoconv_leaves_state():
     """A step forced to fail (one Newton iteration allowed, huge dt) returns ENOCONV and
     leaves the state and time untouched."""
