@@ -42,7 +42,7 @@ def kernel_source_sha256(kind):
     return h.hexdigest()
 
 
-def measured_traffic(kind, workload, precision):
+def measured_traffic(kind, workload, precision, tile, overlap):
     """HBM bytes per launch of one kernel from the committed rocprofv3 counter summary
     (FETCH_SIZE and WRITE_SIZE, each scaled by the reading of a plain copy of known size), or
     None when there is none for this kernel and workload or the kernel source has changed."""
@@ -50,7 +50,8 @@ def measured_traffic(kind, workload, precision):
     if not os.path.exists(path):
         return None, None
     with open(path) as fh:
-        rec = json.load(fh).get(f"{kind}/{workload}/{precision}")
+        shape = "x".join(str(t) for t in tile)
+        rec = json.load(fh).get(f"{kind}/{workload}/{precision}/tile{shape}/ov{overlap}")
     if not rec or rec.get("source_sha256") != kernel_source_sha256(kind):
         return None, None
     return rec["traffic_bytes_per_launch"], rec["summary"]
@@ -180,6 +181,60 @@ def run_ensemble(args, wl):
     print(json.dumps(out))
 
 
+def run_serving(args, wl):
+    """Serving workload: seeded Poisson arrivals served with continuous batching; value =
+    accepted steps per second over the makespan; per-step latency while resident and queue
+    wait reported separately."""
+    import torch
+
+    from paper_2209_08001_amd import pfnks
+    from paper_2209_08001_amd import workloads as W
+    from paper_2209_08001_amd.serve import Server, poisson_requests
+
+    solver = dict(W.DEFAULT_SOLVER, sweeps=args.sweeps,
+                  pc=pfnks.PC_RAS if args.pc == "ras" else pfnks.PC_RAS_SPECTRAL,
+                  precision=pfnks.MIXED if args.precision == "mixed" else pfnks.FP64)
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(0.8 * free)
+    mk = lambda seed: poisson_requests(wl["rate"], wl["window"], seed, wl["sides2d"], wl["sides3d"],
+                                       wl["frac3d"], args.steps if args.steps_given else wl["steps"])
+    if args.warmup > 0:
+        Server(solver, wl, budget, threads=args.threads).run(mk(wl["seed"] + 1000)[:4], realtime=False)
+    reqs = mk(wl["seed"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Server(solver, wl, budget, threads=args.threads).run(reqs, realtime=True)
+    torch.cuda.synchronize()
+    makespan = time.perf_counter() - t0
+    steps = sum(r.done for r in reqs)
+    lat = [x for r in reqs for x in r.step_ms]
+    waits = [r.admitted_at - r.arrival for r in reqs]
+    out = {
+        "metric": "served Newton time steps/s (continuous batching); per-step latency p50/p99",
+        "value": steps / makespan,
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * makespan / max(steps, 1),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f64+f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "requests": len(reqs), "rate_per_s": wl["rate"],
+                   "window_s": wl["window"], "steps_per_request": reqs[0].steps if reqs else 0,
+                   "hbm_budget_bytes": budget, "precision": args.precision, "host_threads": args.threads},
+        "makespan_s": makespan,
+        "p50_step_ms": percentile(lat, 50),
+        "p99_step_ms": percentile(lat, 99),
+        "p50_queue_wait_s": percentile(waits, 50),
+        "p99_queue_wait_s": percentile(waits, 99),
+        "roofline": None,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -190,6 +245,8 @@ def main():
     ap.add_argument("--sweeps", type=int, default=2)
     ap.add_argument("--tile", default=None, help="Schwarz tile, e.g. 32,32 (2D) or 8,8,8 (3D)")
     ap.add_argument("--overlap", type=int, default=None)
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick tile / overlap / sweeps by timing candidates first (reported in config)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
                     help="mixed: float Krylov basis and Schwarz/Fourier preconditioner, double "
                          "residual, J v arithmetic, Newton update, energy and mass")
@@ -201,6 +258,7 @@ def main():
                     help="before the run, copy a device buffer of this many MiB once (a plain copy "
                          "kernel of known size, to scale the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
+    args.steps_given = any(a == "--steps" or a.startswith("--steps=") for a in sys.argv[1:])
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU decomposition is a design note, not built", file=sys.stderr)
@@ -215,6 +273,8 @@ def main():
     wl = W.WORKLOADS[args.workload]
     if wl.get("ensemble"):
         return run_ensemble(args, wl)
+    if wl.get("serve"):
+        return run_serving(args, wl)
     n = wl["n"]
     c0, e0 = W.init_fields(n, wl["seed"], cbar=wl["cbar"])
     solver = dict(W.DEFAULT_SOLVER, sweeps=args.sweeps,
@@ -228,6 +288,13 @@ def main():
     if args.overlap is not None:
         solver["overlap"] = args.overlap
     dev = "cuda:0"
+    tuned = None
+    if args.autotune:
+        from paper_2209_08001_amd.autotune import autotune
+
+        best, table = autotune(n, W.H, W.DEFAULT_MODEL, solver, c0, e0, wl, device=dev)
+        solver.update(tile=best["tile"], overlap=best["overlap"], sweeps=best["sweeps"])
+        tuned = {"best": best, "candidates": len(table)}
     if args.copy_calibration_mb > 0:
         src = torch.ones(args.copy_calibration_mb * (1 << 20) // 8, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
@@ -286,7 +353,8 @@ def main():
             "precision": args.precision,
             "tile": list(solver["tile"][:len(n)]),
             "overlap": solver["overlap"],
-            "gs_sweeps": args.sweeps,
+            "gs_sweeps": solver["sweeps"],
+            "autotuned": tuned,
             "gmres_restart": solver["gmres_restart"],
             "newton_rtol": solver["newton_rtol"],
             "gmres_rtol": solver["gmres_rtol"],
@@ -308,7 +376,8 @@ def main():
                                  for k, v in table.items()}
     if not args.no_roofline:
         roof = p.roofline(HBM_PEAK_GBS)
-        traffic, summary = measured_traffic(roof["kernel"], args.workload, args.precision)
+        traffic, summary = measured_traffic(roof["kernel"], args.workload, args.precision,
+                                            solver["tile"][:len(n)], solver["overlap"])
         roof["traffic"] = traffic
         if traffic is not None:
             roof["traffic_over_algorithmic"] = traffic / roof["bytes_per_launch"]

@@ -37,9 +37,11 @@ class _Clock:
         self.rate = st["dx_rms"] / dt
 
 
-def adaptive_run(p, nsteps, wl):
-    """nsteps accepted steps of one problem; returns (per-step wall latencies, stats)."""
+def adaptive_run(p, nsteps, wl, rate0=None):
+    """nsteps accepted steps of one problem; returns (per-step wall latencies, stats).
+    rate0: the change rate of the step before (None: the first step takes dt_min)."""
     clk = _Clock(wl)
+    clk.rate = rate0
     lat, stats = [], []
     for _ in range(nsteps):
         dt = clk.next_dt()

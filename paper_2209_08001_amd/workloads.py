@@ -77,6 +77,10 @@ WORKLOADS = {
     # instance k's noise from seed 4000 + k), 50 adaptive steps each
     "ens2d_64": {"ensemble": True, "count": 64, "seed": 4, "sides": (128, 256, 512),
                  "cbar_range": (0.13, 0.21), "steps": 50, "dt_min": 1e-3, "dt_max": 1.0, "zeta": 100.0},
+    # serving: Poisson arrivals (4 requests/s over 10 s, seed 5), 70 % 2D (sides 64..512) and
+    # 30 % 3D (side 64), 20 adaptive steps per request, continuous batching
+    "serve_mix": {"serve": True, "rate": 4.0, "window": 10.0, "seed": 5, "sides2d": (64, 128, 256, 512),
+                  "sides3d": (64,), "frac3d": 0.3, "steps": 20, "dt_min": 1e-3, "dt_max": 1.0, "zeta": 100.0},
 }
 
 

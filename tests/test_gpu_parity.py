@@ -318,6 +318,29 @@ def test_batch_step_equals_single_and_oracle(oracle_c1):
         p.close()
 
 
+def test_serving_alone_equals_mix():
+    """Continuous batching: requests of different sizes (2D and 3D, FP64), admitted under an
+    HBM budget that holds only some of them at once, joining and leaving between ticks; every
+    request's final state is bitwise the state of the same request run alone."""
+    from paper_2209_08001_amd import pfnks
+    from paper_2209_08001_amd.serve import Request, Server, run_alone
+
+    _cuda()
+    _note("serving alone vs mix")
+    wl = dict(W.WORKLOADS["serve_mix"])
+    reqs = [Request(0, (32, 32), 11, 0.15, 3), Request(1, (64, 64), 12, 0.17, 5),
+            Request(2, (16, 16, 16), 13, 0.19, 2), Request(3, (32, 64), 14, 0.16, 4),
+            Request(4, (64, 64), 15, 0.2, 3)]
+    srv = Server(dict(W.DEFAULT_SOLVER), wl, hbm_budget=0, keep_state=True, threads=4)
+    need = sorted(srv.bytes_for(r) for r in reqs)
+    srv.budget = need[-1] + need[-2]  # at most two of the largest resident at once
+    srv.run(reqs, realtime=False)
+    for r in reqs:
+        assert r.done == r.steps
+        Xa, ta = run_alone(r, srv._solver_for, wl)
+        assert np.array_equal(r.state, Xa) and r.t == ta, r.rid
+
+
 def test_enoconv_leaves_state():
     """A step forced to fail (one Newton iteration allowed, huge dt) returns ENOCONV and
     leaves the state and time untouched."""
