@@ -28,10 +28,6 @@ namespace {
 // thread and two workgroups fit the LDS of one compute unit (they then overlap their barriers)
 constexpr int kRasThreadsMax = 512, kRasThreadsSmall = 256;
 
-// bound on the dG nodes (extended tile and its ring of one) per thread of the batched dG
-// phase; the host rejects tile shapes that need more
-constexpr __host__ __device__ int ras_dg_iters(int dim, int npt) { return dim == 2 ? npt + 1 : npt + 2; }
-
 struct Geo {
   int ex, ey, ez;      // extended tile
   int zx, zy, zz;      // LDS iterate (ext + ring of 2; zz = 1 in 2D)
@@ -203,10 +199,9 @@ __global__ __launch_bounds__(TH, (TH == kRasThreadsSmall) ? 2 : 1) void k_ras(Co
 
   // coefficients in the arithmetic type of the solve (formed in double, rounded once)
   const R idt = (R)(1.0 / dt);
-  const R ih2 = (R)K.ih2, i2h = (R)K.i2h, kel = (R)K.kel, Le = (R)K.L_eta, eps0 = (R)K.eps0;
+  const R ih2 = (R)K.ih2, i2h = (R)K.i2h, Le = (R)K.L_eta, eps0 = (R)K.eps0;
   const R C11 = (R)K.C11, C12 = (R)K.C12, C44 = (R)K.C44;
-  const R lapc = (R)(-2.0 * DIM * K.ih2);
-  const R hgc = (R)(-0.5 * K.gamma_c), hk = (R)(0.5 * K.kappa);
+  const R hk = (R)(0.5 * K.kappa);
   const int sdir_z[3] = {1, sy, sz};
   const int sdir_d[3] = {1, ty_, tz_};
   const R a_u = (R)(-0.5 * K.eps0 * K.Ctr * K.i2h);  // coefficient of the difference of z_u in dG
@@ -216,6 +211,8 @@ __global__ __launch_bounds__(TH, (TH == kRasThreadsSmall) ? 2 : 1) void k_ras(Co
   const R iduu = (R)(-2.0 * K.h * K.h / (K.C11 + (DIM - 1) * K.C44));
   const R cxu = (R)(K.eps0 * K.Ctr * 0.25 * K.ih2 * K.ih);
   const R cge = (R)(0.5 * K.L_eta * K.gamma_eta * K.ih2);  // eta-row neighbour coefficient
+  const R dgc = (R)(K.kel + K.gamma_c * DIM * K.ih2);    // d dG / d z_c at the node (besides B_cc)
+  const R dgn = (R)(-0.5 * K.gamma_c * K.ih2);           // d dG / d z_c at a neighbour
   // Per node, the diagonal block of the tile operator (the node's own unknowns) is
   //   [d_cc  u'  ]      d_cc = 1/dt + sc (B_cc + kel + gamma_c (2 DIM + 1) / (2 h^2)),
   //   [v     E   ]      u_e = sc B_ce, v_e = L_eta B_ec, E = dee I + L_eta B_ee,
@@ -339,86 +336,40 @@ __global__ __launch_bounds__(TH, (TH == kRasThreadsSmall) ? 2 : 1) void k_ras(Co
     }
     const R zc = zv[0] + xc;
     zs[zi] = zc;
+    R dz[4];
+    dz[0] = xc;
 #pragma unroll
-    for (int e = 0; e < 3; ++e) zs[(1 + e) * zsz + zi] = y[e] - w[e] * zc;
+    for (int e = 0; e < 3; ++e) {
+      const R ze = y[e] - w[e] * zc;
+      zs[(1 + e) * zsz + zi] = ze;
+      dz[1 + e] = ze - zv[1 + e];
+    }
     if (WU) {
 #pragma unroll
       for (int I = 0; I < DIM; ++I) zs[(4 + I) * zsz + zi] = zv[4 + I] + xu[I];
     }
+    // dG follows the change: at the node through B_c, kel and the centre of the Laplacian, at
+    // the 2 DIM neighbours through the Laplacian (and the divergence of u).  Nodes of one
+    // colour share no neighbour, so these read-modify-writes never collide within a phase.
+    R dself = dgc * xc;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) dself += bc[f * ne + q] * dz[f];
+    dg[di] += dself;
+    const R dn = dgn * xc;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const R du = WU ? a_u * xu[d] : R(0);
+      dg[di + sdir_d[d]] += dn - du;
+      dg[di - sdir_d[d]] += dn + du;
+    }
   };
 
-  // dG at iterate position pz; qe: c-row block index, -1 on the ring of width 1 (where only
-  // the Laplacian term enters)
-  auto dg_at = [&](int pz, int qe) -> R {
-    R l = lapc * zs[pz];
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) l += (zs[pz + sdir_z[d]] + zs[pz - sdir_z[d]]) * ih2;
-    R sg_ = hgc * l;
-    if (qe >= 0) {
-      sg_ += kel * zs[pz];
-#pragma unroll
-      for (int f = 0; f < 4; ++f) sg_ += bc[f * ne + qe] * zs[f * zsz + pz];
-    }
-    if (WU) {
-      R dv = R(0);
-#pragma unroll
-      for (int d = 0; d < DIM; ++d) dv += zs[(4 + d) * zsz + pz + sdir_z[d]] - zs[(4 + d) * zsz + pz - sdir_z[d]];
-      sg_ += a_u * dv;
-    }
-    return sg_;
-  };
-  auto dg_node = [&](int qd, int& pz, int& qe) {
-    const int a = qd % G.dx, b = (qd / G.dx) % G.dy, c = qd / (G.dx * G.dy);
-    const bool inside = a >= 1 && a <= G.ex && b >= 1 && b <= G.ey && (DIM == 2 || (c >= 1 && c <= G.ez));
-    pz = (a - 1 + ring) + sy * (b - 1 + ring) + ((DIM == 3) ? sz * (c - 1 + ring) : 0);
-    qe = inside ? (a - 1) + G.ex * ((b - 1) + ((DIM == 3) ? G.ey * (c - 1) : 0)) : -1;
-  };
-  // The dG phase either keeps this thread's dG nodes precomputed (packed pz | (qe + 1) << 16,
-  // pz < 2^16) and forms all their values before the stores, so that their LDS loads are in
-  // flight together (stores to dg could otherwise alias them), or walks its nodes one at a
-  // time with fewer live registers: the float 3D tile needs the latter to keep two workgroups
-  // resident per compute unit.
-  constexpr bool kBatch = !(DIM == 3 && sizeof(R) == 4);
-  constexpr int DIT = kBatch ? ras_dg_iters(DIM, NPT) : 1;
-  int dpq[DIT];
-  if constexpr (kBatch) {
-#pragma unroll
-    for (int it = 0; it < DIT; ++it) {
-      const int qd = threadIdx.x + it * TH;
-      dpq[it] = -1;
-      if (qd < dsz) {
-        int pz, qe;
-        dg_node(qd, pz, qe);
-        dpq[it] = pz | ((qe + 1) << 16);
-      }
-    }
-  }
-  bool first = true;
-
+  // Symmetric multicolour sweeps.  dG (zero for the zero initial iterate) is kept current by
+  // the updates themselves, so a colour phase is just the update of its nodes.
   for (int sw = 0; sw < G.sweeps; ++sw) {
     for (int pass = 0; pass < 2; ++pass) {
       for (int cc = 0; cc < NCOL; ++cc) {
         const int col = pass == 0 ? cc : NCOL - 1 - cc;
-        // ---- dG on ext and on the ring of width 1 (all threads) -----------------------
-        if (!first) {
-          if constexpr (kBatch) {
-            R sgv[DIT];
-#pragma unroll
-            for (int it = 0; it < DIT; ++it)
-              sgv[it] = (dpq[it] < 0) ? R(0) : dg_at(dpq[it] & 0xffff, (dpq[it] >> 16) - 1);
-#pragma unroll
-            for (int it = 0; it < DIT; ++it)
-              if (dpq[it] >= 0) dg[threadIdx.x + it * TH] = sgv[it];
-          } else {
-            for (int qd = threadIdx.x; qd < dsz; qd += TH) {
-              int pz, qe;
-              dg_node(qd, pz, qe);
-              dg[qd] = dg_at(pz, qe);
-            }
-          }
-          __syncthreads();
-        }
-        first = false;
         // ---- update the nodes of this colour (a contiguous range of threads) -------------
         // A thread's nodes lie in different colour ranges (a range is shorter than the block),
         // so at most one of them is active here: select it, then run one copy of the update.
@@ -532,14 +483,12 @@ void launch_dim(const Consts& K, const Geo& G, size_t lds, int ntiles, int th, i
     launch_npt<DIM, WU, R, kRasThreadsMax>(G, K, lds, ntiles, npt, dt, B, cn, r, z, s);
 }
 
-// nodes of the extended tile per thread (1..3) at th threads, 0 if the tile does not fit
-// (more than three nodes per thread, or more dG nodes than the batched dG phase holds)
+// nodes of the extended tile per thread (1..3) at th threads, 0 if more than three
 int npt_for(int dim, const Geo& G, int th) {
+  (void)dim;
   const int ne = G.ex * G.ey * G.ez;
   const int npt = (ne + th - 1) / th;
-  const int dsz = G.dx * G.dy * G.dz;
-  if (npt > 3 || (dsz + th - 1) / th > ras_dg_iters(dim, npt)) return 0;
-  return npt;
+  return npt <= 3 ? npt : 0;
 }
 
 }  // namespace

@@ -173,7 +173,7 @@ def make_solver(d, dim):
     t = d["tile"]
     s.tile[0], s.tile[1], s.tile[2] = t[0], t[1], (t[2] if dim == 3 else 1)
     s.overlap = d["overlap"]
-    s.sweeps = d.get("sweeps", 2)
+    s.sweeps = d.get("sweeps", 6)
     s.pc = d.get("pc", PC_RAS_SPECTRAL)
     s.precision = d.get("precision", FP64)
     s.ls_alpha = d["ls_alpha"]

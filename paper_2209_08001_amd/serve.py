@@ -62,7 +62,7 @@ class Server:
     def _solver_for(self, n):
         sv = dict(self.solver)
         if len(n) == 3:
-            sv.update(tile=(8, 8, 8) if min(n) >= 16 else (4, 4, 4), overlap=1)
+            sv.update(tile=(8, 8, 8) if min(n) >= 16 else (4, 4, 4), overlap=1, sweeps=W.SWEEPS_3D)
         else:
             t = 32
             while t + 2 * sv["overlap"] > min(n):

@@ -60,9 +60,15 @@ DEFAULT_SOLVER = {
     "gmres_maxit": 600,
     "tile": (32, 32, 1),
     "overlap": 2,
+    # symmetric Gauss-Seidel sweeps of the tile solve: each sweep costs ~18 us per apply at
+    # 512^2 and saves GMRES iterations (512^2 FP64: 2 sweeps 24 iterations per Newton step,
+    # 91 steps/s; 6 sweeps 13.7, 120 steps/s); 3D 8^3 tiles: 4 (the measured optimum there)
+    "sweeps": 6,
     "ls_alpha": 1e-4,
     "ls_max_halvings": 10,
 }
+
+SWEEPS_3D = 4
 
 WORKLOADS = {
     # 2D 64 x 64, 10 fixed steps dt = 1e-2
