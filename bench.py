@@ -123,7 +123,7 @@ def run_ensemble(args, wl):
     from paper_2209_08001_amd.driver import adaptive_batch_run
 
     members = W.ensemble_members(wl)
-    solver = dict(W.DEFAULT_SOLVER, sweeps=args.sweeps or W.DEFAULT_SOLVER["sweeps"],
+    solver = dict(W.DEFAULT_SOLVER, sweeps=args.sweeps or W.default_sweeps(2, args.precision == "mixed"),
                   pc=pfnks.PC_RAS if args.pc == "ras" else pfnks.PC_RAS_SPECTRAL,
                   precision=pfnks.MIXED if args.precision == "mixed" else pfnks.FP64)
     dev = "cuda:0"
@@ -191,7 +191,7 @@ def run_serving(args, wl):
     from paper_2209_08001_amd import workloads as W
     from paper_2209_08001_amd.serve import Server, poisson_requests
 
-    solver = dict(W.DEFAULT_SOLVER, sweeps=args.sweeps or W.DEFAULT_SOLVER["sweeps"],
+    solver = dict(W.DEFAULT_SOLVER, sweeps=args.sweeps or W.default_sweeps(2, args.precision == "mixed"),
                   pc=pfnks.PC_RAS if args.pc == "ras" else pfnks.PC_RAS_SPECTRAL,
                   precision=pfnks.MIXED if args.precision == "mixed" else pfnks.FP64)
     free, _ = torch.cuda.mem_get_info()
@@ -243,7 +243,7 @@ def main():
     ap.add_argument("--workload", default="pf2d_512")
     ap.add_argument("--pc", default="ras_spectral", choices=["ras_spectral", "ras"])
     ap.add_argument("--sweeps", type=int, default=None,
-                    help="Gauss-Seidel sweeps of the tile solve (default 6 in 2D, 4 in 3D)")
+                    help="Gauss-Seidel sweeps of the tile solve (default: workloads.default_sweeps)")
     ap.add_argument("--tile", default=None, help="Schwarz tile, e.g. 32,32 (2D) or 8,8,8 (3D)")
     ap.add_argument("--overlap", type=int, default=None)
     ap.add_argument("--autotune", action="store_true",
@@ -278,11 +278,11 @@ def main():
         return run_serving(args, wl)
     n = wl["n"]
     c0, e0 = W.init_fields(n, wl["seed"], cbar=wl["cbar"])
-    solver = dict(W.DEFAULT_SOLVER, sweeps=args.sweeps or W.DEFAULT_SOLVER["sweeps"],
+    solver = dict(W.DEFAULT_SOLVER, sweeps=args.sweeps or W.default_sweeps(2, args.precision == "mixed"),
                   pc=pfnks.PC_RAS if args.pc == "ras" else pfnks.PC_RAS_SPECTRAL,
                   precision=pfnks.MIXED if args.precision == "mixed" else pfnks.FP64)
     if len(n) == 3:
-        solver.update(tile=(8, 8, 8), overlap=1, sweeps=args.sweeps or W.SWEEPS_3D)
+        solver.update(tile=(8, 8, 8), overlap=1, sweeps=args.sweeps or W.default_sweeps(3, args.precision == "mixed"))
     if args.tile:
         t = tuple(int(v) for v in args.tile.split(","))
         solver["tile"] = t if len(t) == 3 else (t[0], t[1], 1)

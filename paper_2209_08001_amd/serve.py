@@ -61,8 +61,9 @@ class Server:
 
     def _solver_for(self, n):
         sv = dict(self.solver)
+        sv["sweeps"] = W.default_sweeps(len(n), sv.get("precision", pfnks.FP64) == pfnks.MIXED)
         if len(n) == 3:
-            sv.update(tile=(8, 8, 8) if min(n) >= 16 else (4, 4, 4), overlap=1, sweeps=W.SWEEPS_3D)
+            sv.update(tile=(8, 8, 8) if min(n) >= 16 else (4, 4, 4), overlap=1)
         else:
             t = 32
             while t + 2 * sv["overlap"] > min(n):

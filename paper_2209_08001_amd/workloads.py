@@ -60,15 +60,21 @@ DEFAULT_SOLVER = {
     "gmres_maxit": 600,
     "tile": (32, 32, 1),
     "overlap": 2,
-    # symmetric Gauss-Seidel sweeps of the tile solve: each sweep costs ~18 us per apply at
-    # 512^2 and saves GMRES iterations (512^2 FP64: 2 sweeps 24 iterations per Newton step,
-    # 91 steps/s; 6 sweeps 13.7, 120 steps/s); 3D 8^3 tiles: 4 (the measured optimum there)
+    # symmetric Gauss-Seidel sweeps of the tile solve (see default_sweeps)
     "sweeps": 6,
     "ls_alpha": 1e-4,
     "ls_max_halvings": 10,
 }
 
-SWEEPS_3D = 4
+def default_sweeps(dim, mixed):
+    """Gauss-Seidel sweeps of the tile solve, as measured fastest per step on MI355X: each
+    sweep costs ~17 us per apply at 512^2 FP64 and saves GMRES iterations (512^2 FP64: 2
+    sweeps 24 iterations per Newton step, 6 sweeps 13.3, 8 sweeps 11.7 at the same speed;
+    mixed: 8 sweeps; 128^3 mixed: 6)."""
+    if dim == 3:
+        return 6
+    return 8 if mixed else 6
+
 
 WORKLOADS = {
     # 2D 64 x 64, 10 fixed steps dt = 1e-2
