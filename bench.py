@@ -277,7 +277,13 @@ def main():
     if wl.get("serve"):
         return run_serving(args, wl)
     n = wl["n"]
-    c0, e0 = W.init_fields(n, wl["seed"], cbar=wl["cbar"])
+    model = W.DEFAULT_MODEL
+    if "particle" in wl:
+        c0, e0 = W.particle_fields(n, W.H, wl["particle"])
+        model = W.P1_MODEL
+        args.no_cpu_baseline = True
+    else:
+        c0, e0 = W.init_fields(n, wl["seed"], cbar=wl["cbar"])
     solver = dict(W.DEFAULT_SOLVER, sweeps=args.sweeps or W.default_sweeps(2, args.precision == "mixed"),
                   pc=pfnks.PC_RAS if args.pc == "ras" else pfnks.PC_RAS_SPECTRAL,
                   precision=pfnks.MIXED if args.precision == "mixed" else pfnks.FP64)
@@ -293,7 +299,7 @@ def main():
     if args.autotune:
         from paper_2209_08001_amd.autotune import autotune
 
-        best, table = autotune(n, W.H, W.DEFAULT_MODEL, solver, c0, e0, wl, device=dev)
+        best, table = autotune(n, W.H, model, solver, c0, e0, wl, device=dev)
         solver.update(tile=best["tile"], overlap=best["overlap"], sweeps=best["sweeps"])
         tuned = {"best": best, "candidates": len(table)}
     if args.copy_calibration_mb > 0:
@@ -307,7 +313,7 @@ def main():
     dominant = "ras"
     table = {}
     if args.warmup > 0:
-        pw = pfnks.Problem(n, W.H, W.DEFAULT_MODEL, solver, c0, e0, device=dev)
+        pw = pfnks.Problem(n, W.H, model, solver, c0, e0, device=dev)
         pw.profile(True)
         adaptive_run(pw, args.warmup, wl)
         table = pw.kernel_table()
@@ -316,7 +322,7 @@ def main():
         pw.close()
         del pw
 
-    p = pfnks.Problem(n, W.H, W.DEFAULT_MODEL, solver, c0, e0, device=dev)
+    p = pfnks.Problem(n, W.H, model, solver, c0, e0, device=dev)
     if not args.no_roofline:
         p.profile([dominant])  # only the dominant kernel is bracketed in the timed region
     m0 = p.mass()

@@ -89,6 +89,11 @@ WORKLOADS = {
     # instance k's noise from seed 4000 + k), 50 adaptive steps each
     "ens2d_64": {"ensemble": True, "count": 64, "seed": 4, "sides": (128, 256, 512),
                  "cbar_range": (0.13, 0.21), "steps": 50, "dt_min": 1e-3, "dt_max": 1.0, "zeta": 100.0},
+    # Section 5.1 single particle (one order parameter via the symmetric subspace): radius 7.5
+    # at the centre, dt_1 = dt_min = 0.01, dt_max = 2, zeta = 100; 128^3 stands for the paper's
+    # 80^3 (the Fourier displacement solve needs power-of-two sides; side 32 > 2 r)
+    "particle3d_128": {"n": (128, 128, 128), "particle": 7.5, "steps": 50,
+                       "dt_min": 1e-2, "dt_max": 2.0, "zeta": 100.0},
     # serving: Poisson arrivals (4 requests/s over 10 s, seed 5), 70 % 2D (sides 64..512) and
     # 30 % 3D (side 64), 20 adaptive steps per request, continuous batching
     "serve_mix": {"serve": True, "rate": 4.0, "window": 10.0, "seed": 5, "sides2d": (64, 128, 256, 512),
@@ -125,6 +130,27 @@ def init_fields(n, seed, cbar=0.17, amp_c=0.01, eta_base=1.0, amp_eta=0.01):
     for p in range(3):
         eta0[p] = eta_base + rng.uniform(-amp_eta, amp_eta, size=shape)
     return c0, eta0
+
+
+def particle_fields(n, h, radius, c_in=0.238, eta_in=0.01, c_out=0.1375, eta_out=0.99):
+    """One spherical (circular in 2D) gamma' particle of the given radius (length units) at the
+    centre of the periodic box, as in the single-particle runs of Section 5.1: c = c_in,
+    eta = eta_in inside, c = c_out, eta = eta_out outside; all three order parameters equal
+    (the one-order-parameter model is the symmetric subspace eta_1 = eta_2 = eta_3 of the
+    three-parameter one, with L_eta = 3).  Returns (c0, eta0) like init_fields."""
+    shape = tuple(reversed(tuple(n)))
+    axes = [(np.arange(m) + 0.5) * h - 0.5 * m * h for m in shape]
+    grids = np.meshgrid(*axes, indexing="ij")
+    inside = sum(g * g for g in grids) <= radius * radius
+    c0 = np.where(inside, c_in, c_out).astype(np.float64)
+    e = np.where(inside, eta_in, eta_out).astype(np.float64)
+    eta0 = np.stack([e, e, e])
+    return c0, eta0
+
+
+# the one-order-parameter model of Sections 2-3 as the symmetric subspace of the three-parameter
+# model: identical eta_p and L_eta = 3 (the three equal eta-rows then carry the 1/3 weights)
+P1_MODEL = dict(DEFAULT_MODEL, L_eta=3.0)
 
 
 def random_state(n, seed, cbar=0.17, amp=0.02, u_amp=1e-3):

@@ -249,17 +249,20 @@ def test_step_parity_pf2d_64(oracle_c1, pc, prec):
     p.close()
 
 
-@pytest.mark.parametrize("tile,prec", [((16, 32), "fp64"), ((32, 16), "fp64"), ((16, 16), "fp64"),
-                                       ((16, 32), "mixed"), ((8, 8), "fp64")])
-def test_step_parity_tile_shapes(oracle_c1, tile, prec):
-    """2D 64 x 64, 3 steps with other Schwarz tile shapes (they select the 256-thread tile
-    kernel and other nodes-per-thread counts): within 1e-8 of the oracle's root."""
+@pytest.mark.parametrize("tile,prec,overlap", [((16, 32), "fp64", 2), ((32, 16), "fp64", 2), ((16, 16), "fp64", 2),
+                                               ((16, 32), "mixed", 2), ((8, 8), "fp64", 2), ((16, 16), "fp64", 0),
+                                               ((32, 32), "fp64", 1)])
+def test_step_parity_tile_shapes(oracle_c1, tile, prec, overlap):
+    """2D 64 x 64, 3 steps with other Schwarz tile shapes and overlaps (they select the
+    256-thread tile kernel and other nodes-per-thread counts; overlap 0 is the classical
+    block-Jacobi / additive Schwarz of the paper's overlap-0 runs): within 1e-8 of the
+    oracle's root."""
     from paper_2209_08001_amd import pfnks
 
     _cuda()
     c0, e0, traj, info, o = oracle_c1
-    _note(f"step parity pf2d_64 tile={tile} precision={prec}")
-    p = _problem((64, 64), c0, e0, tile=(tile[0], tile[1], 1),
+    _note(f"step parity pf2d_64 tile={tile} overlap={overlap} precision={prec}")
+    p = _problem((64, 64), c0, e0, tile=(tile[0], tile[1], 1), overlap=overlap,
                  precision=pfnks.MIXED if prec == "mixed" else pfnks.FP64)
     for k in range(3):
         st = p.step(0.01)
@@ -339,6 +342,44 @@ def test_serving_alone_equals_mix():
         assert r.done == r.steps
         Xa, ta = run_alone(r, srv._solver_for, wl)
         assert np.array_equal(r.state, Xa) and r.t == ta, r.rid
+
+
+@pytest.fixture(scope="module")
+def oracle_particle():
+    n = (32, 32)
+    c0, e0 = W.particle_fields(n, W.H, 2.5)
+    o = Oracle(n, W.H, W.P1_MODEL, c0, e0)
+    traj = [o.X.copy()]
+    for _ in range(2):
+        o.step(0.01)
+        traj.append(o.X.copy())
+    return n, c0, e0, traj
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_p1_particle_parity(oracle_particle, prec):
+    """Section 5.1 single particle with one order parameter (the symmetric subspace of the
+    three-parameter model, L_eta = 3), sharp initial interface, 32 x 32: two steps within
+    1e-8 of the oracle's root; the three order parameters stay equal (to 1e-13)."""
+    from paper_2209_08001_amd import pfnks
+
+    _cuda()
+    n, c0, e0, traj = oracle_particle
+    _note(f"P=1 particle parity precision={prec}")
+    p = _problem(n, c0, e0, model=W.P1_MODEL, precision=pfnks.MIXED if prec == "mixed" else pfnks.FP64)
+    E_prev = p.energy()[0]
+    for k in range(2):
+        st = p.step(0.01)
+        X, _ = p.get_state()
+        errs = [_relmax(X[f], traj[k + 1][f]) for f in range(X.shape[0])]
+        sym = max(np.max(np.abs(X[1] - X[2])), np.max(np.abs(X[1] - X[3])))
+        _note(f"  step {k}: newton={st['newton_its']} gmres={st['gmres_its']} max err={max(errs):.2e} "
+              f"eta asymmetry={sym:.1e}")
+        assert max(errs) <= 1e-8, (k, errs)
+        assert sym <= 1e-13
+        assert st["energy"] <= E_prev + 1e-12 * abs(E_prev)
+        E_prev = st["energy"]
+    p.close()
 
 
 def test_enoconv_leaves_state():
