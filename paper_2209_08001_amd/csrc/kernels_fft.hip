@@ -26,68 +26,6 @@ __device__ inline double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// Lines of length n (power of two), points pstride apart; line l starts at
-// (l % la) * lb + (l / la) * lc.  contiguous = 1 when pstride == 1 (threads walk along a line),
-// else consecutive threads take consecutive lines (la lines adjacent in memory).
-__global__ __launch_bounds__(kFftThreads) void k_fft_lines(double2* __restrict__ data, int n, int logn,
-                                                           long long pstride, long long la,
-                                                           long long lb, long long lc, long long nlines,
-                                                           int lpb, const double2* __restrict__ tw,
-                                                           int inverse, int contiguous) {
-  __shared__ double2 sm[kFftLds];
-  const long long line0 = (long long)blockIdx.x * lpb;
-  const int total = lpb * n;
-  for (int e = threadIdx.x; e < total; e += kFftThreads) {
-    int l, p;
-    if (contiguous) {
-      l = e / n;
-      p = e - l * n;
-    } else {
-      l = e % lpb;
-      p = e / lpb;
-    }
-    const long long line = line0 + l;
-    if (line < nlines) {
-      const long long off = (line % la) * lb + (line / la) * lc;
-      const int rp = (int)(__brev((unsigned)p) >> (32 - logn));
-      sm[l * n + rp] = data[off + p * pstride];
-    }
-  }
-  __syncthreads();
-  const int halfn = n >> 1;
-  for (int s = 1; s <= logn; ++s) {
-    const int half = 1 << (s - 1);
-    const int tstride = n >> s;  // twiddle index step
-    for (int t = threadIdx.x; t < lpb * halfn; t += kFftThreads) {
-      const int l = t / halfn, r = t - l * halfn;
-      const int grp = r / half, pos = r - grp * half;
-      const int i0 = l * n + grp * 2 * half + pos, i1 = i0 + half;
-      double2 w = tw[pos * tstride];
-      if (inverse) w.y = -w.y;
-      const double2 a0 = sm[i0];
-      const double2 a1 = cmul(sm[i1], w);
-      sm[i0] = make_double2(a0.x + a1.x, a0.y + a1.y);
-      sm[i1] = make_double2(a0.x - a1.x, a0.y - a1.y);
-    }
-    __syncthreads();
-  }
-  for (int e = threadIdx.x; e < total; e += kFftThreads) {
-    int l, p;
-    if (contiguous) {
-      l = e / n;
-      p = e - l * n;
-    } else {
-      l = e % lpb;
-      p = e / lpb;
-    }
-    const long long line = line0 + l;
-    if (line < nlines) {
-      const long long off = (line % la) * lb + (line / la) * lc;
-      data[off + p * pstride] = sm[l * n + p];
-    }
-  }
-}
-
 // ---- fused 2D pipeline ------------------------------------------------------------------
 // In-LDS transform of one line of n = 2^logn complex points stored at buf[0 .. n) in
 // bit-reversed order; radix-4 stage pairs (two radix-2 stages per thread, 4 points in
@@ -136,6 +74,52 @@ __device__ inline void fft_lds(double2* buf, int n, int logn, int nl, const doub
       b[half] = make_double2(a0.x - a1.x, a0.y - a1.y);
     }
     __syncthreads();
+  }
+}
+
+// Lines of length n (power of two), points pstride apart; line l starts at
+// (l % la) * lb + (l / la) * lc.  contiguous = 1 when pstride == 1 (threads walk along a line),
+// else consecutive threads take consecutive lines (la lines adjacent in memory).
+__global__ __launch_bounds__(kFftThreads) void k_fft_lines(double2* __restrict__ data, int n, int logn,
+                                                           long long pstride, long long la,
+                                                           long long lb, long long lc, long long nlines,
+                                                           int lpb, const double2* __restrict__ tw,
+                                                           int inverse, int contiguous) {
+  __shared__ double2 sm[kFftLds];
+  const long long line0 = (long long)blockIdx.x * lpb;
+  const int total = lpb * n;
+  for (int e = threadIdx.x; e < total; e += kFftThreads) {
+    int l, p;
+    if (contiguous) {
+      l = e / n;
+      p = e - l * n;
+    } else {
+      l = e % lpb;
+      p = e / lpb;
+    }
+    const long long line = line0 + l;
+    if (line < nlines) {
+      const long long off = (line % la) * lb + (line / la) * lc;
+      const int rp = (int)(__brev((unsigned)p) >> (32 - logn));
+      sm[l * n + rp] = data[off + p * pstride];
+    }
+  }
+  __syncthreads();
+  fft_lds(sm, n, logn, lpb, tw, inverse);
+  for (int e = threadIdx.x; e < total; e += kFftThreads) {
+    int l, p;
+    if (contiguous) {
+      l = e / n;
+      p = e - l * n;
+    } else {
+      l = e % lpb;
+      p = e / lpb;
+    }
+    const long long line = line0 + l;
+    if (line < nlines) {
+      const long long off = (line % la) * lb + (line / la) * lc;
+      data[off + p * pstride] = sm[l * n + p];
+    }
   }
 }
 
@@ -265,10 +249,10 @@ template <int DIM, typename T>
 __global__ __launch_bounds__(256) void k_pack(Consts K, const T* __restrict__ r, double a,
                                               const T* __restrict__ zc, double2* __restrict__ z0,
                                               double2* __restrict__ z1) {
-  const int i = blockIdx.x * 256 + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
-  if (i >= K.nx) return;
+  const long long n = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (n >= K.N) return;
   {
-    const long long n = (long long)i + (long long)K.nx * ((long long)j + (long long)K.ny * k);
+    const int i = (int)(n % K.nx), j = (int)((n / K.nx) % K.ny), k = (int)(n / ((long long)K.nx * K.ny));
     double q[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int I = 0; I < DIM; ++I) {
@@ -303,10 +287,10 @@ __global__ __launch_bounds__(256) void k_symbol_solve(Consts K, const double2* _
                                                       const double* __restrict__ sx,
                                                       const double* __restrict__ sy,
                                                       const double* __restrict__ szt) {
-  const int i = blockIdx.x * 256 + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
-  if (i >= K.nx) return;
+  const long long n = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (n >= K.N) return;
   {
-    const long long n = (long long)i + (long long)K.nx * ((long long)j + (long long)K.ny * k);
+    const int i = (int)(n % K.nx), j = (int)((n / K.nx) % K.ny), k = (int)(n / ((long long)K.nx * K.ny));
     const long long nm = (long long)wrapi(-i, K.nx) +
                          (long long)K.nx * ((long long)wrapi(-j, K.ny) + (long long)K.ny * wrapi(-k, K.nz));
     double S[3];
@@ -405,9 +389,10 @@ void fft_dir(const Consts& K, const FftPlan& P, double2* data, int dir, int inve
   const int logn = ilog2(n);
   // enough workgroups to fill the chip: one 256-butterfly stage per workgroup (n <= 512),
   // at least two adjacent lines for the strided passes (32-byte segments)
-  int lpb = 512 / n;
+  // contiguous lines: enough per workgroup for one 256-butterfly stage (n <= 512); strided
+  // lines: 16 adjacent ones, so that every row of the block reads 256 contiguous bytes
+  int lpb = (dir == 0) ? 512 / n : 16;
   if (lpb < 1) lpb = 1;
-  if (dir != 0 && lpb < 2) lpb = 2;
   if (lpb * n > kFftLds) lpb = kFftLds / n;
   long long nlines, la, lb, lc, pstride;
   const long long nx = K.nx, ny = K.ny;
@@ -469,7 +454,7 @@ void launch_spectral_solve(const Consts& K, const FftPlan& P, const T* r, double
   double2* z1 = work0 + K.N;
   double2* w0 = work1;
   double2* w1 = work1 + K.N;
-  const dim3 g3((K.nx + 255) / 256, K.ny, K.nz);
+  const dim3 g3((unsigned)((K.N + 255) / 256));
   if (K.dim == 2) hipLaunchKernelGGL((k_pack<2, T>), g3, dim3(256), 0, s, K, r, a, zc, z0, z1);
   else hipLaunchKernelGGL((k_pack<3, T>), g3, dim3(256), 0, s, K, r, a, zc, z0, z1);
   fft_all(K, P, z0, 0, s);
