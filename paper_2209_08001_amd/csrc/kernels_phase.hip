@@ -30,11 +30,9 @@ struct Pt {
   int i, j, k;
 };
 
-__device__ inline int wrap(int a, int n) {
-  a += (a < 0) ? n : 0;
-  a -= (a >= n) ? n : 0;
-  return a;
-}
+// periodic index: every grid side is a power of two (the Fourier solve needs it), so the
+// mask is exact for any offset, including halo columns of a block wider than the grid
+__device__ inline int wrap(int a, int n) { return a & (n - 1); }
 
 __device__ inline long long at(const Consts& K, Pt p, int di, int dj, int dk) {
   const int i = wrap(p.i + di, K.nx), j = wrap(p.j + dj, K.ny), k = wrap(p.k + dk, K.nz);
@@ -409,49 +407,33 @@ __global__ __launch_bounds__(256) void k_linearise(Consts K, const double* __res
 //   (Jv)_e = v_e/dt + L_eta (B_e. v - (gamma_eta/2) Lap_h v_e)
 //   (Jv)_u = sum_J Dhat_J sigma_IJ(v_u, v_c)   (composition enters through -eps0 v_c)
 // ---------------------------------------------------------------------------------
-// J v in one pass: one block of kBX x kBY (x 1) nodes; dG on the block and a halo of one node
-// is computed into LDS, the c row reads it there; the eta and u rows are local stencils.
-// v has element type Tv (double, or float for a mixed-precision Krylov vector); the
-// arithmetic and w are double.
+// dG_c of the J v product at point p (p may lie one node outside the block: wrapped here)
 template <int DIM, typename Tv>
-__global__ __launch_bounds__(kBX* kBY) void k_jv_fused(Consts K, double dt, const double* __restrict__ B,
-                                                       const double* __restrict__ cn,
-                                                       const Tv* __restrict__ v,
-                                                       double* __restrict__ w) {
-  constexpr int HX = kBX + 2, HY = kBY + 2, HZ = (DIM == 3) ? 3 : 1;
-  __shared__ double sdg[HX * HY * HZ];
-  const long long N = K.N;
-  int bx, by, bz;
-  xcd_block(bx, by, bz);
-  const int i0 = bx * kBX, j0 = by * kBY, k0 = bz;
-  const int tid = threadIdx.x + kBX * threadIdx.y;
-  const double Ka = -0.5 * K.eps0 * K.Ctr;
-  for (int q = tid; q < HX * HY * HZ; q += kBX * kBY) {
-    const int a = q % HX, b = (q / HX) % HY, c = q / (HX * HY);
-    Pt p{wrap(i0 + a - 1, K.nx), wrap(j0 + b - 1, K.ny), (DIM == 3) ? wrap(k0 + c - 1, K.nz) : 0};
-    const long long n = lin(K, p);
-    double vv[4];
+__device__ inline double jv_dg(const Consts& K, const double* __restrict__ B, const Tv* __restrict__ v, Pt p) {
+  const long long N = K.N, n = lin(K, p);
+  double vv[4];
 #pragma unroll
-    for (int f = 0; f < 4; ++f) vv[f] = v[f * N + n];
-    double g = K.kel * vv[0] - 0.5 * K.gamma_c * lap(K, v, p, vv[0]);
+  for (int f = 0; f < 4; ++f) vv[f] = v[f * N + n];
+  double g = K.kel * vv[0] - 0.5 * K.gamma_c * lap(K, v, p, vv[0]);
 #pragma unroll
-    for (int f = 0; f < 4; ++f) g += B[f * N + n] * vv[f];
-    if (K.elastic) {
-      double div = 0.0;
+  for (int f = 0; f < 4; ++f) g += B[f * N + n] * vv[f];
+  if (K.elastic) {
+    double div = 0.0;
 #pragma unroll
-      for (int I = 0; I < DIM; ++I) div += dhat(K, v + (4 + I) * N, p, I);
-      g += Ka * div;
-    }
-    sdg[q] = g;
+    for (int I = 0; I < DIM; ++I) div += dhat(K, v + (4 + I) * N, p, I);
+    g += -0.5 * K.eps0 * K.Ctr * div;
   }
-  __syncthreads();
-  Pt p{i0 + (int)threadIdx.x, j0 + (int)threadIdx.y, k0};
-  if (p.i >= K.nx || p.j >= K.ny) return;
-  const long long n = lin(K, p);
-  const int hq = (threadIdx.x + 1) + HX * ((threadIdx.y + 1) + ((DIM == 3) ? HY : 0));
-  const int hs[3] = {1, HX, HX * HY};
-  const double idt = 1.0 / dt;
-  // c row
+  return g;
+}
+
+// the rows of J v at p: the c row from dG in LDS (sdg[hq], its neighbours in direction dir at
+// sdg[hq + up[dir]] and sdg[hq + dn[dir]]), the eta and u rows as local stencils
+template <int DIM, typename Tv>
+__device__ inline void jv_rows(const Consts& K, double idt, const double* __restrict__ B,
+                               const double* __restrict__ cn, const Tv* __restrict__ v,
+                               double* __restrict__ w, Pt p, const double* sdg, int hq, const int* up,
+                               const int* dn) {
+  const long long N = K.N, n = lin(K, p);
   {
     const double mc = cn[n] * (1.0 - cn[n]);
     const double g0 = sdg[hq];
@@ -461,7 +443,7 @@ __global__ __launch_bounds__(kBX* kBY) void k_jv_fused(Consts K, double dt, cons
       const long long np = at_dir(K, p, dir, 1), nm = at_dir(K, p, dir, -1);
       const double Mp = 0.5 * K.kappa * (mc + cn[np] * (1.0 - cn[np]));
       const double Mm = 0.5 * K.kappa * (mc + cn[nm] * (1.0 - cn[nm]));
-      s += Mp * (sdg[hq + hs[dir]] - g0) - Mm * (g0 - sdg[hq - hs[dir]]);
+      s += Mp * (sdg[hq + up[dir]] - g0) - Mm * (g0 - sdg[hq + dn[dir]]);
     }
     w[n] = (double)v[n] * idt - s * K.ih2;
   }
@@ -478,6 +460,71 @@ __global__ __launch_bounds__(kBX* kBY) void k_jv_fused(Consts K, double dt, cons
 #pragma unroll
   for (int I = 0; I < DIM; ++I) {
     w[(4 + I) * N + n] = K.elastic ? div_sigma(K, v + 4 * N, N, v, 0.0, p, I) : (double)v[(4 + I) * N + n];
+  }
+}
+
+// J v in 2D, one pass: a block of kBX x kJY2 nodes computes dG on the block and a halo of one
+// node into LDS; the c row reads it there.  v has element type Tv (double, or float for a
+// mixed-precision Krylov vector); the arithmetic and w are double.
+constexpr int kJY2 = 8;
+template <typename Tv>
+__global__ __launch_bounds__(kBX* kJY2) void k_jv2(Consts K, double dt, const double* __restrict__ B,
+                                                   const double* __restrict__ cn, const Tv* __restrict__ v,
+                                                   double* __restrict__ w) {
+  constexpr int HX = kBX + 2, HY = kJY2 + 2;
+  __shared__ double sdg[HX * HY];
+  int bx, by, bz;
+  xcd_block(bx, by, bz);
+  const int i0 = bx * kBX, j0 = by * kJY2;
+  const int tid = threadIdx.x + kBX * threadIdx.y;
+  for (int q = tid; q < HX * HY; q += kBX * kJY2) {
+    const int a = q % HX, b = q / HX;
+    sdg[q] = jv_dg<2>(K, B, v, Pt{wrap(i0 + a - 1, K.nx), wrap(j0 + b - 1, K.ny), 0});
+  }
+  __syncthreads();
+  const Pt p{i0 + (int)threadIdx.x, j0 + (int)threadIdx.y, 0};
+  if (p.i >= K.nx || p.j >= K.ny) return;
+  const int up[2] = {1, HX}, dn[2] = {-1, -HX};
+  jv_rows<2>(K, 1.0 / dt, B, cn, v, w, p, sdg, (threadIdx.x + 1) + HX * (threadIdx.y + 1), up, dn);
+}
+
+// J v in 3D: a block of kBX x kBY columns marches through kJZ planes in z, keeping three
+// planes of dG (with their one-node halo in x and y) in LDS, so dG is formed once per node
+// and halo column instead of once per node of a 3 x 3 x 3 neighbourhood.
+constexpr int kJZ = 4;
+template <typename Tv>
+__global__ __launch_bounds__(kBX* kBY) void k_jv3(Consts K, double dt, const double* __restrict__ B,
+                                                  const double* __restrict__ cn, const Tv* __restrict__ v,
+                                                  double* __restrict__ w, int zc) {
+  constexpr int HX = kBX + 2, HY = kBY + 2, HP = HX * HY;
+  __shared__ double sdg[3 * HP];
+  int bx, by, bz;
+  xcd_block(bx, by, bz);
+  const int i0 = bx * kBX, j0 = by * kBY, z0 = bz * zc;
+  const int tid = threadIdx.x + kBX * threadIdx.y;
+  auto plane = [&](int z) {  // dG of plane z (wrapped) into slot z mod 3
+    double* dst = sdg + ((z + 3) % 3) * HP;
+    for (int q = tid; q < HP; q += kBX * kBY) {
+      const int a = q % HX, b = q / HX;
+      dst[q] = jv_dg<3>(K, B, v, Pt{wrap(i0 + a - 1, K.nx), wrap(j0 + b - 1, K.ny), wrap(z, K.nz)});
+    }
+  };
+  plane(z0 - 1);
+  plane(z0);
+  const bool live = (i0 + (int)threadIdx.x < K.nx) && (j0 + (int)threadIdx.y < K.ny);
+  const double idt = 1.0 / dt;
+  for (int z = z0; z < z0 + zc; ++z) {
+    plane(z + 1);
+    __syncthreads();
+    if (live) {
+      // centre plane in slot z mod 3, its z neighbours in the slots of z + 1 and z - 1
+      const int sz = (z + 3) % 3;
+      const int hq = sz * HP + (threadIdx.x + 1) + HX * (threadIdx.y + 1);
+      const int up[3] = {1, HX, ((z + 4) % 3 - sz) * HP};
+      const int dn[3] = {-1, -HX, ((z + 2) % 3 - sz) * HP};
+      jv_rows<3>(K, idt, B, cn, v, w, Pt{i0 + (int)threadIdx.x, j0 + (int)threadIdx.y, z}, sdg, hq, up, dn);
+    }
+    __syncthreads();
   }
 }
 
@@ -564,10 +611,14 @@ void launch_linearise(const Consts& K, const double* X, const double* Xn, double
 template <typename Tv>
 void launch_jv(const Consts& K, double dt, const double* B, const double* cn, const Tv* v, double* w,
                hipStream_t s) {
-  if (K.dim == 2)
-    hipLaunchKernelGGL((k_jv_fused<2, Tv>), stencil_grid(K), dim3(kBX, kBY), 0, s, K, dt, B, cn, v, w);
-  else
-    hipLaunchKernelGGL((k_jv_fused<3, Tv>), stencil_grid(K), dim3(kBX, kBY), 0, s, K, dt, B, cn, v, w);
+  if (K.dim == 2) {
+    const dim3 g((K.nx + kBX - 1) / kBX, (K.ny + kJY2 - 1) / kJY2, 1);
+    hipLaunchKernelGGL((k_jv2<Tv>), g, dim3(kBX, kJY2), 0, s, K, dt, B, cn, v, w);
+  } else {
+    const int zc = K.nz < kJZ ? K.nz : kJZ;  // nz is a power of two: zc divides it
+    const dim3 g((K.nx + kBX - 1) / kBX, (K.ny + kBY - 1) / kBY, K.nz / zc);
+    hipLaunchKernelGGL((k_jv3<Tv>), g, dim3(kBX, kBY), 0, s, K, dt, B, cn, v, w, zc);
+  }
 }
 template void launch_jv<double>(const Consts&, double, const double*, const double*, const double*, double*,
                                 hipStream_t);
