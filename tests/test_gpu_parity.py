@@ -4,8 +4,12 @@ Tolerances.  Kernel-level results (F, J v, energy) differ from the oracle only b
 order: each entry sums at most ~60 FP64 terms whose magnitude is at most ~1e3 times the
 largest entry of the field for these random states, so |gpu - oracle| <= 60 * 1.1e-16 * 1e3
 ~ 1e-11 relative to the field's max-norm; the tests use 1e-10.  Step-level results compare
-the Newton-Krylov root (stopped at ||F|| <= 1e-8 ||F_0||, GMRES at 1e-6) with the oracle's
-exact-LU root: the required bound is 1e-8 relative to the field's max-norm.
+the root the GPU's Newton-Krylov iteration converges to with the oracle's exact-LU root,
+within 1e-8 relative to the field's max-norm.  The distance of an iterate from the root is
+bounded by |J^{-1}| |F|, so a residual stop at the paper's 1e-8 leaves up to ~1e-8 (observed
+up to 1.1e-8 with the default solver); the root comparisons therefore stop Newton at
+ROOT_RTOL = 1e-10, and the full-size tests check the 1e-8 residual stop itself with the
+oracle's residual.
 """
 
 import sys
@@ -20,6 +24,8 @@ from oracle.scheme import strain_el
 from paper_2209_08001_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
+
+ROOT_RTOL = 1e-10
 
 
 def _cuda():
@@ -230,7 +236,7 @@ def test_step_parity_pf2d_64(oracle_c1, pc, prec):
     c0, e0, traj, info, o = oracle_c1
     _note(f"step parity pf2d_64 pc={pc} precision={prec}")
     p = _problem((64, 64), c0, e0, pc=pfnks.PC_RAS if pc == "ras" else pfnks.PC_RAS_SPECTRAL,
-                 precision=pfnks.MIXED if prec == "mixed" else pfnks.FP64)
+                 precision=pfnks.MIXED if prec == "mixed" else pfnks.FP64, newton_rtol=ROOT_RTOL)
     m0 = p.mass()
     E_prev = p.energy()[0]
     for k in range(10):
@@ -263,7 +269,7 @@ def test_step_parity_tile_shapes(oracle_c1, tile, prec, overlap):
     c0, e0, traj, info, o = oracle_c1
     _note(f"step parity pf2d_64 tile={tile} overlap={overlap} precision={prec}")
     p = _problem((64, 64), c0, e0, tile=(tile[0], tile[1], 1), overlap=overlap,
-                 precision=pfnks.MIXED if prec == "mixed" else pfnks.FP64)
+                 precision=pfnks.MIXED if prec == "mixed" else pfnks.FP64, newton_rtol=ROOT_RTOL)
     for k in range(3):
         st = p.step(0.01)
         X, _ = p.get_state()
@@ -292,7 +298,8 @@ def test_batch_step_equals_single_and_oracle(oracle_c1):
     batch = []
     for n, seed, prec in specs:
         cc, ee = (c0, e0) if seed is None else W.init_fields(n, seed)
-        sv = dict(W.DEFAULT_SOLVER, precision=pfnks.MIXED if prec == "mixed" else pfnks.FP64)
+        sv = dict(W.DEFAULT_SOLVER, precision=pfnks.MIXED if prec == "mixed" else pfnks.FP64,
+                  newton_rtol=ROOT_RTOL)
         sv["tile"] = (4, 4, 4) if len(n) == 3 else (16, 16, 1)
         sv["overlap"] = 1 if len(n) == 3 else 2
         batch.append(pfnks.Problem(n, W.H, W.DEFAULT_MODEL, sv, cc, ee, stream=torch.cuda.Stream()))
@@ -302,7 +309,8 @@ def test_batch_step_equals_single_and_oracle(oracle_c1):
     alone = []
     for n, seed, prec in specs:
         cc, ee = (c0, e0) if seed is None else W.init_fields(n, seed)
-        sv = dict(W.DEFAULT_SOLVER, precision=pfnks.MIXED if prec == "mixed" else pfnks.FP64)
+        sv = dict(W.DEFAULT_SOLVER, precision=pfnks.MIXED if prec == "mixed" else pfnks.FP64,
+                  newton_rtol=ROOT_RTOL)
         sv["tile"] = (4, 4, 4) if len(n) == 3 else (16, 16, 1)
         sv["overlap"] = 1 if len(n) == 3 else 2
         q = pfnks.Problem(n, W.H, W.DEFAULT_MODEL, sv, cc, ee)
@@ -366,7 +374,8 @@ def test_p1_particle_parity(oracle_particle, prec):
     _cuda()
     n, c0, e0, traj = oracle_particle
     _note(f"P=1 particle parity precision={prec}")
-    p = _problem(n, c0, e0, model=W.P1_MODEL, precision=pfnks.MIXED if prec == "mixed" else pfnks.FP64)
+    p = _problem(n, c0, e0, model=W.P1_MODEL, precision=pfnks.MIXED if prec == "mixed" else pfnks.FP64,
+                 newton_rtol=ROOT_RTOL)
     E_prev = p.energy()[0]
     for k in range(2):
         st = p.step(0.01)
@@ -379,6 +388,30 @@ def test_p1_particle_parity(oracle_particle, prec):
         assert sym <= 1e-13
         assert st["energy"] <= E_prev + 1e-12 * abs(E_prev)
         E_prev = st["energy"]
+    p.close()
+
+
+def test_stop_rule_pf2d_64(oracle_c1):
+    """With the paper's tolerances (Newton 1e-8, GMRES 1e-6) every step of pf2d_64 stops at
+    a point whose residual, evaluated by the oracle from the GPU's own previous state, is
+    below 1e-8 of the residual at that state (10 % slack for the evaluation's rounding)."""
+    _cuda()
+    c0, e0, traj, info, o = oracle_c1
+    _note("stop rule pf2d_64 (default tolerances)")
+    n = (64, 64)
+    p = _problem(n, c0, e0)
+    g = Grid(n, W.H)
+    m = Model.from_dict(W.DEFAULT_MODEL)
+    cb0 = float(c0.mean())
+    Xp, _ = p.get_state()
+    for k in range(4):
+        p.step(0.01)
+        X, _ = p.get_state()
+        r0 = np.linalg.norm(residual(Xp, Xp, 0.01, g, m, cb0))
+        r1 = np.linalg.norm(residual(X, Xp, 0.01, g, m, cb0))
+        _note(f"  step {k}: |F(X)|/|F(Xn)| = {r1 / r0:.2e}")
+        assert r1 <= 1.1e-8 * r0
+        Xp = X
     p.close()
 
 
@@ -423,7 +456,7 @@ def test_step_parity_3d(oracle_3d, pc, prec):
     _note(f"step parity 3d pc={pc} precision={prec}")
     p = _problem(n, c0, e0, tile=(4, 4, 4), overlap=1,
                  pc=pfnks.PC_RAS if pc == "ras" else pfnks.PC_RAS_SPECTRAL,
-                 precision=pfnks.MIXED if prec == "mixed" else pfnks.FP64)
+                 precision=pfnks.MIXED if prec == "mixed" else pfnks.FP64, newton_rtol=ROOT_RTOL)
     m0 = p.mass()
     for k, dt in enumerate((0.01, 0.05)):
         st = p.step(dt)
