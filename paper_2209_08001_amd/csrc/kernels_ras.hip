@@ -52,7 +52,8 @@ __global__ __launch_bounds__(TH, (TH == kRasThreadsSmall) ? 2 : 1) void k_ras(Co
                                                      const R* __restrict__ Bg,
                                                      const double* __restrict__ cn,
                                                      const R* __restrict__ rg,
-                                                     R* __restrict__ zg) {
+                                                     R* __restrict__ zg,
+                                                     const int* __restrict__ permg) {
   constexpr int NFZ = WU ? 4 + DIM : 4;
   constexpr int NCOL = (DIM == 3) ? 7 : 5;
   extern __shared__ double lds_raw[];
@@ -64,9 +65,6 @@ __global__ __launch_bounds__(TH, (TH == kRasThreadsSmall) ? 2 : 1) void k_ras(Co
   R* dg = zs + NFZ * zsz;   // dsz: dG on ext and a ring of 1
   R* gg = dg + dsz;         // dsz: g = c^n (1 - c^n)
   R* bc = gg + dsz;         // 4 planes of ne: c-row of the chemical block
-  int* perm = (int*)(bc + 4 * ne);  // ne: ext nodes sorted by colour
-  int* rowoff = perm + ne;          // NCOL * rows: colour offsets of each row
-  __shared__ int cstart[NCOL + 1], cfill[NCOL];
 
   // tile of this workgroup: workgroups go to the 8 XCDs round-robin, so each XCD is given a
   // contiguous run of tiles (whole tile rows) and the overlap shared by neighbouring tiles is
@@ -80,6 +78,9 @@ __global__ __launch_bounds__(TH, (TH == kRasThreadsSmall) ? 2 : 1) void k_ras(Co
   const int ty_ = G.dx, tz_ = G.dx * G.dy;  // strides of dG / g
   const int ring = 2;
 
+  // Set-up, one barrier: g and dG = 0 on ext and its ring, the c-row blocks (coalesced), the
+  // zero iterate, and each thread's own nodes (right-hand side and eta rows of the blocks,
+  // straight into registers).
   for (int q = threadIdx.x; q < dsz; q += TH) {
     const int a = q % G.dx, b = (q / G.dx) % G.dy, c = q / (G.dx * G.dy);
     const int gi = wrapg(ox + a - 1, K.nx), gj = wrapg(oy + b - 1, K.ny);
@@ -88,8 +89,6 @@ __global__ __launch_bounds__(TH, (TH == kRasThreadsSmall) ? 2 : 1) void k_ras(Co
     gg[q] = (R)(v * (1.0 - v));
     dg[q] = R(0);
   }
-  __syncthreads();
-  // c-row blocks into LDS
   for (int q = threadIdx.x; q < ne; q += TH) {
     const int a = q % G.ex, b = (q / G.ex) % G.ey, c = q / (G.ex * G.ey);
     const int gi = wrapg(ox + a, K.nx), gj = wrapg(oy + b, K.ny);
@@ -98,53 +97,15 @@ __global__ __launch_bounds__(TH, (TH == kRasThreadsSmall) ? 2 : 1) void k_ras(Co
 #pragma unroll
     for (int f = 0; f < 4; ++f) bc[f * ne + q] = Bg[f * N + n];
   }
-  // Colour-sorted order, computed arithmetically: in row (b, c) the nodes of colour col are
-  // a = r0 + NCOL m with r0 = (col - 2b - 3c) mod NCOL; rowoff[col][row] is the number of
-  // colour-col nodes in the rows before.  (The order inside a colour is immaterial: nodes of
-  // one colour do not couple.)
-  const int nrow = G.ey * G.ez;
-  for (int idx = threadIdx.x; idx < NCOL * nrow; idx += TH) {
-    const int col = idx / nrow, row = idx % nrow;
-    int acc = 0;
-    for (int r = 0; r < row; ++r) {
-      const int b = r % G.ey, c = r / G.ey;
-      const int r0 = ((col - 2 * b - ((DIM == 3) ? 3 * c : 0)) % NCOL + NCOL) % NCOL;
-      acc += (r0 < G.ex) ? (G.ex - 1 - r0) / NCOL + 1 : 0;
-    }
-    rowoff[idx] = acc;
-  }
-  __syncthreads();
-  if (threadIdx.x < NCOL) {
-    const int col = threadIdx.x, r = nrow - 1;
-    const int b = r % G.ey, c = r / G.ey;
-    const int r0 = ((col - 2 * b - ((DIM == 3) ? 3 * c : 0)) % NCOL + NCOL) % NCOL;
-    cfill[col] = rowoff[col * nrow + r] + ((r0 < G.ex) ? (G.ex - 1 - r0) / NCOL + 1 : 0);
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int acc = 0;
-    for (int c = 0; c < NCOL; ++c) {
-      cstart[c] = acc;
-      acc += cfill[c];
-    }
-    cstart[NCOL] = acc;
-  }
-  __syncthreads();
-  for (int q = threadIdx.x; q < ne; q += TH) {
-    const int a = q % G.ex, b = (q / G.ex) % G.ey, c = q / (G.ex * G.ey);
-    const int col = (DIM == 3) ? (a + 2 * b + 3 * c) % 7 : (a + 2 * b) % 5;
-    const int r0 = ((col - 2 * b - ((DIM == 3) ? 3 * c : 0)) % NCOL + NCOL) % NCOL;
-    perm[cstart[col] + rowoff[col * nrow + b + G.ey * c] + (a - r0) / NCOL] = q;
-  }
-  __syncthreads();
+  for (int q = threadIdx.x; q < NFZ * zsz; q += TH) zs[q] = R(0);
 
-  // nodes of this thread: right-hand side and eta-rows of the chemical block in registers.
-  // The planes are staged through LDS four at a time with row-major (coalesced) loads and
-  // then picked up by the thread that owns each node in colour order.
+  // Nodes of this thread: positions threadIdx.x + m TH of the colour-sorted order permg (ext
+  // nodes grouped by colour, the same for every tile of this shape; formed by the host), so
+  // the nodes of one colour sit on consecutive threads.
   R rr[NPT][NFZ];
   R be[NPT][12];
   // per node, packed in 16-bit halves (every index is below 2^16): zd = iterate position |
-  // dG position << 16, qc = ext index | (colour + 1) << 16 (colour -1: no node)
+  // dG position << 16; qc = ext index
   int zd_[NPT], qc_[NPT];
   int col_[NPT];
 #pragma unroll
@@ -153,48 +114,27 @@ __global__ __launch_bounds__(TH, (TH == kRasThreadsSmall) ? 2 : 1) void k_ras(Co
     col_[m] = -1;
     zd_[m] = qc_[m] = 0;
     if (pos < ne) {
-      const int q = perm[pos];
+      const int q = permg[pos];
       const int a = q % G.ex, b = (q / G.ex) % G.ey, c = q / (G.ex * G.ey);
       const int zi = (a + ring) + sy * (b + ring) + ((DIM == 3) ? sz * (c + ring) : 0);
       const int di = (a + 1) + ty_ * (b + 1) + ((DIM == 3) ? tz_ * (c + 1) : 0);
       col_[m] = (DIM == 3) ? (a + 2 * b + 3 * c) % 7 : (a + 2 * b) % 5;
       zd_[m] = zi | (di << 16);
       qc_[m] = q;
-    }
-  }
-  constexpr int NPL = NFZ + 12;  // staged planes: r (NFZ), then B rows 1..3 (12)
-  for (int p0 = 0; p0 < NPL; p0 += 4) {
-    const int np = (NPL - p0 < 4) ? NPL - p0 : 4;
-    for (int q = threadIdx.x; q < ne; q += TH) {
-      const int a = q % G.ex, b = (q / G.ex) % G.ey, c = q / (G.ex * G.ey);
       const int gi = wrapg(ox + a, K.nx), gj = wrapg(oy + b, K.ny);
       const int gk = (DIM == 3) ? wrapg(oz + c, K.nz) : 0;
       const long long n = gi + (long long)K.nx * (gj + (long long)K.ny * gk);
-      for (int k = 0; k < np; ++k) {
-        const int pl = p0 + k;
-        zs[k * ne + q] = (pl < NFZ) ? rg[pl * N + n] : Bg[(4 + pl - NFZ) * N + n];
-      }
+#pragma unroll
+      for (int f = 0; f < NFZ; ++f) rr[m][f] = rg[f * N + n];
+#pragma unroll
+      for (int f = 0; f < 12; ++f) be[m][f] = Bg[(4 + f) * N + n];
+    } else {
+#pragma unroll
+      for (int f = 0; f < NFZ; ++f) rr[m][f] = R(0);
+#pragma unroll
+      for (int f = 0; f < 12; ++f) be[m][f] = R(0);
     }
-    __syncthreads();
-#pragma unroll
-    for (int m = 0; m < NPT; ++m) {
-      if (col_[m] < 0) continue;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int pl = p0 + k;
-        if (k >= np) break;
-        const R v = zs[k * ne + qc_[m]];
-#pragma unroll
-        for (int f = 0; f < NFZ; ++f)
-          if (pl == f) rr[m][f] = v;
-#pragma unroll
-        for (int f = 0; f < 12; ++f)
-          if (pl == NFZ + f) be[m][f] = v;
-      }
-    }
-    __syncthreads();
   }
-  for (int q = threadIdx.x; q < NFZ * zsz; q += TH) zs[q] = R(0);
   __syncthreads();
 
   // coefficients in the arithmetic type of the solve (formed in double, rounded once)
@@ -458,12 +398,12 @@ Geo make_geo(const Consts& K, const TileCfg& T) {
 
 template <int DIM, bool WU, typename R, int TH>
 void launch_npt(const Geo& G, const Consts& K, size_t lds, int ntiles, int npt, double dt, const R* B,
-                const double* cn, const R* r, R* z, hipStream_t s) {
+                const double* cn, const R* r, R* z, const int* perm, hipStream_t s) {
 #define PF_RAS_CASE(NPTV)                                                                             \
   case NPTV:                                                                                          \
     (void)hipFuncSetAttribute((const void*)k_ras<DIM, WU, NPTV, R, TH>,                              \
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                  \
-    hipLaunchKernelGGL((k_ras<DIM, WU, NPTV, R, TH>), dim3(ntiles), dim3(TH), lds, s, K, G, dt, B, cn, r, z); \
+    hipLaunchKernelGGL((k_ras<DIM, WU, NPTV, R, TH>), dim3(ntiles), dim3(TH), lds, s, K, G, dt, B, cn, r, z, perm); \
     break;
   switch (npt) {
     PF_RAS_CASE(1)
@@ -476,11 +416,11 @@ void launch_npt(const Geo& G, const Consts& K, size_t lds, int ntiles, int npt, 
 
 template <int DIM, bool WU, typename R>
 void launch_dim(const Consts& K, const Geo& G, size_t lds, int ntiles, int th, int npt, double dt,
-                const R* B, const double* cn, const R* r, R* z, hipStream_t s) {
+                const R* B, const double* cn, const R* r, R* z, const int* perm, hipStream_t s) {
   if (!WU && th == kRasThreadsSmall)
-    launch_npt<DIM, false, R, kRasThreadsSmall>(G, K, lds, ntiles, npt, dt, B, cn, r, z, s);
+    launch_npt<DIM, false, R, kRasThreadsSmall>(G, K, lds, ntiles, npt, dt, B, cn, r, z, perm, s);
   else
-    launch_npt<DIM, WU, R, kRasThreadsMax>(G, K, lds, ntiles, npt, dt, B, cn, r, z, s);
+    launch_npt<DIM, WU, R, kRasThreadsMax>(G, K, lds, ntiles, npt, dt, B, cn, r, z, perm, s);
 }
 
 // nodes of the extended tile per thread (1..3) at th threads, 0 if more than three
@@ -497,9 +437,25 @@ size_t ras_lds_bytes(const Consts& K, const TileCfg& T, size_t real_bytes) {
   const Geo G = make_geo(K, T);
   const int nfz = T.with_u ? 4 + K.dim : 4;
   const size_t ne = (size_t)G.ex * G.ey * G.ez;
-  const size_t ncol = (K.dim == 3) ? 7 : 5;
-  return real_bytes * ((size_t)nfz * G.zx * G.zy * G.zz + 2 * (size_t)G.dx * G.dy * G.dz + 4 * ne) +
-         sizeof(int) * (ne + ncol * G.ey * G.ez);
+  return real_bytes * ((size_t)nfz * G.zx * G.zy * G.zz + 2 * (size_t)G.dx * G.dy * G.dz + 4 * ne);
+}
+
+int ras_ext_nodes(const Consts& K, const TileCfg& T) {
+  const Geo G = make_geo(K, T);
+  return G.ex * G.ey * G.ez;
+}
+
+void ras_colour_order(const Consts& K, const TileCfg& T, int* perm) {
+  const Geo G = make_geo(K, T);
+  const int ncol = (K.dim == 3) ? 7 : 5;
+  int pos = 0;
+  for (int col = 0; col < ncol; ++col)
+    for (int c = 0; c < G.ez; ++c)
+      for (int b = 0; b < G.ey; ++b)
+        for (int a = 0; a < G.ex; ++a) {
+          const int ca = (K.dim == 3) ? (a + 2 * b + 3 * c) % 7 : (a + 2 * b) % 5;
+          if (ca == col) perm[pos++] = a + G.ex * (b + G.ey * c);
+        }
 }
 
 int ras_threads(const Consts& K, const TileCfg& T, size_t real_bytes, int* npt) {
@@ -523,11 +479,11 @@ void launch_ras(const Consts& K, const TileCfg& T, double dt, const R* B, const 
   int npt = 0;
   const int th = ras_threads(K, T, sizeof(R), &npt);
   if (K.dim == 2) {
-    if (T.with_u) launch_dim<2, true, R>(K, G, lds, ntiles, th, npt, dt, B, cn, r, z, s);
-    else launch_dim<2, false, R>(K, G, lds, ntiles, th, npt, dt, B, cn, r, z, s);
+    if (T.with_u) launch_dim<2, true, R>(K, G, lds, ntiles, th, npt, dt, B, cn, r, z, T.perm, s);
+    else launch_dim<2, false, R>(K, G, lds, ntiles, th, npt, dt, B, cn, r, z, T.perm, s);
   } else {
-    if (T.with_u) launch_dim<3, true, R>(K, G, lds, ntiles, th, npt, dt, B, cn, r, z, s);
-    else launch_dim<3, false, R>(K, G, lds, ntiles, th, npt, dt, B, cn, r, z, s);
+    if (T.with_u) launch_dim<3, true, R>(K, G, lds, ntiles, th, npt, dt, B, cn, r, z, T.perm, s);
+    else launch_dim<3, false, R>(K, G, lds, ntiles, th, npt, dt, B, cn, r, z, T.perm, s);
   }
 }
 template void launch_ras<double>(const Consts&, const TileCfg&, double, const double*, const double*,

@@ -54,6 +54,7 @@ struct TileCfg {
   int ov;           // overlap delta
   int sweeps;       // symmetric GS sweeps
   int with_u;       // 1: all fields (plain RAS); 0: (c, eta) block only
+  const int* perm;  // device: nodes of the extended tile sorted by colour (ras_colour_order)
 };
 // R (double or float): element type of the blocks B, of r and z, and of the tile arithmetic
 template <typename R>
@@ -63,6 +64,9 @@ size_t ras_lds_bytes(const Consts& K, const TileCfg& T, size_t real_bytes);
 // workgroup size of the tile kernel for this tile shape and element size (0: shape not
 // supported); *npt (may be null): nodes of the extended tile per thread
 int ras_threads(const Consts& K, const TileCfg& T, size_t real_bytes, int* npt);
+// nodes of one extended tile, and their colour-sorted order (host; the same for every tile)
+int ras_ext_nodes(const Consts& K, const TileCfg& T);
+void ras_colour_order(const Consts& K, const TileCfg& T, int* perm);
 
 // ---- spectral displacement solve (kernels_fft.hip) -----------------------------------
 struct FftPlan {

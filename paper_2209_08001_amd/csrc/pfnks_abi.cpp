@@ -47,7 +47,7 @@ struct Layout {
 
 enum Buf {
   B_X, B_XN, B_XT, B_F, B_FT, B_S, B_B, B_BPC, B_G4, B_V, B_ZB, B_W, B_Z, B_TMP, B_TMPV, B_PART, B_RED,
-  B_FFT0, B_FFT1, B_TW0, B_TW1, B_TW2, B_SN0, B_SN1, B_SN2, B_HDEV, B_COUNT
+  B_FFT0, B_FFT1, B_TW0, B_TW1, B_TW2, B_SN0, B_SN1, B_SN2, B_HDEV, B_PERM, B_COUNT
 };
 
 // bytes of one element of the Krylov basis, the preconditioner blocks and the tile solve
@@ -58,7 +58,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // Krylov basis V, the preconditioned basis Z, the single vectors z and tmpv and the lagged
 // preconditioner blocks Bpc are stored in the Krylov element type (float when mixed); the
 // state, residuals, Newton update S, J v output w and the Jacobian blocks B are double.
-Layout make_layout(int dim, long long N, int restart, const int* n, int precision) {
+Layout make_layout(int dim, long long N, int restart, const int* n, int precision, long long ext_nodes) {
   const int nf = 4 + dim;
   const size_t kb = krylov_bytes(precision);
   const size_t vec = sizeof(double) * (size_t)nf * N;
@@ -84,6 +84,7 @@ Layout make_layout(int dim, long long N, int restart, const int* n, int precisio
   sz[B_SN1] = sizeof(double) * (size_t)n[1];
   sz[B_SN2] = sizeof(double) * (size_t)(dim == 3 ? n[2] : 2);
   sz[B_HDEV] = sizeof(double) * (size_t)(restart + 1) * (restart + 2);
+  sz[B_PERM] = sizeof(int) * (size_t)ext_nodes;  // colour order of one extended tile
   Layout L{};
   size_t o = 0;
   for (int b = 0; b < B_COUNT; ++b) {
@@ -92,6 +93,13 @@ Layout make_layout(int dim, long long N, int restart, const int* n, int precisio
   }
   L.total = o;
   return L;
+}
+
+// nodes of one extended Schwarz tile
+long long ext_nodes(const pfnks_grid* g, const pfnks_solver* s) {
+  long long e = 1;
+  for (int k = 0; k < g->dim; ++k) e *= s->tile[k] + 2 * s->overlap;
+  return e;
 }
 
 int validate(const pfnks_grid* g, const pfnks_model* m, const pfnks_solver* s) {
@@ -123,12 +131,8 @@ int validate(const pfnks_grid* g, const pfnks_model* m, const pfnks_solver* s) {
   }
   if (ext > 3 * 512) return PFNKS_EINVAL;
   const int nfz = (s->pc == PFNKS_PC_RAS) ? 4 + g->dim : 4;
-  const long long rows = (g->dim == 3) ? (long long)(s->tile[1] + 2 * s->overlap) * (s->tile[2] + 2 * s->overlap)
-                                       : (long long)(s->tile[1] + 2 * s->overlap);
-  const long long ncol = (g->dim == 3) ? 7 : 5;
   const long long kb = (long long)krylov_bytes(s->precision);
-  if (s->pc <= PFNKS_PC_RAS_SPECTRAL && kb * (nfz * zpad + 2 * dpad + 4 * ext) + 4 * (ext + ncol * rows) > 160 * 1024)
-    return PFNKS_EINVAL;
+  if (s->pc <= PFNKS_PC_RAS_SPECTRAL && kb * (nfz * zpad + 2 * dpad + 4 * ext) > 160 * 1024) return PFNKS_EINVAL;
   return PFNKS_OK;
 }
 
@@ -552,7 +556,7 @@ int pfnks_workspace_bytes(const pfnks_grid* grid, const pfnks_model* model, cons
   int st = validate(grid, model, solver);
   if (st) return st;
   const long long N = (long long)grid->n[0] * grid->n[1] * (grid->dim == 3 ? grid->n[2] : 1);
-  *bytes = make_layout(grid->dim, N, solver->gmres_restart, grid->n, solver->precision).total;
+  *bytes = make_layout(grid->dim, N, solver->gmres_restart, grid->n, solver->precision, ext_nodes(grid, solver)).total;
   return PFNKS_OK;
 }
 
@@ -565,7 +569,7 @@ int pfnks_create_problem(const pfnks_grid* grid, const pfnks_model* model, const
   if (st) return st;
   if (((uintptr_t)d_workspace & 255) != 0) return PFNKS_EINVAL;
   const long long N = (long long)grid->n[0] * grid->n[1] * (grid->dim == 3 ? grid->n[2] : 1);
-  const Layout L = make_layout(grid->dim, N, solver->gmres_restart, grid->n, solver->precision);
+  const Layout L = make_layout(grid->dim, N, solver->gmres_restart, grid->n, solver->precision, ext_nodes(grid, solver));
   if (ws_bytes < L.total) return PFNKS_ENOSPACE;
   st = check_domain_host(c0, eta0, N);
   if (st) return st;
@@ -595,6 +599,7 @@ int pfnks_create_problem(const pfnks_grid* grid, const pfnks_model* model, const
   p->T.ov = solver->overlap;
   p->T.sweeps = solver->sweeps;
   p->T.with_u = 0;
+  p->T.perm = (const int*)(p->ws + L.off[B_PERM]);
   pf::TileCfg tcheck = p->T;
   tcheck.with_u = (solver->pc == PFNKS_PC_RAS) ? 1 : 0;
   if (solver->pc <= PFNKS_PC_RAS_SPECTRAL && pf::ras_threads(p->K, tcheck, krylov_bytes(solver->precision), nullptr) == 0) {
@@ -665,6 +670,13 @@ int pfnks_create_problem(const pfnks_grid* grid, const pfnks_model* model, const
     e = hipMemcpy(sdst, sn.data(), sizeof(double) * nd, hipMemcpyHostToDevice);
     if (e != hipSuccess) return fail(device_error(e, "hipMemcpy symbols"));
     p->plan.sn[d] = sdst;
+  }
+  // colour order of the extended tile (the same for every tile), for the Schwarz kernel
+  {
+    std::vector<int> order((size_t)pf::ras_ext_nodes(p->K, p->T));
+    pf::ras_colour_order(p->K, p->T, order.data());
+    e = hipMemcpy((void*)p->T.perm, order.data(), sizeof(int) * order.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail(device_error(e, "hipMemcpy colour order"));
   }
   // state: c, eta, u = 0
   e = hipMemcpy(p->Xn, c0, sizeof(double) * N, hipMemcpyHostToDevice);
