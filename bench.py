@@ -32,6 +32,12 @@ KERNEL_SOURCE = {"residual": "kernels_phase.hip", "linearise": "kernels_phase.hi
                  "update": "kernels_blas.hip"}
 
 
+def pc_names():
+    from paper_2209_08001_amd import pfnks
+
+    return {"ras_spectral": pfnks.PC_RAS_SPECTRAL, "ras": pfnks.PC_RAS, "as": pfnks.PC_AS, "rras": pfnks.PC_RRAS}
+
+
 def kernel_source_sha256(kind):
     import hashlib
 
@@ -124,7 +130,7 @@ def run_ensemble(args, wl):
 
     members = W.ensemble_members(wl)
     solver = dict(W.DEFAULT_SOLVER, sweeps=args.sweeps or W.default_sweeps(2, args.precision == "mixed"),
-                  pc=pfnks.PC_RAS if args.pc == "ras" else pfnks.PC_RAS_SPECTRAL,
+                  pc=pc_names()[args.pc],
                   precision=pfnks.MIXED if args.precision == "mixed" else pfnks.FP64)
     dev = "cuda:0"
 
@@ -192,7 +198,7 @@ def run_serving(args, wl):
     from paper_2209_08001_amd.serve import Server, poisson_requests
 
     solver = dict(W.DEFAULT_SOLVER, sweeps=args.sweeps or W.default_sweeps(2, args.precision == "mixed"),
-                  pc=pfnks.PC_RAS if args.pc == "ras" else pfnks.PC_RAS_SPECTRAL,
+                  pc=pc_names()[args.pc],
                   precision=pfnks.MIXED if args.precision == "mixed" else pfnks.FP64)
     free, _ = torch.cuda.mem_get_info()
     budget = int(0.8 * free)
@@ -241,7 +247,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="pf2d_512")
-    ap.add_argument("--pc", default="ras_spectral", choices=["ras_spectral", "ras"])
+    ap.add_argument("--pc", default="ras_spectral", choices=["ras_spectral", "ras", "as", "rras"])
     ap.add_argument("--sweeps", type=int, default=None,
                     help="Gauss-Seidel sweeps of the tile solve (default: workloads.default_sweeps)")
     ap.add_argument("--tile", default=None, help="Schwarz tile, e.g. 32,32 (2D) or 8,8,8 (3D)")
@@ -285,7 +291,7 @@ def main():
     else:
         c0, e0 = W.init_fields(n, wl["seed"], cbar=wl["cbar"])
     solver = dict(W.DEFAULT_SOLVER, sweeps=args.sweeps or W.default_sweeps(2, args.precision == "mixed"),
-                  pc=pfnks.PC_RAS if args.pc == "ras" else pfnks.PC_RAS_SPECTRAL,
+                  pc=pc_names()[args.pc],
                   precision=pfnks.MIXED if args.precision == "mixed" else pfnks.FP64)
     if len(n) == 3:
         solver.update(tile=(8, 8, 8), overlap=1, sweeps=args.sweeps or W.default_sweeps(3, args.precision == "mixed"))

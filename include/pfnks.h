@@ -52,12 +52,18 @@ typedef enum { PFNKS_FP64 = 0, PFNKS_MIXED = 1 } pfnks_precision;
  * exact Fourier solve of the constant-coefficient periodic displacement block.
  * PFNKS_PC_NONE: identity (unpreconditioned GMRES; for testing and comparison).
  * PFNKS_PC_SPECTRAL: identity on (c, eta) composed with the same exact displacement solve
- * (isolates the Fourier block for testing). */
+ * (isolates the Fourier block for testing).
+ * PFNKS_PC_AS: classical additive Schwarz over all fields, z = sum_t R_t^delta' A_t^{-1}
+ * R_t^delta r (the extended solutions are summed where tiles overlap; Section 4, the paper's
+ * classical-AS runs).  PFNKS_PC_RRAS: right-RAS, z = sum_t R_t^delta' A_t^{-1} R_t^0 r (r
+ * restricted to the owned nodes).  Both need overlap <= tile side. */
 typedef enum {
   PFNKS_PC_RAS = 0,
   PFNKS_PC_RAS_SPECTRAL = 1,
   PFNKS_PC_NONE = 2,
-  PFNKS_PC_SPECTRAL = 3
+  PFNKS_PC_SPECTRAL = 3,
+  PFNKS_PC_AS = 4,
+  PFNKS_PC_RRAS = 5
 } pfnks_pc;
 
 typedef struct {

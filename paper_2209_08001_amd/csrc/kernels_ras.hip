@@ -28,6 +28,14 @@ namespace {
 // thread and two workgroups fit the LDS of one compute unit (they then overlap their barriers)
 constexpr int kRasThreadsMax = 512, kRasThreadsSmall = 256;
 
+// Schwarz variants (Section 4): left-RAS z = sum_t R0_t' A_t^{-1} R_t r (owned part of each
+// tile's solution), classical AS z = sum_t R_t' A_t^{-1} R_t r and right-RAS
+// z = sum_t R_t' A_t^{-1} R0_t r (whole extended solutions summed where tiles overlap; right-
+// RAS restricts r to the owned nodes first).  The summing variants write each tile's
+// extended solution to a scratch array and a gather kernel adds, per node, the solutions of
+// the tiles covering it in a fixed order (deterministic).
+enum { kRasLeft = 0, kRasClassical = 1, kRasRight = 2 };
+
 struct Geo {
   int ex, ey, ez;      // extended tile
   int zx, zy, zz;      // LDS iterate (ext + ring of 2; zz = 1 in 2D)
@@ -35,6 +43,7 @@ struct Geo {
   int ntx, nty;        // tiles per direction
   int tx, ty, tz, ov;
   int sweeps;
+  int mode;            // kRasLeft, kRasClassical or kRasRight
 };
 
 __device__ inline int wrapg(int a, int n) {
@@ -53,7 +62,8 @@ __global__ __launch_bounds__(TH, (TH == kRasThreadsSmall) ? 2 : 1) void k_ras(Co
                                                      const double* __restrict__ cn,
                                                      const R* __restrict__ rg,
                                                      R* __restrict__ zg,
-                                                     const int* __restrict__ permg) {
+                                                     const int* __restrict__ permg,
+                                                     R* __restrict__ xs) {
   constexpr int NFZ = WU ? 4 + DIM : 4;
   constexpr int NCOL = (DIM == 3) ? 7 : 5;
   extern __shared__ double lds_raw[];
@@ -124,8 +134,12 @@ __global__ __launch_bounds__(TH, (TH == kRasThreadsSmall) ? 2 : 1) void k_ras(Co
       const int gi = wrapg(ox + a, K.nx), gj = wrapg(oy + b, K.ny);
       const int gk = (DIM == 3) ? wrapg(oz + c, K.nz) : 0;
       const long long n = gi + (long long)K.nx * (gj + (long long)K.ny * gk);
+      // right-RAS restricts the right-hand side to the owned nodes
+      const bool owned = a >= G.ov && a < G.ov + G.tx && b >= G.ov && b < G.ov + G.ty &&
+                         (DIM == 2 || (c >= G.ov && c < G.ov + G.tz));
+      const bool keep = G.mode != kRasRight || owned;
 #pragma unroll
-      for (int f = 0; f < NFZ; ++f) rr[m][f] = rg[f * N + n];
+      for (int f = 0; f < NFZ; ++f) rr[m][f] = keep ? rg[f * N + n] : R(0);
 #pragma unroll
       for (int f = 0; f < 12; ++f) be[m][f] = Bg[(4 + f) * N + n];
     } else {
@@ -361,6 +375,17 @@ __global__ __launch_bounds__(TH, (TH == kRasThreadsSmall) ? 2 : 1) void k_ras(Co
       }
     }
   }
+  if (G.mode != kRasLeft) {
+    // the whole extended solution, to be summed by the gather kernel
+    R* out = xs + (long long)t * NFZ * ne;
+    for (int q = threadIdx.x; q < ne; q += TH) {
+      const int a = q % G.ex, b = (q / G.ex) % G.ey, c = q / (G.ex * G.ey);
+      const int zi = (a + ring) + sy * (b + ring) + ((DIM == 3) ? sz * (c + ring) : 0);
+#pragma unroll
+      for (int f = 0; f < NFZ; ++f) out[f * ne + q] = zs[f * zsz + zi];
+    }
+    return;
+  }
   // restricted prolongation: write the owned nodes only (coalesced, row-major)
   for (int q = threadIdx.x; q < ne; q += TH) {
     const int a = q % G.ex, b = (q / G.ex) % G.ey, c = q / (G.ex * G.ey);
@@ -373,6 +398,46 @@ __global__ __launch_bounds__(TH, (TH == kRasThreadsSmall) ? 2 : 1) void k_ras(Co
 #pragma unroll
     for (int f = 0; f < NFZ; ++f) zg[f * N + n] = zs[f * zsz + zi];
   }
+}
+
+// z at every node = sum of the extended solutions of the tiles whose extended block contains
+// it, tiles taken in a fixed order (at most two per direction: overlap <= tile / 2)
+template <int DIM, int NFZ, typename R>
+__global__ __launch_bounds__(256) void k_ras_gather(Consts K, Geo G, const R* __restrict__ xs, R* __restrict__ zg) {
+  const long long n = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (n >= K.N) return;
+  const int i = (int)(n % K.nx), j = (int)((n / K.nx) % K.ny), k = (int)(n / ((long long)K.nx * K.ny));
+  const int ne = G.ex * G.ey * G.ez;
+  const int ntz = (DIM == 3) ? K.nz / G.tz : 1;
+  double acc[NFZ];
+#pragma unroll
+  for (int f = 0; f < NFZ; ++f) acc[f] = 0.0;
+  // candidate tiles per direction: the owner and its two neighbours, each taken once (with
+  // one or two tiles in a direction the neighbours coincide)
+  for (int dk = (DIM == 3 ? -1 : 0); dk <= (DIM == 3 ? 1 : 0); ++dk) {
+    if (DIM == 3 && ((dk == 1 && ntz <= 2) || (dk == -1 && ntz <= 1))) continue;
+    const int tk = (DIM == 3) ? (k / G.tz + dk + ntz) % ntz : 0;
+    const int lc = (DIM == 3) ? wrapg(k - (tk * G.tz - G.ov), K.nz) : 0;
+    if (lc >= G.ez) continue;
+    for (int dj = -1; dj <= 1; ++dj) {
+      if ((dj == 1 && G.nty <= 2) || (dj == -1 && G.nty <= 1)) continue;
+      const int tj = (j / G.ty + dj + G.nty) % G.nty;
+      const int lb = wrapg(j - (tj * G.ty - G.ov), K.ny);
+      if (lb >= G.ey) continue;
+      for (int di = -1; di <= 1; ++di) {
+        if ((di == 1 && G.ntx <= 2) || (di == -1 && G.ntx <= 1)) continue;
+        const int ti = (i / G.tx + di + G.ntx) % G.ntx;
+        const int la = wrapg(i - (ti * G.tx - G.ov), K.nx);
+        if (la >= G.ex) continue;
+        const long long t = ti + (long long)G.ntx * (tj + (long long)G.nty * tk);
+        const R* src = xs + t * NFZ * ne + la + G.ex * (lb + G.ey * lc);
+#pragma unroll
+        for (int f = 0; f < NFZ; ++f) acc[f] += (double)src[(long long)f * ne];
+      }
+    }
+  }
+#pragma unroll
+  for (int f = 0; f < NFZ; ++f) zg[f * K.N + n] = (R)acc[f];
 }
 
 Geo make_geo(const Consts& K, const TileCfg& T) {
@@ -393,17 +458,18 @@ Geo make_geo(const Consts& K, const TileCfg& T) {
   G.dz = (K.dim == 3) ? G.ez + 2 : 1;
   G.ntx = K.nx / T.tx;
   G.nty = K.ny / T.ty;
+  G.mode = T.mode;
   return G;
 }
 
 template <int DIM, bool WU, typename R, int TH>
 void launch_npt(const Geo& G, const Consts& K, size_t lds, int ntiles, int npt, double dt, const R* B,
-                const double* cn, const R* r, R* z, const int* perm, hipStream_t s) {
+                const double* cn, const R* r, R* z, const int* perm, R* xs, hipStream_t s) {
 #define PF_RAS_CASE(NPTV)                                                                             \
   case NPTV:                                                                                          \
     (void)hipFuncSetAttribute((const void*)k_ras<DIM, WU, NPTV, R, TH>,                              \
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                  \
-    hipLaunchKernelGGL((k_ras<DIM, WU, NPTV, R, TH>), dim3(ntiles), dim3(TH), lds, s, K, G, dt, B, cn, r, z, perm); \
+    hipLaunchKernelGGL((k_ras<DIM, WU, NPTV, R, TH>), dim3(ntiles), dim3(TH), lds, s, K, G, dt, B, cn, r, z, perm, xs); \
     break;
   switch (npt) {
     PF_RAS_CASE(1)
@@ -416,11 +482,16 @@ void launch_npt(const Geo& G, const Consts& K, size_t lds, int ntiles, int npt, 
 
 template <int DIM, bool WU, typename R>
 void launch_dim(const Consts& K, const Geo& G, size_t lds, int ntiles, int th, int npt, double dt,
-                const R* B, const double* cn, const R* r, R* z, const int* perm, hipStream_t s) {
+                const R* B, const double* cn, const R* r, R* z, const int* perm, R* xs, hipStream_t s) {
   if (!WU && th == kRasThreadsSmall)
-    launch_npt<DIM, false, R, kRasThreadsSmall>(G, K, lds, ntiles, npt, dt, B, cn, r, z, perm, s);
+    launch_npt<DIM, false, R, kRasThreadsSmall>(G, K, lds, ntiles, npt, dt, B, cn, r, z, perm, xs, s);
   else
-    launch_npt<DIM, WU, R, kRasThreadsMax>(G, K, lds, ntiles, npt, dt, B, cn, r, z, perm, s);
+    launch_npt<DIM, WU, R, kRasThreadsMax>(G, K, lds, ntiles, npt, dt, B, cn, r, z, perm, xs, s);
+  if (G.mode != kRasLeft) {
+    constexpr int NFZ = WU ? 4 + DIM : 4;
+    hipLaunchKernelGGL((k_ras_gather<DIM, NFZ, R>), dim3((unsigned)((K.N + 255) / 256)), dim3(256), 0, s, K, G,
+                       (const R*)xs, z);
+  }
 }
 
 // nodes of the extended tile per thread (1..3) at th threads, 0 if more than three
@@ -478,12 +549,13 @@ void launch_ras(const Consts& K, const TileCfg& T, double dt, const R* B, const 
   const size_t lds = ras_lds_bytes(K, T, sizeof(R));
   int npt = 0;
   const int th = ras_threads(K, T, sizeof(R), &npt);
+  R* xs = static_cast<R*>(T.scratch);
   if (K.dim == 2) {
-    if (T.with_u) launch_dim<2, true, R>(K, G, lds, ntiles, th, npt, dt, B, cn, r, z, T.perm, s);
-    else launch_dim<2, false, R>(K, G, lds, ntiles, th, npt, dt, B, cn, r, z, T.perm, s);
+    if (T.with_u) launch_dim<2, true, R>(K, G, lds, ntiles, th, npt, dt, B, cn, r, z, T.perm, xs, s);
+    else launch_dim<2, false, R>(K, G, lds, ntiles, th, npt, dt, B, cn, r, z, T.perm, xs, s);
   } else {
-    if (T.with_u) launch_dim<3, true, R>(K, G, lds, ntiles, th, npt, dt, B, cn, r, z, T.perm, s);
-    else launch_dim<3, false, R>(K, G, lds, ntiles, th, npt, dt, B, cn, r, z, T.perm, s);
+    if (T.with_u) launch_dim<3, true, R>(K, G, lds, ntiles, th, npt, dt, B, cn, r, z, T.perm, xs, s);
+    else launch_dim<3, false, R>(K, G, lds, ntiles, th, npt, dt, B, cn, r, z, T.perm, xs, s);
   }
 }
 template void launch_ras<double>(const Consts&, const TileCfg&, double, const double*, const double*,

@@ -55,6 +55,8 @@ struct TileCfg {
   int sweeps;       // symmetric GS sweeps
   int with_u;       // 1: all fields (plain RAS); 0: (c, eta) block only
   const int* perm;  // device: nodes of the extended tile sorted by colour (ras_colour_order)
+  int mode;         // 0 left-RAS, 1 classical AS, 2 right-RAS
+  void* scratch;    // modes 1, 2: one extended solution per tile (Krylov type)
 };
 // R (double or float): element type of the blocks B, of r and z, and of the tile arithmetic
 template <typename R>

@@ -37,6 +37,11 @@ int device_error(hipError_t e, const char* what) {
 
 bool is_pow2(int n) { return n >= 2 && (n & (n - 1)) == 0; }
 
+// preconditioners built on the Schwarz tile solve, and those that solve all fields there
+bool uses_tiles(int pc) { return pc == PFNKS_PC_RAS || pc == PFNKS_PC_RAS_SPECTRAL || pc == PFNKS_PC_AS || pc == PFNKS_PC_RRAS; }
+bool tiles_all_fields(int pc) { return pc == PFNKS_PC_RAS || pc == PFNKS_PC_AS || pc == PFNKS_PC_RRAS; }
+bool sums_overlap(int pc) { return pc == PFNKS_PC_AS || pc == PFNKS_PC_RRAS; }
+
 // ---------------------------------------------------------------------------------------
 // workspace layout
 // ---------------------------------------------------------------------------------------
@@ -47,7 +52,7 @@ struct Layout {
 
 enum Buf {
   B_X, B_XN, B_XT, B_F, B_FT, B_S, B_B, B_BPC, B_G4, B_V, B_ZB, B_W, B_Z, B_TMP, B_TMPV, B_PART, B_RED,
-  B_FFT0, B_FFT1, B_TW0, B_TW1, B_TW2, B_SN0, B_SN1, B_SN2, B_HDEV, B_PERM, B_COUNT
+  B_FFT0, B_FFT1, B_TW0, B_TW1, B_TW2, B_SN0, B_SN1, B_SN2, B_HDEV, B_PERM, B_ASX, B_COUNT
 };
 
 // bytes of one element of the Krylov basis, the preconditioner blocks and the tile solve
@@ -58,7 +63,8 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // Krylov basis V, the preconditioned basis Z, the single vectors z and tmpv and the lagged
 // preconditioner blocks Bpc are stored in the Krylov element type (float when mixed); the
 // state, residuals, Newton update S, J v output w and the Jacobian blocks B are double.
-Layout make_layout(int dim, long long N, int restart, const int* n, int precision, long long ext_nodes) {
+Layout make_layout(int dim, long long N, int restart, const int* n, int precision, long long ext_nodes,
+                   long long tiles_summed) {
   const int nf = 4 + dim;
   const size_t kb = krylov_bytes(precision);
   const size_t vec = sizeof(double) * (size_t)nf * N;
@@ -85,6 +91,8 @@ Layout make_layout(int dim, long long N, int restart, const int* n, int precisio
   sz[B_SN2] = sizeof(double) * (size_t)(dim == 3 ? n[2] : 2);
   sz[B_HDEV] = sizeof(double) * (size_t)(restart + 1) * (restart + 2);
   sz[B_PERM] = sizeof(int) * (size_t)ext_nodes;  // colour order of one extended tile
+  // classical AS / right-RAS: every tile's extended solution (all fields), summed afterwards
+  sz[B_ASX] = kb * (size_t)nf * (size_t)ext_nodes * (size_t)tiles_summed;
   Layout L{};
   size_t o = 0;
   for (int b = 0; b < B_COUNT; ++b) {
@@ -102,6 +110,14 @@ long long ext_nodes(const pfnks_grid* g, const pfnks_solver* s) {
   return e;
 }
 
+// tiles whose extended solutions need storing (classical AS / right-RAS), else 0
+long long tiles_summed(const pfnks_grid* g, const pfnks_solver* s) {
+  if (!sums_overlap(s->pc)) return 0;
+  long long t = 1;
+  for (int k = 0; k < g->dim; ++k) t *= g->n[k] / s->tile[k];
+  return t;
+}
+
 int validate(const pfnks_grid* g, const pfnks_model* m, const pfnks_solver* s) {
   if (!g || !m || !s) return PFNKS_EINVAL;
   if (g->dim != 2 && g->dim != 3) return PFNKS_EINVAL;
@@ -117,7 +133,10 @@ int validate(const pfnks_grid* g, const pfnks_model* m, const pfnks_solver* s) {
   if (s->gmres_restart < 1 || s->gmres_restart > 64) return PFNKS_EINVAL;
   if (s->sweeps < 1 || s->sweeps > 16) return PFNKS_EINVAL;
   if (s->newton_maxit < 1 || s->gmres_maxit < 1) return PFNKS_EINVAL;
-  if (s->pc < PFNKS_PC_RAS || s->pc > PFNKS_PC_SPECTRAL) return PFNKS_EINVAL;
+  if (s->pc < PFNKS_PC_RAS || s->pc > PFNKS_PC_RRAS) return PFNKS_EINVAL;
+  if (sums_overlap(s->pc))
+    for (int k = 0; k < g->dim; ++k)
+      if (s->overlap > s->tile[k]) return PFNKS_EINVAL;  // at most three tiles per direction cover a node
   if (s->precision != PFNKS_FP64 && s->precision != PFNKS_MIXED) return PFNKS_EINVAL;
   if (m->S < 1 || m->S > pf::kMaxS) return PFNKS_EINVAL;
   if (!(m->kappa >= 0.0) || !(m->L_eta > 0.0) || m->Lscale < 0.0) return PFNKS_EINVAL;
@@ -130,9 +149,9 @@ int validate(const pfnks_grid* g, const pfnks_model* m, const pfnks_solver* s) {
     dpad *= s->tile[k] + 2 * s->overlap + 2;
   }
   if (ext > 3 * 512) return PFNKS_EINVAL;
-  const int nfz = (s->pc == PFNKS_PC_RAS) ? 4 + g->dim : 4;
+  const int nfz = tiles_all_fields(s->pc) ? 4 + g->dim : 4;
   const long long kb = (long long)krylov_bytes(s->precision);
-  if (s->pc <= PFNKS_PC_RAS_SPECTRAL && kb * (nfz * zpad + 2 * dpad + 4 * ext) > 160 * 1024) return PFNKS_EINVAL;
+  if (uses_tiles(s->pc) && kb * (nfz * zpad + 2 * dpad + 4 * ext) > 160 * 1024) return PFNKS_EINVAL;
   return PFNKS_OK;
 }
 
@@ -335,12 +354,13 @@ void pc_apply(pfnks_problem* p, double dt, const T* r, T* z) {
   const long long N = p->N;
   const int pc = p->solver.pc;
   const T* Bpc = static_cast<const T*>(p->Bpc);
-  if (pc == PFNKS_PC_RAS) {
+  if (tiles_all_fields(pc)) {
     pf::TileCfg T_ = p->T;
     T_.with_u = 1;
+    T_.mode = (pc == PFNKS_PC_AS) ? 1 : (pc == PFNKS_PC_RRAS) ? 2 : 0;
     Prof pr(p, PFNKS_K_RAS, ras_bytes(p, 4 + p->K.dim));
     pf::launch_ras<T>(p->K, T_, dt, Bpc, p->Xn, r, z, p->stream);
-    p->launches += 1;
+    p->launches += sums_overlap(pc) ? 2 : 1;
     return;
   }
   if (pc == PFNKS_PC_RAS_SPECTRAL) {
@@ -556,7 +576,8 @@ int pfnks_workspace_bytes(const pfnks_grid* grid, const pfnks_model* model, cons
   int st = validate(grid, model, solver);
   if (st) return st;
   const long long N = (long long)grid->n[0] * grid->n[1] * (grid->dim == 3 ? grid->n[2] : 1);
-  *bytes = make_layout(grid->dim, N, solver->gmres_restart, grid->n, solver->precision, ext_nodes(grid, solver)).total;
+  *bytes = make_layout(grid->dim, N, solver->gmres_restart, grid->n, solver->precision, ext_nodes(grid, solver),
+                       tiles_summed(grid, solver)).total;
   return PFNKS_OK;
 }
 
@@ -569,7 +590,8 @@ int pfnks_create_problem(const pfnks_grid* grid, const pfnks_model* model, const
   if (st) return st;
   if (((uintptr_t)d_workspace & 255) != 0) return PFNKS_EINVAL;
   const long long N = (long long)grid->n[0] * grid->n[1] * (grid->dim == 3 ? grid->n[2] : 1);
-  const Layout L = make_layout(grid->dim, N, solver->gmres_restart, grid->n, solver->precision, ext_nodes(grid, solver));
+  const Layout L = make_layout(grid->dim, N, solver->gmres_restart, grid->n, solver->precision, ext_nodes(grid, solver),
+                               tiles_summed(grid, solver));
   if (ws_bytes < L.total) return PFNKS_ENOSPACE;
   st = check_domain_host(c0, eta0, N);
   if (st) return st;
@@ -600,9 +622,11 @@ int pfnks_create_problem(const pfnks_grid* grid, const pfnks_model* model, const
   p->T.sweeps = solver->sweeps;
   p->T.with_u = 0;
   p->T.perm = (const int*)(p->ws + L.off[B_PERM]);
+  p->T.mode = 0;
+  p->T.scratch = p->ws + L.off[B_ASX];
   pf::TileCfg tcheck = p->T;
-  tcheck.with_u = (solver->pc == PFNKS_PC_RAS) ? 1 : 0;
-  if (solver->pc <= PFNKS_PC_RAS_SPECTRAL && pf::ras_threads(p->K, tcheck, krylov_bytes(solver->precision), nullptr) == 0) {
+  tcheck.with_u = tiles_all_fields(solver->pc) ? 1 : 0;
+  if (uses_tiles(solver->pc) && pf::ras_threads(p->K, tcheck, krylov_bytes(solver->precision), nullptr) == 0) {
     delete p;
     return PFNKS_EINVAL;  // tile shape beyond what the tile kernel holds per thread
   }

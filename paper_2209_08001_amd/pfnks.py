@@ -25,6 +25,8 @@ PC_RAS = 0
 PC_RAS_SPECTRAL = 1
 PC_NONE = 2
 PC_SPECTRAL = 3
+PC_AS = 4     # classical additive Schwarz (extended solutions summed)
+PC_RRAS = 5   # right-RAS (right-hand side restricted to the owned nodes, solutions summed)
 
 FP64 = 0   # every vector and kernel in double
 MIXED = 1  # float Krylov basis, preconditioner and tile solve; double residual, J v, update

@@ -94,6 +94,10 @@ WORKLOADS = {
     # 80^3 (the Fourier displacement solve needs power-of-two sides; side 32 > 2 r)
     "particle3d_128": {"n": (128, 128, 128), "particle": 7.5, "steps": 50,
                        "dt_min": 1e-2, "dt_max": 2.0, "zeta": 100.0},
+    # the Section 5.2 preconditioner comparison in kind: the first 10 steps with a fixed
+    # dt = 0.01 (the paper: 80^3 on 256 cores; here 64^3 on one GPU)
+    "table2_3d": {"n": (64, 64, 64), "seed": 3, "cbar": 0.17, "steps": 10,
+                  "dt_min": 1e-2, "dt_max": 1e-2, "zeta": 100.0},
     # serving: Poisson arrivals (4 requests/s over 10 s, seed 5), 70 % 2D (sides 64..512) and
     # 30 % 3D (side 64), 20 adaptive steps per request, continuous batching
     "serve_mix": {"serve": True, "rate": 4.0, "window": 10.0, "seed": 5, "sides2d": (64, 128, 256, 512),

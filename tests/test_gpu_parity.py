@@ -162,7 +162,10 @@ def test_spectral_block_is_exact_solve():
     p.close()
 
 
-@pytest.mark.parametrize("pc", ["ras_spectral", "ras"])
+PCS = {"ras_spectral": "PC_RAS_SPECTRAL", "ras": "PC_RAS", "as": "PC_AS", "rras": "PC_RRAS"}
+
+
+@pytest.mark.parametrize("pc", ["ras_spectral", "ras", "as", "rras"])
 def test_pc_linear_and_deterministic(pc):
     from paper_2209_08001_amd import pfnks
 
@@ -170,7 +173,7 @@ def test_pc_linear_and_deterministic(pc):
     _note(f"pc linearity {pc}")
     n = (64, 64)
     c0, e0 = W.init_fields(n, 23)
-    p = _problem(n, c0, e0, pc=pfnks.PC_RAS if pc == "ras" else pfnks.PC_RAS_SPECTRAL)
+    p = _problem(n, c0, e0, pc=getattr(pfnks, PCS[pc]))
     Xn, _ = p.get_state()
     rng = np.random.default_rng(9)
     r1 = rng.normal(size=Xn.shape)
@@ -412,6 +415,28 @@ def test_stop_rule_pf2d_64(oracle_c1):
         _note(f"  step {k}: |F(X)|/|F(Xn)| = {r1 / r0:.2e}")
         assert r1 <= 1.1e-8 * r0
         Xp = X
+    p.close()
+
+
+@pytest.mark.parametrize("pc,overlap,tile", [("as", 0, (16, 16)), ("as", 2, (16, 16)), ("rras", 1, (16, 16)),
+                                            ("rras", 2, (32, 32)), ("as", 1, (32, 32))])
+def test_step_parity_schwarz_variants(oracle_c1, pc, overlap, tile):
+    """Classical additive Schwarz and right-RAS (the paper's other preconditioners, summed
+    extended solutions): 3 steps of pf2d_64 within 1e-8 of the oracle's root; the 32 x 32
+    tiles put two tiles per direction, where the neighbour on both sides is the same tile."""
+    from paper_2209_08001_amd import pfnks
+
+    _cuda()
+    c0, e0, traj, info, o = oracle_c1
+    _note(f"step parity pf2d_64 pc={pc} overlap={overlap} tile={tile}")
+    p = _problem((64, 64), c0, e0, pc=getattr(pfnks, PCS[pc]), overlap=overlap, tile=(tile[0], tile[1], 1),
+                 newton_rtol=ROOT_RTOL)
+    for k in range(3):
+        st = p.step(0.01)
+        X, _ = p.get_state()
+        errs = [_relmax(X[f], traj[k + 1][f]) for f in range(X.shape[0])]
+        _note(f"  step {k}: newton={st['newton_its']} gmres={st['gmres_its']} max err={max(errs):.2e}")
+        assert max(errs) <= 1e-8, (k, errs)
     p.close()
 
 
