@@ -86,44 +86,13 @@ struct Coefs {
   double c[kMaxRed];
 };
 
-template <int MAXV>
-__global__ __launch_bounds__(kThreads) void k_update(long long n, int nv, const double* __restrict__ V,
-                                                     long long ldv, Coefs cf, const double* __restrict__ w,
-                                                     double scale, double* __restrict__ out,
-                                                     double* __restrict__ partial) {
-  __shared__ double lds[kThreads / 64];
-  double acc = 0.0;
-  // n and ldv are even and every vector is 16-byte aligned: two elements per load
-  const long long n2 = n >> 1, ld2 = ldv >> 1;
-  const double2* __restrict__ V2 = reinterpret_cast<const double2*>(V);
-  const double2* __restrict__ w2 = reinterpret_cast<const double2*>(w);
-  double2* __restrict__ o2 = reinterpret_cast<double2*>(out);
-  for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < n2;
-       e += (long long)gridDim.x * kThreads) {
-    double2 x = w2[e];
-#pragma unroll
-    for (int v = 0; v < MAXV; ++v)
-      if (MAXV <= 32 || v < nv) {
-        const double2 y = V2[v * ld2 + e];
-        x.x -= cf.c[v] * y.x;
-        x.y -= cf.c[v] * y.y;
-      }
-    acc += x.x * x.x + x.y * x.y;
-    o2[e] = make_double2(scale * x.x, scale * x.y);
-  }
-  double s = block_sum(acc, lds);
-  if (threadIdx.x == 0) partial[blockIdx.x] = s;
-}
-
 // v_{j+1} = (w - sum_v h_v V_v) / h_{j+1,j} with the coefficients read from device memory
 // (hc = [h_0 .. h_{nv-1}, <w, w>], written by the finalize of the multi-dot) and
-// h_{j+1,j} = sqrt(<w,w> - sum h_v^2); partial: ||w - sum h V||^2 for a later check.
+// h_{j+1,j} = sqrt(<w,w> - sum h_v^2).
 template <int MAXV, typename T>
 __global__ __launch_bounds__(kThreads) void k_update_dev(long long n, int nv, const T* __restrict__ V,
                                                          long long ldv, const double* __restrict__ hc,
-                                                         const double* __restrict__ w, T* __restrict__ out,
-                                                         double* __restrict__ partial) {
-  __shared__ double lds[kThreads / 64];
+                                                         const double* __restrict__ w, T* __restrict__ out) {
   double c[MAXV];
   double hh = 0.0;
 #pragma unroll
@@ -132,7 +101,6 @@ __global__ __launch_bounds__(kThreads) void k_update_dev(long long n, int nv, co
     hh += c[v] * c[v];
   }
   const double scale = 1.0 / sqrt(hc[nv] - hh);
-  double acc = 0.0;
   const long long n2 = n >> 1, ld2 = ldv >> 1;
   using T2 = typename Vec2<T>::type;
   const T2* __restrict__ V2 = reinterpret_cast<const T2*>(V);
@@ -148,14 +116,11 @@ __global__ __launch_bounds__(kThreads) void k_update_dev(long long n, int nv, co
         x.x -= c[v] * (double)y.x;
         x.y -= c[v] * (double)y.y;
       }
-    acc += x.x * x.x + x.y * x.y;
     T2 o;
     o.x = (T)(scale * x.x);
     o.y = (T)(scale * x.y);
     o2[e] = o;
   }
-  double s = block_sum(acc, lds);
-  if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
 template <int MAXV, typename T, typename To>
@@ -356,27 +321,17 @@ void launch_multidot(long long n, int nv, const T* V, long long ldv, const doubl
 template void launch_multidot<double>(long long, int, const double*, long long, const double*, double*, hipStream_t);
 template void launch_multidot<float>(long long, int, const float*, long long, const double*, double*, hipStream_t);
 
-// out = scale * (w - sum_v coef[v] V_v); partial: ||w - sum coef V||^2
-void launch_update(long long n, int nv, const double* V, long long ldv, const double* coef,
-                   const double* w, double scale, double* out, double* partial, hipStream_t s) {
-  Coefs cf{};
-  for (int v = 0; v < nv; ++v) cf.c[v] = coef[v];
-#define F(N) hipLaunchKernelGGL(k_update<N>, dim3(kRedBlocks), dim3(kThreads), 0, s, n, nv, V, ldv, cf, w, scale, out, partial)
-  switch (nv) { PF_NV_CASES(F) }
-#undef F
-}
-
 template <typename T>
 void launch_update_dev(long long n, int nv, const T* V, long long ldv, const double* hc, const double* w,
-                       T* out, double* partial, hipStream_t s) {
-#define F(N) hipLaunchKernelGGL((k_update_dev<N, T>), dim3(kRedBlocks), dim3(kThreads), 0, s, n, nv, V, ldv, hc, w, out, partial)
+                       T* out, hipStream_t s) {
+#define F(N) hipLaunchKernelGGL((k_update_dev<N, T>), dim3(kRedBlocks), dim3(kThreads), 0, s, n, nv, V, ldv, hc, w, out)
   switch (nv) { PF_NV_CASES(F) }
 #undef F
 }
 template void launch_update_dev<double>(long long, int, const double*, long long, const double*, const double*,
-                                        double*, double*, hipStream_t);
+                                        double*, hipStream_t);
 template void launch_update_dev<float>(long long, int, const float*, long long, const double*, const double*,
-                                       float*, double*, hipStream_t);
+                                       float*, hipStream_t);
 
 // out = beta * out + sum_v coef[v] V_v
 template <typename T, typename To>
@@ -390,8 +345,6 @@ void launch_lincomb(long long n, int nv, const T* V, long long ldv, const double
 }
 template void launch_lincomb<double, double>(long long, int, const double*, long long, const double*, double,
                                              double*, hipStream_t);
-template void launch_lincomb<float, float>(long long, int, const float*, long long, const double*, double, float*,
-                                           hipStream_t);
 template void launch_lincomb<float, double>(long long, int, const float*, long long, const double*, double,
                                             double*, hipStream_t);
 
@@ -402,8 +355,6 @@ void launch_axpby(long long n, double a, const Tx* x, double b, const Ty* y, To*
 template void launch_axpby<double, double, double>(long long, double, const double*, double, const double*,
                                                    double*, hipStream_t);
 template void launch_axpby<double, double, float>(long long, double, const double*, double, const double*, float*,
-                                                  hipStream_t);
-template void launch_axpby<double, float, double>(long long, double, const double*, double, const float*, double*,
                                                   hipStream_t);
 template void launch_axpby<float, float, float>(long long, double, const float*, double, const float*, float*,
                                                 hipStream_t);

@@ -89,20 +89,17 @@ void launch_spectral_solve(const Consts& K, const FftPlan& P, const T* r, double
 template <typename T>
 void launch_multidot(long long n, int nv, const T* V, long long ldv, const double* w,
                      double* partial, hipStream_t s);
-void launch_update(long long n, int nv, const double* V, long long ldv, const double* coef,
-                   const double* w, double scale, double* out, double* partial, hipStream_t s);
 template <typename T, typename To>
 void launch_lincomb(long long n, int nv, const T* V, long long ldv, const double* coef,
                     double beta, To* out, hipStream_t s);
-// out = a x + b y (y unread when b == 0); instantiated for (d,d,d), (d,d,f), (d,f,d), (f,f,f),
-// (f,f,d)
+// out = a x + b y (y unread when b == 0); instantiated for (d,d,d), (d,d,f), (f,f,f), (f,f,d)
 template <typename Tx, typename Ty, typename To>
 void launch_axpby(long long n, double a, const Tx* x, double b, const Ty* y, To* out, hipStream_t s);
 void launch_finalize(const double* partial, int nvals, double* out, hipStream_t s, double* out2 = nullptr);
 // v_{j+1} from device-resident Gram-Schmidt coefficients hc = [h_0..h_{nv-1}, <w,w>]
 template <typename T>
 void launch_update_dev(long long n, int nv, const T* V, long long ldv, const double* hc,
-                       const double* w, T* out, double* partial, hipStream_t s);
+                       const double* w, T* out, hipStream_t s);
 void launch_sum2(long long n, const double* x, const double* y, const double* yn, double* partial,
                  hipStream_t s);
 void launch_trial(const Consts& K, int nf, const double* X, const double* S, double lam,

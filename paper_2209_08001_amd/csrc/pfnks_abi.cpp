@@ -437,7 +437,7 @@ int gmres(pfnks_problem* p, double dt, const double* Bm, double fnorm, double to
     (void)hipEventRecord(p->hev[j], p->stream);
     {
       Prof pr(p, PFNKS_K_UPDATE, (kb * (j + 2) + 8.0) * n);
-      pf::launch_update_dev<T>(n, j + 1, V, n, p->hdev + j * ld, p->w, V + (j + 1) * n, p->part, p->stream);
+      pf::launch_update_dev<T>(n, j + 1, V, n, p->hdev + j * ld, p->w, V + (j + 1) * n, p->stream);
     }
     p->launches += 3;
   };
