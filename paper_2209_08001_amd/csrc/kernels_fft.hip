@@ -238,6 +238,192 @@ __global__ __launch_bounds__(256) void k_fft2_rows_inv(Consts K, int logn, int n
   }
 }
 
+// ---- 3D pipeline with real-to-complex transforms along x ---------------------------
+// The three displacement fields are real, so along x only the half spectrum kx <= nx/2 is
+// kept (nxh = nx/2 + 1 columns; the rest follows by conjugation).  Half spectra are stored
+// as Qh[f][k][j][kx] (f = 0..2, one plane of nxh * ny * nz complex each; 1.52 N complex in
+// all at nx = 128).  Five passes: x (real to complex, fused with forming q = r + a Dhat zc),
+// y (all three fields in one launch), z fused with the pointwise solve, y inverse, x inverse
+// (complex to real, scaled by 1/N).  In the x passes y and z are still physical, so every
+// x line is real and its spectrum is Hermitian in kx alone.
+
+// x pass.  A block takes rp row pairs (j0, j0 + 1) of plane k and transforms three complex
+// lines per pair: q1 + i q2 of each row and q3(j0) + i q3(j0 + 1); the two real spectra in
+// each line are separated with kx <-> nx - kx.
+template <typename T>
+__global__ __launch_bounds__(256) void k_r2c_x(Consts K, const T* __restrict__ r, double a,
+                                               const T* __restrict__ zc, int logn, int rp,
+                                               const double2* __restrict__ tw, double2* __restrict__ Qh) {
+  extern __shared__ double2 sm[];  // 3 rp lines of nx
+  const int n = K.nx, nxh = n / 2 + 1, hb = K.ny / (2 * rp);
+  const int b = xcd_band((int)blockIdx.x, (int)gridDim.x);
+  const int jb = (b % hb) * 2 * rp, k = b / hb;
+  const long long NN = K.N;
+  for (int e = threadIdx.x; e < 2 * rp * n; e += blockDim.x) {
+    const int rr = e / n, i = e - rr * n, j = jb + rr;
+    const int q = rr >> 1, l = rr & 1;
+    const long long row = (long long)n * ((long long)j + (long long)K.ny * k);
+    const long long m = row + i;
+    double q0 = r ? (double)r[m] : 0.0, q1 = r ? (double)r[NN + m] : 0.0, q2 = r ? (double)r[2 * NN + m] : 0.0;
+    if (zc && a != 0.0) {
+      const int jp = (j + 1) & (K.ny - 1), jm = (j - 1) & (K.ny - 1);
+      const int kp = (k + 1) & (K.nz - 1), km = (k - 1) & (K.nz - 1);
+      q0 += a * ((double)zc[row + ((i + 1) & (n - 1))] - (double)zc[row + ((i - 1) & (n - 1))]) * K.i2h;
+      q1 += a * ((double)zc[i + (long long)n * (jp + (long long)K.ny * k)] -
+                 (double)zc[i + (long long)n * (jm + (long long)K.ny * k)]) * K.i2h;
+      q2 += a * ((double)zc[i + (long long)n * (j + (long long)K.ny * kp)] -
+                 (double)zc[i + (long long)n * (j + (long long)K.ny * km)]) * K.i2h;
+    }
+    const int bi = brev(i, logn);
+    sm[(3 * q + l) * n + bi] = make_double2(q0, q1);
+    reinterpret_cast<double*>(&sm[(3 * q + 2) * n + bi])[l] = q2;
+  }
+  __syncthreads();
+  fft_lds(sm, n, logn, 3 * rp, tw, 0);
+  const long long plane = (long long)nxh * K.ny * K.nz;
+  for (int e = threadIdx.x; e < 3 * rp * nxh; e += blockDim.x) {
+    const int line = e / nxh, kx = e - line * nxh;
+    const int q = line / 3, t = line - 3 * q, j0 = jb + 2 * q;
+    const double2 av = sm[line * n + kx], bv = sm[line * n + ((n - kx) & (n - 1))];
+    const double2 A = make_double2(0.5 * (av.x + bv.x), 0.5 * (av.y - bv.y));   // real part's spectrum
+    const double2 B = make_double2(0.5 * (av.y + bv.y), -0.5 * (av.x - bv.x));  // imaginary part's
+    if (t < 2) {
+      const long long o = kx + (long long)nxh * ((long long)(j0 + t) + (long long)K.ny * k);
+      Qh[o] = A;
+      Qh[plane + o] = B;
+    } else {
+      const long long o = 2 * plane + kx + (long long)nxh * ((long long)j0 + (long long)K.ny * k);
+      Qh[o] = A;
+      Qh[o + nxh] = B;
+    }
+  }
+}
+
+// z pass with the solve: lpb adjacent kx columns at one ky, all three fields.  Forward FFT
+// along z, Khat U = Q at every mode (U = 0 where every S_J = 0: the gauge; U = Q without
+// elasticity), the bit-reversal permutation in place, inverse FFT along z.
+__global__ __launch_bounds__(256) void k_z_solve(Consts K, int logn, int lpb, const double2* __restrict__ tw,
+                                                 const double* __restrict__ sx, const double* __restrict__ sy,
+                                                 const double* __restrict__ szt, double2* __restrict__ Qh) {
+  extern __shared__ double2 sm[];  // 3 lpb lines of nz: line (f lpb + l)
+  const int n = K.nz, nxh = K.nx / 2 + 1;
+  const int nxb = (nxh + lpb - 1) / lpb;
+  const int b = xcd_band((int)blockIdx.x, (int)gridDim.x);
+  const int kx0 = (b % nxb) * lpb, ky = b / nxb;
+  const long long plane = (long long)nxh * K.ny * K.nz;
+  const long long zs = (long long)nxh * K.ny;
+  const long long base = kx0 + (long long)nxh * ky;
+  const int nl = 3 * lpb;
+  for (int e = threadIdx.x; e < nl * n; e += blockDim.x) {
+    const int l = e % lpb, rest = e / lpb, p = rest % n, f = rest / n;
+    double2 v = make_double2(0.0, 0.0);
+    if (kx0 + l < nxh) v = Qh[f * plane + base + l + zs * p];
+    sm[(f * lpb + l) * n + brev(p, logn)] = v;
+  }
+  __syncthreads();
+  fft_lds(sm, n, logn, nl, tw, 0);
+  for (int e = threadIdx.x; e < lpb * n; e += blockDim.x) {
+    const int l = e % lpb, p = e / lpb, kx = kx0 + l;
+    if (kx >= nxh) continue;
+    const double S0 = sx[kx], S1 = sy[ky], S2 = szt[p];
+    const double s2 = S0 * S0 + S1 * S1 + S2 * S2;
+    double2 Q[3];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) Q[f] = sm[(f * lpb + l) * n + p];
+    if (K.elastic) {
+      double2 U[3] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
+      if (s2 != 0.0) {
+        const double S[3] = {S0, S1, S2};
+        double A[3][3];
+#pragma unroll
+        for (int I = 0; I < 3; ++I)
+#pragma unroll
+          for (int L = 0; L < 3; ++L)
+            A[I][L] = (I == L) ? -(K.C11 * S[I] * S[I] + K.C44 * (s2 - S[I] * S[I])) : -(K.C12 + K.C44) * S[I] * S[L];
+        // symmetric 3 x 3 inverse by the adjugate
+        const double c00 = A[1][1] * A[2][2] - A[1][2] * A[2][1];
+        const double c01 = A[0][2] * A[2][1] - A[0][1] * A[2][2];
+        const double c02 = A[0][1] * A[1][2] - A[0][2] * A[1][1];
+        const double c11 = A[0][0] * A[2][2] - A[0][2] * A[2][0];
+        const double c12 = A[0][2] * A[1][0] - A[0][0] * A[1][2];
+        const double c22 = A[0][0] * A[1][1] - A[0][1] * A[1][0];
+        const double id = 1.0 / (A[0][0] * c00 + A[0][1] * (A[1][2] * A[2][0] - A[1][0] * A[2][2]) +
+                                 A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]));
+        const double Ai[3][3] = {{c00 * id, c01 * id, c02 * id}, {c01 * id, c11 * id, c12 * id},
+                                 {c02 * id, c12 * id, c22 * id}};
+#pragma unroll
+        for (int I = 0; I < 3; ++I)
+          U[I] = make_double2(Ai[I][0] * Q[0].x + Ai[I][1] * Q[1].x + Ai[I][2] * Q[2].x,
+                              Ai[I][0] * Q[0].y + Ai[I][1] * Q[1].y + Ai[I][2] * Q[2].y);
+      }
+#pragma unroll
+      for (int f = 0; f < 3; ++f) sm[(f * lpb + l) * n + p] = U[f];
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < nl * n; e += blockDim.x) {
+    const int line = e / n, p = e - line * n, q = brev(p, logn);
+    if (p < q) {
+      const double2 t = sm[line * n + p];
+      sm[line * n + p] = sm[line * n + q];
+      sm[line * n + q] = t;
+    }
+  }
+  __syncthreads();
+  fft_lds(sm, n, logn, nl, tw, 1);
+  for (int e = threadIdx.x; e < nl * n; e += blockDim.x) {
+    const int l = e % lpb, rest = e / lpb, p = rest % n, f = rest / n;
+    if (kx0 + l < nxh) Qh[f * plane + base + l + zs * p] = sm[(f * lpb + l) * n + p];
+  }
+}
+
+// x pass back: rp row pairs of plane k.  Each line is rebuilt over the full kx range from
+// the half spectra (conjugates above nx/2) as U1 + i U2 of one row, or U3(j0) + i U3(j0 + 1);
+// one inverse FFT per line gives the real fields, u = result / N.
+template <typename T>
+__global__ __launch_bounds__(256) void k_c2r_x(Consts K, int logn, int rp, const double2* __restrict__ tw,
+                                               const double2* __restrict__ Qh, T* __restrict__ u) {
+  extern __shared__ double2 sm[];  // 3 rp lines of nx
+  const int n = K.nx, nxh = n / 2 + 1, hb = K.ny / (2 * rp);
+  const int b = xcd_band((int)blockIdx.x, (int)gridDim.x);
+  const int jb = (b % hb) * 2 * rp, k = b / hb;
+  const long long plane = (long long)nxh * K.ny * K.nz;
+  for (int e = threadIdx.x; e < 3 * rp * n; e += blockDim.x) {
+    const int line = e / n, kx = e - line * n;
+    const int q = line / 3, t = line - 3 * q, j0 = jb + 2 * q;
+    const bool mirror = kx >= nxh;
+    const int kk = mirror ? n - kx : kx;
+    long long o1, o2;
+    if (t < 2) {
+      o1 = kk + (long long)nxh * ((long long)(j0 + t) + (long long)K.ny * k);
+      o2 = plane + o1;
+    } else {
+      o1 = 2 * plane + kk + (long long)nxh * ((long long)j0 + (long long)K.ny * k);
+      o2 = o1 + nxh;
+    }
+    double2 P = Qh[o1], Q = Qh[o2];
+    if (mirror) {
+      P.y = -P.y;
+      Q.y = -Q.y;
+    }
+    sm[line * n + brev(kx, logn)] = make_double2(P.x - Q.y, P.y + Q.x);  // P + i Q
+  }
+  __syncthreads();
+  fft_lds(sm, n, logn, 3 * rp, tw, 1);
+  const double inv = 1.0 / (double)K.N;
+  const long long NN = K.N;
+  for (int e = threadIdx.x; e < 2 * rp * n; e += blockDim.x) {
+    const int rr = e / n, i = e - rr * n, j = jb + rr;
+    const int q = rr >> 1, l = rr & 1;
+    const long long m = (long long)i + (long long)n * ((long long)j + (long long)K.ny * k);
+    const double2 z = sm[(3 * q + l) * n + i];
+    const double2 z3 = sm[(3 * q + 2) * n + i];
+    u[m] = (T)(z.x * inv);
+    u[NN + m] = (T)(z.y * inv);
+    u[2 * NN + m] = (T)((l == 0 ? z3.x : z3.y) * inv);
+  }
+}
+
 __device__ inline int wrapi(int a, int n) {
   a += (a < 0) ? n : 0;
   a -= (a >= n) ? n : 0;
@@ -448,6 +634,34 @@ void launch_spectral_solve(const Consts& K, const FftPlan& P, const T* r, double
     hipLaunchKernelGGL(k_fft2_cols_solve, dim3(K.nx / 2 + 1), dim3(256), lcol, s, K, ly, P.tw[1], P.sn[0],
                        P.sn[1], work0);
     hipLaunchKernelGGL(k_fft2_rows_inv<T>, dim3(K.ny / nl), dim3(256), lrow, s, K, lx, nl, P.tw[0], work0, u);
+    return;
+  }
+  if (K.dim == 3 && K.nx >= 8 && K.nx <= 1024 && K.nz <= 1024 && K.ny <= 4096) {
+    const int lx = ilog2(K.nx), ly = ilog2(K.ny), lz = ilog2(K.nz);
+    const int nxh = K.nx / 2 + 1;
+    double2* Qh = work0;  // 3 nxh ny nz <= 2 N complex for nx >= 8
+    int rp = 256 / K.nx;  // row pairs per x block: about 768 points per block
+    if (rp < 1) rp = 1;
+    while (rp > 1 && (K.ny / 2) % rp) rp >>= 1;
+    const size_t lx_bytes = sizeof(double2) * 3 * rp * K.nx;
+    const unsigned xblocks = (unsigned)((K.ny / (2 * rp)) * K.nz);
+    int lpz = 1024 / K.nz;  // kx columns per z block: 48 KiB of LDS
+    if (lpz > 8) lpz = 8;
+    if (lpz < 1) lpz = 1;
+    const size_t lz_bytes = sizeof(double2) * 3 * lpz * K.nz;
+    const unsigned zblocks = (unsigned)(((nxh + lpz - 1) / lpz) * K.ny);
+    int lpy = kFftLds / K.ny;  // adjacent kx lines per y block
+    if (lpy > 16) lpy = 16;
+    const long long ylines = 3LL * nxh * K.nz;
+    const unsigned yblocks = (unsigned)((ylines + lpy - 1) / lpy);
+    hipLaunchKernelGGL(k_r2c_x<T>, dim3(xblocks), dim3(256), lx_bytes, s, K, r, a, zc, lx, rp, P.tw[0], Qh);
+    hipLaunchKernelGGL(k_fft_lines, dim3(yblocks), dim3(kFftThreads), 0, s, Qh, K.ny, ly, (long long)nxh,
+                       (long long)nxh, 1LL, (long long)nxh * K.ny, ylines, lpy, P.tw[1], 0, 0);
+    hipLaunchKernelGGL(k_z_solve, dim3(zblocks), dim3(256), lz_bytes, s, K, lz, lpz, P.tw[2], P.sn[0], P.sn[1],
+                       P.sn[2], Qh);
+    hipLaunchKernelGGL(k_fft_lines, dim3(yblocks), dim3(kFftThreads), 0, s, Qh, K.ny, ly, (long long)nxh,
+                       (long long)nxh, 1LL, (long long)nxh * K.ny, ylines, lpy, P.tw[1], 1, 0);
+    hipLaunchKernelGGL(k_c2r_x<T>, dim3(xblocks), dim3(256), lx_bytes, s, K, lx, rp, P.tw[0], Qh, u);
     return;
   }
   double2* z0 = work0;
