@@ -218,18 +218,21 @@ __global__ __launch_bounds__(TH, (TH == kRasThreadsSmall) ? 2 : 1) void k_ras(Co
   // The c row is taken in correction form, x_c = (res_c - u'E^{-1} res_e) / (d_cc - u'w) with
   // E^{-1} res_e = y - z_e - w z_c; the displacement rows (with_u) by their diagonal.
   auto update_node = [&](const R* rv, const R* Ai, const R* w, R id, int zi, int di, int q) {
-    R zv[NFZ];
+    R zv[NFZ], dgp[DIM], dgm[DIM];
 #pragma unroll
     for (int f = 0; f < NFZ; ++f) zv[f] = zs[f * zsz + zi];
-    // c row residual: r_c - (z_c/dt - div_h(M grad_h dG))
+    // c row residual: r_c - (z_c/dt - div_h(M grad_h dG)); the dG values at the node and its
+    // neighbours are kept for the write-back below
     R sumM = R(0), dM[3] = {R(0), R(0), R(0)};
     R divm = R(0);
     const R g0 = gg[di], dg0 = dg[di];
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
+      dgp[d] = dg[di + sdir_d[d]];
+      dgm[d] = dg[di - sdir_d[d]];
       const R Mp = hk * (g0 + gg[di + sdir_d[d]]);
       const R Mm = hk * (g0 + gg[di - sdir_d[d]]);
-      divm += Mp * (dg[di + sdir_d[d]] - dg0) - Mm * (dg0 - dg[di - sdir_d[d]]);
+      divm += Mp * (dgp[d] - dg0) - Mm * (dg0 - dgm[d]);
       sumM += Mp + Mm;
       dM[d] = Mm - Mp;
     }
@@ -279,14 +282,17 @@ __global__ __launch_bounds__(TH, (TH == kRasThreadsSmall) ? 2 : 1) void k_ras(Co
       }
     }
     const R sc = sumM * ih2;
+    R bcv[4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) bcv[f] = bc[f * ne + q];
     R t = R(0);
 #pragma unroll
-    for (int e = 0; e < 3; ++e) t += bc[(1 + e) * ne + q] * (y[e] - zv[1 + e] - w[e] * zv[0]);
+    for (int e = 0; e < 3; ++e) t += bcv[1 + e] * (y[e] - zv[1 + e] - w[e] * zv[0]);
     if (kPre) {
       xc = (xc - sc * t) * id;
     } else {
-      const R uw = sc * (bc[ne + q] * w[0] + bc[2 * ne + q] * w[1] + bc[3 * ne + q] * w[2]);
-      xc = (xc - sc * t) / (dcc0 + sc * (bc[q] + dcc1) - uw);
+      const R uw = sc * (bcv[1] * w[0] + bcv[2] * w[1] + bcv[3] * w[2]);
+      xc = (xc - sc * t) / (dcc0 + sc * (bcv[0] + dcc1) - uw);
     }
     const R zc = zv[0] + xc;
     zs[zi] = zc;
@@ -304,17 +310,18 @@ __global__ __launch_bounds__(TH, (TH == kRasThreadsSmall) ? 2 : 1) void k_ras(Co
     }
     // dG follows the change: at the node through B_c, kel and the centre of the Laplacian, at
     // the 2 DIM neighbours through the Laplacian (and the divergence of u).  Nodes of one
-    // colour share no neighbour, so these read-modify-writes never collide within a phase.
+    // colour are at least three steps apart, so no other update of this phase reads or writes
+    // these five (seven) dG values: the ones read above are still current.
     R dself = dgc * xc;
 #pragma unroll
-    for (int f = 0; f < 4; ++f) dself += bc[f * ne + q] * dz[f];
-    dg[di] += dself;
+    for (int f = 0; f < 4; ++f) dself += bcv[f] * dz[f];
+    dg[di] = dg0 + dself;
     const R dn = dgn * xc;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
       const R du = WU ? a_u * xu[d] : R(0);
-      dg[di + sdir_d[d]] += dn - du;
-      dg[di - sdir_d[d]] += dn + du;
+      dg[di + sdir_d[d]] = dgp[d] + (dn - du);
+      dg[di - sdir_d[d]] = dgm[d] + (dn + du);
     }
   };
 
