@@ -6,8 +6,12 @@
 // approximately with symmetric multicolour block Gauss-Seidel sweeps; only the owned nodes
 // are written back (the restricted prolongation R_t^0').
 //
-// The iterate of the whole extended tile lives in LDS with a zero ring two nodes wide (the
-// Jacobian couples nodes up to distance 2: the 13-point diamond in 2D, 25 points in 3D).
+// The iterate of the whole extended tile lives in LDS with a zero ring: one node wide for the
+// eta fields (nearest-neighbour coupling), two with the displacement rows (sigma reaches
+// distance 2).  Without them the c iterate is read only at its own node (its couplings to
+// the rest of the diamond go through dG, kept in LDS), so it stays in the registers of the
+// thread that owns the node.  The Jacobian couples nodes up to distance 2 (the 13-point
+// diamond in 2D, 25 points in 3D).
 // Colour (i + 2j) mod 5 (2D) or (i + 2j + 3k) mod 7 (3D) separates every pair of nodes
 // inside one diamond, so all nodes of a colour update at once, exactly as sequential
 // Gauss-Seidel would.  The per-node 4 x 4 chemical block B and the right-hand side stay in
@@ -24,8 +28,9 @@ namespace pf {
 
 namespace {
 
-// workgroup sizes of the tile kernel: 512 threads, or 256 when the tile fits three nodes per
-// thread and two workgroups fit the LDS of one compute unit (they then overlap their barriers)
+// workgroup sizes of the tile kernel: 512 threads, or 256 when the tile fits four nodes per
+// thread and two or more workgroups fit the LDS of one compute unit (they then overlap their
+// barriers, and fewer of their waves idle in a colour phase)
 constexpr int kRasThreadsMax = 512, kRasThreadsSmall = 256;
 
 // Schwarz variants (Section 4): left-RAS z = sum_t R0_t' A_t^{-1} R_t r (owned part of each
@@ -38,7 +43,7 @@ enum { kRasLeft = 0, kRasClassical = 1, kRasRight = 2 };
 
 struct Geo {
   int ex, ey, ez;      // extended tile
-  int zx, zy, zz;      // LDS iterate (ext + ring of 2; zz = 1 in 2D)
+  int zx, zy, zz;      // LDS iterate (ext + ring of 2 with u, of 1 without; zz = 1 in 2D)
   int dx, dy, dz;      // dG / mobility arrays (ext + ring of 1; dz = 1 in 2D)
   int ntx, nty;        // tiles per direction
   int tx, ty, tz, ov;
@@ -51,13 +56,15 @@ __device__ inline int wrapg(int a, int n) {
   return a < 0 ? a + n : a;
 }
 
-// float tiles are small enough that two workgroups share a compute unit's LDS (3D 8^3 tiles
-// with overlap 1: 80 KB each); registers are capped so that both fit (4 waves per SIMD)
-template <typename R>
-constexpr int ras_waves_per_simd() { return sizeof(R) == 4 ? 4 : 2; }
+// minimum waves per SIMD the registers are sized for (the second launch bound): two for
+// 256-thread workgroups (two or more per compute unit), one for 512 threads (one per unit)
+template <int TH>
+constexpr int ras_waves_per_eu() {
+  return TH == kRasThreadsSmall ? 2 : 1;
+}
 
 template <int DIM, bool WU, int NPT, typename R, int TH>
-__global__ __launch_bounds__(TH, (TH == kRasThreadsSmall) ? 2 : 1) void k_ras(Consts K, Geo G, double dt,
+__global__ __launch_bounds__(TH, (ras_waves_per_eu<TH>())) void k_ras(Consts K, Geo G, double dt,
                                                      const R* __restrict__ Bg,
                                                      const double* __restrict__ cn,
                                                      const R* __restrict__ rg,
@@ -65,14 +72,16 @@ __global__ __launch_bounds__(TH, (TH == kRasThreadsSmall) ? 2 : 1) void k_ras(Co
                                                      const int* __restrict__ permg,
                                                      R* __restrict__ xs) {
   constexpr int NFZ = WU ? 4 + DIM : 4;
+  constexpr int ZP0 = WU ? 0 : 1;     // first field of the iterate held in LDS
+  constexpr int NZL = NFZ - ZP0;      // its LDS planes
   constexpr int NCOL = (DIM == 3) ? 7 : 5;
   extern __shared__ double lds_raw[];
   R* lds = reinterpret_cast<R*>(lds_raw);
   const int zsz = G.zx * G.zy * G.zz;
   const int dsz = G.dx * G.dy * G.dz;
   const int ne = G.ex * G.ey * G.ez;
-  R* zs = lds;              // NFZ planes of zsz: the iterate with a zero ring of 2
-  R* dg = zs + NFZ * zsz;   // dsz: dG on ext and a ring of 1
+  R* zs = lds;              // NZL planes of zsz: fields ZP0.. of the iterate with a zero ring
+  R* dg = zs + NZL * zsz;   // dsz: dG on ext and a ring of 1
   R* gg = dg + dsz;         // dsz: g = c^n (1 - c^n)
   R* bc = gg + dsz;         // 4 planes of ne: c-row of the chemical block
 
@@ -86,7 +95,7 @@ __global__ __launch_bounds__(TH, (TH == kRasThreadsSmall) ? 2 : 1) void k_ras(Co
   const long long N = K.N;
   const int sy = G.zx, sz = G.zx * G.zy;    // LDS strides of the iterate
   const int ty_ = G.dx, tz_ = G.dx * G.dy;  // strides of dG / g
-  const int ring = 2;
+  const int ring = WU ? 2 : 1;
 
   // Set-up, one barrier: g and dG = 0 on ext and its ring, the c-row blocks (coalesced), the
   // zero iterate, and each thread's own nodes (right-hand side and eta rows of the blocks,
@@ -107,13 +116,14 @@ __global__ __launch_bounds__(TH, (TH == kRasThreadsSmall) ? 2 : 1) void k_ras(Co
 #pragma unroll
     for (int f = 0; f < 4; ++f) bc[f * ne + q] = Bg[f * N + n];
   }
-  for (int q = threadIdx.x; q < NFZ * zsz; q += TH) zs[q] = R(0);
+  for (int q = threadIdx.x; q < NZL * zsz; q += TH) zs[q] = R(0);
 
   // Nodes of this thread: positions threadIdx.x + m TH of the colour-sorted order permg (ext
   // nodes grouped by colour, the same for every tile of this shape; formed by the host), so
   // the nodes of one colour sit on consecutive threads.
   R rr[NPT][NFZ];
   R be[NPT][12];
+  R zcr_[NPT];  // c iterate of this thread's nodes (without u; LDS plane 0 with u)
   // per node, packed in 16-bit halves (every index is below 2^16): zd = iterate position |
   // dG position << 16; qc = ext index
   int zd_[NPT], qc_[NPT];
@@ -123,6 +133,7 @@ __global__ __launch_bounds__(TH, (TH == kRasThreadsSmall) ? 2 : 1) void k_ras(Co
     const int pos = threadIdx.x + m * TH;
     col_[m] = -1;
     zd_[m] = qc_[m] = 0;
+    zcr_[m] = R(0);
     if (pos < ne) {
       const int q = permg[pos];
       const int a = q % G.ex, b = (q / G.ex) % G.ey, c = q / (G.ex * G.ey);
@@ -187,28 +198,23 @@ __global__ __launch_bounds__(TH, (TH == kRasThreadsSmall) ? 2 : 1) void k_ras(Co
 #pragma unroll
     for (int e = 0; e < 3; ++e) w[e] = Ai[3 * e] * v1 + Ai[3 * e + 1] * v2 + Ai[3 * e + 2] * v3;
   };
-  // Float tiles keep E^{-1}, w and 1 / (d_cc - u'w) per node in registers (formed once);
-  // double tiles keep the 12 eta-row entries of B instead and form them in every update
-  // (the precomputed form does not fit the registers of three double nodes per thread).
-  constexpr bool kPre = sizeof(R) == 4;
-  constexpr int NPRE = kPre ? NPT : 1;
-  R ai[NPRE][9], wq[NPRE][3], invd[NPRE];
-  if constexpr (kPre) {
+  // E^{-1}, w and 1 / (d_cc - u'w) of each of this thread's nodes stay in registers, formed
+  // once per apply (the B entries they come from are not needed afterwards).
+  R ai[NPT][9], wq[NPT][3], invd[NPT];
 #pragma unroll
-    for (int m = 0; m < NPT; ++m) {
-      block_inverse(be[m], ai[m], wq[m]);
-      invd[m] = R(0);
-      if (col_[m] >= 0) {
-        const int di = zd_[m] >> 16, q = qc_[m];
-        const R g0 = gg[di];
-        R sumM = R(0);
+  for (int m = 0; m < NPT; ++m) {
+    block_inverse(be[m], ai[m], wq[m]);
+    invd[m] = R(0);
+    if (col_[m] >= 0) {
+      const int di = zd_[m] >> 16, q = qc_[m];
+      const R g0 = gg[di];
+      R sumM = R(0);
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) sumM += hk * (g0 + gg[di + sdir_d[d]]) + hk * (g0 + gg[di - sdir_d[d]]);
-        const R sc = sumM * ih2;
-        const R dcc = dcc0 + sc * (bc[q] + dcc1);
-        const R uw = sc * (bc[ne + q] * wq[m][0] + bc[2 * ne + q] * wq[m][1] + bc[3 * ne + q] * wq[m][2]);
-        invd[m] = R(1) / (dcc - uw);
-      }
+      for (int d = 0; d < DIM; ++d) sumM += hk * (g0 + gg[di + sdir_d[d]]) + hk * (g0 + gg[di - sdir_d[d]]);
+      const R sc = sumM * ih2;
+      const R dcc = dcc0 + sc * (bc[q] + dcc1);
+      const R uw = sc * (bc[ne + q] * wq[m][0] + bc[2 * ne + q] * wq[m][1] + bc[3 * ne + q] * wq[m][2]);
+      invd[m] = R(1) / (dcc - uw);
     }
   }
 
@@ -217,10 +223,11 @@ __global__ __launch_bounds__(TH, (TH == kRasThreadsSmall) ? 2 : 1) void k_ras(Co
   // new values satisfy E z_e' + v z_c' = rhs_e, so z_e' = y - w z_c' with y = E^{-1} rhs_e.
   // The c row is taken in correction form, x_c = (res_c - u'E^{-1} res_e) / (d_cc - u'w) with
   // E^{-1} res_e = y - z_e - w z_c; the displacement rows (with_u) by their diagonal.
-  auto update_node = [&](const R* rv, const R* Ai, const R* w, R id, int zi, int di, int q) {
+  auto update_node = [&](const R* rv, const R* Ai, const R* w, R id, int zi, int di, int q, R& zcr) {
     R zv[NFZ], dgp[DIM], dgm[DIM];
+    zv[0] = WU ? zs[zi] : zcr;
 #pragma unroll
-    for (int f = 0; f < NFZ; ++f) zv[f] = zs[f * zsz + zi];
+    for (int f = 1; f < NFZ; ++f) zv[f] = zs[(f - ZP0) * zsz + zi];
     // c row residual: r_c - (z_c/dt - div_h(M grad_h dG)); the dG values at the node and its
     // neighbours are kept for the write-back below
     R sumM = R(0), dM[3] = {R(0), R(0), R(0)};
@@ -241,7 +248,7 @@ __global__ __launch_bounds__(TH, (TH == kRasThreadsSmall) ? 2 : 1) void k_ras(Co
     R rh[3];
 #pragma unroll
     for (int e = 0; e < 3; ++e) {
-      const int ze = (1 + e) * zsz + zi;
+      const int ze = (1 + e - ZP0) * zsz + zi;
       R nb = R(0);
 #pragma unroll
       for (int d = 0; d < DIM; ++d) nb += zs[ze + sdir_z[d]] + zs[ze - sdir_z[d]];
@@ -288,20 +295,16 @@ __global__ __launch_bounds__(TH, (TH == kRasThreadsSmall) ? 2 : 1) void k_ras(Co
     R t = R(0);
 #pragma unroll
     for (int e = 0; e < 3; ++e) t += bcv[1 + e] * (y[e] - zv[1 + e] - w[e] * zv[0]);
-    if (kPre) {
-      xc = (xc - sc * t) * id;
-    } else {
-      const R uw = sc * (bcv[1] * w[0] + bcv[2] * w[1] + bcv[3] * w[2]);
-      xc = (xc - sc * t) / (dcc0 + sc * (bcv[0] + dcc1) - uw);
-    }
+    xc = (xc - sc * t) * id;
     const R zc = zv[0] + xc;
-    zs[zi] = zc;
+    if (WU) zs[zi] = zc;
+    else zcr = zc;
     R dz[4];
     dz[0] = xc;
 #pragma unroll
     for (int e = 0; e < 3; ++e) {
       const R ze = y[e] - w[e] * zc;
-      zs[(1 + e) * zsz + zi] = ze;
+      zs[(1 + e - ZP0) * zsz + zi] = ze;
       dz[1 + e] = ze - zv[1 + e];
     }
     if (WU) {
@@ -326,61 +329,67 @@ __global__ __launch_bounds__(TH, (TH == kRasThreadsSmall) ? 2 : 1) void k_ras(Co
   };
 
   // Symmetric multicolour sweeps.  dG (zero for the zero initial iterate) is kept current by
-  // the updates themselves, so a colour phase is just the update of its nodes.
-  for (int sw = 0; sw < G.sweeps; ++sw) {
-    for (int pass = 0; pass < 2; ++pass) {
-      for (int cc = 0; cc < NCOL; ++cc) {
-        const int col = pass == 0 ? cc : NCOL - 1 - cc;
-        // ---- update the nodes of this colour (a contiguous range of threads) -------------
-        // A thread's nodes lie in different colour ranges (a range is shorter than the block),
-        // so at most one of them is active here: select it, then run one copy of the update.
-        int msel = -1;
+  // the updates themselves, so a colour phase is just the update of its nodes.  Where the
+  // colour order turns (the last colour of a forward pass, the first of a backward pass) the
+  // same colour would be updated twice in a row; the second update solves the same node
+  // equations with the same neighbours, so it changes nothing but rounding and is left out:
+  // the phases run the colours 0 1 .. NCOL-1 .. 1 0 1 .. with period 2 (NCOL - 1), sweeps
+  // times and once more for the final colour 0.
+  const int period = 2 * (NCOL - 1);
+  const int nphase = G.sweeps > 0 ? G.sweeps * period + 1 : 0;
+  for (int ph = 0; ph < nphase; ++ph) {
+    const int pm = ph % period;
+    const int col = pm < NCOL ? pm : period - pm;
+    // ---- update the nodes of this colour (a contiguous range of threads) -------------
+    // A thread's nodes lie in different colour ranges (a range is shorter than the block),
+    // so at most one of them is active here: select it, then run one copy of the update.
+    int msel = -1;
 #pragma unroll
-        for (int m = 0; m < NPT; ++m)
-          if (col_[m] == col) msel = m;
-        if (msel >= 0) {
-          R rv[NFZ], av[9], wv[3], idv = R(0);
-          int zd = zd_[0], q = qc_[0];
+    for (int m = 0; m < NPT; ++m)
+      if (col_[m] == col) msel = m;
+    if (msel >= 0) {
+      R rv[NFZ], av[9], wv[3], idv = R(0), zcv = zcr_[0];
+      int zd = zd_[0], q = qc_[0];
 #pragma unroll
-          for (int f = 0; f < NFZ; ++f) rv[f] = rr[0][f];
+      for (int f = 0; f < NFZ; ++f) rv[f] = rr[0][f];
 #pragma unroll
-          for (int m = 1; m < NPT; ++m) {
-            const bool sel = (msel == m);
+      for (int m = 1; m < NPT; ++m) {
+        const bool sel = (msel == m);
 #pragma unroll
-            for (int f = 0; f < NFZ; ++f) rv[f] = sel ? rr[m][f] : rv[f];
-            zd = sel ? zd_[m] : zd;
-            q = sel ? qc_[m] : q;
-          }
-          if constexpr (kPre) {
-            idv = invd[0];
+        for (int f = 0; f < NFZ; ++f) rv[f] = sel ? rr[m][f] : rv[f];
+        zd = sel ? zd_[m] : zd;
+        q = sel ? qc_[m] : q;
+        zcv = sel ? zcr_[m] : zcv;
+      }
+      idv = invd[0];
 #pragma unroll
-            for (int k = 0; k < 9; ++k) av[k] = ai[0][k];
+      for (int k = 0; k < 9; ++k) av[k] = ai[0][k];
 #pragma unroll
-            for (int e = 0; e < 3; ++e) wv[e] = wq[0][e];
+      for (int e = 0; e < 3; ++e) wv[e] = wq[0][e];
 #pragma unroll
-            for (int m = 1; m < NPT; ++m) {
-              const bool sel = (msel == m);
+      for (int m = 1; m < NPT; ++m) {
+        const bool sel = (msel == m);
 #pragma unroll
-              for (int k = 0; k < 9; ++k) av[k] = sel ? ai[m][k] : av[k];
+        for (int k = 0; k < 9; ++k) av[k] = sel ? ai[m][k] : av[k];
 #pragma unroll
-              for (int e = 0; e < 3; ++e) wv[e] = sel ? wq[m][e] : wv[e];
-              idv = sel ? invd[m] : idv;
-            }
-          } else {
-            R bv[12];
+        for (int e = 0; e < 3; ++e) wv[e] = sel ? wq[m][e] : wv[e];
+        idv = sel ? invd[m] : idv;
+      }
+      update_node(rv, av, wv, idv, zd & 0xffff, zd >> 16, q, zcv);
+      if (!WU) {
 #pragma unroll
-            for (int f = 0; f < 12; ++f) bv[f] = be[0][f];
-#pragma unroll
-            for (int m = 1; m < NPT; ++m)
-#pragma unroll
-              for (int f = 0; f < 12; ++f) bv[f] = (msel == m) ? be[m][f] : bv[f];
-            block_inverse(bv, av, wv);
-          }
-          update_node(rv, av, wv, idv, zd & 0xffff, zd >> 16, q);
-        }
-        __syncthreads();
+        for (int m = 0; m < NPT; ++m) zcr_[m] = (msel == m) ? zcv : zcr_[m];
       }
     }
+    __syncthreads();
+  }
+  if (!WU) {
+    // the c iterate, held by the threads that own the nodes, goes to LDS in ext order (dG is
+    // no longer read: the last phase ended with a barrier)
+#pragma unroll
+    for (int m = 0; m < NPT; ++m)
+      if (col_[m] >= 0) dg[qc_[m]] = zcr_[m];
+    __syncthreads();
   }
   if (G.mode != kRasLeft) {
     // the whole extended solution, to be summed by the gather kernel
@@ -388,8 +397,9 @@ __global__ __launch_bounds__(TH, (TH == kRasThreadsSmall) ? 2 : 1) void k_ras(Co
     for (int q = threadIdx.x; q < ne; q += TH) {
       const int a = q % G.ex, b = (q / G.ex) % G.ey, c = q / (G.ex * G.ey);
       const int zi = (a + ring) + sy * (b + ring) + ((DIM == 3) ? sz * (c + ring) : 0);
+      out[q] = WU ? zs[zi] : dg[q];
 #pragma unroll
-      for (int f = 0; f < NFZ; ++f) out[f * ne + q] = zs[f * zsz + zi];
+      for (int f = 1; f < NFZ; ++f) out[f * ne + q] = zs[(f - ZP0) * zsz + zi];
     }
     return;
   }
@@ -402,8 +412,9 @@ __global__ __launch_bounds__(TH, (TH == kRasThreadsSmall) ? 2 : 1) void k_ras(Co
     const int gk = (DIM == 3) ? wrapg(oz + c, K.nz) : 0;
     const long long n = gi + (long long)K.nx * (gj + (long long)K.ny * gk);
     const int zi = (a + ring) + sy * (b + ring) + ((DIM == 3) ? sz * (c + ring) : 0);
+    zg[n] = WU ? zs[zi] : dg[q];
 #pragma unroll
-    for (int f = 0; f < NFZ; ++f) zg[f * N + n] = zs[f * zsz + zi];
+    for (int f = 1; f < NFZ; ++f) zg[f * N + n] = zs[(f - ZP0) * zsz + zi];
   }
 }
 
@@ -457,9 +468,10 @@ Geo make_geo(const Consts& K, const TileCfg& T) {
   G.ex = T.tx + 2 * T.ov;
   G.ey = T.ty + 2 * T.ov;
   G.ez = (K.dim == 3) ? T.tz + 2 * T.ov : 1;
-  G.zx = G.ex + 4;
-  G.zy = G.ey + 4;
-  G.zz = (K.dim == 3) ? G.ez + 4 : 1;
+  const int ring = T.with_u ? 2 : 1;
+  G.zx = G.ex + 2 * ring;
+  G.zy = G.ey + 2 * ring;
+  G.zz = (K.dim == 3) ? G.ez + 2 * ring : 1;
   G.dx = G.ex + 2;
   G.dy = G.ey + 2;
   G.dz = (K.dim == 3) ? G.ez + 2 : 1;
@@ -478,6 +490,14 @@ void launch_npt(const Geo& G, const Consts& K, size_t lds, int ntiles, int npt, 
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                  \
     hipLaunchKernelGGL((k_ras<DIM, WU, NPTV, R, TH>), dim3(ntiles), dim3(TH), lds, s, K, G, dt, B, cn, r, z, perm, xs); \
     break;
+  if constexpr (TH == kRasThreadsSmall) {
+    if (npt == 4) {
+      (void)hipFuncSetAttribute((const void*)k_ras<DIM, WU, 4, R, TH>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds);
+      hipLaunchKernelGGL((k_ras<DIM, WU, 4, R, TH>), dim3(ntiles), dim3(TH), lds, s, K, G, dt, B, cn, r, z, perm, xs);
+      return;
+    }
+  }
   switch (npt) {
     PF_RAS_CASE(1)
     PF_RAS_CASE(2)
@@ -501,21 +521,33 @@ void launch_dim(const Consts& K, const Geo& G, size_t lds, int ntiles, int th, i
   }
 }
 
-// nodes of the extended tile per thread (1..3) at th threads, 0 if more than three
-int npt_for(int dim, const Geo& G, int th) {
-  (void)dim;
+// nodes of the extended tile per thread at th threads: up to four with 256 threads, three
+// with 512; 0 beyond
+int npt_for(const Geo& G, int th) {
   const int ne = G.ex * G.ey * G.ez;
   const int npt = (ne + th - 1) / th;
-  return npt <= 3 ? npt : 0;
+  return npt <= (th == kRasThreadsSmall ? 4 : 3) ? npt : 0;
+}
+
+// largest number of extended-tile nodes of one colour (a colour's nodes sit on consecutive
+// threads, so that each thread has at most one active node per phase: at most th of them)
+int max_colour_nodes(int dim, const Geo& G) {
+  int cnt[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int c = 0; c < G.ez; ++c)
+    for (int b = 0; b < G.ey; ++b)
+      for (int a = 0; a < G.ex; ++a) ++cnt[(dim == 3) ? (a + 2 * b + 3 * c) % 7 : (a + 2 * b) % 5];
+  int m = 0;
+  for (int k = 0; k < 7; ++k) m = cnt[k] > m ? cnt[k] : m;
+  return m;
 }
 
 }  // namespace
 
 size_t ras_lds_bytes(const Consts& K, const TileCfg& T, size_t real_bytes) {
   const Geo G = make_geo(K, T);
-  const int nfz = T.with_u ? 4 + K.dim : 4;
+  const int nzl = T.with_u ? 4 + K.dim : 3;  // LDS planes of the iterate
   const size_t ne = (size_t)G.ex * G.ey * G.ez;
-  return real_bytes * ((size_t)nfz * G.zx * G.zy * G.zz + 2 * (size_t)G.dx * G.dy * G.dz + 4 * ne);
+  return real_bytes * ((size_t)nzl * G.zx * G.zy * G.zz + 2 * (size_t)G.dx * G.dy * G.dz + 4 * ne);
 }
 
 int ras_ext_nodes(const Consts& K, const TileCfg& T) {
@@ -538,12 +570,14 @@ void ras_colour_order(const Consts& K, const TileCfg& T, int* perm) {
 
 int ras_threads(const Consts& K, const TileCfg& T, size_t real_bytes, int* npt) {
   const Geo G = make_geo(K, T);
-  const int ns = npt_for(K.dim, G, kRasThreadsSmall);
-  if (!T.with_u && ns > 0 && 2 * ras_lds_bytes(K, T, real_bytes) <= 160 * 1024) {
+  const int ns = npt_for(G, kRasThreadsSmall);
+  if (!T.with_u && ns > 0 && max_colour_nodes(K.dim, G) <= kRasThreadsSmall &&
+      2 * ras_lds_bytes(K, T, real_bytes) <= 160 * 1024) {
     if (npt) *npt = ns;
     return kRasThreadsSmall;
   }
-  const int nm = npt_for(K.dim, G, kRasThreadsMax);
+  const int nm = npt_for(G, kRasThreadsMax);
+  if (nm > 0 && max_colour_nodes(K.dim, G) > kRasThreadsMax) return 0;
   if (npt) *npt = nm;
   return nm > 0 ? kRasThreadsMax : 0;
 }

@@ -142,14 +142,17 @@ int validate(const pfnks_grid* g, const pfnks_model* m, const pfnks_solver* s) {
   if (!(m->kappa >= 0.0) || !(m->L_eta > 0.0) || m->Lscale < 0.0) return PFNKS_EINVAL;
   // extended tile must fit the kernel's registers (<= 3 nodes per thread of 512) and the
   // 160 KiB of LDS of one compute unit
+  // (the iterate's LDS planes: all 4 + dim fields with a ring of two when the tiles solve the
+  // displacement too, else the three eta fields with a ring of one)
+  const bool all = tiles_all_fields(s->pc);
   long long ext = 1, zpad = 1, dpad = 1;
   for (int k = 0; k < g->dim; ++k) {
     ext *= s->tile[k] + 2 * s->overlap;
-    zpad *= s->tile[k] + 2 * s->overlap + 4;
+    zpad *= s->tile[k] + 2 * s->overlap + (all ? 4 : 2);
     dpad *= s->tile[k] + 2 * s->overlap + 2;
   }
   if (ext > 3 * 512) return PFNKS_EINVAL;
-  const int nfz = tiles_all_fields(s->pc) ? 4 + g->dim : 4;
+  const int nfz = all ? 4 + g->dim : 3;
   const long long kb = (long long)krylov_bytes(s->precision);
   if (uses_tiles(s->pc) && kb * (nfz * zpad + 2 * dpad + 4 * ext) > 160 * 1024) return PFNKS_EINVAL;
   return PFNKS_OK;

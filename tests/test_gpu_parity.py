@@ -260,10 +260,10 @@ def test_step_parity_pf2d_64(oracle_c1, pc, prec):
 
 @pytest.mark.parametrize("tile,prec,overlap", [((16, 32), "fp64", 2), ((32, 16), "fp64", 2), ((16, 16), "fp64", 2),
                                                ((16, 32), "mixed", 2), ((8, 8), "fp64", 2), ((16, 16), "fp64", 0),
-                                               ((32, 32), "fp64", 1)])
+                                               ((32, 32), "fp64", 1), ((16, 32), "fp64", 4), ((16, 32), "mixed", 4)])
 def test_step_parity_tile_shapes(oracle_c1, tile, prec, overlap):
     """2D 64 x 64, 3 steps with other Schwarz tile shapes and overlaps (they select the
-    256-thread tile kernel and other nodes-per-thread counts; overlap 0 is the classical
+    256-thread tile kernel and 1 to 4 nodes per thread; overlap 0 is the classical
     block-Jacobi / additive Schwarz of the paper's overlap-0 runs): within 1e-8 of the
     oracle's root."""
     from paper_2209_08001_amd import pfnks
