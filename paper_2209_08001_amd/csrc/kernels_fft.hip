@@ -163,7 +163,9 @@ __global__ __launch_bounds__(256) void k_fft2_rows_fwd(Consts K, const T* __rest
 }
 
 // pass 2: the column pair (kx, -kx): forward FFT along y, pointwise solve of the 2 x 2
-// symbol system (needs Z(k) and Z(-k), both in this block), inverse FFT along y.
+// symbol system (needs Z(k) and Z(-k), both in this block), inverse FFT along y.  Block kx
+// (0 .. nx/2 - 1) takes columns kx and nx - kx; block 0 takes the two columns that are
+// their own mirrors, 0 and nx/2, so that nx/2 blocks cover the spectrum.
 __global__ __launch_bounds__(256) void k_fft2_cols_solve(Consts K, int logn, const double2* __restrict__ tw,
                                                          const double* __restrict__ sx,
                                                          const double* __restrict__ syt,
@@ -171,11 +173,11 @@ __global__ __launch_bounds__(256) void k_fft2_cols_solve(Consts K, int logn, con
   extern __shared__ double2 sm[];  // 2 n, then the output spectra (2 n)
   double2* wo = sm + 2 * K.ny;
   const int n = K.ny, nx = K.nx;
-  // 0 .. nx/2; the first multiple-of-8 blocks in XCD-band order, so that the columns one XCD
-  // reads are adjacent and share cache lines
-  const int kx = xcd_band(blockIdx.x, (gridDim.x - 1) & ~7);
-  const int kxm = (kx == 0) ? 0 : nx - kx;
-  const int ncol = (kx == kxm) ? 1 : 2;
+  // XCD-band order, so that the columns one XCD reads are adjacent and share cache lines
+  const int kx = xcd_band(blockIdx.x, gridDim.x);
+  const bool self = (kx == 0);
+  const int kxm = self ? nx / 2 : nx - kx;
+  constexpr int ncol = 2;
   for (int e = threadIdx.x; e < ncol * n; e += blockDim.x) {
     const int l = e / n, j = e - l * n;
     const int col = l ? kxm : kx;
@@ -186,7 +188,7 @@ __global__ __launch_bounds__(256) void k_fft2_cols_solve(Consts K, int logn, con
   for (int e = threadIdx.x; e < ncol * n; e += blockDim.x) {
     const int l = e / n, j = e - l * n;
     const int col = l ? kxm : kx;
-    const int lm = (ncol == 1) ? 0 : 1 - l;   // the mirror column's line
+    const int lm = self ? l : 1 - l;   // the mirror column's line
     const int jm = (j == 0) ? 0 : n - j;
     const double2 av = sm[l * n + j], bv = sm[lm * n + jm];
     double2 Q0 = make_double2(0.5 * (av.x + bv.x), 0.5 * (av.y - bv.y));
@@ -631,7 +633,7 @@ void launch_spectral_solve(const Consts& K, const FftPlan& P, const T* r, double
     while (K.ny % nl) nl >>= 1;
     const size_t lrow = sizeof(double2) * nl * K.nx, lcol = sizeof(double2) * 4 * K.ny;
     hipLaunchKernelGGL(k_fft2_rows_fwd<T>, dim3(K.ny / nl), dim3(256), lrow, s, K, r, a, zc, lx, nl, P.tw[0], work0);
-    hipLaunchKernelGGL(k_fft2_cols_solve, dim3(K.nx / 2 + 1), dim3(256), lcol, s, K, ly, P.tw[1], P.sn[0],
+    hipLaunchKernelGGL(k_fft2_cols_solve, dim3(K.nx / 2), dim3(256), lcol, s, K, ly, P.tw[1], P.sn[0],
                        P.sn[1], work0);
     hipLaunchKernelGGL(k_fft2_rows_inv<T>, dim3(K.ny / nl), dim3(256), lrow, s, K, lx, nl, P.tw[0], work0, u);
     return;

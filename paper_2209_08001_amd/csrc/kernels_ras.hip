@@ -335,6 +335,10 @@ __global__ __launch_bounds__(TH, (ras_waves_per_eu<TH>())) void k_ras(Consts K, 
   // equations with the same neighbours, so it changes nothing but rounding and is left out:
   // the phases run the colours 0 1 .. NCOL-1 .. 1 0 1 .. with period 2 (NCOL - 1), sweeps
   // times and once more for the final colour 0.
+  // The update runs on the active node slot's registers through one branch per slot where the
+  // registers allow the copies (tiles without u, up to two nodes per thread or three in 2D);
+  // the others select the slot's values into one copy, which keeps their occupancy.
+  constexpr bool kBranch = !WU && (NPT <= 2 || (NPT == 3 && DIM == 2));
   const int period = 2 * (NCOL - 1);
   const int nphase = G.sweeps > 0 ? G.sweeps * period + 1 : 0;
   for (int ph = 0; ph < nphase; ++ph) {
@@ -342,26 +346,23 @@ __global__ __launch_bounds__(TH, (ras_waves_per_eu<TH>())) void k_ras(Consts K, 
     const int col = pm < NCOL ? pm : period - pm;
     // ---- update the nodes of this colour (a contiguous range of threads) -------------
     // A thread's nodes lie in different colour ranges (a range is shorter than the block),
-    // so at most one of them is active here: select it, then run one copy of the update.
+    // so at most one of them is active here.
     int msel = -1;
 #pragma unroll
     for (int m = 0; m < NPT; ++m)
       if (col_[m] == col) msel = m;
-    if (msel >= 0) {
-      R rv[NFZ], av[9], wv[3], idv = R(0), zcv = zcr_[0];
+    if constexpr (kBranch) {
+      // one copy of the update per node slot, each on that slot's registers directly; within
+      // a wave the active slot is the same for all lanes except at the ends of a colour range
+#pragma unroll
+      for (int m = 0; m < NPT; ++m)
+        if (msel == m) update_node(rr[m], ai[m], wq[m], invd[m], zd_[m] & 0xffff, zd_[m] >> 16, qc_[m], zcr_[m]);
+    } else if (msel >= 0) {
+      // one copy of the update on the active slot's values, selected into registers
+      R rv[NFZ], av[9], wv[3], idv = invd[0], zcv = zcr_[0];
       int zd = zd_[0], q = qc_[0];
 #pragma unroll
       for (int f = 0; f < NFZ; ++f) rv[f] = rr[0][f];
-#pragma unroll
-      for (int m = 1; m < NPT; ++m) {
-        const bool sel = (msel == m);
-#pragma unroll
-        for (int f = 0; f < NFZ; ++f) rv[f] = sel ? rr[m][f] : rv[f];
-        zd = sel ? zd_[m] : zd;
-        q = sel ? qc_[m] : q;
-        zcv = sel ? zcr_[m] : zcv;
-      }
-      idv = invd[0];
 #pragma unroll
       for (int k = 0; k < 9; ++k) av[k] = ai[0][k];
 #pragma unroll
@@ -370,10 +371,15 @@ __global__ __launch_bounds__(TH, (ras_waves_per_eu<TH>())) void k_ras(Consts K, 
       for (int m = 1; m < NPT; ++m) {
         const bool sel = (msel == m);
 #pragma unroll
+        for (int f = 0; f < NFZ; ++f) rv[f] = sel ? rr[m][f] : rv[f];
+#pragma unroll
         for (int k = 0; k < 9; ++k) av[k] = sel ? ai[m][k] : av[k];
 #pragma unroll
         for (int e = 0; e < 3; ++e) wv[e] = sel ? wq[m][e] : wv[e];
         idv = sel ? invd[m] : idv;
+        zd = sel ? zd_[m] : zd;
+        q = sel ? qc_[m] : q;
+        zcv = sel ? zcr_[m] : zcv;
       }
       update_node(rv, av, wv, idv, zd & 0xffff, zd >> 16, q, zcv);
       if (!WU) {
