@@ -20,7 +20,7 @@ namespace pf {
 namespace {
 
 constexpr int kFftThreads = 256;
-constexpr int kFftLds = 4096;  // complex doubles per workgroup (64 KiB)
+constexpr int kFftLds = 4096;  // complex doubles of line data per workgroup (64 KiB; twiddles extra)
 
 __device__ inline double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -77,6 +77,13 @@ __device__ inline void fft_lds(double2* buf, int n, int logn, int nl, const doub
   }
 }
 
+// The twiddles W_n^k, k < n/2, copied into LDS (tws) once per workgroup: every stage of the
+// in-LDS transforms reads three per butterfly, which would otherwise wait on global loads.
+// Visible after the workgroup's next barrier.
+__device__ inline void stage_twiddles(double2* tws, const double2* __restrict__ tw, int n) {
+  for (int e = threadIdx.x; e < n / 2; e += blockDim.x) tws[e] = tw[e];
+}
+
 // Lines of length n (power of two), points pstride apart; line l starts at
 // (l % la) * lb + (l / la) * lc.  contiguous = 1 when pstride == 1 (threads walk along a line),
 // else consecutive threads take consecutive lines (la lines adjacent in memory).
@@ -85,7 +92,9 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_lines(double2* __restrict__
                                                            long long lb, long long lc, long long nlines,
                                                            int lpb, const double2* __restrict__ tw,
                                                            int inverse, int contiguous) {
-  __shared__ double2 sm[kFftLds];
+  extern __shared__ double2 sm[];  // lpb lines of n, then n/2 twiddles
+  double2* tws = sm + lpb * n;
+  stage_twiddles(tws, tw, n);
   const long long line0 = (long long)blockIdx.x * lpb;
   const int total = lpb * n;
   for (int e = threadIdx.x; e < total; e += kFftThreads) {
@@ -105,7 +114,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_lines(double2* __restrict__
     }
   }
   __syncthreads();
-  fft_lds(sm, n, logn, lpb, tw, inverse);
+  fft_lds(sm, n, logn, lpb, tws, inverse);
   for (int e = threadIdx.x; e < total; e += kFftThreads) {
     int l, p;
     if (contiguous) {
@@ -139,8 +148,10 @@ __global__ __launch_bounds__(256) void k_fft2_rows_fwd(Consts K, const T* __rest
                                                        const T* __restrict__ zc, int logn, int nl,
                                                        const double2* __restrict__ tw,
                                                        double2* __restrict__ out) {
-  extern __shared__ double2 sm[];  // nl * n
+  extern __shared__ double2 sm[];  // nl * n, then n/2 twiddles
   const int n = K.nx;
+  double2* tws = sm + nl * n;
+  stage_twiddles(tws, tw, n);
   const int j0 = xcd_band(blockIdx.x, gridDim.x) * nl;
   for (int e = threadIdx.x; e < nl * n; e += blockDim.x) {
     const int l = e / n, i = e - l * n, j = j0 + l;
@@ -155,7 +166,7 @@ __global__ __launch_bounds__(256) void k_fft2_rows_fwd(Consts K, const T* __rest
     sm[l * n + brev(i, logn)] = make_double2(qx, qy);
   }
   __syncthreads();
-  fft_lds(sm, n, logn, nl, tw, 0);
+  fft_lds(sm, n, logn, nl, tws, 0);
   for (int e = threadIdx.x; e < nl * n; e += blockDim.x) {
     const int l = e / n, i = e - l * n;
     out[(long long)i + (long long)n * (j0 + l)] = sm[e];
@@ -170,9 +181,11 @@ __global__ __launch_bounds__(256) void k_fft2_cols_solve(Consts K, int logn, con
                                                          const double* __restrict__ sx,
                                                          const double* __restrict__ syt,
                                                          double2* __restrict__ data) {
-  extern __shared__ double2 sm[];  // 2 n, then the output spectra (2 n)
+  extern __shared__ double2 sm[];  // 2 n, then the output spectra (2 n), then n/2 twiddles
   double2* wo = sm + 2 * K.ny;
   const int n = K.ny, nx = K.nx;
+  double2* tws = sm + 4 * n;
+  stage_twiddles(tws, tw, n);
   // XCD-band order, so that the columns one XCD reads are adjacent and share cache lines
   const int kx = xcd_band(blockIdx.x, gridDim.x);
   const bool self = (kx == 0);
@@ -184,7 +197,7 @@ __global__ __launch_bounds__(256) void k_fft2_cols_solve(Consts K, int logn, con
     sm[l * n + brev(j, logn)] = data[(long long)col + (long long)nx * j];
   }
   __syncthreads();
-  fft_lds(sm, n, logn, ncol, tw, 0);
+  fft_lds(sm, n, logn, ncol, tws, 0);
   for (int e = threadIdx.x; e < ncol * n; e += blockDim.x) {
     const int l = e / n, j = e - l * n;
     const int col = l ? kxm : kx;
@@ -210,7 +223,7 @@ __global__ __launch_bounds__(256) void k_fft2_cols_solve(Consts K, int logn, con
     wo[l * n + brev(j, logn)] = make_double2(U0.x - U1.y, U0.y + U1.x);
   }
   __syncthreads();
-  fft_lds(wo, n, logn, ncol, tw, 1);
+  fft_lds(wo, n, logn, ncol, tws, 1);
   for (int e = threadIdx.x; e < ncol * n; e += blockDim.x) {
     const int l = e / n, j = e - l * n;
     const int col = l ? kxm : kx;
@@ -222,15 +235,17 @@ __global__ __launch_bounds__(256) void k_fft2_cols_solve(Consts K, int logn, con
 template <typename T>
 __global__ __launch_bounds__(256) void k_fft2_rows_inv(Consts K, int logn, int nl, const double2* __restrict__ tw,
                                                        const double2* __restrict__ in, T* __restrict__ u) {
-  extern __shared__ double2 sm[];  // nl * n
+  extern __shared__ double2 sm[];  // nl * n, then n/2 twiddles
   const int n = K.nx;
+  double2* tws = sm + nl * n;
+  stage_twiddles(tws, tw, n);
   const int j0 = xcd_band(blockIdx.x, gridDim.x) * nl;
   for (int e = threadIdx.x; e < nl * n; e += blockDim.x) {
     const int l = e / n, i = e - l * n;
     sm[l * n + brev(i, logn)] = in[(long long)i + (long long)n * (j0 + l)];
   }
   __syncthreads();
-  fft_lds(sm, n, logn, nl, tw, 1);
+  fft_lds(sm, n, logn, nl, tws, 1);
   const double inv = 1.0 / (double)K.N;
   for (int e = threadIdx.x; e < nl * n; e += blockDim.x) {
     const int l = e / n, i = e - l * n;
@@ -256,8 +271,10 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_r2c_x(Consts K, const T* __restrict__ r, double a,
                                                const T* __restrict__ zc, int logn, int rp,
                                                const double2* __restrict__ tw, double2* __restrict__ Qh) {
-  extern __shared__ double2 sm[];  // 3 rp lines of nx
+  extern __shared__ double2 sm[];  // 3 rp lines of nx, then nx/2 twiddles
   const int n = K.nx, nxh = n / 2 + 1, hb = K.ny / (2 * rp);
+  double2* tws = sm + 3 * rp * n;
+  stage_twiddles(tws, tw, n);
   const int b = xcd_band((int)blockIdx.x, (int)gridDim.x);
   const int jb = (b % hb) * 2 * rp, k = b / hb;
   const long long NN = K.N;
@@ -281,7 +298,7 @@ __global__ __launch_bounds__(256) void k_r2c_x(Consts K, const T* __restrict__ r
     reinterpret_cast<double*>(&sm[(3 * q + 2) * n + bi])[l] = q2;
   }
   __syncthreads();
-  fft_lds(sm, n, logn, 3 * rp, tw, 0);
+  fft_lds(sm, n, logn, 3 * rp, tws, 0);
   const long long plane = (long long)nxh * K.ny * K.nz;
   for (int e = threadIdx.x; e < 3 * rp * nxh; e += blockDim.x) {
     const int line = e / nxh, kx = e - line * nxh;
@@ -307,8 +324,10 @@ __global__ __launch_bounds__(256) void k_r2c_x(Consts K, const T* __restrict__ r
 __global__ __launch_bounds__(256) void k_z_solve(Consts K, int logn, int lpb, const double2* __restrict__ tw,
                                                  const double* __restrict__ sx, const double* __restrict__ sy,
                                                  const double* __restrict__ szt, double2* __restrict__ Qh) {
-  extern __shared__ double2 sm[];  // 3 lpb lines of nz: line (f lpb + l)
+  extern __shared__ double2 sm[];  // 3 lpb lines of nz: line (f lpb + l), then nz/2 twiddles
   const int n = K.nz, nxh = K.nx / 2 + 1;
+  double2* tws = sm + 3 * lpb * n;
+  stage_twiddles(tws, tw, n);
   const int nxb = (nxh + lpb - 1) / lpb;
   const int b = xcd_band((int)blockIdx.x, (int)gridDim.x);
   const int kx0 = (b % nxb) * lpb, ky = b / nxb;
@@ -323,7 +342,7 @@ __global__ __launch_bounds__(256) void k_z_solve(Consts K, int logn, int lpb, co
     sm[(f * lpb + l) * n + brev(p, logn)] = v;
   }
   __syncthreads();
-  fft_lds(sm, n, logn, nl, tw, 0);
+  fft_lds(sm, n, logn, nl, tws, 0);
   for (int e = threadIdx.x; e < lpb * n; e += blockDim.x) {
     const int l = e % lpb, p = e / lpb, kx = kx0 + l;
     if (kx >= nxh) continue;
@@ -372,7 +391,7 @@ __global__ __launch_bounds__(256) void k_z_solve(Consts K, int logn, int lpb, co
     }
   }
   __syncthreads();
-  fft_lds(sm, n, logn, nl, tw, 1);
+  fft_lds(sm, n, logn, nl, tws, 1);
   for (int e = threadIdx.x; e < nl * n; e += blockDim.x) {
     const int l = e % lpb, rest = e / lpb, p = rest % n, f = rest / n;
     if (kx0 + l < nxh) Qh[f * plane + base + l + zs * p] = sm[(f * lpb + l) * n + p];
@@ -385,8 +404,10 @@ __global__ __launch_bounds__(256) void k_z_solve(Consts K, int logn, int lpb, co
 template <typename T>
 __global__ __launch_bounds__(256) void k_c2r_x(Consts K, int logn, int rp, const double2* __restrict__ tw,
                                                const double2* __restrict__ Qh, T* __restrict__ u) {
-  extern __shared__ double2 sm[];  // 3 rp lines of nx
+  extern __shared__ double2 sm[];  // 3 rp lines of nx, then nx/2 twiddles
   const int n = K.nx, nxh = n / 2 + 1, hb = K.ny / (2 * rp);
+  double2* tws = sm + 3 * rp * n;
+  stage_twiddles(tws, tw, n);
   const int b = xcd_band((int)blockIdx.x, (int)gridDim.x);
   const int jb = (b % hb) * 2 * rp, k = b / hb;
   const long long plane = (long long)nxh * K.ny * K.nz;
@@ -411,7 +432,7 @@ __global__ __launch_bounds__(256) void k_c2r_x(Consts K, int logn, int rp, const
     sm[line * n + brev(kx, logn)] = make_double2(P.x - Q.y, P.y + Q.x);  // P + i Q
   }
   __syncthreads();
-  fft_lds(sm, n, logn, 3 * rp, tw, 1);
+  fft_lds(sm, n, logn, 3 * rp, tws, 1);
   const double inv = 1.0 / (double)K.N;
   const long long NN = K.N;
   for (int e = threadIdx.x; e < 2 * rp * n; e += blockDim.x) {
@@ -572,6 +593,17 @@ int ilog2(int n) {
   return l;
 }
 
+// k_fft_lines with its LDS: lpb lines and the n/2 twiddles (beyond 64 KiB for the longest lines)
+void launch_lines(double2* data, int n, int logn, long long pstride, long long la, long long lb, long long lc,
+                  long long nlines, int lpb, const double2* tw, int inverse, int contiguous, hipStream_t s) {
+  const size_t lds = sizeof(double2) * ((size_t)lpb * n + n / 2);
+  if (lds > 64 * 1024)
+    (void)hipFuncSetAttribute((const void*)k_fft_lines, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  const long long blocks = (nlines + lpb - 1) / lpb;
+  hipLaunchKernelGGL(k_fft_lines, dim3((unsigned)blocks), dim3(kFftThreads), lds, s, data, n, logn, pstride, la,
+                     lb, lc, nlines, lpb, tw, inverse, contiguous);
+}
+
 void fft_dir(const Consts& K, const FftPlan& P, double2* data, int dir, int inverse, hipStream_t s) {
   const int n = P.n[dir];
   const int logn = ilog2(n);
@@ -604,9 +636,7 @@ void fft_dir(const Consts& K, const FftPlan& P, double2* data, int dir, int inve
     pstride = nx * ny;
   }
   if (dir != 0 && lpb > la) lpb = (int)la;  // consecutive lines of a block stay adjacent
-  const long long blocks = (nlines + lpb - 1) / lpb;
-  hipLaunchKernelGGL(k_fft_lines, dim3((unsigned)blocks), dim3(kFftThreads), 0, s, data, n, logn,
-                     pstride, la, lb, lc, nlines, lpb, P.tw[dir], inverse, dir == 0 ? 1 : 0);
+  launch_lines(data, n, logn, pstride, la, lb, lc, nlines, lpb, P.tw[dir], inverse, dir == 0 ? 1 : 0, s);
 }
 
 void fft_all(const Consts& K, const FftPlan& P, double2* data, int inverse, hipStream_t s) {
@@ -631,7 +661,9 @@ void launch_spectral_solve(const Consts& K, const FftPlan& P, const T* r, double
     int nl = 512 / K.nx;
     if (nl < 1) nl = 1;
     while (K.ny % nl) nl >>= 1;
-    const size_t lrow = sizeof(double2) * nl * K.nx, lcol = sizeof(double2) * 4 * K.ny;
+    const size_t lrow = sizeof(double2) * (nl * K.nx + K.nx / 2), lcol = sizeof(double2) * (4 * K.ny + K.ny / 2);
+    if (lcol > 64 * 1024)  // ny = 1024: 72 KiB
+      (void)hipFuncSetAttribute((const void*)k_fft2_cols_solve, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lcol);
     hipLaunchKernelGGL(k_fft2_rows_fwd<T>, dim3(K.ny / nl), dim3(256), lrow, s, K, r, a, zc, lx, nl, P.tw[0], work0);
     hipLaunchKernelGGL(k_fft2_cols_solve, dim3(K.nx / 2), dim3(256), lcol, s, K, ly, P.tw[1], P.sn[0],
                        P.sn[1], work0);
@@ -645,24 +677,21 @@ void launch_spectral_solve(const Consts& K, const FftPlan& P, const T* r, double
     int rp = 256 / K.nx;  // row pairs per x block: about 768 points per block
     if (rp < 1) rp = 1;
     while (rp > 1 && (K.ny / 2) % rp) rp >>= 1;
-    const size_t lx_bytes = sizeof(double2) * 3 * rp * K.nx;
+    const size_t lx_bytes = sizeof(double2) * (3 * rp * K.nx + K.nx / 2);
     const unsigned xblocks = (unsigned)((K.ny / (2 * rp)) * K.nz);
     int lpz = 1024 / K.nz;  // kx columns per z block: 48 KiB of LDS
     if (lpz > 8) lpz = 8;
     if (lpz < 1) lpz = 1;
-    const size_t lz_bytes = sizeof(double2) * 3 * lpz * K.nz;
+    const size_t lz_bytes = sizeof(double2) * (3 * lpz * K.nz + K.nz / 2);
     const unsigned zblocks = (unsigned)(((nxh + lpz - 1) / lpz) * K.ny);
     int lpy = kFftLds / K.ny;  // adjacent kx lines per y block
     if (lpy > 16) lpy = 16;
     const long long ylines = 3LL * nxh * K.nz;
-    const unsigned yblocks = (unsigned)((ylines + lpy - 1) / lpy);
     hipLaunchKernelGGL(k_r2c_x<T>, dim3(xblocks), dim3(256), lx_bytes, s, K, r, a, zc, lx, rp, P.tw[0], Qh);
-    hipLaunchKernelGGL(k_fft_lines, dim3(yblocks), dim3(kFftThreads), 0, s, Qh, K.ny, ly, (long long)nxh,
-                       (long long)nxh, 1LL, (long long)nxh * K.ny, ylines, lpy, P.tw[1], 0, 0);
+    launch_lines(Qh, K.ny, ly, nxh, nxh, 1, (long long)nxh * K.ny, ylines, lpy, P.tw[1], 0, 0, s);
     hipLaunchKernelGGL(k_z_solve, dim3(zblocks), dim3(256), lz_bytes, s, K, lz, lpz, P.tw[2], P.sn[0], P.sn[1],
                        P.sn[2], Qh);
-    hipLaunchKernelGGL(k_fft_lines, dim3(yblocks), dim3(kFftThreads), 0, s, Qh, K.ny, ly, (long long)nxh,
-                       (long long)nxh, 1LL, (long long)nxh * K.ny, ylines, lpy, P.tw[1], 1, 0);
+    launch_lines(Qh, K.ny, ly, nxh, nxh, 1, (long long)nxh * K.ny, ylines, lpy, P.tw[1], 1, 0, s);
     hipLaunchKernelGGL(k_c2r_x<T>, dim3(xblocks), dim3(256), lx_bytes, s, K, lx, rp, P.tw[0], Qh, u);
     return;
   }

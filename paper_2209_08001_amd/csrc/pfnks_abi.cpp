@@ -260,8 +260,10 @@ hipEvent_t prof_event(pfnks_problem* p) {
     p->pool.pop_back();
     return e;
   }
+  // timing only: no system-scope fence (L2 write-back) when the event is recorded, so that
+  // bracketing a kernel adds no cache flush between it and the next one
   hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
   return e;
 }
 
