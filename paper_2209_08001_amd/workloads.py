@@ -61,19 +61,20 @@ DEFAULT_SOLVER = {
     "tile": (32, 32, 1),
     "overlap": 2,
     # symmetric Gauss-Seidel sweeps of the tile solve (see default_sweeps)
-    "sweeps": 6,
+    "sweeps": 8,
     "ls_alpha": 1e-4,
     "ls_max_halvings": 10,
 }
 
 def default_sweeps(dim, mixed):
     """Gauss-Seidel sweeps of the tile solve, as measured fastest per step on MI355X: each
-    sweep costs ~17 us per apply at 512^2 FP64 and saves GMRES iterations (512^2 FP64: 2
-    sweeps 24 iterations per Newton step, 6 sweeps 13.3, 8 sweeps 11.7 at the same speed;
-    mixed: 8 sweeps; 128^3 mixed: 6)."""
+    sweep costs ~6 us per apply at 512^2 FP64 (~4 us mixed) and saves GMRES iterations
+    (512^2 FP64: 6 sweeps 13.7 iterations per Newton step and 178 steps/s, 8 sweeps 11.7 and
+    195, 10 and 12 sweeps the same speed as 8; mixed: 8 sweeps 244 steps/s; 128^3 mixed: 6
+    sweeps, 4 and 8 slower)."""
     if dim == 3:
         return 6
-    return 8 if mixed else 6
+    return 8
 
 
 WORKLOADS = {
