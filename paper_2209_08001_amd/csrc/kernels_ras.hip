@@ -56,6 +56,83 @@ __device__ inline int wrapg(int a, int n) {
   return a < 0 ? a + n : a;
 }
 
+constexpr int kPackVals = 13;  // per extended-tile node: E^{-1} (9), w = E^{-1} v (3), 1 / (d_cc - u'w)
+
+// Per time step (the preconditioner blocks are lagged): the constant pieces of every extended-
+// tile node's diagonal block of the tile operator (the node's own unknowns),
+//   [d_cc  u'  ]      d_cc = 1/dt + sc (B_cc + kel + gamma_c (2 DIM + 1) / (2 h^2)),
+//   [v     E   ]      u_e = sc B_ce, v_e = L_eta B_ec, E = dee I + L_eta B_ee,
+// dee = 1/dt + L_eta gamma_eta DIM / h^2, sc = (sum of the 2 DIM face mobilities
+// kappa/2 (g_i + g_j), g = c^n (1 - c^n)) / h^2: E^{-1} by the adjugate, w = E^{-1} v and the
+// Schur denominator 1 / (d_cc - u'w).  Stored per tile in colour order (plane k of tile t at
+// pack[(t kPackVals + k) ne + pos]), so that the tile kernel's thread for colour position pos
+// reads them with coalesced loads.  Here the nodes are taken in natural order (coalesced
+// loads) and scattered to their colour positions (iperm).
+constexpr int kPackThreads = 1024;
+template <int DIM, typename R>
+__global__ __launch_bounds__(kPackThreads) void k_ras_pack(Consts K, Geo G, double dt, const R* __restrict__ Bg,
+                                                           const double* __restrict__ cn,
+                                                           const int* __restrict__ iperm, R* __restrict__ pack) {
+  const int t = blockIdx.x;
+  const int tix = t % G.ntx, tiy = (t / G.ntx) % G.nty, tiz = t / (G.ntx * G.nty);
+  const int ox = tix * G.tx - G.ov, oy = tiy * G.ty - G.ov, oz = (DIM == 3) ? tiz * G.tz - G.ov : 0;
+  const int ne = G.ex * G.ey * G.ez;
+  const long long N = K.N;
+  // coefficients in the arithmetic type of the solve (formed in double, rounded once)
+  const R idt = (R)(1.0 / dt);
+  const R ih2 = (R)K.ih2, Le = (R)K.L_eta, hk = (R)(0.5 * K.kappa);
+  const R dcc1 = (R)(K.kel + K.gamma_c * DIM * K.ih2 + 0.5 * K.gamma_c * K.ih2);
+  const R dee = (R)(1.0 / dt + K.L_eta * K.gamma_eta * DIM * K.ih2);
+  R* out = pack + (long long)t * kPackVals * ne;
+  auto gnode = [&](int i, int j, int k) {
+    return (long long)wrapg(i, K.nx) + (long long)K.nx * ((long long)wrapg(j, K.ny) + (long long)K.ny * wrapg(k, K.nz));
+  };
+  auto gval = [&](long long m) {
+    const double v = cn[m];
+    return (R)(v * (1.0 - v));
+  };
+  for (int q = threadIdx.x; q < ne; q += blockDim.x) {
+    const int pos = iperm[q];
+    const int a = q % G.ex, b = (q / G.ex) % G.ey, c = q / (G.ex * G.ey);
+    const int gi = ox + a, gj = oy + b, gk = (DIM == 3) ? oz + c : 0;
+    const long long n = gnode(gi, gj, gk);
+    R bv[12];
+#pragma unroll
+    for (int f = 0; f < 12; ++f) bv[f] = Bg[(4 + f) * N + n];
+    // E^{-1} by the adjugate and w = E^{-1} v
+    const R E00 = dee + Le * bv[1], E01 = Le * bv[2], E02 = Le * bv[3];
+    const R E10 = Le * bv[5], E11 = dee + Le * bv[6], E12 = Le * bv[7];
+    const R E20 = Le * bv[9], E21 = Le * bv[10], E22 = dee + Le * bv[11];
+    const R A00 = E11 * E22 - E12 * E21, A01 = E02 * E21 - E01 * E22, A02 = E01 * E12 - E02 * E11;
+    const R A10 = E12 * E20 - E10 * E22, A11 = E00 * E22 - E02 * E20, A12 = E02 * E10 - E00 * E12;
+    const R A20 = E10 * E21 - E11 * E20, A21 = E01 * E20 - E00 * E21, A22 = E00 * E11 - E01 * E10;
+    const R idet = R(1) / (E00 * A00 + E01 * A10 + E02 * A20);
+    const R Ai[9] = {A00 * idet, A01 * idet, A02 * idet, A10 * idet, A11 * idet,
+                     A12 * idet, A20 * idet, A21 * idet, A22 * idet};
+    const R v1 = Le * bv[0], v2 = Le * bv[4], v3 = Le * bv[8];
+    R w[3];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) w[e] = Ai[3 * e] * v1 + Ai[3 * e + 1] * v2 + Ai[3 * e + 2] * v3;
+    // Schur denominator of the c row
+    const R g0 = gval(n);
+    R sumM = R(0);
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const R gp = gval(gnode(gi + (d == 0), gj + (d == 1), gk + (d == 2)));
+      const R gm = gval(gnode(gi - (d == 0), gj - (d == 1), gk - (d == 2)));
+      sumM += hk * (g0 + gp) + hk * (g0 + gm);
+    }
+    const R sc = sumM * ih2;
+    const R dcc = idt + sc * (Bg[n] + dcc1);
+    const R uw = sc * (Bg[N + n] * w[0] + Bg[2 * N + n] * w[1] + Bg[3 * N + n] * w[2]);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) out[k * ne + pos] = Ai[k];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) out[(9 + e) * ne + pos] = w[e];
+    out[12 * ne + pos] = R(1) / (dcc - uw);
+  }
+}
+
 // minimum waves per SIMD the registers are sized for (the second launch bound): two for
 // 256-thread workgroups (two or more per compute unit), one for 512 threads (one per unit)
 template <int TH>
@@ -70,6 +147,7 @@ __global__ __launch_bounds__(TH, (ras_waves_per_eu<TH>())) void k_ras(Consts K, 
                                                      const R* __restrict__ rg,
                                                      R* __restrict__ zg,
                                                      const int* __restrict__ permg,
+                                                     const R* __restrict__ pack,
                                                      R* __restrict__ xs) {
   constexpr int NFZ = WU ? 4 + DIM : 4;
   constexpr int ZP0 = WU ? 0 : 1;     // first field of the iterate held in LDS
@@ -122,7 +200,9 @@ __global__ __launch_bounds__(TH, (ras_waves_per_eu<TH>())) void k_ras(Consts K, 
   // nodes grouped by colour, the same for every tile of this shape; formed by the host), so
   // the nodes of one colour sit on consecutive threads.
   R rr[NPT][NFZ];
-  R be[NPT][12];
+  // E^{-1}, w and 1 / (d_cc - u'w) of each node (the diagonal block of the tile operator,
+  // below), formed once per time step by k_ras_pack in colour order: coalesced loads
+  R ai[NPT][9], wq[NPT][3], invd[NPT];
   R zcr_[NPT];  // c iterate of this thread's nodes (without u; LDS plane 0 with u)
   // per node, packed in 16-bit halves (every index is below 2^16): zd = iterate position |
   // dG position << 16; qc = ext index
@@ -151,28 +231,32 @@ __global__ __launch_bounds__(TH, (ras_waves_per_eu<TH>())) void k_ras(Consts K, 
       const bool keep = G.mode != kRasRight || owned;
 #pragma unroll
       for (int f = 0; f < NFZ; ++f) rr[m][f] = keep ? rg[f * N + n] : R(0);
+      const R* pk = pack + (long long)t * kPackVals * ne + pos;
 #pragma unroll
-      for (int f = 0; f < 12; ++f) be[m][f] = Bg[(4 + f) * N + n];
+      for (int k = 0; k < 9; ++k) ai[m][k] = pk[k * ne];
+#pragma unroll
+      for (int e = 0; e < 3; ++e) wq[m][e] = pk[(9 + e) * ne];
+      invd[m] = pk[12 * ne];
     } else {
 #pragma unroll
       for (int f = 0; f < NFZ; ++f) rr[m][f] = R(0);
 #pragma unroll
-      for (int f = 0; f < 12; ++f) be[m][f] = R(0);
+      for (int k = 0; k < 9; ++k) ai[m][k] = R(0);
+#pragma unroll
+      for (int e = 0; e < 3; ++e) wq[m][e] = R(0);
+      invd[m] = R(0);
     }
   }
   __syncthreads();
 
   // coefficients in the arithmetic type of the solve (formed in double, rounded once)
   const R idt = (R)(1.0 / dt);
-  const R ih2 = (R)K.ih2, i2h = (R)K.i2h, Le = (R)K.L_eta, eps0 = (R)K.eps0;
+  const R ih2 = (R)K.ih2, i2h = (R)K.i2h, eps0 = (R)K.eps0;
   const R C11 = (R)K.C11, C12 = (R)K.C12, C44 = (R)K.C44;
   const R hk = (R)(0.5 * K.kappa);
   const int sdir_z[3] = {1, sy, sz};
   const int sdir_d[3] = {1, ty_, tz_};
   const R a_u = (R)(-0.5 * K.eps0 * K.Ctr * K.i2h);  // coefficient of the difference of z_u in dG
-  const R dcc0 = idt;                                // parts of the c-c diagonal entry
-  const R dcc1 = (R)(K.kel + K.gamma_c * DIM * K.ih2 + 0.5 * K.gamma_c * K.ih2);
-  const R dee = (R)(1.0 / dt + K.L_eta * K.gamma_eta * DIM * K.ih2);
   const R iduu = (R)(-2.0 * K.h * K.h / (K.C11 + (DIM - 1) * K.C44));
   const R cxu = (R)(K.eps0 * K.Ctr * 0.25 * K.ih2 * K.ih);
   const R cge = (R)(0.5 * K.L_eta * K.gamma_eta * K.ih2);  // eta-row neighbour coefficient
@@ -181,42 +265,8 @@ __global__ __launch_bounds__(TH, (ras_waves_per_eu<TH>())) void k_ras(Consts K, 
   // Per node, the diagonal block of the tile operator (the node's own unknowns) is
   //   [d_cc  u'  ]      d_cc = 1/dt + sc (B_cc + kel + gamma_c (2 DIM + 1) / (2 h^2)),
   //   [v     E   ]      u_e = sc B_ce, v_e = L_eta B_ec, E = dee I + L_eta B_ee,
-  // sc = (sum of the 2 DIM face mobilities) / h^2.  It is constant during the sweeps.
-  // block_inverse: E^{-1} (by the adjugate) and w = E^{-1} v from the eta rows bv of B.
-  auto block_inverse = [&](const R* bv, R* Ai, R* w) {
-    const R E00 = dee + Le * bv[1], E01 = Le * bv[2], E02 = Le * bv[3];
-    const R E10 = Le * bv[5], E11 = dee + Le * bv[6], E12 = Le * bv[7];
-    const R E20 = Le * bv[9], E21 = Le * bv[10], E22 = dee + Le * bv[11];
-    const R A00 = E11 * E22 - E12 * E21, A01 = E02 * E21 - E01 * E22, A02 = E01 * E12 - E02 * E11;
-    const R A10 = E12 * E20 - E10 * E22, A11 = E00 * E22 - E02 * E20, A12 = E02 * E10 - E00 * E12;
-    const R A20 = E10 * E21 - E11 * E20, A21 = E01 * E20 - E00 * E21, A22 = E00 * E11 - E01 * E10;
-    const R idet = R(1) / (E00 * A00 + E01 * A10 + E02 * A20);
-    Ai[0] = A00 * idet; Ai[1] = A01 * idet; Ai[2] = A02 * idet;
-    Ai[3] = A10 * idet; Ai[4] = A11 * idet; Ai[5] = A12 * idet;
-    Ai[6] = A20 * idet; Ai[7] = A21 * idet; Ai[8] = A22 * idet;
-    const R v1 = Le * bv[0], v2 = Le * bv[4], v3 = Le * bv[8];
-#pragma unroll
-    for (int e = 0; e < 3; ++e) w[e] = Ai[3 * e] * v1 + Ai[3 * e + 1] * v2 + Ai[3 * e + 2] * v3;
-  };
-  // E^{-1}, w and 1 / (d_cc - u'w) of each of this thread's nodes stay in registers, formed
-  // once per apply (the B entries they come from are not needed afterwards).
-  R ai[NPT][9], wq[NPT][3], invd[NPT];
-#pragma unroll
-  for (int m = 0; m < NPT; ++m) {
-    block_inverse(be[m], ai[m], wq[m]);
-    invd[m] = R(0);
-    if (col_[m] >= 0) {
-      const int di = zd_[m] >> 16, q = qc_[m];
-      const R g0 = gg[di];
-      R sumM = R(0);
-#pragma unroll
-      for (int d = 0; d < DIM; ++d) sumM += hk * (g0 + gg[di + sdir_d[d]]) + hk * (g0 + gg[di - sdir_d[d]]);
-      const R sc = sumM * ih2;
-      const R dcc = dcc0 + sc * (bc[q] + dcc1);
-      const R uw = sc * (bc[ne + q] * wq[m][0] + bc[2 * ne + q] * wq[m][1] + bc[3 * ne + q] * wq[m][2]);
-      invd[m] = R(1) / (dcc - uw);
-    }
-  }
+  // sc = (sum of the 2 DIM face mobilities) / h^2; constant during the sweeps, its pieces
+  // E^{-1}, w = E^{-1} v and 1 / (d_cc - u'w) come from k_ras_pack.
 
   // Block Gauss-Seidel update of one node.  The eta rows are taken in Gauss-Seidel form:
   // with rhs_e = r_e + (L_eta gamma_eta / (2 h^2)) (sum of the 2 DIM neighbours of z_e) the
@@ -489,18 +539,19 @@ Geo make_geo(const Consts& K, const TileCfg& T) {
 
 template <int DIM, bool WU, typename R, int TH>
 void launch_npt(const Geo& G, const Consts& K, size_t lds, int ntiles, int npt, double dt, const R* B,
-                const double* cn, const R* r, R* z, const int* perm, R* xs, hipStream_t s) {
+                const double* cn, const R* r, R* z, const int* perm, const R* pack, R* xs, hipStream_t s) {
 #define PF_RAS_CASE(NPTV)                                                                             \
   case NPTV:                                                                                          \
     (void)hipFuncSetAttribute((const void*)k_ras<DIM, WU, NPTV, R, TH>,                              \
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                  \
-    hipLaunchKernelGGL((k_ras<DIM, WU, NPTV, R, TH>), dim3(ntiles), dim3(TH), lds, s, K, G, dt, B, cn, r, z, perm, xs); \
+    hipLaunchKernelGGL((k_ras<DIM, WU, NPTV, R, TH>), dim3(ntiles), dim3(TH), lds, s, K, G, dt, B, cn, r, z, perm, pack, xs); \
     break;
   if constexpr (TH == kRasThreadsSmall) {
     if (npt == 4) {
       (void)hipFuncSetAttribute((const void*)k_ras<DIM, WU, 4, R, TH>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)lds);
-      hipLaunchKernelGGL((k_ras<DIM, WU, 4, R, TH>), dim3(ntiles), dim3(TH), lds, s, K, G, dt, B, cn, r, z, perm, xs);
+      hipLaunchKernelGGL((k_ras<DIM, WU, 4, R, TH>), dim3(ntiles), dim3(TH), lds, s, K, G, dt, B, cn, r, z, perm, pack,
+                         xs);
       return;
     }
   }
@@ -515,11 +566,12 @@ void launch_npt(const Geo& G, const Consts& K, size_t lds, int ntiles, int npt, 
 
 template <int DIM, bool WU, typename R>
 void launch_dim(const Consts& K, const Geo& G, size_t lds, int ntiles, int th, int npt, double dt,
-                const R* B, const double* cn, const R* r, R* z, const int* perm, R* xs, hipStream_t s) {
+                const R* B, const double* cn, const R* r, R* z, const int* perm, const R* pack, R* xs,
+                hipStream_t s) {
   if (!WU && th == kRasThreadsSmall)
-    launch_npt<DIM, false, R, kRasThreadsSmall>(G, K, lds, ntiles, npt, dt, B, cn, r, z, perm, xs, s);
+    launch_npt<DIM, false, R, kRasThreadsSmall>(G, K, lds, ntiles, npt, dt, B, cn, r, z, perm, pack, xs, s);
   else
-    launch_npt<DIM, WU, R, kRasThreadsMax>(G, K, lds, ntiles, npt, dt, B, cn, r, z, perm, xs, s);
+    launch_npt<DIM, WU, R, kRasThreadsMax>(G, K, lds, ntiles, npt, dt, B, cn, r, z, perm, pack, xs, s);
   if (G.mode != kRasLeft) {
     constexpr int NFZ = WU ? 4 + DIM : 4;
     hipLaunchKernelGGL((k_ras_gather<DIM, NFZ, R>), dim3((unsigned)((K.N + 255) / 256)), dim3(256), 0, s, K, G,
@@ -597,13 +649,36 @@ void launch_ras(const Consts& K, const TileCfg& T, double dt, const R* B, const 
   int npt = 0;
   const int th = ras_threads(K, T, sizeof(R), &npt);
   R* xs = static_cast<R*>(T.scratch);
+  const R* pk = static_cast<const R*>(T.pack);
   if (K.dim == 2) {
-    if (T.with_u) launch_dim<2, true, R>(K, G, lds, ntiles, th, npt, dt, B, cn, r, z, T.perm, xs, s);
-    else launch_dim<2, false, R>(K, G, lds, ntiles, th, npt, dt, B, cn, r, z, T.perm, xs, s);
+    if (T.with_u) launch_dim<2, true, R>(K, G, lds, ntiles, th, npt, dt, B, cn, r, z, T.perm, pk, xs, s);
+    else launch_dim<2, false, R>(K, G, lds, ntiles, th, npt, dt, B, cn, r, z, T.perm, pk, xs, s);
   } else {
-    if (T.with_u) launch_dim<3, true, R>(K, G, lds, ntiles, th, npt, dt, B, cn, r, z, T.perm, xs, s);
-    else launch_dim<3, false, R>(K, G, lds, ntiles, th, npt, dt, B, cn, r, z, T.perm, xs, s);
+    if (T.with_u) launch_dim<3, true, R>(K, G, lds, ntiles, th, npt, dt, B, cn, r, z, T.perm, pk, xs, s);
+    else launch_dim<3, false, R>(K, G, lds, ntiles, th, npt, dt, B, cn, r, z, T.perm, pk, xs, s);
   }
+}
+
+template <typename R>
+void launch_ras_pack(const Consts& K, const TileCfg& T, double dt, const R* B, const double* cn, hipStream_t s) {
+  const Geo G = make_geo(K, T);
+  const int ntiles = G.ntx * G.nty * ((K.dim == 3) ? K.nz / T.tz : 1);
+  R* pk = static_cast<R*>(T.pack);
+  const int* iperm = T.perm + G.ex * G.ey * G.ez;
+  if (K.dim == 2)
+    hipLaunchKernelGGL((k_ras_pack<2, R>), dim3(ntiles), dim3(kPackThreads), 0, s, K, G, dt, B, cn, iperm, pk);
+  else
+    hipLaunchKernelGGL((k_ras_pack<3, R>), dim3(ntiles), dim3(kPackThreads), 0, s, K, G, dt, B, cn, iperm, pk);
+}
+template void launch_ras_pack<double>(const Consts&, const TileCfg&, double, const double*, const double*,
+                                      hipStream_t);
+template void launch_ras_pack<float>(const Consts&, const TileCfg&, double, const float*, const double*,
+                                     hipStream_t);
+
+size_t ras_pack_values(const Consts& K, const TileCfg& T) {
+  const Geo G = make_geo(K, T);
+  const size_t ntiles = (size_t)G.ntx * G.nty * ((K.dim == 3) ? K.nz / T.tz : 1);
+  return ntiles * kPackVals * (size_t)G.ex * G.ey * G.ez;
 }
 template void launch_ras<double>(const Consts&, const TileCfg&, double, const double*, const double*,
                                  const double*, double*, hipStream_t);

@@ -54,15 +54,23 @@ struct TileCfg {
   int ov;           // overlap delta
   int sweeps;       // symmetric GS sweeps
   int with_u;       // 1: all fields (plain RAS); 0: (c, eta) block only
-  const int* perm;  // device: nodes of the extended tile sorted by colour (ras_colour_order)
+  const int* perm;  // device: nodes of the extended tile sorted by colour (ras_colour_order),
+                    // followed by the inverse order (colour position of each node)
   int mode;         // 0 left-RAS, 1 classical AS, 2 right-RAS
   void* scratch;    // modes 1, 2: one extended solution per tile (Krylov type)
+  void* pack;       // per tile and extended node, colour order: E^{-1}, E^{-1} v, Schur
+                    // denominator of the node block (13 values, Krylov type; launch_ras_pack)
 };
 // R (double or float): element type of the blocks B, of r and z, and of the tile arithmetic
 template <typename R>
 void launch_ras(const Consts& K, const TileCfg& T, double dt, const R* B, const double* cn,
                 const R* r, R* z, hipStream_t s);
 size_t ras_lds_bytes(const Consts& K, const TileCfg& T, size_t real_bytes);
+// once per time step, after the preconditioner blocks B: the node-block pieces of every
+// extended tile into T.pack (ras_pack_values(K, T) elements of type R)
+template <typename R>
+void launch_ras_pack(const Consts& K, const TileCfg& T, double dt, const R* B, const double* cn, hipStream_t s);
+size_t ras_pack_values(const Consts& K, const TileCfg& T);
 // workgroup size of the tile kernel for this tile shape and element size (0: shape not
 // supported); *npt (may be null): nodes of the extended tile per thread
 int ras_threads(const Consts& K, const TileCfg& T, size_t real_bytes, int* npt);

@@ -52,7 +52,7 @@ struct Layout {
 
 enum Buf {
   B_X, B_XN, B_XT, B_F, B_FT, B_S, B_B, B_BPC, B_G4, B_V, B_ZB, B_W, B_Z, B_TMP, B_TMPV, B_PART, B_RED,
-  B_FFT0, B_FFT1, B_TW0, B_TW1, B_TW2, B_SN0, B_SN1, B_SN2, B_HDEV, B_PERM, B_ASX, B_COUNT
+  B_FFT0, B_FFT1, B_TW0, B_TW1, B_TW2, B_SN0, B_SN1, B_SN2, B_HDEV, B_PERM, B_ASX, B_PACK, B_COUNT
 };
 
 // bytes of one element of the Krylov basis, the preconditioner blocks and the tile solve
@@ -64,7 +64,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // preconditioner blocks Bpc are stored in the Krylov element type (float when mixed); the
 // state, residuals, Newton update S, J v output w and the Jacobian blocks B are double.
 Layout make_layout(int dim, long long N, int restart, const int* n, int precision, long long ext_nodes,
-                   long long tiles_summed) {
+                   long long tiles_summed, long long tiles_packed) {
   const int nf = 4 + dim;
   const size_t kb = krylov_bytes(precision);
   const size_t vec = sizeof(double) * (size_t)nf * N;
@@ -90,9 +90,11 @@ Layout make_layout(int dim, long long N, int restart, const int* n, int precisio
   sz[B_SN1] = sizeof(double) * (size_t)n[1];
   sz[B_SN2] = sizeof(double) * (size_t)(dim == 3 ? n[2] : 2);
   sz[B_HDEV] = sizeof(double) * (size_t)(restart + 1) * (restart + 2);
-  sz[B_PERM] = sizeof(int) * (size_t)ext_nodes;  // colour order of one extended tile
+  sz[B_PERM] = sizeof(int) * 2 * (size_t)ext_nodes;  // colour order of one extended tile, and its inverse
   // classical AS / right-RAS: every tile's extended solution (all fields), summed afterwards
   sz[B_ASX] = kb * (size_t)nf * (size_t)ext_nodes * (size_t)tiles_summed;
+  // every tile's node-block pieces (13 per extended node), formed once per time step
+  sz[B_PACK] = kb * 13 * (size_t)ext_nodes * (size_t)tiles_packed;
   Layout L{};
   size_t o = 0;
   for (int b = 0; b < B_COUNT; ++b) {
@@ -113,6 +115,14 @@ long long ext_nodes(const pfnks_grid* g, const pfnks_solver* s) {
 // tiles whose extended solutions need storing (classical AS / right-RAS), else 0
 long long tiles_summed(const pfnks_grid* g, const pfnks_solver* s) {
   if (!sums_overlap(s->pc)) return 0;
+  long long t = 1;
+  for (int k = 0; k < g->dim; ++k) t *= g->n[k] / s->tile[k];
+  return t;
+}
+
+// tiles of the Schwarz preconditioners (their node blocks are set up per time step), else 0
+long long tiles_packed(const pfnks_grid* g, const pfnks_solver* s) {
+  if (!uses_tiles(s->pc)) return 0;
   long long t = 1;
   for (int k = 0; k < g->dim; ++k) t *= g->n[k] / s->tile[k];
   return t;
@@ -341,8 +351,9 @@ int dot_norm(pfnks_problem* p, const double* x, double* nrm) {
   return PFNKS_OK;
 }
 
-// algorithmic bytes of one Schwarz apply: every extended tile reads r (nfz planes), the
-// chemical blocks (16) in the Krylov element type and c^n (double); the owned nodes write z
+// algorithmic bytes of one Schwarz apply: every extended tile node reads r (nfz planes), its
+// node-block pieces (13, formed once per step) and the c row of its chemical block (4), in
+// the Krylov element type, and c^n (double); the owned nodes write z
 double ras_bytes(pfnks_problem* p, int nfz) {
   double rho = 1.0;
   for (int k = 0; k < p->K.dim; ++k) {
@@ -350,7 +361,17 @@ double ras_bytes(pfnks_problem* p, int nfz) {
     rho *= (double)(t + 2 * p->solver.overlap) / t;
   }
   const double kb = (double)p->kb;
-  return p->N * (rho * ((nfz + 16) * kb + 8.0) + nfz * kb);
+  return p->N * (rho * ((nfz + 17) * kb + 8.0) + nfz * kb);
+}
+
+// once per time step, after the lagged preconditioner blocks Bpc: the tile solve's node blocks
+void pc_setup(pfnks_problem* p, double dt) {
+  if (!uses_tiles(p->solver.pc)) return;
+  if (p->solver.precision == PFNKS_MIXED)
+    pf::launch_ras_pack<float>(p->K, p->T, dt, (const float*)p->Bpc, p->Xn, p->stream);
+  else
+    pf::launch_ras_pack<double>(p->K, p->T, dt, (const double*)p->Bpc, p->Xn, p->stream);
+  p->launches += 1;
 }
 
 // z = M^{-1} r with the lagged preconditioner blocks Bpc; T is the Krylov element type
@@ -582,7 +603,7 @@ int pfnks_workspace_bytes(const pfnks_grid* grid, const pfnks_model* model, cons
   if (st) return st;
   const long long N = (long long)grid->n[0] * grid->n[1] * (grid->dim == 3 ? grid->n[2] : 1);
   *bytes = make_layout(grid->dim, N, solver->gmres_restart, grid->n, solver->precision, ext_nodes(grid, solver),
-                       tiles_summed(grid, solver)).total;
+                       tiles_summed(grid, solver), tiles_packed(grid, solver)).total;
   return PFNKS_OK;
 }
 
@@ -596,7 +617,7 @@ int pfnks_create_problem(const pfnks_grid* grid, const pfnks_model* model, const
   if (((uintptr_t)d_workspace & 255) != 0) return PFNKS_EINVAL;
   const long long N = (long long)grid->n[0] * grid->n[1] * (grid->dim == 3 ? grid->n[2] : 1);
   const Layout L = make_layout(grid->dim, N, solver->gmres_restart, grid->n, solver->precision, ext_nodes(grid, solver),
-                               tiles_summed(grid, solver));
+                               tiles_summed(grid, solver), tiles_packed(grid, solver));
   if (ws_bytes < L.total) return PFNKS_ENOSPACE;
   st = check_domain_host(c0, eta0, N);
   if (st) return st;
@@ -629,6 +650,7 @@ int pfnks_create_problem(const pfnks_grid* grid, const pfnks_model* model, const
   p->T.perm = (const int*)(p->ws + L.off[B_PERM]);
   p->T.mode = 0;
   p->T.scratch = p->ws + L.off[B_ASX];
+  p->T.pack = p->ws + L.off[B_PACK];
   pf::TileCfg tcheck = p->T;
   tcheck.with_u = tiles_all_fields(solver->pc) ? 1 : 0;
   if (uses_tiles(solver->pc) && pf::ras_threads(p->K, tcheck, krylov_bytes(solver->precision), nullptr) == 0) {
@@ -700,10 +722,13 @@ int pfnks_create_problem(const pfnks_grid* grid, const pfnks_model* model, const
     if (e != hipSuccess) return fail(device_error(e, "hipMemcpy symbols"));
     p->plan.sn[d] = sdst;
   }
-  // colour order of the extended tile (the same for every tile), for the Schwarz kernel
+  // colour order of the extended tile (the same for every tile) and its inverse (the colour
+  // position of each node), for the Schwarz kernels
   {
-    std::vector<int> order((size_t)pf::ras_ext_nodes(p->K, p->T));
+    const size_t ne = (size_t)pf::ras_ext_nodes(p->K, p->T);
+    std::vector<int> order(2 * ne);
     pf::ras_colour_order(p->K, p->T, order.data());
+    for (size_t pos = 0; pos < ne; ++pos) order[ne + (size_t)order[pos]] = (int)pos;
     e = hipMemcpy((void*)p->T.perm, order.data(), sizeof(int) * order.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) return fail(device_error(e, "hipMemcpy colour order"));
   }
@@ -756,6 +781,7 @@ int pfnks_step(pfnks_problem* p, double dt, pfnks_step_stats* stats) {
       } else {
         pf::launch_linearise(p->K, p->X, p->Xn, p->B, (newton == 0) ? (float*)p->Bpc : nullptr, p->stream);
       }
+      if (newton == 0) pc_setup(p, dt);
     }
     p->launches += 1;
     const double tol = std::fmax(sv.gmres_rtol * fn, xi_a);
@@ -980,11 +1006,13 @@ int pfnks_debug_pc(pfnks_problem* p, const double* X, double dt, const double* r
   if (p->solver.precision == PFNKS_MIXED) {
     // the preconditioner in float: r rounded to float, z widened back to double
     pf::launch_linearise(p->K, p->Xt, p->Xn, p->B, (float*)p->Bpc, p->stream);
+    pc_setup(p, dt);
     pf::launch_axpby<double, double, float>(p->nvec, 1.0, p->tmp, 0.0, nullptr, (float*)p->tmpv, p->stream);
     pc_apply<float>(p, dt, (const float*)p->tmpv, (float*)p->z);
     pf::launch_axpby<float, float, double>(p->nvec, 1.0, (const float*)p->z, 0.0, nullptr, p->w, p->stream);
   } else {
     pf::launch_linearise(p->K, p->Xt, p->Xn, (double*)p->Bpc, nullptr, p->stream);
+    pc_setup(p, dt);
     pc_apply<double>(p, dt, p->tmp, (double*)p->z);
     HIPCHK(hipMemcpyAsync(p->w, p->z, sizeof(double) * p->nvec, hipMemcpyDeviceToDevice, p->stream));
   }
