@@ -463,29 +463,113 @@ __device__ inline void jv_rows(const Consts& K, double idt, const double* __rest
   }
 }
 
-// J v in 2D, one pass: a block of kBX x kJY2 nodes computes dG on the block and a halo of one
-// node into LDS; the c row reads it there.  v has element type Tv (double, or float for a
-// mixed-precision Krylov vector); the arithmetic and w are double.
+// J v in 2D, one pass: a block of kBX x kJY2 nodes stages v in LDS, computes dG on the block
+// and a halo of one node into LDS, and forms the c, eta and u rows from LDS (the same
+// arithmetic as jv_dg / jv_rows, which the 3D kernel uses on global memory).  v has element
+// type Tv (double, or float for a mixed-precision Krylov vector); the arithmetic and w are
+// double.
 constexpr int kJY2 = 8;
 template <typename Tv>
 __global__ __launch_bounds__(kBX* kJY2) void k_jv2(Consts K, double dt, const double* __restrict__ B,
                                                    const double* __restrict__ cn, const Tv* __restrict__ v,
                                                    double* __restrict__ w) {
-  constexpr int HX = kBX + 2, HY = kJY2 + 2;
-  __shared__ double sdg[HX * HY];
+  // v (all six fields, as double) with a halo of 2 (sigma of the u rows reaches distance 2),
+  // g = c^n (1 - c^n) and dG with a halo of 1; every stencil below reads LDS, only B comes
+  // from global memory
+  constexpr int SX = kBX + 4, SY = kJY2 + 4, SP = SX * SY;
+  constexpr int HX = kBX + 2, HY = kJY2 + 2, HP = HX * HY;
+  __shared__ double sv[6 * SP];
+  __shared__ double sg[HP], sdg[HP];
   int bx, by, bz;
   xcd_block(bx, by, bz);
   const int i0 = bx * kBX, j0 = by * kJY2;
   const int tid = threadIdx.x + kBX * threadIdx.y;
-  for (int q = tid; q < HX * HY; q += kBX * kJY2) {
+  const long long N = K.N;
+  for (int q = tid; q < 6 * SP; q += kBX * kJY2) {
+    const int f = q / SP, r = q - f * SP, a = r % SX, b = r / SX;
+    sv[q] = (double)v[f * N + wrap(i0 + a - 2, K.nx) + (long long)K.nx * wrap(j0 + b - 2, K.ny)];
+  }
+  for (int q = tid; q < HP; q += kBX * kJY2) {
     const int a = q % HX, b = q / HX;
-    sdg[q] = jv_dg<2>(K, B, v, Pt{wrap(i0 + a - 1, K.nx), wrap(j0 + b - 1, K.ny), 0});
+    const double c = cn[wrap(i0 + a - 1, K.nx) + (long long)K.nx * wrap(j0 + b - 1, K.ny)];
+    sg[q] = c * (1.0 - c);
   }
   __syncthreads();
-  const Pt p{i0 + (int)threadIdx.x, j0 + (int)threadIdx.y, 0};
-  if (p.i >= K.nx || p.j >= K.ny) return;
-  const int up[2] = {1, HX}, dn[2] = {-1, -HX};
-  jv_rows<2>(K, 1.0 / dt, B, cn, v, w, p, sdg, (threadIdx.x + 1) + HX * (threadIdx.y + 1), up, dn);
+  const int st[2] = {1, SX};
+  auto lap_s = [&](const double* F, int ci, double fc) {
+    double s = 0.0;
+#pragma unroll
+    for (int dir = 0; dir < 2; ++dir) s += F[ci + st[dir]] + F[ci - st[dir]];
+    return (s - 4.0 * fc) * K.ih2;
+  };
+  auto dhat_s = [&](const double* F, int ci, int dir) { return (F[ci + st[dir]] - F[ci - st[dir]]) * K.i2h; };
+  const double* su = sv + 4 * SP;
+  // sigma_IJ of u with the eigenstrain of v_c (reference 0), at LDS position ci
+  auto sigma_s = [&](int ci, int I, int J) {
+    if (I != J) return K.C44 * (dhat_s(su + J * SP, ci, I) + dhat_s(su + I * SP, ci, J));
+    const double ec = K.eps0 * (sv[ci] - 0.0);
+    double s = 0.0;
+#pragma unroll
+    for (int L = 0; L < 2; ++L) s += (L == I ? K.C11 : K.C12) * (dhat_s(su + L * SP, ci, L) - ec);
+    return s;
+  };
+  // dG on the block and its halo of 1 (halo point (a, b) sits at v position (a + 1, b + 1))
+  for (int q = tid; q < HP; q += kBX * kJY2) {
+    const int a = q % HX, b = q / HX, ci = (a + 1) + SX * (b + 1);
+    const long long n = wrap(i0 + a - 1, K.nx) + (long long)K.nx * wrap(j0 + b - 1, K.ny);
+    double vv[4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) vv[f] = sv[f * SP + ci];
+    double g = K.kel * vv[0] - 0.5 * K.gamma_c * lap_s(sv, ci, vv[0]);
+#pragma unroll
+    for (int f = 0; f < 4; ++f) g += B[f * N + n] * vv[f];
+    if (K.elastic) {
+      double div = 0.0;
+#pragma unroll
+      for (int I = 0; I < 2; ++I) div += dhat_s(su + I * SP, ci, I);
+      g += -0.5 * K.eps0 * K.Ctr * div;
+    }
+    sdg[q] = g;
+  }
+  __syncthreads();
+  const int pi = i0 + (int)threadIdx.x, pj = j0 + (int)threadIdx.y;
+  if (pi >= K.nx || pj >= K.ny) return;
+  const long long n = pi + (long long)K.nx * pj;
+  const int ci = (threadIdx.x + 2) + SX * (threadIdx.y + 2);
+  const int hq = (threadIdx.x + 1) + HX * (threadIdx.y + 1);
+  const int hs[2] = {1, HX};
+  const double idt = 1.0 / dt;
+  {
+    // c row: v_c / dt - div_h(M grad_h dG), face mobility M = kappa/2 (g_i + g_j)
+    const double mc = sg[hq], g0 = sdg[hq];
+    double s = 0.0;
+#pragma unroll
+    for (int dir = 0; dir < 2; ++dir) {
+      const double Mp = 0.5 * K.kappa * (mc + sg[hq + hs[dir]]);
+      const double Mm = 0.5 * K.kappa * (mc + sg[hq - hs[dir]]);
+      s += Mp * (sdg[hq + hs[dir]] - g0) - Mm * (g0 - sdg[hq - hs[dir]]);
+    }
+    w[n] = sv[ci] * idt - s * K.ih2;
+  }
+  double vv[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) vv[q] = sv[q * SP + ci];
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    double s = -0.5 * K.gamma_eta * lap_s(sv + (1 + e) * SP, ci, vv[1 + e]);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) s += B[(4 * (1 + e) + q) * N + n] * vv[q];
+    w[(1 + e) * N + n] = vv[1 + e] * idt + K.L_eta * s;
+  }
+#pragma unroll
+  for (int I = 0; I < 2; ++I) {
+    double d = 0.0;
+    if (K.elastic) {
+#pragma unroll
+      for (int J = 0; J < 2; ++J) d += sigma_s(ci + st[J], I, J) - sigma_s(ci - st[J], I, J);
+    }
+    w[(4 + I) * N + n] = K.elastic ? d * K.i2h : su[I * SP + ci];
+  }
 }
 
 // J v in 3D: a block of kBX x kBY columns marches through kJZ planes in z, keeping three
