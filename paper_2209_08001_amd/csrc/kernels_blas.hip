@@ -201,9 +201,11 @@ __global__ __launch_bounds__(kThreads) void k_sum2(long long n, const double* __
 // 0 < c < 1, 0 < c eta_i < 1 (i = 1..4, eta_4 = 4 - eta_1 - eta_2 - eta_3).
 __global__ __launch_bounds__(kThreads) void k_trial(long long N, int nf, const double* __restrict__ X,
                                                     const double* __restrict__ S, double lam,
-                                                    double shift, double* __restrict__ Xt,
+                                                    const double* __restrict__ msums, double* __restrict__ Xt,
                                                     double* __restrict__ partial) {
   __shared__ double lds[kThreads / 64];
+  // mass projection of the update: shift = -(sum S_c + sum (c - c^n)) / N, from the device sums
+  const double shift = -(msums[0] + msums[1]) / (double)N;
   double bad = 0.0;
   for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < N;
        e += (long long)gridDim.x * kThreads) {
@@ -377,8 +379,8 @@ void launch_sum2(long long n, const double* x, const double* y, const double* yn
 }
 
 void launch_trial(const Consts& K, int nf, const double* X, const double* S, double lam,
-                  double shift, double* Xt, double* partial, hipStream_t s) {
-  hipLaunchKernelGGL(k_trial, dim3(kRedBlocks), dim3(kThreads), 0, s, K.N, nf, X, S, lam, shift,
+                  const double* msums, double* Xt, double* partial, hipStream_t s) {
+  hipLaunchKernelGGL(k_trial, dim3(kRedBlocks), dim3(kThreads), 0, s, K.N, nf, X, S, lam, msums,
                      Xt, partial);
 }
 

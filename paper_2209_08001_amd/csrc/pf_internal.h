@@ -110,8 +110,10 @@ void launch_update_dev(long long n, int nv, const T* V, long long ldv, const dou
                        const double* w, T* out, hipStream_t s);
 void launch_sum2(long long n, const double* x, const double* y, const double* yn, double* partial,
                  hipStream_t s);
+// Xt = X + lam (S + shift e_c), shift = -(msums[0] + msums[1]) / N (device sums of launch_sum2,
+// finalized); partial: count of nodes outside the log domain
 void launch_trial(const Consts& K, int nf, const double* X, const double* S, double lam,
-                  double shift, double* Xt, double* partial, hipStream_t s);
+                  const double* msums, double* Xt, double* partial, hipStream_t s);
 void launch_dx2(long long n4, const double* X, const double* Xn, double* partial, hipStream_t s);
 void launch_class_sums(const Consts& K, const double* u, double* partial, hipStream_t s);
 void launch_class_shift(const Consts& K, double* u, const double* sums, hipStream_t s);

@@ -317,6 +317,10 @@ void prof_resolve(pfnks_problem* p) {
   p->pending.erase(p->pending.begin(), p->pending.begin() + done);
 }
 
+// slot of the two mass-projection sums in p->red, kept on the device for the line search's
+// trials; every other reduction into p->red writes fewer values (at most 3 * 2^3 = 24)
+constexpr int kRedMassSlot = pf::kMaxRed - 2;
+
 // finalize partial sums of nvals values and copy them to p->hbuf
 int reduce_to_host(pfnks_problem* p, int nvals) {
   pf::launch_finalize(p->part, nvals, p->red, p->stream, p->hbuf);
@@ -791,27 +795,29 @@ int pfnks_step(pfnks_problem* p, double dt, pfnks_step_stats* stats) {
     gm_total += its;
     if (s == PFNKS_ENOCONV) break;
     if (s) return s;
-    // mass projection of the update: sum S_c = -sum (c - c^n)
+    // mass projection of the update: sum S_c = -sum (c - c^n); the two sums stay on the
+    // device (a slot of red no other reduction writes) and the trial kernel forms the shift
+    double* msums = p->red + kRedMassSlot;
     pf::launch_sum2(N, p->S, p->X, p->Xn, p->part, p->stream);
-    p->launches += 1;
-    s = reduce_to_host(p, 2);
-    if (s) return s;
-    const double shift = -(p->hbuf[0] + p->hbuf[1]) / (double)N;
-    // backtracking line search (Armijo)
+    pf::launch_finalize(p->part, 2, msums, p->stream);
+    p->launches += 2;
+    // backtracking line search (Armijo).  One host synchronisation per trial: the trial's
+    // count of nodes outside the log domain goes to host memory without one, and the residual
+    // is evaluated at the trial point whatever it is (outside the domain it is not finite and
+    // counts the same nodes, and the point is rejected either way).
     double lam = 1.0, ft = 0.0;
     bool accepted = false;
     for (int hv = 0; hv <= sv.ls_max_halvings; ++hv) {
-      pf::launch_trial(p->K, p->nf, p->X, p->S, lam, shift, p->Xt, p->part, p->stream);
-      p->launches += 1;
-      s = reduce_to_host(p, 1);
+      pf::launch_trial(p->K, p->nf, p->X, p->S, lam, msums, p->Xt, p->part, p->stream);
+      pf::launch_finalize(p->part, 1, p->red, p->stream, p->hbuf + 2);
+      p->launches += 2;
+      s = residual(p, p->Xt, dt, p->Ft, &ft, &bad);
       if (s) return s;
-      if (p->hbuf[0] == 0.0) {
-        s = residual(p, p->Xt, dt, p->Ft, &ft, &bad);
-        if (s) return s;
-        if (bad == 0.0 && std::isfinite(ft) && ft * ft <= (1.0 - 2.0 * sv.ls_alpha * lam) * fn * fn) {
-          accepted = true;
-          break;
-        }
+      const double trial_bad = p->hbuf[2];
+      if (trial_bad == 0.0 && bad == 0.0 && std::isfinite(ft) &&
+          ft * ft <= (1.0 - 2.0 * sv.ls_alpha * lam) * fn * fn) {
+        accepted = true;
+        break;
       }
       lam *= 0.5;
       ++backtracks;
@@ -840,14 +846,14 @@ int pfnks_step(pfnks_problem* p, double dt, pfnks_step_stats* stats) {
   // already returns updates without those modes, but only up to the rounding of the Krylov
   // element type, and the other preconditioners do not remove them at all
   project_gauge(p, p->X);
-  // step close: ||X - X^n|| over c and eta, energy, mass
+  // step close: ||X - X^n|| over c and eta (to host memory, read after the energy's
+  // synchronisation), energy, mass
   pf::launch_dx2(4 * N, p->X, p->Xn, p->part, p->stream);
-  p->launches += 1;
-  s = reduce_to_host(p, 1);
-  if (s) return s;
-  st.dx_rms = std::sqrt(p->hbuf[0] / (4.0 * N));
+  pf::launch_finalize(p->part, 1, p->red, p->stream, p->hbuf + 4);
+  p->launches += 2;
   s = step_close(p, &st, p->X, dt);
   if (s) return s;
+  st.dx_rms = std::sqrt(p->hbuf[4] / (4.0 * N));
   std::swap(p->X, p->Xn);
   p->t += dt;
   st.status = PFNKS_OK;
