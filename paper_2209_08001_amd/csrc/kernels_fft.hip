@@ -26,13 +26,20 @@ __device__ inline double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
+// LDS position of line element i: one pad slot after every 8 elements, which spreads the
+// power-of-two strides of the bit-reversed stores and the first butterfly stages over all LDS
+// banks (unpadded, the 16-byte elements of a wave landed on the same banks); lp_size(len)
+// slots hold elements 0 .. len - 1.
+__host__ __device__ constexpr int lp(int i) { return i + (i >> 3); }
+__host__ __device__ constexpr int lp_size(int len) { return len + (len >> 3) + 1; }
+
 // ---- fused 2D pipeline ------------------------------------------------------------------
-// In-LDS transform of one line of n = 2^logn complex points stored at buf[0 .. n) in
-// bit-reversed order; radix-4 stage pairs (two radix-2 stages per thread, 4 points in
-// registers) and a final radix-2 stage when logn is odd.  All threads of the block take part;
-// nl lines are transformed together (line l at buf + l * n).
+// In-LDS transform of one line of n = 2^logn complex points stored in bit-reversed order at
+// padded positions lp(base + l n + k), k < n, of buf; radix-4 stage pairs (two radix-2 stages
+// per thread, 4 points in registers) and a final radix-2 stage when logn is odd.  All threads
+// of the block take part; nl lines l are transformed together.
 __device__ inline void fft_lds(double2* buf, int n, int logn, int nl, const double2* __restrict__ tw,
-                               int inverse) {
+                               int inverse, int base = 0) {
   int s = 1;
   for (; s + 1 <= logn; s += 2) {
     const int half = 1 << (s - 1);
@@ -40,7 +47,7 @@ __device__ inline void fft_lds(double2* buf, int n, int logn, int nl, const doub
     for (int t = threadIdx.x; t < nl * nq; t += blockDim.x) {
       const int l = t / nq, r = t - l * nq;
       const int grp = r / half, pos = r - grp * half;
-      double2* b = buf + l * n + grp * 4 * half + pos;
+      const int i0 = base + l * n + grp * 4 * half + pos;
       double2 w1 = tw[pos * (n >> s)];                 // W_{2 half}^pos
       double2 w2 = tw[pos * (n >> (s + 1))];           // W_{4 half}^pos
       double2 w3 = tw[(pos + half) * (n >> (s + 1))];  // W_{4 half}^(pos + half)
@@ -49,14 +56,15 @@ __device__ inline void fft_lds(double2* buf, int n, int logn, int nl, const doub
         w2.y = -w2.y;
         w3.y = -w3.y;
       }
-      const double2 a0 = b[0], a1 = cmul(b[half], w1), a2 = b[2 * half], a3 = cmul(b[3 * half], w1);
+      const double2 a0 = buf[lp(i0)], a1 = cmul(buf[lp(i0 + half)], w1), a2 = buf[lp(i0 + 2 * half)],
+                    a3 = cmul(buf[lp(i0 + 3 * half)], w1);
       const double2 c0 = make_double2(a0.x + a1.x, a0.y + a1.y), c1 = make_double2(a0.x - a1.x, a0.y - a1.y);
       const double2 c2 = make_double2(a2.x + a3.x, a2.y + a3.y), c3 = make_double2(a2.x - a3.x, a2.y - a3.y);
       const double2 d2 = cmul(c2, w2), d3 = cmul(c3, w3);
-      b[0] = make_double2(c0.x + d2.x, c0.y + d2.y);
-      b[2 * half] = make_double2(c0.x - d2.x, c0.y - d2.y);
-      b[half] = make_double2(c1.x + d3.x, c1.y + d3.y);
-      b[3 * half] = make_double2(c1.x - d3.x, c1.y - d3.y);
+      buf[lp(i0)] = make_double2(c0.x + d2.x, c0.y + d2.y);
+      buf[lp(i0 + 2 * half)] = make_double2(c0.x - d2.x, c0.y - d2.y);
+      buf[lp(i0 + half)] = make_double2(c1.x + d3.x, c1.y + d3.y);
+      buf[lp(i0 + 3 * half)] = make_double2(c1.x - d3.x, c1.y - d3.y);
     }
     __syncthreads();
   }
@@ -66,12 +74,12 @@ __device__ inline void fft_lds(double2* buf, int n, int logn, int nl, const doub
     for (int t = threadIdx.x; t < nl * nh; t += blockDim.x) {
       const int l = t / nh, r = t - l * nh;
       const int grp = r / half, pos = r - grp * half;
-      double2* b = buf + l * n + grp * 2 * half + pos;
+      const int i0 = base + l * n + grp * 2 * half + pos;
       double2 w = tw[pos * (n >> s)];
       if (inverse) w.y = -w.y;
-      const double2 a0 = b[0], a1 = cmul(b[half], w);
-      b[0] = make_double2(a0.x + a1.x, a0.y + a1.y);
-      b[half] = make_double2(a0.x - a1.x, a0.y - a1.y);
+      const double2 a0 = buf[lp(i0)], a1 = cmul(buf[lp(i0 + half)], w);
+      buf[lp(i0)] = make_double2(a0.x + a1.x, a0.y + a1.y);
+      buf[lp(i0 + half)] = make_double2(a0.x - a1.x, a0.y - a1.y);
     }
     __syncthreads();
   }
@@ -92,8 +100,8 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_lines(double2* __restrict__
                                                            long long lb, long long lc, long long nlines,
                                                            int lpb, const double2* __restrict__ tw,
                                                            int inverse, int contiguous) {
-  extern __shared__ double2 sm[];  // lpb lines of n, then n/2 twiddles
-  double2* tws = sm + lpb * n;
+  extern __shared__ double2 sm[];  // lpb lines of n (padded), then n/2 twiddles
+  double2* tws = sm + lp_size(lpb * n);
   stage_twiddles(tws, tw, n);
   const long long line0 = (long long)blockIdx.x * lpb;
   const int total = lpb * n;
@@ -110,7 +118,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_lines(double2* __restrict__
     if (line < nlines) {
       const long long off = (line % la) * lb + (line / la) * lc;
       const int rp = (int)(__brev((unsigned)p) >> (32 - logn));
-      sm[l * n + rp] = data[off + p * pstride];
+      sm[lp(l * n + rp)] = data[off + p * pstride];
     }
   }
   __syncthreads();
@@ -127,7 +135,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_lines(double2* __restrict__
     const long long line = line0 + l;
     if (line < nlines) {
       const long long off = (line % la) * lb + (line / la) * lc;
-      data[off + p * pstride] = sm[l * n + p];
+      data[off + p * pstride] = sm[lp(l * n + p)];
     }
   }
 }
@@ -148,9 +156,9 @@ __global__ __launch_bounds__(256) void k_fft2_rows_fwd(Consts K, const T* __rest
                                                        const T* __restrict__ zc, int logn, int nl,
                                                        const double2* __restrict__ tw,
                                                        double2* __restrict__ out) {
-  extern __shared__ double2 sm[];  // nl * n, then n/2 twiddles
+  extern __shared__ double2 sm[];  // nl * n (padded), then n/2 twiddles
   const int n = K.nx;
-  double2* tws = sm + nl * n;
+  double2* tws = sm + lp_size(nl * n);
   stage_twiddles(tws, tw, n);
   const int j0 = xcd_band(blockIdx.x, gridDim.x) * nl;
   for (int e = threadIdx.x; e < nl * n; e += blockDim.x) {
@@ -163,13 +171,13 @@ __global__ __launch_bounds__(256) void k_fft2_rows_fwd(Consts K, const T* __rest
       qx += a * ((double)zc[ip + (long long)n * j] - (double)zc[im + (long long)n * j]) * K.i2h;
       qy += a * ((double)zc[i + (long long)n * jp] - (double)zc[i + (long long)n * jm]) * K.i2h;
     }
-    sm[l * n + brev(i, logn)] = make_double2(qx, qy);
+    sm[lp(l * n + brev(i, logn))] = make_double2(qx, qy);
   }
   __syncthreads();
   fft_lds(sm, n, logn, nl, tws, 0);
   for (int e = threadIdx.x; e < nl * n; e += blockDim.x) {
     const int l = e / n, i = e - l * n;
-    out[(long long)i + (long long)n * (j0 + l)] = sm[e];
+    out[(long long)i + (long long)n * (j0 + l)] = sm[lp(e)];
   }
 }
 
@@ -181,10 +189,11 @@ __global__ __launch_bounds__(256) void k_fft2_cols_solve(Consts K, int logn, con
                                                          const double* __restrict__ sx,
                                                          const double* __restrict__ syt,
                                                          double2* __restrict__ data) {
-  extern __shared__ double2 sm[];  // 2 n, then the output spectra (2 n), then n/2 twiddles
-  double2* wo = sm + 2 * K.ny;
+  // 2 lines of n, then the 2 lines of output spectra (elements 2n .. 4n; padded), then n/2
+  // twiddles
+  extern __shared__ double2 sm[];
   const int n = K.ny, nx = K.nx;
-  double2* tws = sm + 4 * n;
+  double2* tws = sm + lp_size(4 * n);
   stage_twiddles(tws, tw, n);
   // XCD-band order, so that the columns one XCD reads are adjacent and share cache lines
   const int kx = xcd_band(blockIdx.x, gridDim.x);
@@ -194,7 +203,7 @@ __global__ __launch_bounds__(256) void k_fft2_cols_solve(Consts K, int logn, con
   for (int e = threadIdx.x; e < ncol * n; e += blockDim.x) {
     const int l = e / n, j = e - l * n;
     const int col = l ? kxm : kx;
-    sm[l * n + brev(j, logn)] = data[(long long)col + (long long)nx * j];
+    sm[lp(l * n + brev(j, logn))] = data[(long long)col + (long long)nx * j];
   }
   __syncthreads();
   fft_lds(sm, n, logn, ncol, tws, 0);
@@ -203,7 +212,7 @@ __global__ __launch_bounds__(256) void k_fft2_cols_solve(Consts K, int logn, con
     const int col = l ? kxm : kx;
     const int lm = self ? l : 1 - l;   // the mirror column's line
     const int jm = (j == 0) ? 0 : n - j;
-    const double2 av = sm[l * n + j], bv = sm[lm * n + jm];
+    const double2 av = sm[lp(l * n + j)], bv = sm[lp(lm * n + jm)];
     double2 Q0 = make_double2(0.5 * (av.x + bv.x), 0.5 * (av.y - bv.y));
     double2 Q1 = make_double2(0.5 * (av.y + bv.y), -0.5 * (av.x - bv.x));
     double2 U0 = make_double2(0.0, 0.0), U1 = make_double2(0.0, 0.0);
@@ -220,14 +229,14 @@ __global__ __launch_bounds__(256) void k_fft2_cols_solve(Consts K, int logn, con
       U1 = make_double2((A00 * Q1.x - A01 * Q0.x) * id, (A00 * Q1.y - A01 * Q0.y) * id);
     }
     // spectrum of u_x + i u_y, written in bit-reversed order for the inverse transform
-    wo[l * n + brev(j, logn)] = make_double2(U0.x - U1.y, U0.y + U1.x);
+    sm[lp(2 * n + l * n + brev(j, logn))] = make_double2(U0.x - U1.y, U0.y + U1.x);
   }
   __syncthreads();
-  fft_lds(wo, n, logn, ncol, tws, 1);
+  fft_lds(sm, n, logn, ncol, tws, 1, 2 * n);
   for (int e = threadIdx.x; e < ncol * n; e += blockDim.x) {
     const int l = e / n, j = e - l * n;
     const int col = l ? kxm : kx;
-    data[(long long)col + (long long)nx * j] = wo[e];
+    data[(long long)col + (long long)nx * j] = sm[lp(2 * n + e)];
   }
 }
 
@@ -235,14 +244,14 @@ __global__ __launch_bounds__(256) void k_fft2_cols_solve(Consts K, int logn, con
 template <typename T>
 __global__ __launch_bounds__(256) void k_fft2_rows_inv(Consts K, int logn, int nl, const double2* __restrict__ tw,
                                                        const double2* __restrict__ in, T* __restrict__ u) {
-  extern __shared__ double2 sm[];  // nl * n, then n/2 twiddles
+  extern __shared__ double2 sm[];  // nl * n (padded), then n/2 twiddles
   const int n = K.nx;
-  double2* tws = sm + nl * n;
+  double2* tws = sm + lp_size(nl * n);
   stage_twiddles(tws, tw, n);
   const int j0 = xcd_band(blockIdx.x, gridDim.x) * nl;
   for (int e = threadIdx.x; e < nl * n; e += blockDim.x) {
     const int l = e / n, i = e - l * n;
-    sm[l * n + brev(i, logn)] = in[(long long)i + (long long)n * (j0 + l)];
+    sm[lp(l * n + brev(i, logn))] = in[(long long)i + (long long)n * (j0 + l)];
   }
   __syncthreads();
   fft_lds(sm, n, logn, nl, tws, 1);
@@ -250,8 +259,8 @@ __global__ __launch_bounds__(256) void k_fft2_rows_inv(Consts K, int logn, int n
   for (int e = threadIdx.x; e < nl * n; e += blockDim.x) {
     const int l = e / n, i = e - l * n;
     const long long m = (long long)i + (long long)n * (j0 + l);
-    u[m] = (T)(sm[e].x * inv);
-    u[K.N + m] = (T)(sm[e].y * inv);
+    u[m] = (T)(sm[lp(e)].x * inv);
+    u[K.N + m] = (T)(sm[lp(e)].y * inv);
   }
 }
 
@@ -271,9 +280,9 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_r2c_x(Consts K, const T* __restrict__ r, double a,
                                                const T* __restrict__ zc, int logn, int rp,
                                                const double2* __restrict__ tw, double2* __restrict__ Qh) {
-  extern __shared__ double2 sm[];  // 3 rp lines of nx, then nx/2 twiddles
+  extern __shared__ double2 sm[];  // 3 rp lines of nx (padded), then nx/2 twiddles
   const int n = K.nx, nxh = n / 2 + 1, hb = K.ny / (2 * rp);
-  double2* tws = sm + 3 * rp * n;
+  double2* tws = sm + lp_size(3 * rp * n);
   stage_twiddles(tws, tw, n);
   const int b = xcd_band((int)blockIdx.x, (int)gridDim.x);
   const int jb = (b % hb) * 2 * rp, k = b / hb;
@@ -294,8 +303,8 @@ __global__ __launch_bounds__(256) void k_r2c_x(Consts K, const T* __restrict__ r
                  (double)zc[i + (long long)n * (j + (long long)K.ny * km)]) * K.i2h;
     }
     const int bi = brev(i, logn);
-    sm[(3 * q + l) * n + bi] = make_double2(q0, q1);
-    reinterpret_cast<double*>(&sm[(3 * q + 2) * n + bi])[l] = q2;
+    sm[lp((3 * q + l) * n + bi)] = make_double2(q0, q1);
+    reinterpret_cast<double*>(&sm[lp((3 * q + 2) * n + bi)])[l] = q2;
   }
   __syncthreads();
   fft_lds(sm, n, logn, 3 * rp, tws, 0);
@@ -303,7 +312,7 @@ __global__ __launch_bounds__(256) void k_r2c_x(Consts K, const T* __restrict__ r
   for (int e = threadIdx.x; e < 3 * rp * nxh; e += blockDim.x) {
     const int line = e / nxh, kx = e - line * nxh;
     const int q = line / 3, t = line - 3 * q, j0 = jb + 2 * q;
-    const double2 av = sm[line * n + kx], bv = sm[line * n + ((n - kx) & (n - 1))];
+    const double2 av = sm[lp(line * n + kx)], bv = sm[lp(line * n + ((n - kx) & (n - 1)))];
     const double2 A = make_double2(0.5 * (av.x + bv.x), 0.5 * (av.y - bv.y));   // real part's spectrum
     const double2 B = make_double2(0.5 * (av.y + bv.y), -0.5 * (av.x - bv.x));  // imaginary part's
     if (t < 2) {
@@ -324,9 +333,9 @@ __global__ __launch_bounds__(256) void k_r2c_x(Consts K, const T* __restrict__ r
 __global__ __launch_bounds__(256) void k_z_solve(Consts K, int logn, int lpb, const double2* __restrict__ tw,
                                                  const double* __restrict__ sx, const double* __restrict__ sy,
                                                  const double* __restrict__ szt, double2* __restrict__ Qh) {
-  extern __shared__ double2 sm[];  // 3 lpb lines of nz: line (f lpb + l), then nz/2 twiddles
+  extern __shared__ double2 sm[];  // 3 lpb lines of nz: line (f lpb + l) (padded), then nz/2 twiddles
   const int n = K.nz, nxh = K.nx / 2 + 1;
-  double2* tws = sm + 3 * lpb * n;
+  double2* tws = sm + lp_size(3 * lpb * n);
   stage_twiddles(tws, tw, n);
   const int nxb = (nxh + lpb - 1) / lpb;
   const int b = xcd_band((int)blockIdx.x, (int)gridDim.x);
@@ -339,7 +348,7 @@ __global__ __launch_bounds__(256) void k_z_solve(Consts K, int logn, int lpb, co
     const int l = e % lpb, rest = e / lpb, p = rest % n, f = rest / n;
     double2 v = make_double2(0.0, 0.0);
     if (kx0 + l < nxh) v = Qh[f * plane + base + l + zs * p];
-    sm[(f * lpb + l) * n + brev(p, logn)] = v;
+    sm[lp((f * lpb + l) * n + brev(p, logn))] = v;
   }
   __syncthreads();
   fft_lds(sm, n, logn, nl, tws, 0);
@@ -350,7 +359,7 @@ __global__ __launch_bounds__(256) void k_z_solve(Consts K, int logn, int lpb, co
     const double s2 = S0 * S0 + S1 * S1 + S2 * S2;
     double2 Q[3];
 #pragma unroll
-    for (int f = 0; f < 3; ++f) Q[f] = sm[(f * lpb + l) * n + p];
+    for (int f = 0; f < 3; ++f) Q[f] = sm[lp((f * lpb + l) * n + p)];
     if (K.elastic) {
       double2 U[3] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
       if (s2 != 0.0) {
@@ -378,23 +387,23 @@ __global__ __launch_bounds__(256) void k_z_solve(Consts K, int logn, int lpb, co
                               Ai[I][0] * Q[0].y + Ai[I][1] * Q[1].y + Ai[I][2] * Q[2].y);
       }
 #pragma unroll
-      for (int f = 0; f < 3; ++f) sm[(f * lpb + l) * n + p] = U[f];
+      for (int f = 0; f < 3; ++f) sm[lp((f * lpb + l) * n + p)] = U[f];
     }
   }
   __syncthreads();
   for (int e = threadIdx.x; e < nl * n; e += blockDim.x) {
     const int line = e / n, p = e - line * n, q = brev(p, logn);
     if (p < q) {
-      const double2 t = sm[line * n + p];
-      sm[line * n + p] = sm[line * n + q];
-      sm[line * n + q] = t;
+      const double2 t = sm[lp(line * n + p)];
+      sm[lp(line * n + p)] = sm[lp(line * n + q)];
+      sm[lp(line * n + q)] = t;
     }
   }
   __syncthreads();
   fft_lds(sm, n, logn, nl, tws, 1);
   for (int e = threadIdx.x; e < nl * n; e += blockDim.x) {
     const int l = e % lpb, rest = e / lpb, p = rest % n, f = rest / n;
-    if (kx0 + l < nxh) Qh[f * plane + base + l + zs * p] = sm[(f * lpb + l) * n + p];
+    if (kx0 + l < nxh) Qh[f * plane + base + l + zs * p] = sm[lp((f * lpb + l) * n + p)];
   }
 }
 
@@ -404,9 +413,9 @@ __global__ __launch_bounds__(256) void k_z_solve(Consts K, int logn, int lpb, co
 template <typename T>
 __global__ __launch_bounds__(256) void k_c2r_x(Consts K, int logn, int rp, const double2* __restrict__ tw,
                                                const double2* __restrict__ Qh, T* __restrict__ u) {
-  extern __shared__ double2 sm[];  // 3 rp lines of nx, then nx/2 twiddles
+  extern __shared__ double2 sm[];  // 3 rp lines of nx (padded), then nx/2 twiddles
   const int n = K.nx, nxh = n / 2 + 1, hb = K.ny / (2 * rp);
-  double2* tws = sm + 3 * rp * n;
+  double2* tws = sm + lp_size(3 * rp * n);
   stage_twiddles(tws, tw, n);
   const int b = xcd_band((int)blockIdx.x, (int)gridDim.x);
   const int jb = (b % hb) * 2 * rp, k = b / hb;
@@ -429,7 +438,7 @@ __global__ __launch_bounds__(256) void k_c2r_x(Consts K, int logn, int rp, const
       P.y = -P.y;
       Q.y = -Q.y;
     }
-    sm[line * n + brev(kx, logn)] = make_double2(P.x - Q.y, P.y + Q.x);  // P + i Q
+    sm[lp(line * n + brev(kx, logn))] = make_double2(P.x - Q.y, P.y + Q.x);  // P + i Q
   }
   __syncthreads();
   fft_lds(sm, n, logn, 3 * rp, tws, 1);
@@ -439,8 +448,8 @@ __global__ __launch_bounds__(256) void k_c2r_x(Consts K, int logn, int rp, const
     const int rr = e / n, i = e - rr * n, j = jb + rr;
     const int q = rr >> 1, l = rr & 1;
     const long long m = (long long)i + (long long)n * ((long long)j + (long long)K.ny * k);
-    const double2 z = sm[(3 * q + l) * n + i];
-    const double2 z3 = sm[(3 * q + 2) * n + i];
+    const double2 z = sm[lp((3 * q + l) * n + i)];
+    const double2 z3 = sm[lp((3 * q + 2) * n + i)];
     u[m] = (T)(z.x * inv);
     u[NN + m] = (T)(z.y * inv);
     u[2 * NN + m] = (T)((l == 0 ? z3.x : z3.y) * inv);
@@ -596,7 +605,7 @@ int ilog2(int n) {
 // k_fft_lines with its LDS: lpb lines and the n/2 twiddles (beyond 64 KiB for the longest lines)
 void launch_lines(double2* data, int n, int logn, long long pstride, long long la, long long lb, long long lc,
                   long long nlines, int lpb, const double2* tw, int inverse, int contiguous, hipStream_t s) {
-  const size_t lds = sizeof(double2) * ((size_t)lpb * n + n / 2);
+  const size_t lds = sizeof(double2) * ((size_t)lp_size(lpb * n) + n / 2);
   if (lds > 64 * 1024)
     (void)hipFuncSetAttribute((const void*)k_fft_lines, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   const long long blocks = (nlines + lpb - 1) / lpb;
@@ -661,8 +670,9 @@ void launch_spectral_solve(const Consts& K, const FftPlan& P, const T* r, double
     int nl = 512 / K.nx;
     if (nl < 1) nl = 1;
     while (K.ny % nl) nl >>= 1;
-    const size_t lrow = sizeof(double2) * (nl * K.nx + K.nx / 2), lcol = sizeof(double2) * (4 * K.ny + K.ny / 2);
-    if (lcol > 64 * 1024)  // ny = 1024: 72 KiB
+    const size_t lrow = sizeof(double2) * (lp_size(nl * K.nx) + K.nx / 2);
+    const size_t lcol = sizeof(double2) * (lp_size(4 * K.ny) + K.ny / 2);
+    if (lcol > 64 * 1024)  // ny = 1024: 80 KiB
       (void)hipFuncSetAttribute((const void*)k_fft2_cols_solve, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lcol);
     hipLaunchKernelGGL(k_fft2_rows_fwd<T>, dim3(K.ny / nl), dim3(256), lrow, s, K, r, a, zc, lx, nl, P.tw[0], work0);
     hipLaunchKernelGGL(k_fft2_cols_solve, dim3(K.nx / 2), dim3(256), lcol, s, K, ly, P.tw[1], P.sn[0],
@@ -677,12 +687,13 @@ void launch_spectral_solve(const Consts& K, const FftPlan& P, const T* r, double
     int rp = 256 / K.nx;  // row pairs per x block: about 768 points per block
     if (rp < 1) rp = 1;
     while (rp > 1 && (K.ny / 2) % rp) rp >>= 1;
-    const size_t lx_bytes = sizeof(double2) * (3 * rp * K.nx + K.nx / 2);
+    const size_t lx_bytes = sizeof(double2) * (lp_size(3 * rp * K.nx) + K.nx / 2);
     const unsigned xblocks = (unsigned)((K.ny / (2 * rp)) * K.nz);
-    int lpz = 1024 / K.nz;  // kx columns per z block: 48 KiB of LDS
+    int lpz = 1024 / K.nz;  // kx columns per z block: at most 53 KiB of LDS (three blocks per CU)
     if (lpz > 8) lpz = 8;
     if (lpz < 1) lpz = 1;
-    const size_t lz_bytes = sizeof(double2) * (3 * lpz * K.nz + K.nz / 2);
+    while (lpz > 1 && sizeof(double2) * (lp_size(3 * lpz * K.nz) + K.nz / 2) > 53 * 1024) --lpz;
+    const size_t lz_bytes = sizeof(double2) * (lp_size(3 * lpz * K.nz) + K.nz / 2);
     const unsigned zblocks = (unsigned)(((nxh + lpz - 1) / lpz) * K.ny);
     int lpy = kFftLds / K.ny;  // adjacent kx lines per y block
     if (lpy > 16) lpy = 16;
