@@ -101,7 +101,7 @@ typedef struct {
   int overlap;            /* delta: extra layers of each subdomain on every side (0..4)     */
   int sweeps;             /* symmetric multicolour block Gauss-Seidel sweeps per tile solve */
   pfnks_pc pc;            /* preconditioner                                                 */
-  pfnks_precision precision; /* PFNKS_FP64 only in this version                            */
+  pfnks_precision precision; /* PFNKS_FP64, or PFNKS_MIXED (float Krylov basis and preconditioner) */
   double ls_alpha;        /* Armijo constant of the backtracking line search                */
   int ls_max_halvings;    /* halvings of lambda before the step is declared failed          */
 } pfnks_solver;
@@ -202,8 +202,9 @@ int pfnks_debug_counters(pfnks_problem* p, long long* launches, long long* syncs
  * operation must move: reads of its inputs plus writes of its outputs, once each). */
 enum {
   PFNKS_K_RESIDUAL = 0,  /* residual F (two kernels)                    */
-  PFNKS_K_LINEARISE = 1, /* local 4 x 4 chemical blocks                 */
-  PFNKS_K_JV = 2,        /* matrix-free Jacobian apply (two kernels)    */
+  PFNKS_K_LINEARISE = 1, /* local 4 x 4 chemical blocks (and, once per
+                            step, the tile solve's node blocks)         */
+  PFNKS_K_JV = 2,        /* matrix-free Jacobian apply                  */
   PFNKS_K_RAS = 3,       /* Schwarz tile solve                          */
   PFNKS_K_SPECTRAL = 4,  /* Fourier solve of the displacement block     */
   PFNKS_K_MULTIDOT = 5,  /* GMRES classical Gram-Schmidt dot products   */

@@ -355,6 +355,19 @@ int dot_norm(pfnks_problem* p, const double* x, double* nrm) {
   return PFNKS_OK;
 }
 
+// algorithmic bytes of the per-step tile set-up: every extended tile node reads its chemical
+// block (16) in the Krylov element type and c^n (double) and writes 13 node-block values
+double pack_bytes(pfnks_problem* p) {
+  if (!uses_tiles(p->solver.pc)) return 0.0;
+  double rho = 1.0;
+  for (int k = 0; k < p->K.dim; ++k) {
+    const int t = p->solver.tile[k];
+    rho *= (double)(t + 2 * p->solver.overlap) / t;
+  }
+  const double kb = (double)p->kb;
+  return p->N * rho * (29.0 * kb + 8.0);
+}
+
 // algorithmic bytes of one Schwarz apply: every extended tile node reads r (nfz planes), its
 // node-block pieces (13, formed once per step) and the c row of its chemical block (4), in
 // the Krylov element type, and c^n (double); the owned nodes write z
@@ -778,7 +791,8 @@ int pfnks_step(pfnks_problem* p, double dt, pfnks_step_stats* stats) {
     double* Bm = p->B;
     {
       const bool mixed = sv.precision == PFNKS_MIXED;
-      Prof pr(p, PFNKS_K_LINEARISE, 8.0 * 24 * N + ((newton == 0 && mixed) ? 64.0 * N : 0.0));
+      Prof pr(p, PFNKS_K_LINEARISE,
+              8.0 * 24 * N + ((newton == 0 && mixed) ? 64.0 * N : 0.0) + ((newton == 0) ? pack_bytes(p) : 0.0));
       if (newton == 0 && !mixed) {
         pf::launch_linearise(p->K, p->X, p->Xn, (double*)p->Bpc, nullptr, p->stream);
         Bm = (double*)p->Bpc;
