@@ -14,8 +14,9 @@
 // diamond in 2D, 25 points in 3D).
 // Colour (i + 2j) mod 5 (2D) or (i + 2j + 3k) mod 7 (3D) separates every pair of nodes
 // inside one diamond, so all nodes of a colour update at once, exactly as sequential
-// Gauss-Seidel would.  The per-node 4 x 4 chemical block B and the right-hand side stay in
-// registers of the thread that owns the node.
+// Gauss-Seidel would.  The pieces of each node's diagonal block (formed once per time step by
+// k_ras_pack) and the right-hand side stay in registers of the thread that owns the node; the
+// c row of the chemical block, which the dG updates need, sits in LDS.
 //
 // Tile operator, per node (the Jacobian of the residual, written in the kernels_phase notes):
 //   dG    = B_c.z + kel z_c - (eps0/2) Ctr div_h z_u - (gamma_c/2) Lap_h z_c   on ext and its ring
