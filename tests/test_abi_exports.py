@@ -66,3 +66,23 @@ def test_batch_step_rejects_bad_arguments_on_host():
     assert lib.pfnks_batch_step(hs, 1, d, 0, None, None) == pfnks.PFNKS_EINVAL
     assert lib.pfnks_batch_step(hs, -1, d, 0, None, None) == pfnks.PFNKS_EINVAL
     assert lib.pfnks_batch_step(hs, 0, d, 0, None, None) == pfnks.PFNKS_OK
+
+
+def test_workspace_holds_the_tile_setup():
+    """The per-step node blocks of the tile solve (13 values per extended-tile node, every
+    tile, in the Krylov element type) are part of the workspace when a Schwarz preconditioner
+    is selected, and absent otherwise."""
+    if not os.path.exists(LIB):
+        pytest.skip("libpfnks.so not built")
+    from paper_2209_08001_amd import pfnks
+    from paper_2209_08001_amd import workloads as W
+
+    n = (512, 512)
+    tiles = (512 // 32) * (512 // 32)
+    ext = (32 + 2 * 2) ** 2
+    for prec, kb in ((pfnks.FP64, 8), (pfnks.MIXED, 4)):
+        s = dict(W.DEFAULT_SOLVER, precision=prec)
+        with_tiles = pfnks.workspace_bytes(n, W.H, W.DEFAULT_MODEL, dict(s, pc=pfnks.PC_RAS_SPECTRAL))
+        without = pfnks.workspace_bytes(n, W.H, W.DEFAULT_MODEL, dict(s, pc=pfnks.PC_SPECTRAL))
+        pack = 13 * tiles * ext * kb
+        assert pack <= with_tiles - without <= pack + 4096
