@@ -667,7 +667,7 @@ void launch_spectral_solve(const Consts& K, const FftPlan& P, const T* r, double
                            hipStream_t s) {
   if (K.dim == 2 && K.ny <= 1024 && K.nx <= 1024) {
     const int lx = ilog2(K.nx), ly = ilog2(K.ny);
-    int nl = 1024 / K.nx;  // rows per x block: 1024 points, every thread busy in each stage
+    int nl = 512 / K.nx;  // rows per x block (one 512-point row: 512 blocks measured faster than 256)
     if (nl < 1) nl = 1;
     while (K.ny % nl) nl >>= 1;
     const size_t lrow = sizeof(double2) * (lp_size(nl * K.nx) + K.nx / 2);
