@@ -474,16 +474,17 @@ def oracle_3d():
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-@pytest.mark.parametrize("pc", ["ras_spectral", "ras"])
+@pytest.mark.parametrize("pc", ["ras_spectral", "ras", "as", "rras"])
 def test_step_parity_3d(oracle_3d, pc, prec):
-    """3D 8 x 8 x 8 (tiles 4^3, overlap 1), two steps: within 1e-8 of the oracle's root."""
+    """3D 8 x 8 x 8 (tiles 4^3, overlap 1, two tiles per direction), two steps, every
+    preconditioner (the all-field ones with the 3D tile kernel holding u, classical AS and
+    right-RAS through the 3D gather): within 1e-8 of the oracle's root."""
     from paper_2209_08001_amd import pfnks
 
     _cuda()
     n, c0, e0, traj = oracle_3d
     _note(f"step parity 3d pc={pc} precision={prec}")
-    p = _problem(n, c0, e0, tile=(4, 4, 4), overlap=1,
-                 pc=pfnks.PC_RAS if pc == "ras" else pfnks.PC_RAS_SPECTRAL,
+    p = _problem(n, c0, e0, tile=(4, 4, 4), overlap=1, pc=getattr(pfnks, PCS[pc]),
                  precision=pfnks.MIXED if prec == "mixed" else pfnks.FP64, newton_rtol=ROOT_RTOL)
     m0 = p.mass()
     for k, dt in enumerate((0.01, 0.05)):
