@@ -16,14 +16,18 @@ from .driver import adaptive_run
 
 
 def default_candidates(dim):
+    """Tile shapes, overlaps and sweep counts around the measured optima (2D: 32 x 32 tiles,
+    overlap 2, 8 sweeps; 3D: 8^3 tiles, overlap 1, 6 sweeps)."""
     if dim == 2:
         tiles = [(32, 32, 1), (32, 16, 1), (16, 32, 1), (64, 16, 1), (16, 16, 1)]
-        overlaps = [1, 2]
+        overlaps = [1, 2, 3]
+        sweeps = (6, 8, 10)
     else:
-        tiles = [(8, 8, 8), (16, 8, 8), (8, 8, 4)]
-        overlaps = [1]
+        tiles = [(8, 8, 8), (8, 8, 4), (16, 8, 4)]
+        overlaps = [1, 2]
+        sweeps = (4, 6, 8)
     return [{"tile": t, "overlap": o, "sweeps": s}
-            for t, o, s in itertools.product(tiles, overlaps, (1, 2, 3))]
+            for t, o, s in itertools.product(tiles, overlaps, sweeps)]
 
 
 def autotune(n, h, model, solver, c0, eta0, wl, candidates=None, warm=10, steps=3, device="cuda:0"):

@@ -534,3 +534,27 @@ def test_full_size_first_step_root(wl, prec):
     assert r1 <= 1.1 * W.DEFAULT_SOLVER["newton_rtol"] * r0, (r1, r0)
     assert abs(st["mass"] - m0) <= 1e-13 * abs(m0)
     assert st["energy"] <= E0 + 1e-12 * abs(E0)
+
+
+def test_autotune_picks_a_valid_candidate():
+    """The autotuner times every candidate the library accepts on real steps from a warmed
+    state, skips shapes it rejects (here a tile whose extended block needs too many nodes per
+    thread), and returns the fastest of the timed ones; that configuration then steps."""
+    from paper_2209_08001_amd import pfnks
+    from paper_2209_08001_amd.autotune import autotune
+
+    _cuda()
+    n = (64, 64)
+    c0, e0 = W.init_fields(n, 41)
+    wl = dict(W.WORKLOADS["pf2d_64"], dt_min=1e-3, dt_max=1.0, zeta=100.0)
+    cands = [{"tile": (32, 32, 1), "overlap": 2, "sweeps": 8}, {"tile": (16, 16, 1), "overlap": 1, "sweeps": 6},
+             {"tile": (64, 64, 1), "overlap": 0, "sweeps": 8}]
+    _note("autotune 64^2, 3 candidates")
+    best, table = autotune(n, W.H, W.DEFAULT_MODEL, dict(W.DEFAULT_SOLVER), c0, e0, wl, candidates=cands,
+                           warm=3, steps=2)
+    assert [r["tile"] for r in table] == [(32, 32, 1), (16, 16, 1)]
+    assert best in table and best["ms_per_step"] == min(r["ms_per_step"] for r in table)
+    p = _problem(n, c0, e0, tile=best["tile"], overlap=best["overlap"], sweeps=best["sweeps"])
+    st = p.step(1e-3)
+    assert st["status"] == pfnks.PFNKS_OK
+    p.close()
