@@ -247,7 +247,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="pf2d_512")
-    ap.add_argument("--pc", default="ras_spectral", choices=["ras_spectral", "ras", "as", "rras"])
+    ap.add_argument("--pc", default="ras_spectral", choices=sorted(pc_names()))
     ap.add_argument("--sweeps", type=int, default=None,
                     help="Gauss-Seidel sweeps of the tile solve (default: workloads.default_sweeps)")
     ap.add_argument("--tile", default=None, help="Schwarz tile, e.g. 32,32 (2D) or 8,8,8 (3D)")
