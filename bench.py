@@ -267,8 +267,8 @@ def main():
     args = ap.parse_args()
     args.steps_given = any(a == "--steps" or a.startswith("--steps=") for a in sys.argv[1:])
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU decomposition is a design note, not built", file=sys.stderr)
+        print(f"bench.py: the solver runs on one GPU (asked for --gpus {args.gpus}); the spatial "
+              "decomposition over several GPUs is described, not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch
