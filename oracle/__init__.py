@@ -23,9 +23,9 @@ of Ni-based alloys system"):
 * the discrete mass <c> (Theorem 3.1/3.2) and the adaptive time-step rule of
   Section 4, eq. (sencondt), with its divergence retry.
 
-Every function is in FP64 (numpy/scipy).  Each function's docstring names the
-passage it follows and, where the paper leaves that passage silent or garbled,
-the reading taken (marked "reading:").
+Every function is in FP64 (numpy/scipy).  Each module's and function's
+docstring names the passage it follows and, where the paper leaves that passage
+silent or garbled, states the reading taken.
 
 Parity status: every part is pinned by the CPU tests in ``tests/test_oracle_*``
 except the adaptive time-step driver, whose sequence of step sizes is pinned
