@@ -86,3 +86,53 @@ def test_workspace_holds_the_tile_setup():
         without = pfnks.workspace_bytes(n, W.H, W.DEFAULT_MODEL, dict(s, pc=pfnks.PC_SPECTRAL))
         pack = 13 * tiles * ext * kb
         assert pack <= with_tiles - without <= pack + 4096
+
+
+def test_create_problem_rejects_on_host():
+    """pfnks_create_problem checks its arguments, the workspace size and the log domain of the
+    initial state (0 < c < 1, 0 < c eta_i < 1 for i = 1..4 with eta_4 = 4 - eta_1 - eta_2 -
+    eta_3) before its first device call.  The workspace address below is 256-aligned and is
+    never dereferenced: every case returns before the device is touched."""
+    if not os.path.exists(LIB):
+        pytest.skip("libpfnks.so not built")
+    from paper_2209_08001_amd import pfnks
+    from paper_2209_08001_amd import workloads as W
+    import numpy as np
+
+    lib = pfnks.load()
+    n = (64, 64)
+    N = n[0] * n[1]
+    g = pfnks.make_grid(n, W.H)
+    m = pfnks.make_model(W.DEFAULT_MODEL)
+    s = pfnks.make_solver(W.DEFAULT_SOLVER, 2)
+    need = pfnks.workspace_bytes(n, W.H, W.DEFAULT_MODEL, W.DEFAULT_SOLVER)
+    fake = ctypes.c_void_p(1 << 30)
+    c0, e0 = W.init_fields(n, 3)
+    c0 = np.ascontiguousarray(c0, dtype=np.float64).ravel()
+    e0 = np.ascontiguousarray(e0, dtype=np.float64).ravel()
+
+    def create(c, e, ws=fake, nbytes=need):
+        out = ctypes.c_void_p(12345)
+        st = lib.pfnks_create_problem(ctypes.byref(g), ctypes.byref(m), ctypes.byref(s),
+                                      None if c is None else pfnks._dp(c), None if e is None else pfnks._dp(e),
+                                      ws, ctypes.c_size_t(nbytes), None, ctypes.byref(out))
+        return st, out.value
+
+    assert create(None, e0) == (pfnks.PFNKS_EINVAL, 12345)  # out is untouched on a null input
+    assert create(c0, e0, ws=ctypes.c_void_p((1 << 30) + 8)) == (pfnks.PFNKS_EINVAL, None)  # misaligned
+    assert create(c0, e0, nbytes=need - 1) == (pfnks.PFNKS_ENOSPACE, None)
+
+    def bad_c(v):
+        c = c0.copy()
+        c[N // 2] = v
+        return c
+
+    for v in (0.0, 1.0, -0.1, float("nan")):
+        assert create(bad_c(v), e0) == (pfnks.PFNKS_EDOMAIN, None), v
+    e = e0.copy()
+    e[N + 5] = 0.0  # c eta_2 = 0 at one node
+    assert create(c0, e) == (pfnks.PFNKS_EDOMAIN, None)
+    e = e0.copy()
+    c = c0.copy()
+    c[7], e[7], e[N + 7], e[2 * N + 7] = 0.5, 0.4, 0.4, 0.4  # eta_4 = 2.8: c eta_4 = 1.4
+    assert create(c, e) == (pfnks.PFNKS_EDOMAIN, None)

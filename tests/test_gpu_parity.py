@@ -461,6 +461,33 @@ def test_enoconv_leaves_state():
     p.close()
 
 
+def test_set_state_rejects_out_of_domain():
+    """pfnks_set_state refuses a state outside the log domain with EDOMAIN and leaves the
+    problem's state and time as they were; a state inside it is taken exactly."""
+    from paper_2209_08001_amd import pfnks
+
+    _cuda()
+    _note("set_state domain check")
+    n = (32, 32)
+    c0, e0 = W.init_fields(n, 37)
+    p = _problem(n, c0, e0)
+    X0, t0 = p.get_state()
+    for f, v in ((0, 1.0), (0, 0.0), (2, 0.0)):
+        bad = X0.copy()
+        bad[f].flat[100] = v
+        with pytest.raises(pfnks.PfnksError) as ei:
+            p.set_state(bad, 3.0)
+        assert ei.value.status == pfnks.PFNKS_EDOMAIN, (f, v)
+        X1, t1 = p.get_state()
+        assert np.array_equal(X0, X1) and t1 == t0
+    good = X0.copy()
+    good[0] *= 0.999
+    p.set_state(good, 2.5)
+    X2, t2 = p.get_state()
+    assert np.array_equal(X2, good) and t2 == 2.5
+    p.close()
+
+
 @pytest.fixture(scope="module")
 def oracle_3d():
     n = (8, 8, 8)
