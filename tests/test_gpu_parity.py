@@ -526,6 +526,29 @@ def test_step_parity_3d(oracle_3d, pc, prec):
     p.close()
 
 
+@pytest.mark.parametrize("n,tile", [((4, 4), (2, 2, 1)), ((4, 16), (2, 4, 1)), ((4, 4, 4), (2, 2, 2))])
+def test_step_parity_smallest_grids(n, tile):
+    """The smallest grids the library accepts (sides of 4: the least power of two with even
+    parity classes), tiles of 2 with overlap 1 (each extended tile spans the whole periodic
+    axis of 4), and in 3D the general Fourier path (x side below 8): two steps within 1e-8 of
+    the oracle's root, mass conserved."""
+    _cuda()
+    c0, e0 = W.init_fields(n, 41)
+    o = Oracle(n, W.H, W.DEFAULT_MODEL, c0, e0)
+    _note(f"step parity smallest grid n={n} tile={tile}")
+    p = _problem(n, c0, e0, tile=tile, overlap=1, newton_rtol=ROOT_RTOL)
+    m0 = p.mass()
+    for k, dt in enumerate((0.01, 0.05)):
+        o.step(dt)
+        st = p.step(dt)
+        X, _ = p.get_state()
+        errs = [_relmax(X[f], o.X[f]) for f in range(X.shape[0])]
+        _note(f"  step {k}: newton={st['newton_its']} gmres={st['gmres_its']} max err={max(errs):.2e}")
+        assert max(errs) <= 1e-8, (k, errs)
+        assert abs(st["mass"] - m0) <= 1e-13 * abs(m0)
+    p.close()
+
+
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 @pytest.mark.parametrize("wl", ["pf2d_512", "pf3d_128"])
 def test_full_size_first_step_root(wl, prec):
