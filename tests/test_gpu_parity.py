@@ -549,6 +549,30 @@ def test_step_parity_smallest_grids(n, tile):
     p.close()
 
 
+@pytest.mark.parametrize("n,tile,dts", [((2048, 4), (32, 2, 1), (0.01,)), ((8, 4, 16), (4, 2, 4), (0.01, 0.05)),
+                                         ((16, 8, 4), (8, 4, 2), (0.01, 0.05))])
+def test_step_parity_unequal_sides(n, tile, dts):
+    """Grids with unequal sides: 2048 x 4 (a side above 1024, so the preconditioner's Fourier
+    solve takes the general path inside every GMRES iteration), and 8 x 4 x 16 and 16 x 8 x 4
+    (the real-to-complex 3D path with three different sides, non-cubic tiles): within 1e-8 of
+    the oracle's root, mass conserved."""
+    _cuda()
+    c0, e0 = W.init_fields(n, 43)
+    o = Oracle(n, W.H, W.DEFAULT_MODEL, c0, e0)
+    _note(f"step parity unequal sides n={n} tile={tile}")
+    p = _problem(n, c0, e0, tile=tile, overlap=1, newton_rtol=ROOT_RTOL)
+    m0 = p.mass()
+    for k, dt in enumerate(dts):
+        o.step(dt)
+        st = p.step(dt)
+        X, _ = p.get_state()
+        errs = [_relmax(X[f], o.X[f]) for f in range(X.shape[0])]
+        _note(f"  step {k}: newton={st['newton_its']} gmres={st['gmres_its']} max err={max(errs):.2e}")
+        assert max(errs) <= 1e-8, (k, errs)
+        assert abs(st["mass"] - m0) <= 1e-13 * abs(m0)
+    p.close()
+
+
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 @pytest.mark.parametrize("wl", ["pf2d_512", "pf3d_128"])
 def test_full_size_first_step_root(wl, prec):
