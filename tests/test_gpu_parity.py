@@ -526,47 +526,70 @@ def test_step_parity_3d(oracle_3d, pc, prec):
     p.close()
 
 
+_TRAJ = {}
+
+
+def _oracle_traj(n, seed, dts):
+    """The oracle's roots X^1, X^2, ... from the seeded fields, computed once per case."""
+    key = (tuple(n), seed, tuple(dts))
+    if key not in _TRAJ:
+        c0, e0 = W.init_fields(n, seed)
+        o = Oracle(n, W.H, W.DEFAULT_MODEL, c0, e0)
+        traj = []
+        for dt in dts:
+            o.step(dt)
+            traj.append(o.X.copy())
+        _TRAJ[key] = traj
+    return _TRAJ[key]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
 @pytest.mark.parametrize("n,tile", [((4, 4), (2, 2, 1)), ((4, 16), (2, 4, 1)), ((4, 4, 4), (2, 2, 2))])
-def test_step_parity_smallest_grids(n, tile):
+def test_step_parity_smallest_grids(n, tile, prec):
     """The smallest grids the library accepts (sides of 4: the least power of two with even
     parity classes), tiles of 2 with overlap 1 (each extended tile spans the whole periodic
     axis of 4), and in 3D the general Fourier path (x side below 8): two steps within 1e-8 of
     the oracle's root, mass conserved."""
     _cuda()
     c0, e0 = W.init_fields(n, 41)
-    o = Oracle(n, W.H, W.DEFAULT_MODEL, c0, e0)
-    _note(f"step parity smallest grid n={n} tile={tile}")
-    p = _problem(n, c0, e0, tile=tile, overlap=1, newton_rtol=ROOT_RTOL)
+    traj = _oracle_traj(n, 41, (0.01, 0.05))
+    from paper_2209_08001_amd import pfnks
+
+    _note(f"step parity smallest grid n={n} tile={tile} precision={prec}")
+    p = _problem(n, c0, e0, tile=tile, overlap=1, newton_rtol=ROOT_RTOL,
+                 precision=pfnks.MIXED if prec == "mixed" else pfnks.FP64)
     m0 = p.mass()
     for k, dt in enumerate((0.01, 0.05)):
-        o.step(dt)
         st = p.step(dt)
         X, _ = p.get_state()
-        errs = [_relmax(X[f], o.X[f]) for f in range(X.shape[0])]
+        errs = [_relmax(X[f], traj[k][f]) for f in range(X.shape[0])]
         _note(f"  step {k}: newton={st['newton_its']} gmres={st['gmres_its']} max err={max(errs):.2e}")
         assert max(errs) <= 1e-8, (k, errs)
         assert abs(st["mass"] - m0) <= 1e-13 * abs(m0)
     p.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
 @pytest.mark.parametrize("n,tile,dts", [((2048, 4), (32, 2, 1), (0.01,)), ((8, 4, 16), (4, 2, 4), (0.01, 0.05)),
                                          ((16, 8, 4), (8, 4, 2), (0.01, 0.05))])
-def test_step_parity_unequal_sides(n, tile, dts):
+def test_step_parity_unequal_sides(n, tile, dts, prec):
     """Grids with unequal sides: 2048 x 4 (a side above 1024, so the preconditioner's Fourier
     solve takes the general path inside every GMRES iteration), and 8 x 4 x 16 and 16 x 8 x 4
     (the real-to-complex 3D path with three different sides, non-cubic tiles): within 1e-8 of
     the oracle's root, mass conserved."""
     _cuda()
     c0, e0 = W.init_fields(n, 43)
-    o = Oracle(n, W.H, W.DEFAULT_MODEL, c0, e0)
-    _note(f"step parity unequal sides n={n} tile={tile}")
-    p = _problem(n, c0, e0, tile=tile, overlap=1, newton_rtol=ROOT_RTOL)
+    traj = _oracle_traj(n, 43, dts)
+    from paper_2209_08001_amd import pfnks
+
+    _note(f"step parity unequal sides n={n} tile={tile} precision={prec}")
+    p = _problem(n, c0, e0, tile=tile, overlap=1, newton_rtol=ROOT_RTOL,
+                 precision=pfnks.MIXED if prec == "mixed" else pfnks.FP64)
     m0 = p.mass()
     for k, dt in enumerate(dts):
-        o.step(dt)
         st = p.step(dt)
         X, _ = p.get_state()
-        errs = [_relmax(X[f], o.X[f]) for f in range(X.shape[0])]
+        errs = [_relmax(X[f], traj[k][f]) for f in range(X.shape[0])]
         _note(f"  step {k}: newton={st['newton_its']} gmres={st['gmres_its']} max err={max(errs):.2e}")
         assert max(errs) <= 1e-8, (k, errs)
         assert abs(st["mass"] - m0) <= 1e-13 * abs(m0)
