@@ -529,12 +529,13 @@ def test_step_parity_3d(oracle_3d, pc, prec):
 _TRAJ = {}
 
 
-def _oracle_traj(n, seed, dts):
+def _oracle_traj(n, seed, dts, model=None):
     """The oracle's roots X^1, X^2, ... from the seeded fields, computed once per case."""
-    key = (tuple(n), seed, tuple(dts))
+    model = model or W.DEFAULT_MODEL
+    key = (tuple(n), seed, tuple(dts), repr(sorted(model.items())))
     if key not in _TRAJ:
         c0, e0 = W.init_fields(n, seed)
-        o = Oracle(n, W.H, W.DEFAULT_MODEL, c0, e0)
+        o = Oracle(n, W.H, model, c0, e0)
         traj = []
         for dt in dts:
             o.step(dt)
@@ -593,6 +594,39 @@ def test_step_parity_unequal_sides(n, tile, dts, prec):
         _note(f"  step {k}: newton={st['newton_its']} gmres={st['gmres_its']} max err={max(errs):.2e}")
         assert max(errs) <= 1e-8, (k, errs)
         assert abs(st["mass"] - m0) <= 1e-13 * abs(m0)
+    p.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("lscale", [0.0, 5.0])
+def test_step_parity_elastic_scale(lscale, prec):
+    """The elastic constants scaled by 0 (no elasticity: the displacement rows reduce to
+    u = 0) and by 5, the ends of the range of Section 5.1: two steps on 32 x 32 within 1e-8
+    of the oracle's root; without elasticity the displacement stays exactly zero and so does
+    the elastic energy."""
+    from paper_2209_08001_amd import pfnks
+
+    _cuda()
+    n = (32, 32)
+    model = dict(W.DEFAULT_MODEL, Lscale=lscale)
+    c0, e0 = W.init_fields(n, 47)
+    traj = _oracle_traj(n, 47, (0.01, 0.05), model)
+    _note(f"step parity elastic scale {lscale} precision={prec}")
+    p = _problem(n, c0, e0, model=model, newton_rtol=ROOT_RTOL,
+                 precision=pfnks.MIXED if prec == "mixed" else pfnks.FP64)
+    m0 = p.mass()
+    for k, dt in enumerate((0.01, 0.05)):
+        st = p.step(dt)
+        X, _ = p.get_state()
+        errs = [_relmax(X[f], traj[k][f]) for f in range(4)]
+        if lscale != 0.0:
+            errs += [_relmax(X[f], traj[k][f]) for f in range(4, X.shape[0])]
+        _note(f"  step {k}: newton={st['newton_its']} gmres={st['gmres_its']} max err={max(errs):.2e}")
+        assert max(errs) <= 1e-8, (k, errs)
+        assert abs(st["mass"] - m0) <= 1e-13 * abs(m0)
+        if lscale == 0.0:
+            assert np.all(X[4:] == 0.0) and np.all(traj[k][4:] == 0.0)
+            assert p.energy()[1][1] == 0.0
     p.close()
 
 
