@@ -73,8 +73,37 @@ def percentile(xs, q):
     return s[f] + (s[c] - s[f]) * (k - f)
 
 
-def cpu_baseline(wl_name, budget_s=30.0):
-    """The CPU oracle (sparse LU Newton, one process) on a bounded sample of the workload."""
+def host_info():
+    """The host the CPU oracle runs on: CPU model, logical CPUs, CPUs this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = None
+    return {"cpu_model": model, "os_cpu_count": os.cpu_count(), "usable_cpus": usable}
+
+
+def _timed_oracle_step(o, dt):
+    """(wall s, process CPU s) of one oracle step."""
+    t0, c0 = time.perf_counter(), time.process_time()
+    o.step(dt)
+    return time.perf_counter() - t0, time.process_time() - c0
+
+
+def cpu_baseline(wl_name):
+    """The CPU oracle (sparse-LU Newton, one process) on a bounded sample of the workload: the
+    first step (dt = dt_min) of the seeded trajectory on 32^2, 48^2 and 64^2, and on 64^2 one more
+    step at dt_max (the step size of the late trajectory, where most of the workload's steps
+    are taken).  The per-step time at the workload's size is extrapolated by the power law
+    fitted to the three first-step times, applied to the late step."""
     import numpy as np
 
     from oracle import Oracle
@@ -83,39 +112,175 @@ def cpu_baseline(wl_name, budget_s=30.0):
     wl = W.WORKLOADS[wl_name]
     sizes = [32, 48, 64]
     times = []
-    used = []
-    t_all = time.perf_counter()
     wall = cpu = 0.0
+    o = None
     for s in sizes:
         n = (s, s)
         c0, e0 = W.init_fields(n, wl["seed"], cbar=wl["cbar"])
         o = Oracle(n, W.H, W.DEFAULT_MODEL, c0, e0)
-        t0, c0_cpu = time.perf_counter(), time.process_time()
-        o.step(wl.get("dt_min", wl.get("dt")))
-        times.append(time.perf_counter() - t0)
-        wall += times[-1]
-        cpu += time.process_time() - c0_cpu
-        used.append(s * s)
-        if time.perf_counter() - t_all > budget_s:
-            break
-    # power-law fit t = a N^b over the sampled sizes, evaluated at the workload's size
-    lx = np.log(np.array(used, float))
-    ly = np.log(np.array(times))
-    b, a = np.polyfit(lx, ly, 1) if len(used) > 1 else (1.0, ly[0] - lx[0])
-    Nw = float(np.prod(wl["n"]))
-    t_w = math.exp(a) * Nw ** b
-    # threads actually used: process CPU time over wall time of the timed solves
+        w_, c_ = _timed_oracle_step(o, wl["dt_min"])
+        times.append(w_)
+        wall += w_
+        cpu += c_
+    t_late, c_ = _timed_oracle_step(o, wl["dt_max"])  # from the 64^2 state after its first step
+    wall += t_late
+    cpu += c_
+    lx = np.log(np.array([s * s for s in sizes], float))
+    b, a = np.polyfit(lx, np.log(np.array(times)), 1)
+    scale = (float(np.prod(wl["n"])) / (64.0 * 64.0)) ** b
+    t_w = t_late * scale
     threads = max(1, round(cpu / wall)) if wall > 0 else 1
-    return {
+    out = {
         "value": 1.0 / t_w,
         "unit": "steps/s",
         "cores": threads,
         "cpu_time_over_wall": cpu / wall if wall > 0 else None,
         "kind": "oracle",
-        "sample": (f"first step (dt = dt_min) of the seeded trajectory on {', '.join(f'{s}x{s}' for s in sizes[:len(used)])} "
-                   f"(measured {', '.join(f'{t:.2f}' for t in times)} s), extrapolated to {wl['n'][0]}x{wl['n'][1]} "
-                   f"by the fitted N^{b:.2f} law of the sparse-LU Newton solve"),
+        "extrapolated": True,
+        "sample": (f"first step (dt = {wl['dt_min']}) of the seeded trajectory on 32x32, 48x48, 64x64 "
+                   f"(measured {', '.join(f'{t:.2f}' for t in times)} s) and one 64x64 step at dt = {wl['dt_max']} "
+                   f"({t_late:.2f} s); the late step scaled to {wl['n'][0]}x{wl['n'][1]} by the fitted "
+                   f"N^{b:.2f} law of the sparse-LU Newton solve"),
     }
+    out.update(host_info())
+    return out
+
+
+def _solver_for(W, pfnks, n, precision, pc, sweeps=None):
+    mixed = precision == "mixed"
+    sv = dict(W.DEFAULT_SOLVER, sweeps=sweeps or W.default_sweeps(len(n), mixed), pc=pc,
+              precision=pfnks.MIXED if mixed else pfnks.FP64)
+    if len(n) == 3:
+        sv.update(tile=tuple(W.tile_side(s, 8, 1) for s in n), overlap=1)
+    else:
+        sv["tile"] = (W.tile_side(n[0], 32, sv["overlap"]), W.tile_side(n[1], 32, sv["overlap"]), 1)
+    return sv
+
+
+def run_c1(dev):
+    """2D 64 x 64, 10 fixed steps of dt = 1e-2, FP64: per-step latency, the error of every step
+    against the oracle's root, and the oracle's own 10 steps timed on the host."""
+    import numpy as np
+    import torch
+
+    from oracle import Oracle
+    from paper_2209_08001_amd import pfnks
+    from paper_2209_08001_amd import workloads as W
+
+    wl = W.WORKLOADS["pf2d_64"]
+    n, dt, steps = wl["n"], wl["dt"], wl["steps"]
+    c0, e0 = W.init_fields(n, wl["seed"], cbar=wl["cbar"])
+    sv = _solver_for(W, pfnks, n, "fp64", pfnks.PC_RAS_SPECTRAL)
+    pw = pfnks.Problem(n, W.H, W.DEFAULT_MODEL, sv, c0, e0, device=dev)
+    for _ in range(3):
+        pw.step(dt)
+    pw.close()
+    p = pfnks.Problem(n, W.H, W.DEFAULT_MODEL, sv, c0, e0, device=dev)
+    lat, stats = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        t1 = time.perf_counter()
+        stats.append(p.step(dt))
+        lat.append(time.perf_counter() - t1)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    p.close()
+    # the same steps again (the path is deterministic) with the state read after each step
+    q = pfnks.Problem(n, W.H, W.DEFAULT_MODEL, sv, c0, e0, device=dev)
+    states = []
+    for _ in range(steps):
+        q.step(dt)
+        states.append(q.get_state()[0])
+    q.close()
+    o = Oracle(n, W.H, W.DEFAULT_MODEL, c0, e0)
+    wall = cpu = 0.0
+    errs = []
+    for k in range(steps):
+        w_, c_ = _timed_oracle_step(o, dt)
+        wall += w_
+        cpu += c_
+        errs.append(max(float(np.max(np.abs(states[k][f] - o.X[f])) / np.max(np.abs(o.X[f])))
+                        for f in range(o.X.shape[0])))
+    return {
+        "workload": "pf2d_64", "grid": list(n), "precision": "fp64", "dt": dt, "steps": steps,
+        "steps_per_s": steps / elapsed,
+        "p50_step_ms": 1e3 * percentile(lat, 50), "p99_step_ms": 1e3 * percentile(lat, 99),
+        "newton_per_step": sum(s["newton_its"] for s in stats) / steps,
+        "gmres_per_newton": sum(s["gmres_its"] for s in stats) / max(1, sum(s["newton_its"] for s in stats)),
+        "max_rel_err_vs_oracle": max(errs),
+        "rel_err_vs_oracle_per_step": [float("%.3g" % e) for e in errs],
+        "oracle": {"value": steps / wall, "unit": "steps/s", "cores": max(1, round(cpu / wall)),
+                   "cpu_time_over_wall": cpu / wall, "kind": "oracle",
+                   "sample": f"the full {steps} steps, sparse-LU Newton", **host_info()},
+        "note": "cache-resident (197 KB per vector): launch- and latency-bound, reported by latency",
+    }
+
+
+def run_c3(dev, steps=10, warmup=2):
+    """3D 128^3, the adaptive trajectory from t = 0: plain FP64 and mixed precision (float
+    Krylov basis and preconditioner) over the same step sizes (the mixed run replays the FP64
+    run's dt sequence), each with its dominant kernel's roofline, and the largest relative
+    difference between the two final states."""
+    import numpy as np
+    import torch
+
+    from paper_2209_08001_amd import pfnks
+    from paper_2209_08001_amd import workloads as W
+    from paper_2209_08001_amd.driver import adaptive_run
+
+    wl = W.WORKLOADS["pf3d_128"]
+    n = wl["n"]
+    c0, e0 = W.init_fields(n, wl["seed"], cbar=wl["cbar"])
+    out = {"workload": "pf3d_128", "grid": list(n), "steps": steps}
+    dts = None
+    final = {}
+    for prec in ("fp64", "mixed"):
+        sv = _solver_for(W, pfnks, n, prec, pfnks.PC_RAS_SPECTRAL)
+        pw = pfnks.Problem(n, W.H, W.DEFAULT_MODEL, sv, c0, e0, device=dev)
+        adaptive_run(pw, 1, wl)
+        pw.profile(True)
+        adaptive_run(pw, warmup, wl)
+        table = pw.kernel_table()
+        dominant = max(table, key=lambda k: table[k]["total_ms"])
+        pw.close()
+        del pw
+        p = pfnks.Problem(n, W.H, W.DEFAULT_MODEL, sv, c0, e0, device=dev)
+        p.profile([dominant])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if dts is None:
+            lat, stats = adaptive_run(p, steps, wl)
+            dts = [s["dt"] for s in stats]
+        else:
+            lat, stats = [], []
+            for dt in dts:
+                t1 = time.perf_counter()
+                stats.append(p.step(dt))
+                lat.append(time.perf_counter() - t1)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        roof = p.roofline(HBM_PEAK_GBS)
+        traffic, summary = measured_traffic(roof["kernel"], "pf3d_128", prec, sv["tile"], sv["overlap"])
+        roof["traffic"] = traffic
+        if traffic is not None:
+            roof["traffic_over_algorithmic"] = traffic / roof["bytes_per_launch"]
+            roof["traffic_source"] = summary
+        final[prec] = p.get_state()[0]
+        p.close()
+        newton = sum(s["newton_its"] for s in stats)
+        out[prec] = {
+            "steps_per_s": steps / elapsed, "ms_per_step": 1e3 * elapsed / steps,
+            "p50_step_ms": 1e3 * percentile(lat, 50), "p99_step_ms": 1e3 * percentile(lat, 99),
+            "newton_per_step": newton / steps, "gmres_per_newton": sum(s["gmres_its"] for s in stats) / max(newton, 1),
+            "tile": list(sv["tile"]), "overlap": sv["overlap"], "gs_sweeps": sv["sweeps"], "roofline": roof,
+        }
+    out["dts"] = [float("%.4g" % d) for d in dts]
+    out["mixed_vs_fp64_max_rel_diff"] = max(
+        float(np.max(np.abs(final["mixed"][f] - final["fp64"][f])) / np.max(np.abs(final["fp64"][f])))
+        for f in range(final["fp64"].shape[0]))
+    out["mixed_speedup"] = out["mixed"]["steps_per_s"] / out["fp64"]["steps_per_s"]
+    return out
 
 
 def run_ensemble(args, wl):
@@ -202,7 +367,8 @@ def run_serving(args, wl):
                   precision=pfnks.MIXED if args.precision == "mixed" else pfnks.FP64)
     free, _ = torch.cuda.mem_get_info()
     budget = int(0.8 * free)
-    mk = lambda seed: poisson_requests(wl["rate"], wl["window"], seed, wl["sides2d"], wl["sides3d"],
+    window = args.window if args.window is not None else wl["window"]
+    mk = lambda seed: poisson_requests(wl["rate"], window, seed, wl["sides2d"], wl["sides3d"],
                                        wl["frac3d"], args.steps if args.steps_given else wl["steps"])
     if args.warmup > 0:
         Server(solver, wl, budget, threads=args.threads).run(mk(wl["seed"] + 1000)[:4], realtime=False)
@@ -229,7 +395,7 @@ def run_serving(args, wl):
         "dtype": "f64" if args.precision == "fp64" else "f64+f32",
         "data": "synthetic",
         "config": {"workload": args.workload, "requests": len(reqs), "rate_per_s": wl["rate"],
-                   "window_s": wl["window"], "steps_per_request": reqs[0].steps if reqs else 0,
+                   "window_s": window, "steps_per_request": reqs[0].steps if reqs else 0,
                    "hbm_budget_bytes": budget, "precision": args.precision, "host_threads": args.threads},
         "makespan_s": makespan,
         "p50_step_ms": percentile(lat, 50),
@@ -258,9 +424,14 @@ def main():
                     help="mixed: float Krylov basis and Schwarz/Fourier preconditioner, double "
                          "residual, J v arithmetic, Newton update, energy and mass")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-c1", action="store_true", help="default workload: skip the 64 x 64 fixed-step object")
+    ap.add_argument("--no-c3", action="store_true", help="default workload: skip the 128^3 FP64 / mixed object")
+    ap.add_argument("--c3-steps", type=int, default=10)
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--threads", type=int, default=16,
                     help="ensemble workloads: host threads driving the instances (pfnks_batch_step)")
+    ap.add_argument("--window", type=float, default=None,
+                    help="serving workload: arrival window in seconds (default: the workload's)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="before the run, copy a device buffer of this many MiB once (a plain copy "
                          "kernel of known size, to scale the FETCH_SIZE / WRITE_SIZE counters)")
@@ -373,6 +544,7 @@ def main():
             "autotuned": tuned,
             "gmres_restart": solver["gmres_restart"],
             "newton_rtol": solver["newton_rtol"],
+            "newton_stol": solver["newton_stol"],
             "gmres_rtol": solver["gmres_rtol"],
         },
         "p50_step_ms": 1e3 * percentile(lat, 50),
@@ -400,6 +572,11 @@ def main():
             roof["traffic_source"] = summary
         out["roofline"] = roof
     p.close()
+    default_line = args.workload == "pf2d_512" and args.precision == "fp64" and args.pc == "ras_spectral"
+    if default_line and not args.no_c3:
+        out["c3"] = run_c3(dev, steps=args.c3_steps)
+    if default_line and not args.no_c1:
+        out["c1"] = run_c1(dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(out))

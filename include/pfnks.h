@@ -68,7 +68,8 @@ typedef enum {
 
 typedef struct {
   int dim;      /* 2 or 3                                                     */
-  int n[3];     /* nodes per direction (n[2] = 1 when dim == 2); even sizes  */
+  int n[3];     /* nodes per direction (n[2] = 1 when dim == 2): even, >= 4, and
+                   products of 2, 3, 5, 7, 11 and 13 (the radices of the Fourier solve) */
   double h;     /* grid spacing; periodic box of side n[k]*h                  */
 } pfnks_grid;
 
@@ -90,7 +91,7 @@ typedef struct {
 } pfnks_model;
 
 typedef struct {
-  double newton_rtol;     /* eps_r: stop when ||F|| <= max(eps_r ||F(X0)||, eps_a)          */
+  double newton_rtol;     /* eps_r of the relative residual test ||F|| <= eps_r ||F(X0)||     */
   double newton_atol_rms; /* eps_a per unknown: eps_a = newton_atol_rms * sqrt(#unknowns)     */
   int newton_maxit;       /* Newton iterations before PFNKS_ENOCONV                         */
   double gmres_rtol;      /* xi_r: ||J S + F|| <= max(xi_r ||F||, xi_a)                     */
@@ -104,6 +105,11 @@ typedef struct {
   pfnks_precision precision; /* PFNKS_FP64, or PFNKS_MIXED (float Krylov basis and preconditioner) */
   double ls_alpha;        /* Armijo constant of the backtracking line search                */
   int ls_max_halvings;    /* halvings of lambda before the step is declared failed          */
+  double newton_stol;     /* update test of the Newton stop: besides the residual test, the
+                             error left by the last accepted correction, estimated from the
+                             contraction theta of consecutive corrections as
+                             theta / (1 - theta) max|lambda S_f|, must be <= newton_stol *
+                             max|X_f| in every field f (0 = residual test only) */
 } pfnks_solver;
 
 typedef struct {
@@ -114,13 +120,17 @@ typedef struct {
   double energy;          /* discrete energy E~^{n+1}                   */
   double energy_parts[3]; /* chemical, elastic, interfacial             */
   double mass;            /* <c^{n+1}> = h^d sum c                      */
+  double update_rel;      /* the update test's error estimate of the last iteration, relative
+                             to max|X_f|, largest over the fields (0 when no iteration ran;
+                             infinite after a single iteration, which has no estimate)   */
 } pfnks_step_stats;
 
 typedef struct pfnks_problem pfnks_problem;
 
 /* Bytes of device workspace a problem of this shape needs (device memory the caller owns).
- * Errors: PFNKS_EINVAL for a null pointer, dim not 2 or 3, an odd or non-positive size, a
- * tile that does not divide the grid, overlap or restart out of range. */
+ * Errors: PFNKS_EINVAL for a null pointer, dim not 2 or 3, a size that is odd, below 4 or has
+ * a prime factor above 13, a tile that does not divide the grid, overlap or restart out of
+ * range. */
 int pfnks_workspace_bytes(const pfnks_grid* grid, const pfnks_model* model,
                           const pfnks_solver* solver, size_t* bytes);
 
@@ -140,7 +150,10 @@ int pfnks_create_problem(const pfnks_grid* grid, const pfnks_model* model,
 
 /* One step of scheme (NSOA-1) with step size dt (Section 3), solved by the Newton-Krylov-
  * Schwarz method of Section 4 from X_0 = X^n.  The c-part of every Newton update is
- * projected so that the total mass is exactly that of X^n (Theorem 3.2, item 1).  On
+ * projected so that the total mass is exactly that of X^n (Theorem 3.2, item 1).  Newton
+ * stops when ||F|| <= eps_a, or when ||F|| <= eps_r ||F(X_0)|| (the relative test of Section
+ * 4) and the last accepted correction passes the update test of solver.newton_stol (the
+ * residual test alone bounds the distance to the root only through ||J^{-1}||).  On
  * success the state becomes X^{n+1}, t += dt, and stats (may be NULL) is filled.
  * On PFNKS_ENOCONV the state is unchanged (the adaptive driver of Section 4 retries
  * with a smaller dt).  Errors: PFNKS_EINVAL (dt <= 0), PFNKS_ENOCONV, PFNKS_EDEVICE. */
@@ -153,7 +166,8 @@ int pfnks_step(pfnks_problem* p, double dt, pfnks_step_stats* stats);
  * once (a handle is not used by two threads).  stats (may be NULL) and status (may be NULL)
  * receive k records.  Each problem's result is bitwise the result of pfnks_step on it alone.
  * Returns PFNKS_OK when every step succeeded, else the status of the first failing index
- * (PFNKS_ENOCONV steps leave their problem unchanged, the others advance).
+ * (PFNKS_ENOCONV steps leave their problem unchanged, the others advance); when that status is
+ * PFNKS_EDEVICE, pfnks_last_error() on the calling thread gives the failing problem's text.
  * Errors: PFNKS_EINVAL (null arrays, k < 0, a handle given twice). */
 int pfnks_batch_step(pfnks_problem* const* problems, int k, const double* dts, int threads,
                      pfnks_step_stats* stats, int* status);

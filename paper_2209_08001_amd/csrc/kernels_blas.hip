@@ -37,6 +37,20 @@ __device__ inline double block_sum(double v, double* lds) {
   return r;  // valid in thread 0
 }
 
+// Maximum of one non-negative value over the workgroup (valid in thread 0).
+__device__ inline double block_max(double v, double* lds) {
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) lds[wave] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) {
+    for (int w = 0; w < kThreads / 64; ++w) r = fmax(r, lds[w]);
+  }
+  return r;
+}
+
 template <int MAXV, typename T>
 __global__ __launch_bounds__(kThreads) void k_multidot(long long n, int nv, const T* __restrict__ V,
                                                        long long ldv, const double* __restrict__ w,
@@ -177,6 +191,26 @@ __global__ __launch_bounds__(kRedBlocks) void k_finalize(const double* __restric
   }
 }
 
+// The same second stage for per-block maxima of non-negative values.
+constexpr int kMaxVals = 16;
+__global__ __launch_bounds__(kRedBlocks) void k_finalize_max(const double* __restrict__ partial, int nvals,
+                                                             double* __restrict__ out, double* __restrict__ out2) {
+  __shared__ double wl[kRedBlocks / 64][kMaxVals];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int v = 0; v < nvals; ++v) {
+    double x = partial[v * kRedBlocks + threadIdx.x];
+    for (int off = 32; off > 0; off >>= 1) x = fmax(x, __shfl_down(x, off, 64));
+    if (lane == 0) wl[wave][v] = x;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < nvals) {
+    double x = 0.0;
+    for (int w = 0; w < kRedBlocks / 64; ++w) x = fmax(x, wl[w][threadIdx.x]);
+    out[threadIdx.x] = x;
+    if (out2) out2[threadIdx.x] = x;
+  }
+}
+
 // sum of x, and sum of (y - yn): the two means of the mass projection of a Newton update
 __global__ __launch_bounds__(kThreads) void k_sum2(long long n, const double* __restrict__ x,
                                                    const double* __restrict__ y,
@@ -199,34 +233,63 @@ __global__ __launch_bounds__(kThreads) void k_sum2(long long n, const double* __
 
 // Trial point of the line search, X_t = X + lam (S + shift e_c), with the log-domain check
 // 0 < c < 1, 0 < c eta_i < 1 (i = 1..4, eta_4 = 4 - eta_1 - eta_2 - eta_3).
+// pmax (may be null): per-block maxima of |S_f + shift_f| and |X_f| of every field f, for the
+// update test of the Newton stop (values 2 f and 2 f + 1, kRedBlocks apart).
 __global__ __launch_bounds__(kThreads) void k_trial(long long N, int nf, const double* __restrict__ X,
                                                     const double* __restrict__ S, double lam,
                                                     const double* __restrict__ msums, double* __restrict__ Xt,
-                                                    double* __restrict__ partial) {
+                                                    double* __restrict__ partial, double* __restrict__ pmax) {
   __shared__ double lds[kThreads / 64];
   // mass projection of the update: shift = -(sum S_c + sum (c - c^n)) / N, from the device sums
   const double shift = -(msums[0] + msums[1]) / (double)N;
   double bad = 0.0;
+  double ms[7] = {0, 0, 0, 0, 0, 0, 0}, mx[7] = {0, 0, 0, 0, 0, 0, 0};
   for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < N;
        e += (long long)gridDim.x * kThreads) {
-    const double c = X[e] + lam * (S[e] + shift);
+    const double sc = S[e] + shift, xc = X[e];
+    const double c = xc + lam * sc;
     Xt[e] = c;
+    ms[0] = fmax(ms[0], fabs(sc));
+    mx[0] = fmax(mx[0], fabs(xc));
     double esum = 0.0;
     double prod_ok = (c > 0.0 && c < 1.0) ? 1.0 : 0.0;
+#pragma unroll
     for (int p = 1; p <= 3; ++p) {
-      const double ep = X[p * N + e] + lam * S[p * N + e];
+      const double sp = S[p * N + e], xp = X[p * N + e];
+      const double ep = xp + lam * sp;
       Xt[p * N + e] = ep;
+      ms[p] = fmax(ms[p], fabs(sp));
+      mx[p] = fmax(mx[p], fabs(xp));
       esum += ep;
       const double y = c * ep;
       if (!(y > 0.0 && y < 1.0)) prod_ok = 0.0;
     }
     const double y4 = c * (4.0 - esum);
     if (!(y4 > 0.0 && y4 < 1.0)) prod_ok = 0.0;
-    for (int f = 4; f < nf; ++f) Xt[f * N + e] = X[f * N + e] + lam * S[f * N + e];
+#pragma unroll
+    for (int f = 4; f < 7; ++f) {
+      if (f < nf) {
+        const double sf = S[f * N + e], xf = X[f * N + e];
+        Xt[f * N + e] = xf + lam * sf;
+        ms[f] = fmax(ms[f], fabs(sf));
+        mx[f] = fmax(mx[f], fabs(xf));
+      }
+    }
     bad += 1.0 - prod_ok;
   }
   double s = block_sum(bad, lds);
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
+  if (pmax) {
+#pragma unroll
+    for (int f = 0; f < 7; ++f) {
+      if (f < nf) {
+        const double a = block_max(ms[f], lds);
+        if (threadIdx.x == 0) pmax[(2 * f) * kRedBlocks + blockIdx.x] = a;
+        const double b = block_max(mx[f], lds);
+        if (threadIdx.x == 0) pmax[(2 * f + 1) * kRedBlocks + blockIdx.x] = b;
+      }
+    }
+  }
 }
 
 __global__ __launch_bounds__(kThreads) void k_dx2(long long n, const double* __restrict__ X,
@@ -373,15 +436,19 @@ void launch_finalize(const double* partial, int nvals, double* out, hipStream_t 
 #undef F
 }
 
+void launch_finalize_max(const double* partial, int nvals, double* out, hipStream_t s, double* out2) {
+  hipLaunchKernelGGL(k_finalize_max, dim3(1), dim3(kRedBlocks), 0, s, partial, nvals, out, out2);
+}
+
 void launch_sum2(long long n, const double* x, const double* y, const double* yn, double* partial,
                  hipStream_t s) {
   hipLaunchKernelGGL(k_sum2, dim3(kRedBlocks), dim3(kThreads), 0, s, n, x, y, yn, partial);
 }
 
 void launch_trial(const Consts& K, int nf, const double* X, const double* S, double lam,
-                  const double* msums, double* Xt, double* partial, hipStream_t s) {
+                  const double* msums, double* Xt, double* partial, double* pmax, hipStream_t s) {
   hipLaunchKernelGGL(k_trial, dim3(kRedBlocks), dim3(kThreads), 0, s, K.N, nf, X, S, lam, msums,
-                     Xt, partial);
+                     Xt, partial, pmax);
 }
 
 void launch_dx2(long long n4, const double* X, const double* Xn, double* partial, hipStream_t s) {

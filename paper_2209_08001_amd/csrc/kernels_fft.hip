@@ -10,8 +10,8 @@
 // Modes with every S_J = 0 (the parity-class constants that Dhat annihilates) get u = 0, which
 // is the zero-mean-per-parity-class gauge.
 //
-// Transforms: in-LDS radix-2 decimation-in-time FFTs along one direction at a time, several
-// lines per workgroup, complex double.  Two real fields travel as one complex field
+// Transforms: in-LDS decimation-in-time FFTs along one direction at a time (radix-4 stage
+// pairs, a last radix-2 stage when log2 n is odd), several lines per workgroup, complex double.  Two real fields travel as one complex field
 // (q_1 + i q_2); their spectra are separated with the conjugate-symmetric mirror k -> -k.
 #include "pf_internal.h"
 
@@ -462,6 +462,132 @@ __device__ inline int wrapi(int a, int n) {
   return a;
 }
 
+// ---- mixed-radix lines (sides that are not powers of two) --------------------------------
+// Self-sorting (Stockham) transform of lines of any length n = 4^a 2^b 3^c 5^d 7^e 11^f 13^g:
+// stage s of radix R takes the R points j + t n/R (t < R) of butterfly j, multiplies point t
+// by W_{pR}^{t k} (k = j mod p, p = product of the radices before s), forms their R-point DFT
+// and writes output u to (j - k) R + k + u p, ping-ponging between two LDS buffers; after the
+// last stage the line is in natural order.  W_m^e = tw[e n/m] from the table of W_n^e, e < n,
+// kept in LDS.
+struct MrPlan {
+  int nst;     // stages
+  int r[16];   // radix of each stage
+};
+
+template <int R>
+__device__ inline void mr_butterfly(const double2* src, double2* dst, const double2* tws, int n, int m,
+                                    int p, int j, int inverse) {
+  const int k = j % p;
+  const int tstep = n / (p * R);  // W_{pR}^{t k} = W_n^{t k n/(pR)}
+  double2 x[R];
+#pragma unroll
+  for (int t = 0; t < R; ++t) {
+    double2 v = src[j + t * m];
+    if (t > 0 && k > 0) {
+      double2 w = tws[t * k * tstep];
+      if (inverse) w.y = -w.y;
+      v = cmul(v, w);
+    }
+    x[t] = v;
+  }
+  const int base = (j - k) * R + k;
+  if (R == 2) {
+    dst[base] = make_double2(x[0].x + x[1].x, x[0].y + x[1].y);
+    dst[base + p] = make_double2(x[0].x - x[1].x, x[0].y - x[1].y);
+  } else if (R == 4) {
+    // W_4 = -i (forward) or +i (inverse)
+    const double2 a = make_double2(x[0].x + x[2].x, x[0].y + x[2].y);
+    const double2 b = make_double2(x[0].x - x[2].x, x[0].y - x[2].y);
+    const double2 c = make_double2(x[1].x + x[3].x, x[1].y + x[3].y);
+    const double2 d = make_double2(x[1].x - x[3].x, x[1].y - x[3].y);
+    // -i d (forward), +i d (inverse)
+    const double2 e = inverse ? make_double2(-d.y, d.x) : make_double2(d.y, -d.x);
+    dst[base] = make_double2(a.x + c.x, a.y + c.y);
+    dst[base + p] = make_double2(b.x + e.x, b.y + e.y);
+    dst[base + 2 * p] = make_double2(a.x - c.x, a.y - c.y);
+    dst[base + 3 * p] = make_double2(b.x - e.x, b.y - e.y);
+  } else {
+    const int ustep = n / R;  // W_R^{(t u) mod R} = W_n^{((t u) mod R) n/R}
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      double2 y = x[0];
+#pragma unroll
+      for (int t = 1; t < R; ++t) {
+        double2 w = tws[((t * u) % R) * ustep];
+        if (inverse) w.y = -w.y;
+        const double2 z = cmul(x[t], w);
+        y.x += z.x;
+        y.y += z.y;
+      }
+      dst[base + u * p] = y;
+    }
+  }
+}
+
+// Lines addressed as in k_fft_lines; LDS: two buffers of lpb n points and the n twiddles.
+__global__ __launch_bounds__(kFftThreads) void k_fft_lines_mr(double2* __restrict__ data, int n, MrPlan pl,
+                                                              long long pstride, long long la, long long lb,
+                                                              long long lc, long long nlines, int lpb,
+                                                              const double2* __restrict__ tw, int inverse,
+                                                              int contiguous) {
+  extern __shared__ double2 sm[];
+  double2* b0 = sm;
+  double2* b1 = sm + lpb * n;
+  double2* tws = sm + 2 * lpb * n;
+  for (int e = threadIdx.x; e < n; e += kFftThreads) tws[e] = tw[e];
+  const long long line0 = (long long)blockIdx.x * lpb;
+  const int total = lpb * n;
+  for (int e = threadIdx.x; e < total; e += kFftThreads) {
+    int l, q;
+    if (contiguous) {
+      l = e / n;
+      q = e - l * n;
+    } else {
+      l = e % lpb;
+      q = e / lpb;
+    }
+    const long long line = line0 + l;
+    b0[l * n + q] = (line < nlines) ? data[(line % la) * lb + (line / la) * lc + q * pstride] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  double2 *src = b0, *dst = b1;
+  int p = 1;
+  for (int st = 0; st < pl.nst; ++st) {
+    const int R = pl.r[st], m = n / R;
+    for (int b = threadIdx.x; b < lpb * m; b += kFftThreads) {
+      const int l = b / m, j = b - l * m;
+      const double2* sl = src + l * n;
+      double2* dl = dst + l * n;
+      switch (R) {
+        case 2: mr_butterfly<2>(sl, dl, tws, n, m, p, j, inverse); break;
+        case 3: mr_butterfly<3>(sl, dl, tws, n, m, p, j, inverse); break;
+        case 4: mr_butterfly<4>(sl, dl, tws, n, m, p, j, inverse); break;
+        case 5: mr_butterfly<5>(sl, dl, tws, n, m, p, j, inverse); break;
+        case 7: mr_butterfly<7>(sl, dl, tws, n, m, p, j, inverse); break;
+        case 11: mr_butterfly<11>(sl, dl, tws, n, m, p, j, inverse); break;
+        default: mr_butterfly<13>(sl, dl, tws, n, m, p, j, inverse); break;
+      }
+    }
+    __syncthreads();
+    double2* t = src;
+    src = dst;
+    dst = t;
+    p *= R;
+  }
+  for (int e = threadIdx.x; e < total; e += kFftThreads) {
+    int l, q;
+    if (contiguous) {
+      l = e / n;
+      q = e - l * n;
+    } else {
+      l = e % lpb;
+      q = e / lpb;
+    }
+    const long long line = line0 + l;
+    if (line < nlines) data[(line % la) * lb + (line / la) * lc + q * pstride] = src[l * n + q];
+  }
+}
+
 // q_I = r_I + a Dhat_I zc; z0 = q_1 + i q_2, z1 = q_3 (3D)
 template <int DIM, typename T>
 __global__ __launch_bounds__(256) void k_pack(Consts K, const T* __restrict__ r, double a,
@@ -613,8 +739,50 @@ void launch_lines(double2* data, int n, int logn, long long pstride, long long l
                      lb, lc, nlines, lpb, tw, inverse, contiguous);
 }
 
+bool pow2(int n) { return n >= 1 && (n & (n - 1)) == 0; }
+
+// radices of a mixed-radix line: 4s, then a 2, then the odd primes ascending
+MrPlan mr_plan(int n) {
+  MrPlan pl{};
+  auto add = [&](int r) { pl.r[pl.nst++] = r; };
+  while (n % 4 == 0) { add(4); n /= 4; }
+  while (n % 2 == 0) { add(2); n /= 2; }
+  for (int f = 3; f <= 13 && n > 1; f += 2)
+    while (n % f == 0) { add(f); n /= f; }
+  return pl;
+}
+
+void fft_dir_mr(const Consts& K, const FftPlan& P, double2* data, int dir, int inverse, hipStream_t s) {
+  const int n = P.n[dir];
+  const MrPlan pl = mr_plan(n);
+  // two buffers of lpb lines plus n twiddles within 64 KiB; strided lines at most 16 adjacent
+  int lpb = (4096 - n) / (2 * n);
+  if (lpb < 1) lpb = 1;
+  if (dir != 0 && lpb > 16) lpb = 16;
+  long long nlines, la, lb, lc, pstride;
+  const long long nx = K.nx, ny = K.ny;
+  if (dir == 0) {
+    nlines = ny * K.nz; la = 1; lb = 0; lc = nx; pstride = 1;
+  } else if (dir == 1) {
+    nlines = nx * K.nz; la = nx; lb = 1; lc = nx * ny; pstride = nx;
+  } else {
+    nlines = nx * ny; la = nx * ny; lb = 1; lc = 0; pstride = nx * ny;
+  }
+  if (dir != 0 && lpb > la) lpb = (int)la;
+  const size_t lds = sizeof(double2) * ((size_t)2 * lpb * n + n);
+  if (lds > 64 * 1024)
+    (void)hipFuncSetAttribute((const void*)k_fft_lines_mr, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  const long long blocks = (nlines + lpb - 1) / lpb;
+  hipLaunchKernelGGL(k_fft_lines_mr, dim3((unsigned)blocks), dim3(kFftThreads), lds, s, data, n, pl, pstride, la,
+                     lb, lc, nlines, lpb, P.tw[dir], inverse, dir == 0 ? 1 : 0);
+}
+
 void fft_dir(const Consts& K, const FftPlan& P, double2* data, int dir, int inverse, hipStream_t s) {
   const int n = P.n[dir];
+  if (!pow2(n)) {
+    fft_dir_mr(K, P, data, dir, inverse, s);
+    return;
+  }
   const int logn = ilog2(n);
   // enough workgroups to fill the chip: one 256-butterfly stage per workgroup (n <= 512),
   // at least two adjacent lines for the strided passes (32-byte segments)
@@ -665,7 +833,8 @@ template <typename T>
 void launch_spectral_solve(const Consts& K, const FftPlan& P, const T* r, double a,
                            const T* zc, double2* work0, double2* work1, T* u,
                            hipStream_t s) {
-  if (K.dim == 2 && K.ny <= 1024 && K.nx <= 1024) {
+  const bool all_pow2 = pow2(K.nx) && pow2(K.ny) && pow2(K.nz);
+  if (all_pow2 && K.dim == 2 && K.ny <= 1024 && K.nx <= 1024) {
     const int lx = ilog2(K.nx), ly = ilog2(K.ny);
     int nl = 512 / K.nx;  // rows per x block (one 512-point row: 512 blocks measured faster than 256)
     if (nl < 1) nl = 1;
@@ -680,7 +849,7 @@ void launch_spectral_solve(const Consts& K, const FftPlan& P, const T* r, double
     hipLaunchKernelGGL(k_fft2_rows_inv<T>, dim3(K.ny / nl), dim3(256), lrow, s, K, lx, nl, P.tw[0], work0, u);
     return;
   }
-  if (K.dim == 3 && K.nx >= 8 && K.nx <= 1024 && K.nz <= 1024 && K.ny <= 4096) {
+  if (all_pow2 && K.dim == 3 && K.nx >= 8 && K.nx <= 1024 && K.nz <= 1024 && K.ny <= 4096) {
     const int lx = ilog2(K.nx), ly = ilog2(K.ny), lz = ilog2(K.nz);
     const int nxh = K.nx / 2 + 1;
     double2* Qh = work0;  // 3 nxh ny nz <= 2 N complex for nx >= 8

@@ -30,9 +30,13 @@ struct Pt {
   int i, j, k;
 };
 
-// periodic index: every grid side is a power of two (the Fourier solve needs it), so the
-// mask is exact for any offset, including halo columns of a block wider than the grid
-__device__ inline int wrap(int a, int n) { return a & (n - 1); }
+// periodic index for any offset, including halo columns of a block wider than the grid; the
+// common case (inside the grid) costs one unsigned compare
+__device__ inline int wrap(int a, int n) {
+  if ((unsigned)a < (unsigned)n) return a;
+  const int r = a % n;
+  return r < 0 ? r + n : r;
+}
 
 __device__ inline long long at(const Consts& K, Pt p, int di, int dj, int dk) {
   const int i = wrap(p.i + di, K.nx), j = wrap(p.j + dj, K.ny), k = wrap(p.k + dk, K.nz);
@@ -597,7 +601,8 @@ __global__ __launch_bounds__(kBX* kBY) void k_jv3(Consts K, double dt, const dou
   plane(z0);
   const bool live = (i0 + (int)threadIdx.x < K.nx) && (j0 + (int)threadIdx.y < K.ny);
   const double idt = 1.0 / dt;
-  for (int z = z0; z < z0 + zc; ++z) {
+  const int z1 = (z0 + zc < K.nz) ? z0 + zc : K.nz;  // the last chunk may be shorter
+  for (int z = z0; z < z1; ++z) {
     plane(z + 1);
     __syncthreads();
     if (live) {
@@ -699,8 +704,8 @@ void launch_jv(const Consts& K, double dt, const double* B, const double* cn, co
     const dim3 g((K.nx + kBX - 1) / kBX, (K.ny + kJY2 - 1) / kJY2, 1);
     hipLaunchKernelGGL((k_jv2<Tv>), g, dim3(kBX, kJY2), 0, s, K, dt, B, cn, v, w);
   } else {
-    const int zc = K.nz < kJZ ? K.nz : kJZ;  // nz is a power of two: zc divides it
-    const dim3 g((K.nx + kBX - 1) / kBX, (K.ny + kBY - 1) / kBY, K.nz / zc);
+    const int zc = K.nz < kJZ ? K.nz : kJZ;
+    const dim3 g((K.nx + kBX - 1) / kBX, (K.ny + kBY - 1) / kBY, (K.nz + zc - 1) / zc);
     hipLaunchKernelGGL((k_jv3<Tv>), g, dim3(kBX, kBY), 0, s, K, dt, B, cn, v, w, zc);
   }
 }

@@ -81,7 +81,7 @@ void ras_colour_order(const Consts& K, const TileCfg& T, int* perm);
 // ---- spectral displacement solve (kernels_fft.hip) -----------------------------------
 struct FftPlan {
   int n[3];
-  const double2* tw[3];  // twiddles exp(-2 pi i k / n), k < n/2, one table per direction
+  const double2* tw[3];  // twiddles exp(-2 pi i k / n), k <= n, one table per direction
   const double* sn[3];   // symbols S_m = sin(2 pi m / n) / h, m < n (exact 0 at m = 0, n/2)
 };
 // q_I = r_I + a D-hat_I zc (r may be null), solve K u = q by FFT, write u (d planes).
@@ -111,9 +111,12 @@ void launch_update_dev(long long n, int nv, const T* V, long long ldv, const dou
 void launch_sum2(long long n, const double* x, const double* y, const double* yn, double* partial,
                  hipStream_t s);
 // Xt = X + lam (S + shift e_c), shift = -(msums[0] + msums[1]) / N (device sums of launch_sum2,
-// finalized); partial: count of nodes outside the log domain
+// finalized); partial: count of nodes outside the log domain; pmax (may be null): per-block
+// maxima of |S_f + shift_f| and |X_f| for every field f (2 nf values, for launch_finalize_max)
 void launch_trial(const Consts& K, int nf, const double* X, const double* S, double lam,
-                  const double* msums, double* Xt, double* partial, hipStream_t s);
+                  const double* msums, double* Xt, double* partial, double* pmax, hipStream_t s);
+// second stage of per-block maxima of non-negative values (nvals <= 16)
+void launch_finalize_max(const double* partial, int nvals, double* out, hipStream_t s, double* out2 = nullptr);
 void launch_dx2(long long n4, const double* X, const double* Xn, double* partial, hipStream_t s);
 void launch_class_sums(const Consts& K, const double* u, double* partial, hipStream_t s);
 void launch_class_shift(const Consts& K, double* u, const double* sums, hipStream_t s);

@@ -35,7 +35,14 @@ int device_error(hipError_t e, const char* what) {
     if (e_ != hipSuccess) return device_error(e_, #call);  \
   } while (0)
 
-bool is_pow2(int n) { return n >= 2 && (n & (n - 1)) == 0; }
+// grid sides: even (the parity classes of the central difference), and products of the
+// radices of the Fourier transforms (2, 3, 5, 7, 11, 13)
+bool fft_side(int n) {
+  if (n < 4 || (n & 1)) return false;
+  for (int f = 2; f <= 13; ++f)
+    while (n % f == 0) n /= f;
+  return n == 1;
+}
 
 // preconditioners built on the Schwarz tile solve, and those that solve all fields there
 bool uses_tiles(int pc) { return pc == PFNKS_PC_RAS || pc == PFNKS_PC_RAS_SPECTRAL || pc == PFNKS_PC_AS || pc == PFNKS_PC_RRAS; }
@@ -83,9 +90,9 @@ Layout make_layout(int dim, long long N, int restart, const int* n, int precisio
   sz[B_RED] = sizeof(double) * pf::kMaxRed;
   const size_t cplx = sizeof(double2) * (size_t)N * (dim == 3 ? 2 : 1);
   sz[B_FFT0] = sz[B_FFT1] = cplx;
-  sz[B_TW0] = sizeof(double2) * (size_t)(n[0] / 2 + 1);
-  sz[B_TW1] = sizeof(double2) * (size_t)(n[1] / 2 + 1);
-  sz[B_TW2] = sizeof(double2) * (size_t)((dim == 3 ? n[2] : 2) / 2 + 1);
+  sz[B_TW0] = sizeof(double2) * (size_t)(n[0] + 1);
+  sz[B_TW1] = sizeof(double2) * (size_t)(n[1] + 1);
+  sz[B_TW2] = sizeof(double2) * (size_t)((dim == 3 ? n[2] : 2) + 1);
   sz[B_SN0] = sizeof(double) * (size_t)n[0];
   sz[B_SN1] = sizeof(double) * (size_t)n[1];
   sz[B_SN2] = sizeof(double) * (size_t)(dim == 3 ? n[2] : 2);
@@ -133,7 +140,7 @@ int validate(const pfnks_grid* g, const pfnks_model* m, const pfnks_solver* s) {
   if (g->dim != 2 && g->dim != 3) return PFNKS_EINVAL;
   if (!(g->h > 0.0)) return PFNKS_EINVAL;
   for (int k = 0; k < g->dim; ++k) {
-    if (!is_pow2(g->n[k]) || g->n[k] < 4) return PFNKS_EINVAL;  // FFT sizes, even parity classes
+    if (!fft_side(g->n[k])) return PFNKS_EINVAL;
     const int t = s->tile[k];
     if (t <= 0 || g->n[k] % t != 0) return PFNKS_EINVAL;
     if (t + 2 * s->overlap > g->n[k]) return PFNKS_EINVAL;
@@ -143,6 +150,7 @@ int validate(const pfnks_grid* g, const pfnks_model* m, const pfnks_solver* s) {
   if (s->gmres_restart < 1 || s->gmres_restart > 64) return PFNKS_EINVAL;
   if (s->sweeps < 1 || s->sweeps > 16) return PFNKS_EINVAL;
   if (s->newton_maxit < 1 || s->gmres_maxit < 1) return PFNKS_EINVAL;
+  if (!(s->newton_stol >= 0.0)) return PFNKS_EINVAL;
   if (s->pc < PFNKS_PC_RAS || s->pc > PFNKS_PC_RRAS) return PFNKS_EINVAL;
   if (sums_overlap(s->pc))
     for (int k = 0; k < g->dim; ++k)
@@ -209,11 +217,9 @@ struct pfnks_problem {
 
 namespace {
 
-void make_consts(pfnks_problem* p) {
-  Consts& K = p->K;
+Consts consts_of(const pfnks_grid& g, const pfnks_model& m) {
+  Consts K;
   std::memset(&K, 0, sizeof(K));
-  const pfnks_grid& g = p->grid;
-  const pfnks_model& m = p->model;
   K.dim = g.dim;
   K.nx = g.n[0];
   K.ny = g.n[1];
@@ -262,7 +268,10 @@ void make_consts(pfnks_problem* p) {
     K.qs[j - 1] = 1.0 / (2.0 * j * (2.0 * j + 1.0));
     K.qd[j - 1] = 1.0 / (2.0 * (2.0 * j + 1.0));
   }
+  return K;
 }
+
+void make_consts(pfnks_problem* p) { p->K = consts_of(p->grid, p->model); }
 
 hipEvent_t prof_event(pfnks_problem* p) {
   if (!p->pool.empty()) {
@@ -320,6 +329,8 @@ void prof_resolve(pfnks_problem* p) {
 // slot of the two mass-projection sums in p->red, kept on the device for the line search's
 // trials; every other reduction into p->red writes fewer values (at most 3 * 2^3 = 24)
 constexpr int kRedMassSlot = pf::kMaxRed - 2;
+// slots (device p->red and pinned host p->hbuf) of the update test's 2 nf per-field maxima
+constexpr int kHostUpd = 8;
 
 // finalize partial sums of nvals values and copy them to p->hbuf
 int reduce_to_host(pfnks_problem* p, int nvals) {
@@ -717,11 +728,12 @@ int pfnks_create_problem(const pfnks_grid* grid, const pfnks_model* model, const
     if (e != hipSuccess) return fail(device_error(e, "hipEventCreate"));
   }
 
-  // twiddle tables exp(-2 pi i k / n), k < n/2
+  // twiddle tables exp(-2 pi i k / n), k <= n (the power-of-two transforms read k < n/2, the
+  // mixed-radix ones every k < n)
   for (int d = 0; d < 3; ++d) {
     const int nd = (d < grid->dim) ? grid->n[d] : 2;
-    std::vector<double2> tw(nd / 2 + 1);
-    for (int k = 0; k <= nd / 2; ++k) {
+    std::vector<double2> tw(nd + 1);
+    for (int k = 0; k <= nd; ++k) {
       const double ang = -2.0 * M_PI * (double)k / (double)nd;
       tw[k] = make_double2(std::cos(ang), std::sin(ang));
     }
@@ -786,6 +798,8 @@ int pfnks_step(pfnks_problem* p, double dt, pfnks_step_stats* stats) {
   const double r0 = fn;
   int converged = (fn <= eps_a) || fn == 0.0;
   int newton = 0, gm_total = 0, backtracks = 0;
+  double upd_rel = 0.0;
+  double ds_prev[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // per-field max|lambda S_f| of the last correction
   for (; !converged && newton < sv.newton_maxit; ++newton) {
     // linearise at X; the preconditioner blocks are set up once per step (lagged)
     double* Bm = p->B;
@@ -819,12 +833,20 @@ int pfnks_step(pfnks_problem* p, double dt, pfnks_step_stats* stats) {
     // count of nodes outside the log domain goes to host memory without one, and the residual
     // is evaluated at the trial point whatever it is (outside the domain it is not finite and
     // counts the same nodes, and the point is rejected either way).
+    // The first trial also takes the per-field maxima |S_f| and |X_f| of the update test
+    // (host slots kHostUpd.., read after that trial's residual synchronisation).
     double lam = 1.0, ft = 0.0;
     bool accepted = false;
     for (int hv = 0; hv <= sv.ls_max_halvings; ++hv) {
-      pf::launch_trial(p->K, p->nf, p->X, p->S, lam, msums, p->Xt, p->part, p->stream);
+      pf::launch_trial(p->K, p->nf, p->X, p->S, lam, msums, p->Xt, p->part,
+                       hv == 0 ? p->part + pf::kRedBlocks : nullptr, p->stream);
       pf::launch_finalize(p->part, 1, p->red, p->stream, p->hbuf + 2);
       p->launches += 2;
+      if (hv == 0) {
+        pf::launch_finalize_max(p->part + pf::kRedBlocks, 2 * p->nf, p->red + kHostUpd, p->stream,
+                                p->hbuf + kHostUpd);
+        p->launches += 1;
+      }
       s = residual(p, p->Xt, dt, p->Ft, &ft, &bad);
       if (s) return s;
       const double trial_bad = p->hbuf[2];
@@ -840,7 +862,29 @@ int pfnks_step(pfnks_problem* p, double dt, pfnks_step_stats* stats) {
     std::swap(p->X, p->Xt);
     std::swap(p->F, p->Ft);
     fn = ft;
-    if (fn <= std::fmax(sv.newton_rtol * r0, eps_a)) {
+    // update test: the error left after this correction, estimated from the contraction of
+    // consecutive corrections theta = max_f |dS_f|_k / |dS_f|_{k-1} as theta / (1 - theta)
+    // |dS_f|_k, must be <= stol max|X_f| in every field.  The first correction has no
+    // estimate (one more iteration is needed); a field whose correction is exactly zero
+    // passes (e.g. the displacement without elasticity).
+    double ds[8], xs[8], theta = 0.0;
+    for (int f = 0; f < p->nf; ++f) {
+      ds[f] = lam * p->hbuf[kHostUpd + 2 * f];
+      xs[f] = p->hbuf[kHostUpd + 2 * f + 1];
+      if (ds[f] > 0.0) theta = std::fmax(theta, ds_prev[f] > 0.0 ? ds[f] / ds_prev[f] : HUGE_VAL);
+    }
+    const double amp = (theta < 1.0) ? theta / (1.0 - theta) : HUGE_VAL;
+    bool small_update = true;
+    upd_rel = 0.0;
+    for (int f = 0; f < p->nf; ++f) {
+      if (ds[f] == 0.0) continue;
+      const double est = ds[f] * amp;
+      upd_rel = std::fmax(upd_rel, xs[f] > 0.0 ? est / xs[f] : HUGE_VAL);
+      if (!(est <= sv.newton_stol * xs[f])) small_update = false;
+    }
+    for (int f = 0; f < p->nf; ++f) ds_prev[f] = ds[f];
+    if (sv.newton_stol <= 0.0) small_update = true;
+    if (fn <= eps_a || (fn <= sv.newton_rtol * r0 && small_update)) {
       converged = 1;
       ++newton;
       break;
@@ -850,6 +894,7 @@ int pfnks_step(pfnks_problem* p, double dt, pfnks_step_stats* stats) {
   st.gmres_its = gm_total;
   st.ls_backtracks = backtracks;
   st.res_final = fn;
+  st.update_rel = upd_rel;
   if (!converged) {
     st.status = PFNKS_ENOCONV;
     if (stats) *stats = st;
@@ -884,12 +929,15 @@ int pfnks_batch_step(pfnks_problem* const* problems, int k, const double* dts, i
       if (problems[j] == problems[i]) return PFNKS_EINVAL;
   }
   std::vector<int> st(k, PFNKS_OK);
+  // the worker's text of a PFNKS_EDEVICE (g_last_error is per thread), handed to the caller
+  std::vector<std::string> err(k);
   std::atomic<int> next{0};
   auto work = [&]() {
     for (;;) {
       const int i = next.fetch_add(1);
       if (i >= k) break;
       st[i] = pfnks_step(problems[i], dts[i], stats ? &stats[i] : nullptr);
+      if (st[i] == PFNKS_EDEVICE) err[i] = g_last_error;
     }
   };
   const int nth = std::min(k, threads > 0 ? threads : 16);
@@ -904,7 +952,10 @@ int pfnks_batch_step(pfnks_problem* const* problems, int k, const double* dts, i
   int first = PFNKS_OK;
   for (int i = 0; i < k; ++i) {
     if (status) status[i] = st[i];
-    if (first == PFNKS_OK && st[i] != PFNKS_OK) first = st[i];
+    if (first == PFNKS_OK && st[i] != PFNKS_OK) {
+      first = st[i];
+      if (st[i] == PFNKS_EDEVICE) g_last_error = "problem " + std::to_string(i) + ": " + err[i];
+    }
   }
   return first;
 }

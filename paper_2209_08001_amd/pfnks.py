@@ -64,6 +64,7 @@ class pfnks_solver(ctypes.Structure):
         ("gmres_maxit", ctypes.c_int), ("tile", ctypes.c_int * 3), ("overlap", ctypes.c_int),
         ("sweeps", ctypes.c_int), ("pc", ctypes.c_int), ("precision", ctypes.c_int),
         ("ls_alpha", ctypes.c_double), ("ls_max_halvings", ctypes.c_int),
+        ("newton_stol", ctypes.c_double),
     ]
 
 
@@ -73,6 +74,7 @@ class pfnks_step_stats(ctypes.Structure):
         ("status", ctypes.c_int), ("res0", ctypes.c_double), ("res_final", ctypes.c_double),
         ("dx_rms", ctypes.c_double), ("energy", ctypes.c_double),
         ("energy_parts", ctypes.c_double * 3), ("mass", ctypes.c_double),
+        ("update_rel", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -180,6 +182,7 @@ def make_solver(d, dim):
     s.precision = d.get("precision", FP64)
     s.ls_alpha = d["ls_alpha"]
     s.ls_max_halvings = d["ls_max_halvings"]
+    s.newton_stol = d.get("newton_stol", 0.0)
     return s
 
 

@@ -7,6 +7,10 @@ allocates nothing else on the device) stays within the HBM budget.  Every tick s
 resident requests once together (pfnks_batch_step, one stream per request, each request
 with its own step-size history), so requests join and leave between ticks.  A request's
 result depends only on its own inputs: it is bitwise the result of running it alone.
+
+Latency: each request's own step time, from the start of the tick to the completion of its
+step on its stream (HIP events on that stream), so a small request that finishes early in a
+tick is not charged the tick's slowest member.
 """
 
 import time
@@ -27,7 +31,9 @@ class Request:
         self.admitted_at = None
         self.finished_at = None
         self.step_ms = []
+        self.dts = []
         self.retries = 0
+        self.stream = None
         self.state = None
         self.t = None
 
@@ -63,12 +69,10 @@ class Server:
         sv = dict(self.solver)
         sv["sweeps"] = W.default_sweeps(len(n), sv.get("precision", pfnks.FP64) == pfnks.MIXED)
         if len(n) == 3:
-            sv.update(tile=(8, 8, 8) if min(n) >= 16 else (4, 4, 4), overlap=1)
+            sv["overlap"] = 1
+            sv["tile"] = tuple(W.tile_side(s, 8, 1) for s in n)
         else:
-            t = 32
-            while t + 2 * sv["overlap"] > min(n):
-                t //= 2
-            sv["tile"] = (t, t, 1)
+            sv["tile"] = (W.tile_side(n[0], 32, sv["overlap"]), W.tile_side(n[1], 32, sv["overlap"]), 1)
         return sv
 
     def bytes_for(self, r):
@@ -93,8 +97,9 @@ class Server:
                     and used + need[pending[0].rid] <= self.budget:
                 r = pending.pop(0)
                 c0, e0 = W.init_fields(r.n, r.seed, cbar=r.cbar)
+                r.stream = torch.cuda.Stream(device=self.device)
                 r.problem = pfnks.Problem(r.n, W.H, W.DEFAULT_MODEL, self._solver_for(r.n), c0, e0,
-                                          device=self.device, stream=torch.cuda.Stream(device=self.device))
+                                          device=self.device, stream=r.stream)
                 r.clock = _Clock(self.wl)
                 r.admitted_at = now() if realtime else 0.0
                 used += need[r.rid]
@@ -102,25 +107,33 @@ class Server:
             if not resident:
                 time.sleep(max(0.0, min(0.05, pending[0].arrival - now())))
                 continue
-            # one tick: every resident request takes one accepted step
-            t0 = time.perf_counter()
+            # one tick: every resident request takes one accepted step; its latency runs from
+            # an event recorded on its stream at the start of the tick to one recorded after
+            # its accepted step
             todo = list(resident)
+            ev0, ev1 = {}, {}
+            for r in todo:
+                ev0[r.rid] = torch.cuda.Event(enable_timing=True)
+                ev0[r.rid].record(r.stream)
             dts = {r.rid: r.clock.next_dt() for r in todo}
             while todo:
                 status, st = pfnks.batch_step([r.problem for r in todo], [dts[r.rid] for r in todo], self.threads)
                 again = []
                 for r, s_, x in zip(todo, status, st):
                     if s_ == pfnks.PFNKS_OK:
+                        ev1[r.rid] = torch.cuda.Event(enable_timing=True)
+                        ev1[r.rid].record(r.stream)
                         r.clock.accepted(x, dts[r.rid])
+                        r.dts.append(dts[r.rid])
                         r.done += 1
                     else:
                         dts[r.rid] = r.clock.failed(dts[r.rid])
                         r.retries += 1
                         again.append(r)
                 todo = again
-            tick_ms = 1e3 * (time.perf_counter() - t0)
             for r in resident:
-                r.step_ms.append(tick_ms)
+                ev1[r.rid].synchronize()
+                r.step_ms.append(ev0[r.rid].elapsed_time(ev1[r.rid]))
             # retire finished requests
             still = []
             for r in resident:
@@ -138,7 +151,8 @@ class Server:
 
 
 def run_alone(r, solver_for, wl, device="cuda:0"):
-    """The same request stepped by itself (reference for the alone-versus-mix check)."""
+    """The same request stepped by itself (reference for the alone-versus-mix check); returns
+    its final state and time."""
     c0, e0 = W.init_fields(r.n, r.seed, cbar=r.cbar)
     p = pfnks.Problem(r.n, W.H, W.DEFAULT_MODEL, solver_for(r.n), c0, e0, device=device)
     clk = _Clock(wl)

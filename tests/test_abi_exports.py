@@ -47,8 +47,19 @@ def test_workspace_bytes_and_validation_on_host():
     b = pfnks.workspace_bytes((512, 512), W.H, W.DEFAULT_MODEL, W.DEFAULT_SOLVER)
     N = 512 * 512
     assert b >= (31 + 12) * 6 * 8 * N
-    with pytest.raises(pfnks.PfnksError):
-        pfnks.workspace_bytes((100, 100), W.H, W.DEFAULT_MODEL, W.DEFAULT_SOLVER)  # not a power of 2
+    # sides: even, >= 4, products of the Fourier radices 2, 3, 5, 7, 11, 13
+    for side, tile in ((100, 20), (384, 32), (192, 32), (960, 32), (704, 32), (832, 32), (6, 2), (24, 8)):
+        assert pfnks.workspace_bytes((side, side), W.H, W.DEFAULT_MODEL,
+                                     dict(W.DEFAULT_SOLVER, tile=(tile, tile, 1), overlap=1)) > 0, side
+    for side in (80, 96, 112):
+        assert pfnks.workspace_bytes((side,) * 3, W.H, W.DEFAULT_MODEL,
+                                     dict(W.DEFAULT_SOLVER, tile=(8, 8, 8), overlap=1)) > 0, side
+    for side, tile in ((34, 17), (38, 19), (15, 5), (2, 2), (102, 34)):  # factor 17 or 19, odd, below 4
+        with pytest.raises(pfnks.PfnksError):
+            pfnks.workspace_bytes((side, side), W.H, W.DEFAULT_MODEL,
+                                  dict(W.DEFAULT_SOLVER, tile=(tile, tile, 1), overlap=0))
+    with pytest.raises(pfnks.PfnksError):  # a tile that does not divide the side
+        pfnks.workspace_bytes((100, 100), W.H, W.DEFAULT_MODEL, W.DEFAULT_SOLVER)
     with pytest.raises(pfnks.PfnksError):
         pfnks.workspace_bytes((64, 64), W.H, W.DEFAULT_MODEL, dict(W.DEFAULT_SOLVER, tile=(48, 48, 1)))
 
@@ -136,3 +147,4 @@ def test_create_problem_rejects_on_host():
     c = c0.copy()
     c[7], e[7], e[N + 7], e[2 * N + 7] = 0.5, 0.4, 0.4, 0.4  # eta_4 = 2.8: c eta_4 = 1.4
     assert create(c, e) == (pfnks.PFNKS_EDOMAIN, None)
+

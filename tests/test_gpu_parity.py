@@ -5,11 +5,12 @@ order: each entry sums at most ~60 FP64 terms whose magnitude is at most ~1e3 ti
 largest entry of the field for these random states, so |gpu - oracle| <= 60 * 1.1e-16 * 1e3
 ~ 1e-11 relative to the field's max-norm; the tests use 1e-10.  Step-level results compare
 the root the GPU's Newton-Krylov iteration converges to with the oracle's exact-LU root,
-within 1e-8 relative to the field's max-norm.  The distance of an iterate from the root is
-bounded by |J^{-1}| |F|, so a residual stop at the paper's 1e-8 leaves up to ~1e-8 (observed
-up to 1.1e-8 with the default solver); the root comparisons therefore stop Newton at
-ROOT_RTOL = 1e-10, and the full-size tests check the 1e-8 residual stop itself with the
-oracle's residual.
+within 1e-8 relative to the field's max-norm, at the solver settings the benchmark times
+(workloads.DEFAULT_SOLVER): the paper's residual test (Newton 1e-8, GMRES 1e-6, Section 5)
+together with the update test (the last accepted Newton correction below 1e-8 of every
+field's max-norm).  The residual test alone bounds the distance from the root only through
+|J^{-1}| |F| and was observed to stop up to 1.25e-8 away; test_residual_stop_alone_root keeps
+that setting at a tighter residual tolerance (ROOT_RTOL) as an extra.
 """
 
 import sys
@@ -42,15 +43,22 @@ def _problem(n, c0, e0, model=None, **solver_kw):
     sv = dict(W.DEFAULT_SOLVER)
     sv.update(solver_kw)
     if len(n) == 3 and "tile" not in solver_kw:
-        sv["tile"] = (8, 8, 8)
+        # largest tile <= 8 per direction that divides the side, overlap 1
         sv["overlap"] = 1
+        t = []
+        for nk in n:
+            tk = 8
+            while nk % tk or tk + 2 > nk:
+                tk -= 1
+            t.append(tk)
+        sv["tile"] = tuple(t)
     elif "tile" not in solver_kw:
-        # largest power-of-two tile <= 32 whose extended block fits the grid side
+        # largest tile <= 32 that divides the grid side and whose extended block fits in it
         t = []
         for nk in n:
             tk = 32
-            while tk + 2 * sv["overlap"] > nk:
-                tk //= 2
+            while nk % tk or tk + 2 * sv["overlap"] > nk:
+                tk -= 1
             t.append(tk)
         sv["tile"] = (t[0], t[1], 1)
     return pfnks.Problem(n, W.H, model or W.DEFAULT_MODEL, sv, c0, e0)
@@ -65,7 +73,7 @@ def _relmax(a, b):
     return np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)
 
 
-@pytest.mark.parametrize("n", [(64, 64), (32, 64), (16, 16, 16)])
+@pytest.mark.parametrize("n", [(64, 64), (32, 64), (16, 16, 16), (24, 40), (12, 10, 14)])
 def test_residual_parity(n):
     _cuda()
     _note(f"residual parity n={n}")
@@ -85,7 +93,7 @@ def test_residual_parity(n):
     p.close()
 
 
-@pytest.mark.parametrize("n", [(64, 64), (16, 16, 16)])
+@pytest.mark.parametrize("n", [(64, 64), (16, 16, 16), (24, 40), (12, 10, 14)])
 def test_jv_parity(n):
     _cuda()
     _note(f"jv parity n={n}")
@@ -107,13 +115,17 @@ def test_jv_parity(n):
 
 
 # (4, 8, 8) and (2048, 4) take the general Fourier path (n_x < 8 in 3D, a side above 1024 in
-# 2D: separate pack, line transforms, symbol solve and unpack kernels); the others the fused ones
-@pytest.mark.parametrize("n", [(64, 64), (32, 16), (16, 16, 16), (4, 8, 8), (2048, 4)])
+# 2D: separate pack, line transforms, symbol solve and unpack kernels), and so does every grid
+# with a side that is not a power of two (mixed-radix lines: radices 3, 5, 7, 11, 13 below);
+# the others the fused ones
+@pytest.mark.parametrize("n", [(64, 64), (32, 16), (16, 16, 16), (4, 8, 8), (2048, 4), (24, 40), (48, 56),
+                               (12, 10, 14), (22, 26), (6, 20, 8)])
 def test_elastic_init_and_energy(n):
     _cuda()
     _note(f"elastic init / energy n={n}")
     c0, e0 = W.init_fields(n, 17)
-    small = {(4, 8, 8): dict(tile=(4, 4, 4), overlap=0), (2048, 4): dict(tile=(32, 4, 1), overlap=0)}
+    small = {(4, 8, 8): dict(tile=(4, 4, 4), overlap=0), (2048, 4): dict(tile=(32, 4, 1), overlap=0),
+             (12, 10, 14): dict(tile=(4, 2, 2), overlap=1), (6, 20, 8): dict(tile=(2, 4, 4), overlap=1)}
     p = _problem(n, c0, e0, **small.get(n, {}))
     o = Oracle(n, W.H, W.DEFAULT_MODEL, c0, e0)
     Xg, _ = p.get_state()
@@ -242,7 +254,7 @@ def test_step_parity_pf2d_64(oracle_c1, pc, prec):
     c0, e0, traj, info, o = oracle_c1
     _note(f"step parity pf2d_64 pc={pc} precision={prec}")
     p = _problem((64, 64), c0, e0, pc=pfnks.PC_RAS if pc == "ras" else pfnks.PC_RAS_SPECTRAL,
-                 precision=pfnks.MIXED if prec == "mixed" else pfnks.FP64, newton_rtol=ROOT_RTOL)
+                 precision=pfnks.MIXED if prec == "mixed" else pfnks.FP64)
     m0 = p.mass()
     E_prev = p.energy()[0]
     for k in range(10):
@@ -250,7 +262,8 @@ def test_step_parity_pf2d_64(oracle_c1, pc, prec):
         X, t = p.get_state()
         errs = [_relmax(X[f], traj[k + 1][f]) for f in range(X.shape[0])]
         _note(f"  step {k}: newton={st['newton_its']} gmres={st['gmres_its']} "
-              f"|F|/|F0|={st['res_final'] / st['res0']:.2e} max err={max(errs):.2e} (field {int(np.argmax(errs))})")
+              f"|F|/|F0|={st['res_final'] / st['res0']:.2e} update={st['update_rel']:.1e} "
+              f"max err={max(errs):.2e} (field {int(np.argmax(errs))})")
         for f in range(X.shape[0]):
             assert errs[f] <= 1e-8, (k, f, errs[f])
         assert abs(st["mass"] - m0) <= 1e-13 * abs(m0)
@@ -275,7 +288,7 @@ def test_step_parity_tile_shapes(oracle_c1, tile, prec, overlap):
     c0, e0, traj, info, o = oracle_c1
     _note(f"step parity pf2d_64 tile={tile} overlap={overlap} precision={prec}")
     p = _problem((64, 64), c0, e0, tile=(tile[0], tile[1], 1), overlap=overlap,
-                 precision=pfnks.MIXED if prec == "mixed" else pfnks.FP64, newton_rtol=ROOT_RTOL)
+                 precision=pfnks.MIXED if prec == "mixed" else pfnks.FP64)
     for k in range(3):
         st = p.step(0.01)
         X, _ = p.get_state()
@@ -304,8 +317,7 @@ def test_batch_step_equals_single_and_oracle(oracle_c1):
     batch = []
     for n, seed, prec in specs:
         cc, ee = (c0, e0) if seed is None else W.init_fields(n, seed)
-        sv = dict(W.DEFAULT_SOLVER, precision=pfnks.MIXED if prec == "mixed" else pfnks.FP64,
-                  newton_rtol=ROOT_RTOL)
+        sv = dict(W.DEFAULT_SOLVER, precision=pfnks.MIXED if prec == "mixed" else pfnks.FP64)
         sv["tile"] = (4, 4, 4) if len(n) == 3 else (16, 16, 1)
         sv["overlap"] = 1 if len(n) == 3 else 2
         batch.append(pfnks.Problem(n, W.H, W.DEFAULT_MODEL, sv, cc, ee, stream=torch.cuda.Stream()))
@@ -315,8 +327,7 @@ def test_batch_step_equals_single_and_oracle(oracle_c1):
     alone = []
     for n, seed, prec in specs:
         cc, ee = (c0, e0) if seed is None else W.init_fields(n, seed)
-        sv = dict(W.DEFAULT_SOLVER, precision=pfnks.MIXED if prec == "mixed" else pfnks.FP64,
-                  newton_rtol=ROOT_RTOL)
+        sv = dict(W.DEFAULT_SOLVER, precision=pfnks.MIXED if prec == "mixed" else pfnks.FP64)
         sv["tile"] = (4, 4, 4) if len(n) == 3 else (16, 16, 1)
         sv["overlap"] = 1 if len(n) == 3 else 2
         q = pfnks.Problem(n, W.H, W.DEFAULT_MODEL, sv, cc, ee)
@@ -335,27 +346,40 @@ def test_batch_step_equals_single_and_oracle(oracle_c1):
         p.close()
 
 
-def test_serving_alone_equals_mix():
-    """Continuous batching: requests of different sizes (2D and 3D, FP64), admitted under an
-    HBM budget that holds only some of them at once, joining and leaving between ticks; every
-    request's final state is bitwise the state of the same request run alone."""
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_serving_alone_equals_mix(prec):
+    """Continuous batching: requests of different sizes (2D and 3D, sides that are and are not
+    powers of two), admitted under an HBM budget that holds only some of them at once, joining
+    and leaving between ticks; every request's final state is bitwise the state of the same
+    request run alone, and within 1e-8 of the oracle's roots taken with the request's own step
+    sizes.  Every request records one latency per step, each at most the tick's wall time."""
     from paper_2209_08001_amd import pfnks
     from paper_2209_08001_amd.serve import Request, Server, run_alone
 
     _cuda()
-    _note("serving alone vs mix")
+    _note(f"serving alone vs mix vs oracle precision={prec}")
     wl = dict(W.WORKLOADS["serve_mix"])
-    reqs = [Request(0, (32, 32), 11, 0.15, 3), Request(1, (64, 64), 12, 0.17, 5),
-            Request(2, (16, 16, 16), 13, 0.19, 2), Request(3, (32, 64), 14, 0.16, 4),
-            Request(4, (64, 64), 15, 0.2, 3)]
-    srv = Server(dict(W.DEFAULT_SOLVER), wl, hbm_budget=0, keep_state=True, threads=4)
+    reqs = [Request(0, (32, 32), 11, 0.15, 3), Request(1, (48, 48), 12, 0.17, 3),
+            Request(2, (12, 12, 12), 13, 0.19, 2), Request(3, (32, 48), 14, 0.16, 3),
+            Request(4, (24, 40), 15, 0.2, 3)]
+    sv = dict(W.DEFAULT_SOLVER, precision=pfnks.MIXED if prec == "mixed" else pfnks.FP64)
+    srv = Server(sv, wl, hbm_budget=0, keep_state=True, threads=4)
     need = sorted(srv.bytes_for(r) for r in reqs)
     srv.budget = need[-1] + need[-2]  # at most two of the largest resident at once
     srv.run(reqs, realtime=False)
     for r in reqs:
-        assert r.done == r.steps
+        assert r.done == r.steps and len(r.step_ms) == r.steps and len(r.dts) == r.steps
+        assert all(x > 0.0 for x in r.step_ms)
         Xa, ta = run_alone(r, srv._solver_for, wl)
         assert np.array_equal(r.state, Xa) and r.t == ta, r.rid
+        c0, e0 = W.init_fields(r.n, r.seed, cbar=r.cbar)
+        o = Oracle(r.n, W.H, W.DEFAULT_MODEL, c0, e0)
+        for dt in r.dts:
+            o.step(dt)
+        err = max(_relmax(r.state[f], o.X[f]) for f in range(r.state.shape[0]))
+        _note(f"  request {r.rid} n={r.n}: {r.steps} steps, dts={['%.3g' % d for d in r.dts]}, "
+              f"latency ms={['%.2f' % x for x in r.step_ms]}, max err vs oracle {err:.2e}")
+        assert err <= 1e-8, (r.rid, err)
 
 
 @pytest.fixture(scope="module")
@@ -380,8 +404,7 @@ def test_p1_particle_parity(oracle_particle, prec):
     _cuda()
     n, c0, e0, traj = oracle_particle
     _note(f"P=1 particle parity precision={prec}")
-    p = _problem(n, c0, e0, model=W.P1_MODEL, precision=pfnks.MIXED if prec == "mixed" else pfnks.FP64,
-                 newton_rtol=ROOT_RTOL)
+    p = _problem(n, c0, e0, model=W.P1_MODEL, precision=pfnks.MIXED if prec == "mixed" else pfnks.FP64)
     E_prev = p.energy()[0]
     for k in range(2):
         st = p.step(0.01)
@@ -421,6 +444,25 @@ def test_stop_rule_pf2d_64(oracle_c1):
     p.close()
 
 
+def test_residual_stop_alone_root(oracle_c1):
+    """The paper's residual test on its own (update test off) at the tighter tolerance
+    ROOT_RTOL = 1e-10: 10 steps of pf2d_64 in both precisions within 1e-8 of the oracle's
+    roots (the bound then follows from |J^{-1}| |F| with two more digits of residual)."""
+    from paper_2209_08001_amd import pfnks
+
+    _cuda()
+    c0, e0, traj, info, o = oracle_c1
+    for prec in (pfnks.FP64, pfnks.MIXED):
+        _note(f"residual stop alone, newton_rtol={ROOT_RTOL}, precision={prec}")
+        p = _problem((64, 64), c0, e0, precision=prec, newton_rtol=ROOT_RTOL, newton_stol=0.0)
+        for k in range(10):
+            p.step(0.01)
+            X, _ = p.get_state()
+            err = max(_relmax(X[f], traj[k + 1][f]) for f in range(X.shape[0]))
+            assert err <= 1e-8, (prec, k, err)
+        p.close()
+
+
 @pytest.mark.parametrize("pc,overlap,tile", [("as", 0, (16, 16)), ("as", 2, (16, 16)), ("rras", 1, (16, 16)),
                                             ("rras", 2, (32, 32)), ("as", 1, (32, 32))])
 def test_step_parity_schwarz_variants(oracle_c1, pc, overlap, tile):
@@ -432,8 +474,7 @@ def test_step_parity_schwarz_variants(oracle_c1, pc, overlap, tile):
     _cuda()
     c0, e0, traj, info, o = oracle_c1
     _note(f"step parity pf2d_64 pc={pc} overlap={overlap} tile={tile}")
-    p = _problem((64, 64), c0, e0, pc=getattr(pfnks, PCS[pc]), overlap=overlap, tile=(tile[0], tile[1], 1),
-                 newton_rtol=ROOT_RTOL)
+    p = _problem((64, 64), c0, e0, pc=getattr(pfnks, PCS[pc]), overlap=overlap, tile=(tile[0], tile[1], 1))
     for k in range(3):
         st = p.step(0.01)
         X, _ = p.get_state()
@@ -488,13 +529,16 @@ def test_set_state_rejects_out_of_domain():
     p.close()
 
 
+DTS_3D = (0.01, 0.05, 0.1, 0.2)
+
+
 @pytest.fixture(scope="module")
 def oracle_3d():
     n = (8, 8, 8)
     c0, e0 = W.init_fields(n, 31)
     o = Oracle(n, W.H, W.DEFAULT_MODEL, c0, e0)
     traj = [o.X.copy()]
-    for dt in (0.01, 0.05):
+    for dt in DTS_3D:
         o.step(dt)
         traj.append(o.X.copy())
     return n, c0, e0, traj
@@ -503,7 +547,7 @@ def oracle_3d():
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 @pytest.mark.parametrize("pc", ["ras_spectral", "ras", "as", "rras"])
 def test_step_parity_3d(oracle_3d, pc, prec):
-    """3D 8 x 8 x 8 (tiles 4^3, overlap 1, two tiles per direction), two steps, every
+    """3D 8 x 8 x 8 (tiles 4^3, overlap 1, two tiles per direction), four steps, every
     preconditioner (the all-field ones with the 3D tile kernel holding u, classical AS and
     right-RAS through the 3D gather): within 1e-8 of the oracle's root."""
     from paper_2209_08001_amd import pfnks
@@ -512,14 +556,15 @@ def test_step_parity_3d(oracle_3d, pc, prec):
     n, c0, e0, traj = oracle_3d
     _note(f"step parity 3d pc={pc} precision={prec}")
     p = _problem(n, c0, e0, tile=(4, 4, 4), overlap=1, pc=getattr(pfnks, PCS[pc]),
-                 precision=pfnks.MIXED if prec == "mixed" else pfnks.FP64, newton_rtol=ROOT_RTOL)
+                 precision=pfnks.MIXED if prec == "mixed" else pfnks.FP64)
     m0 = p.mass()
-    for k, dt in enumerate((0.01, 0.05)):
+    for k, dt in enumerate(DTS_3D):
         st = p.step(dt)
         X, _ = p.get_state()
         errs = [_relmax(X[f], traj[k + 1][f]) for f in range(X.shape[0])]
         _note(f"  step {k}: newton={st['newton_its']} gmres={st['gmres_its']} "
-              f"|F|/|F0|={st['res_final'] / st['res0']:.2e} max err={max(errs):.2e} (field {int(np.argmax(errs))})")
+              f"|F|/|F0|={st['res_final'] / st['res0']:.2e} update={st['update_rel']:.1e} "
+              f"max err={max(errs):.2e} (field {int(np.argmax(errs))})")
         for f in range(X.shape[0]):
             assert errs[f] <= 1e-8, (k, f, errs[f])
         assert abs(st["mass"] - m0) <= 1e-13 * abs(m0)
@@ -557,7 +602,7 @@ def test_step_parity_smallest_grids(n, tile, prec):
     from paper_2209_08001_amd import pfnks
 
     _note(f"step parity smallest grid n={n} tile={tile} precision={prec}")
-    p = _problem(n, c0, e0, tile=tile, overlap=1, newton_rtol=ROOT_RTOL,
+    p = _problem(n, c0, e0, tile=tile, overlap=1, 
                  precision=pfnks.MIXED if prec == "mixed" else pfnks.FP64)
     m0 = p.mass()
     for k, dt in enumerate((0.01, 0.05)):
@@ -584,7 +629,7 @@ def test_step_parity_unequal_sides(n, tile, dts, prec):
     from paper_2209_08001_amd import pfnks
 
     _note(f"step parity unequal sides n={n} tile={tile} precision={prec}")
-    p = _problem(n, c0, e0, tile=tile, overlap=1, newton_rtol=ROOT_RTOL,
+    p = _problem(n, c0, e0, tile=tile, overlap=1, 
                  precision=pfnks.MIXED if prec == "mixed" else pfnks.FP64)
     m0 = p.mass()
     for k, dt in enumerate(dts):
@@ -593,6 +638,37 @@ def test_step_parity_unequal_sides(n, tile, dts, prec):
         errs = [_relmax(X[f], traj[k][f]) for f in range(X.shape[0])]
         _note(f"  step {k}: newton={st['newton_its']} gmres={st['gmres_its']} max err={max(errs):.2e}")
         assert max(errs) <= 1e-8, (k, errs)
+        assert abs(st["mass"] - m0) <= 1e-13 * abs(m0)
+    p.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("pc", ["ras_spectral", "ras"])
+@pytest.mark.parametrize("n,tile,overlap", [((24, 40), (8, 8, 1), 2), ((48, 56), (16, 8, 1), 2),
+                                            ((12, 10, 14), (4, 2, 2), 1)])
+def test_step_parity_non_power_of_two(n, tile, overlap, pc, prec):
+    """Periodic grids whose sides are not powers of two (factors 3, 5 and 7; the Fourier
+    displacement solve on mixed-radix lines, the stencils with the general periodic wrap):
+    three steps at the default solver settings within 1e-8 of the oracle's roots, mass
+    conserved to 1e-13."""
+    from paper_2209_08001_amd import pfnks
+
+    _cuda()
+    dts = (0.01, 0.05, 0.1)
+    c0, e0 = W.init_fields(n, 43)
+    traj = _oracle_traj(n, 43, dts)
+    _note(f"step parity non-power-of-two n={n} tile={tile} pc={pc} precision={prec}")
+    p = _problem(n, c0, e0, tile=tile, overlap=overlap, pc=getattr(pfnks, PCS[pc]),
+                 precision=pfnks.MIXED if prec == "mixed" else pfnks.FP64)
+    m0 = p.mass()
+    for k, dt in enumerate(dts):
+        st = p.step(dt)
+        X, _ = p.get_state()
+        errs = [_relmax(X[f], traj[k][f]) for f in range(X.shape[0])]
+        _note(f"  step {k}: newton={st['newton_its']} gmres={st['gmres_its']} update={st['update_rel']:.1e} "
+              f"max err={max(errs):.2e} (field {int(np.argmax(errs))})")
+        for f in range(X.shape[0]):
+            assert errs[f] <= 1e-8, (k, f, errs[f])
         assert abs(st["mass"] - m0) <= 1e-13 * abs(m0)
     p.close()
 
@@ -612,7 +688,7 @@ def test_step_parity_elastic_scale(lscale, prec):
     c0, e0 = W.init_fields(n, 47)
     traj = _oracle_traj(n, 47, (0.01, 0.05), model)
     _note(f"step parity elastic scale {lscale} precision={prec}")
-    p = _problem(n, c0, e0, model=model, newton_rtol=ROOT_RTOL,
+    p = _problem(n, c0, e0, model=model, 
                  precision=pfnks.MIXED if prec == "mixed" else pfnks.FP64)
     m0 = p.mass()
     for k, dt in enumerate((0.01, 0.05)):
@@ -630,8 +706,18 @@ def test_step_parity_elastic_scale(lscale, prec):
     p.close()
 
 
+# the benchmark's full sizes, and sides of the ensemble and serving mixes that are not powers
+# of two (384 = 2^7 3, 96 = 2^5 3)
+FULL_SIZE = {
+    "pf2d_512": W.WORKLOADS["pf2d_512"],
+    "pf3d_128": W.WORKLOADS["pf3d_128"],
+    "pf2d_384": dict(W.WORKLOADS["pf2d_512"], n=(384, 384), seed=6),
+    "pf3d_96": dict(W.WORKLOADS["pf3d_128"], n=(96, 96, 96), seed=7),
+}
+
+
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-@pytest.mark.parametrize("wl", ["pf2d_512", "pf3d_128"])
+@pytest.mark.parametrize("wl", sorted(FULL_SIZE))
 def test_full_size_first_step_root(wl, prec):
     """Full-size workloads, the first step of the adaptive trajectory (dt = dt_min) in the
     launch configuration the benchmark times.  The oracle's LU solve does not reach these
@@ -642,7 +728,7 @@ def test_full_size_first_step_root(wl, prec):
     from paper_2209_08001_amd import pfnks
 
     _cuda()
-    spec = W.WORKLOADS[wl]
+    spec = FULL_SIZE[wl]
     n = spec["n"]
     _note(f"full-size root {wl} precision={prec}")
     c0, e0 = W.init_fields(n, spec["seed"], cbar=spec["cbar"])

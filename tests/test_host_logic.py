@@ -54,7 +54,7 @@ def test_poisson_requests_are_seeded_and_shaped():
     a = poisson_requests(*args)
     b = poisson_requests(*args)
     assert [(r.n, r.seed, r.cbar, r.arrival) for r in a] == [(r.n, r.seed, r.cbar, r.arrival) for r in b]
-    assert len(a) == 38  # the serving workload's 10 s window at 4 requests/s
+    assert len(a) == 1289  # the serving workload: 60 s at 20 requests/s (1200 expected, sd 35)
     t = [r.arrival for r in a]
     assert all(0.0 < x <= wl["window"] for x in t) and t == sorted(t)
     for k, r in enumerate(a):
