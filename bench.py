@@ -217,6 +217,57 @@ def run_c1(dev):
     }
 
 
+def run_c4(dev, steps=3, threads=16):
+    """Ensemble: the 64 instances of ens2d_64 (sides from {128, 192, 256, 384, 512}, mean
+    compositions in [0.13, 0.21]) in mixed precision, stepped together (pfnks_batch_step, one
+    stream per instance) over the first steps of their adaptive trajectories: instance steps/s
+    and node steps/s."""
+    import torch
+
+    from paper_2209_08001_amd import pfnks
+    from paper_2209_08001_amd import workloads as W
+    from paper_2209_08001_amd.driver import adaptive_batch_run
+
+    wl = W.WORKLOADS["ens2d_64"]
+    members = W.ensemble_members(wl)
+
+    def make(ms):
+        out = []
+        for m in ms:
+            c0, e0 = W.init_fields(m["n"], m["seed"], cbar=m["cbar"])
+            sv = _solver_for(W, pfnks, m["n"], "mixed", pfnks.PC_RAS_SPECTRAL)
+            out.append(pfnks.Problem(m["n"], W.H, W.DEFAULT_MODEL, sv, c0, e0, device=dev,
+                                     stream=torch.cuda.Stream(device=dev)))
+        return out
+
+    scratch = make(members[:8])
+    adaptive_batch_run(scratch, 1, wl, threads)
+    for p in scratch:
+        p.close()
+    del scratch
+    probs = make(members)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat, stats = adaptive_batch_run(probs, steps, wl, threads)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    nodes = sum(p.N for p in probs)
+    newton = sum(s["newton_its"] for ss in stats for s in ss)
+    out = {
+        "workload": "ens2d_64", "instances": len(probs), "total_nodes": nodes,
+        "sides": sorted({p.n[0] for p in probs}), "precision": "mixed", "steps": steps,
+        "host_threads": threads,
+        "instance_steps_per_s": len(probs) * steps / elapsed,
+        "node_steps_per_s": nodes * steps / elapsed,
+        "p50_round_ms": 1e3 * percentile(lat, 50), "p99_round_ms": 1e3 * percentile(lat, 99),
+        "newton_per_step": newton / (len(probs) * steps),
+        "gmres_per_newton": sum(s["gmres_its"] for ss in stats for s in ss) / max(newton, 1),
+    }
+    for p in probs:
+        p.close()
+    return out
+
+
 def run_c3(dev, steps=10, warmup=2):
     """3D 128^3, the adaptive trajectory from t = 0: plain FP64 and mixed precision (float
     Krylov basis and preconditioner) over the same step sizes (the mixed run replays the FP64
@@ -418,6 +469,10 @@ def main():
                     help="Gauss-Seidel sweeps of the tile solve (default: workloads.default_sweeps)")
     ap.add_argument("--tile", default=None, help="Schwarz tile, e.g. 32,32 (2D) or 8,8,8 (3D)")
     ap.add_argument("--overlap", type=int, default=None)
+    ap.add_argument("--sor", type=float, default=None,
+                    help="over-relaxation of the tile sweeps (default: workloads.default_omega)")
+    ap.add_argument("--pc-refresh", action="store_true",
+                    help="rebuild the preconditioner at every Newton iteration (default: once per step)")
     ap.add_argument("--autotune", action="store_true",
                     help="pick tile / overlap / sweeps by timing candidates first (reported in config)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
@@ -427,6 +482,7 @@ def main():
     ap.add_argument("--no-c1", action="store_true", help="default workload: skip the 64 x 64 fixed-step object")
     ap.add_argument("--no-c3", action="store_true", help="default workload: skip the 128^3 FP64 / mixed object")
     ap.add_argument("--c3-steps", type=int, default=10)
+    ap.add_argument("--no-c4", action="store_true", help="default workload: skip the 64-instance ensemble object")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--threads", type=int, default=16,
                     help="ensemble workloads: host threads driving the instances (pfnks_batch_step)")
@@ -471,6 +527,9 @@ def main():
         solver["tile"] = t if len(t) == 3 else (t[0], t[1], 1)
     if args.overlap is not None:
         solver["overlap"] = args.overlap
+    solver["pc_refresh"] = 1 if args.pc_refresh else 0
+    if args.sor is not None:
+        solver["sor_omega"] = args.sor
     dev = "cuda:0"
     tuned = None
     if args.autotune:
@@ -541,6 +600,8 @@ def main():
             "tile": list(solver["tile"][:len(n)]),
             "overlap": solver["overlap"],
             "gs_sweeps": solver["sweeps"],
+            "sor_omega": solver.get("sor_omega", 1.0),
+            "pc_refresh": solver["pc_refresh"],
             "autotuned": tuned,
             "gmres_restart": solver["gmres_restart"],
             "newton_rtol": solver["newton_rtol"],
@@ -575,6 +636,10 @@ def main():
     default_line = args.workload == "pf2d_512" and args.precision == "fp64" and args.pc == "ras_spectral"
     if default_line and not args.no_c3:
         out["c3"] = run_c3(dev, steps=args.c3_steps)
+    if default_line and not args.no_c4:
+        out["c4"] = run_c4(dev)
+        # the mixed-precision batched form against this line's plain FP64 form, per node step
+        out["c4"]["vs_fp64_single_node_steps"] = out["c4"]["node_steps_per_s"] / (out["value"] * float(math.prod(n)))
     if default_line and not args.no_c1:
         out["c1"] = run_c1(dev)
     if not args.no_cpu_baseline:

@@ -101,6 +101,7 @@ typedef struct {
   int tile[3];            /* owned tile of the Schwarz preconditioner (tile[2] = 1 in 2D)   */
   int overlap;            /* delta: extra layers of each subdomain on every side (0..4)     */
   int sweeps;             /* symmetric multicolour block Gauss-Seidel sweeps per tile solve */
+  double sor_omega;       /* over-relaxation of those sweeps (SSOR), 0 < omega < 2; 1 = GS */
   pfnks_pc pc;            /* preconditioner                                                 */
   pfnks_precision precision; /* PFNKS_FP64, or PFNKS_MIXED (float Krylov basis and preconditioner) */
   double ls_alpha;        /* Armijo constant of the backtracking line search                */
@@ -110,6 +111,9 @@ typedef struct {
                              contraction theta of consecutive corrections as
                              theta / (1 - theta) max|lambda S_f|, must be <= newton_stol *
                              max|X_f| in every field f (0 = residual test only) */
+  int pc_refresh;         /* 0: the preconditioner is built once per time step, at X^n, and
+                             reused over the Newton iterations (the reuse of Section 5.4);
+                             1: rebuilt at every Newton iteration                         */
 } pfnks_solver;
 
 typedef struct {

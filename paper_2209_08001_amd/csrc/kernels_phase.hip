@@ -30,21 +30,35 @@ struct Pt {
   int i, j, k;
 };
 
-// periodic index for any offset, including halo columns of a block wider than the grid; the
-// common case (inside the grid) costs one unsigned compare
+// Periodic indices.  P2 (every side a power of two): a mask, exact for any offset.  Otherwise
+// two selects, exact for a in [-n, 2n) (a grid point plus a stencil offset, or a block's halo
+// on grids wider than the block), or the remainder for any a (FAR: halos of grids narrower
+// than the block).  The stencil kernels are instantiated for both P2 values.
+template <bool P2>
 __device__ inline int wrap(int a, int n) {
-  if ((unsigned)a < (unsigned)n) return a;
+  if (P2) return a & (n - 1);
+  a += (a < 0) ? n : 0;
+  a -= (a >= n) ? n : 0;
+  return a;
+}
+__device__ inline int wrap_far(int a, int n) {
   const int r = a % n;
   return r < 0 ? r + n : r;
 }
+template <bool P2, bool FAR>
+__device__ inline int wrap_t(int a, int n) {
+  return (FAR && !P2) ? wrap_far(a, n) : wrap<P2>(a, n);
+}
 
+template <bool P2>
 __device__ inline long long at(const Consts& K, Pt p, int di, int dj, int dk) {
-  const int i = wrap(p.i + di, K.nx), j = wrap(p.j + dj, K.ny), k = wrap(p.k + dk, K.nz);
+  const int i = wrap<P2>(p.i + di, K.nx), j = wrap<P2>(p.j + dj, K.ny), k = wrap<P2>(p.k + dk, K.nz);
   return (long long)i + (long long)K.nx * ((long long)j + (long long)K.ny * k);
 }
 
+template <bool P2>
 __device__ inline long long at_dir(const Consts& K, Pt p, int dir, int s) {
-  return at(K, p, dir == 0 ? s : 0, dir == 1 ? s : 0, dir == 2 ? s : 0);
+  return at<P2>(K, p, dir == 0 ? s : 0, dir == 1 ? s : 0, dir == 2 ? s : 0);
 }
 
 __device__ inline Pt shift(Pt p, int dir, int s) {
@@ -85,44 +99,44 @@ __device__ inline Pt coords(const Consts& K, long long n) {
 // Krylov vector) and compute in double.
 
 // 2*d+1 point Laplacian of one plane
-template <typename T>
+template <bool P2, typename T>
 __device__ inline double lap(const Consts& K, const T* __restrict__ f, Pt p, double fc) {
   double s = 0.0;
-  for (int dir = 0; dir < K.dim; ++dir) s += (double)f[at_dir(K, p, dir, 1)] + (double)f[at_dir(K, p, dir, -1)];
+  for (int dir = 0; dir < K.dim; ++dir) s += (double)f[at_dir<P2>(K, p, dir, 1)] + (double)f[at_dir<P2>(K, p, dir, -1)];
   return (s - 2.0 * K.dim * fc) * K.ih2;
 }
 
 // Dhat_dir of one plane at p (p may be an unwrapped neighbour)
-template <typename T>
+template <bool P2, typename T>
 __device__ inline double dhat(const Consts& K, const T* __restrict__ f, Pt p, int dir) {
-  return ((double)f[at_dir(K, p, dir, 1)] - (double)f[at_dir(K, p, dir, -1)]) * K.i2h;
+  return ((double)f[at_dir<P2>(K, p, dir, 1)] - (double)f[at_dir<P2>(K, p, dir, -1)]) * K.i2h;
 }
 
 // sigma_IJ at point p from displacement planes u (d planes) and composition c.
 // xi = 1 includes the eigenstrain -eps0 (c - cbar0) delta_IJ; for a perturbation (J v) the
 // composition enters as -eps0 dc (xi = 1, cref = 0).
-template <typename T>
+template <bool P2, typename T>
 __device__ inline double sigma(const Consts& K, const T* __restrict__ u, long long N,
                                const T* __restrict__ c, double cref, Pt p, int I, int J) {
   if (I != J) {
-    return K.C44 * (dhat(K, u + (long long)J * N, p, I) + dhat(K, u + (long long)I * N, p, J));
+    return K.C44 * (dhat<P2>(K, u + (long long)J * N, p, I) + dhat<P2>(K, u + (long long)I * N, p, J));
   }
-  const double ec = K.eps0 * ((double)c[at(K, p, 0, 0, 0)] - cref);
+  const double ec = K.eps0 * ((double)c[at<P2>(K, p, 0, 0, 0)] - cref);
   double s = 0.0;
   for (int L = 0; L < K.dim; ++L) {
-    const double e = dhat(K, u + (long long)L * N, p, L) - ec;
+    const double e = dhat<P2>(K, u + (long long)L * N, p, L) - ec;
     s += (L == I ? K.C11 : K.C12) * e;
   }
   return s;
 }
 
 // sum_J Dhat_J sigma_IJ at p
-template <typename T>
+template <bool P2, typename T>
 __device__ inline double div_sigma(const Consts& K, const T* __restrict__ u, long long N,
                                    const T* __restrict__ c, double cref, Pt p, int I) {
   double s = 0.0;
   for (int J = 0; J < K.dim; ++J) {
-    s += sigma(K, u, N, c, cref, shift(p, J, 1), I, J) - sigma(K, u, N, c, cref, shift(p, J, -1), I, J);
+    s += sigma<P2>(K, u, N, c, cref, shift(p, J, 1), I, J) - sigma<P2>(K, u, N, c, cref, shift(p, J, -1), I, J);
   }
   return s * K.i2h;
 }
@@ -274,6 +288,7 @@ __device__ inline void chem_dg(const Consts& K, double c1, const double* e1, dou
 // residual
 // ---------------------------------------------------------------------------------
 // pass 1: G_c, G_eta (4 planes) and F_u
+template <bool P2>
 __global__ __launch_bounds__(kBX* kBY) void k_residual_g(Consts K, const double* __restrict__ X,
                                                          const double* __restrict__ Xn,
                                                          double* __restrict__ G4,
@@ -294,21 +309,21 @@ __global__ __launch_bounds__(kBX* kBY) void k_residual_g(Consts K, const double*
   if (K.elastic) {
     double div1 = 0.0, div0 = 0.0;
     for (int I = 0; I < K.dim; ++I) {
-      div1 += dhat(K, X + (4 + I) * N, p, I);
-      div0 += dhat(K, Xn + (4 + I) * N, p, I);
+      div1 += dhat<P2>(K, X + (4 + I) * N, p, I);
+      div0 += dhat<P2>(K, Xn + (4 + I) * N, p, I);
     }
     const double tr1 = K.Ctr * (div1 - K.dim * K.eps0 * (c1 - K.cbar0));
     const double tr0 = K.Ctr * (div0 - K.dim * K.eps0 * (c0 - K.cbar0));
     Gc -= K.eps0 * 0.5 * (tr1 + tr0);
   }
-  Gc -= K.gamma_c * 0.5 * (lap(K, X, p, c1) + lap(K, Xn, p, c0));
+  Gc -= K.gamma_c * 0.5 * (lap<P2>(K, X, p, c1) + lap<P2>(K, Xn, p, c0));
   G4[n] = Gc;
   for (int q = 0; q < 3; ++q) {
-    Ge[q] -= K.gamma_eta * 0.5 * (lap(K, X + (1 + q) * N, p, e1[q]) + lap(K, Xn + (1 + q) * N, p, e0[q]));
+    Ge[q] -= K.gamma_eta * 0.5 * (lap<P2>(K, X + (1 + q) * N, p, e1[q]) + lap<P2>(K, Xn + (1 + q) * N, p, e0[q]));
     G4[(1 + q) * N + n] = Ge[q];
   }
   for (int I = 0; I < K.dim; ++I) {
-    F[(4 + I) * N + n] = K.elastic ? div_sigma(K, X + 4 * N, N, X, K.cbar0, p, I) : X[(4 + I) * N + n];
+    F[(4 + I) * N + n] = K.elastic ? div_sigma<P2>(K, X + 4 * N, N, X, K.cbar0, p, I) : X[(4 + I) * N + n];
   }
 }
 
@@ -325,13 +340,14 @@ __device__ inline double block_sum(double v, double* lds) {
 }
 
 // div_h (M grad_h g) at p with face mobilities from g_n = c^n (1 - c^n)
+template <bool P2>
 __device__ inline double div_M_grad(const Consts& K, const double* __restrict__ g,
                                     const double* __restrict__ cn, Pt p, long long n) {
   const double gc = g[n];
   const double mc = cn[n] * (1.0 - cn[n]);
   double s = 0.0;
   for (int dir = 0; dir < K.dim; ++dir) {
-    const long long np = at_dir(K, p, dir, 1), nm = at_dir(K, p, dir, -1);
+    const long long np = at_dir<P2>(K, p, dir, 1), nm = at_dir<P2>(K, p, dir, -1);
     const double Mp = 0.5 * K.kappa * (mc + cn[np] * (1.0 - cn[np]));
     const double Mm = 0.5 * K.kappa * (mc + cn[nm] * (1.0 - cn[nm]));
     s += Mp * (g[np] - gc) - Mm * (gc - g[nm]);
@@ -340,6 +356,7 @@ __device__ inline double div_M_grad(const Consts& K, const double* __restrict__ 
 }
 
 // pass 2: F_c, F_eta; partial[0] = ||F||^2, partial[1] = number of nodes outside the log domain
+template <bool P2>
 __global__ __launch_bounds__(256) void k_residual_f(Consts K, double dt, const double* __restrict__ X,
                                                     const double* __restrict__ Xn,
                                                     const double* __restrict__ G4,
@@ -352,7 +369,7 @@ __global__ __launch_bounds__(256) void k_residual_f(Consts K, double dt, const d
   for (long long n = (long long)blockIdx.x * 256 + threadIdx.x; n < N; n += (long long)gridDim.x * 256) {
     const Pt p = coords(K, n);
     const double c1 = X[n];
-    const double fc = (c1 - Xn[n]) * idt - div_M_grad(K, G4, Xn, p, n);
+    const double fc = (c1 - Xn[n]) * idt - div_M_grad<P2>(K, G4, Xn, p, n);
     F[n] = fc;
     nrm += fc * fc;
     bool ok = (c1 > 0.0 && c1 < 1.0);
@@ -412,19 +429,19 @@ __global__ __launch_bounds__(256) void k_linearise(Consts K, const double* __res
 //   (Jv)_u = sum_J Dhat_J sigma_IJ(v_u, v_c)   (composition enters through -eps0 v_c)
 // ---------------------------------------------------------------------------------
 // dG_c of the J v product at point p (p may lie one node outside the block: wrapped here)
-template <int DIM, typename Tv>
+template <bool P2, int DIM, typename Tv>
 __device__ inline double jv_dg(const Consts& K, const double* __restrict__ B, const Tv* __restrict__ v, Pt p) {
   const long long N = K.N, n = lin(K, p);
   double vv[4];
 #pragma unroll
   for (int f = 0; f < 4; ++f) vv[f] = v[f * N + n];
-  double g = K.kel * vv[0] - 0.5 * K.gamma_c * lap(K, v, p, vv[0]);
+  double g = K.kel * vv[0] - 0.5 * K.gamma_c * lap<P2>(K, v, p, vv[0]);
 #pragma unroll
   for (int f = 0; f < 4; ++f) g += B[f * N + n] * vv[f];
   if (K.elastic) {
     double div = 0.0;
 #pragma unroll
-    for (int I = 0; I < DIM; ++I) div += dhat(K, v + (4 + I) * N, p, I);
+    for (int I = 0; I < DIM; ++I) div += dhat<P2>(K, v + (4 + I) * N, p, I);
     g += -0.5 * K.eps0 * K.Ctr * div;
   }
   return g;
@@ -432,7 +449,7 @@ __device__ inline double jv_dg(const Consts& K, const double* __restrict__ B, co
 
 // the rows of J v at p: the c row from dG in LDS (sdg[hq], its neighbours in direction dir at
 // sdg[hq + up[dir]] and sdg[hq + dn[dir]]), the eta and u rows as local stencils
-template <int DIM, typename Tv>
+template <bool P2, int DIM, typename Tv>
 __device__ inline void jv_rows(const Consts& K, double idt, const double* __restrict__ B,
                                const double* __restrict__ cn, const Tv* __restrict__ v,
                                double* __restrict__ w, Pt p, const double* sdg, int hq, const int* up,
@@ -444,7 +461,7 @@ __device__ inline void jv_rows(const Consts& K, double idt, const double* __rest
     double s = 0.0;
 #pragma unroll
     for (int dir = 0; dir < DIM; ++dir) {
-      const long long np = at_dir(K, p, dir, 1), nm = at_dir(K, p, dir, -1);
+      const long long np = at_dir<P2>(K, p, dir, 1), nm = at_dir<P2>(K, p, dir, -1);
       const double Mp = 0.5 * K.kappa * (mc + cn[np] * (1.0 - cn[np]));
       const double Mm = 0.5 * K.kappa * (mc + cn[nm] * (1.0 - cn[nm]));
       s += Mp * (sdg[hq + up[dir]] - g0) - Mm * (g0 - sdg[hq + dn[dir]]);
@@ -456,14 +473,14 @@ __device__ inline void jv_rows(const Consts& K, double idt, const double* __rest
   for (int q = 0; q < 4; ++q) vv[q] = v[q * N + n];
 #pragma unroll
   for (int e = 0; e < 3; ++e) {
-    double s = -0.5 * K.gamma_eta * lap(K, v + (1 + e) * N, p, vv[1 + e]);
+    double s = -0.5 * K.gamma_eta * lap<P2>(K, v + (1 + e) * N, p, vv[1 + e]);
 #pragma unroll
     for (int q = 0; q < 4; ++q) s += B[(4 * (1 + e) + q) * N + n] * vv[q];
     w[(1 + e) * N + n] = vv[1 + e] * idt + K.L_eta * s;
   }
 #pragma unroll
   for (int I = 0; I < DIM; ++I) {
-    w[(4 + I) * N + n] = K.elastic ? div_sigma(K, v + 4 * N, N, v, 0.0, p, I) : (double)v[(4 + I) * N + n];
+    w[(4 + I) * N + n] = K.elastic ? div_sigma<P2>(K, v + 4 * N, N, v, 0.0, p, I) : (double)v[(4 + I) * N + n];
   }
 }
 
@@ -473,7 +490,7 @@ __device__ inline void jv_rows(const Consts& K, double idt, const double* __rest
 // type Tv (double, or float for a mixed-precision Krylov vector); the arithmetic and w are
 // double.
 constexpr int kJY2 = 8;
-template <typename Tv>
+template <typename Tv, bool P2, bool FAR>
 __global__ __launch_bounds__(kBX* kJY2) void k_jv2(Consts K, double dt, const double* __restrict__ B,
                                                    const double* __restrict__ cn, const Tv* __restrict__ v,
                                                    double* __restrict__ w) {
@@ -491,11 +508,11 @@ __global__ __launch_bounds__(kBX* kJY2) void k_jv2(Consts K, double dt, const do
   const long long N = K.N;
   for (int q = tid; q < 6 * SP; q += kBX * kJY2) {
     const int f = q / SP, r = q - f * SP, a = r % SX, b = r / SX;
-    sv[q] = (double)v[f * N + wrap(i0 + a - 2, K.nx) + (long long)K.nx * wrap(j0 + b - 2, K.ny)];
+    sv[q] = (double)v[f * N + wrap_t<P2, FAR>(i0 + a - 2, K.nx) + (long long)K.nx * wrap_t<P2, FAR>(j0 + b - 2, K.ny)];
   }
   for (int q = tid; q < HP; q += kBX * kJY2) {
     const int a = q % HX, b = q / HX;
-    const double c = cn[wrap(i0 + a - 1, K.nx) + (long long)K.nx * wrap(j0 + b - 1, K.ny)];
+    const double c = cn[wrap_t<P2, FAR>(i0 + a - 1, K.nx) + (long long)K.nx * wrap_t<P2, FAR>(j0 + b - 1, K.ny)];
     sg[q] = c * (1.0 - c);
   }
   __syncthreads();
@@ -520,7 +537,7 @@ __global__ __launch_bounds__(kBX* kJY2) void k_jv2(Consts K, double dt, const do
   // dG on the block and its halo of 1 (halo point (a, b) sits at v position (a + 1, b + 1))
   for (int q = tid; q < HP; q += kBX * kJY2) {
     const int a = q % HX, b = q / HX, ci = (a + 1) + SX * (b + 1);
-    const long long n = wrap(i0 + a - 1, K.nx) + (long long)K.nx * wrap(j0 + b - 1, K.ny);
+    const long long n = wrap_t<P2, FAR>(i0 + a - 1, K.nx) + (long long)K.nx * wrap_t<P2, FAR>(j0 + b - 1, K.ny);
     double vv[4];
 #pragma unroll
     for (int f = 0; f < 4; ++f) vv[f] = sv[f * SP + ci];
@@ -580,7 +597,7 @@ __global__ __launch_bounds__(kBX* kJY2) void k_jv2(Consts K, double dt, const do
 // planes of dG (with their one-node halo in x and y) in LDS, so dG is formed once per node
 // and halo column instead of once per node of a 3 x 3 x 3 neighbourhood.
 constexpr int kJZ = 4;
-template <typename Tv>
+template <typename Tv, bool P2, bool FAR>
 __global__ __launch_bounds__(kBX* kBY) void k_jv3(Consts K, double dt, const double* __restrict__ B,
                                                   const double* __restrict__ cn, const Tv* __restrict__ v,
                                                   double* __restrict__ w, int zc) {
@@ -594,7 +611,8 @@ __global__ __launch_bounds__(kBX* kBY) void k_jv3(Consts K, double dt, const dou
     double* dst = sdg + ((z + 3) % 3) * HP;
     for (int q = tid; q < HP; q += kBX * kBY) {
       const int a = q % HX, b = q / HX;
-      dst[q] = jv_dg<3>(K, B, v, Pt{wrap(i0 + a - 1, K.nx), wrap(j0 + b - 1, K.ny), wrap(z, K.nz)});
+      dst[q] = jv_dg<P2, 3>(K, B, v, Pt{wrap_t<P2, FAR>(i0 + a - 1, K.nx), wrap_t<P2, FAR>(j0 + b - 1, K.ny),
+                                        wrap_t<P2, FAR>(z, K.nz)});
     }
   };
   plane(z0 - 1);
@@ -611,7 +629,7 @@ __global__ __launch_bounds__(kBX* kBY) void k_jv3(Consts K, double dt, const dou
       const int hq = sz * HP + (threadIdx.x + 1) + HX * (threadIdx.y + 1);
       const int up[3] = {1, HX, ((z + 4) % 3 - sz) * HP};
       const int dn[3] = {-1, -HX, ((z + 2) % 3 - sz) * HP};
-      jv_rows<3>(K, idt, B, cn, v, w, Pt{i0 + (int)threadIdx.x, j0 + (int)threadIdx.y, z}, sdg, hq, up, dn);
+      jv_rows<P2, 3>(K, idt, B, cn, v, w, Pt{i0 + (int)threadIdx.x, j0 + (int)threadIdx.y, z}, sdg, hq, up, dn);
     }
     __syncthreads();
   }
@@ -622,6 +640,7 @@ __global__ __launch_bounds__(kBX* kBY) void k_jv3(Consts K, double dt, const dou
 // ---------------------------------------------------------------------------------
 __device__ inline double psi(double z) { return z * log(z) + (1.0 - z) * log(1.0 - z); }
 
+template <bool P2>
 __global__ __launch_bounds__(256) void k_energy(Consts K, const double* __restrict__ X,
                                                 double* __restrict__ partial) {
   __shared__ double lds[4];
@@ -649,9 +668,9 @@ __global__ __launch_bounds__(256) void k_energy(Consts K, const double* __restri
       double s = 0.0;
       for (int I = 0; I < K.dim; ++I)
         for (int J = 0; J < K.dim; ++J) {
-          double eij = 0.5 * (dhat(K, X + (4 + I) * N, p, J) + dhat(K, X + (4 + J) * N, p, I));
+          double eij = 0.5 * (dhat<P2>(K, X + (4 + I) * N, p, J) + dhat<P2>(K, X + (4 + J) * N, p, I));
           if (I == J) eij -= K.eps0 * (c - K.cbar0);
-          s += eij * sigma(K, X + 4 * N, N, X, K.cbar0, p, I, J);
+          s += eij * sigma<P2>(K, X + 4 * N, N, X, K.cbar0, p, I, J);
         }
       eel += 0.5 * s;
     }
@@ -662,7 +681,7 @@ __global__ __launch_bounds__(256) void k_energy(Consts K, const double* __restri
       const double wc = w[n];
       double s = 0.0;
       for (int dir = 0; dir < K.dim; ++dir) {
-        const double dp = (w[at_dir(K, p, dir, 1)] - wc) * K.ih, dm = (wc - w[at_dir(K, p, dir, -1)]) * K.ih;
+        const double dp = (w[at_dir<P2>(K, p, dir, 1)] - wc) * K.ih, dm = (wc - w[at_dir<P2>(K, p, dir, -1)]) * K.ih;
         s += 0.5 * (dp * dp + dm * dm);
       }
       ein += 0.5 * gam * s;
@@ -685,10 +704,20 @@ dim3 stencil_grid(const Consts& K) {
 
 }  // namespace
 
+bool pow2_sides(const Consts& K) {
+  auto p2 = [](int n) { return (n & (n - 1)) == 0; };
+  return p2(K.nx) && p2(K.ny) && p2(K.nz);
+}
+
 void launch_residual(const Consts& K, double dt, const double* X, const double* Xn, double* G4,
                      double* F, double* partial, hipStream_t s) {
-  hipLaunchKernelGGL(k_residual_g, stencil_grid(K), dim3(kBX, kBY), 0, s, K, X, Xn, G4, F);
-  hipLaunchKernelGGL(k_residual_f, dim3(kRedBlocks), dim3(256), 0, s, K, dt, X, Xn, G4, F, partial);
+  if (pow2_sides(K)) {
+    hipLaunchKernelGGL(k_residual_g<true>, stencil_grid(K), dim3(kBX, kBY), 0, s, K, X, Xn, G4, F);
+    hipLaunchKernelGGL(k_residual_f<true>, dim3(kRedBlocks), dim3(256), 0, s, K, dt, X, Xn, G4, F, partial);
+  } else {
+    hipLaunchKernelGGL(k_residual_g<false>, stencil_grid(K), dim3(kBX, kBY), 0, s, K, X, Xn, G4, F);
+    hipLaunchKernelGGL(k_residual_f<false>, dim3(kRedBlocks), dim3(256), 0, s, K, dt, X, Xn, G4, F, partial);
+  }
 }
 
 void launch_linearise(const Consts& K, const double* X, const double* Xn, double* B, float* Bf,
@@ -700,13 +729,23 @@ void launch_linearise(const Consts& K, const double* X, const double* Xn, double
 template <typename Tv>
 void launch_jv(const Consts& K, double dt, const double* B, const double* cn, const Tv* v, double* w,
                hipStream_t s) {
+  const bool p2 = pow2_sides(K);
   if (K.dim == 2) {
     const dim3 g((K.nx + kBX - 1) / kBX, (K.ny + kJY2 - 1) / kJY2, 1);
-    hipLaunchKernelGGL((k_jv2<Tv>), g, dim3(kBX, kJY2), 0, s, K, dt, B, cn, v, w);
+    // halo positions run from -2 to (blocks x block side) + 1: the two-select wrap holds while
+    // that stays below 2n (sides are >= 4)
+    const bool far = !((int)g.x * kBX + 1 < 2 * K.nx && (int)g.y * kJY2 + 1 < 2 * K.ny);
+    if (p2) hipLaunchKernelGGL((k_jv2<Tv, true, false>), g, dim3(kBX, kJY2), 0, s, K, dt, B, cn, v, w);
+    else if (far) hipLaunchKernelGGL((k_jv2<Tv, false, true>), g, dim3(kBX, kJY2), 0, s, K, dt, B, cn, v, w);
+    else hipLaunchKernelGGL((k_jv2<Tv, false, false>), g, dim3(kBX, kJY2), 0, s, K, dt, B, cn, v, w);
   } else {
     const int zc = K.nz < kJZ ? K.nz : kJZ;
     const dim3 g((K.nx + kBX - 1) / kBX, (K.ny + kBY - 1) / kBY, (K.nz + zc - 1) / zc);
-    hipLaunchKernelGGL((k_jv3<Tv>), g, dim3(kBX, kBY), 0, s, K, dt, B, cn, v, w, zc);
+    // halo columns run from -1 to (blocks x block side), planes from z0 - 1 to z0 + zc
+    const bool far = !((int)g.x * kBX < 2 * K.nx && (int)g.y * kBY < 2 * K.ny && (int)g.z * zc < 2 * K.nz);
+    if (p2) hipLaunchKernelGGL((k_jv3<Tv, true, false>), g, dim3(kBX, kBY), 0, s, K, dt, B, cn, v, w, zc);
+    else if (far) hipLaunchKernelGGL((k_jv3<Tv, false, true>), g, dim3(kBX, kBY), 0, s, K, dt, B, cn, v, w, zc);
+    else hipLaunchKernelGGL((k_jv3<Tv, false, false>), g, dim3(kBX, kBY), 0, s, K, dt, B, cn, v, w, zc);
   }
 }
 template void launch_jv<double>(const Consts&, double, const double*, const double*, const double*, double*,
@@ -715,7 +754,8 @@ template void launch_jv<float>(const Consts&, double, const double*, const doubl
                                hipStream_t);
 
 void launch_energy(const Consts& K, const double* X, double* partial, hipStream_t s) {
-  hipLaunchKernelGGL(k_energy, dim3(kRedBlocks), dim3(256), 0, s, K, X, partial);
+  if (pow2_sides(K)) hipLaunchKernelGGL(k_energy<true>, dim3(kRedBlocks), dim3(256), 0, s, K, X, partial);
+  else hipLaunchKernelGGL(k_energy<false>, dim3(kRedBlocks), dim3(256), 0, s, K, X, partial);
 }
 
 }  // namespace pf

@@ -50,6 +50,7 @@ struct Geo {
   int tx, ty, tz, ov;
   int sweeps;
   int mode;            // kRasLeft, kRasClassical or kRasRight
+  double omega;        // over-relaxation of the block updates (1: plain Gauss-Seidel)
 };
 
 __device__ inline int wrapg(int a, int n) {
@@ -263,6 +264,7 @@ __global__ __launch_bounds__(TH, (ras_waves_per_eu<TH>())) void k_ras(Consts K, 
   const R cge = (R)(0.5 * K.L_eta * K.gamma_eta * K.ih2);  // eta-row neighbour coefficient
   const R dgc = (R)(K.kel + K.gamma_c * DIM * K.ih2);    // d dG / d z_c at the node (besides B_cc)
   const R dgn = (R)(-0.5 * K.gamma_c * K.ih2);           // d dG / d z_c at a neighbour
+  const R om = (R)G.omega;
   // Per node, the diagonal block of the tile operator (the node's own unknowns) is
   //   [d_cc  u'  ]      d_cc = 1/dt + sc (B_cc + kel + gamma_c (2 DIM + 1) / (2 h^2)),
   //   [v     E   ]      u_e = sc B_ce, v_e = L_eta B_ec, E = dee I + L_eta B_ee,
@@ -281,8 +283,9 @@ __global__ __launch_bounds__(TH, (ras_waves_per_eu<TH>())) void k_ras(Consts K, 
     for (int f = 1; f < NFZ; ++f) zv[f] = zs[(f - ZP0) * zsz + zi];
     // c row residual: r_c - (z_c/dt - div_h(M grad_h dG)); the dG values at the node and its
     // neighbours are kept for the write-back below
-    R sumM = R(0), dM[3] = {R(0), R(0), R(0)};
-    R divm = R(0);
+    // (the sums start from their first term: x + 0 is not folded away in floating point)
+    R sumM, dM[3] = {R(0), R(0), R(0)};
+    R divm;
     const R g0 = gg[di], dg0 = dg[di];
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
@@ -290,8 +293,9 @@ __global__ __launch_bounds__(TH, (ras_waves_per_eu<TH>())) void k_ras(Consts K, 
       dgm[d] = dg[di - sdir_d[d]];
       const R Mp = hk * (g0 + gg[di + sdir_d[d]]);
       const R Mm = hk * (g0 + gg[di - sdir_d[d]]);
-      divm += Mp * (dgp[d] - dg0) - Mm * (dg0 - dgm[d]);
-      sumM += Mp + Mm;
+      const R dv = Mp * (dgp[d] - dg0) - Mm * (dg0 - dgm[d]);
+      divm = (d == 0) ? dv : divm + dv;
+      sumM = (d == 0) ? Mp + Mm : sumM + (Mp + Mm);
       dM[d] = Mm - Mp;
     }
     R xc = rv[0] - (zv[0] * idt - divm * ih2);
@@ -300,9 +304,9 @@ __global__ __launch_bounds__(TH, (ras_waves_per_eu<TH>())) void k_ras(Consts K, 
 #pragma unroll
     for (int e = 0; e < 3; ++e) {
       const int ze = (1 + e - ZP0) * zsz + zi;
-      R nb = R(0);
+      R nb = zs[ze + 1] + zs[ze - 1];
 #pragma unroll
-      for (int d = 0; d < DIM; ++d) nb += zs[ze + sdir_z[d]] + zs[ze - sdir_z[d]];
+      for (int d = 1; d < DIM; ++d) nb += zs[ze + sdir_z[d]] + zs[ze - sdir_z[d]];
       rh[e] = rv[1 + e] + cge * nb;
     }
     R y[3];
@@ -343,10 +347,14 @@ __global__ __launch_bounds__(TH, (ras_waves_per_eu<TH>())) void k_ras(Consts K, 
     R bcv[4];
 #pragma unroll
     for (int f = 0; f < 4; ++f) bcv[f] = bc[f * ne + q];
-    R t = R(0);
+    R t = bcv[1] * (y[0] - zv[1] - w[0] * zv[0]);
 #pragma unroll
-    for (int e = 0; e < 3; ++e) t += bcv[1 + e] * (y[e] - zv[1 + e] - w[e] * zv[0]);
+    for (int e = 1; e < 3; ++e) t += bcv[1 + e] * (y[e] - zv[1 + e] - w[e] * zv[0]);
     xc = (xc - sc * t) * id;
+    // over-relaxed block update: z <- z + omega (z_GS - z), z_GS the block Gauss-Seidel values
+    // (c from the Schur form, eta = y - w c_GS)
+    const R zcg = zv[0] + xc;
+    xc *= om;
     const R zc = zv[0] + xc;
     if (WU) zs[zi] = zc;
     else zcr = zc;
@@ -354,13 +362,16 @@ __global__ __launch_bounds__(TH, (ras_waves_per_eu<TH>())) void k_ras(Consts K, 
     dz[0] = xc;
 #pragma unroll
     for (int e = 0; e < 3; ++e) {
-      const R ze = y[e] - w[e] * zc;
-      zs[(1 + e - ZP0) * zsz + zi] = ze;
-      dz[1 + e] = ze - zv[1 + e];
+      const R dze = om * (y[e] - w[e] * zcg - zv[1 + e]);
+      zs[(1 + e - ZP0) * zsz + zi] = zv[1 + e] + dze;
+      dz[1 + e] = dze;
     }
     if (WU) {
 #pragma unroll
-      for (int I = 0; I < DIM; ++I) zs[(4 + I) * zsz + zi] = zv[4 + I] + xu[I];
+      for (int I = 0; I < DIM; ++I) {
+        xu[I] *= om;
+        zs[(4 + I) * zsz + zi] = zv[4 + I] + xu[I];
+      }
     }
     // dG follows the change: at the node through B_c, kel and the centre of the Laplacian, at
     // the 2 DIM neighbours through the Laplacian (and the divergence of u).  Nodes of one
@@ -373,9 +384,14 @@ __global__ __launch_bounds__(TH, (ras_waves_per_eu<TH>())) void k_ras(Consts K, 
     const R dn = dgn * xc;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
-      const R du = WU ? a_u * xu[d] : R(0);
-      dg[di + sdir_d[d]] = dgp[d] + (dn - du);
-      dg[di - sdir_d[d]] = dgm[d] + (dn + du);
+      if (WU) {
+        const R du = a_u * xu[d];
+        dg[di + sdir_d[d]] = dgp[d] + (dn - du);
+        dg[di - sdir_d[d]] = dgm[d] + (dn + du);
+      } else {
+        dg[di + sdir_d[d]] = dgp[d] + dn;
+        dg[di - sdir_d[d]] = dgm[d] + dn;
+      }
     }
   };
 
@@ -522,6 +538,7 @@ Geo make_geo(const Consts& K, const TileCfg& T) {
   G.tz = (K.dim == 3) ? T.tz : 1;
   G.ov = T.ov;
   G.sweeps = T.sweeps;
+  G.omega = T.omega;
   G.ex = T.tx + 2 * T.ov;
   G.ey = T.ty + 2 * T.ov;
   G.ez = (K.dim == 3) ? T.tz + 2 * T.ov : 1;

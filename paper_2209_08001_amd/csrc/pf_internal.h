@@ -53,6 +53,7 @@ struct TileCfg {
   int tx, ty, tz;   // owned tile
   int ov;           // overlap delta
   int sweeps;       // symmetric GS sweeps
+  double omega;     // over-relaxation factor of the sweeps (1: Gauss-Seidel)
   int with_u;       // 1: all fields (plain RAS); 0: (c, eta) block only
   const int* perm;  // device: nodes of the extended tile sorted by colour (ras_colour_order),
                     // followed by the inverse order (colour position of each node)

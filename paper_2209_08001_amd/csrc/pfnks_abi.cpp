@@ -151,6 +151,8 @@ int validate(const pfnks_grid* g, const pfnks_model* m, const pfnks_solver* s) {
   if (s->sweeps < 1 || s->sweeps > 16) return PFNKS_EINVAL;
   if (s->newton_maxit < 1 || s->gmres_maxit < 1) return PFNKS_EINVAL;
   if (!(s->newton_stol >= 0.0)) return PFNKS_EINVAL;
+  if (s->pc_refresh != 0 && s->pc_refresh != 1) return PFNKS_EINVAL;
+  if (!(s->sor_omega > 0.0 && s->sor_omega < 2.0)) return PFNKS_EINVAL;
   if (s->pc < PFNKS_PC_RAS || s->pc > PFNKS_PC_RRAS) return PFNKS_EINVAL;
   if (sums_overlap(s->pc))
     for (int k = 0; k < g->dim; ++k)
@@ -674,6 +676,7 @@ int pfnks_create_problem(const pfnks_grid* grid, const pfnks_model* model, const
   p->T.tz = (grid->dim == 3) ? solver->tile[2] : 1;
   p->T.ov = solver->overlap;
   p->T.sweeps = solver->sweeps;
+  p->T.omega = solver->sor_omega;
   p->T.with_u = 0;
   p->T.perm = (const int*)(p->ws + L.off[B_PERM]);
   p->T.mode = 0;
@@ -801,19 +804,22 @@ int pfnks_step(pfnks_problem* p, double dt, pfnks_step_stats* stats) {
   double upd_rel = 0.0;
   double ds_prev[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // per-field max|lambda S_f| of the last correction
   for (; !converged && newton < sv.newton_maxit; ++newton) {
-    // linearise at X; the preconditioner blocks are set up once per step (lagged)
+    // linearise at X; the preconditioner blocks are set up once per step (lagged over the
+    // Newton iterations, the paper's factorisation reuse) or, with pc_refresh, at every
+    // Newton iteration
     double* Bm = p->B;
     {
       const bool mixed = sv.precision == PFNKS_MIXED;
+      const bool build_pc = (newton == 0) || sv.pc_refresh;
       Prof pr(p, PFNKS_K_LINEARISE,
-              8.0 * 24 * N + ((newton == 0 && mixed) ? 64.0 * N : 0.0) + ((newton == 0) ? pack_bytes(p) : 0.0));
-      if (newton == 0 && !mixed) {
+              8.0 * 24 * N + ((build_pc && mixed) ? 64.0 * N : 0.0) + (build_pc ? pack_bytes(p) : 0.0));
+      if (build_pc && !mixed) {
         pf::launch_linearise(p->K, p->X, p->Xn, (double*)p->Bpc, nullptr, p->stream);
         Bm = (double*)p->Bpc;
       } else {
-        pf::launch_linearise(p->K, p->X, p->Xn, p->B, (newton == 0) ? (float*)p->Bpc : nullptr, p->stream);
+        pf::launch_linearise(p->K, p->X, p->Xn, p->B, build_pc ? (float*)p->Bpc : nullptr, p->stream);
       }
-      if (newton == 0) pc_setup(p, dt);
+      if (build_pc) pc_setup(p, dt);
     }
     p->launches += 1;
     const double tol = std::fmax(sv.gmres_rtol * fn, xi_a);

@@ -62,9 +62,10 @@ class pfnks_solver(ctypes.Structure):
         ("newton_maxit", ctypes.c_int), ("gmres_rtol", ctypes.c_double),
         ("gmres_atol_rms", ctypes.c_double), ("gmres_restart", ctypes.c_int),
         ("gmres_maxit", ctypes.c_int), ("tile", ctypes.c_int * 3), ("overlap", ctypes.c_int),
-        ("sweeps", ctypes.c_int), ("pc", ctypes.c_int), ("precision", ctypes.c_int),
+        ("sweeps", ctypes.c_int), ("sor_omega", ctypes.c_double), ("pc", ctypes.c_int),
+        ("precision", ctypes.c_int),
         ("ls_alpha", ctypes.c_double), ("ls_max_halvings", ctypes.c_int),
-        ("newton_stol", ctypes.c_double),
+        ("newton_stol", ctypes.c_double), ("pc_refresh", ctypes.c_int),
     ]
 
 
@@ -178,11 +179,13 @@ def make_solver(d, dim):
     s.tile[0], s.tile[1], s.tile[2] = t[0], t[1], (t[2] if dim == 3 else 1)
     s.overlap = d["overlap"]
     s.sweeps = d.get("sweeps", 6)
+    s.sor_omega = float(d.get("sor_omega", 1.0))
     s.pc = d.get("pc", PC_RAS_SPECTRAL)
     s.precision = d.get("precision", FP64)
     s.ls_alpha = d["ls_alpha"]
     s.ls_max_halvings = d["ls_max_halvings"]
     s.newton_stol = d.get("newton_stol", 0.0)
+    s.pc_refresh = int(d.get("pc_refresh", 0))
     return s
 
 

@@ -97,3 +97,17 @@ def test_autotune_candidates_against_host_validation(name, default):
                 assert e.status == pfnks.PFNKS_EINVAL, (cand, e)
         assert default in accepted
         assert len(accepted) >= (2 * len(cands)) // 3, (precision, len(accepted), len(cands))
+
+
+@pytest.mark.parametrize("dim,ncol", [(2, 5), (3, 7)])
+def test_tile_colourings_separate_every_diamond(dim, ncol):
+    """The multicolour orders of the Schwarz tile solve: colour (a + 2b) mod 5 in 2D,
+    (a + 2b + 3c) mod 7 in 3D.  Two nodes coupled by the Jacobian (|da| + |db| (+ |dc|) <= 2,
+    the 13- and 25-point diamonds) never share a colour, so a colour's nodes update at once
+    exactly as sequential Gauss-Seidel would."""
+    w = (1, 2, 3)[:dim]
+    offsets = [o for o in np.ndindex(*(5,) * dim)]
+    for o in offsets:
+        d = [x - 2 for x in o]
+        if 0 < sum(abs(x) for x in d) <= 2:
+            assert sum(wi * di for wi, di in zip(w, d)) % ncol != 0, d
