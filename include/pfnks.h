@@ -210,6 +210,26 @@ int pfnks_debug_jv(pfnks_problem* p, const double* X, double dt, const double* v
 /* z = M^{-1} r, the preconditioner built at X (current state as X^n).  r, z: host planes. */
 int pfnks_debug_pc(pfnks_problem* p, const double* X, double dt, const double* r, double* z);
 
+/* ---- allocation-free residual ------------------------------------------------------ */
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the residual F(X; X^n, dt) of pfnks_debug_residual,
+ * on device arrays and without a problem handle.  Its scratch (the four G planes between the
+ * two stencil passes and the reductions' partial sums) is a file-scope device array of the
+ * library, 64 MiB + 17 KiB per GPU, held from first use until the process ends; the call
+ * allocates nothing (no hipMalloc, no pinned memory, no library allocation).
+ * grid, model: as for pfnks_create_problem, at most 2^21 nodes (PFNKS_ENOSPACE beyond).
+ * cbar0: the eigenstrain's reference composition (mean of c^0 at creation).
+ * d_X, d_Xn: 4 + dim device planes (X, and X^n); d_F: 4 + dim device planes, written.
+ * norm, bad (host, may be NULL): ||F||_2 and the count of nodes of X outside the log domain;
+ * when either is given the call synchronises the stream, otherwise it only enqueues work on
+ * hip_stream (the device of the current context).  Every call on one GPU shares that GPU's
+ * scratch: calls that overlap on one GPU (distinct streams or threads) race.
+ * Errors: PFNKS_EINVAL, PFNKS_ENOSPACE, PFNKS_EDEVICE. */
+int pfnks_residual_static(const pfnks_grid* grid, const pfnks_model* model, double cbar0, double dt,
+                          const double* d_X, const double* d_Xn, double* d_F, double* norm, double* bad,
+                          void* hip_stream);
+
 /* Counters of the last pfnks_step: kernel launches and host synchronisations. */
 int pfnks_debug_counters(pfnks_problem* p, long long* launches, long long* syncs);
 

@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -622,9 +623,84 @@ int check_domain_host(const double* c, const double* eta, long long N) {
   return PFNKS_OK;
 }
 
+// ---------------------------------------------------------------------------------------
+// allocation-free residual: file-scope device scratch
+// ---------------------------------------------------------------------------------------
+// Largest grid of pfnks_residual_static, and its scratch: the four G planes of the residual's
+// first pass, then the reductions' per-block partial sums (two values) and their two sums.
+constexpr long long kStaticMaxNodes = 1LL << 21;
+constexpr size_t kStaticG = 4 * (size_t)kStaticMaxNodes;
+constexpr size_t kStaticDoubles = kStaticG + 2 * (size_t)pf::kRedBlocks + 64;
+static __device__ __align__(256) double scratch[kStaticDoubles];
+
+// Device address of `scratch` on each GPU (each holds its own copy), taken once per device
+// with that device current.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+int static_scratch(double** out) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return PFNKS_EINVAL;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[dev] = (double*)ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return PFNKS_OK;
+}
+
+int validate_grid_model(const pfnks_grid* g, const pfnks_model* m) {
+  if (!g || !m) return PFNKS_EINVAL;
+  if (g->dim != 2 && g->dim != 3) return PFNKS_EINVAL;
+  if (!(g->h > 0.0)) return PFNKS_EINVAL;
+  for (int k = 0; k < g->dim; ++k)
+    if (!fft_side(g->n[k])) return PFNKS_EINVAL;
+  if (g->dim == 2 && g->n[2] != 1) return PFNKS_EINVAL;
+  if (m->S < 1 || m->S > pf::kMaxS) return PFNKS_EINVAL;
+  if (!(m->kappa >= 0.0) || !(m->L_eta > 0.0) || m->Lscale < 0.0) return PFNKS_EINVAL;
+  return PFNKS_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+int pfnks_residual_static(const pfnks_grid* grid, const pfnks_model* model, double cbar0, double dt,
+                          const double* d_X, const double* d_Xn, double* d_F, double* norm, double* bad,
+                          void* hip_stream) {
+  int st = validate_grid_model(grid, model);
+  if (st) return st;
+  if (!d_X || !d_Xn || !d_F || !(dt > 0.0) || !std::isfinite(dt) || !std::isfinite(cbar0)) return PFNKS_EINVAL;
+  const long long N = (long long)grid->n[0] * grid->n[1] * (grid->dim == 3 ? grid->n[2] : 1);
+  if (N > kStaticMaxNodes) return PFNKS_ENOSPACE;
+  double* scr = nullptr;
+  st = static_scratch(&scr);
+  if (st) return st;
+  pfnks_grid g = *grid;
+  if (g.dim == 2) g.n[2] = 1;
+  Consts K = consts_of(g, *model);
+  K.cbar0 = cbar0;
+  hipStream_t s = (hipStream_t)hip_stream;
+  double* G4 = scr;
+  double* part = scr + kStaticG;
+  double* red = part + 2 * pf::kRedBlocks;
+  pf::launch_residual(K, dt, d_X, d_Xn, G4, d_F, part, s);
+  HIPCHK(hipGetLastError());
+  if (norm || bad) {
+    pf::launch_finalize(part, 2, red, s);
+    HIPCHK(hipGetLastError());
+    double h[2];
+    HIPCHK(hipMemcpyAsync(h, red, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (norm) *norm = std::sqrt(h[0]);
+    if (bad) *bad = h[1];
+  }
+  return PFNKS_OK;
+}
 
 int pfnks_workspace_bytes(const pfnks_grid* grid, const pfnks_model* model, const pfnks_solver* solver,
                           size_t* bytes) {

@@ -35,7 +35,7 @@ EXPORTED = [
     "pfnks_workspace_bytes", "pfnks_create_problem", "pfnks_step", "pfnks_energy", "pfnks_mass",
     "pfnks_get_state", "pfnks_set_state", "pfnks_destroy", "pfnks_strerror", "pfnks_last_error",
     "pfnks_debug_residual", "pfnks_debug_jv", "pfnks_debug_pc", "pfnks_debug_counters",
-    "pfnks_debug_profile", "pfnks_debug_kernel_time", "pfnks_batch_step",
+    "pfnks_debug_profile", "pfnks_debug_kernel_time", "pfnks_batch_step", "pfnks_residual_static",
 ]
 
 KERNEL_KINDS = ["residual", "linearise", "jv", "ras", "spectral", "multidot", "update"]
@@ -120,6 +120,8 @@ def load():
     lib.pfnks_debug_kernel_time.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_longlong), dp, dp]
     lib.pfnks_batch_step.argtypes = [ctypes.POINTER(P), ctypes.c_int, dp, ctypes.c_int,
                                      ctypes.POINTER(pfnks_step_stats), ctypes.POINTER(ctypes.c_int)]
+    lib.pfnks_residual_static.argtypes = [ctypes.POINTER(pfnks_grid), ctypes.POINTER(pfnks_model), ctypes.c_double,
+                                          ctypes.c_double, P, P, P, dp, dp, P]
     for name in EXPORTED:
         if name not in ("pfnks_strerror", "pfnks_last_error"):
             getattr(lib, name).restype = ctypes.c_int
@@ -198,6 +200,28 @@ def workspace_bytes(n, h, model, solver):
     _check(lib.pfnks_workspace_bytes(ctypes.byref(g), ctypes.byref(m), ctypes.byref(s), ctypes.byref(out)),
            "pfnks_workspace_bytes")
     return out.value
+
+
+def residual_static(n, h, model, cbar0, dt, X, Xn, F, stream=None, sync=True):
+    """pfnks_residual_static on device tensors X, Xn (read) and F (written), each 4 + d
+    contiguous float64 planes on the current device: F = F(X; Xn, dt) with the library's own
+    scratch (no allocation).  Returns (||F||, out-of-domain count) when sync, else None."""
+    lib = load()
+    for a in (X, Xn, F):
+        if not (a.is_cuda and a.is_contiguous() and str(a.dtype) == "torch.float64"):
+            raise ValueError("X, Xn, F must be contiguous float64 device tensors")
+        if a.numel() != (4 + len(n)) * int(np.prod(n)):
+            raise ValueError("X, Xn, F must hold 4 + dim planes of the grid")
+    g = make_grid(n, h)
+    m = make_model(model)
+    nrm = ctypes.c_double(0.0)
+    bad = ctypes.c_double(0.0)
+    sp = ctypes.c_void_p(stream.cuda_stream) if stream is not None else None
+    _check(lib.pfnks_residual_static(ctypes.byref(g), ctypes.byref(m), float(cbar0), float(dt),
+                                     ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(Xn.data_ptr()),
+                                     ctypes.c_void_p(F.data_ptr()), ctypes.byref(nrm) if sync else None,
+                                     ctypes.byref(bad) if sync else None, sp), "pfnks_residual_static")
+    return (nrm.value, bad.value) if sync else None
 
 
 def batch_step(problems, dts, threads=0):

@@ -148,3 +148,25 @@ def test_create_problem_rejects_on_host():
     c[7], e[7], e[N + 7], e[2 * N + 7] = 0.5, 0.4, 0.4, 0.4  # eta_4 = 2.8: c eta_4 = 1.4
     assert create(c, e) == (pfnks.PFNKS_EDOMAIN, None)
 
+
+def test_residual_static_rejects_on_host():
+    """pfnks_residual_static checks its arguments and its scratch limit (2^21 nodes) before the
+    first device call (the device addresses below are never dereferenced)."""
+    if not os.path.exists(LIB):
+        pytest.skip("libpfnks.so not built")
+    from paper_2209_08001_amd import pfnks
+    from paper_2209_08001_amd import workloads as W
+
+    lib = pfnks.load()
+    m = pfnks.make_model(W.DEFAULT_MODEL)
+    fake = ctypes.c_void_p(1 << 30)
+
+    def call(n, dt=0.1, ptr=fake):
+        g = pfnks.make_grid(n, W.H)
+        return lib.pfnks_residual_static(ctypes.byref(g), ctypes.byref(m), 0.17, dt, ptr, ptr, ptr, None, None, None)
+
+    assert call((2048, 2048)) == pfnks.PFNKS_ENOSPACE  # 2^22 nodes
+    assert call((256, 128, 128)) == pfnks.PFNKS_ENOSPACE
+    assert call((64, 64), dt=0.0) == pfnks.PFNKS_EINVAL
+    assert call((64, 64), ptr=None) == pfnks.PFNKS_EINVAL
+    assert call((34, 34)) == pfnks.PFNKS_EINVAL
