@@ -180,7 +180,8 @@ def cpu_baseline(wl_name):
 
 def _solver_for(W, pfnks, n, precision, pc, sweeps=None):
     mixed = precision == "mixed"
-    sv = dict(W.DEFAULT_SOLVER, sweeps=sweeps or W.default_sweeps(len(n), mixed), pc=pc,
+    sv = dict(W.DEFAULT_SOLVER, sweeps=sweeps or W.default_sweeps(len(n), mixed),
+              sor_omega=W.default_omega(len(n), mixed), pc=pc,
               precision=pfnks.MIXED if mixed else pfnks.FP64)
     if len(n) == 3:
         sv.update(tile=tuple(W.tile_side(s, 8, 1) for s in n), overlap=1)
@@ -378,6 +379,7 @@ def run_ensemble(args, wl):
 
     members = W.ensemble_members(wl)
     solver = dict(W.DEFAULT_SOLVER, sweeps=args.sweeps or W.default_sweeps(2, args.precision == "mixed"),
+                  sor_omega=W.default_omega(2, args.precision == "mixed"),
                   pc=pc_names()[args.pc],
                   precision=pfnks.MIXED if args.precision == "mixed" else pfnks.FP64)
     dev = "cuda:0"
@@ -446,6 +448,7 @@ def run_serving(args, wl):
     from paper_2209_08001_amd.serve import Server, poisson_requests
 
     solver = dict(W.DEFAULT_SOLVER, sweeps=args.sweeps or W.default_sweeps(2, args.precision == "mixed"),
+                  sor_omega=W.default_omega(2, args.precision == "mixed"),
                   pc=pc_names()[args.pc],
                   precision=pfnks.MIXED if args.precision == "mixed" else pfnks.FP64)
     free, _ = torch.cuda.mem_get_info()
@@ -550,10 +553,12 @@ def main():
     else:
         c0, e0 = W.init_fields(n, wl["seed"], cbar=wl["cbar"])
     solver = dict(W.DEFAULT_SOLVER, sweeps=args.sweeps or W.default_sweeps(2, args.precision == "mixed"),
+                  sor_omega=W.default_omega(2, args.precision == "mixed"),
                   pc=pc_names()[args.pc],
                   precision=pfnks.MIXED if args.precision == "mixed" else pfnks.FP64)
     if len(n) == 3:
-        solver.update(tile=(8, 8, 8), overlap=1, sweeps=args.sweeps or W.default_sweeps(3, args.precision == "mixed"))
+        solver.update(tile=(8, 8, 8), overlap=1, sweeps=args.sweeps or W.default_sweeps(3, args.precision == "mixed"),
+                      sor_omega=W.default_omega(3, args.precision == "mixed"))
     if args.tile:
         t = tuple(int(v) for v in args.tile.split(","))
         solver["tile"] = t if len(t) == 3 else (t[0], t[1], 1)

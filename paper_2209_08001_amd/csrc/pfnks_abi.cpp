@@ -760,9 +760,10 @@ int pfnks_create_problem(const pfnks_grid* grid, const pfnks_model* model, const
   p->T.pack = p->ws + L.off[B_PACK];
   pf::TileCfg tcheck = p->T;
   tcheck.with_u = tiles_all_fields(solver->pc) ? 1 : 0;
-  if (uses_tiles(solver->pc) && pf::ras_threads(p->K, tcheck, krylov_bytes(solver->precision), nullptr) == 0) {
+  if (uses_tiles(solver->pc) && (pf::ras_threads(p->K, tcheck, krylov_bytes(solver->precision), nullptr) == 0 ||
+                                 pf::ras_lds_bytes(p->K, tcheck, krylov_bytes(solver->precision)) > 160 * 1024)) {
     delete p;
-    return PFNKS_EINVAL;  // tile shape beyond what the tile kernel holds per thread
+    return PFNKS_EINVAL;  // tile shape beyond what the tile kernel holds per thread or in LDS
   }
   auto ptr = [&](int b) { return (double*)(p->ws + L.off[b]); };
   p->kb = krylov_bytes(solver->precision);

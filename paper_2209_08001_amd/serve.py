@@ -67,7 +67,9 @@ class Server:
 
     def _solver_for(self, n):
         sv = dict(self.solver)
-        sv["sweeps"] = W.default_sweeps(len(n), sv.get("precision", pfnks.FP64) == pfnks.MIXED)
+        mixed = sv.get("precision", pfnks.FP64) == pfnks.MIXED
+        sv["sweeps"] = W.default_sweeps(len(n), mixed)
+        sv["sor_omega"] = W.default_omega(len(n), mixed)
         if len(n) == 3:
             sv["overlap"] = 1
             sv["tile"] = tuple(W.tile_side(s, 8, 1) for s in n)
