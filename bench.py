@@ -250,6 +250,67 @@ def run_c1(dev):
     }
 
 
+def make_groups(W, pfnks, members, prec, dev):
+    """Lockstep groups of an ensemble: the instances of each side together (at most
+    pfnks.MAX_GROUP per group), each group on a stream of its own."""
+    import torch
+
+    by_side = {}
+    for m in members:
+        by_side.setdefault(tuple(m["n"]), []).append(m)
+    groups = []
+    for n, ms in sorted(by_side.items()):
+        for k in range(0, len(ms), pfnks.MAX_GROUP):
+            part = ms[k:k + pfnks.MAX_GROUP]
+            fields = [W.init_fields(n, m["seed"], cbar=m["cbar"]) for m in part]
+            sv = _solver_for(W, pfnks, n, prec, pfnks.PC_RAS_SPECTRAL)
+            groups.append(pfnks.Group(n, W.H, W.DEFAULT_MODEL, sv, [f[0] for f in fields], [f[1] for f in fields],
+                                      device=dev, stream=torch.cuda.Stream(device=dev)))
+    return groups
+
+
+def run_c4_lockstep(dev, steps=3, prec="mixed"):
+    """The ens2d_64 ensemble as lockstep groups (one per side, pfnks_group_step: one launch per
+    kernel and phase for all instances of a side, the GMRES rotations on the device), the
+    groups on concurrent host threads and streams, over the first steps of every instance's
+    adaptive trajectory: instance steps/s and node steps/s."""
+    import torch
+
+    from paper_2209_08001_amd import pfnks
+    from paper_2209_08001_amd import workloads as W
+    from paper_2209_08001_amd.driver import adaptive_group_run
+
+    wl = W.WORKLOADS["ens2d_64"]
+    members = W.ensemble_members(wl)
+    scratch = make_groups(W, pfnks, members[:8], prec, dev)
+    adaptive_group_run(scratch, 1, wl)
+    for g in scratch:
+        g.close()
+    del scratch
+    groups = make_groups(W, pfnks, members, prec, dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat, stats = adaptive_group_run(groups, steps, wl)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    count = sum(g.count for g in groups)
+    nodes = sum(g.N * g.count for g in groups)
+    flat = [s for gs in stats for ss in gs for s in ss]
+    newton = sum(s["newton_its"] for s in flat)
+    out = {
+        "workload": "ens2d_64", "mode": "lockstep groups", "instances": count, "groups": len(groups),
+        "group_sizes": [g.count for g in groups], "total_nodes": nodes, "precision": prec, "steps": steps,
+        "instance_steps_per_s": count * steps / elapsed,
+        "node_steps_per_s": nodes * steps / elapsed,
+        "p50_round_ms": 1e3 * percentile(lat, 50), "p99_round_ms": 1e3 * percentile(lat, 99),
+        "newton_per_step": newton / (count * steps),
+        "gmres_per_newton": sum(s["gmres_its"] for s in flat) / max(newton, 1),
+    }
+    for g in groups:
+        g.close()
+    return out
+
+
 def run_c4(dev, steps=3, threads=16):
     """Ensemble: the 64 instances of ens2d_64 (sides from {128, 192, 256, 384, 512}, mean
     compositions in [0.13, 0.21]) in mixed precision, stepped together (pfnks_batch_step, one
@@ -369,15 +430,39 @@ def run_c3(dev, steps=10, warmup=2):
 
 def run_ensemble(args, wl):
     """Ensemble workload: every instance takes K adaptive steps; the instances are stepped
-    together (pfnks_batch_step, one stream per instance).  value = instance steps per second
-    over the whole ensemble."""
+    together, either as lockstep groups of one side each (--ensemble-mode lockstep,
+    pfnks_group_step) or by host threads over one stream per instance (threads,
+    pfnks_batch_step).  value = instance steps per second over the whole ensemble."""
     import torch
 
     from paper_2209_08001_amd import pfnks
     from paper_2209_08001_amd import workloads as W
-    from paper_2209_08001_amd.driver import adaptive_batch_run
+    from paper_2209_08001_amd.driver import adaptive_batch_run, adaptive_group_run
 
     members = W.ensemble_members(wl)
+    if args.ensemble_mode == "lockstep":
+        dev = "cuda:0"
+        if args.warmup > 0:
+            scratch = make_groups(W, pfnks, members[:8], args.precision, dev)
+            adaptive_group_run(scratch, args.warmup, wl)
+            for g in scratch:
+                g.close()
+            del scratch
+        groups = make_groups(W, pfnks, members, args.precision, dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lat, gstats = adaptive_group_run(groups, args.steps, wl)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        stats = [ss for gs in gstats for ss in gs]
+        k = sum(g.count for g in groups)
+        nodes = sum(g.N * g.count for g in groups)
+        sides = sorted({g.n[0] for g in groups})
+        mode_cfg = {"mode": "lockstep groups", "groups": [g.count for g in groups]}
+        for g in groups:
+            g.close()
+    else:
+        lat = stats = None
     solver = dict(W.DEFAULT_SOLVER, sweeps=args.sweeps or W.default_sweeps(2, args.precision == "mixed"),
                   sor_omega=W.default_omega(2, args.precision == "mixed"),
                   pc=pc_names()[args.pc],
@@ -392,20 +477,25 @@ def run_ensemble(args, wl):
                                      stream=torch.cuda.Stream(device=dev)))
         return out
 
-    if args.warmup > 0:
-        scratch = make(members[:8])
-        adaptive_batch_run(scratch, args.warmup, wl, args.threads)
-        for p in scratch:
+    if stats is None:
+        if args.warmup > 0:
+            scratch = make(members[:8])
+            adaptive_batch_run(scratch, args.warmup, wl, args.threads)
+            for p in scratch:
+                p.close()
+            del scratch
+        probs = make(members)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lat, stats = adaptive_batch_run(probs, args.steps, wl, args.threads)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        k = len(probs)
+        nodes = sum(p.N for p in probs)
+        sides = sorted({p.n[0] for p in probs})
+        mode_cfg = {"mode": "threads", "host_threads": args.threads}
+        for p in probs:
             p.close()
-        del scratch
-    probs = make(members)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    lat, stats = adaptive_batch_run(probs, args.steps, wl, args.threads)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    k = len(probs)
-    nodes = sum(p.N for p in probs)
     newton = sum(s["newton_its"] for ss in stats for s in ss)
     gmres = sum(s["gmres_its"] for ss in stats for s in ss)
     out = {
@@ -421,9 +511,8 @@ def run_ensemble(args, wl):
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f64+f32",
         "data": "synthetic",
-        "config": {"workload": args.workload, "instances": k, "total_nodes": nodes,
-                   "sides": sorted({p.n[0] for p in probs}), "precision": args.precision,
-                   "preconditioner": args.pc, "host_threads": args.threads},
+        "config": dict({"workload": args.workload, "instances": k, "total_nodes": nodes,
+                        "sides": sides, "precision": args.precision, "preconditioner": args.pc}, **mode_cfg),
         "node_steps_per_s": nodes * args.steps / elapsed,
         "p50_round_ms": 1e3 * percentile(lat, 50),
         "p99_round_ms": 1e3 * percentile(lat, 99),
@@ -432,8 +521,6 @@ def run_ensemble(args, wl):
         "retries": sum(s["retries"] for ss in stats for s in ss),
         "roofline": None,
     }
-    for p in probs:
-        p.close()
     print(json.dumps(out))
 
 
@@ -521,6 +608,9 @@ def main():
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--threads", type=int, default=16,
                     help="ensemble workloads: host threads driving the instances (pfnks_batch_step)")
+    ap.add_argument("--ensemble-mode", default="lockstep", choices=["lockstep", "threads"],
+                    help="ensemble workloads: lockstep groups of one side each (pfnks_group_step) or "
+                         "host threads over one stream per instance (pfnks_batch_step)")
     ap.add_argument("--window", type=float, default=None,
                     help="serving workload: arrival window in seconds (default: the workload's)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,

@@ -176,6 +176,44 @@ int pfnks_step(pfnks_problem* p, double dt, pfnks_step_stats* stats);
 int pfnks_batch_step(pfnks_problem* const* problems, int k, const double* dts, int threads,
                      pfnks_step_stats* stats, int* status);
 
+/* ---- lockstep problem groups (ensembles of one grid shape) ----------------------------
+ * `count` (1 .. 32) problems with one grid, model and solver, stepped together.  Every phase
+ * of the step of Section 4 (residual, linearisation, the preconditioner set-up, each Arnoldi
+ * step of GMRES with its Schwarz tile solve, Fourier block and J v, the line-search trials,
+ * the step close) is one launch per kernel for all instances still working in that phase;
+ * the Hessenberg columns, Givens rotations and the triangular solve of each GMRES cycle run
+ * on the device, and the host synchronises once per Arnoldi step, residual evaluation and
+ * cycle end for all instances together.  Each instance follows the iteration pfnks_step
+ * would take on it alone (its own dt, Newton and GMRES counts, line search and stop rule);
+ * the results agree with pfnks_step's to rounding (the rotations are computed on the device
+ * instead of the host).
+ * The workspace (device, 256-byte aligned, caller-owned, kept alive until
+ * pfnks_group_destroy) holds count copies of the single-problem layout, instance i at
+ * i * pfnks_workspace_bytes bytes.  c0: count * N doubles, eta0: count * 3 N doubles
+ * (instance-major, each as for pfnks_create_problem).  Errors: PFNKS_EINVAL (count outside
+ * 1 .. 32, bad configuration, misaligned workspace), PFNKS_ENOSPACE, PFNKS_EDOMAIN,
+ * PFNKS_EDEVICE. */
+typedef struct pfnks_group pfnks_group;
+int pfnks_group_workspace_bytes(const pfnks_grid* grid, const pfnks_model* model,
+                                const pfnks_solver* solver, int count, size_t* bytes);
+int pfnks_group_create(const pfnks_grid* grid, const pfnks_model* model, const pfnks_solver* solver,
+                       int count, const double* c0, const double* eta0, void* d_workspace,
+                       size_t ws_bytes, void* hip_stream, pfnks_group** out);
+/* One step of every instance, dts[i] for instance i (host array of count); an instance with
+ * dts[i] = 0 sits the step out (state unchanged, status PFNKS_OK, zero stats), so that an
+ * adaptive driver can retry only the instances that failed.  stats and status (may be NULL)
+ * receive count records.  An instance whose step succeeds advances (X^{n+1}, t += dts[i]);
+ * one that does not converge keeps its state (status PFNKS_ENOCONV).  Returns PFNKS_OK when
+ * every instance succeeded, else the first failing instance's status.
+ * Errors: PFNKS_EINVAL (null group or dts, dts[i] < 0 or not finite), PFNKS_EDEVICE. */
+int pfnks_group_step(pfnks_group* g, const double* dts, pfnks_step_stats* stats, int* status);
+/* State of instance i to host (4 + dim planes, as pfnks_get_state); t may be NULL. */
+int pfnks_group_get_state(pfnks_group* g, int i, double* X, double* t);
+/* Kernel launches and host synchronisations of the last pfnks_group_step. */
+int pfnks_group_counters(pfnks_group* g, long long* launches, long long* syncs);
+/* Release the handle (host memory only; the caller frees the workspace afterwards). */
+int pfnks_group_destroy(pfnks_group* g);
+
 /* Discrete free energy E~ of eqs. (relations)/(freeenergy) at the current state; parts
  * (may be NULL) receives (chemical E1+E2, elastic E3, interfacial E4). */
 int pfnks_energy(pfnks_problem* p, double* total, double parts[3]);

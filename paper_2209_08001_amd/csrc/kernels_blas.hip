@@ -54,7 +54,12 @@ __device__ inline double block_max(double v, double* lds) {
 template <int MAXV, typename T>
 __global__ __launch_bounds__(kThreads) void k_multidot(long long n, int nv, const T* __restrict__ V,
                                                        long long ldv, const double* __restrict__ w,
-                                                       double* __restrict__ partial) {
+                                                       double* __restrict__ partial, Bat bt) {
+  const int bi = bat_inst(bt);
+  if (bat_skip(bt, bi)) return;
+  V = bat_at(V, bi * bt.stride);
+  w = bat_at(w, bi * bt.stride);
+  partial = bat_at(partial, bi * bt.stride);
   __shared__ double lds[kThreads / 64];
   double acc[MAXV + 1];
 #pragma unroll
@@ -106,7 +111,13 @@ struct Coefs {
 template <int MAXV, typename T>
 __global__ __launch_bounds__(kThreads) void k_update_dev(long long n, int nv, const T* __restrict__ V,
                                                          long long ldv, const double* __restrict__ hc,
-                                                         const double* __restrict__ w, T* __restrict__ out) {
+                                                         const double* __restrict__ w, T* __restrict__ out, Bat bt) {
+  const int bi = bat_inst(bt);
+  if (bat_skip(bt, bi)) return;
+  V = bat_at(V, bi * bt.stride);
+  hc = bat_at(hc, bi * bt.stride);
+  w = bat_at(w, bi * bt.stride);
+  out = bat_at(out, bi * bt.stride);
   double c[MAXV];
   double hh = 0.0;
 #pragma unroll
@@ -140,7 +151,11 @@ __global__ __launch_bounds__(kThreads) void k_update_dev(long long n, int nv, co
 template <int MAXV, typename T, typename To>
 __global__ __launch_bounds__(kThreads) void k_lincomb(long long n, int nv, const T* __restrict__ V,
                                                       long long ldv, Coefs cf, double beta,
-                                                      To* __restrict__ out) {
+                                                      To* __restrict__ out, Bat bt) {
+  const int bi = bat_inst(bt);
+  if (bat_skip(bt, bi)) return;
+  V = bat_at(V, bi * bt.stride);
+  out = bat_at(out, bi * bt.stride);
   for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < n;
        e += (long long)gridDim.x * kThreads) {
     double x = (beta == 0.0) ? 0.0 : beta * (double)out[e];
@@ -154,7 +169,13 @@ __global__ __launch_bounds__(kThreads) void k_lincomb(long long n, int nv, const
 template <typename Tx, typename Ty, typename To>
 __global__ __launch_bounds__(kThreads) void k_axpby(long long n, double a, const Tx* __restrict__ x,
                                                     double b, const Ty* __restrict__ y,
-                                                    To* __restrict__ out) {
+                                                    To* __restrict__ out, Bat bt) {
+  const int bi = bat_inst(bt);
+  if (bat_skip(bt, bi)) return;
+  x = bat_at(x, bi * bt.stride);
+  y = bat_at(y, bi * bt.stride);
+  out = bat_at(out, bi * bt.stride);
+  a = bat_s(bt, bi, a);
   for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < n;
        e += (long long)gridDim.x * kThreads) {
     double v = a * (double)x[e];
@@ -168,7 +189,13 @@ __global__ __launch_bounds__(kThreads) void k_axpby(long long n, double a, const
 // waves.  Fixed order, so the result is deterministic.
 template <int MAXV>
 __global__ __launch_bounds__(kRedBlocks) void k_finalize(const double* __restrict__ partial, int nvals,
-                                                         double* __restrict__ out, double* __restrict__ out2) {
+                                                         double* __restrict__ out, double* __restrict__ out2,
+                                                         Bat bt) {
+  const int bi = bat_inst(bt);
+  if (bat_skip(bt, bi)) return;
+  partial = bat_at(partial, bi * bt.stride);
+  out = bat_at(out, bi * bt.stride);
+  out2 = bat_at(out2, bi * bt.hstride);
   __shared__ double wl[kRedBlocks / 64][MAXV];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double acc[MAXV];
@@ -194,7 +221,13 @@ __global__ __launch_bounds__(kRedBlocks) void k_finalize(const double* __restric
 // The same second stage for per-block maxima of non-negative values.
 constexpr int kMaxVals = 16;
 __global__ __launch_bounds__(kRedBlocks) void k_finalize_max(const double* __restrict__ partial, int nvals,
-                                                             double* __restrict__ out, double* __restrict__ out2) {
+                                                             double* __restrict__ out, double* __restrict__ out2,
+                                                             Bat bt) {
+  const int bi = bat_inst(bt);
+  if (bat_skip(bt, bi)) return;
+  partial = bat_at(partial, bi * bt.stride);
+  out = bat_at(out, bi * bt.stride);
+  out2 = bat_at(out2, bi * bt.hstride);
   __shared__ double wl[kRedBlocks / 64][kMaxVals];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int v = 0; v < nvals; ++v) {
@@ -215,7 +248,13 @@ __global__ __launch_bounds__(kRedBlocks) void k_finalize_max(const double* __res
 __global__ __launch_bounds__(kThreads) void k_sum2(long long n, const double* __restrict__ x,
                                                    const double* __restrict__ y,
                                                    const double* __restrict__ yn,
-                                                   double* __restrict__ partial) {
+                                                   double* __restrict__ partial, Bat bt) {
+  const int bi = bat_inst(bt);
+  if (bat_skip(bt, bi)) return;
+  x = bat_at(x, bi * bt.stride);
+  y = bat_at(y, bi * bt.stride);
+  yn = bat_at(yn, bi * bt.stride);
+  partial = bat_at(partial, bi * bt.stride);
   __shared__ double lds[kThreads / 64];
   double a = 0.0, b = 0.0;
   for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < n;
@@ -238,7 +277,18 @@ __global__ __launch_bounds__(kThreads) void k_sum2(long long n, const double* __
 __global__ __launch_bounds__(kThreads) void k_trial(long long N, int nf, const double* __restrict__ X,
                                                     const double* __restrict__ S, double lam,
                                                     const double* __restrict__ msums, double* __restrict__ Xt,
-                                                    double* __restrict__ partial, double* __restrict__ pmax) {
+                                                    double* __restrict__ partial, double* __restrict__ pmax,
+                                                    Bat bt) {
+  const int bi = bat_inst(bt);
+  if (bat_skip(bt, bi)) return;
+  const long long bo = bi * bt.stride;
+  X = bat_at(X, bo);
+  S = bat_at(S, bo);
+  msums = bat_at(msums, bo);
+  Xt = bat_at(Xt, bo);
+  partial = bat_at(partial, bo);
+  pmax = bat_at(pmax, bo);
+  lam = bat_s(bt, bi, lam);
   __shared__ double lds[kThreads / 64];
   // mass projection of the update: shift = -(sum S_c + sum (c - c^n)) / N, from the device sums
   const double shift = -(msums[0] + msums[1]) / (double)N;
@@ -294,7 +344,12 @@ __global__ __launch_bounds__(kThreads) void k_trial(long long N, int nf, const d
 
 __global__ __launch_bounds__(kThreads) void k_dx2(long long n, const double* __restrict__ X,
                                                   const double* __restrict__ Xn,
-                                                  double* __restrict__ partial) {
+                                                  double* __restrict__ partial, Bat bt) {
+  const int bi = bat_inst(bt);
+  if (bat_skip(bt, bi)) return;
+  X = bat_at(X, bi * bt.stride);
+  Xn = bat_at(Xn, bi * bt.stride);
+  partial = bat_at(partial, bi * bt.stride);
   __shared__ double lds[kThreads / 64];
   double a = 0.0;
   for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < n;
@@ -308,7 +363,11 @@ __global__ __launch_bounds__(kThreads) void k_dx2(long long n, const double* __r
 
 // Sums of each displacement component over each parity class (i mod 2, j mod 2, k mod 2).
 __global__ __launch_bounds__(kThreads) void k_class_sums(Consts K, const double* __restrict__ u,
-                                                         double* __restrict__ partial) {
+                                                         double* __restrict__ partial, Bat bt) {
+  const int bi = bat_inst(bt);
+  if (bat_skip(bt, bi)) return;
+  u = bat_at(u, bi * bt.stride);
+  partial = bat_at(partial, bi * bt.stride);
   __shared__ double lds[kThreads / 64];
   const int ncls = 1 << K.dim;
   double acc[3][8];
@@ -340,7 +399,11 @@ __global__ __launch_bounds__(kThreads) void k_class_sums(Consts K, const double*
 }
 
 __global__ __launch_bounds__(kThreads) void k_class_shift(Consts K, double* __restrict__ u,
-                                                          const double* __restrict__ sums) {
+                                                          const double* __restrict__ sums, Bat bt) {
+  const int bi = bat_inst(bt);
+  if (bat_skip(bt, bi)) return;
+  u = bat_at(u, bi * bt.stride);
+  sums = bat_at(sums, bi * bt.stride);
   const int ncls = 1 << K.dim;
   const double inv = (double)ncls / (double)K.N;  // every class holds N / 2^d nodes
   for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < K.N;
@@ -351,10 +414,176 @@ __global__ __launch_bounds__(kThreads) void k_class_shift(Consts K, double* __re
   }
 }
 
+// ---- device-side GMRES cycle of a lockstep batch (pfnks_group) -----------------------
+// Arnoldi column j, one workgroup per instance: the second stage of the multi-dot (as
+// k_finalize) into hcol = [h_0 .. h_j, <w, w>], then, in thread 0, h_{j+1,j} =
+// sqrt(<w,w> - sum h_i^2), the earlier Givens rotations and a new one applied to column j of
+// H and to the rotated right-hand side g, and the end test of the cycle: |g_{j+1}| <= tol,
+// the loss of more than two digits in <w,w> - sum h_i^2, a zero h_{j+1,j}, the column limit
+// of the cycle, or an estimate that is not finite.  The status goes to the instance's state
+// and to its pinned host slots (ended, |g_{j+1}|, columns, not finite).  An instance whose
+// cycle has already ended (a step launched ahead of the host's test) is left untouched.
+template <int MAXV>
+__global__ __launch_bounds__(kRedBlocks) void k_arnoldi(const double* __restrict__ partial, int j, int m,
+                                                        double* __restrict__ hcol, double* __restrict__ giv,
+                                                        double* __restrict__ host, Bat bt) {
+  const int bi = bat_inst(bt);
+  if (bat_skip(bt, bi)) return;
+  partial = bat_at(partial, bi * bt.stride);
+  hcol = bat_at(hcol, bi * bt.stride);
+  giv = bat_at(giv, bi * bt.stride);
+  host = bat_at(host, bi * bt.hstride);
+  const GivLayout L = giv_layout(m);
+  double* st = giv + L.st;
+  if (st[kGivEnded] != 0.0) return;
+  const int nvals = j + 2;
+  __shared__ double wl[kRedBlocks / 64][MAXV];
+  __shared__ double col[MAXV];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double acc[MAXV];
+#pragma unroll
+  for (int v = 0; v < MAXV; ++v) acc[v] = (MAXV <= 32 || v < nvals) ? partial[v * kRedBlocks + threadIdx.x] : 0.0;
+#pragma unroll
+  for (int v = 0; v < MAXV; ++v) {
+    if (MAXV <= 32 || v < nvals) {
+      double x = acc[v];
+      for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+      if (lane == 0) wl[wave][v] = x;
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < nvals) {
+    double x = 0.0;
+    for (int w = 0; w < kRedBlocks / 64; ++w) x += wl[w][threadIdx.x];
+    hcol[threadIdx.x] = x;
+    col[threadIdx.x] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double* H = giv + L.H;
+  double* cs = giv + L.cs;
+  double* sn = giv + L.sn;
+  double* g = giv + L.g;
+  double* h = H + (long long)j * (m + 1);
+  double hh = 0.0;
+  for (int i = 0; i <= j; ++i) {
+    h[i] = col[i];
+    hh += col[i] * col[i];
+  }
+  const double ww = col[j + 1];
+  const double nrm2 = ww - hh;
+  const bool cancel = !(nrm2 > 1e-2 * ww);
+  const double hnext = sqrt(fmax(nrm2, 0.0));
+  h[j + 1] = hnext;
+  for (int i = 0; i < j; ++i) {
+    const double a = h[i], b = h[i + 1];
+    h[i] = cs[i] * a + sn[i] * b;
+    h[i + 1] = -sn[i] * a + cs[i] * b;
+  }
+  const double a = h[j], b = h[j + 1];
+  const double r = hypot(a, b);
+  cs[j] = (r == 0.0) ? 1.0 : a / r;
+  sn[j] = (r == 0.0) ? 0.0 : b / r;
+  h[j] = r;
+  h[j + 1] = 0.0;
+  g[j + 1] = -sn[j] * g[j];
+  g[j] = cs[j] * g[j];
+  const double resid = fabs(g[j + 1]);
+  const bool nonfinite = !isfinite(resid);
+  const bool ended = nonfinite || resid <= st[kGivTol] || cancel || hnext == 0.0 || (double)(j + 1) >= st[kGivLim];
+  st[kGivEnded] = ended ? 1.0 : 0.0;
+  st[kGivCols] = (double)(j + 1);
+  st[kGivResid] = resid;
+  st[kGivNonfinite] = nonfinite ? 1.0 : 0.0;
+  host[0] = st[kGivEnded];
+  host[1] = resid;
+  host[2] = (double)(j + 1);
+  host[3] = st[kGivNonfinite];
+}
+
+// start of a cycle, per instance: g = beta e_1 (beta = bt.s), tolerance bt.s2, column limit
+// bt.s3, nothing ended yet
+__global__ __launch_bounds__(64) void k_giv_init(double* __restrict__ giv, int m, Bat bt) {
+  const int bi = bat_inst(bt);
+  if (bat_skip(bt, bi)) return;
+  giv = bat_at(giv, bi * bt.stride);
+  const GivLayout L = giv_layout(m);
+  for (int i = threadIdx.x; i <= m; i += 64) giv[L.g + i] = (i == 0) ? bt.s[bi] : 0.0;
+  if (threadIdx.x == 0) {
+    double* st = giv + L.st;
+    st[kGivEnded] = 0.0;
+    st[kGivCols] = 0.0;
+    st[kGivTol] = bt.s2[bi];
+    st[kGivLim] = bt.s3[bi];
+    st[kGivResid] = bt.s[bi];
+    st[kGivNonfinite] = 0.0;
+  }
+}
+
+// end of a cycle, per instance: y = H^{-1} g over the cycle's k columns (upper triangular),
+// zero beyond, and y[m] = k for the combination S += Z y
+__global__ __launch_bounds__(64) void k_ysolve(double* __restrict__ giv, int m, Bat bt) {
+  const int bi = bat_inst(bt);
+  if (bat_skip(bt, bi)) return;
+  if (threadIdx.x != 0) return;
+  giv = bat_at(giv, bi * bt.stride);
+  const GivLayout L = giv_layout(m);
+  const double* H = giv + L.H;
+  const double* g = giv + L.g;
+  double* y = giv + L.y;
+  const int k = (int)giv[L.st + kGivCols];
+  for (int i = k - 1; i >= 0; --i) {
+    double s_ = g[i];
+    for (int c = i + 1; c < k; ++c) s_ -= H[(long long)c * (m + 1) + i] * y[c];
+    y[i] = s_ / H[(long long)i * (m + 1) + i];
+  }
+  for (int i = k; i < m; ++i) y[i] = 0.0;
+  y[m] = (double)k;
+}
+
+// out += sum_{v < k} y_v V_v with each instance's own y and column count k (from k_ysolve);
+// nv: the largest k of the launch
+template <int MAXV, typename T, typename To>
+__global__ __launch_bounds__(kThreads) void k_lincomb_dev(long long n, int nv, const T* __restrict__ V,
+                                                          long long ldv, const double* __restrict__ giv, int m,
+                                                          To* __restrict__ out, Bat bt) {
+  const int bi = bat_inst(bt);
+  if (bat_skip(bt, bi)) return;
+  V = bat_at(V, bi * bt.stride);
+  giv = bat_at(giv, bi * bt.stride);
+  out = bat_at(out, bi * bt.stride);
+  const double* y = giv + giv_layout(m).y;
+  const int k = (int)y[m];
+  const int nvb = k < nv ? k : nv;
+  double c[MAXV];
+#pragma unroll
+  for (int v = 0; v < MAXV; ++v) c[v] = (v < nvb) ? y[v] : 0.0;
+  for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < n;
+       e += (long long)gridDim.x * kThreads) {
+    double x = (double)out[e];
+#pragma unroll
+    for (int v = 0; v < MAXV; ++v)
+      if (v < nvb) x += c[v] * (double)V[v * ldv + e];
+    out[e] = (To)x;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_fill_zero(long long n, T* __restrict__ out, Bat bt) {
+  const int bi = bat_inst(bt);
+  if (bat_skip(bt, bi)) return;
+  out = bat_at(out, bi * bt.stride);
+  for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < n;
+       e += (long long)gridDim.x * kThreads)
+    out[e] = T(0);
+}
+
 int grid_for(long long n) {
   long long b = (n + kThreads - 1) / kThreads;
   return (int)(b < kRedBlocks ? b : kRedBlocks);
 }
+
+dim3 bg(int x, const Bat& bt) { return bat_grid(dim3((unsigned)x), bt); }
 
 }  // namespace
 
@@ -374,60 +603,62 @@ int grid_for(long long n) {
 // partial receives nv + 1 values: <w, V_v> for v < nv and <w, w>.  Always kRedBlocks blocks.
 template <typename T>
 void launch_multidot(long long n, int nv, const T* V, long long ldv, const double* w, double* partial,
-                     hipStream_t s) {
+                     hipStream_t s, const Bat& bt) {
   if (nv == 0) {
-    hipLaunchKernelGGL((k_multidot<0, T>), dim3(kRedBlocks), dim3(kThreads), 0, s, n, nv, V, ldv, w, partial);
+    hipLaunchKernelGGL((k_multidot<0, T>), bg(kRedBlocks, bt), dim3(kThreads), 0, s, n, nv, V, ldv, w, partial, bt);
     return;
   }
-#define F(N) hipLaunchKernelGGL((k_multidot<N, T>), dim3(kRedBlocks), dim3(kThreads), 0, s, n, nv, V, ldv, w, partial)
+#define F(N) hipLaunchKernelGGL((k_multidot<N, T>), bg(kRedBlocks, bt), dim3(kThreads), 0, s, n, nv, V, ldv, w, partial, bt)
   switch (nv) { PF_NV_CASES(F) }
 #undef F
 }
-template void launch_multidot<double>(long long, int, const double*, long long, const double*, double*, hipStream_t);
-template void launch_multidot<float>(long long, int, const float*, long long, const double*, double*, hipStream_t);
+template void launch_multidot<double>(long long, int, const double*, long long, const double*, double*, hipStream_t,
+                                      const Bat&);
+template void launch_multidot<float>(long long, int, const float*, long long, const double*, double*, hipStream_t,
+                                     const Bat&);
 
 template <typename T>
 void launch_update_dev(long long n, int nv, const T* V, long long ldv, const double* hc, const double* w,
-                       T* out, hipStream_t s) {
-#define F(N) hipLaunchKernelGGL((k_update_dev<N, T>), dim3(kRedBlocks), dim3(kThreads), 0, s, n, nv, V, ldv, hc, w, out)
+                       T* out, hipStream_t s, const Bat& bt) {
+#define F(N) hipLaunchKernelGGL((k_update_dev<N, T>), bg(kRedBlocks, bt), dim3(kThreads), 0, s, n, nv, V, ldv, hc, w, out, bt)
   switch (nv) { PF_NV_CASES(F) }
 #undef F
 }
 template void launch_update_dev<double>(long long, int, const double*, long long, const double*, const double*,
-                                        double*, hipStream_t);
+                                        double*, hipStream_t, const Bat&);
 template void launch_update_dev<float>(long long, int, const float*, long long, const double*, const double*,
-                                       float*, hipStream_t);
+                                       float*, hipStream_t, const Bat&);
 
 // out = beta * out + sum_v coef[v] V_v
 template <typename T, typename To>
 void launch_lincomb(long long n, int nv, const T* V, long long ldv, const double* coef, double beta, To* out,
-                    hipStream_t s) {
+                    hipStream_t s, const Bat& bt) {
   Coefs cf{};
   for (int v = 0; v < nv; ++v) cf.c[v] = coef[v];
-#define F(N) hipLaunchKernelGGL((k_lincomb<N, T, To>), dim3(grid_for(n)), dim3(kThreads), 0, s, n, nv, V, ldv, cf, beta, out)
+#define F(N) hipLaunchKernelGGL((k_lincomb<N, T, To>), bg(grid_for(n), bt), dim3(kThreads), 0, s, n, nv, V, ldv, cf, beta, out, bt)
   switch (nv) { PF_NV_CASES(F) }
 #undef F
 }
 template void launch_lincomb<double, double>(long long, int, const double*, long long, const double*, double,
-                                             double*, hipStream_t);
+                                             double*, hipStream_t, const Bat&);
 template void launch_lincomb<float, double>(long long, int, const float*, long long, const double*, double,
-                                            double*, hipStream_t);
+                                            double*, hipStream_t, const Bat&);
 
 template <typename Tx, typename Ty, typename To>
-void launch_axpby(long long n, double a, const Tx* x, double b, const Ty* y, To* out, hipStream_t s) {
-  hipLaunchKernelGGL((k_axpby<Tx, Ty, To>), dim3(grid_for(n)), dim3(kThreads), 0, s, n, a, x, b, y, out);
+void launch_axpby(long long n, double a, const Tx* x, double b, const Ty* y, To* out, hipStream_t s, const Bat& bt) {
+  hipLaunchKernelGGL((k_axpby<Tx, Ty, To>), bg(grid_for(n), bt), dim3(kThreads), 0, s, n, a, x, b, y, out, bt);
 }
 template void launch_axpby<double, double, double>(long long, double, const double*, double, const double*,
-                                                   double*, hipStream_t);
+                                                   double*, hipStream_t, const Bat&);
 template void launch_axpby<double, double, float>(long long, double, const double*, double, const double*, float*,
-                                                  hipStream_t);
+                                                  hipStream_t, const Bat&);
 template void launch_axpby<float, float, float>(long long, double, const float*, double, const float*, float*,
-                                                hipStream_t);
+                                                hipStream_t, const Bat&);
 template void launch_axpby<float, float, double>(long long, double, const float*, double, const float*, double*,
-                                                 hipStream_t);
+                                                 hipStream_t, const Bat&);
 
-void launch_finalize(const double* partial, int nvals, double* out, hipStream_t s, double* out2) {
-#define F(N) hipLaunchKernelGGL(k_finalize<N>, dim3(1), dim3(kRedBlocks), 0, s, partial, nvals, out, out2)
+void launch_finalize(const double* partial, int nvals, double* out, hipStream_t s, double* out2, const Bat& bt) {
+#define F(N) hipLaunchKernelGGL(k_finalize<N>, bg(1, bt), dim3(kRedBlocks), 0, s, partial, nvals, out, out2, bt)
   if (nvals > 32) {
     F(80);
     return;
@@ -436,31 +667,71 @@ void launch_finalize(const double* partial, int nvals, double* out, hipStream_t 
 #undef F
 }
 
-void launch_finalize_max(const double* partial, int nvals, double* out, hipStream_t s, double* out2) {
-  hipLaunchKernelGGL(k_finalize_max, dim3(1), dim3(kRedBlocks), 0, s, partial, nvals, out, out2);
+void launch_finalize_max(const double* partial, int nvals, double* out, hipStream_t s, double* out2,
+                         const Bat& bt) {
+  hipLaunchKernelGGL(k_finalize_max, bg(1, bt), dim3(kRedBlocks), 0, s, partial, nvals, out, out2, bt);
 }
 
 void launch_sum2(long long n, const double* x, const double* y, const double* yn, double* partial,
-                 hipStream_t s) {
-  hipLaunchKernelGGL(k_sum2, dim3(kRedBlocks), dim3(kThreads), 0, s, n, x, y, yn, partial);
+                 hipStream_t s, const Bat& bt) {
+  hipLaunchKernelGGL(k_sum2, bg(kRedBlocks, bt), dim3(kThreads), 0, s, n, x, y, yn, partial, bt);
 }
 
 void launch_trial(const Consts& K, int nf, const double* X, const double* S, double lam,
-                  const double* msums, double* Xt, double* partial, double* pmax, hipStream_t s) {
-  hipLaunchKernelGGL(k_trial, dim3(kRedBlocks), dim3(kThreads), 0, s, K.N, nf, X, S, lam, msums,
-                     Xt, partial, pmax);
+                  const double* msums, double* Xt, double* partial, double* pmax, hipStream_t s, const Bat& bt) {
+  hipLaunchKernelGGL(k_trial, bg(kRedBlocks, bt), dim3(kThreads), 0, s, K.N, nf, X, S, lam, msums,
+                     Xt, partial, pmax, bt);
 }
 
-void launch_dx2(long long n4, const double* X, const double* Xn, double* partial, hipStream_t s) {
-  hipLaunchKernelGGL(k_dx2, dim3(kRedBlocks), dim3(kThreads), 0, s, n4, X, Xn, partial);
+void launch_dx2(long long n4, const double* X, const double* Xn, double* partial, hipStream_t s, const Bat& bt) {
+  hipLaunchKernelGGL(k_dx2, bg(kRedBlocks, bt), dim3(kThreads), 0, s, n4, X, Xn, partial, bt);
 }
 
-void launch_class_sums(const Consts& K, const double* u, double* partial, hipStream_t s) {
-  hipLaunchKernelGGL(k_class_sums, dim3(kRedBlocks), dim3(kThreads), 0, s, K, u, partial);
+void launch_class_sums(const Consts& K, const double* u, double* partial, hipStream_t s, const Bat& bt) {
+  hipLaunchKernelGGL(k_class_sums, bg(kRedBlocks, bt), dim3(kThreads), 0, s, K, u, partial, bt);
 }
 
-void launch_class_shift(const Consts& K, double* u, const double* sums, hipStream_t s) {
-  hipLaunchKernelGGL(k_class_shift, dim3(grid_for(K.N)), dim3(kThreads), 0, s, K, u, sums);
+void launch_class_shift(const Consts& K, double* u, const double* sums, hipStream_t s, const Bat& bt) {
+  hipLaunchKernelGGL(k_class_shift, bg(grid_for(K.N), bt), dim3(kThreads), 0, s, K, u, sums, bt);
 }
+
+void launch_arnoldi(const double* partial, int j, int m, double* hcol, double* giv, double* host, hipStream_t s,
+                    const Bat& bt) {
+  const int nvals = j + 2;
+#define F(N) hipLaunchKernelGGL(k_arnoldi<N>, bg(1, bt), dim3(kRedBlocks), 0, s, partial, j, m, hcol, giv, host, bt)
+  if (nvals > 32) {
+    F(80);
+    return;
+  }
+  switch (nvals) { PF_NV_CASES(F) }
+#undef F
+}
+
+void launch_giv_init(double* giv, int m, hipStream_t s, const Bat& bt) {
+  hipLaunchKernelGGL(k_giv_init, bg(1, bt), dim3(64), 0, s, giv, m, bt);
+}
+
+void launch_ysolve(double* giv, int m, hipStream_t s, const Bat& bt) {
+  hipLaunchKernelGGL(k_ysolve, bg(1, bt), dim3(64), 0, s, giv, m, bt);
+}
+
+template <typename T, typename To>
+void launch_lincomb_dev(long long n, int nv, const T* V, long long ldv, const double* giv, int m, To* out,
+                        hipStream_t s, const Bat& bt) {
+#define F(N) hipLaunchKernelGGL((k_lincomb_dev<N, T, To>), bg(grid_for(n), bt), dim3(kThreads), 0, s, n, nv, V, ldv, giv, m, out, bt)
+  switch (nv) { PF_NV_CASES(F) }
+#undef F
+}
+template void launch_lincomb_dev<double, double>(long long, int, const double*, long long, const double*, int,
+                                                 double*, hipStream_t, const Bat&);
+template void launch_lincomb_dev<float, double>(long long, int, const float*, long long, const double*, int,
+                                                double*, hipStream_t, const Bat&);
+
+template <typename T>
+void launch_fill_zero(long long n, T* out, hipStream_t s, const Bat& bt) {
+  hipLaunchKernelGGL((k_fill_zero<T>), bg(grid_for(n), bt), dim3(kThreads), 0, s, n, out, bt);
+}
+template void launch_fill_zero<double>(long long, double*, hipStream_t, const Bat&);
+template void launch_fill_zero<float>(long long, float*, hipStream_t, const Bat&);
 
 }  // namespace pf

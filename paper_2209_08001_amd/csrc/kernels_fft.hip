@@ -99,7 +99,11 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_lines(double2* __restrict__
                                                            long long pstride, long long la,
                                                            long long lb, long long lc, long long nlines,
                                                            int lpb, const double2* __restrict__ tw,
-                                                           int inverse, int contiguous) {
+                                                           int inverse, int contiguous, Bat bt) {
+  const int binst = bat_inst(bt);
+  if (bat_skip(bt, binst)) return;
+  const long long bo = binst * bt.stride;
+  data = bat_at(data, bo);
   extern __shared__ double2 sm[];  // lpb lines of n (padded), then n/2 twiddles
   double2* tws = sm + lp_size(lpb * n);
   stage_twiddles(tws, tw, n);
@@ -155,7 +159,13 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_fft2_rows_fwd(Consts K, const T* __restrict__ r, double a,
                                                        const T* __restrict__ zc, int logn, int nl,
                                                        const double2* __restrict__ tw,
-                                                       double2* __restrict__ out) {
+                                                       double2* __restrict__ out, Bat bt) {
+  const int binst = bat_inst(bt);
+  if (bat_skip(bt, binst)) return;
+  const long long bo = binst * bt.stride;
+  r = bat_at(r, bo);
+  zc = bat_at(zc, bo);
+  out = bat_at(out, bo);
   extern __shared__ double2 sm[];  // nl * n (padded), then n/2 twiddles
   const int n = K.nx;
   double2* tws = sm + lp_size(nl * n);
@@ -188,7 +198,11 @@ __global__ __launch_bounds__(256) void k_fft2_rows_fwd(Consts K, const T* __rest
 __global__ __launch_bounds__(256) void k_fft2_cols_solve(Consts K, int logn, const double2* __restrict__ tw,
                                                          const double* __restrict__ sx,
                                                          const double* __restrict__ syt,
-                                                         double2* __restrict__ data) {
+                                                         double2* __restrict__ data, Bat bt) {
+  const int binst = bat_inst(bt);
+  if (bat_skip(bt, binst)) return;
+  const long long bo = binst * bt.stride;
+  data = bat_at(data, bo);
   // 2 lines of n, then the 2 lines of output spectra (elements 2n .. 4n; padded), then n/2
   // twiddles
   extern __shared__ double2 sm[];
@@ -243,7 +257,12 @@ __global__ __launch_bounds__(256) void k_fft2_cols_solve(Consts K, int logn, con
 // pass 3: inverse FFT along x, unpack u_x = Re / N, u_y = Im / N
 template <typename T>
 __global__ __launch_bounds__(256) void k_fft2_rows_inv(Consts K, int logn, int nl, const double2* __restrict__ tw,
-                                                       const double2* __restrict__ in, T* __restrict__ u) {
+                                                       const double2* __restrict__ in, T* __restrict__ u, Bat bt) {
+  const int binst = bat_inst(bt);
+  if (bat_skip(bt, binst)) return;
+  const long long bo = binst * bt.stride;
+  in = bat_at(in, bo);
+  u = bat_at(u, bo);
   extern __shared__ double2 sm[];  // nl * n (padded), then n/2 twiddles
   const int n = K.nx;
   double2* tws = sm + lp_size(nl * n);
@@ -279,7 +298,13 @@ __global__ __launch_bounds__(256) void k_fft2_rows_inv(Consts K, int logn, int n
 template <typename T>
 __global__ __launch_bounds__(256) void k_r2c_x(Consts K, const T* __restrict__ r, double a,
                                                const T* __restrict__ zc, int logn, int rp,
-                                               const double2* __restrict__ tw, double2* __restrict__ Qh) {
+                                               const double2* __restrict__ tw, double2* __restrict__ Qh, Bat bt) {
+  const int binst = bat_inst(bt);
+  if (bat_skip(bt, binst)) return;
+  const long long bo = binst * bt.stride;
+  r = bat_at(r, bo);
+  zc = bat_at(zc, bo);
+  Qh = bat_at(Qh, bo);
   extern __shared__ double2 sm[];  // 3 rp lines of nx (padded), then nx/2 twiddles
   const int n = K.nx, nxh = n / 2 + 1, hb = K.ny / (2 * rp);
   double2* tws = sm + lp_size(3 * rp * n);
@@ -332,7 +357,11 @@ __global__ __launch_bounds__(256) void k_r2c_x(Consts K, const T* __restrict__ r
 // elasticity), the bit-reversal permutation in place, inverse FFT along z.
 __global__ __launch_bounds__(256) void k_z_solve(Consts K, int logn, int lpb, const double2* __restrict__ tw,
                                                  const double* __restrict__ sx, const double* __restrict__ sy,
-                                                 const double* __restrict__ szt, double2* __restrict__ Qh) {
+                                                 const double* __restrict__ szt, double2* __restrict__ Qh, Bat bt) {
+  const int binst = bat_inst(bt);
+  if (bat_skip(bt, binst)) return;
+  const long long bo = binst * bt.stride;
+  Qh = bat_at(Qh, bo);
   extern __shared__ double2 sm[];  // 3 lpb lines of nz: line (f lpb + l) (padded), then nz/2 twiddles
   const int n = K.nz, nxh = K.nx / 2 + 1;
   double2* tws = sm + lp_size(3 * lpb * n);
@@ -412,7 +441,12 @@ __global__ __launch_bounds__(256) void k_z_solve(Consts K, int logn, int lpb, co
 // one inverse FFT per line gives the real fields, u = result / N.
 template <typename T>
 __global__ __launch_bounds__(256) void k_c2r_x(Consts K, int logn, int rp, const double2* __restrict__ tw,
-                                               const double2* __restrict__ Qh, T* __restrict__ u) {
+                                               const double2* __restrict__ Qh, T* __restrict__ u, Bat bt) {
+  const int binst = bat_inst(bt);
+  if (bat_skip(bt, binst)) return;
+  const long long bo = binst * bt.stride;
+  Qh = bat_at(Qh, bo);
+  u = bat_at(u, bo);
   extern __shared__ double2 sm[];  // 3 rp lines of nx (padded), then nx/2 twiddles
   const int n = K.nx, nxh = n / 2 + 1, hb = K.ny / (2 * rp);
   double2* tws = sm + lp_size(3 * rp * n);
@@ -529,7 +563,11 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_lines_mr(double2* __restric
                                                               long long pstride, long long la, long long lb,
                                                               long long lc, long long nlines, int lpb,
                                                               const double2* __restrict__ tw, int inverse,
-                                                              int contiguous) {
+                                                              int contiguous, Bat bt) {
+  const int binst = bat_inst(bt);
+  if (bat_skip(bt, binst)) return;
+  const long long bo = binst * bt.stride;
+  data = bat_at(data, bo);
   extern __shared__ double2 sm[];
   double2* b0 = sm;
   double2* b1 = sm + lpb * n;
@@ -592,7 +630,14 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_lines_mr(double2* __restric
 template <int DIM, typename T>
 __global__ __launch_bounds__(256) void k_pack(Consts K, const T* __restrict__ r, double a,
                                               const T* __restrict__ zc, double2* __restrict__ z0,
-                                              double2* __restrict__ z1) {
+                                              double2* __restrict__ z1, Bat bt) {
+  const int binst = bat_inst(bt);
+  if (bat_skip(bt, binst)) return;
+  const long long bo = binst * bt.stride;
+  r = bat_at(r, bo);
+  zc = bat_at(zc, bo);
+  z0 = bat_at(z0, bo);
+  z1 = bat_at(z1, bo);
   const long long n = (long long)blockIdx.x * 256 + threadIdx.x;
   if (n >= K.N) return;
   {
@@ -630,7 +675,14 @@ __global__ __launch_bounds__(256) void k_symbol_solve(Consts K, const double2* _
                                                       double2* __restrict__ w1,
                                                       const double* __restrict__ sx,
                                                       const double* __restrict__ sy,
-                                                      const double* __restrict__ szt) {
+                                                      const double* __restrict__ szt, Bat bt) {
+  const int binst = bat_inst(bt);
+  if (bat_skip(bt, binst)) return;
+  const long long bo = binst * bt.stride;
+  z0 = bat_at(z0, bo);
+  z1 = bat_at(z1, bo);
+  w0 = bat_at(w0, bo);
+  w1 = bat_at(w1, bo);
   const long long n = (long long)blockIdx.x * 256 + threadIdx.x;
   if (n >= K.N) return;
   {
@@ -712,7 +764,13 @@ __global__ __launch_bounds__(256) void k_symbol_solve(Consts K, const double2* _
 template <typename T>
 __global__ __launch_bounds__(256) void k_unpack(Consts K, const double2* __restrict__ w0,
                                                 const double2* __restrict__ w1,
-                                                T* __restrict__ u) {
+                                                T* __restrict__ u, Bat bt) {
+  const int binst = bat_inst(bt);
+  if (bat_skip(bt, binst)) return;
+  const long long bo = binst * bt.stride;
+  w0 = bat_at(w0, bo);
+  w1 = bat_at(w1, bo);
+  u = bat_at(u, bo);
   const double inv = 1.0 / (double)K.N;
   for (long long n = (long long)blockIdx.x * 256 + threadIdx.x; n < K.N; n += (long long)gridDim.x * 256) {
     const double2 a = w0[n];
@@ -730,13 +788,14 @@ int ilog2(int n) {
 
 // k_fft_lines with its LDS: lpb lines and the n/2 twiddles (beyond 64 KiB for the longest lines)
 void launch_lines(double2* data, int n, int logn, long long pstride, long long la, long long lb, long long lc,
-                  long long nlines, int lpb, const double2* tw, int inverse, int contiguous, hipStream_t s) {
+                  long long nlines, int lpb, const double2* tw, int inverse, int contiguous, hipStream_t s,
+                  const Bat& bt) {
   const size_t lds = sizeof(double2) * ((size_t)lp_size(lpb * n) + n / 2);
   if (lds > 64 * 1024)
     (void)hipFuncSetAttribute((const void*)k_fft_lines, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   const long long blocks = (nlines + lpb - 1) / lpb;
-  hipLaunchKernelGGL(k_fft_lines, dim3((unsigned)blocks), dim3(kFftThreads), lds, s, data, n, logn, pstride, la,
-                     lb, lc, nlines, lpb, tw, inverse, contiguous);
+  hipLaunchKernelGGL(k_fft_lines, bat_grid(dim3((unsigned)blocks), bt), dim3(kFftThreads), lds, s, data, n, logn,
+                     pstride, la, lb, lc, nlines, lpb, tw, inverse, contiguous, bt);
 }
 
 bool pow2(int n) { return n >= 1 && (n & (n - 1)) == 0; }
@@ -752,7 +811,8 @@ MrPlan mr_plan(int n) {
   return pl;
 }
 
-void fft_dir_mr(const Consts& K, const FftPlan& P, double2* data, int dir, int inverse, hipStream_t s) {
+void fft_dir_mr(const Consts& K, const FftPlan& P, double2* data, int dir, int inverse, hipStream_t s,
+                const Bat& bt) {
   const int n = P.n[dir];
   const MrPlan pl = mr_plan(n);
   // two buffers of lpb lines plus n twiddles within 64 KiB; strided lines at most 16 adjacent
@@ -773,14 +833,15 @@ void fft_dir_mr(const Consts& K, const FftPlan& P, double2* data, int dir, int i
   if (lds > 64 * 1024)
     (void)hipFuncSetAttribute((const void*)k_fft_lines_mr, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   const long long blocks = (nlines + lpb - 1) / lpb;
-  hipLaunchKernelGGL(k_fft_lines_mr, dim3((unsigned)blocks), dim3(kFftThreads), lds, s, data, n, pl, pstride, la,
-                     lb, lc, nlines, lpb, P.tw[dir], inverse, dir == 0 ? 1 : 0);
+  hipLaunchKernelGGL(k_fft_lines_mr, bat_grid(dim3((unsigned)blocks), bt), dim3(kFftThreads), lds, s, data, n, pl,
+                     pstride, la, lb, lc, nlines, lpb, P.tw[dir], inverse, dir == 0 ? 1 : 0, bt);
 }
 
-void fft_dir(const Consts& K, const FftPlan& P, double2* data, int dir, int inverse, hipStream_t s) {
+void fft_dir(const Consts& K, const FftPlan& P, double2* data, int dir, int inverse, hipStream_t s,
+             const Bat& bt) {
   const int n = P.n[dir];
   if (!pow2(n)) {
-    fft_dir_mr(K, P, data, dir, inverse, s);
+    fft_dir_mr(K, P, data, dir, inverse, s, bt);
     return;
   }
   const int logn = ilog2(n);
@@ -813,11 +874,11 @@ void fft_dir(const Consts& K, const FftPlan& P, double2* data, int dir, int inve
     pstride = nx * ny;
   }
   if (dir != 0 && lpb > la) lpb = (int)la;  // consecutive lines of a block stay adjacent
-  launch_lines(data, n, logn, pstride, la, lb, lc, nlines, lpb, P.tw[dir], inverse, dir == 0 ? 1 : 0, s);
+  launch_lines(data, n, logn, pstride, la, lb, lc, nlines, lpb, P.tw[dir], inverse, dir == 0 ? 1 : 0, s, bt);
 }
 
-void fft_all(const Consts& K, const FftPlan& P, double2* data, int inverse, hipStream_t s) {
-  for (int dir = 0; dir < K.dim; ++dir) fft_dir(K, P, data, dir, inverse, s);
+void fft_all(const Consts& K, const FftPlan& P, double2* data, int inverse, hipStream_t s, const Bat& bt) {
+  for (int dir = 0; dir < K.dim; ++dir) fft_dir(K, P, data, dir, inverse, s, bt);
 }
 
 int grid_n(long long n) {
@@ -832,7 +893,8 @@ int grid_n(long long n) {
 template <typename T>
 void launch_spectral_solve(const Consts& K, const FftPlan& P, const T* r, double a,
                            const T* zc, double2* work0, double2* work1, T* u,
-                           hipStream_t s) {
+                           hipStream_t s, const Bat& bt) {
+  auto G = [&](unsigned blocks) { return bat_grid(dim3(blocks), bt); };
   const bool all_pow2 = pow2(K.nx) && pow2(K.ny) && pow2(K.nz);
   if (all_pow2 && K.dim == 2 && K.ny <= 1024 && K.nx <= 1024) {
     const int lx = ilog2(K.nx), ly = ilog2(K.ny);
@@ -843,10 +905,10 @@ void launch_spectral_solve(const Consts& K, const FftPlan& P, const T* r, double
     const size_t lcol = sizeof(double2) * (lp_size(4 * K.ny) + K.ny / 2);
     if (lcol > 64 * 1024)  // ny = 1024: 80 KiB
       (void)hipFuncSetAttribute((const void*)k_fft2_cols_solve, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lcol);
-    hipLaunchKernelGGL(k_fft2_rows_fwd<T>, dim3(K.ny / nl), dim3(256), lrow, s, K, r, a, zc, lx, nl, P.tw[0], work0);
-    hipLaunchKernelGGL(k_fft2_cols_solve, dim3(K.nx / 2), dim3(256), lcol, s, K, ly, P.tw[1], P.sn[0],
-                       P.sn[1], work0);
-    hipLaunchKernelGGL(k_fft2_rows_inv<T>, dim3(K.ny / nl), dim3(256), lrow, s, K, lx, nl, P.tw[0], work0, u);
+    hipLaunchKernelGGL(k_fft2_rows_fwd<T>, G(K.ny / nl), dim3(256), lrow, s, K, r, a, zc, lx, nl, P.tw[0], work0, bt);
+    hipLaunchKernelGGL(k_fft2_cols_solve, G(K.nx / 2), dim3(256), lcol, s, K, ly, P.tw[1], P.sn[0],
+                       P.sn[1], work0, bt);
+    hipLaunchKernelGGL(k_fft2_rows_inv<T>, G(K.ny / nl), dim3(256), lrow, s, K, lx, nl, P.tw[0], work0, u, bt);
     return;
   }
   if (all_pow2 && K.dim == 3 && K.nx >= 8 && K.nx <= 1024 && K.nz <= 1024 && K.ny <= 4096) {
@@ -867,35 +929,35 @@ void launch_spectral_solve(const Consts& K, const FftPlan& P, const T* r, double
     int lpy = kFftLds / K.ny;  // adjacent kx lines per y block
     if (lpy > 16) lpy = 16;
     const long long ylines = 3LL * nxh * K.nz;
-    hipLaunchKernelGGL(k_r2c_x<T>, dim3(xblocks), dim3(256), lx_bytes, s, K, r, a, zc, lx, rp, P.tw[0], Qh);
-    launch_lines(Qh, K.ny, ly, nxh, nxh, 1, (long long)nxh * K.ny, ylines, lpy, P.tw[1], 0, 0, s);
-    hipLaunchKernelGGL(k_z_solve, dim3(zblocks), dim3(256), lz_bytes, s, K, lz, lpz, P.tw[2], P.sn[0], P.sn[1],
-                       P.sn[2], Qh);
-    launch_lines(Qh, K.ny, ly, nxh, nxh, 1, (long long)nxh * K.ny, ylines, lpy, P.tw[1], 1, 0, s);
-    hipLaunchKernelGGL(k_c2r_x<T>, dim3(xblocks), dim3(256), lx_bytes, s, K, lx, rp, P.tw[0], Qh, u);
+    hipLaunchKernelGGL(k_r2c_x<T>, G(xblocks), dim3(256), lx_bytes, s, K, r, a, zc, lx, rp, P.tw[0], Qh, bt);
+    launch_lines(Qh, K.ny, ly, nxh, nxh, 1, (long long)nxh * K.ny, ylines, lpy, P.tw[1], 0, 0, s, bt);
+    hipLaunchKernelGGL(k_z_solve, G(zblocks), dim3(256), lz_bytes, s, K, lz, lpz, P.tw[2], P.sn[0], P.sn[1],
+                       P.sn[2], Qh, bt);
+    launch_lines(Qh, K.ny, ly, nxh, nxh, 1, (long long)nxh * K.ny, ylines, lpy, P.tw[1], 1, 0, s, bt);
+    hipLaunchKernelGGL(k_c2r_x<T>, G(xblocks), dim3(256), lx_bytes, s, K, lx, rp, P.tw[0], Qh, u, bt);
     return;
   }
   double2* z0 = work0;
   double2* z1 = work0 + K.N;
   double2* w0 = work1;
   double2* w1 = work1 + K.N;
-  const dim3 g3((unsigned)((K.N + 255) / 256));
-  if (K.dim == 2) hipLaunchKernelGGL((k_pack<2, T>), g3, dim3(256), 0, s, K, r, a, zc, z0, z1);
-  else hipLaunchKernelGGL((k_pack<3, T>), g3, dim3(256), 0, s, K, r, a, zc, z0, z1);
-  fft_all(K, P, z0, 0, s);
-  if (K.dim == 3) fft_all(K, P, z1, 0, s);
+  const dim3 g3 = G((unsigned)((K.N + 255) / 256));
+  if (K.dim == 2) hipLaunchKernelGGL((k_pack<2, T>), g3, dim3(256), 0, s, K, r, a, zc, z0, z1, bt);
+  else hipLaunchKernelGGL((k_pack<3, T>), g3, dim3(256), 0, s, K, r, a, zc, z0, z1, bt);
+  fft_all(K, P, z0, 0, s, bt);
+  if (K.dim == 3) fft_all(K, P, z1, 0, s, bt);
   if (K.dim == 2)
-    hipLaunchKernelGGL(k_symbol_solve<2>, g3, dim3(256), 0, s, K, z0, z1, w0, w1, P.sn[0], P.sn[1], P.sn[2]);
+    hipLaunchKernelGGL(k_symbol_solve<2>, g3, dim3(256), 0, s, K, z0, z1, w0, w1, P.sn[0], P.sn[1], P.sn[2], bt);
   else
-    hipLaunchKernelGGL(k_symbol_solve<3>, g3, dim3(256), 0, s, K, z0, z1, w0, w1, P.sn[0], P.sn[1], P.sn[2]);
-  fft_all(K, P, w0, 1, s);
-  if (K.dim == 3) fft_all(K, P, w1, 1, s);
-  hipLaunchKernelGGL(k_unpack<T>, dim3(grid_n(K.N)), dim3(256), 0, s, K, w0, w1, u);
+    hipLaunchKernelGGL(k_symbol_solve<3>, g3, dim3(256), 0, s, K, z0, z1, w0, w1, P.sn[0], P.sn[1], P.sn[2], bt);
+  fft_all(K, P, w0, 1, s, bt);
+  if (K.dim == 3) fft_all(K, P, w1, 1, s, bt);
+  hipLaunchKernelGGL(k_unpack<T>, G(grid_n(K.N)), dim3(256), 0, s, K, w0, w1, u, bt);
 }
 
 template void launch_spectral_solve<double>(const Consts&, const FftPlan&, const double*, double, const double*,
-                                            double2*, double2*, double*, hipStream_t);
+                                            double2*, double2*, double*, hipStream_t, const Bat&);
 template void launch_spectral_solve<float>(const Consts&, const FftPlan&, const float*, double, const float*,
-                                           double2*, double2*, float*, hipStream_t);
+                                           double2*, double2*, float*, hipStream_t, const Bat&);
 
 }  // namespace pf

@@ -75,15 +75,18 @@ __device__ inline long long lin(const Consts& K, Pt p) {
 // Block coordinates of a stencil launch, reordered for the 8 XCDs: workgroups go to the XCDs
 // round-robin by linear id, so linear id b is given block b' = (b mod 8) * (nb / 8) + b / 8
 // (when nb is a multiple of 8).  Each XCD then sweeps a contiguous band of rows and the halo
-// lines shared by neighbouring blocks are fetched once into its own L2.
-__device__ inline void xcd_block(int& bx, int& by, int& bz) {
-  const int gx = gridDim.x, gy = gridDim.y;
-  const int nb = gx * gy * gridDim.z;
+// lines shared by neighbouring blocks are fetched once into its own L2.  The instance of a
+// lockstep batch is the slowest part of z; returns it.
+__device__ inline int xcd_block(const Bat& bt, int& bx, int& by, int& bz) {
+  const int gx = gridDim.x, gy = gridDim.y, gz = gridDim.z;
+  const int nb = gx * gy * gz;
   int b = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
   if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
   bx = b % gx;
   by = (b / gx) % gy;
-  bz = b / (gx * gy);
+  const int zt = b / (gx * gy), nzl = gz / bt.count;
+  bz = zt % nzl;
+  return zt / nzl;
 }
 
 __device__ inline Pt coords(const Consts& K, long long n) {
@@ -292,9 +295,18 @@ template <bool P2>
 __global__ __launch_bounds__(kBX* kBY) void k_residual_g(Consts K, const double* __restrict__ X,
                                                          const double* __restrict__ Xn,
                                                          double* __restrict__ G4,
-                                                         double* __restrict__ F) {
+                                                         double* __restrict__ F, Bat bt) {
   int bx, by, bz;
-  xcd_block(bx, by, bz);
+  const int bi = xcd_block(bt, bx, by, bz);
+  if (bat_skip(bt, bi)) return;
+  {
+    const long long bo = bi * bt.stride;
+    X = bat_at(X, bo);
+    Xn = bat_at(Xn, bo);
+    G4 = bat_at(G4, bo);
+    F = bat_at(F, bo);
+  }
+  const double cb = bt.cb[bi];
   Pt p{bx * kBX + (int)threadIdx.x, by * kBY + (int)threadIdx.y, bz};
   if (p.i >= K.nx || p.j >= K.ny) return;
   const long long N = K.N, n = lin(K, p);
@@ -312,8 +324,8 @@ __global__ __launch_bounds__(kBX* kBY) void k_residual_g(Consts K, const double*
       div1 += dhat<P2>(K, X + (4 + I) * N, p, I);
       div0 += dhat<P2>(K, Xn + (4 + I) * N, p, I);
     }
-    const double tr1 = K.Ctr * (div1 - K.dim * K.eps0 * (c1 - K.cbar0));
-    const double tr0 = K.Ctr * (div0 - K.dim * K.eps0 * (c0 - K.cbar0));
+    const double tr1 = K.Ctr * (div1 - K.dim * K.eps0 * (c1 - cb));
+    const double tr0 = K.Ctr * (div0 - K.dim * K.eps0 * (c0 - cb));
     Gc -= K.eps0 * 0.5 * (tr1 + tr0);
   }
   Gc -= K.gamma_c * 0.5 * (lap<P2>(K, X, p, c1) + lap<P2>(K, Xn, p, c0));
@@ -323,7 +335,7 @@ __global__ __launch_bounds__(kBX* kBY) void k_residual_g(Consts K, const double*
     G4[(1 + q) * N + n] = Ge[q];
   }
   for (int I = 0; I < K.dim; ++I) {
-    F[(4 + I) * N + n] = K.elastic ? div_sigma<P2>(K, X + 4 * N, N, X, K.cbar0, p, I) : X[(4 + I) * N + n];
+    F[(4 + I) * N + n] = K.elastic ? div_sigma<P2>(K, X + 4 * N, N, X, cb, p, I) : X[(4 + I) * N + n];
   }
 }
 
@@ -361,7 +373,18 @@ __global__ __launch_bounds__(256) void k_residual_f(Consts K, double dt, const d
                                                     const double* __restrict__ Xn,
                                                     const double* __restrict__ G4,
                                                     double* __restrict__ F,
-                                                    double* __restrict__ partial) {
+                                                    double* __restrict__ partial, Bat bt) {
+  const int bi = bat_inst(bt);
+  if (bat_skip(bt, bi)) return;
+  {
+    const long long bo = bi * bt.stride;
+    X = bat_at(X, bo);
+    Xn = bat_at(Xn, bo);
+    G4 = bat_at(G4, bo);
+    F = bat_at(F, bo);
+    partial = bat_at(partial, bo);
+  }
+  dt = bat_s(bt, bi, dt);
   __shared__ double lds[4];
   const long long N = K.N;
   const double idt = 1.0 / dt;
@@ -406,7 +429,16 @@ __global__ __launch_bounds__(256) void k_residual_f(Consts K, double dt, const d
 // mixed-precision preconditioner
 __global__ __launch_bounds__(256) void k_linearise(Consts K, const double* __restrict__ X,
                                                    const double* __restrict__ Xn,
-                                                   double* __restrict__ B, float* __restrict__ Bf) {
+                                                   double* __restrict__ B, float* __restrict__ Bf, Bat bt) {
+  const int bi = bat_inst(bt);
+  if (bat_skip(bt, bi)) return;
+  {
+    const long long bo = bi * bt.stride;
+    X = bat_at(X, bo);
+    Xn = bat_at(Xn, bo);
+    B = bat_at(B, bo);
+    Bf = bat_at(Bf, bo);
+  }
   const long long N = K.N;
   for (long long n = (long long)blockIdx.x * 256 + threadIdx.x; n < N; n += (long long)gridDim.x * 256) {
     double e1[3], e0[3], Ge[3], Gc, b[16];
@@ -493,7 +525,7 @@ constexpr int kJY2 = 8;
 template <typename Tv, bool P2, bool FAR>
 __global__ __launch_bounds__(kBX* kJY2) void k_jv2(Consts K, double dt, const double* __restrict__ B,
                                                    const double* __restrict__ cn, const Tv* __restrict__ v,
-                                                   double* __restrict__ w) {
+                                                   double* __restrict__ w, Bat bt) {
   // v (all six fields, as double) with a halo of 2 (sigma of the u rows reaches distance 2),
   // g = c^n (1 - c^n) and dG with a halo of 1; every stencil below reads LDS, only B comes
   // from global memory
@@ -502,7 +534,16 @@ __global__ __launch_bounds__(kBX* kJY2) void k_jv2(Consts K, double dt, const do
   __shared__ double sv[6 * SP];
   __shared__ double sg[HP], sdg[HP];
   int bx, by, bz;
-  xcd_block(bx, by, bz);
+  const int bi = xcd_block(bt, bx, by, bz);
+  if (bat_skip(bt, bi)) return;
+  {
+    const long long bo = bi * bt.stride;
+    B = bat_at(B, bo);
+    cn = bat_at(cn, bo);
+    v = bat_at(v, bo);
+    w = bat_at(w, bo);
+  }
+  dt = bat_s(bt, bi, dt);
   const int i0 = bx * kBX, j0 = by * kJY2;
   const int tid = threadIdx.x + kBX * threadIdx.y;
   const long long N = K.N;
@@ -600,11 +641,20 @@ constexpr int kJZ = 4;
 template <typename Tv, bool P2, bool FAR>
 __global__ __launch_bounds__(kBX* kBY) void k_jv3(Consts K, double dt, const double* __restrict__ B,
                                                   const double* __restrict__ cn, const Tv* __restrict__ v,
-                                                  double* __restrict__ w, int zc) {
+                                                  double* __restrict__ w, int zc, Bat bt) {
   constexpr int HX = kBX + 2, HY = kBY + 2, HP = HX * HY;
   __shared__ double sdg[3 * HP];
   int bx, by, bz;
-  xcd_block(bx, by, bz);
+  const int bi = xcd_block(bt, bx, by, bz);
+  if (bat_skip(bt, bi)) return;
+  {
+    const long long bo = bi * bt.stride;
+    B = bat_at(B, bo);
+    cn = bat_at(cn, bo);
+    v = bat_at(v, bo);
+    w = bat_at(w, bo);
+  }
+  dt = bat_s(bt, bi, dt);
   const int i0 = bx * kBX, j0 = by * kBY, z0 = bz * zc;
   const int tid = threadIdx.x + kBX * threadIdx.y;
   auto plane = [&](int z) {  // dG of plane z (wrapped) into slot z mod 3
@@ -642,7 +692,12 @@ __device__ inline double psi(double z) { return z * log(z) + (1.0 - z) * log(1.0
 
 template <bool P2>
 __global__ __launch_bounds__(256) void k_energy(Consts K, const double* __restrict__ X,
-                                                double* __restrict__ partial) {
+                                                double* __restrict__ partial, Bat bt) {
+  const int bi = bat_inst(bt);
+  if (bat_skip(bt, bi)) return;
+  X = bat_at(X, bi * bt.stride);
+  partial = bat_at(partial, bi * bt.stride);
+  const double cb = bt.cb[bi];
   __shared__ double lds[4];
   const long long N = K.N;
   double ech = 0.0, eel = 0.0, ein = 0.0, mc = 0.0;
@@ -669,8 +724,8 @@ __global__ __launch_bounds__(256) void k_energy(Consts K, const double* __restri
       for (int I = 0; I < K.dim; ++I)
         for (int J = 0; J < K.dim; ++J) {
           double eij = 0.5 * (dhat<P2>(K, X + (4 + I) * N, p, J) + dhat<P2>(K, X + (4 + J) * N, p, I));
-          if (I == J) eij -= K.eps0 * (c - K.cbar0);
-          s += eij * sigma<P2>(K, X + 4 * N, N, X, K.cbar0, p, I, J);
+          if (I == J) eij -= K.eps0 * (c - cb);
+          s += eij * sigma<P2>(K, X + 4 * N, N, X, cb, p, I, J);
         }
       eel += 0.5 * s;
     }
@@ -709,53 +764,67 @@ bool pow2_sides(const Consts& K) {
   return p2(K.nx) && p2(K.ny) && p2(K.nz);
 }
 
+// the mean composition of each instance (a single problem's from K)
+static Bat with_cbar0(const Consts& K, const Bat& bt) {
+  Bat b = bt;
+  if (!b.per) b.cb[0] = K.cbar0;
+  return b;
+}
+
 void launch_residual(const Consts& K, double dt, const double* X, const double* Xn, double* G4,
-                     double* F, double* partial, hipStream_t s) {
+                     double* F, double* partial, hipStream_t s, const Bat& bt_) {
+  const Bat bt = with_cbar0(K, bt_);
+  const dim3 gg = bat_grid(stencil_grid(K), bt), gf = bat_grid(dim3(kRedBlocks), bt);
   if (pow2_sides(K)) {
-    hipLaunchKernelGGL(k_residual_g<true>, stencil_grid(K), dim3(kBX, kBY), 0, s, K, X, Xn, G4, F);
-    hipLaunchKernelGGL(k_residual_f<true>, dim3(kRedBlocks), dim3(256), 0, s, K, dt, X, Xn, G4, F, partial);
+    hipLaunchKernelGGL(k_residual_g<true>, gg, dim3(kBX, kBY), 0, s, K, X, Xn, G4, F, bt);
+    hipLaunchKernelGGL(k_residual_f<true>, gf, dim3(256), 0, s, K, dt, X, Xn, G4, F, partial, bt);
   } else {
-    hipLaunchKernelGGL(k_residual_g<false>, stencil_grid(K), dim3(kBX, kBY), 0, s, K, X, Xn, G4, F);
-    hipLaunchKernelGGL(k_residual_f<false>, dim3(kRedBlocks), dim3(256), 0, s, K, dt, X, Xn, G4, F, partial);
+    hipLaunchKernelGGL(k_residual_g<false>, gg, dim3(kBX, kBY), 0, s, K, X, Xn, G4, F, bt);
+    hipLaunchKernelGGL(k_residual_f<false>, gf, dim3(256), 0, s, K, dt, X, Xn, G4, F, partial, bt);
   }
 }
 
 void launch_linearise(const Consts& K, const double* X, const double* Xn, double* B, float* Bf,
-                      hipStream_t s) {
+                      hipStream_t s, const Bat& bt) {
   long long nb = (K.N + 255) / 256;
-  hipLaunchKernelGGL(k_linearise, dim3((unsigned)(nb < 4096 ? nb : 4096)), dim3(256), 0, s, K, X, Xn, B, Bf);
+  hipLaunchKernelGGL(k_linearise, bat_grid(dim3((unsigned)(nb < 4096 ? nb : 4096)), bt), dim3(256), 0, s, K, X,
+                     Xn, B, Bf, bt);
 }
 
 template <typename Tv>
 void launch_jv(const Consts& K, double dt, const double* B, const double* cn, const Tv* v, double* w,
-               hipStream_t s) {
+               hipStream_t s, const Bat& bt) {
   const bool p2 = pow2_sides(K);
   if (K.dim == 2) {
     const dim3 g((K.nx + kBX - 1) / kBX, (K.ny + kJY2 - 1) / kJY2, 1);
     // halo positions run from -2 to (blocks x block side) + 1: the two-select wrap holds while
     // that stays below 2n (sides are >= 4)
     const bool far = !((int)g.x * kBX + 1 < 2 * K.nx && (int)g.y * kJY2 + 1 < 2 * K.ny);
-    if (p2) hipLaunchKernelGGL((k_jv2<Tv, true, false>), g, dim3(kBX, kJY2), 0, s, K, dt, B, cn, v, w);
-    else if (far) hipLaunchKernelGGL((k_jv2<Tv, false, true>), g, dim3(kBX, kJY2), 0, s, K, dt, B, cn, v, w);
-    else hipLaunchKernelGGL((k_jv2<Tv, false, false>), g, dim3(kBX, kJY2), 0, s, K, dt, B, cn, v, w);
+    const dim3 gb = bat_grid(g, bt);
+    if (p2) hipLaunchKernelGGL((k_jv2<Tv, true, false>), gb, dim3(kBX, kJY2), 0, s, K, dt, B, cn, v, w, bt);
+    else if (far) hipLaunchKernelGGL((k_jv2<Tv, false, true>), gb, dim3(kBX, kJY2), 0, s, K, dt, B, cn, v, w, bt);
+    else hipLaunchKernelGGL((k_jv2<Tv, false, false>), gb, dim3(kBX, kJY2), 0, s, K, dt, B, cn, v, w, bt);
   } else {
     const int zc = K.nz < kJZ ? K.nz : kJZ;
     const dim3 g((K.nx + kBX - 1) / kBX, (K.ny + kBY - 1) / kBY, (K.nz + zc - 1) / zc);
     // halo columns run from -1 to (blocks x block side), planes from z0 - 1 to z0 + zc
     const bool far = !((int)g.x * kBX < 2 * K.nx && (int)g.y * kBY < 2 * K.ny && (int)g.z * zc < 2 * K.nz);
-    if (p2) hipLaunchKernelGGL((k_jv3<Tv, true, false>), g, dim3(kBX, kBY), 0, s, K, dt, B, cn, v, w, zc);
-    else if (far) hipLaunchKernelGGL((k_jv3<Tv, false, true>), g, dim3(kBX, kBY), 0, s, K, dt, B, cn, v, w, zc);
-    else hipLaunchKernelGGL((k_jv3<Tv, false, false>), g, dim3(kBX, kBY), 0, s, K, dt, B, cn, v, w, zc);
+    const dim3 gb = bat_grid(g, bt);
+    if (p2) hipLaunchKernelGGL((k_jv3<Tv, true, false>), gb, dim3(kBX, kBY), 0, s, K, dt, B, cn, v, w, zc, bt);
+    else if (far) hipLaunchKernelGGL((k_jv3<Tv, false, true>), gb, dim3(kBX, kBY), 0, s, K, dt, B, cn, v, w, zc, bt);
+    else hipLaunchKernelGGL((k_jv3<Tv, false, false>), gb, dim3(kBX, kBY), 0, s, K, dt, B, cn, v, w, zc, bt);
   }
 }
 template void launch_jv<double>(const Consts&, double, const double*, const double*, const double*, double*,
-                                hipStream_t);
+                                hipStream_t, const Bat&);
 template void launch_jv<float>(const Consts&, double, const double*, const double*, const float*, double*,
-                               hipStream_t);
+                               hipStream_t, const Bat&);
 
-void launch_energy(const Consts& K, const double* X, double* partial, hipStream_t s) {
-  if (pow2_sides(K)) hipLaunchKernelGGL(k_energy<true>, dim3(kRedBlocks), dim3(256), 0, s, K, X, partial);
-  else hipLaunchKernelGGL(k_energy<false>, dim3(kRedBlocks), dim3(256), 0, s, K, X, partial);
+void launch_energy(const Consts& K, const double* X, double* partial, hipStream_t s, const Bat& bt_) {
+  const Bat bt = with_cbar0(K, bt_);
+  const dim3 g = bat_grid(dim3(kRedBlocks), bt);
+  if (pow2_sides(K)) hipLaunchKernelGGL(k_energy<true>, g, dim3(256), 0, s, K, X, partial, bt);
+  else hipLaunchKernelGGL(k_energy<false>, g, dim3(256), 0, s, K, X, partial, bt);
 }
 
 }  // namespace pf

@@ -74,7 +74,17 @@ constexpr int kPackThreads = 1024;
 template <int DIM, typename R>
 __global__ __launch_bounds__(kPackThreads) void k_ras_pack(Consts K, Geo G, double dt, const R* __restrict__ Bg,
                                                            const double* __restrict__ cn,
-                                                           const int* __restrict__ iperm, R* __restrict__ pack) {
+                                                           const int* __restrict__ iperm, R* __restrict__ pack,
+                                                           Bat bt) {
+  const int bi = bat_inst(bt);
+  if (bat_skip(bt, bi)) return;
+  {
+    const long long bo = bi * bt.stride;
+    Bg = bat_at(Bg, bo);
+    cn = bat_at(cn, bo);
+    pack = bat_at(pack, bo);
+  }
+  dt = bat_s(bt, bi, dt);
   const int t = blockIdx.x;
   const int tix = t % G.ntx, tiy = (t / G.ntx) % G.nty, tiz = t / (G.ntx * G.nty);
   const int ox = tix * G.tx - G.ov, oy = tiy * G.ty - G.ov, oz = (DIM == 3) ? tiz * G.tz - G.ov : 0;
@@ -150,7 +160,20 @@ __global__ __launch_bounds__(TH, (ras_waves_per_eu<TH>())) void k_ras(Consts K, 
                                                      R* __restrict__ zg,
                                                      const int* __restrict__ permg,
                                                      const R* __restrict__ pack,
-                                                     R* __restrict__ xs) {
+                                                     R* __restrict__ xs, Bat bt) {
+  // instance of a lockstep batch (the colour order permg is shared, read from instance 0)
+  const int bi = bat_inst(bt);
+  if (bat_skip(bt, bi)) return;
+  {
+    const long long bo = bi * bt.stride;
+    Bg = bat_at(Bg, bo);
+    cn = bat_at(cn, bo);
+    rg = bat_at(rg, bo);
+    zg = bat_at(zg, bo);
+    pack = bat_at(pack, bo);
+    xs = bat_at(xs, bo);
+  }
+  dt = bat_s(bt, bi, dt);
   constexpr int NFZ = WU ? 4 + DIM : 4;
   constexpr int ZP0 = WU ? 0 : 1;     // first field of the iterate held in LDS
   constexpr int NZL = NFZ - ZP0;      // its LDS planes
@@ -494,7 +517,12 @@ __global__ __launch_bounds__(TH, (ras_waves_per_eu<TH>())) void k_ras(Consts K, 
 // z at every node = sum of the extended solutions of the tiles whose extended block contains
 // it, tiles taken in a fixed order (at most two per direction: overlap <= tile / 2)
 template <int DIM, int NFZ, typename R>
-__global__ __launch_bounds__(256) void k_ras_gather(Consts K, Geo G, const R* __restrict__ xs, R* __restrict__ zg) {
+__global__ __launch_bounds__(256) void k_ras_gather(Consts K, Geo G, const R* __restrict__ xs, R* __restrict__ zg,
+                                                    Bat bt) {
+  const int bi = bat_inst(bt);
+  if (bat_skip(bt, bi)) return;
+  xs = bat_at(xs, bi * bt.stride);
+  zg = bat_at(zg, bi * bt.stride);
   const long long n = (long long)blockIdx.x * 256 + threadIdx.x;
   if (n >= K.N) return;
   const int i = (int)(n % K.nx), j = (int)((n / K.nx) % K.ny), k = (int)(n / ((long long)K.nx * K.ny));
@@ -557,19 +585,21 @@ Geo make_geo(const Consts& K, const TileCfg& T) {
 
 template <int DIM, bool WU, typename R, int TH>
 void launch_npt(const Geo& G, const Consts& K, size_t lds, int ntiles, int npt, double dt, const R* B,
-                const double* cn, const R* r, R* z, const int* perm, const R* pack, R* xs, hipStream_t s) {
+                const double* cn, const R* r, R* z, const int* perm, const R* pack, R* xs, hipStream_t s,
+                const Bat& bt) {
+  const dim3 grid = bat_grid(dim3(ntiles), bt);
 #define PF_RAS_CASE(NPTV)                                                                             \
   case NPTV:                                                                                          \
     (void)hipFuncSetAttribute((const void*)k_ras<DIM, WU, NPTV, R, TH>,                              \
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                  \
-    hipLaunchKernelGGL((k_ras<DIM, WU, NPTV, R, TH>), dim3(ntiles), dim3(TH), lds, s, K, G, dt, B, cn, r, z, perm, pack, xs); \
+    hipLaunchKernelGGL((k_ras<DIM, WU, NPTV, R, TH>), grid, dim3(TH), lds, s, K, G, dt, B, cn, r, z, perm, pack, xs, bt); \
     break;
   if constexpr (TH == kRasThreadsSmall) {
     if (npt == 4) {
       (void)hipFuncSetAttribute((const void*)k_ras<DIM, WU, 4, R, TH>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)lds);
-      hipLaunchKernelGGL((k_ras<DIM, WU, 4, R, TH>), dim3(ntiles), dim3(TH), lds, s, K, G, dt, B, cn, r, z, perm, pack,
-                         xs);
+      hipLaunchKernelGGL((k_ras<DIM, WU, 4, R, TH>), grid, dim3(TH), lds, s, K, G, dt, B, cn, r, z, perm, pack,
+                         xs, bt);
       return;
     }
   }
@@ -585,15 +615,15 @@ void launch_npt(const Geo& G, const Consts& K, size_t lds, int ntiles, int npt, 
 template <int DIM, bool WU, typename R>
 void launch_dim(const Consts& K, const Geo& G, size_t lds, int ntiles, int th, int npt, double dt,
                 const R* B, const double* cn, const R* r, R* z, const int* perm, const R* pack, R* xs,
-                hipStream_t s) {
+                hipStream_t s, const Bat& bt) {
   if (!WU && th == kRasThreadsSmall)
-    launch_npt<DIM, false, R, kRasThreadsSmall>(G, K, lds, ntiles, npt, dt, B, cn, r, z, perm, pack, xs, s);
+    launch_npt<DIM, false, R, kRasThreadsSmall>(G, K, lds, ntiles, npt, dt, B, cn, r, z, perm, pack, xs, s, bt);
   else
-    launch_npt<DIM, WU, R, kRasThreadsMax>(G, K, lds, ntiles, npt, dt, B, cn, r, z, perm, pack, xs, s);
+    launch_npt<DIM, WU, R, kRasThreadsMax>(G, K, lds, ntiles, npt, dt, B, cn, r, z, perm, pack, xs, s, bt);
   if (G.mode != kRasLeft) {
     constexpr int NFZ = WU ? 4 + DIM : 4;
-    hipLaunchKernelGGL((k_ras_gather<DIM, NFZ, R>), dim3((unsigned)((K.N + 255) / 256)), dim3(256), 0, s, K, G,
-                       (const R*)xs, z);
+    hipLaunchKernelGGL((k_ras_gather<DIM, NFZ, R>), bat_grid(dim3((unsigned)((K.N + 255) / 256)), bt), dim3(256), 0,
+                       s, K, G, (const R*)xs, z, bt);
   }
 }
 
@@ -660,7 +690,7 @@ int ras_threads(const Consts& K, const TileCfg& T, size_t real_bytes, int* npt) 
 
 template <typename R>
 void launch_ras(const Consts& K, const TileCfg& T, double dt, const R* B, const double* cn,
-                const R* r, R* z, hipStream_t s) {
+                const R* r, R* z, hipStream_t s, const Bat& bt) {
   const Geo G = make_geo(K, T);
   const int ntiles = G.ntx * G.nty * ((K.dim == 3) ? K.nz / T.tz : 1);
   const size_t lds = ras_lds_bytes(K, T, sizeof(R));
@@ -669,29 +699,32 @@ void launch_ras(const Consts& K, const TileCfg& T, double dt, const R* B, const 
   R* xs = static_cast<R*>(T.scratch);
   const R* pk = static_cast<const R*>(T.pack);
   if (K.dim == 2) {
-    if (T.with_u) launch_dim<2, true, R>(K, G, lds, ntiles, th, npt, dt, B, cn, r, z, T.perm, pk, xs, s);
-    else launch_dim<2, false, R>(K, G, lds, ntiles, th, npt, dt, B, cn, r, z, T.perm, pk, xs, s);
+    if (T.with_u) launch_dim<2, true, R>(K, G, lds, ntiles, th, npt, dt, B, cn, r, z, T.perm, pk, xs, s, bt);
+    else launch_dim<2, false, R>(K, G, lds, ntiles, th, npt, dt, B, cn, r, z, T.perm, pk, xs, s, bt);
   } else {
-    if (T.with_u) launch_dim<3, true, R>(K, G, lds, ntiles, th, npt, dt, B, cn, r, z, T.perm, pk, xs, s);
-    else launch_dim<3, false, R>(K, G, lds, ntiles, th, npt, dt, B, cn, r, z, T.perm, pk, xs, s);
+    if (T.with_u) launch_dim<3, true, R>(K, G, lds, ntiles, th, npt, dt, B, cn, r, z, T.perm, pk, xs, s, bt);
+    else launch_dim<3, false, R>(K, G, lds, ntiles, th, npt, dt, B, cn, r, z, T.perm, pk, xs, s, bt);
   }
 }
 
 template <typename R>
-void launch_ras_pack(const Consts& K, const TileCfg& T, double dt, const R* B, const double* cn, hipStream_t s) {
+void launch_ras_pack(const Consts& K, const TileCfg& T, double dt, const R* B, const double* cn, hipStream_t s,
+                     const Bat& bt) {
   const Geo G = make_geo(K, T);
   const int ntiles = G.ntx * G.nty * ((K.dim == 3) ? K.nz / T.tz : 1);
   R* pk = static_cast<R*>(T.pack);
   const int* iperm = T.perm + G.ex * G.ey * G.ez;
   if (K.dim == 2)
-    hipLaunchKernelGGL((k_ras_pack<2, R>), dim3(ntiles), dim3(kPackThreads), 0, s, K, G, dt, B, cn, iperm, pk);
+    hipLaunchKernelGGL((k_ras_pack<2, R>), bat_grid(dim3(ntiles), bt), dim3(kPackThreads), 0, s, K, G, dt, B, cn,
+                       iperm, pk, bt);
   else
-    hipLaunchKernelGGL((k_ras_pack<3, R>), dim3(ntiles), dim3(kPackThreads), 0, s, K, G, dt, B, cn, iperm, pk);
+    hipLaunchKernelGGL((k_ras_pack<3, R>), bat_grid(dim3(ntiles), bt), dim3(kPackThreads), 0, s, K, G, dt, B, cn,
+                       iperm, pk, bt);
 }
 template void launch_ras_pack<double>(const Consts&, const TileCfg&, double, const double*, const double*,
-                                      hipStream_t);
+                                      hipStream_t, const Bat&);
 template void launch_ras_pack<float>(const Consts&, const TileCfg&, double, const float*, const double*,
-                                     hipStream_t);
+                                     hipStream_t, const Bat&);
 
 size_t ras_pack_values(const Consts& K, const TileCfg& T) {
   const Geo G = make_geo(K, T);
@@ -699,8 +732,8 @@ size_t ras_pack_values(const Consts& K, const TileCfg& T) {
   return ntiles * kPackVals * (size_t)G.ex * G.ey * G.ez;
 }
 template void launch_ras<double>(const Consts&, const TileCfg&, double, const double*, const double*,
-                                 const double*, double*, hipStream_t);
+                                 const double*, double*, hipStream_t, const Bat&);
 template void launch_ras<float>(const Consts&, const TileCfg&, double, const float*, const double*,
-                                const float*, float*, hipStream_t);
+                                const float*, float*, hipStream_t, const Bat&);
 
 }  // namespace pf

@@ -35,18 +35,84 @@ struct Consts {
   double qd[kMaxS];      // qd[j-1] = 1/(2(2j+1))               (coefficients of P')
 };
 
+// ---- lockstep batches of one grid shape (pfnks_group) --------------------------------
+// A launch may cover `count` problems of one shape at once.  Instance b's workspace starts
+// b * stride bytes after instance 0's, so every pointer argument points into instance 0's
+// workspace and a workgroup of instance b adds b * stride; pinned host slots (the second
+// output of the finalize kernels) are hstride bytes apart.  The slowest grid axis (z) is
+// split into count equal parts, one per instance, and a workgroup whose instance has its bit
+// of mask clear returns at once.  Tables that every instance shares (twiddles, Fourier
+// symbols, colour order) are read from instance 0.  A single problem is the batch of one.
+// With per = 1 the per-instance scalars replace a launch's scalar argument: s is the time
+// step of the stencil, tile and residual launches, the coefficient a of axpby and the step
+// length of the line-search trial; cb is the mean composition cbar0 of each instance (the
+// eigenstrain reference of the residual and the energy).
+constexpr int kMaxBatch = 32;
+struct Bat {
+  long long stride = 0;
+  long long hstride = 0;
+  int count = 1;
+  int per = 0;
+  unsigned mask = 0xffffffffu;
+  double s[kMaxBatch] = {};
+  double s2[kMaxBatch] = {};
+  double s3[kMaxBatch] = {};
+  double cb[kMaxBatch] = {};
+};
+
+// the grid of a launch over every instance of bt (z multiplied by the instance count)
+inline dim3 bat_grid(dim3 g, const Bat& bt) {
+  g.z *= (unsigned)bt.count;
+  return g;
+}
+// p moved by off bytes; null stays null (optional arguments)
+template <typename T>
+__host__ __device__ inline T* bat_at(T* p, long long off) {
+  return p ? reinterpret_cast<T*>(reinterpret_cast<char*>(p) + off) : p;
+}
+template <typename T>
+__host__ __device__ inline const T* bat_at(const T* p, long long off) {
+  return p ? reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) + off) : p;
+}
+// Per-instance state of the device-side GMRES cycle of a lockstep batch: the Hessenberg
+// matrix H ((m + 1) x m, column j at j (m + 1)), the Givens rotations cs, sn, the rotated
+// right-hand side g (m + 1), the cycle's solution y (m + 1; y[m] = its column count) and a
+// status block (kGiv*).
+struct GivLayout {
+  long long H, cs, sn, g, y, st, total;
+};
+__host__ __device__ inline GivLayout giv_layout(int m) {
+  GivLayout L;
+  L.H = 0;
+  L.cs = L.H + (long long)(m + 1) * m;
+  L.sn = L.cs + m;
+  L.g = L.sn + m;
+  L.y = L.g + m + 1;
+  L.st = L.y + m + 1;
+  L.total = L.st + 8;
+  return L;
+}
+constexpr int kGivEnded = 0, kGivCols = 1, kGivTol = 2, kGivLim = 3, kGivResid = 4, kGivNonfinite = 5;
+
+// instance of this workgroup and its position along the instance's own part of z
+__device__ inline int bat_inst(const Bat& bt) { return (int)(blockIdx.z / (gridDim.z / (unsigned)bt.count)); }
+__device__ inline int bat_z(const Bat& bt) { return (int)(blockIdx.z % (gridDim.z / (unsigned)bt.count)); }
+__device__ inline int bat_nz(const Bat& bt) { return (int)(gridDim.z / (unsigned)bt.count); }
+__device__ inline bool bat_skip(const Bat& bt, int b) { return ((bt.mask >> b) & 1u) == 0u; }
+__device__ inline double bat_s(const Bat& bt, int b, double v) { return bt.per ? bt.s[b] : v; }
+
 // ---- phase-field kernels (kernels_phase.hip) ---------------------------------------
 // X, Xn: nf planes (c, eta1..3, u1..ud); all plane strides are N.
 void launch_residual(const Consts& K, double dt, const double* X, const double* Xn, double* G4,
-                     double* F, double* partial, hipStream_t s);
+                     double* F, double* partial, hipStream_t s, const Bat& bt = Bat());
 // B: 16 block planes; Bf (may be null): the same rounded to float
 void launch_linearise(const Consts& K, const double* X, const double* Xn, double* B, float* Bf,
-                      hipStream_t s);
+                      hipStream_t s, const Bat& bt = Bat());
 // w = J v; v has element type Tv (double or float), w is double
 template <typename Tv>
 void launch_jv(const Consts& K, double dt, const double* B, const double* cn, const Tv* v, double* w,
-               hipStream_t s);
-void launch_energy(const Consts& K, const double* X, double* partial, hipStream_t s);
+               hipStream_t s, const Bat& bt = Bat());
+void launch_energy(const Consts& K, const double* X, double* partial, hipStream_t s, const Bat& bt = Bat());
 
 // ---- Schwarz tile solve (kernels_ras.hip) -------------------------------------------
 struct TileCfg {
@@ -65,12 +131,13 @@ struct TileCfg {
 // R (double or float): element type of the blocks B, of r and z, and of the tile arithmetic
 template <typename R>
 void launch_ras(const Consts& K, const TileCfg& T, double dt, const R* B, const double* cn,
-                const R* r, R* z, hipStream_t s);
+                const R* r, R* z, hipStream_t s, const Bat& bt = Bat());
 size_t ras_lds_bytes(const Consts& K, const TileCfg& T, size_t real_bytes);
 // once per time step, after the preconditioner blocks B: the node-block pieces of every
 // extended tile into T.pack (ras_pack_values(K, T) elements of type R)
 template <typename R>
-void launch_ras_pack(const Consts& K, const TileCfg& T, double dt, const R* B, const double* cn, hipStream_t s);
+void launch_ras_pack(const Consts& K, const TileCfg& T, double dt, const R* B, const double* cn, hipStream_t s,
+                     const Bat& bt = Bat());
 size_t ras_pack_values(const Consts& K, const TileCfg& T);
 // workgroup size of the tile kernel for this tile shape and element size (0: shape not
 // supported); *npt (may be null): nodes of the extended tile per thread
@@ -90,36 +157,57 @@ struct FftPlan {
 template <typename T>
 void launch_spectral_solve(const Consts& K, const FftPlan& P, const T* r, double a,
                            const T* zc, double2* work0, double2* work1, T* u,
-                           hipStream_t s);
+                           hipStream_t s, const Bat& bt = Bat());
 
 // ---- vector kernels and reductions (kernels_blas.hip) --------------------------------
 // V: nv vectors of length n stored ldv apart.  The basis element type T is double or float
 // (instantiated for both); every sum is accumulated in double.
 template <typename T>
 void launch_multidot(long long n, int nv, const T* V, long long ldv, const double* w,
-                     double* partial, hipStream_t s);
+                     double* partial, hipStream_t s, const Bat& bt = Bat());
 template <typename T, typename To>
 void launch_lincomb(long long n, int nv, const T* V, long long ldv, const double* coef,
-                    double beta, To* out, hipStream_t s);
+                    double beta, To* out, hipStream_t s, const Bat& bt = Bat());
 // out = a x + b y (y unread when b == 0); instantiated for (d,d,d), (d,d,f), (f,f,f), (f,f,d)
 template <typename Tx, typename Ty, typename To>
-void launch_axpby(long long n, double a, const Tx* x, double b, const Ty* y, To* out, hipStream_t s);
-void launch_finalize(const double* partial, int nvals, double* out, hipStream_t s, double* out2 = nullptr);
+void launch_axpby(long long n, double a, const Tx* x, double b, const Ty* y, To* out, hipStream_t s,
+                  const Bat& bt = Bat());
+void launch_finalize(const double* partial, int nvals, double* out, hipStream_t s, double* out2 = nullptr,
+                     const Bat& bt = Bat());
 // v_{j+1} from device-resident Gram-Schmidt coefficients hc = [h_0..h_{nv-1}, <w,w>]
 template <typename T>
 void launch_update_dev(long long n, int nv, const T* V, long long ldv, const double* hc,
-                       const double* w, T* out, hipStream_t s);
+                       const double* w, T* out, hipStream_t s, const Bat& bt = Bat());
 void launch_sum2(long long n, const double* x, const double* y, const double* yn, double* partial,
-                 hipStream_t s);
+                 hipStream_t s, const Bat& bt = Bat());
 // Xt = X + lam (S + shift e_c), shift = -(msums[0] + msums[1]) / N (device sums of launch_sum2,
 // finalized); partial: count of nodes outside the log domain; pmax (may be null): per-block
 // maxima of |S_f + shift_f| and |X_f| for every field f (2 nf values, for launch_finalize_max)
 void launch_trial(const Consts& K, int nf, const double* X, const double* S, double lam,
-                  const double* msums, double* Xt, double* partial, double* pmax, hipStream_t s);
+                  const double* msums, double* Xt, double* partial, double* pmax, hipStream_t s,
+                  const Bat& bt = Bat());
 // second stage of per-block maxima of non-negative values (nvals <= 16)
-void launch_finalize_max(const double* partial, int nvals, double* out, hipStream_t s, double* out2 = nullptr);
-void launch_dx2(long long n4, const double* X, const double* Xn, double* partial, hipStream_t s);
-void launch_class_sums(const Consts& K, const double* u, double* partial, hipStream_t s);
-void launch_class_shift(const Consts& K, double* u, const double* sums, hipStream_t s);
+void launch_finalize_max(const double* partial, int nvals, double* out, hipStream_t s, double* out2 = nullptr,
+                         const Bat& bt = Bat());
+void launch_dx2(long long n4, const double* X, const double* Xn, double* partial, hipStream_t s,
+                const Bat& bt = Bat());
+void launch_class_sums(const Consts& K, const double* u, double* partial, hipStream_t s, const Bat& bt = Bat());
+void launch_class_shift(const Consts& K, double* u, const double* sums, hipStream_t s, const Bat& bt = Bat());
+
+// ---- device-side GMRES cycle of a lockstep batch (kernels_blas.hip) -------------------
+// giv: each instance's GivLayout(m) block.  launch_giv_init starts a cycle (bt.s: beta,
+// bt.s2: tolerance, bt.s3: column limit); launch_arnoldi finalizes the multi-dot partials of
+// Arnoldi step j into hcol (as launch_finalize), applies the Givens rotations and the end
+// test, and writes (ended, |g_{j+1}|, columns, not finite) to host (pinned, hstride apart);
+// launch_ysolve solves the cycle's triangular system; launch_lincomb_dev adds Z y to out.
+void launch_giv_init(double* giv, int m, hipStream_t s, const Bat& bt);
+void launch_arnoldi(const double* partial, int j, int m, double* hcol, double* giv, double* host, hipStream_t s,
+                    const Bat& bt);
+void launch_ysolve(double* giv, int m, hipStream_t s, const Bat& bt);
+template <typename T, typename To>
+void launch_lincomb_dev(long long n, int nv, const T* V, long long ldv, const double* giv, int m, To* out,
+                        hipStream_t s, const Bat& bt);
+template <typename T>
+void launch_fill_zero(long long n, T* out, hipStream_t s, const Bat& bt = Bat());
 
 }  // namespace pf

@@ -60,7 +60,7 @@ struct Layout {
 
 enum Buf {
   B_X, B_XN, B_XT, B_F, B_FT, B_S, B_B, B_BPC, B_G4, B_V, B_ZB, B_W, B_Z, B_TMP, B_TMPV, B_PART, B_RED,
-  B_FFT0, B_FFT1, B_TW0, B_TW1, B_TW2, B_SN0, B_SN1, B_SN2, B_HDEV, B_PERM, B_ASX, B_PACK, B_COUNT
+  B_FFT0, B_FFT1, B_TW0, B_TW1, B_TW2, B_SN0, B_SN1, B_SN2, B_HDEV, B_PERM, B_ASX, B_PACK, B_GIV, B_COUNT
 };
 
 // bytes of one element of the Krylov basis, the preconditioner blocks and the tile solve
@@ -103,6 +103,8 @@ Layout make_layout(int dim, long long N, int restart, const int* n, int precisio
   sz[B_ASX] = kb * (size_t)nf * (size_t)ext_nodes * (size_t)tiles_summed;
   // every tile's node-block pieces (13 per extended node), formed once per time step
   sz[B_PACK] = kb * 13 * (size_t)ext_nodes * (size_t)tiles_packed;
+  // Hessenberg matrix, rotations and status of the device-side GMRES cycle (problem groups)
+  sz[B_GIV] = sizeof(double) * (size_t)pf::giv_layout(restart).total;
   Layout L{};
   size_t o = 0;
   for (int b = 0; b < B_COUNT; ++b) {
@@ -202,6 +204,7 @@ struct pfnks_problem {
   double* hbuf;   // pinned host scalars (written directly by the finalize kernels)
   double* hdev;   // device Gram-Schmidt columns [h_0..h_j, <w,w>], one slot of m+2 per j
   double* hhost;  // pinned host mirror of hdev
+  double* giv;    // device GMRES cycle state (GivLayout), used by problem groups
   std::vector<hipEvent_t> hev;  // one per Arnoldi column
   double t;
   long long launches, syncs;
@@ -369,6 +372,13 @@ int dot_norm(pfnks_problem* p, const double* x, double* nrm) {
   return PFNKS_OK;
 }
 
+// bt with every instance's scalar set to 1 (a plain copy through axpby)
+pf::Bat bat_ones(const pf::Bat& bt) {
+  pf::Bat b = bt;
+  for (int i = 0; i < pf::kMaxBatch; ++i) b.s[i] = 1.0;
+  return b;
+}
+
 // algorithmic bytes of the per-step tile set-up: every extended tile node reads its chemical
 // block (16) in the Krylov element type and c^n (double) and writes 13 node-block values
 double pack_bytes(pfnks_problem* p) {
@@ -396,18 +406,18 @@ double ras_bytes(pfnks_problem* p, int nfz) {
 }
 
 // once per time step, after the lagged preconditioner blocks Bpc: the tile solve's node blocks
-void pc_setup(pfnks_problem* p, double dt) {
+void pc_setup(pfnks_problem* p, double dt, const pf::Bat& bt = pf::Bat()) {
   if (!uses_tiles(p->solver.pc)) return;
   if (p->solver.precision == PFNKS_MIXED)
-    pf::launch_ras_pack<float>(p->K, p->T, dt, (const float*)p->Bpc, p->Xn, p->stream);
+    pf::launch_ras_pack<float>(p->K, p->T, dt, (const float*)p->Bpc, p->Xn, p->stream, bt);
   else
-    pf::launch_ras_pack<double>(p->K, p->T, dt, (const double*)p->Bpc, p->Xn, p->stream);
+    pf::launch_ras_pack<double>(p->K, p->T, dt, (const double*)p->Bpc, p->Xn, p->stream, bt);
   p->launches += 1;
 }
 
 // z = M^{-1} r with the lagged preconditioner blocks Bpc; T is the Krylov element type
 template <typename T>
-void pc_apply(pfnks_problem* p, double dt, const T* r, T* z) {
+void pc_apply(pfnks_problem* p, double dt, const T* r, T* z, const pf::Bat& bt = pf::Bat()) {
   const long long N = p->N;
   const int pc = p->solver.pc;
   const T* Bpc = static_cast<const T*>(p->Bpc);
@@ -416,7 +426,7 @@ void pc_apply(pfnks_problem* p, double dt, const T* r, T* z) {
     T_.with_u = 1;
     T_.mode = (pc == PFNKS_PC_AS) ? 1 : (pc == PFNKS_PC_RRAS) ? 2 : 0;
     Prof pr(p, PFNKS_K_RAS, ras_bytes(p, 4 + p->K.dim));
-    pf::launch_ras<T>(p->K, T_, dt, Bpc, p->Xn, r, z, p->stream);
+    pf::launch_ras<T>(p->K, T_, dt, Bpc, p->Xn, r, z, p->stream, bt);
     p->launches += sums_overlap(pc) ? 2 : 1;
     return;
   }
@@ -424,30 +434,31 @@ void pc_apply(pfnks_problem* p, double dt, const T* r, T* z) {
     pf::TileCfg T_ = p->T;
     T_.with_u = 0;
     Prof pr(p, PFNKS_K_RAS, ras_bytes(p, 4));
-    pf::launch_ras<T>(p->K, T_, dt, Bpc, p->Xn, r, z, p->stream);
+    pf::launch_ras<T>(p->K, T_, dt, Bpc, p->Xn, r, z, p->stream, bt);
     p->launches += 1;
   } else {
-    // PFNKS_PC_NONE and PFNKS_PC_SPECTRAL: z_w = r_w
-    pf::launch_axpby<T, T, T>(4 * N, 1.0, r, 0.0, nullptr, z, p->stream);
+    // PFNKS_PC_NONE and PFNKS_PC_SPECTRAL: z_w = r_w (a copy: every instance's scale is 1)
+    pf::launch_axpby<T, T, T>(4 * N, 1.0, r, 0.0, nullptr, z, p->stream, bat_ones(bt));
     p->launches += 1;
   }
   if (pc == PFNKS_PC_NONE) {
-    pf::launch_axpby<T, T, T>((long long)p->K.dim * N, 1.0, r + 4 * N, 0.0, nullptr, z + 4 * N, p->stream);
+    pf::launch_axpby<T, T, T>((long long)p->K.dim * N, 1.0, r + 4 * N, 0.0, nullptr, z + 4 * N, p->stream,
+                              bat_ones(bt));
     p->launches += 1;
     return;
   }
   // displacement block: z_u = K^{-1} (r_u - J_uc z_c) = K^{-1} (r_u + eps0 Ctr Dhat z_c)
   Prof pr(p, PFNKS_K_SPECTRAL, (double)p->kb * (2 * p->K.dim + 1) * N);
   pf::launch_spectral_solve<T>(p->K, p->plan, r + 4 * N, p->K.eps0 * p->K.Ctr, z, p->fft0, p->fft1,
-                               z + 4 * N, p->stream);
+                               z + 4 * N, p->stream, bt);
   p->launches += 3 + 4 * p->K.dim * (p->K.dim == 3 ? 2 : 1);
 }
 
 // w = J v (v in element type Tv; arithmetic and w in double)
 template <typename Tv>
-void jv(pfnks_problem* p, double dt, const double* Bm, const Tv* v, double* w) {
+void jv(pfnks_problem* p, double dt, const double* Bm, const Tv* v, double* w, const pf::Bat& bt = pf::Bat()) {
   Prof pr(p, PFNKS_K_JV, (double)p->nvec * (sizeof(Tv) + 8.0) + 136.0 * p->N);
-  pf::launch_jv<Tv>(p->K, dt, Bm, p->Xn, v, w, p->stream);
+  pf::launch_jv<Tv>(p->K, dt, Bm, p->Xn, v, w, p->stream, bt);
   p->launches += 1;
 }
 
@@ -702,32 +713,14 @@ int pfnks_residual_static(const pfnks_grid* grid, const pfnks_model* model, doub
   return PFNKS_OK;
 }
 
-int pfnks_workspace_bytes(const pfnks_grid* grid, const pfnks_model* model, const pfnks_solver* solver,
-                          size_t* bytes) {
-  if (!bytes) return PFNKS_EINVAL;
-  int st = validate(grid, model, solver);
-  if (st) return st;
-  const long long N = (long long)grid->n[0] * grid->n[1] * (grid->dim == 3 ? grid->n[2] : 1);
-  *bytes = make_layout(grid->dim, N, solver->gmres_restart, grid->n, solver->precision, ext_nodes(grid, solver),
-                       tiles_summed(grid, solver), tiles_packed(grid, solver)).total;
-  return PFNKS_OK;
-}
+}  // extern "C"
 
-int pfnks_create_problem(const pfnks_grid* grid, const pfnks_model* model, const pfnks_solver* solver,
-                         const double* c0, const double* eta0, void* d_workspace, size_t ws_bytes,
-                         void* hip_stream, pfnks_problem** out) {
-  if (!out || !c0 || !eta0 || !d_workspace) return PFNKS_EINVAL;
-  *out = nullptr;
-  int st = validate(grid, model, solver);
-  if (st) return st;
-  if (((uintptr_t)d_workspace & 255) != 0) return PFNKS_EINVAL;
-  const long long N = (long long)grid->n[0] * grid->n[1] * (grid->dim == 3 ? grid->n[2] : 1);
-  const Layout L = make_layout(grid->dim, N, solver->gmres_restart, grid->n, solver->precision, ext_nodes(grid, solver),
-                               tiles_summed(grid, solver), tiles_packed(grid, solver));
-  if (ws_bytes < L.total) return PFNKS_ENOSPACE;
-  st = check_domain_host(c0, eta0, N);
-  if (st) return st;
+namespace {
 
+// the problem object over a workspace laid out by L: device pointers, pinned host scalars,
+// events, twiddle and symbol tables and the tile colour order (no state yet)
+int setup_problem(const pfnks_grid* grid, const pfnks_model* model, const pfnks_solver* solver, const Layout& L,
+                  long long N, char* ws, hipStream_t stream, pfnks_problem** out) {
   pfnks_problem* p = new pfnks_problem();
   p->prof = 0;
   p->hbuf = nullptr;
@@ -744,8 +737,8 @@ int pfnks_create_problem(const pfnks_grid* grid, const pfnks_model* model, const
   p->nf = 4 + grid->dim;
   p->N = N;
   p->nvec = (long long)p->nf * N;
-  p->stream = (hipStream_t)hip_stream;
-  p->ws = (char*)d_workspace;
+  p->stream = stream;
+  p->ws = ws;
   make_consts(p);
   p->T.tx = solver->tile[0];
   p->T.ty = solver->tile[1];
@@ -786,6 +779,7 @@ int pfnks_create_problem(const pfnks_grid* grid, const pfnks_model* model, const
   p->red = ptr(B_RED);
   p->fft0 = (double2*)(p->ws + L.off[B_FFT0]);
   p->fft1 = (double2*)(p->ws + L.off[B_FFT1]);
+  p->giv = ptr(B_GIV);
   p->t = 0.0;
 
   auto fail = [&](int code) {
@@ -841,6 +835,62 @@ int pfnks_create_problem(const pfnks_grid* grid, const pfnks_model* model, const
     e = hipMemcpy((void*)p->T.perm, order.data(), sizeof(int) * order.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) return fail(device_error(e, "hipMemcpy colour order"));
   }
+  *out = p;
+  return PFNKS_OK;
+}
+
+void destroy_problem(pfnks_problem* p) {
+  if (!p) return;
+  for (auto& r : p->pending) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto ev : p->pool) (void)hipEventDestroy(ev);
+  for (auto ev : p->hev)
+    if (ev) (void)hipEventDestroy(ev);
+  if (p->hbuf) (void)hipHostFree(p->hbuf);
+  if (p->hhost) (void)hipHostFree(p->hhost);
+  delete p;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pfnks_workspace_bytes(const pfnks_grid* grid, const pfnks_model* model, const pfnks_solver* solver,
+                          size_t* bytes) {
+  if (!bytes) return PFNKS_EINVAL;
+  int st = validate(grid, model, solver);
+  if (st) return st;
+  const long long N = (long long)grid->n[0] * grid->n[1] * (grid->dim == 3 ? grid->n[2] : 1);
+  *bytes = make_layout(grid->dim, N, solver->gmres_restart, grid->n, solver->precision, ext_nodes(grid, solver),
+                       tiles_summed(grid, solver), tiles_packed(grid, solver)).total;
+  return PFNKS_OK;
+}
+
+int pfnks_create_problem(const pfnks_grid* grid, const pfnks_model* model, const pfnks_solver* solver,
+                         const double* c0, const double* eta0, void* d_workspace, size_t ws_bytes,
+                         void* hip_stream, pfnks_problem** out) {
+  if (!out || !c0 || !eta0 || !d_workspace) return PFNKS_EINVAL;
+  *out = nullptr;
+  int st = validate(grid, model, solver);
+  if (st) return st;
+  if (((uintptr_t)d_workspace & 255) != 0) return PFNKS_EINVAL;
+  const long long N = (long long)grid->n[0] * grid->n[1] * (grid->dim == 3 ? grid->n[2] : 1);
+  const Layout L = make_layout(grid->dim, N, solver->gmres_restart, grid->n, solver->precision, ext_nodes(grid, solver),
+                               tiles_summed(grid, solver), tiles_packed(grid, solver));
+  if (ws_bytes < L.total) return PFNKS_ENOSPACE;
+  st = check_domain_host(c0, eta0, N);
+  if (st) return st;
+
+  pfnks_problem* p = nullptr;
+  st = setup_problem(grid, model, solver, L, N, (char*)d_workspace, (hipStream_t)hip_stream, &p);
+  if (st) return st;
+  auto fail = [&](int code) {
+    destroy_problem(p);
+    return code;
+  };
+  hipError_t e = hipSuccess;
   // state: c, eta, u = 0
   e = hipMemcpy(p->Xn, c0, sizeof(double) * N, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->Xn + N, eta0, sizeof(double) * 3 * N, hipMemcpyHostToDevice);
@@ -1043,6 +1093,485 @@ int pfnks_batch_step(pfnks_problem* const* problems, int k, const double* dts, i
   return first;
 }
 
+// ---------------------------------------------------------------------------------------
+// lockstep problem groups
+// ---------------------------------------------------------------------------------------
+// A group is `count` problems of one grid, model and solver in one workspace: instance i's
+// workspace is instance 0's layout, i * stride bytes further on.  Every kernel launch covers
+// all instances still working in that phase (pf::Bat), so a Newton iteration costs one
+// launch per kernel kind however many instances there are, and the host synchronises once
+// per Arnoldi step, residual evaluation and cycle end for all of them together.  The
+// Hessenberg columns, Givens rotations and the cycle's triangular solve run on the device
+// (launch_arnoldi, launch_ysolve), so the host reads only each instance's status.
+}  // extern "C"
+
+namespace {
+
+// pinned host slots of one instance: the single problem's reduction slots, then the GMRES
+// cycle status (ended, |g_{j+1}|, columns, not finite)
+constexpr int kHostGiv = pf::kMaxRed;
+constexpr int kHostSlot = pf::kMaxRed + 8;
+
+unsigned all_mask(int count) { return count >= 32 ? 0xffffffffu : ((1u << count) - 1u); }
+
+}  // namespace
+
+struct pfnks_group {
+  pfnks_problem* p;  // instance 0: grid, model, solver, kernel constants, pointers into its workspace
+  int count;
+  long long stride;  // bytes between the instances' workspaces
+  double* hs;        // pinned host slots, kHostSlot per instance
+  std::vector<double> cbar0, t, dt;
+  long long launches, syncs;
+};
+
+namespace {
+
+// launch descriptor over the instances in mask: the per-instance scalar is the time step
+pf::Bat gbat(const pfnks_group* G, unsigned mask) {
+  pf::Bat b;
+  b.stride = G->stride;
+  b.hstride = (long long)sizeof(double) * kHostSlot;
+  b.count = G->count;
+  b.per = 1;
+  b.mask = mask;
+  for (int i = 0; i < G->count; ++i) {
+    b.s[i] = G->dt[i];
+    b.cb[i] = G->cbar0[i];
+  }
+  return b;
+}
+
+// the same with every instance's scalar v (the coefficient of axpby)
+pf::Bat gbat_s(const pfnks_group* G, unsigned mask, double v) {
+  pf::Bat b = gbat(G, mask);
+  for (int i = 0; i < G->count; ++i) b.s[i] = v;
+  return b;
+}
+
+inline bool has(unsigned mask, int i) { return (mask >> i) & 1u; }
+inline double* gslot(pfnks_group* G, int i) { return G->hs + (size_t)i * kHostSlot; }
+
+int gsync(pfnks_group* G) {
+  HIPCHK(hipStreamSynchronize(G->p->stream));
+  G->syncs += 1;
+  return PFNKS_OK;
+}
+
+void gcopy(pfnks_group* G, unsigned mask, const double* src, double* dst) {
+  pf::launch_axpby<double, double, double>(G->p->nvec, 1.0, src, 0.0, nullptr, dst, G->p->stream,
+                                           gbat_s(G, mask, 1.0));
+  G->launches += 1;
+}
+
+// F = F(X) for the instances in mask; their ||F|| and counts of nodes outside the log domain
+int gresidual(pfnks_group* G, unsigned mask, const double* X, double* F, double* nrm, double* bad) {
+  pfnks_problem* p = G->p;
+  const pf::Bat bt = gbat(G, mask);
+  pf::launch_residual(p->K, 0.0, X, p->Xn, p->G4, F, p->part, p->stream, bt);
+  pf::launch_finalize(p->part, 2, p->red, p->stream, G->hs, bt);
+  G->launches += 3;
+  int st = gsync(G);
+  if (st) return st;
+  for (int i = 0; i < G->count; ++i)
+    if (has(mask, i)) {
+      nrm[i] = std::sqrt(gslot(G, i)[0]);
+      bad[i] = gslot(G, i)[1];
+    }
+  return PFNKS_OK;
+}
+
+// GMRES of gmres() for the instances in act, in lockstep: every Arnoldi step is launched for
+// the instances whose cycle is still running (as far as the host knows: one step is launched
+// ahead, and the device leaves an instance whose cycle has ended untouched).  its: total
+// iterations; *bad: instances whose residual estimate became non-finite.
+template <typename T>
+int gmres_group(pfnks_group* G, unsigned act, const double* Bm, const double* fnorm, const double* tol, int* its,
+                unsigned* bad) {
+  pfnks_problem* p = G->p;
+  const long long n = p->nvec;
+  const int m = p->solver.gmres_restart, maxit = p->solver.gmres_maxit, ld = m + 2;
+  T* V = static_cast<T*>(p->V);
+  T* Z = static_cast<T*>(p->Zb);
+  const int B = G->count;
+  std::vector<double> beta(B, 0.0);
+  std::vector<int> total(B, 0), cols(B, 0);
+  *bad = 0;
+  pf::launch_fill_zero<double>(n, p->S, p->stream, gbat(G, act));
+  pf::launch_axpby<double, double, double>(n, -1.0, p->F, 0.0, nullptr, p->tmp, p->stream, gbat_s(G, act, -1.0));
+  G->launches += 2;
+  for (int i = 0; i < B; ++i)
+    if (has(act, i)) {
+      beta[i] = fnorm[i];
+      its[i] = 0;
+    }
+  auto launch_step = [&](int j, unsigned mask) {
+    const pf::Bat bt = gbat(G, mask);  // per-instance time step of the tile solve and J v
+    pc_apply<T>(p, 0.0, V + j * n, Z + j * n, bt);
+    jv<T>(p, 0.0, Bm, Z + j * n, p->w, bt);
+    pf::launch_multidot<T>(n, j + 1, V, n, p->w, p->part, p->stream, bt);
+    pf::launch_arnoldi(p->part, j, m, p->hdev + j * ld, p->giv, G->hs + kHostGiv, p->stream, bt);
+    (void)hipEventRecord(p->hev[j], p->stream);
+    pf::launch_update_dev<T>(n, j + 1, V, n, p->hdev + j * ld, p->w, V + (j + 1) * n, p->stream, bt);
+    G->launches += 3;
+  };
+  unsigned live = act;
+  while (true) {
+    for (int i = 0; i < B; ++i)
+      if (has(live, i) && beta[i] <= tol[i]) live &= ~(1u << i);
+    if (!live) break;
+    // v_0 = r / beta and the start of the cycle on the device: g = beta e_1, its tolerance
+    // and column limit
+    int lim_max = 0;
+    {
+      pf::Bat bv = gbat(G, live), bg = gbat(G, live);
+      for (int i = 0; i < B; ++i)
+        if (has(live, i)) {
+          const int lim = std::min(m, maxit - total[i]);
+          bv.s[i] = 1.0 / beta[i];
+          bg.s[i] = beta[i];
+          bg.s2[i] = tol[i];
+          bg.s3[i] = (double)lim;
+          lim_max = std::max(lim_max, lim);
+        }
+      pf::launch_axpby<double, double, T>(n, 0.0, p->tmp, 0.0, nullptr, V, p->stream, bv);
+      pf::launch_giv_init(p->giv, m, p->stream, bg);
+      G->launches += 2;
+    }
+    unsigned run = live;
+    launch_step(0, run);
+    int launched = 1;
+    for (int j = 0;; ++j) {
+      if (launched == j + 1 && j + 1 < lim_max) {
+        launch_step(j + 1, run);
+        ++launched;
+      }
+      HIPCHK(hipEventSynchronize(p->hev[j]));
+      G->syncs += 1;
+      for (int i = 0; i < B; ++i) {
+        if (!has(run, i)) continue;
+        const double* h = gslot(G, i) + kHostGiv;
+        if (h[0] != 0.0) {
+          run &= ~(1u << i);
+          cols[i] = (int)h[2];
+          if (h[3] != 0.0) *bad |= 1u << i;
+        }
+      }
+      if (!run) break;
+      if (j + 1 >= launched) {
+        // every cycle ends by its column limit, which no launched step exceeds
+        g_last_error = "GMRES cycle of a problem group did not end at its column limit";
+        return PFNKS_EDEVICE;
+      }
+    }
+    // S += Z y per instance, then the true residual r = -F - J S decides and restarts
+    const unsigned fin = live & ~*bad;
+    if (fin) {
+      int kmax = 1;
+      for (int i = 0; i < B; ++i)
+        if (has(fin, i)) kmax = std::max(kmax, cols[i]);
+      const pf::Bat bf = gbat(G, fin);
+      pf::launch_ysolve(p->giv, m, p->stream, bf);
+      pf::launch_lincomb_dev<T, double>(n, kmax, Z, n, p->giv, m, p->S, p->stream, bf);
+      jv<double>(p, 0.0, Bm, p->S, p->w, bf);
+      pf::launch_axpby<double, double, double>(n, -1.0, p->F, -1.0, p->w, p->tmp, p->stream, gbat_s(G, fin, -1.0));
+      pf::launch_multidot<double>(n, 0, p->tmp, 0, p->tmp, p->part, p->stream, bf);
+      pf::launch_finalize(p->part, 1, p->red, p->stream, G->hs, bf);
+      G->launches += 5;
+      int st = gsync(G);
+      if (st) return st;
+      for (int i = 0; i < B; ++i) {
+        if (!has(fin, i)) continue;
+        beta[i] = std::sqrt(gslot(G, i)[0]);
+        total[i] += cols[i];
+        its[i] = total[i];
+        if (beta[i] <= tol[i] || total[i] >= maxit) live &= ~(1u << i);
+      }
+    }
+    live &= ~*bad;
+  }
+  return PFNKS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pfnks_group_workspace_bytes(const pfnks_grid* grid, const pfnks_model* model, const pfnks_solver* solver,
+                                int count, size_t* bytes) {
+  if (!bytes || count < 1 || count > pf::kMaxBatch) return PFNKS_EINVAL;
+  size_t one = 0;
+  int st = pfnks_workspace_bytes(grid, model, solver, &one);
+  if (st) return st;
+  *bytes = one * (size_t)count;
+  return PFNKS_OK;
+}
+
+int pfnks_group_create(const pfnks_grid* grid, const pfnks_model* model, const pfnks_solver* solver, int count,
+                       const double* c0, const double* eta0, void* d_workspace, size_t ws_bytes, void* hip_stream,
+                       pfnks_group** out) {
+  if (!out || !c0 || !eta0 || !d_workspace || count < 1 || count > pf::kMaxBatch) return PFNKS_EINVAL;
+  *out = nullptr;
+  int st = validate(grid, model, solver);
+  if (st) return st;
+  if (((uintptr_t)d_workspace & 255) != 0) return PFNKS_EINVAL;
+  const long long N = (long long)grid->n[0] * grid->n[1] * (grid->dim == 3 ? grid->n[2] : 1);
+  const Layout L = make_layout(grid->dim, N, solver->gmres_restart, grid->n, solver->precision, ext_nodes(grid, solver),
+                               tiles_summed(grid, solver), tiles_packed(grid, solver));
+  if (ws_bytes / (size_t)count < L.total) return PFNKS_ENOSPACE;
+  for (int i = 0; i < count; ++i) {
+    st = check_domain_host(c0 + (size_t)i * N, eta0 + (size_t)i * 3 * N, N);
+    if (st) return st;
+  }
+  pfnks_problem* p = nullptr;
+  st = setup_problem(grid, model, solver, L, N, (char*)d_workspace, (hipStream_t)hip_stream, &p);
+  if (st) return st;
+  pfnks_group* G = new pfnks_group();
+  G->p = p;
+  G->count = count;
+  G->stride = (long long)L.total;
+  G->hs = nullptr;
+  G->cbar0.assign(count, 0.0);
+  G->t.assign(count, 0.0);
+  G->dt.assign(count, 0.0);
+  G->launches = G->syncs = 0;
+  auto fail = [&](int code) {
+    destroy_problem(p);
+    if (G->hs) (void)hipHostFree(G->hs);
+    delete G;
+    return code;
+  };
+  hipError_t e = hipHostMalloc((void**)&G->hs, sizeof(double) * kHostSlot * count, hipHostMallocDefault);
+  if (e != hipSuccess) return fail(device_error(e, "hipHostMalloc"));
+  // states: c, eta, u = 0
+  for (int i = 0; i < count && e == hipSuccess; ++i) {
+    double* Xn = pf::bat_at(p->Xn, i * G->stride);
+    e = hipMemcpy(Xn, c0 + (size_t)i * N, sizeof(double) * N, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(Xn + N, eta0 + (size_t)i * 3 * N, sizeof(double) * 3 * N, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(Xn + 4 * N, 0, sizeof(double) * grid->dim * N);
+  }
+  if (e != hipSuccess) return fail(device_error(e, "state upload"));
+  // cbar0 of every instance, then u0 from the discrete equilibrium at c0 (as pfnks_create_problem)
+  const pf::Bat ball = gbat(G, all_mask(count));
+  pf::launch_sum2(N, p->Xn, p->Xn, p->Xn, p->part, p->stream, ball);
+  pf::launch_finalize(p->part, 1, p->red, p->stream, G->hs, ball);
+  st = gsync(G);
+  if (st) return fail(st);
+  for (int i = 0; i < count; ++i) G->cbar0[i] = gslot(G, i)[0] / (double)N;
+  pf::launch_spectral_solve<double>(p->K, p->plan, nullptr, p->K.eps0 * p->K.Ctr, p->Xn, p->fft0, p->fft1,
+                                    p->Xn + 4 * N, p->stream, ball);
+  e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) return fail(device_error(e, "elastic init"));
+  *out = G;
+  return PFNKS_OK;
+}
+
+int pfnks_group_step(pfnks_group* G, const double* dts, pfnks_step_stats* stats, int* status) {
+  if (!G || !dts) return PFNKS_EINVAL;
+  const int B = G->count;
+  for (int i = 0; i < B; ++i)
+    if (!(dts[i] >= 0.0) || !std::isfinite(dts[i])) return PFNKS_EINVAL;
+  pfnks_problem* p = G->p;
+  // instances with dt = 0 sit this step out
+  unsigned all = 0;
+  for (int i = 0; i < B; ++i) {
+    G->dt[i] = dts[i];
+    if (dts[i] > 0.0) all |= 1u << i;
+  }
+  G->launches = 0;
+  G->syncs = 0;
+  const long long n = p->nvec, N = p->N;
+  const pfnks_solver& sv = p->solver;
+  const double sq = std::sqrt((double)n);
+  const double eps_a = sv.newton_atol_rms * sq, xi_a = sv.gmres_atol_rms * sq;
+  const bool mixed = sv.precision == PFNKS_MIXED;
+  std::vector<pfnks_step_stats> st(B);
+  for (int i = 0; i < B; ++i) st[i] = pfnks_step_stats{};
+  if (!all) {
+    for (int i = 0; i < B; ++i) {
+      if (stats) stats[i] = st[i];
+      if (status) status[i] = PFNKS_OK;
+    }
+    return PFNKS_OK;
+  }
+  std::vector<double> fn(B), r0(B), bad(B), ft(B), badt(B), lam(B, 1.0), tol(B), upd(B, 0.0), ds_prev((size_t)B * 8, 0.0);
+  std::vector<int> its(B, 0), newton(B, 0), gm(B, 0), backs(B, 0);
+  unsigned conv = 0, failed = 0;
+  // X_0 = X^n
+  gcopy(G, all, p->Xn, p->X);
+  int s = gresidual(G, all, p->X, p->F, fn.data(), bad.data());
+  if (s) return s;
+  for (int i = 0; i < B; ++i) {
+    if (!has(all, i)) continue;
+    st[i].res0 = r0[i] = fn[i];
+    if (fn[i] <= eps_a || fn[i] == 0.0) conv |= 1u << i;
+  }
+  for (int it = 0; it < sv.newton_maxit; ++it) {
+    const unsigned act = all & ~conv & ~failed;
+    if (!act) break;
+    // linearise; the preconditioner blocks as in pfnks_step (lagged unless pc_refresh)
+    const pf::Bat ba = gbat(G, act);
+    const bool build_pc = (it == 0) || sv.pc_refresh;
+    double* Bm = p->B;
+    if (build_pc && !mixed) {
+      pf::launch_linearise(p->K, p->X, p->Xn, (double*)p->Bpc, nullptr, p->stream, ba);
+      Bm = (double*)p->Bpc;
+    } else {
+      pf::launch_linearise(p->K, p->X, p->Xn, p->B, build_pc ? (float*)p->Bpc : nullptr, p->stream, ba);
+    }
+    G->launches += 1;
+    if (build_pc) pc_setup(p, 0.0, ba);
+    for (int i = 0; i < B; ++i)
+      if (has(act, i)) tol[i] = std::fmax(sv.gmres_rtol * fn[i], xi_a);
+    unsigned gbad = 0;
+    s = mixed ? gmres_group<float>(G, act, Bm, fn.data(), tol.data(), its.data(), &gbad)
+              : gmres_group<double>(G, act, Bm, fn.data(), tol.data(), its.data(), &gbad);
+    if (s) return s;
+    for (int i = 0; i < B; ++i)
+      if (has(act, i)) gm[i] += its[i];
+    failed |= gbad;
+    const unsigned lsm = act & ~gbad;
+    if (!lsm) continue;
+    // mass projection sums (device), then the backtracking line search of pfnks_step
+    double* msums = p->red + kRedMassSlot;
+    pf::launch_sum2(N, p->S, p->X, p->Xn, p->part, p->stream, gbat(G, lsm));
+    pf::launch_finalize(p->part, 2, msums, p->stream, nullptr, gbat(G, lsm));
+    G->launches += 2;
+    unsigned ls = lsm, accepted = 0;
+    for (int i = 0; i < B; ++i) lam[i] = 1.0;
+    for (int hv = 0; hv <= sv.ls_max_halvings && ls; ++hv) {
+      pf::Bat bl = gbat(G, ls);
+      for (int i = 0; i < B; ++i) bl.s[i] = lam[i];
+      pf::launch_trial(p->K, p->nf, p->X, p->S, 0.0, msums, p->Xt, p->part, hv == 0 ? p->part + pf::kRedBlocks : nullptr,
+                       p->stream, bl);
+      pf::launch_finalize(p->part, 1, p->red, p->stream, G->hs + 2, bl);
+      G->launches += 2;
+      if (hv == 0) {
+        pf::launch_finalize_max(p->part + pf::kRedBlocks, 2 * p->nf, p->red + kHostUpd, p->stream, G->hs + kHostUpd, bl);
+        G->launches += 1;
+      }
+      s = gresidual(G, ls, p->Xt, p->Ft, ft.data(), badt.data());
+      if (s) return s;
+      for (int i = 0; i < B; ++i) {
+        if (!has(ls, i)) continue;
+        const double trial_bad = gslot(G, i)[2];
+        if (trial_bad == 0.0 && badt[i] == 0.0 && std::isfinite(ft[i]) &&
+            ft[i] * ft[i] <= (1.0 - 2.0 * sv.ls_alpha * lam[i]) * fn[i] * fn[i]) {
+          accepted |= 1u << i;
+          ls &= ~(1u << i);
+        } else {
+          lam[i] *= 0.5;
+          ++backs[i];
+        }
+      }
+    }
+    failed |= lsm & ~accepted;
+    if (!accepted) continue;
+    gcopy(G, accepted, p->Xt, p->X);
+    gcopy(G, accepted, p->Ft, p->F);
+    for (int i = 0; i < B; ++i) {
+      if (!has(accepted, i)) continue;
+      fn[i] = ft[i];
+      ++newton[i];
+      // update test of pfnks_step, on this instance's maxima
+      const double* h = gslot(G, i);
+      double ds[8], xs[8], theta = 0.0;
+      for (int f = 0; f < p->nf; ++f) {
+        ds[f] = lam[i] * h[kHostUpd + 2 * f];
+        xs[f] = h[kHostUpd + 2 * f + 1];
+        const double prev = ds_prev[(size_t)i * 8 + f];
+        if (ds[f] > 0.0) theta = std::fmax(theta, prev > 0.0 ? ds[f] / prev : HUGE_VAL);
+      }
+      const double amp = (theta < 1.0) ? theta / (1.0 - theta) : HUGE_VAL;
+      bool small_update = true;
+      upd[i] = 0.0;
+      for (int f = 0; f < p->nf; ++f) {
+        if (ds[f] == 0.0) continue;
+        const double est = ds[f] * amp;
+        upd[i] = std::fmax(upd[i], xs[f] > 0.0 ? est / xs[f] : HUGE_VAL);
+        if (!(est <= sv.newton_stol * xs[f])) small_update = false;
+      }
+      for (int f = 0; f < p->nf; ++f) ds_prev[(size_t)i * 8 + f] = ds[f];
+      if (sv.newton_stol <= 0.0) small_update = true;
+      if (fn[i] <= eps_a || (fn[i] <= sv.newton_rtol * r0[i] && small_update)) conv |= 1u << i;
+    }
+  }
+  const unsigned ok = conv & ~failed;
+  for (int i = 0; i < B; ++i) {
+    if (!has(all, i)) {
+      st[i].status = PFNKS_OK;  // sat the step out
+      continue;
+    }
+    st[i].newton_its = newton[i];
+    st[i].gmres_its = gm[i];
+    st[i].ls_backtracks = backs[i];
+    st[i].res_final = fn[i];
+    st[i].update_rel = upd[i];
+    st[i].status = has(ok, i) ? PFNKS_OK : PFNKS_ENOCONV;
+  }
+  if (ok) {
+    // step close of the converged instances: gauge projection, ||X - X^n||, energy, mass
+    const pf::Bat bo = gbat(G, ok);
+    const int ncls = 1 << p->grid.dim;
+    pf::launch_class_sums(p->K, p->X + 4 * N, p->part, p->stream, bo);
+    pf::launch_finalize(p->part, p->grid.dim * ncls, p->red, p->stream, nullptr, bo);
+    pf::launch_class_shift(p->K, p->X + 4 * N, p->red, p->stream, bo);
+    pf::launch_dx2(4 * N, p->X, p->Xn, p->part, p->stream, bo);
+    pf::launch_finalize(p->part, 1, p->red, p->stream, G->hs + 4, bo);
+    pf::launch_energy(p->K, p->X, p->part, p->stream, bo);
+    pf::launch_finalize(p->part, 4, p->red, p->stream, G->hs, bo);
+    G->launches += 7;
+    gcopy(G, ok, p->X, p->Xn);
+  }
+  s = gsync(G);
+  if (s) return s;
+  const double hd = std::pow(p->grid.h, p->grid.dim);
+  for (int i = 0; i < B; ++i) {
+    if (!has(ok, i)) continue;
+    const double* h = gslot(G, i);
+    st[i].energy_parts[0] = h[0] * hd;
+    st[i].energy_parts[1] = h[1] * hd;
+    st[i].energy_parts[2] = h[2] * hd;
+    st[i].energy = st[i].energy_parts[0] + st[i].energy_parts[1] + st[i].energy_parts[2];
+    st[i].mass = h[3] * hd;
+    st[i].dx_rms = std::sqrt(h[4] / (4.0 * N));
+    G->t[i] += dts[i];
+  }
+  int first = PFNKS_OK;
+  for (int i = 0; i < B; ++i) {
+    if (stats) stats[i] = st[i];
+    if (status) status[i] = st[i].status;
+    if (first == PFNKS_OK && st[i].status != PFNKS_OK) first = st[i].status;
+  }
+  return first;
+}
+
+int pfnks_group_get_state(pfnks_group* G, int i, double* X, double* t) {
+  if (!G || !X || i < 0 || i >= G->count) return PFNKS_EINVAL;
+  pfnks_problem* p = G->p;
+  HIPCHK(hipMemcpyAsync(X, pf::bat_at(p->Xn, i * G->stride), sizeof(double) * p->nvec, hipMemcpyDeviceToHost,
+                        p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  if (t) *t = G->t[i];
+  return PFNKS_OK;
+}
+
+int pfnks_group_counters(pfnks_group* G, long long* launches, long long* syncs) {
+  if (!G) return PFNKS_EINVAL;
+  if (launches) *launches = G->launches;
+  if (syncs) *syncs = G->syncs;
+  return PFNKS_OK;
+}
+
+int pfnks_group_destroy(pfnks_group* G) {
+  if (!G) return PFNKS_EINVAL;
+  if (G->p->stream) (void)hipStreamSynchronize(G->p->stream);
+  destroy_problem(G->p);
+  if (G->hs) (void)hipHostFree(G->hs);
+  delete G;
+  return PFNKS_OK;
+}
+
 int pfnks_energy(pfnks_problem* p, double* total, double parts[3]) {
   if (!p || !total) return PFNKS_EINVAL;
   pfnks_step_stats st{};
@@ -1085,11 +1614,7 @@ int pfnks_destroy(pfnks_problem* p) {
   if (!p) return PFNKS_EINVAL;
   if (p->stream) (void)hipStreamSynchronize(p->stream);
   prof_resolve(p);
-  for (hipEvent_t e : p->pool) (void)hipEventDestroy(e);
-  for (hipEvent_t e : p->hev) (void)hipEventDestroy(e);
-  if (p->hbuf) (void)hipHostFree(p->hbuf);
-  if (p->hhost) (void)hipHostFree(p->hhost);
-  delete p;
+  destroy_problem(p);
   return PFNKS_OK;
 }
 

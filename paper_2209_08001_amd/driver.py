@@ -2,8 +2,9 @@
     dt_{n+1} = max(dt_min, dt_max / sqrt(1 + zeta |X'_d|^2)),
 with X'_d the RMS change of (c, eta) over the last step divided by its dt, dt_1 = dt_min, and
 the divergence retry (dt <- dt / sqrt(2), zeta <- 2 zeta, the doubled zeta kept).  A retry
-below dt_min / 2^6 gives up.  One problem (`adaptive_run`) or an ensemble stepped together
-through pfnks_batch_step (`adaptive_batch_run`, each instance with its own dt history).
+below dt_min / 2^6 gives up.  One problem (`adaptive_run`), an ensemble stepped together
+through pfnks_batch_step (`adaptive_batch_run`, each instance with its own dt history), or
+lockstep groups of one grid shape each (`adaptive_group_run`).
 """
 
 import math
@@ -86,4 +87,41 @@ def adaptive_batch_run(problems, nsteps, wl, threads=0):
                     again.append(i)
             todo = again
         lat.append(time.perf_counter() - t0)
+    return lat, stats
+
+
+def adaptive_group_run(groups, nsteps, wl):
+    """nsteps accepted steps of every instance of every lockstep group (pfnks.Group).  Each
+    group runs on a host thread of its own (and its own stream); in a round a group steps all
+    its instances together, then re-steps only those that must retry while the others sit out
+    (dt = 0).  Returns (per-round wall latencies, stats[group][instance][step])."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    clocks = [[_Clock(wl) for _ in range(g.count)] for g in groups]
+    stats = [[[] for _ in range(g.count)] for g in groups]
+
+    def one_round(gi):
+        g, cl = groups[gi], clocks[gi]
+        dts = [c.next_dt() for c in cl]
+        retries = [0] * g.count
+        todo = set(range(g.count))
+        while todo:
+            status, st = g.step([dts[i] if i in todo else 0.0 for i in range(g.count)])
+            for i in sorted(todo):
+                if status[i] == pfnks.PFNKS_OK:
+                    st[i]["dt"], st[i]["retries"] = dts[i], retries[i]
+                    stats[gi][i].append(st[i])
+                    cl[i].accepted(st[i], dts[i])
+                    todo.discard(i)
+                else:
+                    dts[i] = cl[i].failed(dts[i])
+                    retries[i] += 1
+
+    lat = []
+    with ThreadPoolExecutor(max_workers=max(1, len(groups))) as pool:
+        for _ in range(nsteps):
+            t0 = time.perf_counter()
+            for f in [pool.submit(one_round, gi) for gi in range(len(groups))]:
+                f.result()
+            lat.append(time.perf_counter() - t0)
     return lat, stats

@@ -36,7 +36,11 @@ EXPORTED = [
     "pfnks_get_state", "pfnks_set_state", "pfnks_destroy", "pfnks_strerror", "pfnks_last_error",
     "pfnks_debug_residual", "pfnks_debug_jv", "pfnks_debug_pc", "pfnks_debug_counters",
     "pfnks_debug_profile", "pfnks_debug_kernel_time", "pfnks_batch_step", "pfnks_residual_static",
+    "pfnks_group_workspace_bytes", "pfnks_group_create", "pfnks_group_step", "pfnks_group_get_state",
+    "pfnks_group_counters", "pfnks_group_destroy",
 ]
+
+MAX_GROUP = 32  # instances of one lockstep group
 
 KERNEL_KINDS = ["residual", "linearise", "jv", "ras", "spectral", "multidot", "update"]
 
@@ -122,6 +126,16 @@ def load():
                                      ctypes.POINTER(pfnks_step_stats), ctypes.POINTER(ctypes.c_int)]
     lib.pfnks_residual_static.argtypes = [ctypes.POINTER(pfnks_grid), ctypes.POINTER(pfnks_model), ctypes.c_double,
                                           ctypes.c_double, P, P, P, dp, dp, P]
+    lib.pfnks_group_workspace_bytes.argtypes = [ctypes.POINTER(pfnks_grid), ctypes.POINTER(pfnks_model),
+                                                ctypes.POINTER(pfnks_solver), ctypes.c_int,
+                                                ctypes.POINTER(ctypes.c_size_t)]
+    lib.pfnks_group_create.argtypes = [ctypes.POINTER(pfnks_grid), ctypes.POINTER(pfnks_model),
+                                       ctypes.POINTER(pfnks_solver), ctypes.c_int, dp, dp, P, ctypes.c_size_t, P,
+                                       ctypes.POINTER(P)]
+    lib.pfnks_group_step.argtypes = [P, dp, ctypes.POINTER(pfnks_step_stats), ctypes.POINTER(ctypes.c_int)]
+    lib.pfnks_group_get_state.argtypes = [P, ctypes.c_int, dp, dp]
+    lib.pfnks_group_counters.argtypes = [P, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong)]
+    lib.pfnks_group_destroy.argtypes = [P]
     for name in EXPORTED:
         if name not in ("pfnks_strerror", "pfnks_last_error"):
             getattr(lib, name).restype = ctypes.c_int
@@ -387,6 +401,79 @@ class Problem:
     def close(self):
         if getattr(self, "_h", None):
             load().pfnks_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Group:
+    """A lockstep group of problems of one grid shape (same names as the C ABI): every kernel of
+    a step is launched once for all instances still working in that phase."""
+
+    def __init__(self, n, h, model, solver, c0s, eta0s, device="cuda:0", stream=None):
+        import torch
+
+        lib = load()
+        self.n = tuple(n)
+        self.dim = len(n)
+        self.nf = 4 + self.dim
+        self.N = int(np.prod(n))
+        self.count = len(c0s)
+        if self.count != len(eta0s) or not 1 <= self.count <= MAX_GROUP:
+            raise ValueError(f"a group holds 1..{MAX_GROUP} instances with one c0 and eta0 each")
+        self._g = make_grid(n, h)
+        self._m = make_model(model)
+        self._s = make_solver(solver, self.dim)
+        nbytes = ctypes.c_size_t(0)
+        _check(lib.pfnks_group_workspace_bytes(ctypes.byref(self._g), ctypes.byref(self._m), ctypes.byref(self._s),
+                                               ctypes.c_int(self.count), ctypes.byref(nbytes)),
+               "pfnks_group_workspace_bytes")
+        self.workspace = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=device)
+        aligned = (self.workspace.data_ptr() + 255) & ~255
+        self._stream = stream if stream is not None else torch.cuda.current_stream(device)
+        c0 = np.ascontiguousarray(np.stack([np.asarray(c, dtype=np.float64).ravel() for c in c0s]))
+        eta0 = np.ascontiguousarray(np.stack([np.asarray(e, dtype=np.float64).ravel() for e in eta0s]))
+        if c0.shape[1] != self.N or eta0.shape[1] != 3 * self.N:
+            raise ValueError("c0 / eta0 sizes do not match the grid")
+        h_ = ctypes.c_void_p()
+        torch.cuda.synchronize(device)
+        _check(lib.pfnks_group_create(ctypes.byref(self._g), ctypes.byref(self._m), ctypes.byref(self._s),
+                                      ctypes.c_int(self.count), _dp(c0), _dp(eta0), ctypes.c_void_p(aligned),
+                                      ctypes.c_size_t(nbytes.value), ctypes.c_void_p(self._stream.cuda_stream),
+                                      ctypes.byref(h_)), "pfnks_group_create")
+        self._h = h_
+
+    def step(self, dts):
+        """One step of every instance; returns (statuses, stats dicts).  Raises only on errors
+        other than an instance's ENOCONV (which leaves that instance unchanged)."""
+        dts = np.ascontiguousarray(np.broadcast_to(np.asarray(dts, dtype=np.float64), (self.count,)))
+        st = (pfnks_step_stats * self.count)()
+        status = (ctypes.c_int * self.count)()
+        rc = load().pfnks_group_step(self._h, _dp(dts), st, status)
+        if rc not in (PFNKS_OK, PFNKS_ENOCONV):
+            _check(rc, "pfnks_group_step")
+        return list(status), [s.as_dict() for s in st]
+
+    def get_state(self, i):
+        X = np.empty((self.nf,) + tuple(reversed(self.n)))
+        t = ctypes.c_double()
+        _check(load().pfnks_group_get_state(self._h, ctypes.c_int(i), _dp(X), ctypes.byref(t)),
+               "pfnks_group_get_state")
+        return X, t.value
+
+    def counters(self):
+        a = ctypes.c_longlong()
+        b = ctypes.c_longlong()
+        _check(load().pfnks_group_counters(self._h, ctypes.byref(a), ctypes.byref(b)), "pfnks_group_counters")
+        return a.value, b.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().pfnks_group_destroy(self._h)
             self._h = None
 
     def __del__(self):

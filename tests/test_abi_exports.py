@@ -170,3 +170,50 @@ def test_residual_static_rejects_on_host():
     assert call((64, 64), dt=0.0) == pfnks.PFNKS_EINVAL
     assert call((64, 64), ptr=None) == pfnks.PFNKS_EINVAL
     assert call((34, 34)) == pfnks.PFNKS_EINVAL
+
+
+def test_group_rejects_on_host():
+    """The lockstep group checks its instance count (1..32), workspace size and every
+    instance's initial log domain before its first device call; its workspace is count copies
+    of the single-problem layout.  The workspace address below is never dereferenced."""
+    if not os.path.exists(LIB):
+        pytest.skip("libpfnks.so not built")
+    from paper_2209_08001_amd import pfnks
+    from paper_2209_08001_amd import workloads as W
+    import numpy as np
+
+    lib = pfnks.load()
+    n = (64, 64)
+    g = pfnks.make_grid(n, W.H)
+    m = pfnks.make_model(W.DEFAULT_MODEL)
+    s = pfnks.make_solver(W.DEFAULT_SOLVER, 2)
+    one = pfnks.workspace_bytes(n, W.H, W.DEFAULT_MODEL, W.DEFAULT_SOLVER)
+
+    def wsb(count):
+        out = ctypes.c_size_t(0)
+        st = lib.pfnks_group_workspace_bytes(ctypes.byref(g), ctypes.byref(m), ctypes.byref(s), count,
+                                             ctypes.byref(out))
+        return st, out.value
+
+    assert wsb(3) == (pfnks.PFNKS_OK, 3 * one)
+    assert wsb(32) == (pfnks.PFNKS_OK, 32 * one)
+    assert wsb(0)[0] == pfnks.PFNKS_EINVAL
+    assert wsb(33)[0] == pfnks.PFNKS_EINVAL
+    fields = [W.init_fields(n, s_) for s_ in (1, 2)]
+    c0 = np.ascontiguousarray(np.stack([f[0].ravel() for f in fields]))
+    e0 = np.ascontiguousarray(np.stack([f[1].ravel() for f in fields]))
+    fake = ctypes.c_void_p(1 << 30)
+
+    def create(c, e, count=2, nbytes=2 * one, ws=fake):
+        out = ctypes.c_void_p(12345)
+        st = lib.pfnks_group_create(ctypes.byref(g), ctypes.byref(m), ctypes.byref(s), count, pfnks._dp(c),
+                                    pfnks._dp(e), ws, ctypes.c_size_t(nbytes), None, ctypes.byref(out))
+        return st, out.value
+
+    assert create(c0, e0, count=0)[0] == pfnks.PFNKS_EINVAL
+    assert create(c0, e0, nbytes=2 * one - 1) == (pfnks.PFNKS_ENOSPACE, None)
+    assert create(c0, e0, ws=ctypes.c_void_p((1 << 30) + 8)) == (pfnks.PFNKS_EINVAL, None)
+    c = c0.copy()
+    c[1, 77] = 1.5  # the second instance leaves the log domain
+    assert create(c, e0) == (pfnks.PFNKS_EDOMAIN, None)
+    assert lib.pfnks_group_step(None, None, None, None) == pfnks.PFNKS_EINVAL
