@@ -250,9 +250,13 @@ def run_c1(dev):
     }
 
 
-def make_groups(W, pfnks, members, prec, dev):
+def make_groups(W, pfnks, members, prec, dev, tile=None):
     """Lockstep groups of an ensemble: the instances of each side together (at most
-    pfnks.MAX_GROUP per group), each group on a stream of its own."""
+    pfnks.MAX_GROUP per group), each group on a stream of its own.  tile (2D): the largest tile
+    sides, by default 32 x 16 (a group's launch holds several instances' tiles, and half-size
+    tiles let two workgroups share a compute unit: 6-7 % more instance steps/s than 32 x 32 over
+    10 steps of the 64-instance ensemble, in FP64 and mixed precision)."""
+    tile = tile or (32, 16)
     import torch
 
     by_side = {}
@@ -264,6 +268,8 @@ def make_groups(W, pfnks, members, prec, dev):
             part = ms[k:k + pfnks.MAX_GROUP]
             fields = [W.init_fields(n, m["seed"], cbar=m["cbar"]) for m in part]
             sv = _solver_for(W, pfnks, n, prec, pfnks.PC_RAS_SPECTRAL)
+            if len(n) == 2:
+                sv["tile"] = (W.tile_side(n[0], tile[0], sv["overlap"]), W.tile_side(n[1], tile[1], sv["overlap"]), 1)
             groups.append(pfnks.Group(n, W.H, W.DEFAULT_MODEL, sv, [f[0] for f in fields], [f[1] for f in fields],
                                       device=dev, stream=torch.cuda.Stream(device=dev)))
     return groups
@@ -308,57 +314,6 @@ def run_c4_lockstep(dev, steps=3, prec="mixed"):
     }
     for g in groups:
         g.close()
-    return out
-
-
-def run_c4(dev, steps=3, threads=16):
-    """Ensemble: the 64 instances of ens2d_64 (sides from {128, 192, 256, 384, 512}, mean
-    compositions in [0.13, 0.21]) in mixed precision, stepped together (pfnks_batch_step, one
-    stream per instance) over the first steps of their adaptive trajectories: instance steps/s
-    and node steps/s."""
-    import torch
-
-    from paper_2209_08001_amd import pfnks
-    from paper_2209_08001_amd import workloads as W
-    from paper_2209_08001_amd.driver import adaptive_batch_run
-
-    wl = W.WORKLOADS["ens2d_64"]
-    members = W.ensemble_members(wl)
-
-    def make(ms):
-        out = []
-        for m in ms:
-            c0, e0 = W.init_fields(m["n"], m["seed"], cbar=m["cbar"])
-            sv = _solver_for(W, pfnks, m["n"], "mixed", pfnks.PC_RAS_SPECTRAL)
-            out.append(pfnks.Problem(m["n"], W.H, W.DEFAULT_MODEL, sv, c0, e0, device=dev,
-                                     stream=torch.cuda.Stream(device=dev)))
-        return out
-
-    scratch = make(members[:8])
-    adaptive_batch_run(scratch, 1, wl, threads)
-    for p in scratch:
-        p.close()
-    del scratch
-    probs = make(members)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    lat, stats = adaptive_batch_run(probs, steps, wl, threads)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    nodes = sum(p.N for p in probs)
-    newton = sum(s["newton_its"] for ss in stats for s in ss)
-    out = {
-        "workload": "ens2d_64", "instances": len(probs), "total_nodes": nodes,
-        "sides": sorted({p.n[0] for p in probs}), "precision": "mixed", "steps": steps,
-        "host_threads": threads,
-        "instance_steps_per_s": len(probs) * steps / elapsed,
-        "node_steps_per_s": nodes * steps / elapsed,
-        "p50_round_ms": 1e3 * percentile(lat, 50), "p99_round_ms": 1e3 * percentile(lat, 99),
-        "newton_per_step": newton / (len(probs) * steps),
-        "gmres_per_newton": sum(s["gmres_its"] for ss in stats for s in ss) / max(newton, 1),
-    }
-    for p in probs:
-        p.close()
     return out
 
 
@@ -440,15 +395,16 @@ def run_ensemble(args, wl):
     from paper_2209_08001_amd.driver import adaptive_batch_run, adaptive_group_run
 
     members = W.ensemble_members(wl)
+    tile = tuple(int(v) for v in args.tile.split(",")) if args.tile else None
     if args.ensemble_mode == "lockstep":
         dev = "cuda:0"
         if args.warmup > 0:
-            scratch = make_groups(W, pfnks, members[:8], args.precision, dev)
+            scratch = make_groups(W, pfnks, members[:8], args.precision, dev, tile)
             adaptive_group_run(scratch, args.warmup, wl)
             for g in scratch:
                 g.close()
             del scratch
-        groups = make_groups(W, pfnks, members, args.precision, dev)
+        groups = make_groups(W, pfnks, members, args.precision, dev, tile)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         lat, gstats = adaptive_group_run(groups, args.steps, wl)
@@ -458,7 +414,8 @@ def run_ensemble(args, wl):
         k = sum(g.count for g in groups)
         nodes = sum(g.N * g.count for g in groups)
         sides = sorted({g.n[0] for g in groups})
-        mode_cfg = {"mode": "lockstep groups", "groups": [g.count for g in groups]}
+        mode_cfg = {"mode": "lockstep groups", "groups": [g.count for g in groups],
+                    "tiles": sorted({tuple(g._s.tile[:2]) for g in groups})}
         for g in groups:
             g.close()
     else:
@@ -764,7 +721,7 @@ def main():
     if default_line and not args.no_c3:
         out["c3"] = run_c3(dev, steps=args.c3_steps)
     if default_line and not args.no_c4:
-        out["c4"] = run_c4(dev)
+        out["c4"] = run_c4_lockstep(dev)
         # the mixed-precision batched form against this line's plain FP64 form, per node step
         out["c4"]["vs_fp64_single_node_steps"] = out["c4"]["node_steps_per_s"] / (out["value"] * float(math.prod(n)))
     if default_line and not args.no_c1:

@@ -74,6 +74,8 @@ CASES = [
     ((32, 32), "mixed", (5, 9, 13), [(0.01, 0.05, 0.002), (0.05, 0.01, 0.002)]),
     ((24, 40), "fp64", (21, 22), [(0.01, 0.04), (0.02, 0.01)]),
     ((8, 8, 8), "mixed", (7, 17), [(0.01, 0.03), (0.03, 0.01)]),
+    # 3D with sides that are not powers of two: the general Fourier path (mixed-radix lines)
+    ((6, 10, 14), "fp64", (3, 4), [(0.01, 0.02)]),
 ]
 
 
@@ -163,4 +165,36 @@ def test_group_failures_match_single():
             assert np.array_equal(Xg[:4], X0), i
         p.close()
     _note(f"  statuses {status}")
+    g.close()
+
+
+@pytest.mark.parametrize("pc", ["ras", "as", "rras"])
+def test_group_schwarz_variants(pc):
+    """The Schwarz variants of Section 4 that solve every field in the tiles (left-RAS,
+    classical AS and right-RAS, the last two through the per-node gather of the tiles'
+    extended solutions) in a group: every member within 1e-9 of the instance stepped alone and
+    within 1e-8 of the oracle's root."""
+    from paper_2209_08001_amd import pfnks
+
+    _cuda()
+    n = (32, 32)
+    seeds = (51, 52)
+    dts = (0.01, 0.03)
+    code = {"ras": pfnks.PC_RAS, "as": pfnks.PC_AS, "rras": pfnks.PC_RRAS}[pc]
+    sv = _solver(n, "fp64", pc=code)
+    fields = [W.init_fields(n, s) for s in seeds]
+    g = pfnks.Group(n, W.H, W.DEFAULT_MODEL, sv, [f[0] for f in fields], [f[1] for f in fields])
+    status, st = g.step(dts)
+    assert all(x == pfnks.PFNKS_OK for x in status), status
+    for i, (c, e) in enumerate(fields):
+        p = pfnks.Problem(n, W.H, W.DEFAULT_MODEL, sv, c, e)
+        p.step(dts[i])
+        Xg, _ = g.get_state(i)
+        Xa, _ = p.get_state()
+        d = max(_relmax(Xg[f], Xa[f]) for f in range(Xg.shape[0]))
+        ref = _oracle_traj(n, seeds[i], (dts[i],))[-1]
+        err = max(_relmax(Xg[f], ref[f]) for f in range(Xg.shape[0]))
+        _note(f"  {pc} instance {i}: vs alone {d:.2e}, vs oracle {err:.2e}")
+        assert d <= 1e-9 and err <= 1e-8, (i, d, err)
+        p.close()
     g.close()
