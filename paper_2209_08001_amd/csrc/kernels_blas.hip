@@ -439,6 +439,13 @@ __global__ __launch_bounds__(kRedBlocks) void k_arnoldi(const double* __restrict
   const int nvals = j + 2;
   __shared__ double wl[kRedBlocks / 64][MAXV];
   __shared__ double col[MAXV];
+  // the earlier rotations, staged in LDS by all threads (thread 0's rotation loop then waits on
+  // LDS, not on a global load behind each of its own stores)
+  __shared__ double rc[kMaxRed], rs[kMaxRed];
+  for (int i = threadIdx.x; i < j; i += kRedBlocks) {
+    rc[i] = giv[L.cs + i];
+    rs[i] = giv[L.sn + i];
+  }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double acc[MAXV];
 #pragma unroll
@@ -460,35 +467,33 @@ __global__ __launch_bounds__(kRedBlocks) void k_arnoldi(const double* __restrict
   }
   __syncthreads();
   if (threadIdx.x != 0) return;
-  double* H = giv + L.H;
-  double* cs = giv + L.cs;
-  double* sn = giv + L.sn;
   double* g = giv + L.g;
-  double* h = H + (long long)j * (m + 1);
+  double* h = giv + L.H + (long long)j * (m + 1);
   double hh = 0.0;
-  for (int i = 0; i <= j; ++i) {
-    h[i] = col[i];
-    hh += col[i] * col[i];
-  }
+  for (int i = 0; i <= j; ++i) hh += col[i] * col[i];
   const double ww = col[j + 1];
   const double nrm2 = ww - hh;
   const bool cancel = !(nrm2 > 1e-2 * ww);
   const double hnext = sqrt(fmax(nrm2, 0.0));
-  h[j + 1] = hnext;
+  // the earlier rotations applied to column j, the rotated entry carried in a register
+  double a = col[0];
   for (int i = 0; i < j; ++i) {
-    const double a = h[i], b = h[i + 1];
-    h[i] = cs[i] * a + sn[i] * b;
-    h[i + 1] = -sn[i] * a + cs[i] * b;
+    const double b = col[i + 1];
+    h[i] = rc[i] * a + rs[i] * b;
+    a = -rs[i] * a + rc[i] * b;
   }
-  const double a = h[j], b = h[j + 1];
+  const double b = hnext;
   const double r = hypot(a, b);
-  cs[j] = (r == 0.0) ? 1.0 : a / r;
-  sn[j] = (r == 0.0) ? 0.0 : b / r;
+  const double c_ = (r == 0.0) ? 1.0 : a / r;
+  const double s_ = (r == 0.0) ? 0.0 : b / r;
+  giv[L.cs + j] = c_;
+  giv[L.sn + j] = s_;
   h[j] = r;
   h[j + 1] = 0.0;
-  g[j + 1] = -sn[j] * g[j];
-  g[j] = cs[j] * g[j];
-  const double resid = fabs(g[j + 1]);
+  const double gj = g[j];
+  g[j + 1] = -s_ * gj;
+  g[j] = c_ * gj;
+  const double resid = fabs(-s_ * gj);
   const bool nonfinite = !isfinite(resid);
   const bool ended = nonfinite || resid <= st[kGivTol] || cancel || hnext == 0.0 || (double)(j + 1) >= st[kGivLim];
   st[kGivEnded] = ended ? 1.0 : 0.0;
@@ -522,23 +527,33 @@ __global__ __launch_bounds__(64) void k_giv_init(double* __restrict__ giv, int m
 
 // end of a cycle, per instance: y = H^{-1} g over the cycle's k columns (upper triangular),
 // zero beyond, and y[m] = k for the combination S += Z y
-__global__ __launch_bounds__(64) void k_ysolve(double* __restrict__ giv, int m, Bat bt) {
+// (H, g and y staged in LDS by the workgroup; thread 0 runs the back substitution there)
+constexpr int kMaxRestart = 64;
+__global__ __launch_bounds__(256) void k_ysolve(double* __restrict__ giv, int m, Bat bt) {
   const int bi = bat_inst(bt);
   if (bat_skip(bt, bi)) return;
-  if (threadIdx.x != 0) return;
   giv = bat_at(giv, bi * bt.stride);
   const GivLayout L = giv_layout(m);
-  const double* H = giv + L.H;
-  const double* g = giv + L.g;
-  double* y = giv + L.y;
+  __shared__ double Hs[kMaxRestart * kMaxRestart], gs[kMaxRestart], ys[kMaxRestart];
   const int k = (int)giv[L.st + kGivCols];
-  for (int i = k - 1; i >= 0; --i) {
-    double s_ = g[i];
-    for (int c = i + 1; c < k; ++c) s_ -= H[(long long)c * (m + 1) + i] * y[c];
-    y[i] = s_ / H[(long long)i * (m + 1) + i];
+  // the leading k x k block of H (column c at c (m + 1)), row-major in LDS, and g
+  for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
+    const int c = e / k, i = e - c * k;
+    Hs[i * kMaxRestart + c] = giv[L.H + (long long)c * (m + 1) + i];
   }
-  for (int i = k; i < m; ++i) y[i] = 0.0;
-  y[m] = (double)k;
+  for (int i = threadIdx.x; i < k; i += blockDim.x) gs[i] = giv[L.g + i];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = k - 1; i >= 0; --i) {
+      double s_ = gs[i];
+      for (int c = i + 1; c < k; ++c) s_ -= Hs[i * kMaxRestart + c] * ys[c];
+      ys[i] = s_ / Hs[i * kMaxRestart + i];
+    }
+  }
+  __syncthreads();
+  double* y = giv + L.y;
+  for (int i = threadIdx.x; i < m; i += blockDim.x) y[i] = (i < k) ? ys[i] : 0.0;
+  if (threadIdx.x == 0) y[m] = (double)k;
 }
 
 // out += sum_{v < k} y_v V_v with each instance's own y and column count k (from k_ysolve);
@@ -712,7 +727,7 @@ void launch_giv_init(double* giv, int m, hipStream_t s, const Bat& bt) {
 }
 
 void launch_ysolve(double* giv, int m, hipStream_t s, const Bat& bt) {
-  hipLaunchKernelGGL(k_ysolve, bg(1, bt), dim3(64), 0, s, giv, m, bt);
+  hipLaunchKernelGGL(k_ysolve, bg(1, bt), dim3(256), 0, s, giv, m, bt);
 }
 
 template <typename T, typename To>
