@@ -309,36 +309,13 @@ __global__ __launch_bounds__(TH, (ras_waves_per_eu<TH>())) void k_ras(Consts K, 
     // (the sums start from their first term: x + 0 is not folded away in floating point)
     R sumM, dM[3] = {R(0), R(0), R(0)};
     R divm;
-    // every LDS operand of the update is read here, before any arithmetic: the reads are
-    // independent, so they can all be in flight at once (one LDS round trip per phase instead of
-    // one per group of reads the scheduler would otherwise interleave with the arithmetic)
     const R g0 = gg[di], dg0 = dg[di];
-    R ggp[DIM], ggm[DIM], nbv[3][2 * DIM], bcv[4];
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
       dgp[d] = dg[di + sdir_d[d]];
       dgm[d] = dg[di - sdir_d[d]];
-      ggp[d] = gg[di + sdir_d[d]];
-      ggm[d] = gg[di - sdir_d[d]];
-    }
-#pragma unroll
-    for (int e = 0; e < 3; ++e) {
-      const int ze = (1 + e - ZP0) * zsz + zi;
-#pragma unroll
-      for (int d = 0; d < DIM; ++d) {
-        nbv[e][2 * d] = zs[ze + sdir_z[d]];
-        nbv[e][2 * d + 1] = zs[ze - sdir_z[d]];
-      }
-    }
-#pragma unroll
-    for (int f = 0; f < 4; ++f) bcv[f] = bc[f * ne + q];
-    // (kept together where the registers hold them: double with up to three node slots in 2D or
-    // two in 3D, float throughout; beyond that the barrier would make the compiler spill)
-    if constexpr (!WU && (sizeof(R) == 4 || NPT <= 2 || (DIM == 2 && NPT == 3))) __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-      const R Mp = hk * (g0 + ggp[d]);
-      const R Mm = hk * (g0 + ggm[d]);
+      const R Mp = hk * (g0 + gg[di + sdir_d[d]]);
+      const R Mm = hk * (g0 + gg[di - sdir_d[d]]);
       const R dv = Mp * (dgp[d] - dg0) - Mm * (dg0 - dgm[d]);
       divm = (d == 0) ? dv : divm + dv;
       sumM = (d == 0) ? Mp + Mm : sumM + (Mp + Mm);
@@ -349,9 +326,10 @@ __global__ __launch_bounds__(TH, (ras_waves_per_eu<TH>())) void k_ras(Consts K, 
     R rh[3];
 #pragma unroll
     for (int e = 0; e < 3; ++e) {
-      R nb = nbv[e][0] + nbv[e][1];
+      const int ze = (1 + e - ZP0) * zsz + zi;
+      R nb = zs[ze + 1] + zs[ze - 1];
 #pragma unroll
-      for (int d = 1; d < DIM; ++d) nb += nbv[e][2 * d] + nbv[e][2 * d + 1];
+      for (int d = 1; d < DIM; ++d) nb += zs[ze + sdir_z[d]] + zs[ze - sdir_z[d]];
       rh[e] = rv[1 + e] + cge * nb;
     }
     R y[3];
@@ -389,6 +367,9 @@ __global__ __launch_bounds__(TH, (ras_waves_per_eu<TH>())) void k_ras(Consts K, 
       }
     }
     const R sc = sumM * ih2;
+    R bcv[4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) bcv[f] = bc[f * ne + q];
     R t = bcv[1] * (y[0] - zv[1] - w[0] * zv[0]);
 #pragma unroll
     for (int e = 1; e < 3; ++e) t += bcv[1 + e] * (y[e] - zv[1 + e] - w[e] * zv[0]);
