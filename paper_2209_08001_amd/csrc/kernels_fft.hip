@@ -508,57 +508,71 @@ struct MrPlan {
   int r[16];   // radix of each stage
 };
 
+// One stage of radix R over the lpb lines of the block (src -> dst).  The R-th roots of unity
+// W_R^u of the butterflies' DFTs are loaded into registers once per stage; the stage twiddles
+// W_{pR}^{t k} come from the LDS table per butterfly.
 template <int R>
-__device__ inline void mr_butterfly(const double2* src, double2* dst, const double2* tws, int n, int m,
-                                    int p, int j, int inverse) {
-  const int k = j % p;
+__device__ inline void mr_stage(const double2* __restrict__ src, double2* __restrict__ dst,
+                                const double2* __restrict__ tws, int n, int p, int lpb, int inverse) {
+  const int m = n / R;
   const int tstep = n / (p * R);  // W_{pR}^{t k} = W_n^{t k n/(pR)}
-  double2 x[R];
+  double2 wr[R];                  // W_R^u = W_n^{u n/R}
 #pragma unroll
-  for (int t = 0; t < R; ++t) {
-    double2 v = src[j + t * m];
-    if (t > 0 && k > 0) {
-      double2 w = tws[t * k * tstep];
-      if (inverse) w.y = -w.y;
-      v = cmul(v, w);
-    }
-    x[t] = v;
+  for (int u = 0; u < R; ++u) {
+    double2 w = tws[u * m];
+    if (inverse) w.y = -w.y;
+    wr[u] = w;
   }
-  const int base = (j - k) * R + k;
-  if (R == 2) {
-    dst[base] = make_double2(x[0].x + x[1].x, x[0].y + x[1].y);
-    dst[base + p] = make_double2(x[0].x - x[1].x, x[0].y - x[1].y);
-  } else if (R == 4) {
-    // W_4 = -i (forward) or +i (inverse)
-    const double2 a = make_double2(x[0].x + x[2].x, x[0].y + x[2].y);
-    const double2 b = make_double2(x[0].x - x[2].x, x[0].y - x[2].y);
-    const double2 c = make_double2(x[1].x + x[3].x, x[1].y + x[3].y);
-    const double2 d = make_double2(x[1].x - x[3].x, x[1].y - x[3].y);
-    // -i d (forward), +i d (inverse)
-    const double2 e = inverse ? make_double2(-d.y, d.x) : make_double2(d.y, -d.x);
-    dst[base] = make_double2(a.x + c.x, a.y + c.y);
-    dst[base + p] = make_double2(b.x + e.x, b.y + e.y);
-    dst[base + 2 * p] = make_double2(a.x - c.x, a.y - c.y);
-    dst[base + 3 * p] = make_double2(b.x - e.x, b.y - e.y);
-  } else {
-    const int ustep = n / R;  // W_R^{(t u) mod R} = W_n^{((t u) mod R) n/R}
+  for (int b = threadIdx.x; b < lpb * m; b += kFftThreads) {
+    const int l = b / m, j = b - l * m;
+    const int k = j % p;
+    const double2* sl = src + l * n;
+    double2* dl = dst + l * n;
+    double2 x[R];
 #pragma unroll
-    for (int u = 0; u < R; ++u) {
-      double2 y = x[0];
-#pragma unroll
-      for (int t = 1; t < R; ++t) {
-        double2 w = tws[((t * u) % R) * ustep];
+    for (int t = 0; t < R; ++t) {
+      double2 v = sl[j + t * m];
+      if (t > 0 && k > 0) {
+        double2 w = tws[t * k * tstep];
         if (inverse) w.y = -w.y;
-        const double2 z = cmul(x[t], w);
-        y.x += z.x;
-        y.y += z.y;
+        v = cmul(v, w);
       }
-      dst[base + u * p] = y;
+      x[t] = v;
+    }
+    const int base = (j - k) * R + k;
+    if constexpr (R == 2) {
+      dl[base] = make_double2(x[0].x + x[1].x, x[0].y + x[1].y);
+      dl[base + p] = make_double2(x[0].x - x[1].x, x[0].y - x[1].y);
+    } else if constexpr (R == 4) {
+      // W_4 = -i (forward) or +i (inverse)
+      const double2 a = make_double2(x[0].x + x[2].x, x[0].y + x[2].y);
+      const double2 c0 = make_double2(x[0].x - x[2].x, x[0].y - x[2].y);
+      const double2 c = make_double2(x[1].x + x[3].x, x[1].y + x[3].y);
+      const double2 d = make_double2(x[1].x - x[3].x, x[1].y - x[3].y);
+      // -i d (forward), +i d (inverse)
+      const double2 e = inverse ? make_double2(-d.y, d.x) : make_double2(d.y, -d.x);
+      dl[base] = make_double2(a.x + c.x, a.y + c.y);
+      dl[base + p] = make_double2(c0.x + e.x, c0.y + e.y);
+      dl[base + 2 * p] = make_double2(a.x - c.x, a.y - c.y);
+      dl[base + 3 * p] = make_double2(c0.x - e.x, c0.y - e.y);
+    } else {
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        double2 y = x[0];
+#pragma unroll
+        for (int t = 1; t < R; ++t) {
+          const double2 z = cmul(x[t], wr[(t * u) % R]);
+          y.x += z.x;
+          y.y += z.y;
+        }
+        dl[base + u * p] = y;
+      }
     }
   }
 }
 
-// Lines addressed as in k_fft_lines; LDS: two buffers of lpb n points and the n twiddles.
+// Lines addressed as in k_fft_lines; LDS: two buffers of lpb n points, the n twiddles, and the
+// offset of each of the block's lines (formed once per line, not per point).
 __global__ __launch_bounds__(kFftThreads) void k_fft_lines_mr(double2* __restrict__ data, int n, MrPlan pl,
                                                               long long pstride, long long la, long long lb,
                                                               long long lc, long long nlines, int lpb,
@@ -572,8 +586,14 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_lines_mr(double2* __restric
   double2* b0 = sm;
   double2* b1 = sm + lpb * n;
   double2* tws = sm + 2 * lpb * n;
+  long long* loff = reinterpret_cast<long long*>(tws + n);  // -1: past the last line
   for (int e = threadIdx.x; e < n; e += kFftThreads) tws[e] = tw[e];
   const long long line0 = (long long)blockIdx.x * lpb;
+  for (int l = threadIdx.x; l < lpb; l += kFftThreads) {
+    const long long line = line0 + l;
+    loff[l] = (line < nlines) ? (line % la) * lb + (line / la) * lc : -1;
+  }
+  __syncthreads();
   const int total = lpb * n;
   for (int e = threadIdx.x; e < total; e += kFftThreads) {
     int l, q;
@@ -584,27 +604,22 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_lines_mr(double2* __restric
       l = e % lpb;
       q = e / lpb;
     }
-    const long long line = line0 + l;
-    b0[l * n + q] = (line < nlines) ? data[(line % la) * lb + (line / la) * lc + q * pstride] : make_double2(0.0, 0.0);
+    const long long off = loff[l];
+    b0[l * n + q] = (off >= 0) ? data[off + q * pstride] : make_double2(0.0, 0.0);
   }
   __syncthreads();
   double2 *src = b0, *dst = b1;
   int p = 1;
   for (int st = 0; st < pl.nst; ++st) {
-    const int R = pl.r[st], m = n / R;
-    for (int b = threadIdx.x; b < lpb * m; b += kFftThreads) {
-      const int l = b / m, j = b - l * m;
-      const double2* sl = src + l * n;
-      double2* dl = dst + l * n;
-      switch (R) {
-        case 2: mr_butterfly<2>(sl, dl, tws, n, m, p, j, inverse); break;
-        case 3: mr_butterfly<3>(sl, dl, tws, n, m, p, j, inverse); break;
-        case 4: mr_butterfly<4>(sl, dl, tws, n, m, p, j, inverse); break;
-        case 5: mr_butterfly<5>(sl, dl, tws, n, m, p, j, inverse); break;
-        case 7: mr_butterfly<7>(sl, dl, tws, n, m, p, j, inverse); break;
-        case 11: mr_butterfly<11>(sl, dl, tws, n, m, p, j, inverse); break;
-        default: mr_butterfly<13>(sl, dl, tws, n, m, p, j, inverse); break;
-      }
+    const int R = pl.r[st];
+    switch (R) {
+      case 2: mr_stage<2>(src, dst, tws, n, p, lpb, inverse); break;
+      case 3: mr_stage<3>(src, dst, tws, n, p, lpb, inverse); break;
+      case 4: mr_stage<4>(src, dst, tws, n, p, lpb, inverse); break;
+      case 5: mr_stage<5>(src, dst, tws, n, p, lpb, inverse); break;
+      case 7: mr_stage<7>(src, dst, tws, n, p, lpb, inverse); break;
+      case 11: mr_stage<11>(src, dst, tws, n, p, lpb, inverse); break;
+      default: mr_stage<13>(src, dst, tws, n, p, lpb, inverse); break;
     }
     __syncthreads();
     double2* t = src;
@@ -621,8 +636,8 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_lines_mr(double2* __restric
       l = e % lpb;
       q = e / lpb;
     }
-    const long long line = line0 + l;
-    if (line < nlines) data[(line % la) * lb + (line / la) * lc + q * pstride] = src[l * n + q];
+    const long long off = loff[l];
+    if (off >= 0) data[off + q * pstride] = src[l * n + q];
   }
 }
 
@@ -791,8 +806,10 @@ void launch_lines(double2* data, int n, int logn, long long pstride, long long l
                   long long nlines, int lpb, const double2* tw, int inverse, int contiguous, hipStream_t s,
                   const Bat& bt) {
   const size_t lds = sizeof(double2) * ((size_t)lp_size(lpb * n) + n / 2);
-  if (lds > 64 * 1024)
-    (void)hipFuncSetAttribute((const void*)k_fft_lines, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (lds > 64 * 1024) {
+    static const bool lds_ok = allow_max_lds((const void*)k_fft_lines);
+    (void)lds_ok;
+  }
   const long long blocks = (nlines + lpb - 1) / lpb;
   hipLaunchKernelGGL(k_fft_lines, bat_grid(dim3((unsigned)blocks), bt), dim3(kFftThreads), lds, s, data, n, logn,
                      pstride, la, lb, lc, nlines, lpb, tw, inverse, contiguous, bt);
@@ -829,9 +846,14 @@ void fft_dir_mr(const Consts& K, const FftPlan& P, double2* data, int dir, int i
     nlines = nx * ny; la = nx * ny; lb = 1; lc = 0; pstride = nx * ny;
   }
   if (dir != 0 && lpb > la) lpb = (int)la;
-  const size_t lds = sizeof(double2) * ((size_t)2 * lpb * n + n);
-  if (lds > 64 * 1024)
-    (void)hipFuncSetAttribute((const void*)k_fft_lines_mr, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  // small grids: fewer lines per workgroup, so that the lines spread over more compute units
+  // (at least 512 workgroups where the line count allows)
+  while (lpb > 1 && (nlines + lpb - 1) / lpb < 512) lpb = (lpb + 1) / 2;
+  const size_t lds = sizeof(double2) * ((size_t)2 * lpb * n + n) + sizeof(long long) * (size_t)lpb;
+  if (lds > 64 * 1024) {
+    static const bool lds_ok = allow_max_lds((const void*)k_fft_lines_mr);
+    (void)lds_ok;
+  }
   const long long blocks = (nlines + lpb - 1) / lpb;
   hipLaunchKernelGGL(k_fft_lines_mr, bat_grid(dim3((unsigned)blocks), bt), dim3(kFftThreads), lds, s, data, n, pl,
                      pstride, la, lb, lc, nlines, lpb, P.tw[dir], inverse, dir == 0 ? 1 : 0, bt);
@@ -903,8 +925,10 @@ void launch_spectral_solve(const Consts& K, const FftPlan& P, const T* r, double
     while (K.ny % nl) nl >>= 1;
     const size_t lrow = sizeof(double2) * (lp_size(nl * K.nx) + K.nx / 2);
     const size_t lcol = sizeof(double2) * (lp_size(4 * K.ny) + K.ny / 2);
-    if (lcol > 64 * 1024)  // ny = 1024: 80 KiB
-      (void)hipFuncSetAttribute((const void*)k_fft2_cols_solve, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lcol);
+    if (lcol > 64 * 1024) {  // ny = 1024: 80 KiB
+      static const bool lds_ok = allow_max_lds((const void*)k_fft2_cols_solve);
+      (void)lds_ok;
+    }
     hipLaunchKernelGGL(k_fft2_rows_fwd<T>, G(K.ny / nl), dim3(256), lrow, s, K, r, a, zc, lx, nl, P.tw[0], work0, bt);
     hipLaunchKernelGGL(k_fft2_cols_solve, G(K.nx / 2), dim3(256), lcol, s, K, ly, P.tw[1], P.sn[0],
                        P.sn[1], work0, bt);

@@ -101,6 +101,13 @@ __device__ inline int bat_nz(const Bat& bt) { return (int)(gridDim.z / (unsigned
 __device__ inline bool bat_skip(const Bat& bt, int b) { return ((bt.mask >> b) & 1u) == 0u; }
 __device__ inline double bat_s(const Bat& bt, int b, double v) { return bt.per ? bt.s[b] : v; }
 
+// Allow a kernel the largest dynamic LDS of one workgroup (160 KiB); its launches then ask for
+// what they need.  Called once per kernel through a function-local static at the launch site
+// (thread-safe initialisation), not on every launch.
+inline bool allow_max_lds(const void* kernel) {
+  return hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) == hipSuccess;
+}
+
 // ---- phase-field kernels (kernels_phase.hip) ---------------------------------------
 // X, Xn: nf planes (c, eta1..3, u1..ud); all plane strides are N.
 void launch_residual(const Consts& K, double dt, const double* X, const double* Xn, double* G4,
