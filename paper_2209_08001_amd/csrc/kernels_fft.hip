@@ -191,6 +191,28 @@ __global__ __launch_bounds__(256) void k_fft2_rows_fwd(Consts K, const T* __rest
   }
 }
 
+// The 2D symbol solve at wave numbers (S0, S1) = (S_kx, S_ky): the spectra av = Z(k) and
+// bv = Z(-k) of z = q_x + i q_y give Q_x = (Z(k) + conj Z(-k)) / 2 and Q_y = (Z(k) -
+// conj Z(-k)) / (2i); Khat U = Q (U = 0 where S0 = S1 = 0: the gauge; U = Q without
+// elasticity); returns the spectrum of u_x + i u_y, U_x + i U_y.
+__device__ inline double2 symbol_solve2(const Consts& K, double2 av, double2 bv, double S0, double S1) {
+  const double2 Q0 = make_double2(0.5 * (av.x + bv.x), 0.5 * (av.y - bv.y));
+  const double2 Q1 = make_double2(0.5 * (av.y + bv.y), -0.5 * (av.x - bv.x));
+  double2 U0 = make_double2(0.0, 0.0), U1 = make_double2(0.0, 0.0);
+  const double s2 = S0 * S0 + S1 * S1;
+  if (!K.elastic) {
+    U0 = Q0;
+    U1 = Q1;
+  } else if (s2 != 0.0) {
+    const double A00 = -(K.C11 * S0 * S0 + K.C44 * S1 * S1), A11 = -(K.C11 * S1 * S1 + K.C44 * S0 * S0);
+    const double A01 = -(K.C12 + K.C44) * S0 * S1;
+    const double id = 1.0 / (A00 * A11 - A01 * A01);
+    U0 = make_double2((A11 * Q0.x - A01 * Q1.x) * id, (A11 * Q0.y - A01 * Q1.y) * id);
+    U1 = make_double2((A00 * Q1.x - A01 * Q0.x) * id, (A00 * Q1.y - A01 * Q0.y) * id);
+  }
+  return make_double2(U0.x - U1.y, U0.y + U1.x);
+}
+
 // pass 2: the column pair (kx, -kx): forward FFT along y, pointwise solve of the 2 x 2
 // symbol system (needs Z(k) and Z(-k), both in this block), inverse FFT along y.  Block kx
 // (0 .. nx/2 - 1) takes columns kx and nx - kx; block 0 takes the two columns that are
@@ -227,23 +249,9 @@ __global__ __launch_bounds__(256) void k_fft2_cols_solve(Consts K, int logn, con
     const int lm = self ? l : 1 - l;   // the mirror column's line
     const int jm = (j == 0) ? 0 : n - j;
     const double2 av = sm[lp(l * n + j)], bv = sm[lp(lm * n + jm)];
-    double2 Q0 = make_double2(0.5 * (av.x + bv.x), 0.5 * (av.y - bv.y));
-    double2 Q1 = make_double2(0.5 * (av.y + bv.y), -0.5 * (av.x - bv.x));
-    double2 U0 = make_double2(0.0, 0.0), U1 = make_double2(0.0, 0.0);
-    const double S0 = sx[col], S1 = syt[j];
-    const double s2 = S0 * S0 + S1 * S1;
-    if (!K.elastic) {
-      U0 = Q0;
-      U1 = Q1;
-    } else if (s2 != 0.0) {
-      const double A00 = -(K.C11 * S0 * S0 + K.C44 * S1 * S1), A11 = -(K.C11 * S1 * S1 + K.C44 * S0 * S0);
-      const double A01 = -(K.C12 + K.C44) * S0 * S1;
-      const double id = 1.0 / (A00 * A11 - A01 * A01);
-      U0 = make_double2((A11 * Q0.x - A01 * Q1.x) * id, (A11 * Q0.y - A01 * Q1.y) * id);
-      U1 = make_double2((A00 * Q1.x - A01 * Q0.x) * id, (A00 * Q1.y - A01 * Q0.y) * id);
-    }
+    const double2 Uv = symbol_solve2(K, av, bv, sx[col], syt[j]);
     // spectrum of u_x + i u_y, written in bit-reversed order for the inverse transform
-    sm[lp(2 * n + l * n + brev(j, logn))] = make_double2(U0.x - U1.y, U0.y + U1.x);
+    sm[lp(2 * n + l * n + brev(j, logn))] = Uv;
   }
   __syncthreads();
   fft_lds(sm, n, logn, ncol, tws, 1, 2 * n);
@@ -641,6 +649,150 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_lines_mr(double2* __restric
   }
 }
 
+// All stages of the mixed-radix transform of lpb contiguous lines of n points held in LDS (b0),
+// ping-ponging with b1; returns the buffer that holds the result, in natural order.
+__device__ inline double2* mr_lines(double2* b0, double2* b1, const double2* tws, int n, int lpb, const MrPlan& pl,
+                                    int inverse) {
+  double2 *src = b0, *dst = b1;
+  int p = 1;
+  for (int st = 0; st < pl.nst; ++st) {
+    const int R = pl.r[st];
+    switch (R) {
+      case 2: mr_stage<2>(src, dst, tws, n, p, lpb, inverse); break;
+      case 3: mr_stage<3>(src, dst, tws, n, p, lpb, inverse); break;
+      case 4: mr_stage<4>(src, dst, tws, n, p, lpb, inverse); break;
+      case 5: mr_stage<5>(src, dst, tws, n, p, lpb, inverse); break;
+      case 7: mr_stage<7>(src, dst, tws, n, p, lpb, inverse); break;
+      case 11: mr_stage<11>(src, dst, tws, n, p, lpb, inverse); break;
+      default: mr_stage<13>(src, dst, tws, n, p, lpb, inverse); break;
+    }
+    __syncthreads();
+    double2* t = src;
+    src = dst;
+    dst = t;
+    p *= R;
+  }
+  return src;
+}
+
+// ---- fused 2D solve for sides that are not powers of two ---------------------------------
+// The three passes of the power-of-two 2D path (rows forward with q = r_u + a Dhat z_c formed
+// on the fly; column pairs (kx, nx - kx) forward, 2 x 2 symbol solve, inverse; rows inverse
+// with the unpack), each line transformed in LDS by the mixed-radix stages above.  LDS per
+// workgroup: two buffers of the block's lines and the line length's twiddles.
+
+// pass 1: rows j0 .. j0 + nl - 1
+template <typename T>
+__global__ __launch_bounds__(kFftThreads) void k_fft2mr_rows_fwd(Consts K, const T* __restrict__ r, double a,
+                                                                 const T* __restrict__ zc, int nl, MrPlan pl,
+                                                                 const double2* __restrict__ tw,
+                                                                 double2* __restrict__ out, Bat bt) {
+  const int binst = bat_inst(bt);
+  if (bat_skip(bt, binst)) return;
+  const long long bo = binst * bt.stride;
+  r = bat_at(r, bo);
+  zc = bat_at(zc, bo);
+  out = bat_at(out, bo);
+  extern __shared__ double2 sm[];
+  const int n = K.nx;
+  double2* b0 = sm;
+  double2* b1 = sm + nl * n;
+  double2* tws = sm + 2 * nl * n;
+  for (int e = threadIdx.x; e < n; e += kFftThreads) tws[e] = tw[e];
+  const int j0 = xcd_band(blockIdx.x, gridDim.x) * nl;
+  for (int e = threadIdx.x; e < nl * n; e += kFftThreads) {
+    const int l = e / n, i = e - l * n, j = j0 + l;
+    const long long m = (long long)i + (long long)n * j;
+    double qx = r ? (double)r[m] : 0.0, qy = r ? (double)r[K.N + m] : 0.0;
+    if (zc && a != 0.0) {
+      const int ip = (i + 1 == n) ? 0 : i + 1, im = (i == 0) ? n - 1 : i - 1;
+      const int jp = (j + 1 == K.ny) ? 0 : j + 1, jm = (j == 0) ? K.ny - 1 : j - 1;
+      qx += a * ((double)zc[ip + (long long)n * j] - (double)zc[im + (long long)n * j]) * K.i2h;
+      qy += a * ((double)zc[i + (long long)n * jp] - (double)zc[i + (long long)n * jm]) * K.i2h;
+    }
+    b0[e] = make_double2(qx, qy);
+  }
+  __syncthreads();
+  const double2* res = mr_lines(b0, b1, tws, n, nl, pl, 0);
+  for (int e = threadIdx.x; e < nl * n; e += kFftThreads) {
+    const int l = e / n, i = e - l * n;
+    out[(long long)i + (long long)n * (j0 + l)] = res[e];
+  }
+}
+
+// pass 2: block kx (0 .. nx/2 - 1) takes columns kx and nx - kx (block 0: 0 and nx/2)
+__global__ __launch_bounds__(kFftThreads) void k_fft2mr_cols_solve(Consts K, MrPlan pl,
+                                                                   const double2* __restrict__ tw,
+                                                                   const double* __restrict__ sx,
+                                                                   const double* __restrict__ syt,
+                                                                   double2* __restrict__ data, Bat bt) {
+  const int binst = bat_inst(bt);
+  if (bat_skip(bt, binst)) return;
+  data = bat_at(data, binst * bt.stride);
+  extern __shared__ double2 sm[];
+  const int n = K.ny, nx = K.nx;
+  double2* b0 = sm;
+  double2* b1 = sm + 2 * n;
+  double2* tws = sm + 4 * n;
+  for (int e = threadIdx.x; e < n; e += kFftThreads) tws[e] = tw[e];
+  const int kx = xcd_band(blockIdx.x, gridDim.x);
+  const bool self = (kx == 0);
+  const int kxm = self ? nx / 2 : nx - kx;
+  for (int e = threadIdx.x; e < 2 * n; e += kFftThreads) {
+    const int l = e / n, j = e - l * n;
+    b0[e] = data[(long long)(l ? kxm : kx) + (long long)nx * j];
+  }
+  __syncthreads();
+  double2* spec = mr_lines(b0, b1, tws, n, 2, pl, 0);
+  double2* other = (spec == b0) ? b1 : b0;
+  for (int e = threadIdx.x; e < 2 * n; e += kFftThreads) {
+    const int l = e / n, j = e - l * n;
+    const int col = l ? kxm : kx;
+    const int lm = self ? l : 1 - l;   // the mirror column's line
+    const int jm = (j == 0) ? 0 : n - j;
+    other[e] = symbol_solve2(K, spec[e], spec[lm * n + jm], sx[col], syt[j]);
+  }
+  __syncthreads();
+  const double2* res = mr_lines(other, spec, tws, n, 2, pl, 1);
+  for (int e = threadIdx.x; e < 2 * n; e += kFftThreads) {
+    const int l = e / n, j = e - l * n;
+    data[(long long)(l ? kxm : kx) + (long long)nx * j] = res[e];
+  }
+}
+
+// pass 3: inverse along x, u_x = Re / N, u_y = Im / N
+template <typename T>
+__global__ __launch_bounds__(kFftThreads) void k_fft2mr_rows_inv(Consts K, int nl, MrPlan pl,
+                                                                 const double2* __restrict__ tw,
+                                                                 const double2* __restrict__ in, T* __restrict__ u,
+                                                                 Bat bt) {
+  const int binst = bat_inst(bt);
+  if (bat_skip(bt, binst)) return;
+  const long long bo = binst * bt.stride;
+  in = bat_at(in, bo);
+  u = bat_at(u, bo);
+  extern __shared__ double2 sm[];
+  const int n = K.nx;
+  double2* b0 = sm;
+  double2* b1 = sm + nl * n;
+  double2* tws = sm + 2 * nl * n;
+  for (int e = threadIdx.x; e < n; e += kFftThreads) tws[e] = tw[e];
+  const int j0 = xcd_band(blockIdx.x, gridDim.x) * nl;
+  for (int e = threadIdx.x; e < nl * n; e += kFftThreads) {
+    const int l = e / n, i = e - l * n;
+    b0[e] = in[(long long)i + (long long)n * (j0 + l)];
+  }
+  __syncthreads();
+  const double2* res = mr_lines(b0, b1, tws, n, nl, pl, 1);
+  const double inv = 1.0 / (double)K.N;
+  for (int e = threadIdx.x; e < nl * n; e += kFftThreads) {
+    const int l = e / n, i = e - l * n;
+    const long long m = (long long)i + (long long)n * (j0 + l);
+    u[m] = (T)(res[e].x * inv);
+    u[K.N + m] = (T)(res[e].y * inv);
+  }
+}
+
 // q_I = r_I + a Dhat_I zc; z0 = q_1 + i q_2, z1 = q_3 (3D)
 template <int DIM, typename T>
 __global__ __launch_bounds__(256) void k_pack(Consts K, const T* __restrict__ r, double a,
@@ -933,6 +1085,31 @@ void launch_spectral_solve(const Consts& K, const FftPlan& P, const T* r, double
     hipLaunchKernelGGL(k_fft2_cols_solve, G(K.nx / 2), dim3(256), lcol, s, K, ly, P.tw[1], P.sn[0],
                        P.sn[1], work0, bt);
     hipLaunchKernelGGL(k_fft2_rows_inv<T>, G(K.ny / nl), dim3(256), lrow, s, K, lx, nl, P.tw[0], work0, u, bt);
+    return;
+  }
+  if (!all_pow2 && K.dim == 2 && K.ny <= 1024 && K.nx <= 1024) {
+    const MrPlan px = mr_plan(K.nx), py = mr_plan(K.ny);
+    // rows per x block: two LDS buffers of nl rows within 64 KiB, and about 512 blocks
+    int nl = 1;
+    while (K.ny % (2 * nl) == 0 && 2 * (2 * nl) * K.nx + K.nx <= 4096 && K.ny / (2 * nl) >= 512) nl *= 2;
+    const size_t lrow = sizeof(double2) * ((size_t)2 * nl * K.nx + K.nx);
+    const size_t lcol = sizeof(double2) * ((size_t)4 * K.ny + K.ny);
+    if (lrow > 64 * 1024) {
+      static const bool ok_f = allow_max_lds((const void*)k_fft2mr_rows_fwd<T>);
+      static const bool ok_i = allow_max_lds((const void*)k_fft2mr_rows_inv<T>);
+      (void)ok_f;
+      (void)ok_i;
+    }
+    if (lcol > 64 * 1024) {
+      static const bool ok_c = allow_max_lds((const void*)k_fft2mr_cols_solve);
+      (void)ok_c;
+    }
+    hipLaunchKernelGGL(k_fft2mr_rows_fwd<T>, G(K.ny / nl), dim3(kFftThreads), lrow, s, K, r, a, zc, nl, px, P.tw[0],
+                       work0, bt);
+    hipLaunchKernelGGL(k_fft2mr_cols_solve, G(K.nx / 2), dim3(kFftThreads), lcol, s, K, py, P.tw[1], P.sn[0],
+                       P.sn[1], work0, bt);
+    hipLaunchKernelGGL(k_fft2mr_rows_inv<T>, G(K.ny / nl), dim3(kFftThreads), lrow, s, K, nl, px, P.tw[0], work0, u,
+                       bt);
     return;
   }
   if (all_pow2 && K.dim == 3 && K.nx >= 8 && K.nx <= 1024 && K.nz <= 1024 && K.ny <= 4096) {
