@@ -501,11 +501,13 @@ def run_serving(args, wl):
     mk = lambda seed: poisson_requests(wl["rate"], window, seed, wl["sides2d"], wl["sides3d"],
                                        wl["frac3d"], args.steps if args.steps_given else wl["steps"])
     if args.warmup > 0:
-        Server(solver, wl, budget, threads=args.threads).run(mk(wl["seed"] + 1000)[:4], realtime=False)
+        Server(solver, wl, budget, threads=args.threads, mode=args.serve_mode,
+               group_capacity=args.group_capacity).run(mk(wl["seed"] + 1000)[:4], realtime=False)
     reqs = mk(wl["seed"])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    Server(solver, wl, budget, threads=args.threads).run(reqs, realtime=True)
+    Server(solver, wl, budget, threads=args.threads, mode=args.serve_mode,
+           group_capacity=args.group_capacity).run(reqs, realtime=True)
     torch.cuda.synchronize()
     makespan = time.perf_counter() - t0
     steps = sum(r.done for r in reqs)
@@ -526,7 +528,8 @@ def run_serving(args, wl):
         "data": "synthetic",
         "config": {"workload": args.workload, "requests": len(reqs), "rate_per_s": wl["rate"],
                    "window_s": window, "steps_per_request": reqs[0].steps if reqs else 0,
-                   "hbm_budget_bytes": budget, "precision": args.precision, "host_threads": args.threads},
+                   "hbm_budget_bytes": budget, "precision": args.precision, "host_threads": args.threads,
+                   "mode": args.serve_mode, "group_capacity": args.group_capacity if args.serve_mode == "groups" else None},
         "makespan_s": makespan,
         "p50_step_ms": percentile(lat, 50),
         "p99_step_ms": percentile(lat, 99),
@@ -565,6 +568,9 @@ def main():
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--threads", type=int, default=16,
                     help="ensemble workloads: host threads driving the instances (pfnks_batch_step)")
+    ap.add_argument("--serve-mode", default="groups", choices=["groups", "threads"],
+                    help="serving workload: lockstep slot groups per grid shape or one problem per request")
+    ap.add_argument("--group-capacity", type=int, default=8, help="serving workload: slots of a shape's group")
     ap.add_argument("--ensemble-mode", default="lockstep", choices=["lockstep", "threads"],
                     help="ensemble workloads: lockstep groups of one side each (pfnks_group_step) or "
                          "host threads over one stream per instance (pfnks_batch_step)")

@@ -207,6 +207,11 @@ int pfnks_group_create(const pfnks_grid* grid, const pfnks_model* model, const p
  * every instance succeeded, else the first failing instance's status.
  * Errors: PFNKS_EINVAL (null group or dts, dts[i] < 0 or not finite), PFNKS_EDEVICE. */
 int pfnks_group_step(pfnks_group* g, const double* dts, pfnks_step_stats* stats, int* status);
+/* Give instance i a new initial state (c0: N doubles, eta0: 3 N, as pfnks_create_problem):
+ * its displacement from the elastic equilibrium, its mean composition and t = 0; the other
+ * instances are untouched.  A serving loop reuses a freed slot this way.  Synchronises the
+ * group's stream.  Errors: PFNKS_EINVAL, PFNKS_EDOMAIN, PFNKS_EDEVICE. */
+int pfnks_group_set_instance(pfnks_group* g, int i, const double* c0, const double* eta0);
 /* State of instance i to host (4 + dim planes, as pfnks_get_state); t may be NULL. */
 int pfnks_group_get_state(pfnks_group* g, int i, double* X, double* t);
 /* Kernel launches and host synchronisations of the last pfnks_group_step. */

@@ -579,8 +579,40 @@ __device__ inline void mr_stage(const double2* __restrict__ src, double2* __rest
   }
 }
 
+// All stages of the mixed-radix transform of lpb contiguous lines of n points held in LDS (b0),
+// ping-ponging with b1; returns the buffer that holds the result, in natural order.  MAXR: the
+// largest radix the kernel is built for (5, 7 or 13: the registers of the largest butterfly
+// bound the kernel's occupancy, so lines without radices 7, 11, 13 use a smaller build).
+template <int MAXR>
+__device__ inline double2* mr_lines(double2* b0, double2* b1, const double2* tws, int n, int lpb, const MrPlan& pl,
+                                    int inverse) {
+  double2 *src = b0, *dst = b1;
+  int p = 1;
+  for (int st = 0; st < pl.nst; ++st) {
+    const int R = pl.r[st];
+    if (R == 2) mr_stage<2>(src, dst, tws, n, p, lpb, inverse);
+    else if (R == 3) mr_stage<3>(src, dst, tws, n, p, lpb, inverse);
+    else if (R == 4) mr_stage<4>(src, dst, tws, n, p, lpb, inverse);
+    else if (R == 5) mr_stage<5>(src, dst, tws, n, p, lpb, inverse);
+    else if constexpr (MAXR >= 7) {
+      if (R == 7) mr_stage<7>(src, dst, tws, n, p, lpb, inverse);
+      else if constexpr (MAXR >= 13) {
+        if (R == 11) mr_stage<11>(src, dst, tws, n, p, lpb, inverse);
+        else mr_stage<13>(src, dst, tws, n, p, lpb, inverse);
+      }
+    }
+    __syncthreads();
+    double2* t = src;
+    src = dst;
+    dst = t;
+    p *= R;
+  }
+  return src;
+}
+
 // Lines addressed as in k_fft_lines; LDS: two buffers of lpb n points, the n twiddles, and the
 // offset of each of the block's lines (formed once per line, not per point).
+template <int MAXR>
 __global__ __launch_bounds__(kFftThreads) void k_fft_lines_mr(double2* __restrict__ data, int n, MrPlan pl,
                                                               long long pstride, long long la, long long lb,
                                                               long long lc, long long nlines, int lpb,
@@ -616,25 +648,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_lines_mr(double2* __restric
     b0[l * n + q] = (off >= 0) ? data[off + q * pstride] : make_double2(0.0, 0.0);
   }
   __syncthreads();
-  double2 *src = b0, *dst = b1;
-  int p = 1;
-  for (int st = 0; st < pl.nst; ++st) {
-    const int R = pl.r[st];
-    switch (R) {
-      case 2: mr_stage<2>(src, dst, tws, n, p, lpb, inverse); break;
-      case 3: mr_stage<3>(src, dst, tws, n, p, lpb, inverse); break;
-      case 4: mr_stage<4>(src, dst, tws, n, p, lpb, inverse); break;
-      case 5: mr_stage<5>(src, dst, tws, n, p, lpb, inverse); break;
-      case 7: mr_stage<7>(src, dst, tws, n, p, lpb, inverse); break;
-      case 11: mr_stage<11>(src, dst, tws, n, p, lpb, inverse); break;
-      default: mr_stage<13>(src, dst, tws, n, p, lpb, inverse); break;
-    }
-    __syncthreads();
-    double2* t = src;
-    src = dst;
-    dst = t;
-    p *= R;
-  }
+  const double2* src = mr_lines<MAXR>(b0, b1, tws, n, lpb, pl, inverse);
   for (int e = threadIdx.x; e < total; e += kFftThreads) {
     int l, q;
     if (contiguous) {
@@ -649,32 +663,6 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_lines_mr(double2* __restric
   }
 }
 
-// All stages of the mixed-radix transform of lpb contiguous lines of n points held in LDS (b0),
-// ping-ponging with b1; returns the buffer that holds the result, in natural order.
-__device__ inline double2* mr_lines(double2* b0, double2* b1, const double2* tws, int n, int lpb, const MrPlan& pl,
-                                    int inverse) {
-  double2 *src = b0, *dst = b1;
-  int p = 1;
-  for (int st = 0; st < pl.nst; ++st) {
-    const int R = pl.r[st];
-    switch (R) {
-      case 2: mr_stage<2>(src, dst, tws, n, p, lpb, inverse); break;
-      case 3: mr_stage<3>(src, dst, tws, n, p, lpb, inverse); break;
-      case 4: mr_stage<4>(src, dst, tws, n, p, lpb, inverse); break;
-      case 5: mr_stage<5>(src, dst, tws, n, p, lpb, inverse); break;
-      case 7: mr_stage<7>(src, dst, tws, n, p, lpb, inverse); break;
-      case 11: mr_stage<11>(src, dst, tws, n, p, lpb, inverse); break;
-      default: mr_stage<13>(src, dst, tws, n, p, lpb, inverse); break;
-    }
-    __syncthreads();
-    double2* t = src;
-    src = dst;
-    dst = t;
-    p *= R;
-  }
-  return src;
-}
-
 // ---- fused 2D solve for sides that are not powers of two ---------------------------------
 // The three passes of the power-of-two 2D path (rows forward with q = r_u + a Dhat z_c formed
 // on the fly; column pairs (kx, nx - kx) forward, 2 x 2 symbol solve, inverse; rows inverse
@@ -682,7 +670,7 @@ __device__ inline double2* mr_lines(double2* b0, double2* b1, const double2* tws
 // workgroup: two buffers of the block's lines and the line length's twiddles.
 
 // pass 1: rows j0 .. j0 + nl - 1
-template <typename T>
+template <typename T, int MAXR>
 __global__ __launch_bounds__(kFftThreads) void k_fft2mr_rows_fwd(Consts K, const T* __restrict__ r, double a,
                                                                  const T* __restrict__ zc, int nl, MrPlan pl,
                                                                  const double2* __restrict__ tw,
@@ -713,7 +701,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft2mr_rows_fwd(Consts K, const
     b0[e] = make_double2(qx, qy);
   }
   __syncthreads();
-  const double2* res = mr_lines(b0, b1, tws, n, nl, pl, 0);
+  const double2* res = mr_lines<MAXR>(b0, b1, tws, n, nl, pl, 0);
   for (int e = threadIdx.x; e < nl * n; e += kFftThreads) {
     const int l = e / n, i = e - l * n;
     out[(long long)i + (long long)n * (j0 + l)] = res[e];
@@ -721,6 +709,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft2mr_rows_fwd(Consts K, const
 }
 
 // pass 2: block kx (0 .. nx/2 - 1) takes columns kx and nx - kx (block 0: 0 and nx/2)
+template <int MAXR>
 __global__ __launch_bounds__(kFftThreads) void k_fft2mr_cols_solve(Consts K, MrPlan pl,
                                                                    const double2* __restrict__ tw,
                                                                    const double* __restrict__ sx,
@@ -743,7 +732,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft2mr_cols_solve(Consts K, MrP
     b0[e] = data[(long long)(l ? kxm : kx) + (long long)nx * j];
   }
   __syncthreads();
-  double2* spec = mr_lines(b0, b1, tws, n, 2, pl, 0);
+  double2* spec = mr_lines<MAXR>(b0, b1, tws, n, 2, pl, 0);
   double2* other = (spec == b0) ? b1 : b0;
   for (int e = threadIdx.x; e < 2 * n; e += kFftThreads) {
     const int l = e / n, j = e - l * n;
@@ -753,7 +742,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft2mr_cols_solve(Consts K, MrP
     other[e] = symbol_solve2(K, spec[e], spec[lm * n + jm], sx[col], syt[j]);
   }
   __syncthreads();
-  const double2* res = mr_lines(other, spec, tws, n, 2, pl, 1);
+  const double2* res = mr_lines<MAXR>(other, spec, tws, n, 2, pl, 1);
   for (int e = threadIdx.x; e < 2 * n; e += kFftThreads) {
     const int l = e / n, j = e - l * n;
     data[(long long)(l ? kxm : kx) + (long long)nx * j] = res[e];
@@ -761,7 +750,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft2mr_cols_solve(Consts K, MrP
 }
 
 // pass 3: inverse along x, u_x = Re / N, u_y = Im / N
-template <typename T>
+template <typename T, int MAXR>
 __global__ __launch_bounds__(kFftThreads) void k_fft2mr_rows_inv(Consts K, int nl, MrPlan pl,
                                                                  const double2* __restrict__ tw,
                                                                  const double2* __restrict__ in, T* __restrict__ u,
@@ -783,7 +772,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft2mr_rows_inv(Consts K, int n
     b0[e] = in[(long long)i + (long long)n * (j0 + l)];
   }
   __syncthreads();
-  const double2* res = mr_lines(b0, b1, tws, n, nl, pl, 1);
+  const double2* res = mr_lines<MAXR>(b0, b1, tws, n, nl, pl, 1);
   const double inv = 1.0 / (double)K.N;
   for (int e = threadIdx.x; e < nl * n; e += kFftThreads) {
     const int l = e / n, i = e - l * n;
@@ -959,8 +948,7 @@ void launch_lines(double2* data, int n, int logn, long long pstride, long long l
                   const Bat& bt) {
   const size_t lds = sizeof(double2) * ((size_t)lp_size(lpb * n) + n / 2);
   if (lds > 64 * 1024) {
-    static const bool lds_ok = allow_max_lds((const void*)k_fft_lines);
-    (void)lds_ok;
+    allow_max_lds((const void*)k_fft_lines);
   }
   const long long blocks = (nlines + lpb - 1) / lpb;
   hipLaunchKernelGGL(k_fft_lines, bat_grid(dim3((unsigned)blocks), bt), dim3(kFftThreads), lds, s, data, n, logn,
@@ -978,6 +966,13 @@ MrPlan mr_plan(int n) {
   for (int f = 3; f <= 13 && n > 1; f += 2)
     while (n % f == 0) { add(f); n /= f; }
   return pl;
+}
+
+// the build of the mixed-radix kernels a plan needs: its largest radix, rounded up to 5, 7 or 13
+int mr_bucket(const MrPlan& pl) {
+  int m = 2;
+  for (int st = 0; st < pl.nst; ++st) m = pl.r[st] > m ? pl.r[st] : m;
+  return m <= 5 ? 5 : (m <= 7 ? 7 : 13);
 }
 
 void fft_dir_mr(const Consts& K, const FftPlan& P, double2* data, int dir, int inverse, hipStream_t s,
@@ -1002,13 +997,16 @@ void fft_dir_mr(const Consts& K, const FftPlan& P, double2* data, int dir, int i
   // (at least 512 workgroups where the line count allows)
   while (lpb > 1 && (nlines + lpb - 1) / lpb < 512) lpb = (lpb + 1) / 2;
   const size_t lds = sizeof(double2) * ((size_t)2 * lpb * n + n) + sizeof(long long) * (size_t)lpb;
-  if (lds > 64 * 1024) {
-    static const bool lds_ok = allow_max_lds((const void*)k_fft_lines_mr);
-    (void)lds_ok;
-  }
   const long long blocks = (nlines + lpb - 1) / lpb;
-  hipLaunchKernelGGL(k_fft_lines_mr, bat_grid(dim3((unsigned)blocks), bt), dim3(kFftThreads), lds, s, data, n, pl,
-                     pstride, la, lb, lc, nlines, lpb, P.tw[dir], inverse, dir == 0 ? 1 : 0, bt);
+  auto go = [&](auto kern) {
+    if (lds > 64 * 1024) allow_max_lds((const void*)kern);
+    hipLaunchKernelGGL(kern, bat_grid(dim3((unsigned)blocks), bt), dim3(kFftThreads), lds, s, data, n, pl, pstride,
+                       la, lb, lc, nlines, lpb, P.tw[dir], inverse, dir == 0 ? 1 : 0, bt);
+  };
+  const int mr = mr_bucket(pl);
+  if (mr == 5) go(k_fft_lines_mr<5>);
+  else if (mr == 7) go(k_fft_lines_mr<7>);
+  else go(k_fft_lines_mr<13>);
 }
 
 void fft_dir(const Consts& K, const FftPlan& P, double2* data, int dir, int inverse, hipStream_t s,
@@ -1078,8 +1076,7 @@ void launch_spectral_solve(const Consts& K, const FftPlan& P, const T* r, double
     const size_t lrow = sizeof(double2) * (lp_size(nl * K.nx) + K.nx / 2);
     const size_t lcol = sizeof(double2) * (lp_size(4 * K.ny) + K.ny / 2);
     if (lcol > 64 * 1024) {  // ny = 1024: 80 KiB
-      static const bool lds_ok = allow_max_lds((const void*)k_fft2_cols_solve);
-      (void)lds_ok;
+      allow_max_lds((const void*)k_fft2_cols_solve);
     }
     hipLaunchKernelGGL(k_fft2_rows_fwd<T>, G(K.ny / nl), dim3(256), lrow, s, K, r, a, zc, lx, nl, P.tw[0], work0, bt);
     hipLaunchKernelGGL(k_fft2_cols_solve, G(K.nx / 2), dim3(256), lcol, s, K, ly, P.tw[1], P.sn[0],
@@ -1089,27 +1086,32 @@ void launch_spectral_solve(const Consts& K, const FftPlan& P, const T* r, double
   }
   if (!all_pow2 && K.dim == 2 && K.ny <= 1024 && K.nx <= 1024) {
     const MrPlan px = mr_plan(K.nx), py = mr_plan(K.ny);
-    // rows per x block: two LDS buffers of nl rows within 64 KiB, and about 512 blocks
-    int nl = 1;
-    while (K.ny % (2 * nl) == 0 && 2 * (2 * nl) * K.nx + K.nx <= 4096 && K.ny / (2 * nl) >= 512) nl *= 2;
+    // rows per x block: about 512 points (as the power-of-two rows), dividing ny
+    int nl = 512 / K.nx;
+    if (nl < 1) nl = 1;
+    while (K.ny % nl) --nl;
     const size_t lrow = sizeof(double2) * ((size_t)2 * nl * K.nx + K.nx);
     const size_t lcol = sizeof(double2) * ((size_t)4 * K.ny + K.ny);
-    if (lrow > 64 * 1024) {
-      static const bool ok_f = allow_max_lds((const void*)k_fft2mr_rows_fwd<T>);
-      static const bool ok_i = allow_max_lds((const void*)k_fft2mr_rows_inv<T>);
-      (void)ok_f;
-      (void)ok_i;
-    }
-    if (lcol > 64 * 1024) {
-      static const bool ok_c = allow_max_lds((const void*)k_fft2mr_cols_solve);
-      (void)ok_c;
-    }
-    hipLaunchKernelGGL(k_fft2mr_rows_fwd<T>, G(K.ny / nl), dim3(kFftThreads), lrow, s, K, r, a, zc, nl, px, P.tw[0],
-                       work0, bt);
-    hipLaunchKernelGGL(k_fft2mr_cols_solve, G(K.nx / 2), dim3(kFftThreads), lcol, s, K, py, P.tw[1], P.sn[0],
-                       P.sn[1], work0, bt);
-    hipLaunchKernelGGL(k_fft2mr_rows_inv<T>, G(K.ny / nl), dim3(kFftThreads), lrow, s, K, nl, px, P.tw[0], work0, u,
-                       bt);
+    auto rows = [&](auto kf, auto ki) {
+      if (lrow > 64 * 1024) {
+        allow_max_lds((const void*)kf);
+        allow_max_lds((const void*)ki);
+      }
+      hipLaunchKernelGGL(kf, G(K.ny / nl), dim3(kFftThreads), lrow, s, K, r, a, zc, nl, px, P.tw[0], work0, bt);
+      return ki;
+    };
+    auto cols = [&](auto kc) {
+      if (lcol > 64 * 1024) allow_max_lds((const void*)kc);
+      hipLaunchKernelGGL(kc, G(K.nx / 2), dim3(kFftThreads), lcol, s, K, py, P.tw[1], P.sn[0], P.sn[1], work0, bt);
+    };
+    const int bx = mr_bucket(px), by = mr_bucket(py);
+    auto ki = (bx == 5) ? rows(k_fft2mr_rows_fwd<T, 5>, k_fft2mr_rows_inv<T, 5>)
+              : (bx == 7) ? rows(k_fft2mr_rows_fwd<T, 7>, k_fft2mr_rows_inv<T, 7>)
+                          : rows(k_fft2mr_rows_fwd<T, 13>, k_fft2mr_rows_inv<T, 13>);
+    if (by == 5) cols(k_fft2mr_cols_solve<5>);
+    else if (by == 7) cols(k_fft2mr_cols_solve<7>);
+    else cols(k_fft2mr_cols_solve<13>);
+    hipLaunchKernelGGL(ki, G(K.ny / nl), dim3(kFftThreads), lrow, s, K, nl, px, P.tw[0], work0, u, bt);
     return;
   }
   if (all_pow2 && K.dim == 3 && K.nx >= 8 && K.nx <= 1024 && K.nz <= 1024 && K.ny <= 4096) {

@@ -86,7 +86,7 @@ __device__ inline int xcd_block(const Bat& bt, int& bx, int& by, int& bz) {
   by = (b / gx) % gy;
   const int zt = b / (gx * gy), nzl = gz / bt.count;
   bz = zt % nzl;
-  return zt / nzl;
+  return bt.map[zt / nzl];
 }
 
 __device__ inline Pt coords(const Consts& K, long long n) {

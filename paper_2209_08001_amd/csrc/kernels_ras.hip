@@ -590,14 +590,12 @@ void launch_npt(const Geo& G, const Consts& K, size_t lds, int ntiles, int npt, 
   const dim3 grid = bat_grid(dim3(ntiles), bt);
 #define PF_RAS_CASE(NPTV)                                                                             \
   case NPTV: {                                                                                        \
-    static const bool lds_ok = allow_max_lds((const void*)k_ras<DIM, WU, NPTV, R, TH>);              \
-    (void)lds_ok;                                                                                     \
+    allow_max_lds((const void*)k_ras<DIM, WU, NPTV, R, TH>); \
     hipLaunchKernelGGL((k_ras<DIM, WU, NPTV, R, TH>), grid, dim3(TH), lds, s, K, G, dt, B, cn, r, z, perm, pack, xs, bt); \
   } break;
   if constexpr (TH == kRasThreadsSmall) {
     if (npt == 4) {
-      static const bool lds_ok = allow_max_lds((const void*)k_ras<DIM, WU, 4, R, TH>);
-      (void)lds_ok;
+      allow_max_lds((const void*)k_ras<DIM, WU, 4, R, TH>);
       hipLaunchKernelGGL((k_ras<DIM, WU, 4, R, TH>), grid, dim3(TH), lds, s, K, G, dt, B, cn, r, z, perm, pack,
                          xs, bt);
       return;

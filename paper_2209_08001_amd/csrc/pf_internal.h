@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <cstddef>
 #include <cstdint>
+#include <mutex>
+#include <unordered_set>
 
 namespace pf {
 
@@ -36,12 +38,13 @@ struct Consts {
 };
 
 // ---- lockstep batches of one grid shape (pfnks_group) --------------------------------
-// A launch may cover `count` problems of one shape at once.  Instance b's workspace starts
+// A launch may cover several problems of one shape at once.  Instance b's workspace starts
 // b * stride bytes after instance 0's, so every pointer argument points into instance 0's
 // workspace and a workgroup of instance b adds b * stride; pinned host slots (the second
 // output of the finalize kernels) are hstride bytes apart.  The slowest grid axis (z) is
-// split into count equal parts, one per instance, and a workgroup whose instance has its bit
-// of mask clear returns at once.  Tables that every instance shares (twiddles, Fourier
+// split into count equal parts, one per launched instance: part k works on instance map[k]
+// (only the instances a phase still works on are launched); a workgroup whose instance has its
+// bit of mask clear returns at once.  Tables that every instance shares (twiddles, Fourier
 // symbols, colour order) are read from instance 0.  A single problem is the batch of one.
 // With per = 1 the per-instance scalars replace a launch's scalar argument: s is the time
 // step of the stencil, tile and residual launches, the coefficient a of axpby and the step
@@ -54,6 +57,8 @@ struct Bat {
   int count = 1;
   int per = 0;
   unsigned mask = 0xffffffffu;
+  unsigned char map[kMaxBatch] = {0,  1,  2,  3,  4,  5,  6,  7,  8,  9,  10, 11, 12, 13, 14, 15,
+                                  16, 17, 18, 19, 20, 21, 22, 23, 24, 25, 26, 27, 28, 29, 30, 31};
   double s[kMaxBatch] = {};
   double s2[kMaxBatch] = {};
   double s3[kMaxBatch] = {};
@@ -94,18 +99,20 @@ __host__ __device__ inline GivLayout giv_layout(int m) {
 }
 constexpr int kGivEnded = 0, kGivCols = 1, kGivTol = 2, kGivLim = 3, kGivResid = 4, kGivNonfinite = 5;
 
-// instance of this workgroup and its position along the instance's own part of z
-__device__ inline int bat_inst(const Bat& bt) { return (int)(blockIdx.z / (gridDim.z / (unsigned)bt.count)); }
-__device__ inline int bat_z(const Bat& bt) { return (int)(blockIdx.z % (gridDim.z / (unsigned)bt.count)); }
-__device__ inline int bat_nz(const Bat& bt) { return (int)(gridDim.z / (unsigned)bt.count); }
+// instance of this workgroup
+__device__ inline int bat_inst(const Bat& bt) { return bt.map[blockIdx.z / (gridDim.z / (unsigned)bt.count)]; }
 __device__ inline bool bat_skip(const Bat& bt, int b) { return ((bt.mask >> b) & 1u) == 0u; }
 __device__ inline double bat_s(const Bat& bt, int b, double v) { return bt.per ? bt.s[b] : v; }
 
 // Allow a kernel the largest dynamic LDS of one workgroup (160 KiB); its launches then ask for
-// what they need.  Called once per kernel through a function-local static at the launch site
-// (thread-safe initialisation), not on every launch.
-inline bool allow_max_lds(const void* kernel) {
-  return hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) == hipSuccess;
+// what they need.  The attribute is set once per kernel (a set of the kernels already done,
+// behind a mutex: launch sites run on several host threads), not on every launch.
+inline void allow_max_lds(const void* kernel) {
+  static std::mutex mu;
+  static std::unordered_set<const void*> done;
+  std::lock_guard<std::mutex> lock(mu);
+  if (done.insert(kernel).second)
+    (void)hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
 }
 
 // ---- phase-field kernels (kernels_phase.hip) ---------------------------------------

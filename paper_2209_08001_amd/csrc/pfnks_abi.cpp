@@ -1127,14 +1127,18 @@ struct pfnks_group {
 
 namespace {
 
-// launch descriptor over the instances in mask: the per-instance scalar is the time step
+// launch descriptor over the instances in mask (only those are launched: the grid's z parts
+// map to them in order); the per-instance scalar is the time step
 pf::Bat gbat(const pfnks_group* G, unsigned mask) {
   pf::Bat b;
   b.stride = G->stride;
   b.hstride = (long long)sizeof(double) * kHostSlot;
-  b.count = G->count;
   b.per = 1;
   b.mask = mask;
+  b.count = 0;
+  for (int i = 0; i < G->count; ++i)
+    if ((mask >> i) & 1u) b.map[b.count++] = (unsigned char)i;
+  if (b.count == 0) b.count = 1;  // an empty launch: its one part has a clear mask bit and returns
   for (int i = 0; i < G->count; ++i) {
     b.s[i] = G->dt[i];
     b.cb[i] = G->cbar0[i];
@@ -1544,6 +1548,31 @@ int pfnks_group_step(pfnks_group* G, const double* dts, pfnks_step_stats* stats,
     if (first == PFNKS_OK && st[i].status != PFNKS_OK) first = st[i].status;
   }
   return first;
+}
+
+int pfnks_group_set_instance(pfnks_group* G, int i, const double* c0, const double* eta0) {
+  if (!G || !c0 || !eta0 || i < 0 || i >= G->count) return PFNKS_EINVAL;
+  pfnks_problem* p = G->p;
+  const long long N = p->N;
+  int st = check_domain_host(c0, eta0, N);
+  if (st) return st;
+  HIPCHK(hipStreamSynchronize(p->stream));
+  double* Xn = pf::bat_at(p->Xn, i * G->stride);
+  HIPCHK(hipMemcpyAsync(Xn, c0, sizeof(double) * N, hipMemcpyHostToDevice, p->stream));
+  HIPCHK(hipMemcpyAsync(Xn + N, eta0, sizeof(double) * 3 * N, hipMemcpyHostToDevice, p->stream));
+  HIPCHK(hipMemsetAsync(Xn + 4 * N, 0, sizeof(double) * p->grid.dim * N, p->stream));
+  // its mean composition, then u0 from the discrete equilibrium at c0 (as at creation)
+  const pf::Bat bi = gbat(G, 1u << i);
+  pf::launch_sum2(N, p->Xn, p->Xn, p->Xn, p->part, p->stream, bi);
+  pf::launch_finalize(p->part, 1, p->red, p->stream, G->hs, bi);
+  st = gsync(G);
+  if (st) return st;
+  G->cbar0[i] = gslot(G, i)[0] / (double)N;
+  pf::launch_spectral_solve<double>(p->K, p->plan, nullptr, p->K.eps0 * p->K.Ctr, p->Xn, p->fft0, p->fft1,
+                                    p->Xn + 4 * N, p->stream, gbat(G, 1u << i));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  G->t[i] = 0.0;
+  return PFNKS_OK;
 }
 
 int pfnks_group_get_state(pfnks_group* G, int i, double* X, double* t) {

@@ -37,7 +37,7 @@ EXPORTED = [
     "pfnks_debug_residual", "pfnks_debug_jv", "pfnks_debug_pc", "pfnks_debug_counters",
     "pfnks_debug_profile", "pfnks_debug_kernel_time", "pfnks_batch_step", "pfnks_residual_static",
     "pfnks_group_workspace_bytes", "pfnks_group_create", "pfnks_group_step", "pfnks_group_get_state",
-    "pfnks_group_counters", "pfnks_group_destroy",
+    "pfnks_group_counters", "pfnks_group_destroy", "pfnks_group_set_instance",
 ]
 
 MAX_GROUP = 32  # instances of one lockstep group
@@ -134,6 +134,7 @@ def load():
                                        ctypes.POINTER(P)]
     lib.pfnks_group_step.argtypes = [P, dp, ctypes.POINTER(pfnks_step_stats), ctypes.POINTER(ctypes.c_int)]
     lib.pfnks_group_get_state.argtypes = [P, ctypes.c_int, dp, dp]
+    lib.pfnks_group_set_instance.argtypes = [P, ctypes.c_int, dp, dp]
     lib.pfnks_group_counters.argtypes = [P, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong)]
     lib.pfnks_group_destroy.argtypes = [P]
     for name in EXPORTED:
@@ -457,6 +458,15 @@ class Group:
         if rc not in (PFNKS_OK, PFNKS_ENOCONV):
             _check(rc, "pfnks_group_step")
         return list(status), [s.as_dict() for s in st]
+
+    def set_instance(self, i, c0, eta0):
+        """A new initial state for instance i (a freed slot taking a new problem)."""
+        c0 = np.ascontiguousarray(c0, dtype=np.float64).ravel()
+        eta0 = np.ascontiguousarray(eta0, dtype=np.float64).ravel()
+        if c0.size != self.N or eta0.size != 3 * self.N:
+            raise ValueError("c0 / eta0 sizes do not match the grid")
+        _check(load().pfnks_group_set_instance(self._h, ctypes.c_int(i), _dp(c0), _dp(eta0)),
+               "pfnks_group_set_instance")
 
     def get_state(self, i):
         X = np.empty((self.nf,) + tuple(reversed(self.n)))

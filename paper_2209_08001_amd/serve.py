@@ -2,18 +2,26 @@
 
 A request asks for `steps` adaptive time steps of one problem (grid, seed, mean
 composition).  Requests wait in arrival order; one is admitted when a slot is free and the
-sum of the resident problems' workspaces (pfnks_workspace_bytes, exact: the library
-allocates nothing else on the device) stays within the HBM budget.  Every tick steps all
-resident requests once together (pfnks_batch_step, one stream per request, each request
-with its own step-size history), so requests join and leave between ticks.  A request's
-result depends only on its own inputs: it is bitwise the result of running it alone.
+resident workspaces (pfnks_workspace_bytes, exact: the library allocates nothing else on the
+device) stay within the HBM budget.  Every tick steps all resident requests once, each with
+its own step-size history, so requests join and leave between ticks.  Two ways to step them:
 
-Latency: each request's own step time, from the start of the tick to the completion of its
-step on its stream (HIP events on that stream), so a small request that finishes early in a
-tick is not charged the tick's slowest member.
+* mode "groups" (default): requests of one grid shape share a lockstep group
+  (pfnks_group_*) of `group_capacity` slots: one launch per kernel and phase for all of
+  them; a freed slot takes the next request of that shape (pfnks_group_set_instance), empty
+  slots sit the step out, and a group is released when its last request leaves.  Each group
+  steps on a host thread and stream of its own.  A request's result is bitwise its result in
+  a group of one (run_alone).
+* mode "threads": every request is a problem of its own (pfnks_batch_step, one stream per
+  request, host threads); a request's result is bitwise its pfnks_step result alone.
+
+Latency: each request's own step time from events on the stream that steps it: from the
+start of the tick to the completion of its accepted step (in a group, of the group's step,
+whose launches the members share).
 """
 
 import time
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
@@ -34,6 +42,7 @@ class Request:
         self.dts = []
         self.retries = 0
         self.stream = None
+        self.slot = None
         self.state = None
         self.t = None
 
@@ -59,11 +68,40 @@ def poisson_requests(rate, window, seed, sides2d, sides3d, frac3d, steps):
     return out
 
 
+class _SlotGroup:
+    """A lockstep group of one grid shape whose slots requests occupy and leave."""
+
+    def __init__(self, n, solver, capacity, c0, e0, device):
+        import torch
+
+        self.n = tuple(n)
+        self.stream = torch.cuda.Stream(device=device)
+        # every slot starts as a copy of the first request's fields; set_instance gives each
+        # slot its own request when it is taken
+        self.group = pfnks.Group(self.n, W.H, W.DEFAULT_MODEL, solver, [c0] * capacity, [e0] * capacity,
+                                 device=device, stream=self.stream)
+        self.slots = [None] * capacity
+
+    def free_slot(self):
+        for i, r in enumerate(self.slots):
+            if r is None:
+                return i
+        return -1
+
+    def occupied(self):
+        return [r for r in self.slots if r is not None]
+
+
 class Server:
-    def __init__(self, solver, wl, hbm_budget, max_resident=64, threads=16, device="cuda:0", keep_state=False):
+    def __init__(self, solver, wl, hbm_budget, max_resident=64, threads=16, device="cuda:0", keep_state=False,
+                 mode="groups", group_capacity=8):
         self.solver, self.wl, self.budget = solver, wl, hbm_budget
         self.max_resident, self.threads, self.device = max_resident, threads, device
         self.keep_state = keep_state
+        if mode not in ("groups", "threads"):
+            raise ValueError("mode is 'groups' or 'threads'")
+        self.mode = mode
+        self.group_capacity = max(1, min(int(group_capacity), pfnks.MAX_GROUP))
 
     def _solver_for(self, n):
         sv = dict(self.solver)
@@ -83,6 +121,100 @@ class Server:
     def run(self, requests, realtime=True):
         """Serve the requests (arrival times in seconds from the start); returns them with
         their records filled (queue wait, per-step latency, final state if keep_state)."""
+        if self.mode == "groups":
+            return self._run_groups(requests, realtime)
+        return self._run_threads(requests, realtime)
+
+    def _run_groups(self, requests, realtime):
+        import torch
+
+        pending = sorted(requests, key=lambda r: r.arrival)
+        one = {r.rid: self.bytes_for(r) for r in pending}
+        for r in pending:
+            if one[r.rid] * self.group_capacity > self.budget:
+                raise ValueError(f"a group of request {r.rid}'s shape needs {one[r.rid] * self.group_capacity} B, "
+                                 "more than the HBM budget")
+        groups, used, nres = [], 0, 0
+        t_start = time.perf_counter()
+        now = lambda: (time.perf_counter() - t_start) if realtime else float("inf")
+        pool = ThreadPoolExecutor(max_workers=max(1, self.threads))
+
+        def admit(r):
+            nonlocal used, nres
+            g = next((g for g in groups if g.n == r.n and g.free_slot() >= 0), None)
+            need = one[r.rid] * self.group_capacity
+            if g is None and used + need > self.budget:
+                return False
+            c0, e0 = W.init_fields(r.n, r.seed, cbar=r.cbar)
+            if g is None:
+                g = _SlotGroup(r.n, self._solver_for(r.n), self.group_capacity, c0, e0, self.device)
+                groups.append(g)
+                used += need
+            i = g.free_slot()
+            g.group.set_instance(i, c0, e0)
+            g.slots[i] = r
+            r.slot = (g, i)
+            r.clock = _Clock(self.wl)
+            r.admitted_at = now() if realtime else 0.0
+            nres += 1
+            return True
+
+        def tick(g):
+            # one accepted step of every request in the group: the others sit out (dt = 0)
+            # while failed ones retry with their smaller dt
+            members = {i: r for i, r in enumerate(g.slots) if r is not None}
+            ev0 = torch.cuda.Event(enable_timing=True)
+            ev0.record(g.stream)
+            dts = {i: r.clock.next_dt() for i, r in members.items()}
+            todo = set(members)
+            while todo:
+                status, st = g.group.step([dts[i] if i in todo else 0.0 for i in range(len(g.slots))])
+                for i in sorted(todo):
+                    r = members[i]
+                    if status[i] == pfnks.PFNKS_OK:
+                        r.clock.accepted(st[i], dts[i])
+                        r.dts.append(dts[i])
+                        r.done += 1
+                        todo.discard(i)
+                    else:
+                        dts[i] = r.clock.failed(dts[i])
+                        r.retries += 1
+            ev1 = torch.cuda.Event(enable_timing=True)
+            ev1.record(g.stream)
+            ev1.synchronize()
+            ms = ev0.elapsed_time(ev1)
+            for r in members.values():
+                r.step_ms.append(ms)
+
+        try:
+            while pending or nres:
+                while pending and pending[0].arrival <= now() and nres < self.max_resident and admit(pending[0]):
+                    pending.pop(0)
+                if not nres:
+                    time.sleep(max(0.0, min(0.05, pending[0].arrival - now())))
+                    continue
+                live = [g for g in groups if g.occupied()]
+                for f in [pool.submit(tick, g) for g in live]:
+                    f.result()
+                # retire finished requests; release groups that have emptied
+                for g in live:
+                    for i, r in enumerate(g.slots):
+                        if r is not None and r.done >= r.steps:
+                            r.finished_at = now() if realtime else 0.0
+                            if self.keep_state:
+                                r.state, r.t = g.group.get_state(i)
+                            g.slots[i] = None
+                            r.slot = None
+                            nres -= 1
+                    if not g.occupied():
+                        g.group.close()
+                        groups.remove(g)
+                        used -= one_shape_bytes(self, g.n) * self.group_capacity
+        finally:
+            pool.shutdown()
+        return requests
+
+    def _run_threads(self, requests, realtime):
         import torch
 
         pending = sorted(requests, key=lambda r: r.arrival)
@@ -152,10 +284,29 @@ class Server:
         return requests
 
 
-def run_alone(r, solver_for, wl, device="cuda:0"):
-    """The same request stepped by itself (reference for the alone-versus-mix check); returns
-    its final state and time."""
+def one_shape_bytes(server, n):
+    return pfnks.workspace_bytes(tuple(n), W.H, W.DEFAULT_MODEL, server._solver_for(tuple(n)))
+
+
+def run_alone(r, solver_for, wl, device="cuda:0", mode="threads"):
+    """The same request stepped by itself (reference for the alone-versus-mix check): a single
+    problem (mode "threads") or a group of one (mode "groups"); returns its final state and
+    time."""
     c0, e0 = W.init_fields(r.n, r.seed, cbar=r.cbar)
+    if mode == "groups":
+        g = pfnks.Group(r.n, W.H, W.DEFAULT_MODEL, solver_for(r.n), [c0], [e0], device=device)
+        clk = _Clock(wl)
+        for _ in range(r.steps):
+            dt = clk.next_dt()
+            while True:
+                status, st = g.step([dt])
+                if status[0] == pfnks.PFNKS_OK:
+                    break
+                dt = clk.failed(dt)
+            clk.accepted(st[0], dt)
+        X, t = g.get_state(0)
+        g.close()
+        return X, t
     p = pfnks.Problem(r.n, W.H, W.DEFAULT_MODEL, solver_for(r.n), c0, e0, device=device)
     clk = _Clock(wl)
     for _ in range(r.steps):

@@ -392,31 +392,37 @@ def test_batch_step_equals_single_and_oracle(oracle_c1):
         p.close()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_serving_alone_equals_mix(prec):
+@pytest.mark.parametrize("mode,prec", [("threads", "fp64"), ("threads", "mixed"), ("groups", "fp64"),
+                                       ("groups", "mixed")])
+def test_serving_alone_equals_mix(mode, prec):
     """Continuous batching: requests of different sizes (2D and 3D, sides that are and are not
-    powers of two), admitted under an HBM budget that holds only some of them at once, joining
-    and leaving between ticks; every request's final state is bitwise the state of the same
-    request run alone, and within 1e-8 of the oracle's roots taken with the request's own step
-    sizes.  Every request records one latency per step, each at most the tick's wall time."""
+    powers of two, several of one shape), admitted under an HBM budget that holds only some of
+    them at once, joining and leaving between ticks; every request's final state is bitwise
+    the state of the same request run alone (a single problem, or in the group mode a group of
+    one: an instance's arithmetic does not depend on the other members of its group), and
+    within 1e-8 of the oracle's roots taken with the request's own step sizes.  Every request
+    records one latency per step.  In the group mode two slots per shape: the third request of
+    a shape waits for a slot, which a finished request frees."""
     from paper_2209_08001_amd import pfnks
     from paper_2209_08001_amd.serve import Request, Server, run_alone
 
     _cuda()
-    _note(f"serving alone vs mix vs oracle precision={prec}")
+    _note(f"serving alone vs mix vs oracle mode={mode} precision={prec}")
     wl = dict(W.WORKLOADS["serve_mix"])
     reqs = [Request(0, (32, 32), 11, 0.15, 3), Request(1, (48, 48), 12, 0.17, 3),
             Request(2, (8, 8, 8), 13, 0.19, 2), Request(3, (32, 48), 14, 0.16, 3),
-            Request(4, (24, 40), 15, 0.2, 3)]
+            Request(4, (24, 40), 15, 0.2, 3), Request(5, (32, 32), 16, 0.14, 2),
+            Request(6, (32, 32), 17, 0.18, 4), Request(7, (24, 40), 18, 0.16, 2)]
     sv = dict(W.DEFAULT_SOLVER, precision=pfnks.MIXED if prec == "mixed" else pfnks.FP64)
-    srv = Server(sv, wl, hbm_budget=0, keep_state=True, threads=4)
+    srv = Server(sv, wl, hbm_budget=0, keep_state=True, threads=4, mode=mode, group_capacity=2)
     need = sorted(srv.bytes_for(r) for r in reqs)
-    srv.budget = need[-1] + need[-2]  # at most two of the largest resident at once
+    # threads: at most two of the largest resident at once; groups: two groups of the largest
+    srv.budget = need[-1] + need[-2] if mode == "threads" else 2 * (need[-1] + need[-2])
     srv.run(reqs, realtime=False)
     for r in reqs:
         assert r.done == r.steps and len(r.step_ms) == r.steps and len(r.dts) == r.steps
         assert all(x > 0.0 for x in r.step_ms)
-        Xa, ta = run_alone(r, srv._solver_for, wl)
+        Xa, ta = run_alone(r, srv._solver_for, wl, mode=mode)
         assert np.array_equal(r.state, Xa) and r.t == ta, r.rid
         c0, e0 = W.init_fields(r.n, r.seed, cbar=r.cbar)
         o = Oracle(r.n, W.H, W.DEFAULT_MODEL, c0, e0)
