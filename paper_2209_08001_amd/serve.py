@@ -10,8 +10,10 @@ its own step-size history, so requests join and leave between ticks.  Two ways t
   (pfnks_group_*) of `group_capacity` slots: one launch per kernel and phase for all of
   them; a freed slot takes the next request of that shape (pfnks_group_set_instance), empty
   slots sit the step out, and a group is released when its last request leaves.  Each group
-  steps on a host thread and stream of its own.  A request's result is bitwise its result in
-  a group of one (run_alone).
+  steps on a host thread and stream of its own.  A shape's group takes at most group_share of
+  the HBM budget (an eighth by default: fewer slots for large grids), and a new group is created only when the device
+  also has the memory free.  A request's result is bitwise its result in a group of one
+  (run_alone).
 * mode "threads": every request is a problem of its own (pfnks_batch_step, one stream per
   request, host threads); a request's result is bitwise its pfnks_step result alone.
 
@@ -71,10 +73,11 @@ def poisson_requests(rate, window, seed, sides2d, sides3d, frac3d, steps):
 class _SlotGroup:
     """A lockstep group of one grid shape whose slots requests occupy and leave."""
 
-    def __init__(self, n, solver, capacity, c0, e0, device):
+    def __init__(self, n, solver, capacity, c0, e0, device, nbytes):
         import torch
 
         self.n = tuple(n)
+        self.nbytes = nbytes  # the group's workspace
         self.stream = torch.cuda.Stream(device=device)
         # every slot starts as a copy of the first request's fields; set_instance gives each
         # slot its own request when it is taken
@@ -94,7 +97,7 @@ class _SlotGroup:
 
 class Server:
     def __init__(self, solver, wl, hbm_budget, max_resident=64, threads=16, device="cuda:0", keep_state=False,
-                 mode="groups", group_capacity=8):
+                 mode="groups", group_capacity=8, group_share=0.125):
         self.solver, self.wl, self.budget = solver, wl, hbm_budget
         self.max_resident, self.threads, self.device = max_resident, threads, device
         self.keep_state = keep_state
@@ -102,6 +105,7 @@ class Server:
             raise ValueError("mode is 'groups' or 'threads'")
         self.mode = mode
         self.group_capacity = max(1, min(int(group_capacity), pfnks.MAX_GROUP))
+        self.group_share = group_share  # largest fraction of the budget one group may take
 
     def _solver_for(self, n):
         sv = dict(self.solver)
@@ -125,15 +129,21 @@ class Server:
             return self._run_groups(requests, realtime)
         return self._run_threads(requests, realtime)
 
+    def capacity_for(self, nbytes_one):
+        """Slots of a new group: group_capacity, fewer for large grids (a group takes at most
+        group_share of the budget), at least one."""
+        return max(1, min(self.group_capacity, int(self.budget * self.group_share // max(nbytes_one, 1))))
+
     def _run_groups(self, requests, realtime):
+        import gc
+
         import torch
 
         pending = sorted(requests, key=lambda r: r.arrival)
         one = {r.rid: self.bytes_for(r) for r in pending}
         for r in pending:
-            if one[r.rid] * self.group_capacity > self.budget:
-                raise ValueError(f"a group of request {r.rid}'s shape needs {one[r.rid] * self.group_capacity} B, "
-                                 "more than the HBM budget")
+            if one[r.rid] > self.budget:
+                raise ValueError(f"request {r.rid} needs {one[r.rid]} B, more than the HBM budget")
         groups, used, nres = [], 0, 0
         t_start = time.perf_counter()
         now = lambda: (time.perf_counter() - t_start) if realtime else float("inf")
@@ -142,12 +152,22 @@ class Server:
         def admit(r):
             nonlocal used, nres
             g = next((g for g in groups if g.n == r.n and g.free_slot() >= 0), None)
-            need = one[r.rid] * self.group_capacity
-            if g is None and used + need > self.budget:
-                return False
+            cap = self.capacity_for(one[r.rid])
+            need = one[r.rid] * cap
+            if g is None:
+                if used + need > self.budget:
+                    return False
+                # the device must hold it too (released workspaces are collected first)
+                if torch.cuda.mem_get_info(self.device)[0] < need + (1 << 30):
+                    gc.collect()
+                    torch.cuda.empty_cache()
+                    if torch.cuda.mem_get_info(self.device)[0] < need + (1 << 30):
+                        if nres:
+                            return False
+                        raise RuntimeError(f"request {r.rid}: {need} B of workspace do not fit on the device")
             c0, e0 = W.init_fields(r.n, r.seed, cbar=r.cbar)
             if g is None:
-                g = _SlotGroup(r.n, self._solver_for(r.n), self.group_capacity, c0, e0, self.device)
+                g = _SlotGroup(r.n, self._solver_for(r.n), cap, c0, e0, self.device, need)
                 groups.append(g)
                 used += need
             i = g.free_slot()
@@ -209,7 +229,7 @@ class Server:
                     if not g.occupied():
                         g.group.close()
                         groups.remove(g)
-                        used -= one_shape_bytes(self, g.n) * self.group_capacity
+                        used -= g.nbytes
         finally:
             pool.shutdown()
         return requests
@@ -282,10 +302,6 @@ class Server:
                     still.append(r)
             resident = still
         return requests
-
-
-def one_shape_bytes(server, n):
-    return pfnks.workspace_bytes(tuple(n), W.H, W.DEFAULT_MODEL, server._solver_for(tuple(n)))
 
 
 def run_alone(r, solver_for, wl, device="cuda:0", mode="threads"):

@@ -217,3 +217,6 @@ def test_group_rejects_on_host():
     c[1, 77] = 1.5  # the second instance leaves the log domain
     assert create(c, e0) == (pfnks.PFNKS_EDOMAIN, None)
     assert lib.pfnks_group_step(None, None, None, None) == pfnks.PFNKS_EINVAL
+    assert lib.pfnks_group_set_instance(None, 0, None, None) == pfnks.PFNKS_EINVAL
+    assert lib.pfnks_group_get_state(None, 0, None, None) == pfnks.PFNKS_EINVAL
+    assert lib.pfnks_group_destroy(None) == pfnks.PFNKS_EINVAL

@@ -414,7 +414,7 @@ def test_serving_alone_equals_mix(mode, prec):
             Request(4, (24, 40), 15, 0.2, 3), Request(5, (32, 32), 16, 0.14, 2),
             Request(6, (32, 32), 17, 0.18, 4), Request(7, (24, 40), 18, 0.16, 2)]
     sv = dict(W.DEFAULT_SOLVER, precision=pfnks.MIXED if prec == "mixed" else pfnks.FP64)
-    srv = Server(sv, wl, hbm_budget=0, keep_state=True, threads=4, mode=mode, group_capacity=2)
+    srv = Server(sv, wl, hbm_budget=0, keep_state=True, threads=4, mode=mode, group_capacity=2, group_share=1.0)
     need = sorted(srv.bytes_for(r) for r in reqs)
     # threads: at most two of the largest resident at once; groups: two groups of the largest
     srv.budget = need[-1] + need[-2] if mode == "threads" else 2 * (need[-1] + need[-2])
