@@ -186,7 +186,8 @@ int pfnks_batch_step(pfnks_problem* const* problems, int k, const double* dts, i
  * cycle end for all instances together.  Each instance follows the iteration pfnks_step
  * would take on it alone (its own dt, Newton and GMRES counts, line search and stop rule);
  * the results agree with pfnks_step's to rounding (the rotations are computed on the device
- * instead of the host).
+ * instead of the host).  An instance's arithmetic does not depend on the other members: its
+ * result is bitwise its result in a group of one.
  * The workspace (device, 256-byte aligned, caller-owned, kept alive until
  * pfnks_group_destroy) holds count copies of the single-problem layout, instance i at
  * i * pfnks_workspace_bytes bytes.  c0: count * N doubles, eta0: count * 3 N doubles
