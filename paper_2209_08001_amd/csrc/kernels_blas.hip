@@ -436,6 +436,14 @@ __global__ __launch_bounds__(kRedBlocks) void k_arnoldi(const double* __restrict
   const GivLayout L = giv_layout(m);
   double* st = giv + L.st;
   if (st[kGivEnded] != 0.0) return;
+  // what thread 0's rotation step reads from the state, loaded before anything is stored to
+  // it (the loads then overlap the reduction instead of waiting behind the stores)
+  double gj = 0.0, tol = 0.0, lim = 0.0;
+  if (threadIdx.x == 0) {
+    gj = giv[L.g + j];
+    tol = st[kGivTol];
+    lim = st[kGivLim];
+  }
   const int nvals = j + 2;
   __shared__ double wl[kRedBlocks / 64][MAXV];
   __shared__ double col[MAXV];
@@ -490,20 +498,19 @@ __global__ __launch_bounds__(kRedBlocks) void k_arnoldi(const double* __restrict
   giv[L.sn + j] = s_;
   h[j] = r;
   h[j + 1] = 0.0;
-  const double gj = g[j];
   g[j + 1] = -s_ * gj;
   g[j] = c_ * gj;
   const double resid = fabs(-s_ * gj);
   const bool nonfinite = !isfinite(resid);
-  const bool ended = nonfinite || resid <= st[kGivTol] || cancel || hnext == 0.0 || (double)(j + 1) >= st[kGivLim];
+  const bool ended = nonfinite || resid <= tol || cancel || hnext == 0.0 || (double)(j + 1) >= lim;
   st[kGivEnded] = ended ? 1.0 : 0.0;
   st[kGivCols] = (double)(j + 1);
   st[kGivResid] = resid;
   st[kGivNonfinite] = nonfinite ? 1.0 : 0.0;
-  host[0] = st[kGivEnded];
+  host[0] = ended ? 1.0 : 0.0;
   host[1] = resid;
   host[2] = (double)(j + 1);
-  host[3] = st[kGivNonfinite];
+  host[3] = nonfinite ? 1.0 : 0.0;
 }
 
 // start of a cycle, per instance: g = beta e_1 (beta = bt.s), tolerance bt.s2, column limit
