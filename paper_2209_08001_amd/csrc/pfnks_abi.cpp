@@ -573,9 +573,14 @@ int gmres(pfnks_problem* p, double dt, const double* Bm, double fnorm, double to
     // S += Z y
     pf::launch_lincomb<T, double>(n, k, Z, n, y.data(), 1.0, p->S, p->stream);
     p->launches += 1;
-    // the true residual r = -F - J S decides convergence (the Hessenberg estimate can be
-    // optimistic by the rounding of the stored basis, 2^-24 when it is float) and starts the
-    // next cycle
+    // With a double basis the Hessenberg estimate |g_k| is the residual of the correction up
+    // to rounding and decides convergence, as GMRES's recursive residual does.  A float basis
+    // can make it optimistic by its rounding (2^-24), so there the true residual
+    // r = -F - J S decides; a cycle that ends unconverged restarts from the true residual.
+    if (sizeof(T) == sizeof(double) && resid <= tol) {
+      *ok = 1;
+      break;
+    }
     jv<double>(p, dt, Bm, p->S, p->w);
     pf::launch_axpby<double, double, double>(n, -1.0, p->F, -1.0, p->w, p->tmp, p->stream);
     p->launches += 1;
@@ -1268,7 +1273,8 @@ int gmres_group(pfnks_group* G, unsigned act, const double* Bm, const double* fn
         return PFNKS_EDEVICE;
       }
     }
-    // S += Z y per instance, then the true residual r = -F - J S decides and restarts
+    // S += Z y per instance; then the true residual r = -F - J S decides and restarts for the
+    // instances whose estimate does not settle it
     const unsigned fin = live & ~*bad;
     if (fin) {
       int kmax = 1;
@@ -1277,19 +1283,34 @@ int gmres_group(pfnks_group* G, unsigned act, const double* Bm, const double* fn
       const pf::Bat bf = gbat(G, fin);
       pf::launch_ysolve(p->giv, m, p->stream, bf);
       pf::launch_lincomb_dev<T, double>(n, kmax, Z, n, p->giv, m, p->S, p->stream, bf);
-      jv<double>(p, 0.0, Bm, p->S, p->w, bf);
-      pf::launch_axpby<double, double, double>(n, -1.0, p->F, -1.0, p->w, p->tmp, p->stream, gbat_s(G, fin, -1.0));
-      pf::launch_multidot<double>(n, 0, p->tmp, 0, p->tmp, p->part, p->stream, bf);
-      pf::launch_finalize(p->part, 1, p->red, p->stream, G->hs, bf);
-      G->launches += 5;
-      int st = gsync(G);
-      if (st) return st;
+      G->launches += 2;
+      // as in gmres(): with a double basis an instance whose estimate met its tolerance has
+      // converged; the others (and every instance with a float basis) take the true residual
+      unsigned rest = fin;
       for (int i = 0; i < B; ++i) {
         if (!has(fin, i)) continue;
-        beta[i] = std::sqrt(gslot(G, i)[0]);
         total[i] += cols[i];
         its[i] = total[i];
-        if (beta[i] <= tol[i] || total[i] >= maxit) live &= ~(1u << i);
+        if (sizeof(T) == sizeof(double) && gslot(G, i)[kHostGiv + 1] <= tol[i]) {
+          rest &= ~(1u << i);
+          live &= ~(1u << i);
+        }
+      }
+      if (rest) {
+        const pf::Bat br = gbat(G, rest);
+        jv<double>(p, 0.0, Bm, p->S, p->w, br);
+        pf::launch_axpby<double, double, double>(n, -1.0, p->F, -1.0, p->w, p->tmp, p->stream,
+                                                 gbat_s(G, rest, -1.0));
+        pf::launch_multidot<double>(n, 0, p->tmp, 0, p->tmp, p->part, p->stream, br);
+        pf::launch_finalize(p->part, 1, p->red, p->stream, G->hs, br);
+        G->launches += 3;
+        int st = gsync(G);
+        if (st) return st;
+        for (int i = 0; i < B; ++i) {
+          if (!has(rest, i)) continue;
+          beta[i] = std::sqrt(gslot(G, i)[0]);
+          if (beta[i] <= tol[i] || total[i] >= maxit) live &= ~(1u << i);
+        }
       }
     }
     live &= ~*bad;
