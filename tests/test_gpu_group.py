@@ -198,3 +198,37 @@ def test_group_schwarz_variants(pc):
         assert d <= 1e-9 and err <= 1e-8, (i, d, err)
         p.close()
     g.close()
+
+
+@pytest.mark.parametrize("case", ["pc_refresh", "spectral", "none", "3d_fp64"])
+def test_group_solver_options(case):
+    """Solver options in a group: the preconditioner rebuilt at every Newton iteration, the
+    Fourier displacement block alone and no preconditioner (the copies of the unsolved blocks
+    go through the per-instance launch), and 3D in FP64: every member within 1e-9 of the
+    instance stepped alone and within 1e-8 of the oracle's root."""
+    from paper_2209_08001_amd import pfnks
+
+    _cuda()
+    n = (8, 8, 8) if case == "3d_fp64" else (24, 24)
+    kw = {"pc_refresh": dict(pc_refresh=1), "spectral": dict(pc=pfnks.PC_SPECTRAL),
+          "none": dict(pc=pfnks.PC_NONE), "3d_fp64": {}}[case]
+    sv = _solver(n, "fp64", **kw)
+    seeds = (61, 62)
+    dts = (0.002, 0.004) if case == "none" else (0.01, 0.004)
+    fields = [W.init_fields(n, s) for s in seeds]
+    g = pfnks.Group(n, W.H, W.DEFAULT_MODEL, sv, [f[0] for f in fields], [f[1] for f in fields])
+    status, st = g.step(dts)
+    assert all(x == pfnks.PFNKS_OK for x in status), status
+    for i, (c, e) in enumerate(fields):
+        p = pfnks.Problem(n, W.H, W.DEFAULT_MODEL, sv, c, e)
+        sa = p.step(dts[i])
+        assert st[i]["newton_its"] == sa["newton_its"], (i, st[i], sa)
+        Xg, _ = g.get_state(i)
+        Xa, _ = p.get_state()
+        d = max(_relmax(Xg[f], Xa[f]) for f in range(Xg.shape[0]))
+        ref = _oracle_traj(n, seeds[i], (dts[i],))[-1]
+        err = max(_relmax(Xg[f], ref[f]) for f in range(Xg.shape[0]))
+        _note(f"  {case} instance {i}: gmres {st[i]['gmres_its']} vs alone {d:.2e}, vs oracle {err:.2e}")
+        assert d <= 1e-9 and err <= 1e-8, (i, d, err)
+        p.close()
+    g.close()
