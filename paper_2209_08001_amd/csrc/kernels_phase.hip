@@ -460,65 +460,8 @@ __global__ __launch_bounds__(256) void k_linearise(Consts K, const double* __res
 //   (Jv)_e = v_e/dt + L_eta (B_e. v - (gamma_eta/2) Lap_h v_e)
 //   (Jv)_u = sum_J Dhat_J sigma_IJ(v_u, v_c)   (composition enters through -eps0 v_c)
 // ---------------------------------------------------------------------------------
-// dG_c of the J v product at point p (p may lie one node outside the block: wrapped here)
-template <bool P2, int DIM, typename Tv>
-__device__ inline double jv_dg(const Consts& K, const double* __restrict__ B, const Tv* __restrict__ v, Pt p) {
-  const long long N = K.N, n = lin(K, p);
-  double vv[4];
-#pragma unroll
-  for (int f = 0; f < 4; ++f) vv[f] = v[f * N + n];
-  double g = K.kel * vv[0] - 0.5 * K.gamma_c * lap<P2>(K, v, p, vv[0]);
-#pragma unroll
-  for (int f = 0; f < 4; ++f) g += B[f * N + n] * vv[f];
-  if (K.elastic) {
-    double div = 0.0;
-#pragma unroll
-    for (int I = 0; I < DIM; ++I) div += dhat<P2>(K, v + (4 + I) * N, p, I);
-    g += -0.5 * K.eps0 * K.Ctr * div;
-  }
-  return g;
-}
-
-// the rows of J v at p: the c row from dG in LDS (sdg[hq], its neighbours in direction dir at
-// sdg[hq + up[dir]] and sdg[hq + dn[dir]]), the eta and u rows as local stencils
-template <bool P2, int DIM, typename Tv>
-__device__ inline void jv_rows(const Consts& K, double idt, const double* __restrict__ B,
-                               const double* __restrict__ cn, const Tv* __restrict__ v,
-                               double* __restrict__ w, Pt p, const double* sdg, int hq, const int* up,
-                               const int* dn) {
-  const long long N = K.N, n = lin(K, p);
-  {
-    const double mc = cn[n] * (1.0 - cn[n]);
-    const double g0 = sdg[hq];
-    double s = 0.0;
-#pragma unroll
-    for (int dir = 0; dir < DIM; ++dir) {
-      const long long np = at_dir<P2>(K, p, dir, 1), nm = at_dir<P2>(K, p, dir, -1);
-      const double Mp = 0.5 * K.kappa * (mc + cn[np] * (1.0 - cn[np]));
-      const double Mm = 0.5 * K.kappa * (mc + cn[nm] * (1.0 - cn[nm]));
-      s += Mp * (sdg[hq + up[dir]] - g0) - Mm * (g0 - sdg[hq + dn[dir]]);
-    }
-    w[n] = (double)v[n] * idt - s * K.ih2;
-  }
-  double vv[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) vv[q] = v[q * N + n];
-#pragma unroll
-  for (int e = 0; e < 3; ++e) {
-    double s = -0.5 * K.gamma_eta * lap<P2>(K, v + (1 + e) * N, p, vv[1 + e]);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) s += B[(4 * (1 + e) + q) * N + n] * vv[q];
-    w[(1 + e) * N + n] = vv[1 + e] * idt + K.L_eta * s;
-  }
-#pragma unroll
-  for (int I = 0; I < DIM; ++I) {
-    w[(4 + I) * N + n] = K.elastic ? div_sigma<P2>(K, v + 4 * N, N, v, 0.0, p, I) : (double)v[(4 + I) * N + n];
-  }
-}
-
 // J v in 2D, one pass: a block of kBX x kJY2 nodes stages v in LDS, computes dG on the block
-// and a halo of one node into LDS, and forms the c, eta and u rows from LDS (the same
-// arithmetic as jv_dg / jv_rows, which the 3D kernel uses on global memory).  v has element
+// and a halo of one node into LDS, and forms the c, eta and u rows from LDS.  v has element
 // type Tv (double, or float for a mixed-precision Krylov vector); the arithmetic and w are
 // double.
 constexpr int kJY2 = 8;
@@ -634,16 +577,173 @@ __global__ __launch_bounds__(kBX* kJY2) void k_jv2(Consts K, double dt, const do
   }
 }
 
-// J v in 3D: a block of kBX x kBY columns marches through kJZ planes in z, keeping three
-// planes of dG (with their one-node halo in x and y) in LDS, so dG is formed once per node
-// and halo column instead of once per node of a 3 x 3 x 3 neighbourhood.
-constexpr int kJZ = 4;
+// J v in 3D in two passes over blocks of kBX x kJY3 columns marching through a chunk of planes.
+// Each thread keeps its column's values at z - 1, z and z + 1 in registers; the x and y
+// neighbours come from the current plane, staged in LDS with a ring of one node (the in-plane
+// stencils are five-point crosses, so the ring's corners are never read).
+//   pass A (k_jv3_dg):   dG of the c row and the stress sigma_IJ(v_u, v_c) at every node, into
+//                        seven scratch planes: dG, s_xx, s_yy, s_zz, s_xy, s_xz, s_yz;
+//   pass B (k_jv3_rows): the c row from dG and g = c^n (1 - c^n), the eta rows, and the u rows
+//                        as sum_J Dhat_J sigma_IJ of the stored stress.
+// Each pass reads every input plane once (plus the ring, shared with the neighbouring blocks
+// through L2, and two planes per chunk in z), so neither re-reads the 3 x 3 x 3 neighbourhood
+// the single-pass stencil needs for sigma at distance two.
+constexpr int kJY3 = 4;   // block rows
+constexpr int kJZ3 = 8;   // planes per chunk
+constexpr int kRX3 = kBX + 2, kRP3 = kRX3 * (kJY3 + 2);
+constexpr int kRing3 = 2 * kBX + 2 * kJY3;
+
+// ring slot r of the staged plane: its offset (a, b) from the block origin and LDS index
+__device__ inline int ring_slot(int r, int& a, int& b) {
+  if (r < kBX) {
+    a = r;
+    b = -1;
+  } else if (r < 2 * kBX) {
+    a = r - kBX;
+    b = kJY3;
+  } else if (r < 2 * kBX + kJY3) {
+    a = -1;
+    b = r - 2 * kBX;
+  } else {
+    a = kBX;
+    b = r - 2 * kBX - kJY3;
+  }
+  return (a + 1) + kRX3 * (b + 1);
+}
+
+// the column of a thread and, for the first kRing3 threads, of a ring slot (wrapped: threads
+// outside a ragged grid stage the periodic image their neighbours read)
+struct Cols3 {
+  long long col, rcol;
+  int slot, rslot;
+};
+template <bool P2, bool FAR>
+__device__ inline Cols3 cols3(const Consts& K, int i0, int j0) {
+  Cols3 c;
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + kBX * ty;
+  c.col = wrap_t<P2, FAR>(i0 + tx, K.nx) + (long long)K.nx * wrap_t<P2, FAR>(j0 + ty, K.ny);
+  c.slot = (tx + 1) + kRX3 * (ty + 1);
+  c.rslot = -1;
+  c.rcol = 0;
+  if (tid < kRing3) {
+    int a, b;
+    c.rslot = ring_slot(tid, a, b);
+    c.rcol = wrap_t<P2, FAR>(i0 + a, K.nx) + (long long)K.nx * wrap_t<P2, FAR>(j0 + b, K.ny);
+  }
+  return c;
+}
+
 template <typename Tv, bool P2, bool FAR>
-__global__ __launch_bounds__(kBX* kBY) void k_jv3(Consts K, double dt, const double* __restrict__ B,
-                                                  const double* __restrict__ cn, const Tv* __restrict__ v,
-                                                  double* __restrict__ w, int zc, Bat bt) {
-  constexpr int HX = kBX + 2, HY = kBY + 2, HP = HX * HY;
-  __shared__ double sdg[3 * HP];
+__global__ __launch_bounds__(kBX* kJY3) void k_jv3_dg(Consts K, const double* __restrict__ B,
+                                                      const Tv* __restrict__ v, double* __restrict__ scr,
+                                                      int zc, Bat bt) {
+  // staged fields: v_c, u_x, u_y, u_z (field f of v at plane offset fo[f] * N)
+  __shared__ Tv sp[4 * kRP3];
+  int bx, by, bz;
+  const int bi = xcd_block(bt, bx, by, bz);
+  if (bat_skip(bt, bi)) return;
+  {
+    const long long bo = bi * bt.stride;
+    B = bat_at(B, bo);
+    v = bat_at(v, bo);
+    scr = bat_at(scr, bo);
+  }
+  const long long N = K.N, NP = (long long)K.nx * K.ny;
+  const int i0 = bx * kBX, j0 = by * kJY3, z0 = bz * zc;
+  const int z1 = (z0 + zc < K.nz) ? z0 + zc : K.nz;
+  const Cols3 c = cols3<P2, FAR>(K, i0, j0);
+  const bool live = (i0 + (int)threadIdx.x < K.nx) && (j0 + (int)threadIdx.y < K.ny);
+  const int fo[4] = {0, 4, 5, 6};
+  auto plane = [&](int z) { return NP * wrap_t<P2, FAR>(z, K.nz); };
+  double prv[4], cur[4], nxt[4];
+  {
+    const long long pm = plane(z0 - 1) + c.col, p0 = plane(z0) + c.col;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      prv[f] = (double)v[fo[f] * N + pm];
+      cur[f] = (double)v[fo[f] * N + p0];
+    }
+  }
+  for (int z = z0; z < z1; ++z) {
+    const long long pz = plane(z), n = pz + c.col, np = plane(z + 1) + c.col;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) nxt[f] = (double)v[fo[f] * N + np];
+    Tv ring[4];
+    if (c.rslot >= 0) {
+#pragma unroll
+      for (int f = 0; f < 4; ++f) ring[f] = v[fo[f] * N + pz + c.rcol];
+    }
+    double ve[3], bc[4];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) ve[e] = (double)v[(1 + e) * N + n];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) bc[f] = B[f * N + n];
+    __syncthreads();  // every thread is done reading the previous plane
+#pragma unroll
+    for (int f = 0; f < 4; ++f) sp[f * kRP3 + c.slot] = (Tv)cur[f];
+    if (c.rslot >= 0) {
+#pragma unroll
+      for (int f = 0; f < 4; ++f) sp[f * kRP3 + c.rslot] = ring[f];
+    }
+    __syncthreads();
+    if (live) {
+      const int q = c.slot;
+      // Dhat_K u_L at the node: du[K][L]
+      double du[3][3];
+#pragma unroll
+      for (int L = 0; L < 3; ++L) {
+        const Tv* s = sp + (1 + L) * kRP3;
+        du[0][L] = ((double)s[q + 1] - (double)s[q - 1]) * K.i2h;
+        du[1][L] = ((double)s[q + kRX3] - (double)s[q - kRX3]) * K.i2h;
+        du[2][L] = (nxt[1 + L] - prv[1 + L]) * K.i2h;
+      }
+      const double vc = cur[0];
+      double lp = 0.0;
+      lp += (double)sp[q + 1] + (double)sp[q - 1];
+      lp += (double)sp[q + kRX3] + (double)sp[q - kRX3];
+      lp += nxt[0] + prv[0];
+      lp = (lp - 6.0 * vc) * K.ih2;
+      double g = K.kel * vc - 0.5 * K.gamma_c * lp;
+      g += bc[0] * vc;
+#pragma unroll
+      for (int e = 0; e < 3; ++e) g += bc[1 + e] * ve[e];
+      if (K.elastic) {
+        g += -0.5 * K.eps0 * K.Ctr * (du[0][0] + du[1][1] + du[2][2]);
+        const double ec = K.eps0 * vc;
+        double sd[3];
+#pragma unroll
+        for (int I = 0; I < 3; ++I) {
+          double s = 0.0;
+#pragma unroll
+          for (int L = 0; L < 3; ++L) s += (L == I ? K.C11 : K.C12) * (du[L][L] - ec);
+          sd[I] = s;
+        }
+        scr[1 * N + n] = sd[0];
+        scr[2 * N + n] = sd[1];
+        scr[3 * N + n] = sd[2];
+        scr[4 * N + n] = K.C44 * (du[0][1] + du[1][0]);
+        scr[5 * N + n] = K.C44 * (du[0][2] + du[2][0]);
+        scr[6 * N + n] = K.C44 * (du[1][2] + du[2][1]);
+      }
+      scr[n] = g;
+    }
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      prv[f] = cur[f];
+      cur[f] = nxt[f];
+    }
+  }
+}
+
+template <typename Tv, bool P2, bool FAR>
+__global__ __launch_bounds__(kBX* kJY3) void k_jv3_rows(Consts K, double dt, const double* __restrict__ B,
+                                                        const double* __restrict__ cn,
+                                                        const Tv* __restrict__ v,
+                                                        const double* __restrict__ scr,
+                                                        double* __restrict__ w, int zc, Bat bt) {
+  // staged fields: 0 dG, 1 g, 2..4 v_eta, 5 s_xx, 6 s_yy, 7 s_xy, 8 s_xz, 9 s_yz
+  // z-queued fields (registers): 0 dG, 1 g, 2..4 v_eta, 5 s_xz, 6 s_yz, 7 s_zz
+  __shared__ double sp[10 * kRP3];
   int bx, by, bz;
   const int bi = xcd_block(bt, bx, by, bz);
   if (bat_skip(bt, bi)) return;
@@ -652,36 +752,137 @@ __global__ __launch_bounds__(kBX* kBY) void k_jv3(Consts K, double dt, const dou
     B = bat_at(B, bo);
     cn = bat_at(cn, bo);
     v = bat_at(v, bo);
+    scr = bat_at(scr, bo);
     w = bat_at(w, bo);
   }
   dt = bat_s(bt, bi, dt);
-  const int i0 = bx * kBX, j0 = by * kBY, z0 = bz * zc;
-  const int tid = threadIdx.x + kBX * threadIdx.y;
-  auto plane = [&](int z) {  // dG of plane z (wrapped) into slot z mod 3
-    double* dst = sdg + ((z + 3) % 3) * HP;
-    for (int q = tid; q < HP; q += kBX * kBY) {
-      const int a = q % HX, b = q / HX;
-      dst[q] = jv_dg<P2, 3>(K, B, v, Pt{wrap_t<P2, FAR>(i0 + a - 1, K.nx), wrap_t<P2, FAR>(j0 + b - 1, K.ny),
-                                        wrap_t<P2, FAR>(z, K.nz)});
+  const long long N = K.N, NP = (long long)K.nx * K.ny;
+  const int i0 = bx * kBX, j0 = by * kJY3, z0 = bz * zc;
+  const int z1 = (z0 + zc < K.nz) ? z0 + zc : K.nz;
+  const Cols3 c = cols3<P2, FAR>(K, i0, j0);
+  const bool live = (i0 + (int)threadIdx.x < K.nx) && (j0 + (int)threadIdx.y < K.ny);
+  const bool el = K.elastic != 0;
+  auto plane = [&](int z) { return NP * wrap_t<P2, FAR>(z, K.nz); };
+  // the z-queued values at node n
+  auto ldq = [&](long long n, double* r) {
+    r[0] = scr[n];
+    const double cc = cn[n];
+    r[1] = cc * (1.0 - cc);
+#pragma unroll
+    for (int e = 0; e < 3; ++e) r[2 + e] = (double)v[(1 + e) * N + n];
+    if (el) {
+      r[5] = scr[5 * N + n];
+      r[6] = scr[6 * N + n];
+      r[7] = scr[3 * N + n];
     }
   };
-  plane(z0 - 1);
-  plane(z0);
-  const bool live = (i0 + (int)threadIdx.x < K.nx) && (j0 + (int)threadIdx.y < K.ny);
+  // the staged values at node n (into a register set of 10)
+  auto lds10 = [&](long long n, double* r) {
+    r[0] = scr[n];
+    const double cc = cn[n];
+    r[1] = cc * (1.0 - cc);
+#pragma unroll
+    for (int e = 0; e < 3; ++e) r[2 + e] = (double)v[(1 + e) * N + n];
+    if (el) {
+      r[5] = scr[1 * N + n];
+      r[6] = scr[2 * N + n];
+      r[7] = scr[4 * N + n];
+      r[8] = scr[5 * N + n];
+      r[9] = scr[6 * N + n];
+    }
+  };
+  double prv[8] = {}, cur[8] = {}, nxt[8] = {};
+  ldq(plane(z0 - 1) + c.col, prv);
+  ldq(plane(z0) + c.col, cur);
   const double idt = 1.0 / dt;
-  const int z1 = (z0 + zc < K.nz) ? z0 + zc : K.nz;  // the last chunk may be shorter
+  const int nst = el ? 10 : 5;
   for (int z = z0; z < z1; ++z) {
-    plane(z + 1);
-    __syncthreads();
-    if (live) {
-      // centre plane in slot z mod 3, its z neighbours in the slots of z + 1 and z - 1
-      const int sz = (z + 3) % 3;
-      const int hq = sz * HP + (threadIdx.x + 1) + HX * (threadIdx.y + 1);
-      const int up[3] = {1, HX, ((z + 4) % 3 - sz) * HP};
-      const int dn[3] = {-1, -HX, ((z + 2) % 3 - sz) * HP};
-      jv_rows<P2, 3>(K, idt, B, cn, v, w, Pt{i0 + (int)threadIdx.x, j0 + (int)threadIdx.y, z}, sdg, hq, up, dn);
+    const long long pz = plane(z), n = pz + c.col;
+    ldq(plane(z + 1) + c.col, nxt);
+    double ring[10] = {};
+    if (c.rslot >= 0) lds10(pz + c.rcol, ring);
+    double sxx = 0.0, syy = 0.0, sxy = 0.0;
+    if (el) {
+      sxx = scr[1 * N + n];
+      syy = scr[2 * N + n];
+      sxy = scr[4 * N + n];
+    }
+    const double vc = (double)v[n];
+    __syncthreads();  // every thread is done reading the previous plane
+    const int q = c.slot;
+#pragma unroll
+    for (int f = 0; f < 5; ++f) sp[f * kRP3 + q] = cur[f];
+    if (el) {
+      sp[5 * kRP3 + q] = sxx;
+      sp[6 * kRP3 + q] = syy;
+      sp[7 * kRP3 + q] = sxy;
+      sp[8 * kRP3 + q] = cur[5];
+      sp[9 * kRP3 + q] = cur[6];
+    }
+    if (c.rslot >= 0) {
+      for (int f = 0; f < nst; ++f) sp[f * kRP3 + c.rslot] = ring[f];
     }
     __syncthreads();
+    if (live) {
+      const double* sdg = sp;
+      const double* sg = sp + kRP3;
+      {
+        // c row: v_c / dt - div_h(M grad_h dG), face mobility M = kappa/2 (g_i + g_j)
+        const double mc = cur[1], g0 = cur[0];
+        double s = 0.0;
+        s += 0.5 * K.kappa * (mc + sg[q + 1]) * (sdg[q + 1] - g0) - 0.5 * K.kappa * (mc + sg[q - 1]) * (g0 - sdg[q - 1]);
+        s += 0.5 * K.kappa * (mc + sg[q + kRX3]) * (sdg[q + kRX3] - g0) -
+             0.5 * K.kappa * (mc + sg[q - kRX3]) * (g0 - sdg[q - kRX3]);
+        s += 0.5 * K.kappa * (mc + nxt[1]) * (nxt[0] - g0) - 0.5 * K.kappa * (mc + prv[1]) * (g0 - prv[0]);
+        w[n] = vc * idt - s * K.ih2;
+      }
+      const double vv[4] = {vc, cur[2], cur[3], cur[4]};
+#pragma unroll
+      for (int e = 0; e < 3; ++e) {
+        const double* se = sp + (2 + e) * kRP3;
+        const double fc = cur[2 + e];
+        double lp = 0.0;
+        lp += se[q + 1] + se[q - 1];
+        lp += se[q + kRX3] + se[q - kRX3];
+        lp += nxt[2 + e] + prv[2 + e];
+        lp = (lp - 6.0 * fc) * K.ih2;
+        double s = -0.5 * K.gamma_eta * lp;
+#pragma unroll
+        for (int f = 0; f < 4; ++f) s += B[(4 * (1 + e) + f) * N + n] * vv[f];
+        w[(1 + e) * N + n] = fc * idt + K.L_eta * s;
+      }
+      if (el) {
+        const double* sxxp = sp + 5 * kRP3;
+        const double* syyp = sp + 6 * kRP3;
+        const double* sxyp = sp + 7 * kRP3;
+        const double* sxzp = sp + 8 * kRP3;
+        const double* syzp = sp + 9 * kRP3;
+        // sum_J (sigma_IJ(p + e_J) - sigma_IJ(p - e_J)), J = x, y, z
+        double d = 0.0;
+        d += sxxp[q + 1] - sxxp[q - 1];
+        d += sxyp[q + kRX3] - sxyp[q - kRX3];
+        d += nxt[5] - prv[5];
+        w[4 * N + n] = d * K.i2h;
+        d = 0.0;
+        d += sxyp[q + 1] - sxyp[q - 1];
+        d += syyp[q + kRX3] - syyp[q - kRX3];
+        d += nxt[6] - prv[6];
+        w[5 * N + n] = d * K.i2h;
+        d = 0.0;
+        d += sxzp[q + 1] - sxzp[q - 1];
+        d += syzp[q + kRX3] - syzp[q - kRX3];
+        d += nxt[7] - prv[7];
+        w[6 * N + n] = d * K.i2h;
+      } else {
+#pragma unroll
+        for (int I = 0; I < 3; ++I) w[(4 + I) * N + n] = (double)v[(4 + I) * N + n];
+      }
+    }
+#pragma unroll
+    for (int f = 0; f < 8; ++f) {
+      prv[f] = cur[f];
+      cur[f] = nxt[f];
+    }
   }
 }
 
@@ -793,7 +994,7 @@ void launch_linearise(const Consts& K, const double* X, const double* Xn, double
 
 template <typename Tv>
 void launch_jv(const Consts& K, double dt, const double* B, const double* cn, const Tv* v, double* w,
-               hipStream_t s, const Bat& bt) {
+               double* scr, hipStream_t s, const Bat& bt) {
   const bool p2 = pow2_sides(K);
   if (K.dim == 2) {
     const dim3 g((K.nx + kBX - 1) / kBX, (K.ny + kJY2 - 1) / kJY2, 1);
@@ -805,20 +1006,28 @@ void launch_jv(const Consts& K, double dt, const double* B, const double* cn, co
     else if (far) hipLaunchKernelGGL((k_jv2<Tv, false, true>), gb, dim3(kBX, kJY2), 0, s, K, dt, B, cn, v, w, bt);
     else hipLaunchKernelGGL((k_jv2<Tv, false, false>), gb, dim3(kBX, kJY2), 0, s, K, dt, B, cn, v, w, bt);
   } else {
-    const int zc = K.nz < kJZ ? K.nz : kJZ;
-    const dim3 g((K.nx + kBX - 1) / kBX, (K.ny + kBY - 1) / kBY, (K.nz + zc - 1) / zc);
-    // halo columns run from -1 to (blocks x block side), planes from z0 - 1 to z0 + zc
-    const bool far = !((int)g.x * kBX < 2 * K.nx && (int)g.y * kBY < 2 * K.ny && (int)g.z * zc < 2 * K.nz);
-    const dim3 gb = bat_grid(g, bt);
-    if (p2) hipLaunchKernelGGL((k_jv3<Tv, true, false>), gb, dim3(kBX, kBY), 0, s, K, dt, B, cn, v, w, zc, bt);
-    else if (far) hipLaunchKernelGGL((k_jv3<Tv, false, true>), gb, dim3(kBX, kBY), 0, s, K, dt, B, cn, v, w, zc, bt);
-    else hipLaunchKernelGGL((k_jv3<Tv, false, false>), gb, dim3(kBX, kBY), 0, s, K, dt, B, cn, v, w, zc, bt);
+    const int zc = K.nz < kJZ3 ? K.nz : kJZ3;
+    const dim3 g((K.nx + kBX - 1) / kBX, (K.ny + kJY3 - 1) / kJY3, (K.nz + zc - 1) / zc);
+    // staged columns run from -1 to (blocks x block side); planes from z0 - 1 to z0 + zc stay
+    // within [-1, nz]
+    const bool far = !((int)g.x * kBX < 2 * K.nx && (int)g.y * kJY3 < 2 * K.ny);
+    const dim3 gb = bat_grid(g, bt), tb(kBX, kJY3);
+    if (p2) {
+      hipLaunchKernelGGL((k_jv3_dg<Tv, true, false>), gb, tb, 0, s, K, B, v, scr, zc, bt);
+      hipLaunchKernelGGL((k_jv3_rows<Tv, true, false>), gb, tb, 0, s, K, dt, B, cn, v, scr, w, zc, bt);
+    } else if (far) {
+      hipLaunchKernelGGL((k_jv3_dg<Tv, false, true>), gb, tb, 0, s, K, B, v, scr, zc, bt);
+      hipLaunchKernelGGL((k_jv3_rows<Tv, false, true>), gb, tb, 0, s, K, dt, B, cn, v, scr, w, zc, bt);
+    } else {
+      hipLaunchKernelGGL((k_jv3_dg<Tv, false, false>), gb, tb, 0, s, K, B, v, scr, zc, bt);
+      hipLaunchKernelGGL((k_jv3_rows<Tv, false, false>), gb, tb, 0, s, K, dt, B, cn, v, scr, w, zc, bt);
+    }
   }
 }
 template void launch_jv<double>(const Consts&, double, const double*, const double*, const double*, double*,
-                                hipStream_t, const Bat&);
+                                double*, hipStream_t, const Bat&);
 template void launch_jv<float>(const Consts&, double, const double*, const double*, const float*, double*,
-                               hipStream_t, const Bat&);
+                               double*, hipStream_t, const Bat&);
 
 void launch_energy(const Consts& K, const double* X, double* partial, hipStream_t s, const Bat& bt_) {
   const Bat bt = with_cbar0(K, bt_);

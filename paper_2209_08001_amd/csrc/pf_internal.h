@@ -122,10 +122,11 @@ void launch_residual(const Consts& K, double dt, const double* X, const double* 
 // B: 16 block planes; Bf (may be null): the same rounded to float
 void launch_linearise(const Consts& K, const double* X, const double* Xn, double* B, float* Bf,
                       hipStream_t s, const Bat& bt = Bat());
-// w = J v; v has element type Tv (double or float), w is double
+// w = J v; v has element type Tv (double or float), w is double.  scr: in 3D, seven planes of
+// N doubles that the two passes of the 3D product pass between them (unused in 2D)
 template <typename Tv>
 void launch_jv(const Consts& K, double dt, const double* B, const double* cn, const Tv* v, double* w,
-               hipStream_t s, const Bat& bt = Bat());
+               double* scr, hipStream_t s, const Bat& bt = Bat());
 void launch_energy(const Consts& K, const double* X, double* partial, hipStream_t s, const Bat& bt = Bat());
 
 // ---- Schwarz tile solve (kernels_ras.hip) -------------------------------------------

@@ -458,8 +458,10 @@ void pc_apply(pfnks_problem* p, double dt, const T* r, T* z, const pf::Bat& bt =
 template <typename Tv>
 void jv(pfnks_problem* p, double dt, const double* Bm, const Tv* v, double* w, const pf::Bat& bt = pf::Bat()) {
   Prof pr(p, PFNKS_K_JV, (double)p->nvec * (sizeof(Tv) + 8.0) + 136.0 * p->N);
-  pf::launch_jv<Tv>(p->K, dt, Bm, p->Xn, v, w, p->stream, bt);
-  p->launches += 1;
+  // 3D: two passes, dG and the stress through seven scratch planes (the trial residual Ft,
+  // which holds nothing while a linear system is solved)
+  pf::launch_jv<Tv>(p->K, dt, Bm, p->Xn, v, w, p->Ft, p->stream, bt);
+  p->launches += (p->K.dim == 3) ? 2 : 1;
 }
 
 // Solve J S = -F: right-preconditioned restarted GMRES with classical Gram-Schmidt, in the

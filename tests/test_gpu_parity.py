@@ -93,23 +93,35 @@ def test_residual_parity(n):
     p.close()
 
 
-@pytest.mark.parametrize("n", [(64, 64), (16, 16, 16), (24, 40), (12, 10, 14)])
-def test_jv_parity(n):
+# 3D: the column blocks march through chunks of 8 planes: (16, 16, 16) two chunks, (8, 4, 32)
+# four, (36, 6, 20) three with a short last one, rows that do not fill the last block, and
+# sides that are not powers of two but wide enough for the two-select periodic index;
+# (12, 10, 14) is narrower than a block (remainder index); Lscale = 0 switches the elastic terms
+# off (the u rows are v_u)
+@pytest.mark.parametrize("n,lscale", [((64, 64), None), ((16, 16, 16), None), ((24, 40), None),
+                                      ((12, 10, 14), None), ((8, 4, 32), None), ((36, 6, 20), None),
+                                      ((12, 10, 14), 0.0), ((8, 4, 32), 0.0)])
+def test_jv_parity(n, lscale):
     _cuda()
-    _note(f"jv parity n={n}")
+    _note(f"jv parity n={n} lscale={lscale}")
+    model = W.DEFAULT_MODEL if lscale is None else dict(W.DEFAULT_MODEL, Lscale=lscale)
     c0, e0 = W.init_fields(n, 13)
-    p = _problem(n, c0, e0)
+    p = _problem(n, c0, e0, model=model)
     Xn, _ = p.get_state()
     X = Xn.copy()
     X[:4] += np.random.default_rng(4).uniform(-0.01, 0.01, X[:4].shape)
     v = np.random.default_rng(5).normal(size=X.shape)
     g = Grid(n, W.H)
-    m = Model.from_dict(W.DEFAULT_MODEL)
+    m = Model.from_dict(model)
     for dt in (0.01, 1.0):
         wg = p.debug_jv(X, dt, v)
         J = jacobian(X, Xn, dt, g, m)
         wo = (J @ v.ravel()).reshape(X.shape)
         for f in range(X.shape[0]):
+            if lscale == 0.0 and f >= 4:
+                # no elasticity: the displacement rows are u = 0 (identity), not 0 = 0
+                assert np.array_equal(wg[f], v[f]), (dt, f)
+                continue
             assert _relmax(wg[f], wo[f]) <= 1e-10, (dt, f, _relmax(wg[f], wo[f]))
     p.close()
 
