@@ -886,6 +886,223 @@ __global__ __launch_bounds__(kBX* kJY3) void k_jv3_rows(Consts K, double dt, con
   }
 }
 
+// The first residual stage in 3D, in two passes over the same z-marching column blocks:
+//   pass A (k_res3_g):   G_c and G_eta (the laps of c and eta at both levels, the trace of
+//                        sigma at both levels, the chemical discrete gradient) into G4, and the
+//                        stress sigma_IJ(X) (eigenstrain about cbar0) into six scratch planes
+//                        s_xx, s_yy, s_zz, s_xy, s_xz, s_yz (without elasticity F_u = X_u instead);
+//   pass B (k_res3_fu):  F_u = sum_J Dhat_J sigma_IJ from the stored stress.
+// The arithmetic is that of k_residual_g term by term.
+template <bool P2, bool FAR>
+__global__ __launch_bounds__(kBX* kJY3) void k_res3_g(Consts K, const double* __restrict__ X,
+                                                      const double* __restrict__ Xn, double* __restrict__ G4,
+                                                      double* __restrict__ F, double* __restrict__ sig,
+                                                      int zc, Bat bt) {
+  // staged fields (in-plane neighbours): 0 c, 1..3 eta, 4..6 u of X; 7 c, 8..10 eta, 11, 12
+  // u_x, u_y of Xn.  z-queued fields: 0..6 those of X, 7..10 c and eta of Xn, 11 u_z of Xn.
+  constexpr int NS = 13, NQ = 12;
+  __shared__ double sp[NS * kRP3];
+  int bx, by, bz;
+  const int bi = xcd_block(bt, bx, by, bz);
+  if (bat_skip(bt, bi)) return;
+  {
+    const long long bo = bi * bt.stride;
+    X = bat_at(X, bo);
+    Xn = bat_at(Xn, bo);
+    G4 = bat_at(G4, bo);
+    F = bat_at(F, bo);
+    sig = bat_at(sig, bo);
+  }
+  const double cb = bt.cb[bi];
+  const long long N = K.N, NP = (long long)K.nx * K.ny;
+  const int i0 = bx * kBX, j0 = by * kJY3, z0 = bz * zc;
+  const int z1 = (z0 + zc < K.nz) ? z0 + zc : K.nz;
+  const Cols3 c = cols3<P2, FAR>(K, i0, j0);
+  const bool live = (i0 + (int)threadIdx.x < K.nx) && (j0 + (int)threadIdx.y < K.ny);
+  const bool el = K.elastic != 0;
+  auto plane = [&](int z) { return NP * wrap_t<P2, FAR>(z, K.nz); };
+  auto ldq = [&](long long n, double* r) {
+#pragma unroll
+    for (int f = 0; f < 7; ++f) r[f] = X[f * N + n];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) r[7 + f] = Xn[f * N + n];
+    r[11] = Xn[6 * N + n];
+  };
+  double prv[NQ], cur[NQ], nxt[NQ];
+  ldq(plane(z0 - 1) + c.col, prv);
+  ldq(plane(z0) + c.col, cur);
+  for (int z = z0; z < z1; ++z) {
+    const long long pz = plane(z), n = pz + c.col;
+    ldq(plane(z + 1) + c.col, nxt);
+    double ring[NS];
+    if (c.rslot >= 0) {
+      const long long m = pz + c.rcol;
+#pragma unroll
+      for (int f = 0; f < 7; ++f) ring[f] = X[f * N + m];
+#pragma unroll
+      for (int f = 0; f < 6; ++f) ring[7 + f] = Xn[f * N + m];
+    }
+    const double u0x = Xn[4 * N + n], u0y = Xn[5 * N + n];
+    __syncthreads();  // every thread is done reading the previous plane
+    const int q = c.slot;
+#pragma unroll
+    for (int f = 0; f < 11; ++f) sp[f * kRP3 + q] = cur[f];
+    sp[11 * kRP3 + q] = u0x;
+    sp[12 * kRP3 + q] = u0y;
+    if (c.rslot >= 0) {
+#pragma unroll
+      for (int f = 0; f < NS; ++f) sp[f * kRP3 + c.rslot] = ring[f];
+    }
+    __syncthreads();
+    if (live) {
+      // 2 d + 1 point Laplacian of staged field f (z neighbours from queue slot fq)
+      auto lap = [&](int f, int fq) {
+        const double* s = sp + f * kRP3;
+        double l = 0.0;
+        l += s[q + 1] + s[q - 1];
+        l += s[q + kRX3] + s[q - kRX3];
+        l += nxt[fq] + prv[fq];
+        return (l - 6.0 * s[q]) * K.ih2;
+      };
+      auto dx = [&](int f) { return (sp[f * kRP3 + q + 1] - sp[f * kRP3 + q - 1]) * K.i2h; };
+      auto dy = [&](int f) { return (sp[f * kRP3 + q + kRX3] - sp[f * kRP3 + q - kRX3]) * K.i2h; };
+      const double c1 = cur[0], c0 = cur[7];
+      const double e1[3] = {cur[1], cur[2], cur[3]}, e0[3] = {cur[8], cur[9], cur[10]};
+      double Gc, Ge[3];
+      chem_dg<false>(K, c1, e1, c0, e0, Gc, Ge, nullptr);
+      if (el) {
+        double div1 = 0.0, div0 = 0.0;
+        div1 += dx(4);
+        div0 += dx(11);
+        div1 += dy(5);
+        div0 += dy(12);
+        div1 += (nxt[6] - prv[6]) * K.i2h;
+        div0 += (nxt[11] - prv[11]) * K.i2h;
+        const double tr1 = K.Ctr * (div1 - 3 * K.eps0 * (c1 - cb));
+        const double tr0 = K.Ctr * (div0 - 3 * K.eps0 * (c0 - cb));
+        Gc -= K.eps0 * 0.5 * (tr1 + tr0);
+      }
+      Gc -= K.gamma_c * 0.5 * (lap(0, 0) + lap(7, 7));
+      G4[n] = Gc;
+#pragma unroll
+      for (int e = 0; e < 3; ++e) {
+        Ge[e] -= K.gamma_eta * 0.5 * (lap(1 + e, 1 + e) + lap(8 + e, 8 + e));
+        G4[(1 + e) * N + n] = Ge[e];
+      }
+      if (el) {
+        // Dhat_K u_L of X at the node: du[K][L]
+        double du[3][3];
+#pragma unroll
+        for (int L = 0; L < 3; ++L) {
+          du[0][L] = dx(4 + L);
+          du[1][L] = dy(4 + L);
+          du[2][L] = (nxt[4 + L] - prv[4 + L]) * K.i2h;
+        }
+        const double ec = K.eps0 * (c1 - cb);
+        double sd[3];
+#pragma unroll
+        for (int I = 0; I < 3; ++I) {
+          double s = 0.0;
+#pragma unroll
+          for (int L = 0; L < 3; ++L) s += (L == I ? K.C11 : K.C12) * (du[L][L] - ec);
+          sd[I] = s;
+        }
+        sig[n] = sd[0];
+        sig[1 * N + n] = sd[1];
+        sig[2 * N + n] = sd[2];
+        sig[3 * N + n] = K.C44 * (du[0][1] + du[1][0]);
+        sig[4 * N + n] = K.C44 * (du[0][2] + du[2][0]);
+        sig[5 * N + n] = K.C44 * (du[1][2] + du[2][1]);
+      } else {
+#pragma unroll
+        for (int I = 0; I < 3; ++I) F[(4 + I) * N + n] = cur[4 + I];
+      }
+    }
+#pragma unroll
+    for (int f = 0; f < NQ; ++f) {
+      prv[f] = cur[f];
+      cur[f] = nxt[f];
+    }
+  }
+}
+
+template <bool P2, bool FAR>
+__global__ __launch_bounds__(kBX* kJY3) void k_res3_fu(Consts K, const double* __restrict__ sig,
+                                                       double* __restrict__ F, int zc, Bat bt) {
+  // staged: 0 s_xx, 1 s_yy, 2 s_xy, 3 s_xz, 4 s_yz; z-queued: 0 s_xz, 1 s_yz, 2 s_zz
+  __shared__ double sp[5 * kRP3];
+  int bx, by, bz;
+  const int bi = xcd_block(bt, bx, by, bz);
+  if (bat_skip(bt, bi)) return;
+  {
+    const long long bo = bi * bt.stride;
+    sig = bat_at(sig, bo);
+    F = bat_at(F, bo);
+  }
+  const long long N = K.N, NP = (long long)K.nx * K.ny;
+  const int i0 = bx * kBX, j0 = by * kJY3, z0 = bz * zc;
+  const int z1 = (z0 + zc < K.nz) ? z0 + zc : K.nz;
+  const Cols3 c = cols3<P2, FAR>(K, i0, j0);
+  const bool live = (i0 + (int)threadIdx.x < K.nx) && (j0 + (int)threadIdx.y < K.ny);
+  auto plane = [&](int z) { return NP * wrap_t<P2, FAR>(z, K.nz); };
+  auto ldq = [&](long long n, double* r) {
+    r[0] = sig[4 * N + n];
+    r[1] = sig[5 * N + n];
+    r[2] = sig[2 * N + n];
+  };
+  double prv[3], cur[3], nxt[3];
+  ldq(plane(z0 - 1) + c.col, prv);
+  ldq(plane(z0) + c.col, cur);
+  const int so[5] = {0, 1, 3, 4, 5};  // scratch plane of each staged field
+  for (int z = z0; z < z1; ++z) {
+    const long long pz = plane(z), n = pz + c.col;
+    ldq(plane(z + 1) + c.col, nxt);
+    double ring[5];
+    if (c.rslot >= 0) {
+#pragma unroll
+      for (int f = 0; f < 5; ++f) ring[f] = sig[so[f] * N + pz + c.rcol];
+    }
+    const double sxx = sig[n], syy = sig[1 * N + n], sxy = sig[3 * N + n];
+    __syncthreads();  // every thread is done reading the previous plane
+    const int q = c.slot;
+    sp[q] = sxx;
+    sp[kRP3 + q] = syy;
+    sp[2 * kRP3 + q] = sxy;
+    sp[3 * kRP3 + q] = cur[0];
+    sp[4 * kRP3 + q] = cur[1];
+    if (c.rslot >= 0) {
+#pragma unroll
+      for (int f = 0; f < 5; ++f) sp[f * kRP3 + c.rslot] = ring[f];
+    }
+    __syncthreads();
+    if (live) {
+      const double *pxx = sp, *pyy = sp + kRP3, *pxy = sp + 2 * kRP3, *pxz = sp + 3 * kRP3,
+                   *pyz = sp + 4 * kRP3;
+      // sum_J (sigma_IJ(p + e_J) - sigma_IJ(p - e_J)), J = x, y, z
+      double d = 0.0;
+      d += pxx[q + 1] - pxx[q - 1];
+      d += pxy[q + kRX3] - pxy[q - kRX3];
+      d += nxt[0] - prv[0];
+      F[4 * N + n] = d * K.i2h;
+      d = 0.0;
+      d += pxy[q + 1] - pxy[q - 1];
+      d += pyy[q + kRX3] - pyy[q - kRX3];
+      d += nxt[1] - prv[1];
+      F[5 * N + n] = d * K.i2h;
+      d = 0.0;
+      d += pxz[q + 1] - pxz[q - 1];
+      d += pyz[q + kRX3] - pyz[q - kRX3];
+      d += nxt[2] - prv[2];
+      F[6 * N + n] = d * K.i2h;
+    }
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+      prv[f] = cur[f];
+      cur[f] = nxt[f];
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------------
 // energy (eqs. (relations)/(freeenergy)) and mass; partial: chem, elastic, interfacial, sum c
 // ---------------------------------------------------------------------------------
@@ -973,9 +1190,31 @@ static Bat with_cbar0(const Consts& K, const Bat& bt) {
 }
 
 void launch_residual(const Consts& K, double dt, const double* X, const double* Xn, double* G4,
-                     double* F, double* partial, hipStream_t s, const Bat& bt_) {
+                     double* F, double* partial, hipStream_t s, const Bat& bt_, double* sig) {
   const Bat bt = with_cbar0(K, bt_);
   const dim3 gg = bat_grid(stencil_grid(K), bt), gf = bat_grid(dim3(kRedBlocks), bt);
+  if (K.dim == 3 && sig) {
+    // the first stage in two passes over z-marching column blocks (as the 3D J v)
+    const int zc = K.nz < kJZ3 ? K.nz : kJZ3;
+    const dim3 g((K.nx + kBX - 1) / kBX, (K.ny + kJY3 - 1) / kJY3, (K.nz + zc - 1) / zc);
+    const bool far = !((int)g.x * kBX < 2 * K.nx && (int)g.y * kJY3 < 2 * K.ny);
+    const dim3 gb = bat_grid(g, bt), tb(kBX, kJY3);
+    const bool p2 = pow2_sides(K);
+    if (p2) {
+      hipLaunchKernelGGL((k_res3_g<true, false>), gb, tb, 0, s, K, X, Xn, G4, F, sig, zc, bt);
+      if (K.elastic) hipLaunchKernelGGL((k_res3_fu<true, false>), gb, tb, 0, s, K, sig, F, zc, bt);
+      hipLaunchKernelGGL(k_residual_f<true>, gf, dim3(256), 0, s, K, dt, X, Xn, G4, F, partial, bt);
+    } else if (far) {
+      hipLaunchKernelGGL((k_res3_g<false, true>), gb, tb, 0, s, K, X, Xn, G4, F, sig, zc, bt);
+      if (K.elastic) hipLaunchKernelGGL((k_res3_fu<false, true>), gb, tb, 0, s, K, sig, F, zc, bt);
+      hipLaunchKernelGGL(k_residual_f<false>, gf, dim3(256), 0, s, K, dt, X, Xn, G4, F, partial, bt);
+    } else {
+      hipLaunchKernelGGL((k_res3_g<false, false>), gb, tb, 0, s, K, X, Xn, G4, F, sig, zc, bt);
+      if (K.elastic) hipLaunchKernelGGL((k_res3_fu<false, false>), gb, tb, 0, s, K, sig, F, zc, bt);
+      hipLaunchKernelGGL(k_residual_f<false>, gf, dim3(256), 0, s, K, dt, X, Xn, G4, F, partial, bt);
+    }
+    return;
+  }
   if (pow2_sides(K)) {
     hipLaunchKernelGGL(k_residual_g<true>, gg, dim3(kBX, kBY), 0, s, K, X, Xn, G4, F, bt);
     hipLaunchKernelGGL(k_residual_f<true>, gf, dim3(256), 0, s, K, dt, X, Xn, G4, F, partial, bt);

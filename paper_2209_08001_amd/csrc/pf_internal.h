@@ -117,8 +117,11 @@ inline void allow_max_lds(const void* kernel) {
 
 // ---- phase-field kernels (kernels_phase.hip) ---------------------------------------
 // X, Xn: nf planes (c, eta1..3, u1..ud); all plane strides are N.
+// sig (may be null): in 3D, six planes of N doubles through which the first stage runs as two
+// passes (the stress); null keeps the single-pass stencil
 void launch_residual(const Consts& K, double dt, const double* X, const double* Xn, double* G4,
-                     double* F, double* partial, hipStream_t s, const Bat& bt = Bat());
+                     double* F, double* partial, hipStream_t s, const Bat& bt = Bat(),
+                     double* sig = nullptr);
 // B: 16 block planes; Bf (may be null): the same rounded to float
 void launch_linearise(const Consts& K, const double* X, const double* Xn, double* B, float* Bf,
                       hipStream_t s, const Bat& bt = Bat());

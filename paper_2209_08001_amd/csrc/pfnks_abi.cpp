@@ -353,7 +353,8 @@ int reduce_to_host(pfnks_problem* p, int nvals) {
 int residual(pfnks_problem* p, const double* X, double dt, double* F, double* nrm, double* bad) {
   {
     Prof pr(p, PFNKS_K_RESIDUAL, 8.0 * 3 * p->nvec);
-    pf::launch_residual(p->K, dt, X, p->Xn, p->G4, F, p->part, p->stream);
+    // 3D: the stress passes between the two stencil passes through w (free outside GMRES)
+    pf::launch_residual(p->K, dt, X, p->Xn, p->G4, F, p->part, p->stream, pf::Bat(), p->w);
   }
   p->launches += 2;
   int st = reduce_to_host(p, 2);
@@ -1179,7 +1180,7 @@ void gcopy(pfnks_group* G, unsigned mask, const double* src, double* dst) {
 int gresidual(pfnks_group* G, unsigned mask, const double* X, double* F, double* nrm, double* bad) {
   pfnks_problem* p = G->p;
   const pf::Bat bt = gbat(G, mask);
-  pf::launch_residual(p->K, 0.0, X, p->Xn, p->G4, F, p->part, p->stream, bt);
+  pf::launch_residual(p->K, 0.0, X, p->Xn, p->G4, F, p->part, p->stream, bt, p->w);
   pf::launch_finalize(p->part, 2, p->red, p->stream, G->hs, bt);
   G->launches += 3;
   int st = gsync(G);

@@ -73,22 +73,31 @@ def _relmax(a, b):
     return np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)
 
 
-@pytest.mark.parametrize("n", [(64, 64), (32, 64), (16, 16, 16), (24, 40), (12, 10, 14)])
-def test_residual_parity(n):
+# 3D grids as in test_jv_parity: the first stage's two passes march through chunks of 8
+# planes (several chunks, a short last one, ragged rows, the remainder index); Lscale = 0
+# switches the elastic terms off (the displacement rows are u = 0: F_u = X_u)
+@pytest.mark.parametrize("n,lscale", [((64, 64), None), ((32, 64), None), ((16, 16, 16), None), ((24, 40), None),
+                                      ((12, 10, 14), None), ((8, 4, 32), None), ((36, 6, 20), None),
+                                      ((12, 10, 14), 0.0), ((8, 4, 32), 0.0)])
+def test_residual_parity(n, lscale):
     _cuda()
-    _note(f"residual parity n={n}")
+    _note(f"residual parity n={n} lscale={lscale}")
+    model = W.DEFAULT_MODEL if lscale is None else dict(W.DEFAULT_MODEL, Lscale=lscale)
     c0, e0 = W.init_fields(n, 11)
-    p = _problem(n, c0, e0)
+    p = _problem(n, c0, e0, model=model)
     Xn, _ = p.get_state()
     X = Xn + 0.2 * (W.random_state(n, 12) - W.random_state(n, 12).mean(axis=tuple(range(1, len(n) + 1)), keepdims=True)) * 0.05
     X[0] = Xn[0] + np.random.default_rng(3).uniform(-0.01, 0.01, X[0].shape)
     g = Grid(n, W.H)
-    m = Model.from_dict(W.DEFAULT_MODEL)
+    m = Model.from_dict(model)
     cb0 = float(c0.mean())
     for dt in (0.01, 1.0):
         Fg = p.debug_residual(X, dt)
         Fo = residual(X, Xn, dt, g, m, cb0)
         for f in range(X.shape[0]):
+            if lscale == 0.0 and f >= 4:
+                assert np.array_equal(Fg[f], X[f]), (dt, f)
+                continue
             assert _relmax(Fg[f], Fo[f]) <= 1e-10, (dt, f, _relmax(Fg[f], Fo[f]))
     p.close()
 
