@@ -349,6 +349,9 @@ int reduce_to_host(pfnks_problem* p, int nvals) {
   return PFNKS_OK;
 }
 
+// kernels of one residual: two stencil passes, three in 3D with elasticity (the stress pass)
+int residual_launches(const pfnks_problem* p) { return (p->K.dim == 3 && p->K.elastic) ? 3 : 2; }
+
 // F = F(X; Xn, dt); returns ||F|| and the count of out-of-domain nodes
 int residual(pfnks_problem* p, const double* X, double dt, double* F, double* nrm, double* bad) {
   {
@@ -356,7 +359,7 @@ int residual(pfnks_problem* p, const double* X, double dt, double* F, double* nr
     // 3D: the stress passes between the two stencil passes through w (free outside GMRES)
     pf::launch_residual(p->K, dt, X, p->Xn, p->G4, F, p->part, p->stream, pf::Bat(), p->w);
   }
-  p->launches += 2;
+  p->launches += residual_launches(p);
   int st = reduce_to_host(p, 2);
   if (st) return st;
   *nrm = std::sqrt(p->hbuf[0]);
@@ -1182,7 +1185,7 @@ int gresidual(pfnks_group* G, unsigned mask, const double* X, double* F, double*
   const pf::Bat bt = gbat(G, mask);
   pf::launch_residual(p->K, 0.0, X, p->Xn, p->G4, F, p->part, p->stream, bt, p->w);
   pf::launch_finalize(p->part, 2, p->red, p->stream, G->hs, bt);
-  G->launches += 3;
+  G->launches += residual_launches(p) + 1;
   int st = gsync(G);
   if (st) return st;
   for (int i = 0; i < G->count; ++i)
