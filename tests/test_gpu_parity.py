@@ -222,21 +222,23 @@ def test_pc_linear_and_deterministic(pc):
     p.close()
 
 
+@pytest.mark.parametrize("n", [(64, 64), (16, 16, 16)])
 @pytest.mark.parametrize("pc", ["ras_spectral", "ras"])
-def test_pc_mixed_close_to_fp64(pc):
+def test_pc_mixed_close_to_fp64(pc, n):
     """The float preconditioner is the double one up to float rounding: a fixed number of
     Gauss-Seidel sweeps (a linear map whose norm is O(10) for these blocks) and one FFT solve,
     each rounding at 2^-24 ~ 6e-8 relative, so ~6e-7 of the max-norm bounds the difference
-    (measured: 8e-8); the test uses 1e-6."""
+    (measured: 8e-8 in 2D); the test uses 1e-6."""
     from paper_2209_08001_amd import pfnks
 
     _cuda()
-    _note(f"pc mixed vs fp64 {pc}")
-    n = (64, 64)
+    _note(f"pc mixed vs fp64 {pc} n={n}")
     c0, e0 = W.init_fields(n, 23)
     kind = pfnks.PC_RAS if pc == "ras" else pfnks.PC_RAS_SPECTRAL
-    pd = _problem(n, c0, e0, pc=kind)
-    pm = _problem(n, c0, e0, pc=kind, precision=pfnks.MIXED)
+    # the all-field tiles hold every field with a ring of two: 4^3 tiles in 3D
+    kw = dict(tile=(4, 4, 4), overlap=1) if (len(n) == 3 and pc == "ras") else {}
+    pd = _problem(n, c0, e0, pc=kind, **kw)
+    pm = _problem(n, c0, e0, pc=kind, precision=pfnks.MIXED, **kw)
     Xn, _ = pd.get_state()
     r = np.random.default_rng(9).normal(size=Xn.shape)
     zd = pd.debug_pc(Xn, 0.05, r)
